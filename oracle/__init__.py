@@ -1,0 +1,327 @@
+"""FP64 CPU oracle for the periodic tree-gravity force evaluation.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The GPU library
+(``paper_1407_2600_amd``) never imports, links or calls it, and the two share
+no code: the oracle is plain C (``oracle/*.c``, built with gcc) behind this
+ctypes wrapper.
+
+What it computes (paper Sec. 2.1, "2HOT"):
+
+* ``direct_ewald``   -- the plain definition: periodic, Plummer-softened,
+  background-neutralised accelerations and potentials by direct summation with
+  the textbook Ewald split (real space + structure factors);
+* ``Tree``           -- the same-acceptance-test FP64 tree: Morton keys, sort,
+  oct-tree, moments, sink groups, 27-image walk, direct and multipole
+  interactions, and the periodic far field as a local expansion of the Ewald
+  remainder about the box centre (the paper's high-order periodic expansion);
+* ``direct_near_far`` -- the tree result at theta=0 for sampled targets
+  (27-image softened direct sum plus far field);
+* ``green_taylor``, ``psi_table``, ``ewald_psi``, ``ewald_xi``,
+  ``multipole_eval``, ``direct_open`` -- the building blocks, exposed so the
+  tests can pin each one to closed forms.
+
+Functions with no pin of their own are marked "parity unpinned" where they are
+defined; every function here is pinned by ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["series.c", "ewald.c", "tree.c"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP64, no fused multiply-add)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    if not force and os.path.exists(_LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(_HERE, "oracle.h")])
+        if os.path.getmtime(_LIB_PATH) >= newest:
+            return _LIB_PATH
+    tmp = _LIB_PATH + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
+           "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        vp, i64, dp, i64p, u64p, i32p = (C.c_void_p, C.c_int64, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                         C.POINTER(C.c_int32))
+        L.or_tree_build.restype = vp
+        L.or_tree_build.argtypes = [i64, dp, dp, C.c_void_p]
+        L.or_tree_free.argtypes = [vp]
+        L.or_tree_ncells.restype = i64
+        L.or_tree_ncells.argtypes = [vp]
+        L.or_tree_ngroups.restype = i64
+        L.or_tree_ngroups.argtypes = [vp]
+        L.or_tree_perm.argtypes = [vp, i64p, u64p]
+        L.or_tree_cells.argtypes = [vp, u64p, i32p, i64p, i64p, i32p, dp, dp, dp]
+        L.or_tree_cell_moments.argtypes = [vp, i64, dp]
+        L.or_tree_groups.argtypes = [vp, i64p, dp, dp]
+        L.or_tree_walk.argtypes = [vp]
+        L.or_tree_list_total.restype = i64
+        L.or_tree_list_total.argtypes = [vp, C.c_int]
+        L.or_tree_lists.argtypes = [vp, C.c_int, i64p, i32p, i64p]
+        L.or_tree_pair_count.restype = i64
+        L.or_tree_pair_count.argtypes = [vp]
+        L.or_tree_forces.argtypes = [vp, i64, i64p, dp, dp]
+        L.or_tree_far.argtypes = [vp, dp, dp, dp]
+        L.or_direct_near_far.argtypes = [vp, i64, i64p, dp, dp]
+        L.or_direct_open.argtypes = [i64, dp, dp, C.c_double, C.c_double, dp, dp]
+        L.or_direct_ewald.argtypes = [i64, dp, dp, i64, i64p, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
+        L.or_keys.argtypes = [i64, dp, C.c_double, u64p, dp]
+        L.or_sort.argtypes = [i64, u64p, i64p]
+        L.or_green_taylor.argtypes = [C.c_int, dp, C.c_double, dp]
+        L.or_psi_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+        L.or_ewald_psi.argtypes = [dp, C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
+        L.or_ewald_xi.restype = C.c_double
+        L.or_ewald_xi.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
+        L.or_multipole_eval.argtypes = [i64, dp, dp, C.c_int, C.c_double, dp, dp, dp]
+        L.or_nterms.restype = C.c_int
+        L.or_nterms.argtypes = [C.c_int]
+        L.or_mi_get.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int)]
+        _lib = L
+    return _lib
+
+
+def _p(a, ct=C.c_double):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class _Params(C.Structure):
+    _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
+                ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
+                ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int)]
+
+
+def _params(p: dict) -> _Params:
+    return _Params(float(p.get("box", 1.0)), float(p.get("G", 1.0)), float(p.get("eps", 0.0)),
+                   float(p.get("theta", 0.5)), int(p.get("order", 2)),
+                   int(p.get("periodic", 1)), int(p.get("leaf_max", 16)),
+                   int(p.get("group_max", 64)), int(p.get("far_order", 8)))
+
+
+def mi_list(D: int) -> list[tuple[int, int, int]]:
+    """Multi-indices |k| <= D in the oracle's order (degree, then a, b descending)."""
+    L = lib()
+    out = []
+    a, b, c = C.c_int(), C.c_int(), C.c_int()
+    for i in range(L.or_nterms(D)):
+        L.or_mi_get(i, C.byref(a), C.byref(b), C.byref(c))
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+def green_taylor(D: int, R, eps: float) -> np.ndarray:
+    """Taylor coefficients d^k g(R)/k! of g = (|r|^2+eps^2)^-1/2, |k| <= D."""
+    L = lib()
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    out = np.zeros(L.or_nterms(D))
+    L.or_green_taylor(D, _p(R), float(eps) ** 2, _p(out))
+    return out
+
+
+def psi_table(D: int, box: float = 1.0, alpha: float | None = None, nreal: int = 5,
+              kmax: int = 6) -> np.ndarray:
+    """Taylor coefficients d^s Psi(0)/s! of the periodic remainder, |s| <= D."""
+    L = lib()
+    alpha = 2.0 / box if alpha is None else alpha
+    out = np.zeros(L.or_nterms(D))
+    L.or_psi_table(D, box, alpha, nreal, kmax, _p(out))
+    return out
+
+
+def ewald_psi(r, box: float = 1.0, alpha: float | None = None, nreal: int = 4, kmax: int = 10):
+    L = lib()
+    alpha = 2.0 / box if alpha is None else alpha
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    psi = np.zeros(1)
+    g = np.zeros(3)
+    L.or_ewald_psi(_p(r), box, alpha, nreal, kmax, _p(psi), _p(g))
+    return psi[0], g
+
+
+def ewald_xi(box: float = 1.0, alpha: float | None = None, nreal: int = 4, kmax: int = 10) -> float:
+    alpha = 2.0 / box if alpha is None else alpha
+    return lib().or_ewald_xi(box, alpha, nreal, kmax)
+
+
+def multipole_eval(pos, mass, order: int, eps: float, x):
+    """Phi and grad Phi at x of one cell's order-p expansion about its COM."""
+    L = lib()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    phi = np.zeros(1)
+    g = np.zeros(3)
+    L.or_multipole_eval(pos.shape[1], _p(pos), _p(mass), order, eps, _p(x), _p(phi), _p(g))
+    return phi[0], g
+
+
+def direct_open(pos, mass, G: float = 1.0, eps: float = 0.0):
+    """Open-boundary softened direct sum; returns (acc[3,N], pot[N])."""
+    L = lib()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[1]
+    acc = np.zeros((3, n))
+    pot = np.zeros(n)
+    L.or_direct_open(n, _p(pos), _p(mass), G, eps, _p(acc), _p(pot))
+    return acc, pot
+
+
+def direct_ewald(pos, mass, params: dict, targets=None, alpha: float | None = None,
+                 nreal: int = 1, kmax: int | None = None):
+    """Exact periodic direct sum (the plain definition) at the targets.
+
+    Returns (acc[3,T], pot[T]).  Default split alpha = 4/L with the real-space
+    sum over the 27 images of the minimum-image separation and |k|_inf <= 8.
+    """
+    L = lib()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[1]
+    box = float(params.get("box", 1.0))
+    if targets is None:
+        targets = np.arange(n, dtype=np.int64)
+    targets = np.ascontiguousarray(targets, dtype=np.int64)
+    alpha = 4.0 / box if alpha is None else alpha
+    if kmax is None:
+        kmax = int(np.ceil(np.sqrt(40.0) * alpha * box / np.pi)) + 1
+    nt = len(targets)
+    acc = np.zeros((3, nt))
+    pot = np.zeros(nt)
+    L.or_direct_ewald(n, _p(pos), _p(mass), nt, _p(targets, C.c_int64), box,
+                      float(params.get("G", 1.0)), float(params.get("eps", 0.0)), alpha,
+                      nreal, kmax, _p(acc), _p(pot))
+    return acc, pot
+
+
+def keys(pos, box: float = 1.0):
+    L = lib()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[1]
+    k = np.zeros(n, dtype=np.uint64)
+    w = np.zeros((3, n))
+    L.or_keys(n, _p(pos), box, _p(k, C.c_uint64), _p(w))
+    return k, w
+
+
+class Tree:
+    """The same-acceptance-test FP64 tree (build on construction)."""
+
+    def __init__(self, pos, mass, params: dict):
+        self.lib = lib()
+        self.params = dict(params)
+        self.pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self.mass = np.ascontiguousarray(mass, dtype=np.float64)
+        self.n = self.pos.shape[1]
+        self._prm = _params(params)
+        self.h = self.lib.or_tree_build(self.n, _p(self.pos), _p(self.mass), C.byref(self._prm))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.or_tree_free(h)
+            self.h = None
+
+    # structure -----------------------------------------------------------
+    def perm(self):
+        perm = np.zeros(self.n, dtype=np.int64)
+        sk = np.zeros(self.n, dtype=np.uint64)
+        self.lib.or_tree_perm(self.h, _p(perm, C.c_int64), _p(sk, C.c_uint64))
+        return perm, sk
+
+    def cells(self) -> dict:
+        nc = self.lib.or_tree_ncells(self.h)
+        d = dict(key=np.zeros(nc, np.uint64), level=np.zeros(nc, np.int32),
+                 first=np.zeros(nc, np.int64), count=np.zeros(nc, np.int64),
+                 is_leaf=np.zeros(nc, np.int32), mass=np.zeros(nc), com=np.zeros((3, nc)),
+                 rcrit=np.zeros(nc))
+        self.lib.or_tree_cells(self.h, _p(d["key"], C.c_uint64), _p(d["level"], C.c_int32),
+                               _p(d["first"], C.c_int64), _p(d["count"], C.c_int64),
+                               _p(d["is_leaf"], C.c_int32), _p(d["mass"]), _p(d["com"]),
+                               _p(d["rcrit"]))
+        return d
+
+    def cell_moments(self, c: int) -> np.ndarray:
+        nm = self.lib.or_nterms(int(self.params.get("order", 2)))
+        M = np.zeros(nm)
+        self.lib.or_tree_cell_moments(self.h, int(c), _p(M))
+        return M
+
+    def groups(self):
+        ng = self.lib.or_tree_ngroups(self.h)
+        cell = np.zeros(ng, np.int64)
+        lo = np.zeros((3, ng))
+        hi = np.zeros((3, ng))
+        self.lib.or_tree_groups(self.h, _p(cell, C.c_int64), _p(lo), _p(hi))
+        return cell, lo, hi
+
+    def lists(self, kind: int):
+        """(offsets[ng+1], image[E], cell[E]) for kind 0 (direct) or 1 (multipole)."""
+        tot = self.lib.or_tree_list_total(self.h, kind)
+        ng = self.lib.or_tree_ngroups(self.h)
+        off = np.zeros(ng + 1, np.int64)
+        img = np.zeros(tot, np.int32)
+        cell = np.zeros(tot, np.int64)
+        self.lib.or_tree_lists(self.h, kind, _p(off, C.c_int64), _p(img, C.c_int32),
+                               _p(cell, C.c_int64))
+        return off, img, cell
+
+    def pair_count(self) -> int:
+        return int(self.lib.or_tree_pair_count(self.h))
+
+    def far(self):
+        pf = int(self.params.get("far_order", 8))
+        T = np.zeros(self.lib.or_nterms(2 * pf))
+        M = np.zeros(self.lib.or_nterms(pf))
+        Lm = np.zeros(self.lib.or_nterms(pf))
+        self.lib.or_tree_far(self.h, _p(T), _p(M), _p(Lm))
+        return T, M, Lm
+
+    # forces ---------------------------------------------------------------
+    def forces(self, groups=None):
+        """(acc[3,N], pot[N]) in original order; with ``groups`` only the
+        particles of those groups are filled (the rest are NaN)."""
+        acc = np.full((3, self.n), np.nan)
+        pot = np.full(self.n, np.nan)
+        if groups is None:
+            self.lib.or_tree_forces(self.h, -1, None, _p(acc), _p(pot))
+        else:
+            g = np.ascontiguousarray(groups, dtype=np.int64)
+            self.lib.or_tree_forces(self.h, len(g), _p(g, C.c_int64), _p(acc), _p(pot))
+        return acc, pot
+
+    def direct_near_far(self, targets):
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        acc = np.zeros((3, len(t)))
+        pot = np.zeros(len(t))
+        self.lib.or_direct_near_far(self.h, len(t), _p(t, C.c_int64), _p(acc), _p(pot))
+        return acc, pot
+
+
+def rms_rel_error(a, ref) -> float:
+    """sqrt(sum |a-ref|^2 / sum |ref|^2) over targets (the rms force error)."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))

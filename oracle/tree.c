@@ -1,0 +1,751 @@
+/* Same-acceptance-test FP64 tree code (oracle; test infrastructure only).
+ *
+ * Steps, in the order of the paper's Sec. 2.1:
+ *  1. wrap positions into the box and assign each particle a 64-bit Morton
+ *     key (the paper's Key; parent = key>>3, daughter = key<<3|octant);
+ *  2. sort particles by key (ties by original index);
+ *  3. build the oct-tree: a cell with more than leaf_max particles (and level
+ *     below 21) is split into its non-empty daughters; cells are listed in
+ *     pre-order, i.e. by (first particle, level);
+ *  4. cell mass, centre of mass and raw Cartesian moments about the centre of
+ *     mass, up to the multipole order (leaf quadrupole/hexadecapole);
+ *  5. sink groups: the largest cells with at most group_max particles (or a
+ *     leaf), sharing one interaction list per group (the m x n bundling);
+ *  6. per group and per periodic image n in {-1,0,1}^3, a depth-first walk
+ *     that accepts a cell for a multipole interaction when the acceptance
+ *     test passes, takes a leaf that fails it as direct interactions, and
+ *     opens other cells;
+ *  7. forces: direct softened sums over the leaves, multipole interactions
+ *     with the Taylor coefficients of the softened Green's function, and the
+ *     periodic far field as a local expansion about the box centre.
+ *
+ * Deterministic choices the paper leaves open are written out here so that an
+ * independent implementation can reproduce keys, order, cells and lists bit
+ * for bit: positions wrap by one add/subtract of L, quantise by
+ * floor(x * (2^21/L)) clamped to 2^21-1, octant bits are (x,y,z) with x most
+ * significant, the centre of mass is summed in key order at leaves and in
+ * octant order over daughters (separate multiply and add, no fused
+ * multiply-add), and the acceptance test is
+ *     (s_B/theta + |com_B - centre_B|)^2 < d^2
+ * with d the distance from com_B (shifted by the image) to the group's tight
+ * bounding box, s_B the cell side.  This is the centre-of-mass opening
+ * criterion with the offset correction of Barnes (1994) / Salmon & Warren
+ * (1994), which keeps the expansion convergent for any theta < 1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include "oracle.h"
+
+#define MAXLEV 21
+
+typedef struct {
+  uint64_t key;
+  int level, is_leaf, nchild;
+  int64_t first, count, parent;
+  int64_t child[8];
+  double m, mx[3], com[3], center[3], side, rcrit;
+  double* M; /* raw moments about com, |k| <= order */
+} cell_t;
+
+typedef struct {
+  int64_t n;
+  int32_t* img;
+  int64_t* cell;
+  int64_t cap;
+} list_t;
+
+typedef struct {
+  or_params p;
+  int64_t n;
+  double* x[3];    /* wrapped positions, original order */
+  double* mass;    /* original order */
+  uint64_t* key;   /* original order */
+  int64_t* perm;   /* sorted -> original */
+  double* sx[3];   /* sorted wrapped positions */
+  double* sm;
+  uint64_t* skey;
+  cell_t* cells;
+  int64_t ncells, ccap;
+  int64_t* groups;
+  int64_t ngroups;
+  int64_t* group_of; /* sorted particle -> group number */
+  double (*glo)[3];
+  double (*ghi)[3];
+  list_t* p2p;
+  list_t* m2p;
+  int walked;
+  int nmom;          /* or_nterms(order) */
+  /* periodic far field */
+  int far_ok;
+  double c0[3];
+  double* Tpsi;  /* |s| <= 2 far_order */
+  double* Mroot; /* |k| <= far_order */
+  double* Lam;   /* |q| <= far_order */
+} tree_t;
+
+/* ---------------- keys ---------------- */
+
+static double wrap1(double x, double L) {
+  if (x < 0.0) x += L;
+  if (x >= L) x -= L;
+  return x;
+}
+
+static uint64_t spread21(uint64_t v) {
+  /* place bit b of v at bit 3b */
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ULL) << (3 * b);
+  return r;
+}
+
+uint64_t or_key_of(double xw, double yw, double zw, double L) {
+  double S = 2097152.0 / L;
+  uint64_t q[3];
+  double w[3] = {xw, yw, zw};
+  for (int a = 0; a < 3; ++a) {
+    double t = w[a] * S;
+    uint64_t v = (uint64_t)(uint32_t)t;
+    if (v > 2097151ULL) v = 2097151ULL;
+    q[a] = v;
+  }
+  return (1ULL << 63) | (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+}
+
+void or_keys(int64_t n, const double* pos, double L, uint64_t* keys, double* wrapped) {
+  for (int64_t i = 0; i < n; ++i) {
+    double w[3];
+    for (int a = 0; a < 3; ++a) w[a] = wrap1(pos[a * n + i], L);
+    keys[i] = or_key_of(w[0], w[1], w[2], L);
+    if (wrapped)
+      for (int a = 0; a < 3; ++a) wrapped[a * n + i] = w[a];
+  }
+}
+
+typedef struct { uint64_t k; int64_t i; } kv_t;
+static int kv_cmp(const void* A, const void* B) {
+  const kv_t* a = A; const kv_t* b = B;
+  if (a->k < b->k) return -1;
+  if (a->k > b->k) return 1;
+  return (a->i < b->i) ? -1 : (a->i > b->i);
+}
+
+void or_sort(int64_t n, const uint64_t* keys, int64_t* perm) {
+  kv_t* kv = malloc(sizeof(kv_t) * (size_t)(n ? n : 1));
+  for (int64_t i = 0; i < n; ++i) { kv[i].k = keys[i]; kv[i].i = i; }
+  qsort(kv, (size_t)n, sizeof(kv_t), kv_cmp);
+  for (int64_t i = 0; i < n; ++i) perm[i] = kv[i].i;
+  free(kv);
+}
+
+/* ---------------- tree ---------------- */
+
+static int64_t new_cell(tree_t* T) {
+  if (T->ncells == T->ccap) {
+    T->ccap = T->ccap ? 2 * T->ccap : 1024;
+    T->cells = realloc(T->cells, sizeof(cell_t) * (size_t)T->ccap);
+  }
+  memset(&T->cells[T->ncells], 0, sizeof(cell_t));
+  return T->ncells++;
+}
+
+static void cell_geometry(tree_t* T, cell_t* c) {
+  /* integer cell coordinates from the key bits below the placeholder */
+  uint64_t k = c->key;
+  uint64_t ix = 0, iy = 0, iz = 0;
+  for (int b = 0; b < c->level; ++b) {
+    ix |= ((k >> (3 * b + 2)) & 1ULL) << b;
+    iy |= ((k >> (3 * b + 1)) & 1ULL) << b;
+    iz |= ((k >> (3 * b)) & 1ULL) << b;
+  }
+  c->side = ldexp(T->p.box, -c->level);
+  c->center[0] = ((double)ix + 0.5) * c->side;
+  c->center[1] = ((double)iy + 0.5) * c->side;
+  c->center[2] = ((double)iz + 0.5) * c->side;
+}
+
+static int64_t build_rec(tree_t* T, int level, uint64_t key, int64_t first, int64_t count,
+                         int64_t parent) {
+  int64_t ci = new_cell(T);
+  cell_t* c = &T->cells[ci];
+  c->key = key; c->level = level; c->first = first; c->count = count; c->parent = parent;
+  for (int o = 0; o < 8; ++o) c->child[o] = -1;
+  cell_geometry(T, c);
+  if (count > T->p.leaf_max && level < MAXLEV) {
+    int shift = 3 * (MAXLEV - level - 1);
+    int64_t s = first, end = first + count;
+    for (int o = 0; o < 8; ++o) {
+      int64_t b = s;
+      while (s < end && (int)((T->skey[s] >> shift) & 7ULL) == o) ++s;
+      if (s > b) {
+        int64_t child = build_rec(T, level + 1, (key << 3) | (uint64_t)o, b, s - b, ci);
+        c = &T->cells[ci]; /* realloc may move */
+        c->child[o] = child;
+        c->nchild++;
+      }
+    }
+    c->is_leaf = 0;
+  } else {
+    c->is_leaf = 1;
+  }
+  return ci;
+}
+
+static void moments(tree_t* T) {
+  int p = T->p.order;
+  int nm = T->nmom;
+  double theta = T->p.theta;
+  /* children have larger indices than their parent: go backwards */
+  for (int64_t ci = T->ncells - 1; ci >= 0; --ci) {
+    cell_t* c = &T->cells[ci];
+    double m = 0.0, mx[3] = {0.0, 0.0, 0.0};
+    if (c->is_leaf) {
+      for (int64_t s = c->first; s < c->first + c->count; ++s) {
+        double ms = T->sm[s];
+        m = m + ms;
+        for (int a = 0; a < 3; ++a) {
+          double t = ms * T->sx[a][s];
+          mx[a] = mx[a] + t;
+        }
+      }
+    } else {
+      for (int o = 0; o < 8; ++o) {
+        if (c->child[o] < 0) continue;
+        cell_t* d = &T->cells[c->child[o]];
+        m = m + d->m;
+        for (int a = 0; a < 3; ++a) mx[a] = mx[a] + d->mx[a];
+      }
+    }
+    c->m = m;
+    for (int a = 0; a < 3; ++a) {
+      c->mx[a] = mx[a];
+      c->com[a] = (m != 0.0) ? mx[a] / m : c->center[a];
+    }
+    double dx = c->com[0] - c->center[0], dy = c->com[1] - c->center[1],
+           dz = c->com[2] - c->center[2];
+    double dd = dx * dx;
+    dd = dd + dy * dy;
+    dd = dd + dz * dz;
+    double delta = sqrt(dd);
+    c->rcrit = (theta > 0.0) ? c->side / theta + delta : INFINITY;
+    /* raw moments about the centre of mass, directly from the particles */
+    c->M = calloc((size_t)nm, sizeof(double));
+    for (int64_t s = c->first; s < c->first + c->count; ++s) {
+      double d[3] = {T->sx[0][s] - c->com[0], T->sx[1][s] - c->com[1], T->sx[2][s] - c->com[2]};
+      double pw[3][OR_DMAX + 1];
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+        for (int e = 1; e <= p; ++e) pw[a][e] = pw[a][e - 1] * d[a];
+      }
+      for (int k = 0; k < nm; ++k) {
+        int ka, kb, kc;
+        or_mi_get(k, &ka, &kb, &kc);
+        c->M[k] += T->sm[s] * pw[0][ka] * pw[1][kb] * pw[2][kc];
+      }
+    }
+  }
+}
+
+static void groups_rec(tree_t* T, int64_t ci) {
+  cell_t* c = &T->cells[ci];
+  if (c->count <= T->p.group_max || c->is_leaf) {
+    T->groups[T->ngroups++] = ci;
+    return;
+  }
+  for (int o = 0; o < 8; ++o)
+    if (c->child[o] >= 0) groups_rec(T, c->child[o]);
+}
+
+/* ---------------- far field ---------------- */
+
+static double binom_mi(int qa, int qb, int qc, int ka, int kb, int kc) {
+  /* C(q+k, q) per component */
+  double r = 1.0;
+  int q[3] = {qa, qb, qc}, k[3] = {ka, kb, kc};
+  for (int a = 0; a < 3; ++a)
+    r *= or_factorial(q[a] + k[a]) / (or_factorial(q[a]) * or_factorial(k[a]));
+  return r;
+}
+
+static void far_setup(tree_t* T) {
+  int pf = T->p.far_order;
+  double L = T->p.box;
+  int D = 2 * pf;
+  int nT = or_nterms(D), nq = or_nterms(pf);
+  T->Tpsi = calloc((size_t)nT, sizeof(double));
+  /* alpha = 2/L; real images to |n|_inf = 5, reciprocal to |k|_inf = 6 */
+  or_psi_table(D, L, 2.0 / L, 5, 6, T->Tpsi);
+  for (int a = 0; a < 3; ++a) T->c0[a] = 0.5 * L;
+  T->Mroot = calloc((size_t)nq, sizeof(double));
+  for (int64_t s = 0; s < T->n; ++s) {
+    double d[3] = {T->sx[0][s] - T->c0[0], T->sx[1][s] - T->c0[1], T->sx[2][s] - T->c0[2]};
+    double pw[3][OR_DMAX + 1];
+    for (int a = 0; a < 3; ++a) {
+      pw[a][0] = 1.0;
+      for (int e = 1; e <= pf; ++e) pw[a][e] = pw[a][e - 1] * d[a];
+    }
+    for (int k = 0; k < nq; ++k) {
+      int ka, kb, kc;
+      or_mi_get(k, &ka, &kb, &kc);
+      T->Mroot[k] += T->sm[s] * pw[0][ka] * pw[1][kb] * pw[2][kc];
+    }
+  }
+  T->Lam = calloc((size_t)nq, sizeof(double));
+  for (int q = 0; q < nq; ++q) {
+    int qa, qb, qc;
+    or_mi_get(q, &qa, &qb, &qc);
+    double acc = 0.0;
+    for (int k = 0; k < nq; ++k) {
+      int ka, kb, kc;
+      or_mi_get(k, &ka, &kb, &kc);
+      double sg = ((ka + kb + kc) % 2) ? -1.0 : 1.0;
+      acc += binom_mi(qa, qb, qc, ka, kb, kc) * sg *
+             T->Tpsi[or_mi(qa + ka, qb + kb, qc + kc)] * T->Mroot[k];
+    }
+    T->Lam[q] = acc;
+  }
+  T->far_ok = 1;
+}
+
+/* Phi_far(h) = sum_q Lam_q h^q and its gradient */
+static void far_eval(const tree_t* T, const double x[3], double* phi, double g[3]) {
+  int pf = T->p.far_order;
+  int nq = or_nterms(pf);
+  double h[3] = {x[0] - T->c0[0], x[1] - T->c0[1], x[2] - T->c0[2]};
+  double pw[3][OR_DMAX + 1];
+  for (int a = 0; a < 3; ++a) {
+    pw[a][0] = 1.0;
+    for (int e = 1; e <= pf; ++e) pw[a][e] = pw[a][e - 1] * h[a];
+  }
+  double P = 0.0, G[3] = {0, 0, 0};
+  for (int q = 0; q < nq; ++q) {
+    int qa, qb, qc;
+    or_mi_get(q, &qa, &qb, &qc);
+    double L = T->Lam[q];
+    P += L * pw[0][qa] * pw[1][qb] * pw[2][qc];
+    if (qa) G[0] += L * qa * pw[0][qa - 1] * pw[1][qb] * pw[2][qc];
+    if (qb) G[1] += L * qb * pw[0][qa] * pw[1][qb - 1] * pw[2][qc];
+    if (qc) G[2] += L * qc * pw[0][qa] * pw[1][qb] * pw[2][qc - 1];
+  }
+  *phi = P;
+  for (int a = 0; a < 3; ++a) g[a] = G[a];
+}
+
+/* ---------------- public: build ---------------- */
+
+void* or_tree_build(int64_t n, const double* pos, const double* mass, const or_params* prm) {
+  or_mi_init();
+  tree_t* T = calloc(1, sizeof(tree_t));
+  T->p = *prm;
+  T->n = n;
+  double L = prm->box;
+  for (int a = 0; a < 3; ++a) {
+    T->x[a] = malloc(sizeof(double) * (size_t)(n ? n : 1));
+    T->sx[a] = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  }
+  T->mass = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  T->sm = malloc(sizeof(double) * (size_t)(n ? n : 1));
+  T->key = malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+  T->skey = malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+  T->perm = malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) T->x[a][i] = wrap1(pos[a * n + i], L);
+    T->mass[i] = mass[i];
+    T->key[i] = or_key_of(T->x[0][i], T->x[1][i], T->x[2][i], L);
+  }
+  or_sort(n, T->key, T->perm);
+  for (int64_t s = 0; s < n; ++s) {
+    int64_t i = T->perm[s];
+    for (int a = 0; a < 3; ++a) T->sx[a][s] = T->x[a][i];
+    T->sm[s] = T->mass[i];
+    T->skey[s] = T->key[i];
+  }
+  T->nmom = or_nterms(prm->order);
+  if (n > 0) {
+    build_rec(T, 0, 1ULL, 0, n, -1);
+    moments(T);
+    T->groups = malloc(sizeof(int64_t) * (size_t)T->ncells);
+    groups_rec(T, 0);
+    T->glo = malloc(sizeof(double[3]) * (size_t)T->ngroups);
+    T->ghi = malloc(sizeof(double[3]) * (size_t)T->ngroups);
+    T->group_of = malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t g = 0; g < T->ngroups; ++g) {
+      cell_t* c = &T->cells[T->groups[g]];
+      for (int a = 0; a < 3; ++a) { T->glo[g][a] = INFINITY; T->ghi[g][a] = -INFINITY; }
+      for (int64_t s = c->first; s < c->first + c->count; ++s) {
+        T->group_of[s] = g;
+        for (int a = 0; a < 3; ++a) {
+          double v = T->sx[a][s];
+          if (v < T->glo[g][a]) T->glo[g][a] = v;
+          if (v > T->ghi[g][a]) T->ghi[g][a] = v;
+        }
+      }
+    }
+    if (prm->periodic) far_setup(T);
+  }
+  return T;
+}
+
+void or_tree_free(void* h) {
+  tree_t* T = h;
+  if (!T) return;
+  for (int a = 0; a < 3; ++a) { free(T->x[a]); free(T->sx[a]); }
+  free(T->mass); free(T->sm); free(T->key); free(T->skey); free(T->perm);
+  for (int64_t c = 0; c < T->ncells; ++c) free(T->cells[c].M);
+  free(T->cells); free(T->groups); free(T->glo); free(T->ghi); free(T->group_of);
+  if (T->p2p) {
+    for (int64_t g = 0; g < T->ngroups; ++g) {
+      free(T->p2p[g].img); free(T->p2p[g].cell); free(T->m2p[g].img); free(T->m2p[g].cell);
+    }
+    free(T->p2p); free(T->m2p);
+  }
+  free(T->Tpsi); free(T->Mroot); free(T->Lam);
+  free(T);
+}
+
+/* ---------------- walk ---------------- */
+
+static void list_push(list_t* l, int img, int64_t cell) {
+  if (l->n == l->cap) {
+    l->cap = l->cap ? 2 * l->cap : 64;
+    l->img = realloc(l->img, sizeof(int32_t) * (size_t)l->cap);
+    l->cell = realloc(l->cell, sizeof(int64_t) * (size_t)l->cap);
+  }
+  l->img[l->n] = img;
+  l->cell[l->n] = cell;
+  l->n++;
+}
+
+static int is_ancestor_or_self(const cell_t* B, const cell_t* A) {
+  if (B->level > A->level) return 0;
+  return (A->key >> (3 * (A->level - B->level))) == B->key;
+}
+
+static int mac_accept(const tree_t* T, int64_t g, const cell_t* B, const int n[3]) {
+  if (!(T->p.theta > 0.0)) return 0;
+  double L = T->p.box;
+  double d[3];
+  for (int a = 0; a < 3; ++a) {
+    double c = B->com[a] + (double)n[a] * L;
+    double lo = T->glo[g][a] - c, hi = c - T->ghi[g][a];
+    double v = lo > hi ? lo : hi;
+    d[a] = v > 0.0 ? v : 0.0;
+  }
+  double d2 = d[0] * d[0];
+  d2 = d2 + d[1] * d[1];
+  d2 = d2 + d[2] * d[2];
+  double rc2 = B->rcrit * B->rcrit;
+  return rc2 < d2;
+}
+
+static void walk_rec(tree_t* T, int64_t g, int img, const int n[3], int64_t bi) {
+  const cell_t* A = &T->cells[T->groups[g]];
+  const cell_t* B = &T->cells[bi];
+  int zero = (n[0] == 0 && n[1] == 0 && n[2] == 0);
+  if (zero && bi == T->groups[g]) return; /* own block: handled directly */
+  if (!(zero && is_ancestor_or_self(B, A))) {
+    if (mac_accept(T, g, B, n)) { list_push(&T->m2p[g], img, bi); return; }
+    if (B->is_leaf) { list_push(&T->p2p[g], img, bi); return; }
+  }
+  for (int o = 0; o < 8; ++o)
+    if (B->child[o] >= 0) walk_rec(T, g, img, n, B->child[o]);
+}
+
+void or_tree_walk(void* h) {
+  tree_t* T = h;
+  if (T->walked || T->n == 0) return;
+  T->p2p = calloc((size_t)T->ngroups, sizeof(list_t));
+  T->m2p = calloc((size_t)T->ngroups, sizeof(list_t));
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t g = 0; g < T->ngroups; ++g) {
+    for (int img = 0; img < 27; ++img) {
+      int n[3] = {img / 9 - 1, (img / 3) % 3 - 1, img % 3 - 1};
+      if (!T->p.periodic && img != 13) continue;
+      walk_rec(T, g, img, n, 0);
+    }
+  }
+  T->walked = 1;
+}
+
+/* ---------------- forces ---------------- */
+
+static void pair_add(double tx, double ty, double tz, double sx, double sy, double sz, double m,
+                     double eps2, double* phi, double g[3]) {
+  double d[3] = {sx - tx, sy - ty, sz - tz};
+  double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+  double si = 1.0 / sqrt(s2);
+  double si3 = si * si * si;
+  *phi += m * si;
+  for (int a = 0; a < 3; ++a) g[a] += m * d[a] * si3;
+}
+
+static void m2p_add(const tree_t* T, const cell_t* B, const double R[3], double* phi,
+                    double g[3]) {
+  int p = T->p.order;
+  double Tk[4096];
+  or_green_taylor(p + 1, R, T->p.eps * T->p.eps, Tk);
+  for (int k = 0; k < T->nmom; ++k) {
+    int ka, kb, kc;
+    or_mi_get(k, &ka, &kb, &kc);
+    double sg = ((ka + kb + kc) % 2) ? -1.0 : 1.0;
+    double Mk = sg * B->M[k];
+    *phi += Mk * Tk[k];
+    g[0] += Mk * (ka + 1) * Tk[or_mi(ka + 1, kb, kc)];
+    g[1] += Mk * (kb + 1) * Tk[or_mi(ka, kb + 1, kc)];
+    g[2] += Mk * (kc + 1) * Tk[or_mi(ka, kb, kc + 1)];
+  }
+}
+
+/* accumulate Phi and grad Phi (grad w.r.t. the target position) at sorted
+ * particle s of group g */
+static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, double g_out[3]) {
+  const cell_t* A = &T->cells[T->groups[g]];
+  double L = T->p.box, eps2 = T->p.eps * T->p.eps;
+  double tx = T->sx[0][s], ty = T->sx[1][s], tz = T->sx[2][s];
+  double phi = 0.0, gr[3] = {0, 0, 0};
+  for (int64_t j = A->first; j < A->first + A->count; ++j) {
+    if (j == s) continue;
+    pair_add(tx, ty, tz, T->sx[0][j], T->sx[1][j], T->sx[2][j], T->sm[j], eps2, &phi, gr);
+  }
+  const list_t* lp = &T->p2p[g];
+  for (int64_t e = 0; e < lp->n; ++e) {
+    int img = lp->img[e];
+    double sh[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
+    const cell_t* B = &T->cells[lp->cell[e]];
+    for (int64_t j = B->first; j < B->first + B->count; ++j)
+      pair_add(tx, ty, tz, T->sx[0][j] + sh[0], T->sx[1][j] + sh[1], T->sx[2][j] + sh[2],
+               T->sm[j], eps2, &phi, gr);
+  }
+  const list_t* lm = &T->m2p[g];
+  for (int64_t e = 0; e < lm->n; ++e) {
+    int img = lm->img[e];
+    double sh[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
+    const cell_t* B = &T->cells[lm->cell[e]];
+    double R[3] = {tx - (B->com[0] + sh[0]), ty - (B->com[1] + sh[1]), tz - (B->com[2] + sh[2])};
+    m2p_add(T, B, R, &phi, gr);
+  }
+  if (T->far_ok) {
+    double pf, gf[3];
+    double x[3] = {tx, ty, tz};
+    far_eval(T, x, &pf, gf);
+    phi += pf;
+    for (int a = 0; a < 3; ++a) gr[a] += gf[a];
+  }
+  *phi_out = phi;
+  for (int a = 0; a < 3; ++a) g_out[a] = gr[a];
+}
+
+/* Forces for every particle (ngsel < 0) or for the particles of the listed
+ * groups.  acc is 3 x n SoA in original order, pot is n (may be NULL);
+ * entries of unselected particles are left untouched. */
+void or_tree_forces(void* h, int64_t ngsel, const int64_t* gsel, double* acc, double* pot) {
+  tree_t* T = h;
+  if (T->n == 0) return;
+  or_tree_walk(T);
+  int64_t ng = ngsel < 0 ? T->ngroups : ngsel;
+  double G = T->p.G;
+  int64_t n = T->n;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t gi = 0; gi < ng; ++gi) {
+    int64_t g = ngsel < 0 ? gi : gsel[gi];
+    const cell_t* A = &T->cells[T->groups[g]];
+    for (int64_t s = A->first; s < A->first + A->count; ++s) {
+      double phi, gr[3];
+      target_eval(T, g, s, &phi, gr);
+      int64_t i = T->perm[s];
+      for (int a = 0; a < 3; ++a) acc[a * n + i] = G * gr[a];
+      if (pot) pot[i] = -G * phi;
+    }
+  }
+}
+
+/* 27-image softened direct sum plus the far-field expansion, for a set of
+ * targets given by original index: the tree result at theta = 0. */
+void or_direct_near_far(void* h, int64_t nt, const int64_t* tgt, double* acc, double* pot) {
+  tree_t* T = h;
+  double L = T->p.box, eps2 = T->p.eps * T->p.eps, G = T->p.G;
+  int64_t n = T->n;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t t = 0; t < nt; ++t) {
+    int64_t i = tgt[t];
+    double tx = T->x[0][i], ty = T->x[1][i], tz = T->x[2][i];
+    double phi = 0.0, gr[3] = {0, 0, 0};
+    for (int img = 0; img < 27; ++img) {
+      if (!T->p.periodic && img != 13) continue;
+      double sh[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
+      for (int64_t j = 0; j < n; ++j) {
+        if (img == 13 && j == i) continue;
+        pair_add(tx, ty, tz, T->x[0][j] + sh[0], T->x[1][j] + sh[1], T->x[2][j] + sh[2],
+                 T->mass[j], eps2, &phi, gr);
+      }
+    }
+    if (T->far_ok) {
+      double pf, gf[3], x[3] = {tx, ty, tz};
+      far_eval(T, x, &pf, gf);
+      phi += pf;
+      for (int a = 0; a < 3; ++a) gr[a] += gf[a];
+    }
+    for (int a = 0; a < 3; ++a) acc[a * nt + t] = G * gr[a];
+    if (pot) pot[t] = -G * phi;
+  }
+}
+
+/* ---------------- accessors ---------------- */
+
+int64_t or_tree_ncells(void* h) { return ((tree_t*)h)->ncells; }
+int64_t or_tree_ngroups(void* h) { return ((tree_t*)h)->ngroups; }
+
+void or_tree_perm(void* h, int64_t* perm, uint64_t* skeys) {
+  tree_t* T = h;
+  for (int64_t s = 0; s < T->n; ++s) {
+    if (perm) perm[s] = T->perm[s];
+    if (skeys) skeys[s] = T->skey[s];
+  }
+}
+
+void or_tree_cells(void* h, uint64_t* key, int32_t* level, int64_t* first, int64_t* count,
+                   int32_t* is_leaf, double* mass, double* com, double* rcrit) {
+  tree_t* T = h;
+  int64_t nc = T->ncells;
+  for (int64_t c = 0; c < nc; ++c) {
+    const cell_t* C = &T->cells[c];
+    if (key) key[c] = C->key;
+    if (level) level[c] = C->level;
+    if (first) first[c] = C->first;
+    if (count) count[c] = C->count;
+    if (is_leaf) is_leaf[c] = C->is_leaf;
+    if (mass) mass[c] = C->m;
+    if (com)
+      for (int a = 0; a < 3; ++a) com[a * nc + c] = C->com[a];
+    if (rcrit) rcrit[c] = C->rcrit;
+  }
+}
+
+/* raw moments of cell c about its centre of mass (or_nterms(order) values) */
+void or_tree_cell_moments(void* h, int64_t c, double* M) {
+  tree_t* T = h;
+  memcpy(M, T->cells[c].M, sizeof(double) * (size_t)T->nmom);
+}
+
+void or_tree_groups(void* h, int64_t* cell, double* lo, double* hi) {
+  tree_t* T = h;
+  int64_t ng = T->ngroups;
+  for (int64_t g = 0; g < ng; ++g) {
+    if (cell) cell[g] = T->groups[g];
+    for (int a = 0; a < 3; ++a) {
+      if (lo) lo[a * ng + g] = T->glo[g][a];
+      if (hi) hi[a * ng + g] = T->ghi[g][a];
+    }
+  }
+}
+
+/* total list lengths (kind 0: direct, 1: multipole) */
+int64_t or_tree_list_total(void* h, int kind) {
+  tree_t* T = h;
+  or_tree_walk(T);
+  int64_t t = 0;
+  for (int64_t g = 0; g < T->ngroups; ++g) t += (kind ? T->m2p[g].n : T->p2p[g].n);
+  return t;
+}
+
+/* offsets (ngroups+1), image indices and cell indices of all lists of a kind,
+ * groups in order, entries in walk order (image, then pre-order) */
+void or_tree_lists(void* h, int kind, int64_t* off, int32_t* img, int64_t* cell) {
+  tree_t* T = h;
+  or_tree_walk(T);
+  int64_t t = 0;
+  for (int64_t g = 0; g < T->ngroups; ++g) {
+    const list_t* l = kind ? &T->m2p[g] : &T->p2p[g];
+    off[g] = t;
+    for (int64_t e = 0; e < l->n; ++e) {
+      img[t] = l->img[e];
+      cell[t] = l->cell[e];
+      ++t;
+    }
+  }
+  off[T->ngroups] = t;
+}
+
+/* direct-interaction pair count (own blocks included) */
+int64_t or_tree_pair_count(void* h) {
+  tree_t* T = h;
+  or_tree_walk(T);
+  int64_t t = 0;
+  for (int64_t g = 0; g < T->ngroups; ++g) {
+    const cell_t* A = &T->cells[T->groups[g]];
+    int64_t src = A->count - 1;
+    for (int64_t e = 0; e < T->p2p[g].n; ++e) src += T->cells[T->p2p[g].cell[e]].count;
+    t += A->count * src;
+    (void)src;
+  }
+  return t;
+}
+
+void or_tree_far(void* h, double* Tpsi, double* Mroot, double* Lam) {
+  tree_t* T = h;
+  int pf = T->p.far_order;
+  if (!T->far_ok) return;
+  if (Tpsi) memcpy(Tpsi, T->Tpsi, sizeof(double) * (size_t)or_nterms(2 * pf));
+  if (Mroot) memcpy(Mroot, T->Mroot, sizeof(double) * (size_t)or_nterms(pf));
+  if (Lam) memcpy(Lam, T->Lam, sizeof(double) * (size_t)or_nterms(pf));
+}
+
+/* Multipole interaction of one cell built from the given particles (about
+ * their centre of mass) at point x: value of Phi and grad Phi, order p. */
+void or_multipole_eval(int64_t n, const double* pos, const double* mass, int order, double eps,
+                       const double x[3], double* phi, double g[3]) {
+  or_mi_init();
+  double m = 0, mx[3] = {0, 0, 0};
+  for (int64_t j = 0; j < n; ++j) {
+    m += mass[j];
+    for (int a = 0; a < 3; ++a) mx[a] += mass[j] * pos[a * n + j];
+  }
+  double com[3] = {mx[0] / m, mx[1] / m, mx[2] / m};
+  int nm = or_nterms(order);
+  double M[4096];
+  memset(M, 0, sizeof(double) * (size_t)nm);
+  for (int64_t j = 0; j < n; ++j) {
+    for (int k = 0; k < nm; ++k) {
+      int ka, kb, kc;
+      or_mi_get(k, &ka, &kb, &kc);
+      M[k] += mass[j] * pow(pos[j] - com[0], ka) * pow(pos[n + j] - com[1], kb) *
+              pow(pos[2 * n + j] - com[2], kc);
+    }
+  }
+  double R[3] = {x[0] - com[0], x[1] - com[1], x[2] - com[2]};
+  double Tk[4096];
+  or_green_taylor(order + 1, R, eps * eps, Tk);
+  double P = 0, G3[3] = {0, 0, 0};
+  for (int k = 0; k < nm; ++k) {
+    int ka, kb, kc;
+    or_mi_get(k, &ka, &kb, &kc);
+    double Mk = (((ka + kb + kc) % 2) ? -1.0 : 1.0) * M[k];
+    P += Mk * Tk[k];
+    G3[0] += Mk * (ka + 1) * Tk[or_mi(ka + 1, kb, kc)];
+    G3[1] += Mk * (kb + 1) * Tk[or_mi(ka, kb + 1, kc)];
+    G3[2] += Mk * (kc + 1) * Tk[or_mi(ka, kb, kc + 1)];
+  }
+  *phi = P;
+  for (int a = 0; a < 3; ++a) g[a] = G3[a];
+}
+
+/* plain open-boundary direct sum (no images): the textbook softened sum */
+void or_direct_open(int64_t n, const double* pos, const double* mass, double G, double eps,
+                    double* acc, double* pot) {
+  double eps2 = eps * eps;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double phi = 0, gr[3] = {0, 0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      pair_add(pos[i], pos[n + i], pos[2 * n + i], pos[j], pos[n + j], pos[2 * n + j], mass[j],
+               eps2, &phi, gr);
+    }
+    for (int a = 0; a < 3; ++a) acc[a * n + i] = G * gr[a];
+    if (pot) pot[i] = -G * phi;
+  }
+}
