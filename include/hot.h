@@ -1,0 +1,225 @@
+/* libhot -- periodic tree-gravity force evaluation on one AMD Instinct MI355X
+ * (gfx950), behind a plain C ABI.
+ *
+ * The method is the pure tree code of the paper's Sec. 2.1 ("2HOT"):
+ * particles get 64-bit Morton keys, are sorted by key, a hashed oct-tree is
+ * built over the sorted list, cells carry truncated Cartesian multipole
+ * expansions, and groups of nearby sink particles share one interaction list
+ * produced by a tree walk with a multipole acceptance test (the m x n
+ * bundling of sinks and sources).  Periodic boundaries: the 27 nearest images
+ * of the box are walked explicitly; every further image enters through
+ * high-order local expansions of the Ewald-summed remainder about the centres
+ * of the box's 8 octants (Sec. 2.1, the p=8 periodic local expansion), which
+ * also subtracts the uniform background density.  A kick-drift-kick step wraps the force
+ * evaluation (Sec. 2.1 uses an adaptive symplectic integrator; this library
+ * offers the fixed-step leapfrog).
+ *
+ * Conventions for every call
+ * --------------------------
+ *  - Arrays are device pointers (HIP global memory) owned by the caller,
+ *    structure-of-arrays: positions are 3 x n FP64 (x[0..n), y[0..n),
+ *    z[0..n)); accelerations 3 x n; masses and potentials n.  The element type
+ *    of mass, acc, pot and vel is FP64 when hot_params.precision == HOT_FP64
+ *    and FP32 when it is HOT_FP32; positions are always FP64.
+ *  - Positions may lie anywhere in (-L, 2L) per axis; they are wrapped into
+ *    [0, L) internally.  Values outside that range, NaN or Inf give
+ *    HOT_EINVAL.  Masses must be >= 0.
+ *  - Units: potential phi_i = -G sum_j m_j g(x_i - x_j) and acceleration
+ *    a_i = -grad phi_i, with the Plummer kernel g(r) = (|r|^2+eps^2)^(-1/2)
+ *    on the 27 nearest images and the unsoftened Ewald kernel (neutralising
+ *    background) on all others; a particle's own periodic images contribute.
+ *  - Scratch memory comes from the caller: every compute call takes a device
+ *    workspace of at least hot_workspace_size(ctx, n) bytes, aligned to 256
+ *    bytes.  The library never allocates device memory in a compute call; it
+ *    owns only the context (parameters, the Ewald table, a few device
+ *    constants), created by hot_create and released by hot_destroy.
+ *  - Calls are enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*; NULL = the default stream).  A compute call synchronises that
+ *    stream a few times to size its launches (tree levels, list totals) and
+ *    returns after the last kernel is enqueued; outputs are ready once the
+ *    stream is synchronised.
+ *  - Errors are status codes; nothing throws across the ABI.  A message for
+ *    the last failure on the calling thread is in hot_last_error().  Inputs
+ *    are never modified, except the in/out arrays of hot_kdk.
+ *  - HOT_EOVERFLOW means a data-dependent capacity (cells or interaction
+ *    lists) did not fit in the workspace.  The context records what was
+ *    needed; call hot_workspace_size again (it now returns a larger size),
+ *    allocate that much and repeat the call.  Nothing was written to outputs.
+ *  - One context may be used by one host thread at a time.
+ */
+#ifndef HOT_H
+#define HOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HOT_OK = 0,
+  HOT_EINVAL = 1,       /* bad argument or input value */
+  HOT_ENOMEM = 2,       /* workspace smaller than hot_workspace_size() */
+  HOT_EOVERFLOW = 3,    /* data-dependent capacity exceeded; resize, retry */
+  HOT_EDEVICE = 4,      /* a HIP runtime call failed; see hot_last_error() */
+  HOT_EUNSUPPORTED = 5  /* parameter combination not built into the library */
+} hot_status;
+
+typedef enum { HOT_FP64 = 0, HOT_FP32 = 1 } hot_precision;
+
+/* Parameters of one simulation (paper Sec. 2.1; the opening angle and the
+ * multipole order stand in for the paper's error-tolerance parameter). */
+typedef struct {
+  double box;      /* side L of the periodic cube, > 0 */
+  double G;        /* gravitational constant */
+  double eps;      /* Plummer softening length, >= 0 */
+  double theta;    /* opening angle, 0 <= theta < 1; 0 = exact direct sum */
+  int order;       /* multipole order p of cells, 0..4 (2 = quadrupole,
+                      4 = hexadecapole: the leaf-level expansions of Sec. 2.1) */
+  int periodic;    /* 1 = periodic box, 0 = open boundaries (no images) */
+  int leaf_max;    /* a cell with more particles is split (1..255) */
+  int group_max;   /* sink groups: largest cells with at most this many
+                      particles share an interaction list (1..4096) */
+  int far_order;   /* order of the periodic far-field local expansion,
+                      0..12 (the paper uses 8) */
+  int precision;   /* hot_precision: FP64 throughout, or FP32 interaction
+                      arithmetic on cell-relative coordinates with
+                      compensated accumulation and FP64 positions, cell
+                      centres of mass, moments and far field */
+} hot_params;
+
+/* Per-call statistics of the last compute call on a context. */
+typedef struct {
+  int64_t n;              /* particles */
+  int64_t ncells;         /* tree cells */
+  int64_t ngroups;        /* sink groups */
+  int64_t nlevels;        /* deepest level + 1 */
+  int64_t p2p_entries;    /* direct-interaction list entries (leaf x image) */
+  int64_t m2p_entries;    /* multipole list entries (cell x image) */
+  int64_t p2p_pairs;      /* particle-particle interactions evaluated */
+  int64_t m2p_pairs;      /* particle-cell interactions evaluated */
+  double flops_p2p;       /* algorithmic flops of the direct kernel */
+  double flops_m2p;       /* algorithmic flops of the multipole kernel */
+  double ms_total;        /* stream time of the whole call (ms) */
+  double ms_sort;         /* keys + sort + gather */
+  double ms_build;        /* tree levels, moments, groups */
+  double ms_walk;         /* both walk passes */
+  double ms_p2p;          /* direct kernel */
+  double ms_m2p;          /* multipole kernel */
+  double ms_far;          /* far field + unpermute */
+  size_t ws_bytes_needed; /* workspace that would have sufficed */
+} hot_stats;
+
+/* Host copies of the internal structures of the last hot_forces call, for
+ * checking against an independent implementation.  The caller passes host
+ * buffers of the sizes given by hot_debug_sizes (any may be NULL to skip).
+ * Cells are in the library's internal order; lists are grouped per sink
+ * group in the internal group order.  List entries encode (image << 27) |
+ * cell, image = (nx+1)*9 + (ny+1)*3 + (nz+1). */
+typedef struct {
+  uint64_t* sorted_keys;  /* n */
+  uint32_t* perm;         /* n: sorted position -> original index */
+  uint64_t* cell_key;     /* ncells: Morton key with placeholder bit */
+  int32_t* cell_level;    /* ncells */
+  int32_t* cell_first;    /* ncells: first sorted particle */
+  int32_t* cell_count;    /* ncells */
+  double* cell_com;       /* 3 x ncells SoA */
+  double* cell_mass;      /* ncells */
+  int32_t* group_cell;    /* ngroups: cell index of each sink group */
+  int64_t* p2p_offset;    /* ngroups + 1 */
+  uint32_t* p2p_entry;    /* p2p_entries */
+  int64_t* m2p_offset;    /* ngroups + 1 */
+  uint32_t* m2p_entry;    /* m2p_entries */
+} hot_debug;
+
+typedef struct hot_ctx hot_ctx;
+
+/* Create a context.  Validates the parameters (HOT_EINVAL), builds the
+ * far-field Ewald table on the host in FP64 and uploads it (HOT_EDEVICE on
+ * a HIP failure).  Uses the current HIP device.  *out is NULL on failure. */
+hot_status hot_create(const hot_params* params, hot_ctx** out);
+
+/* Release a context (NULL is allowed). */
+void hot_destroy(hot_ctx* ctx);
+
+/* Bytes of device workspace a compute call needs for n particles.  Grows
+ * after a HOT_EOVERFLOW so that a retry fits.  0 if ctx is NULL. */
+size_t hot_workspace_size(const hot_ctx* ctx, size_t n);
+
+/* Accelerations and potentials of n particles (paper Sec. 2.1: the force
+ * evaluation of one timestep).
+ *   pos   device, 3 x n FP64 SoA, read only
+ *   mass  device, n, FP64 or FP32 (precision), read only
+ *   acc   device, 3 x n (precision), written
+ *   pot   device, n (precision), written; may be NULL
+ *   workspace, ws_bytes  device scratch (>= hot_workspace_size)
+ *   stream  hipStream_t or NULL
+ * Returns HOT_OK, HOT_EINVAL (n == 0 is allowed and does nothing; NULL
+ * pointers with n > 0, non-finite or out-of-range positions), HOT_ENOMEM,
+ * HOT_EOVERFLOW or HOT_EDEVICE. */
+hot_status hot_forces(hot_ctx* ctx, size_t n, const double* pos, const void* mass, void* acc,
+                      void* pot, void* workspace, size_t ws_bytes, void* stream);
+
+/* nsteps fixed-step kick-drift-kick leapfrog steps of length dt:
+ * v += a dt/2; x = wrap(x + v dt); a = forces(x); v += a dt/2.
+ *   pos   device, 3 x n FP64, in/out (wrapped into [0, L) on return)
+ *   vel   device, 3 x n (precision), in/out
+ *   mass  device, n (precision), read only
+ *   acc   device, 3 x n (precision), in/out: on entry the accelerations at
+ *         pos if (flags & HOT_ACC_VALID), otherwise they are computed first;
+ *         on return the accelerations at the final positions
+ *   pot   device, n (precision) or NULL: potentials at the final positions
+ * Same errors as hot_forces. */
+#define HOT_ACC_VALID 1u
+hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* mass, void* acc,
+                   void* pot, double dt, int nsteps, unsigned flags, void* workspace,
+                   size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of hot_forces (an extension beyond the paper):
+ * given cotangents gacc (3 x n) and gpot (n, or NULL for zero) of the
+ * outputs, returns
+ *   xbar = (d acc/d pos)^T gacc + (d pot/d pos)^T gpot   (3 x n FP64)
+ *   mbar = (d acc/d mass)^T gacc + (d pot/d mass)^T gpot (n, precision)
+ * for the tree approximation of the forces at the same parameters (the
+ * exact derivative of the direct sum when theta == 0).  gacc, gpot and mbar
+ * use the precision type; xbar is FP64.  Same errors as hot_forces;
+ * HOT_EUNSUPPORTED if the build lacks the adjoint for the order. */
+hot_status hot_vjp(hot_ctx* ctx, size_t n, const double* pos, const void* mass, const void* gacc,
+                   const void* gpot, double* xbar, void* mbar, void* workspace, size_t ws_bytes,
+                   void* stream);
+
+/* Statistics of the last compute call (synchronises nothing). */
+hot_status hot_get_stats(const hot_ctx* ctx, hot_stats* out);
+
+/* Sizes for hot_debug_export after the last hot_forces call. */
+hot_status hot_debug_sizes(const hot_ctx* ctx, int64_t* n, int64_t* ncells, int64_t* ngroups,
+                           int64_t* p2p_entries, int64_t* m2p_entries);
+
+/* Copy the internal structures of the last hot_forces call to host buffers
+ * (synchronises the stream of that call).  The workspace of that call must
+ * still hold its contents.  HOT_EINVAL if no hot_forces call preceded. */
+hot_status hot_debug_export(hot_ctx* ctx, void* workspace, hot_debug* out);
+
+/* A Taylor table of the periodic far field, as built by hot_create:
+ * Tpsi_s = d^s Psi(r0) / s!, |s| <= 2 far_order, of the periodic remainder
+ * Psi = Ewald potential minus the 27 nearest bare images (paper Sec. 2.1:
+ * the periodic local expansion), about the point r0 = (dx, dy, dz) L/2 with
+ * offset = (dx+1)*9 + (dy+1)*3 + (dz+1), dx, dy, dz in {-1, 0, 1}: the
+ * offsets between the centres of the 8 octants about which the far field is
+ * expanded.  Multi-indices (a,b,c) are ordered by total degree, then a
+ * descending, then b descending.  out: host array of count >=
+ * (D+1)(D+2)(D+3)/6 doubles, D = 2 far_order.  Host-only; touches no GPU.
+ * HOT_EINVAL on bad arguments. */
+hot_status hot_far_table(int far_order, double box, int offset, double* out, size_t count);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* hot_last_error(void);
+
+/* Library version string. */
+const char* hot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOT_H */

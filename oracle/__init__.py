@@ -79,6 +79,8 @@ def lib():
         L.or_tree_list_total.restype = i64
         L.or_tree_list_total.argtypes = [vp, C.c_int]
         L.or_tree_lists.argtypes = [vp, C.c_int, i64p, i32p, i64p]
+        L.or_tree_group_list.restype = i64
+        L.or_tree_group_list.argtypes = [vp, i64, C.c_int, i32p, i64p]
         L.or_tree_pair_count.restype = i64
         L.or_tree_pair_count.argtypes = [vp]
         L.or_tree_forces.argtypes = [vp, i64, i64p, dp, dp]
@@ -91,6 +93,7 @@ def lib():
         L.or_sort.argtypes = [i64, u64p, i64p]
         L.or_green_taylor.argtypes = [C.c_int, dp, C.c_double, dp]
         L.or_psi_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, dp]
+        L.or_psi_table_at.argtypes = [C.c_int, C.c_double, dp, C.c_double, C.c_int, C.c_int, dp]
         L.or_ewald_psi.argtypes = [dp, C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
         L.or_ewald_xi.restype = C.c_double
         L.or_ewald_xi.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
@@ -147,6 +150,17 @@ def psi_table(D: int, box: float = 1.0, alpha: float | None = None, nreal: int =
     alpha = 2.0 / box if alpha is None else alpha
     out = np.zeros(L.or_nterms(D))
     L.or_psi_table(D, box, alpha, nreal, kmax, _p(out))
+    return out
+
+
+def psi_table_at(D: int, r0, box: float = 1.0, alpha: float | None = None, nreal: int = 5,
+                 kmax: int = 6) -> np.ndarray:
+    """Taylor coefficients d^s Psi(r0)/s! of the periodic remainder about r0."""
+    L = lib()
+    alpha = 2.0 / box if alpha is None else alpha
+    r0 = np.ascontiguousarray(r0, dtype=np.float64)
+    out = np.zeros(L.or_nterms(D))
+    L.or_psi_table_at(D, box, _p(r0), alpha, nreal, kmax, _p(out))
     return out
 
 
@@ -288,14 +302,24 @@ class Tree:
                                _p(cell, C.c_int64))
         return off, img, cell
 
+    def group_list(self, g: int, kind: int):
+        """(image[E], cell[E]) of group g's list of a kind (walks g only)."""
+        m = self.lib.or_tree_group_list(self.h, int(g), kind, None, None)
+        img = np.zeros(m, np.int32)
+        cell = np.zeros(m, np.int64)
+        self.lib.or_tree_group_list(self.h, int(g), kind, _p(img, C.c_int32), _p(cell, C.c_int64))
+        return img, cell
+
     def pair_count(self) -> int:
         return int(self.lib.or_tree_pair_count(self.h))
 
     def far(self):
+        """(Tpsi[27, nt(2p)], M[8, nt(p)], Lam[8, nt(p)]): the 27 offset tables,
+        octant moments and octant local coefficients."""
         pf = int(self.params.get("far_order", 8))
-        T = np.zeros(self.lib.or_nterms(2 * pf))
-        M = np.zeros(self.lib.or_nterms(pf))
-        Lm = np.zeros(self.lib.or_nterms(pf))
+        T = np.zeros((27, self.lib.or_nterms(2 * pf)))
+        M = np.zeros((8, self.lib.or_nterms(pf)))
+        Lm = np.zeros((8, self.lib.or_nterms(pf)))
         self.lib.or_tree_far(self.h, _p(T), _p(M), _p(Lm))
         return T, M, Lm
 

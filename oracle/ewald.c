@@ -152,27 +152,51 @@ static void compose_radial(int D, const double c[3], const double* phi, int M, d
   free(t); free(P); free(Q);
 }
 
-void or_psi_table(int D, double L, double alpha, int nreal, int kmax, double* T) {
+/* Taylor coefficients of Psi about the point r0 (|r0|_inf <= L/2):
+ * T_s = d^s Psi(r0) / s!.  Each real-space image term is a radial function
+ * of |r0 + nL + h| expanded about c = r0 + nL; the reciprocal terms use
+ * cos(a + w.h) = cos(a) cos(w.h) - sin(a) sin(w.h), a = w.r0. */
+void or_psi_table_at(int D, double L, const double r0[3], double alpha, int nreal, int kmax,
+                     double* T) {
   or_mi_init();
   int nt = or_nterms(D);
   memset(T, 0, sizeof(double) * (size_t)nt);
   double phi[OR_DMAX + 3], tmp[OR_DMAX + 3];
-  /* real space: erfc images beyond the near zone, minus erf of the near zone */
   for (int nx = -nreal; nx <= nreal; ++nx)
     for (int ny = -nreal; ny <= nreal; ++ny)
       for (int nz = -nreal; nz <= nreal; ++nz) {
         int ninf = abs(nx) > abs(ny) ? abs(nx) : abs(ny);
         if (abs(nz) > ninf) ninf = abs(nz);
-        double c[3] = {nx * L, ny * L, nz * L};
+        double c[3] = {r0[0] + nx * L, r0[1] + ny * L, r0[2] + nz * L};
         double u0 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
         if (ninf >= 2) {
           erfc_over_r_series(u0, alpha, D, phi);
           compose_radial(D, c, phi, D, 1.0, T);
-        } else if (ninf == 1) {
+        } else if (u0 >= L * L) {
           /* -erf/r = erfc/r - 1/r */
           erfc_over_r_series(u0, alpha, D, phi);
           inv_sqrt_series(u0, D, tmp);
           for (int m = 0; m <= D; ++m) phi[m] -= tmp[m];
+          compose_radial(D, c, phi, D, 1.0, T);
+        } else if (u0 > 0.0) {
+          /* close to the origin erfc/r - 1/r cancels many digits: expand the
+           * entire function f(u) = erf(a sqrt u)/sqrt u
+           *   = 2a/sqrt(pi) sum_k (-a^2 u)^k / (k! (2k+1))
+           * about u0 directly: f^(m)(u0)/m! = 2a/sqrt(pi)
+           *   sum_{k>=m} (-a^2)^k C(k,m) u0^(k-m) / (k! (2k+1)) */
+          for (int m = 0; m <= D; ++m) {
+            double acc = 0.0, term = 0.0;
+            for (int k = m; k <= m + 80; ++k) {
+              /* (-a^2)^k C(k,m) u0^(k-m) / k! = (-a^2)^k u0^(k-m) / (m! (k-m)!) */
+              if (k == m) {
+                term = pow(-alpha * alpha, m) / or_factorial(m);
+              } else {
+                term *= -alpha * alpha * u0 / (double)(k - m);
+              }
+              acc += term / (2.0 * k + 1.0);
+            }
+            phi[m] = -TWO_OVER_SQRTPI * alpha * acc;
+          }
           compose_radial(D, c, phi, D, 1.0, T);
         } else {
           /* -erf(a sqrt u)/sqrt u at u0=0: entire series in u */
@@ -184,7 +208,7 @@ void or_psi_table(int D, double L, double alpha, int nreal, int kmax, double* T)
           compose_radial(D, c, phi, D / 2, 1.0, T);
         }
       }
-  /* reciprocal space: cos(w.h) = sum_{m even} (-1)^{m/2} (w.h)^m / m! */
+  /* reciprocal space: cos(w.h) and sin(w.h) from the powers of w.h */
   double* lin = calloc((size_t)nt, sizeof(double));
   double* P = calloc((size_t)nt, sizeof(double));
   double* Q = calloc((size_t)nt, sizeof(double));
@@ -196,27 +220,37 @@ void or_psi_table(int D, double L, double alpha, int nreal, int kmax, double* T)
         double k2 = (double)(kx * kx + ky * ky + kz * kz);
         double A = pre * exp(-M_PI * M_PI * k2 / (alpha * alpha * L * L)) / k2;
         if (A == 0.0) continue;
+        double w[3] = {2 * M_PI * kx / L, 2 * M_PI * ky / L, 2 * M_PI * kz / L};
+        double a = w[0] * r0[0] + w[1] * r0[1] + w[2] * r0[2];
+        double ca = cos(a), sa = sin(a);
         memset(lin, 0, sizeof(double) * (size_t)nt);
         if (D >= 1) {
-          lin[or_mi(1, 0, 0)] = 2 * M_PI * kx / L;
-          lin[or_mi(0, 1, 0)] = 2 * M_PI * ky / L;
-          lin[or_mi(0, 0, 1)] = 2 * M_PI * kz / L;
+          lin[or_mi(1, 0, 0)] = w[0];
+          lin[or_mi(0, 1, 0)] = w[1];
+          lin[or_mi(0, 0, 1)] = w[2];
         }
         memset(P, 0, sizeof(double) * (size_t)nt);
         P[0] = 1.0;
-        T[0] += A;
+        T[0] += A * ca;
         double fact = 1.0;
         for (int m = 1; m <= D; ++m) {
           or_ser_mul(D, lin, P, Q);
           memcpy(P, Q, sizeof(double) * (size_t)nt);
           fact *= m;
-          if (m % 2) continue;
-          double s = ((m / 2) % 2 ? -1.0 : 1.0) * A / fact;
+          /* cos(a + x) = sum_m x^m/m! * {cos a, -sin a, -cos a, sin a}[m % 4] */
+          double cm = (m % 4 == 0) ? ca : (m % 4 == 1) ? -sa : (m % 4 == 2) ? -ca : sa;
+          double s = A * cm / fact;
+          if (s == 0.0) continue;
           for (int i = 0; i < nt; ++i) T[i] += s * P[i];
         }
       }
   free(lin); free(P); free(Q);
   T[0] -= M_PI / (alpha * alpha * L * L * L);
+}
+
+void or_psi_table(int D, double L, double alpha, int nreal, int kmax, double* T) {
+  const double r0[3] = {0.0, 0.0, 0.0};
+  or_psi_table_at(D, L, r0, alpha, nreal, kmax, T);
 }
 
 /* ---------------- O1: direct periodic sum ---------------- */

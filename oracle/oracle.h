@@ -48,6 +48,9 @@ void or_green_taylor(int D, const double R[3], double eps2, double* T);
 /* Taylor table Tpsi_s = d^s Psi(0)/s!, |s| <= D, where Psi is the Ewald
  * potential minus the 27 nearest bare images. */
 void or_psi_table(int D, double box, double alpha, int nreal, int kmax, double* T);
+/* the same table about an expansion point r0 (|r0|_inf <= L/2) */
+void or_psi_table_at(int D, double box, const double r0[3], double alpha, int nreal, int kmax,
+                     double* T);
 /* Ewald potential psi_E(r) of a unit mass with neutralising background
  * (value) and its gradient; r must not be a lattice vector. */
 void or_ewald_psi(const double r[3], double box, double alpha, int nreal, int kmax,

@@ -17,7 +17,7 @@
  *     opens other cells;
  *  7. forces: direct softened sums over the leaves, multipole interactions
  *     with the Taylor coefficients of the softened Green's function, and the
- *     periodic far field as a local expansion about the box centre.
+ *     periodic far field as local expansions about the 8 octant centres.
  *
  * Deterministic choices the paper leaves open are written out here so that an
  * independent implementation can reproduce keys, order, cells and lists bit
@@ -78,14 +78,14 @@ typedef struct {
   double (*ghi)[3];
   list_t* p2p;
   list_t* m2p;
+  int* gwalked;
   int walked;
   int nmom;          /* or_nterms(order) */
   /* periodic far field */
   int far_ok;
-  double c0[3];
-  double* Tpsi;  /* |s| <= 2 far_order */
-  double* Mroot; /* |k| <= far_order */
-  double* Lam;   /* |q| <= far_order */
+  double* Tpsi;  /* 27 tables (offsets between octant centres), |s| <= 2 far_order */
+  double* Mroot; /* 8 octants x (|k| <= far_order) */
+  double* Lam;   /* 8 octants x (|q| <= far_order) */
 } tree_t;
 
 /* ---------------- keys ---------------- */
@@ -271,18 +271,55 @@ static double binom_mi(int qa, int qb, int qc, int ka, int kb, int kc) {
   return r;
 }
 
+/* octant (level-1 cell) of a wrapped position: the key's top octal digit */
+static int octant_of(uint64_t key) { return (int)((key >> 60) & 7ULL); }
+
+static void octant_center(const tree_t* T, int o, double c[3]) {
+  double h = 0.5 * T->p.box;
+  c[0] = ((double)((o >> 2) & 1) + 0.5) * h;
+  c[1] = ((double)((o >> 1) & 1) + 0.5) * h;
+  c[2] = ((double)(o & 1) + 0.5) * h;
+}
+
+/* Far field about the 8 octant centres c_o.  For a target in octant t and
+ * the sources of octant s, Psi(x - y) is expanded about r0 = c_t - c_s (one
+ * of 27 offsets of L/2 steps), with h = x - c_t and s_j = y_j - c_s:
+ *   Lam^t_q = sum_s sum_k C(q+k, q) (-1)^|k| Tpsi^{c_t - c_s}_{q+k} M^s_k,
+ *   M^s_k = sum_{j in s} m_j s_j^k,   Phi_far(x) = sum_q Lam^t_q h^q. */
 static void far_setup(tree_t* T) {
   int pf = T->p.far_order;
   double L = T->p.box;
   int D = 2 * pf;
   int nT = or_nterms(D), nq = or_nterms(pf);
-  T->Tpsi = calloc((size_t)nT, sizeof(double));
-  /* alpha = 2/L; real images to |n|_inf = 5, reciprocal to |k|_inf = 6 */
-  or_psi_table(D, L, 2.0 / L, 5, 6, T->Tpsi);
-  for (int a = 0; a < 3; ++a) T->c0[a] = 0.5 * L;
-  T->Mroot = calloc((size_t)nq, sizeof(double));
+  T->Tpsi = calloc((size_t)27 * nT, sizeof(double));
+  /* the tables depend only on (far_order, L): keep the last set */
+  static double* cache = NULL;
+  static int cache_D = -1;
+  static double cache_L = 0.0;
+#pragma omp critical(or_far_cache)
+  {
+    if (!(cache && cache_D == D && cache_L == L)) {
+      free(cache);
+      cache = calloc((size_t)27 * nT, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int d = 0; d < 27; ++d) {
+        double r0[3] = {(d / 9 - 1) * 0.5 * L, ((d / 3) % 3 - 1) * 0.5 * L,
+                        (d % 3 - 1) * 0.5 * L};
+        /* alpha = 2/L; real images to |n|_inf = 4 (the first omitted image
+         * is >= 4.5 L away: erfc(9) ~ 4e-37), reciprocal to |k|_inf = 6 */
+        or_psi_table_at(D, L, r0, 2.0 / L, 4, 6, cache + (size_t)d * nT);
+      }
+      cache_D = D;
+      cache_L = L;
+    }
+    memcpy(T->Tpsi, cache, sizeof(double) * 27 * (size_t)nT);
+  }
+  T->Mroot = calloc((size_t)8 * nq, sizeof(double));
   for (int64_t s = 0; s < T->n; ++s) {
-    double d[3] = {T->sx[0][s] - T->c0[0], T->sx[1][s] - T->c0[1], T->sx[2][s] - T->c0[2]};
+    int o = octant_of(T->skey[s]);
+    double c[3];
+    octant_center(T, o, c);
+    double d[3] = {T->sx[0][s] - c[0], T->sx[1][s] - c[1], T->sx[2][s] - c[2]};
     double pw[3][OR_DMAX + 1];
     for (int a = 0; a < 3; ++a) {
       pw[a][0] = 1.0;
@@ -291,41 +328,51 @@ static void far_setup(tree_t* T) {
     for (int k = 0; k < nq; ++k) {
       int ka, kb, kc;
       or_mi_get(k, &ka, &kb, &kc);
-      T->Mroot[k] += T->sm[s] * pw[0][ka] * pw[1][kb] * pw[2][kc];
+      T->Mroot[(size_t)o * nq + k] += T->sm[s] * pw[0][ka] * pw[1][kb] * pw[2][kc];
     }
   }
-  T->Lam = calloc((size_t)nq, sizeof(double));
-  for (int q = 0; q < nq; ++q) {
-    int qa, qb, qc;
-    or_mi_get(q, &qa, &qb, &qc);
-    double acc = 0.0;
-    for (int k = 0; k < nq; ++k) {
-      int ka, kb, kc;
-      or_mi_get(k, &ka, &kb, &kc);
-      double sg = ((ka + kb + kc) % 2) ? -1.0 : 1.0;
-      acc += binom_mi(qa, qb, qc, ka, kb, kc) * sg *
-             T->Tpsi[or_mi(qa + ka, qb + kb, qc + kc)] * T->Mroot[k];
+  T->Lam = calloc((size_t)8 * nq, sizeof(double));
+  for (int t = 0; t < 8; ++t)
+    for (int q = 0; q < nq; ++q) {
+      int qa, qb, qc;
+      or_mi_get(q, &qa, &qb, &qc);
+      double acc = 0.0;
+      for (int so = 0; so < 8; ++so) {
+        int dx = ((t >> 2) & 1) - ((so >> 2) & 1), dy = ((t >> 1) & 1) - ((so >> 1) & 1),
+            dz = (t & 1) - (so & 1);
+        const double* Tp = T->Tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * nT;
+        const double* M = T->Mroot + (size_t)so * nq;
+        for (int k = 0; k < nq; ++k) {
+          int ka, kb, kc;
+          or_mi_get(k, &ka, &kb, &kc);
+          double sg = ((ka + kb + kc) % 2) ? -1.0 : 1.0;
+          acc += binom_mi(qa, qb, qc, ka, kb, kc) * sg * Tp[or_mi(qa + ka, qb + kb, qc + kc)] * M[k];
+        }
+      }
+      T->Lam[(size_t)t * nq + q] = acc;
     }
-    T->Lam[q] = acc;
-  }
   T->far_ok = 1;
 }
 
-/* Phi_far(h) = sum_q Lam_q h^q and its gradient */
-static void far_eval(const tree_t* T, const double x[3], double* phi, double g[3]) {
+/* Phi_far(x) = sum_q Lam^t_q (x - c_t)^q and its gradient; t = octant of x */
+static void far_eval(const tree_t* T, const double x[3], uint64_t key, double* phi, double g[3]) {
   int pf = T->p.far_order;
   int nq = or_nterms(pf);
-  double h[3] = {x[0] - T->c0[0], x[1] - T->c0[1], x[2] - T->c0[2]};
+  int t = octant_of(key);
+  double c[3];
+  octant_center(T, t, c);
+  double h[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
   double pw[3][OR_DMAX + 1];
   for (int a = 0; a < 3; ++a) {
     pw[a][0] = 1.0;
     for (int e = 1; e <= pf; ++e) pw[a][e] = pw[a][e - 1] * h[a];
   }
+  const double* Lm = T->Lam + (size_t)t * nq;
   double P = 0.0, G[3] = {0, 0, 0};
   for (int q = 0; q < nq; ++q) {
     int qa, qb, qc;
     or_mi_get(q, &qa, &qb, &qc);
-    double L = T->Lam[q];
+    double L = Lm[q];
     P += L * pw[0][qa] * pw[1][qb] * pw[2][qc];
     if (qa) G[0] += L * qa * pw[0][qa - 1] * pw[1][qb] * pw[2][qc];
     if (qb) G[1] += L * qb * pw[0][qa] * pw[1][qb - 1] * pw[2][qc];
@@ -401,7 +448,7 @@ void or_tree_free(void* h) {
     for (int64_t g = 0; g < T->ngroups; ++g) {
       free(T->p2p[g].img); free(T->p2p[g].cell); free(T->m2p[g].img); free(T->m2p[g].cell);
     }
-    free(T->p2p); free(T->m2p);
+    free(T->p2p); free(T->m2p); free(T->gwalked);
   }
   free(T->Tpsi); free(T->Mroot); free(T->Lam);
   free(T);
@@ -455,20 +502,44 @@ static void walk_rec(tree_t* T, int64_t g, int img, const int n[3], int64_t bi) 
     if (B->child[o] >= 0) walk_rec(T, g, img, n, B->child[o]);
 }
 
+static void ensure_lists(tree_t* T) {
+  if (T->p2p) return;
+  T->p2p = calloc((size_t)T->ngroups, sizeof(list_t));
+  T->m2p = calloc((size_t)T->ngroups, sizeof(list_t));
+  T->gwalked = calloc((size_t)T->ngroups, sizeof(int));
+}
+
+/* walk one sink group over all images (idempotent) */
+static void walk_group(tree_t* T, int64_t g) {
+  if (T->gwalked[g]) return;
+  for (int img = 0; img < 27; ++img) {
+    int n[3] = {img / 9 - 1, (img / 3) % 3 - 1, img % 3 - 1};
+    if (!T->p.periodic && img != 13) continue;
+    walk_rec(T, g, img, n, 0);
+  }
+  T->gwalked[g] = 1;
+}
+
 void or_tree_walk(void* h) {
   tree_t* T = h;
   if (T->walked || T->n == 0) return;
-  T->p2p = calloc((size_t)T->ngroups, sizeof(list_t));
-  T->m2p = calloc((size_t)T->ngroups, sizeof(list_t));
+  ensure_lists(T);
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int64_t g = 0; g < T->ngroups; ++g) {
-    for (int img = 0; img < 27; ++img) {
-      int n[3] = {img / 9 - 1, (img / 3) % 3 - 1, img % 3 - 1};
-      if (!T->p.periodic && img != 13) continue;
-      walk_rec(T, g, img, n, 0);
-    }
-  }
+  for (int64_t g = 0; g < T->ngroups; ++g) walk_group(T, g);
   T->walked = 1;
+}
+
+/* list of one group: returns its length; fills img/cell when non-NULL */
+int64_t or_tree_group_list(void* h, int64_t g, int kind, int32_t* img, int64_t* cell) {
+  tree_t* T = h;
+  ensure_lists(T);
+  walk_group(T, g);
+  const list_t* l = kind ? &T->m2p[g] : &T->p2p[g];
+  for (int64_t e = 0; e < l->n; ++e) {
+    if (img) img[e] = l->img[e];
+    if (cell) cell[e] = l->cell[e];
+  }
+  return l->n;
 }
 
 /* ---------------- forces ---------------- */
@@ -531,7 +602,7 @@ static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, 
   if (T->far_ok) {
     double pf, gf[3];
     double x[3] = {tx, ty, tz};
-    far_eval(T, x, &pf, gf);
+    far_eval(T, x, T->skey[s], &pf, gf);
     phi += pf;
     for (int a = 0; a < 3; ++a) gr[a] += gf[a];
   }
@@ -545,13 +616,15 @@ static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, 
 void or_tree_forces(void* h, int64_t ngsel, const int64_t* gsel, double* acc, double* pot) {
   tree_t* T = h;
   if (T->n == 0) return;
-  or_tree_walk(T);
+  if (ngsel < 0) or_tree_walk(T);
+  ensure_lists(T);
   int64_t ng = ngsel < 0 ? T->ngroups : ngsel;
   double G = T->p.G;
   int64_t n = T->n;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t gi = 0; gi < ng; ++gi) {
     int64_t g = ngsel < 0 ? gi : gsel[gi];
+    walk_group(T, g);
     const cell_t* A = &T->cells[T->groups[g]];
     for (int64_t s = A->first; s < A->first + A->count; ++s) {
       double phi, gr[3];
@@ -585,7 +658,7 @@ void or_direct_near_far(void* h, int64_t nt, const int64_t* tgt, double* acc, do
     }
     if (T->far_ok) {
       double pf, gf[3], x[3] = {tx, ty, tz};
-      far_eval(T, x, &pf, gf);
+      far_eval(T, x, T->key[i], &pf, gf);
       phi += pf;
       for (int a = 0; a < 3; ++a) gr[a] += gf[a];
     }
@@ -689,9 +762,9 @@ void or_tree_far(void* h, double* Tpsi, double* Mroot, double* Lam) {
   tree_t* T = h;
   int pf = T->p.far_order;
   if (!T->far_ok) return;
-  if (Tpsi) memcpy(Tpsi, T->Tpsi, sizeof(double) * (size_t)or_nterms(2 * pf));
-  if (Mroot) memcpy(Mroot, T->Mroot, sizeof(double) * (size_t)or_nterms(pf));
-  if (Lam) memcpy(Lam, T->Lam, sizeof(double) * (size_t)or_nterms(pf));
+  if (Tpsi) memcpy(Tpsi, T->Tpsi, sizeof(double) * 27 * (size_t)or_nterms(2 * pf));
+  if (Mroot) memcpy(Mroot, T->Mroot, sizeof(double) * 8 * (size_t)or_nterms(pf));
+  if (Lam) memcpy(Lam, T->Lam, sizeof(double) * 8 * (size_t)or_nterms(pf));
 }
 
 /* Multipole interaction of one cell built from the given particles (about

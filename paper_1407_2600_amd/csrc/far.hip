@@ -1,0 +1,255 @@
+// Periodic far field (paper Sec. 2.1: periodic boundary conditions through a
+// high-order multipole local expansion; the uniform background is
+// subtracted).
+//
+// With the 27 nearest images walked explicitly, all other images of every
+// source contribute Psi(x_i - x_j), Psi = Ewald potential minus the 27 bare
+// nearest images, which is smooth inside the box.  It is expanded per pair of
+// octants (level-1 cells): for a target in octant t and the sources of octant
+// s, about r0 = c_t - c_s with h = x - c_t, s_j = x_j - c_s,
+//   Phi_far(x) = sum_q Lam^t_q h^q,
+//   Lam^t_q = sum_s sum_k C(q+k, q) (-1)^|k| Tpsi^{c_t-c_s}_{q+k} M^s_k,
+//   M^s_k = sum_{j in s} m_j s_j^k,
+// |q|, |k| <= far_order, with the 27 Taylor tables Tpsi built on the host.
+// Expanding about octant centres instead of the box centre halves the radius
+// of the expansions and makes the truncation error orders of magnitude
+// smaller at the same order.  Octant s holds a contiguous range of the sorted
+// particles (its keys share the top octal digit), found by binary search.
+// The moments are a blocked reduction (one coefficient per thread, particle
+// powers staged in LDS); the local coefficients one block per target octant;
+// the evaluation one thread per particle in FP64, fused with the scaling
+// (-G, G) and the scatter back to the caller's particle order.
+#include "hot_internal.h"
+
+namespace hot {
+
+constexpr int kFarThreads = 256;
+constexpr int kFarStage = 64;
+
+__device__ __forceinline__ void octant_center(int o, double L, double c[3]) {
+  const double h = 0.5 * L;
+  c[0] = ((double)((o >> 2) & 1) + 0.5) * h;
+  c[1] = ((double)((o >> 1) & 1) + 0.5) * h;
+  c[2] = ((double)(o & 1) + 0.5) * h;
+}
+
+// first sorted index whose key's top octal digit is >= o (keys ascend, and
+// bit 63 is the placeholder, so the top digit is non-decreasing)
+__device__ __forceinline__ size_t digit_lb(const uint64_t* __restrict__ skey, size_t n,
+                                           uint64_t o) {
+  size_t lo = 0, hi = n;
+  while (lo < hi) {
+    const size_t mid = lo + ((hi - lo) >> 1);
+    if (((skey[mid] >> 60) & 7ull) < o)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// [beg, end) of the sorted particles in octant o
+__device__ __forceinline__ void octant_range(const uint64_t* __restrict__ skey, size_t n, int o,
+                                             size_t* beg, size_t* end) {
+  *beg = digit_lb(skey, n, (uint64_t)o);
+  *end = (o == 7) ? n : digit_lb(skey, n, (uint64_t)(o + 1));
+}
+
+template <int PF>
+__global__ void __launch_bounds__(kFarThreads) k_far_moments(const double* __restrict__ spos,
+                                                              const double* __restrict__ smass,
+                                                              const uint64_t* __restrict__ skey,
+                                                              size_t n, double L, int nblk,
+                                                              double* __restrict__ part) {
+  constexpr int NQ = nt(PF);
+  constexpr MI<PF> mi{};
+  __shared__ double pw[kFarStage][3][PF + 1];
+  __shared__ double ms[kFarStage];
+  const int o = blockIdx.y;
+  size_t obeg, oend;
+  octant_range(skey, n, o, &obeg, &oend);
+  const size_t len = oend - obeg;
+  const size_t chunk = (len + nblk - 1) / nblk;
+  const size_t beg = obeg + (size_t)blockIdx.x * chunk;
+  const size_t end = beg + chunk < oend ? beg + chunk : oend;
+  double c[3];
+  octant_center(o, L, c);
+  constexpr int PER = (NQ + kFarThreads - 1) / kFarThreads;
+  double acc[PER];
+  int ka[PER], kb[PER], kc[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    acc[r] = 0.0;
+    const int k = threadIdx.x + r * kFarThreads;
+    ka[r] = k < NQ ? mi.a[k] : 0;
+    kb[r] = k < NQ ? mi.b[k] : 0;
+    kc[r] = k < NQ ? mi.c[k] : 0;
+  }
+  for (size_t b0 = beg; b0 < end; b0 += kFarStage) {
+    if (threadIdx.x < kFarStage) {
+      const size_t s = b0 + threadIdx.x;
+      const bool ok = s < end;
+      const double d[3] = {ok ? spos[s] - c[0] : 0.0, ok ? spos[n + s] - c[1] : 0.0,
+                           ok ? spos[2 * n + s] - c[2] : 0.0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double p = 1.0;
+        pw[threadIdx.x][a][0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= PF; ++e) {
+          p *= d[a];
+          pw[threadIdx.x][a][e] = p;
+        }
+      }
+      ms[threadIdx.x] = ok ? smass[s] : 0.0;
+    }
+    __syncthreads();
+    for (int p = 0; p < kFarStage; ++p) {
+      const double m = ms[p];
+#pragma unroll
+      for (int r = 0; r < PER; ++r)
+        acc[r] += m * pw[p][0][ka[r]] * pw[p][1][kb[r]] * pw[p][2][kc[r]];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int k = threadIdx.x + r * kFarThreads;
+    if (k < NQ) part[((size_t)o * nblk + blockIdx.x) * NQ + k] = acc[r];
+  }
+}
+
+// one block per target octant t
+template <int PF>
+__global__ void __launch_bounds__(512) k_far_lambda(const double* __restrict__ part, int nblk,
+                                                    const double* __restrict__ tpsi,
+                                                    double* __restrict__ mom,
+                                                    double* __restrict__ lam) {
+  constexpr int NQ = nt(PF);
+  constexpr int NT2 = nt(2 * PF);
+  constexpr MI<PF> mi{};
+  __shared__ double M[8][NQ];
+  const int t = blockIdx.x;
+  for (int i = threadIdx.x; i < 8 * NQ; i += blockDim.x) {
+    const int s = i / NQ, k = i % NQ;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[((size_t)s * nblk + b) * NQ + k];
+    M[s][k] = acc;
+    if (t == 0) mom[i] = acc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NQ; q += blockDim.x) {
+    const int qa = mi.a[q], qb = mi.b[q], qc = mi.c[q];
+    double acc = 0.0;
+    for (int s = 0; s < 8; ++s) {
+      const int dx = ((t >> 2) & 1) - ((s >> 2) & 1), dy = ((t >> 1) & 1) - ((s >> 1) & 1),
+                dz = (t & 1) - (s & 1);
+      const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
+      for (int k = 0; k < NQ; ++k) {
+        const int ka = mi.a[k], kb = mi.b[k], kc = mi.c[k];
+        double bin = 1.0;
+        for (int u = 1; u <= ka; ++u) bin = bin * (double)(qa + u) / (double)u;
+        for (int u = 1; u <= kb; ++u) bin = bin * (double)(qb + u) / (double)u;
+        for (int u = 1; u <= kc; ++u) bin = bin * (double)(qc + u) / (double)u;
+        const double sg = ((ka + kb + kc) & 1) ? -1.0 : 1.0;
+        acc += sg * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)] * M[s][k];
+      }
+    }
+    lam[(size_t)t * NQ + q] = acc;
+  }
+}
+
+template <int PF, typename T>
+__global__ void __launch_bounds__(256) k_far_apply(const double* __restrict__ spos,
+                                                   const uint64_t* __restrict__ skey,
+                                                   const double4* __restrict__ near, size_t n,
+                                                   const uint32_t* __restrict__ idx, double L,
+                                                   double G, const double* __restrict__ lam,
+                                                   int periodic, T* __restrict__ acc,
+                                                   T* __restrict__ pot) {
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double4 v = near[s];
+  double phi = v.w, gx = v.x, gy = v.y, gz = v.z;
+  if (periodic) {
+    constexpr int NQ = nt(PF);
+    constexpr MI<PF> mi{};
+    const int o = (int)((skey[s] >> 60) & 7ull);
+    double c[3];
+    octant_center(o, L, c);
+    const double h[3] = {spos[s] - c[0], spos[n + s] - c[1], spos[2 * n + s] - c[2]};
+    double px[PF + 1], py[PF + 1], pz[PF + 1];
+    px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= PF; ++e) {
+      px[e] = px[e - 1] * h[0];
+      py[e] = py[e - 1] * h[1];
+      pz[e] = pz[e - 1] * h[2];
+    }
+    const double* lm = lam + (size_t)o * NQ;
+    double P = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int a = mi.a[q], b = mi.b[q], c3 = mi.c[q];
+      const double Lq = lm[q];
+      const double yz = py[b] * pz[c3];
+      P = fma(Lq, px[a] * yz, P);
+      if (a) Gx = fma(Lq * (double)a, px[a - 1] * yz, Gx);
+      if (b) Gy = fma(Lq * (double)b, px[a] * py[b - 1] * pz[c3], Gy);
+      if (c3) Gz = fma(Lq * (double)c3, px[a] * py[b] * pz[c3 - 1], Gz);
+    }
+    phi += P;
+    gx += Gx;
+    gy += Gy;
+    gz += Gz;
+  }
+  const uint32_t i = idx[s];
+  acc[i] = (T)(G * gx);
+  acc[n + i] = (T)(G * gy);
+  acc[2 * n + i] = (T)(G * gz);
+  if (pot) pot[i] = (T)(-G * phi);
+}
+
+template <int PF>
+static hipError_t far_run(const double* spos, const double* smass, const uint64_t* skey,
+                          const double4* near, size_t n, const uint32_t* idx, double box,
+                          double G, const double* tpsi, double* part, int nblk_max, double* mom,
+                          double* lam, int periodic, bool fp32, void* acc, void* pot,
+                          hipStream_t s) {
+  if (periodic) {
+    int nblk = (int)((n / 8 + 2047) / 2048);
+    if (nblk > nblk_max) nblk = nblk_max;
+    if (nblk < 1) nblk = 1;
+    k_far_moments<PF><<<dim3(nblk, 8), kFarThreads, 0, s>>>(spos, smass, skey, n, box, nblk,
+                                                            part);
+    k_far_lambda<PF><<<8, 512, 0, s>>>(part, nblk, tpsi, mom, lam);
+  }
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (fp32)
+    k_far_apply<PF, float><<<g, 256, 0, s>>>(spos, skey, near, n, idx, box, G, lam, periodic,
+                                              (float*)acc, (float*)pot);
+  else
+    k_far_apply<PF, double><<<g, 256, 0, s>>>(spos, skey, near, n, idx, box, G, lam, periodic,
+                                               (double*)acc, (double*)pot);
+  return hipGetLastError();
+}
+
+hipError_t far_launch(int far_order, const double* spos, const double* smass,
+                      const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx,
+                      double box, double G, const double* tpsi, double* part, int nblk_max,
+                      double* mom, double* lam, int periodic, bool fp32, void* acc, void* pot,
+                      hipStream_t s) {
+  if (n == 0) return hipSuccess;
+#define HOT_FAR(PF)                                                                            \
+  case PF:                                                                                     \
+    return far_run<PF>(spos, smass, skey, near, n, idx, box, G, tpsi, part, nblk_max, mom, lam, \
+                       periodic, fp32, acc, pot, s);
+  switch (far_order) {
+    HOT_FAR(0) HOT_FAR(1) HOT_FAR(2) HOT_FAR(3) HOT_FAR(4) HOT_FAR(5) HOT_FAR(6)
+    HOT_FAR(7) HOT_FAR(8) HOT_FAR(9) HOT_FAR(10) HOT_FAR(11) HOT_FAR(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef HOT_FAR
+}
+
+}  // namespace hot

@@ -1,0 +1,334 @@
+// Interaction kernels (paper Sec. 2.1: the gravitational inner loops; direct
+// interactions with the particles of nearby leaves and multipole interactions
+// with accepted cells, m source cells x n sink particles per list).
+//
+// One 64-lane wavefront handles one sink group: each lane holds one target
+// (tiles of 64 for larger groups) in registers, and the wavefront steps
+// through the group's list together, so every source particle or cell record
+// is wave-uniform and is read once per wavefront through the scalar cache
+// into scalar registers, feeding all 64 targets.
+//
+// Precision: coordinates are relative to the group's cell centre; positions,
+// cell centres and centres of mass are FP64 and are differenced in FP64
+// before rounding to the arithmetic type T.  In FP32, per-leaf (direct) and
+// per-16-cell (multipole) partial sums are folded into a (hi, lo) pair with
+// Knuth's TwoSum, so the long sums keep about twice FP32 precision.
+#include <type_traits>
+
+#include "hot_internal.h"
+
+namespace hot {
+
+constexpr int kForceWaves = 4;
+
+__device__ __forceinline__ void center_of(uint64_t key, int level, double L, double c[3]) {
+  uint32_t ix = 0, iy = 0, iz = 0;
+  for (int b = 0; b < level; ++b) {
+    ix |= (uint32_t)((key >> (3 * b + 2)) & 1ull) << b;
+    iy |= (uint32_t)((key >> (3 * b + 1)) & 1ull) << b;
+    iz |= (uint32_t)((key >> (3 * b)) & 1ull) << b;
+  }
+  double s = ldexp(L, -level);
+  c[0] = ((double)ix + 0.5) * s;
+  c[1] = ((double)iy + 0.5) * s;
+  c[2] = ((double)iz + 0.5) * s;
+}
+
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x) {
+  return 1.0 / sqrt(x);
+}
+
+// accumulator: plain in FP64, (hi, lo) TwoSum pairs in FP32
+template <typename T>
+struct Acc {
+  T hi[4];
+  T lo[4];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hi[k] = lo[k] = (T)0;
+  }
+  __device__ __forceinline__ void fold(const T x[4]) {
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        T s = hi[k] + x[k];
+        T bb = s - hi[k];
+        T err = (hi[k] - (s - bb)) + (x[k] - bb);
+        hi[k] = s;
+        lo[k] += err;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hi[k] += x[k];
+    }
+  }
+  __device__ __forceinline__ void fold1(int k, T x) {
+    if constexpr (std::is_same<T, float>::value) {
+      T s = hi[k] + x;
+      T bb = s - hi[k];
+      T err = (hi[k] - (s - bb)) + (x - bb);
+      hi[k] = s;
+      lo[k] += err;
+    } else {
+      hi[k] += x;
+    }
+  }
+  __device__ __forceinline__ double get(int k) const { return (double)hi[k] + (double)lo[k]; }
+};
+
+// ------------------------------------------------------------------- direct
+template <typename T, typename T4>
+__global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uint32_t ngroups,
+                                                          double L, T eps2,
+                                                          const double* __restrict__ spos,
+                                                          const T4* __restrict__ srec, size_t n,
+                                                          const uint32_t* __restrict__ list,
+                                                          double4* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kForceWaves + wid);
+  if (g >= ngroups) return;
+  const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
+  const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
+  double cA[3];
+  center_of(C.key[A], C.level[A], L, cA);
+  const uint32_t off = G.off_p2p[g], cnt = G.cnt_p2p[g];
+  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
+    const uint32_t s = first + t0 + lane;
+    const bool act = s < first + count;
+    const uint32_t ss = act ? s : first;
+    const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
+            tz = (T)(spos[2 * n + ss] - cA[2]);
+    Acc<T> acc;
+    acc.zero();
+    // own group (image 0), excluding the target itself
+    {
+      T part[4] = {0, 0, 0, 0};
+      for (uint32_t j = first; j < first + count; ++j) {
+        const T sx = (T)(spos[j] - cA[0]), sy = (T)(spos[n + j] - cA[1]),
+                sz = (T)(spos[2 * n + j] - cA[2]);
+        const T m = srec[j].w;
+        const T dx = sx - tx, dy = sy - ty, dz = sz - tz;
+        T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+        const bool self = (j == ss);
+        r2 = self ? (T)1 : r2;
+        const T ri = rsqrt_t<T>(r2);
+        const T mr = self ? (T)0 : m * ri;
+        const T mr3 = mr * (ri * ri);
+        part[0] = fma(dx, mr3, part[0]);
+        part[1] = fma(dy, mr3, part[1]);
+        part[2] = fma(dz, mr3, part[2]);
+        part[3] += mr;
+      }
+      acc.fold(part);
+    }
+    for (uint32_t q = 0; q < cnt; ++q) {
+      const uint32_t e = list[off + q];
+      const int img = (int)(e >> 27);
+      const int B = (int)(e & kCellMask);
+      double cB[3];
+      center_of(C.key[B], C.level[B], L, cB);
+      const T shx = (T)(cB[0] + (double)(img / 9 - 1) * L - cA[0]);
+      const T shy = (T)(cB[1] + (double)((img / 3) % 3 - 1) * L - cA[1]);
+      const T shz = (T)(cB[2] + (double)(img % 3 - 1) * L - cA[2]);
+      const uint32_t bf = C.first[B], bc = C.count[B];
+      T part[4] = {0, 0, 0, 0};
+      for (uint32_t j = bf; j < bf + bc; ++j) {
+        const T4 r = srec[j];
+        const T dx = (shx + r.x) - tx, dy = (shy + r.y) - ty, dz = (shz + r.z) - tz;
+        const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+        const T ri = rsqrt_t<T>(r2);
+        const T mr = r.w * ri;
+        const T mr3 = mr * (ri * ri);
+        part[0] = fma(dx, mr3, part[0]);
+        part[1] = fma(dy, mr3, part[1]);
+        part[2] = fma(dz, mr3, part[2]);
+        part[3] += mr;
+      }
+      acc.fold(part);
+    }
+    if (act) out[s] = make_double4(acc.get(0), acc.get(1), acc.get(2), acc.get(3));
+  }
+}
+
+// ---------------------------------------------------------------- multipole
+// Phi = rinv sum_m rho^m P_m(R), grad Phi = rinv sum_m rho^m grad P_m
+//       - rinv rho R sum_m (2m+1) rho^m P_m   (coefficient layout: tree.hip)
+template <int P, typename T>
+__device__ __forceinline__ void m2p_eval(T Rx, T Ry, T Rz, T eps2, const T* __restrict__ cf,
+                                         T out[4]) {
+  const T u = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, eps2)));
+  const T rinv = rsqrt_t<T>(u);
+  const T rho = rinv * rinv;
+  constexpr int DM = P > 0 ? P - 1 : 0;
+  constexpr MI<DM> mi{};
+  T mono[nt(DM)];
+  mono[0] = (T)1;
+#pragma unroll
+  for (int k = 1; k < nt(DM); ++k) {
+    const int a = mi.a[k], b = mi.b[k], c = mi.c[k];
+    if (a > 0)
+      mono[k] = (a + b + c == 1) ? Rx : mono[mi_index(a - 1, b, c)] * Rx;
+    else if (b > 0)
+      mono[k] = (b + c == 1) ? Ry : mono[mi_index(a, b - 1, c)] * Ry;
+    else
+      mono[k] = (c == 1) ? Rz : mono[mi_index(a, b, c - 1)] * Rz;
+  }
+  T Pm[P + 1], Vx[P + 1], Vy[P + 1], Vz[P + 1];
+#pragma unroll
+  for (int m = 0; m <= P; ++m) Pm[m] = Vx[m] = Vy[m] = Vz[m] = (T)0;
+  int o = 0;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+#pragma unroll
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      const int d = m - j;
+      if (!part_stored(m, d)) continue;
+      if (d == 0) {
+        Pm[m] += cf[o];
+        o += 1;
+      } else {
+        const int nk = nte(d - 1);
+        const int base = nt(d - 2);
+        T vx = (T)0, vy = (T)0, vz = (T)0;
+#pragma unroll
+        for (int k = 0; k < nk; ++k) {
+          vx = fma(cf[o + k], mono[base + k], vx);
+          vy = fma(cf[o + nk + k], mono[base + k], vy);
+          vz = fma(cf[o + 2 * nk + k], mono[base + k], vz);
+        }
+        o += 3 * nk;
+        Vx[m] += vx;
+        Vy[m] += vy;
+        Vz[m] += vz;
+        const T dot = fma(Rx, vx, fma(Ry, vy, Rz * vz));
+        Pm[m] = fma(dot, (T)(1.0 / d), Pm[m]);
+      }
+    }
+  }
+  T Pv = Pm[P], Q = (T)(2 * P + 1) * Pm[P], Gx = Vx[P], Gy = Vy[P], Gz = Vz[P];
+#pragma unroll
+  for (int m = P - 1; m >= 0; --m) {
+    Pv = fma(Pv, rho, Pm[m]);
+    Q = fma(Q, rho, (T)(2 * m + 1) * Pm[m]);
+    Gx = fma(Gx, rho, Vx[m]);
+    Gy = fma(Gy, rho, Vy[m]);
+    Gz = fma(Gz, rho, Vz[m]);
+  }
+  const T rq = rho * Q;
+  out[0] = rinv * fma(-rq, Rx, Gx);
+  out[1] = rinv * fma(-rq, Ry, Gy);
+  out[2] = rinv * fma(-rq, Rz, Gz);
+  out[3] = rinv * Pv;
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uint32_t ngroups,
+                                                          double L, T eps2,
+                                                          const double* __restrict__ spos,
+                                                          size_t n,
+                                                          const uint32_t* __restrict__ list,
+                                                          double4* __restrict__ out) {
+  constexpr int STR = coef_stride(P);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kForceWaves + wid);
+  if (g >= ngroups) return;
+  const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
+  const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
+  double cA[3];
+  center_of(C.key[A], C.level[A], L, cA);
+  const uint32_t off = G.off_m2p[g], cnt = G.cnt_m2p[g];
+  const T* __restrict__ coef = (const T*)C.coef;
+  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
+    const uint32_t s = first + t0 + lane;
+    const bool act = s < first + count;
+    const uint32_t ss = act ? s : first;
+    const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
+            tz = (T)(spos[2 * n + ss] - cA[2]);
+    Acc<T> acc;
+    acc.zero();
+    T part[4] = {0, 0, 0, 0};
+    for (uint32_t q = 0; q < cnt; ++q) {
+      const uint32_t e = list[off + q];
+      const int img = (int)(e >> 27);
+      const int B = (int)(e & kCellMask);
+      const double4 w = C.walk[B];
+      const T cx = (T)(w.x + (double)(img / 9 - 1) * L - cA[0]);
+      const T cy = (T)(w.y + (double)((img / 3) % 3 - 1) * L - cA[1]);
+      const T cz = (T)(w.z + (double)(img % 3 - 1) * L - cA[2]);
+      T r[4];
+      m2p_eval<P, T>(tx - cx, ty - cy, tz - cz, eps2, coef + (size_t)B * STR, r);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) part[k] += r[k];
+      // the potential sums many same-signed terms that the far field later
+      // cancels almost entirely: fold every term
+      acc.fold1(3, r[3]);
+      if ((q & 15) == 15) {
+        acc.fold(part);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) part[k] = (T)0;
+      }
+    }
+    acc.fold(part);
+    if (act) {
+      double4 o = out[s];
+      o.x += acc.get(0);
+      o.y += acc.get(1);
+      o.z += acc.get(2);
+      o.w += acc.get(3);
+      out[s] = o;
+    }
+  }
+}
+
+hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                      double eps, const double* spos, const void* srec, size_t n,
+                      const uint32_t* list, double4* out, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
+  if (fp32)
+    k_p2p<float, float4><<<blocks, 64 * kForceWaves, 0, s>>>(
+        C, G, ngroups, L, (float)(eps * eps), spos, (const float4*)srec, n, list, out);
+  else
+    k_p2p<double, double4><<<blocks, 64 * kForceWaves, 0, s>>>(
+        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n, list, out);
+  return hipGetLastError();
+}
+
+template <int P>
+static void m2p_launch_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                         double eps, const double* spos, size_t n, const uint32_t* list,
+                         double4* out, hipStream_t s) {
+  unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
+  if (fp32)
+    k_m2p<P, float><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, (float)(eps * eps),
+                                                         spos, n, list, out);
+  else
+    k_m2p<P, double><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps * eps, spos, n,
+                                                          list, out);
+}
+
+hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
+                      double L, double eps, const double* spos, size_t n, const uint32_t* list,
+                      double4* out, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  switch (order) {
+    case 0: m2p_launch_p<0>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
+    case 1: m2p_launch_p<1>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
+    case 2: m2p_launch_p<2>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
+    case 3: m2p_launch_p<3>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
+    case 4: m2p_launch_p<4>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hot

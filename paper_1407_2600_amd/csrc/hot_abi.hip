@@ -1,0 +1,583 @@
+// C ABI of libhot: parameter checks, workspace plan, and the sequence of
+// stages of one force evaluation (keys, sort, tree, moments, groups, walk,
+// interactions, far field).  See include/hot.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hot_internal.h"
+
+namespace hot {
+// stage launchers (other translation units)
+hipError_t launch_keys(const double* pos, size_t n, double L, double S, uint64_t* key,
+                       uint32_t* idx, uint32_t* bad, hipStream_t s);
+hipError_t radix_sort(uint64_t* key0, uint32_t* idx0, uint64_t* key1, uint32_t* idx1, size_t n,
+                      uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+hipError_t launch_gather(const double* pos, const void* mass, bool fp32, size_t n, double L,
+                         const uint32_t* idx, double* spos, double* smass, uint32_t* bad,
+                         hipStream_t s);
+hipError_t tree_root(const Cells& C, uint32_t n, hipStream_t s);
+hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
+                            int level, int leaf_max, uint32_t* nch, uint32_t* total,
+                            uint32_t* scan_tmp, hipStream_t s);
+hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
+                           int level, int leaf_max, const uint32_t* choff, uint32_t next,
+                           hipStream_t s);
+hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
+                              uint32_t beg, uint32_t cnt, double L, double theta, int order,
+                              bool fp32, hipStream_t s);
+hipError_t tree_groups(const Cells& C, uint32_t ncells, int gmax, size_t n, uint32_t* gflag,
+                       uint32_t* gid, int32_t* gcell_at, const Groups& G, uint32_t* ngroups_dev,
+                       uint32_t* scan_tmp, hipStream_t s);
+hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
+                           const double* spos, size_t n, hipStream_t s);
+hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
+                     size_t n, double L, void* srec, bool fp32, hipStream_t s);
+hipError_t walk_launch(bool emit, const Cells& C, const Groups& G, uint32_t ngroups,
+                       uint32_t gcap, double L, int periodic, uint32_t* p2p_list,
+                       uint32_t* m2p_list, uint32_t* status, hipStream_t s);
+hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* p2p_list,
+                       unsigned long long* out, hipStream_t s);
+hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                      double eps, const double* spos, const void* srec, size_t n,
+                      const uint32_t* list, double4* out, hipStream_t s);
+hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
+                      double L, double eps, const double* spos, size_t n, const uint32_t* list,
+                      double4* out, hipStream_t s);
+hipError_t far_launch(int far_order, const double* spos, const double* smass,
+                      const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx, double box, double G, const double* tpsi,
+                      double* part, int nblk_max, double* mroot, double* lam, int periodic,
+                      bool fp32, void* acc, void* pot, hipStream_t s);
+hipError_t kick_launch(bool fp32, void* vel, const void* acc, size_t n, double h, hipStream_t s);
+hipError_t drift_launch(bool fp32, double* pos, const void* vel, size_t n, double dt, double L,
+                        hipStream_t s);
+
+namespace {
+thread_local std::string g_err;
+constexpr int kFarBlocks = 64;  // far-moment blocks per octant
+constexpr size_t kAlign = 256;
+
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// counters in the workspace (uint32 unless noted)
+enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
+       CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_N = 64 };
+
+bool valid_params(const hot_params* p, std::string* why) {
+  if (!(p->box > 0.0) || !std::isfinite(p->box)) return *why = "box must be finite and > 0", false;
+  if (!std::isfinite(p->G)) return *why = "G must be finite", false;
+  if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return *why = "eps must be >= 0", false;
+  if (!(p->theta >= 0.0 && p->theta < 1.0)) return *why = "theta must be in [0, 1)", false;
+  if (p->order < 0 || p->order > kMaxOrder) return *why = "order must be in 0..4", false;
+  if (p->periodic != 0 && p->periodic != 1) return *why = "periodic must be 0 or 1", false;
+  if (p->leaf_max < 1 || p->leaf_max > 255) return *why = "leaf_max must be in 1..255", false;
+  if (p->group_max < 1 || p->group_max > 4096) return *why = "group_max must be in 1..4096", false;
+  if (p->far_order < 0 || p->far_order > kMaxFarOrder)
+    return *why = "far_order must be in 0..12", false;
+  if (p->precision != HOT_FP64 && p->precision != HOT_FP32)
+    return *why = "precision must be HOT_FP64 or HOT_FP32", false;
+  return true;
+}
+
+Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
+  Plan P{};
+  P.n = n;
+  const bool fp32 = c->p.precision == HOT_FP32;
+  const size_t tsz = fp32 ? 4 : 8;
+  P.cap_cells = (size_t)std::ceil(c->cells_per_particle * (double)n) + 1024;
+  P.cap_groups = std::min(P.cap_cells, n + 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += up(bytes);
+    return r;
+  };
+  P.o_key[0] = take(8 * n);
+  P.o_key[1] = take(8 * n);
+  P.o_idx[0] = take(4 * n);
+  P.o_idx[1] = take(4 * n);
+  P.o_spos = take(24 * n);
+  P.o_smass = take(8 * n);
+  P.o_srec = take(4 * tsz * n);
+  P.o_acc = take(32 * n);
+  P.o_tmp = take(4 * std::max(n, P.cap_cells));  // split-level counts / group ids
+  P.o_scan = take(4 * (kScanBlocks + 64));
+  const size_t nblk_sort = (n + kSortTile - 1) / kSortTile;
+  P.o_hist = take(4 * kSortBins * std::max<size_t>(nblk_sort, 1));
+  P.o_ctr = take(4 * CTR_N);
+  const size_t C = P.cap_cells;
+  const int NM = nt(c->p.order);
+  const int STR = coef_stride(c->p.order);
+  P.o_c_key = take(8 * C);
+  P.o_c_level = take(4 * C);
+  P.o_c_first = take(4 * C);
+  P.o_c_count = take(4 * C);
+  P.o_c_child = take(4 * C);
+  P.o_c_nchild = take(4 * C);
+  P.o_c_parent = take(4 * C);
+  P.o_c_mmx = take(32 * C);
+  P.o_c_walk = take(32 * C);
+  P.o_c_mom = take(8 * (size_t)NM * C);
+  P.o_c_coef = take(tsz * (size_t)STR * C);
+  const size_t Gc = P.cap_groups;
+  P.o_g_cell = take(4 * Gc);
+  P.o_g_lo = take(24 * Gc);
+  P.o_g_hi = take(24 * Gc);
+  P.o_g_cp = take(4 * Gc);
+  P.o_g_cm = take(4 * Gc);
+  P.o_g_op = take(4 * Gc);
+  P.o_g_om = take(4 * Gc);
+  const int NQ = nt(c->p.far_order);
+  P.o_far_part = take(8 * 8 * (size_t)NQ * kFarBlocks);
+  P.o_far_mom = take(8 * 8 * (size_t)NQ);
+  P.o_far_lam = take(8 * 8 * (size_t)NQ);
+  P.o_list = o;
+  const size_t want_list = (size_t)std::ceil(c->list_per_particle * (double)n) + 65536;
+  if (ws_bytes == 0) {
+    P.cap_list = want_list;
+  } else {
+    P.cap_list = ws_bytes > o ? (ws_bytes - o) / 4 : 0;
+  }
+  P.total = o + up(4 * want_list);
+  return P;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+Cells cells_of(void* ws, const Plan& P) {
+  Cells C;
+  C.key = at<uint64_t>(ws, P.o_c_key);
+  C.level = at<int32_t>(ws, P.o_c_level);
+  C.first = at<uint32_t>(ws, P.o_c_first);
+  C.count = at<uint32_t>(ws, P.o_c_count);
+  C.child = at<int32_t>(ws, P.o_c_child);
+  C.nchild = at<int32_t>(ws, P.o_c_nchild);
+  C.parent = at<int32_t>(ws, P.o_c_parent);
+  C.mmx = at<double4>(ws, P.o_c_mmx);
+  C.walk = at<double4>(ws, P.o_c_walk);
+  C.mom = at<double>(ws, P.o_c_mom);
+  C.coef = at<void>(ws, P.o_c_coef);
+  return C;
+}
+
+Groups groups_of(void* ws, const Plan& P) {
+  Groups G;
+  G.cell = at<int32_t>(ws, P.o_g_cell);
+  G.lo = at<double>(ws, P.o_g_lo);
+  G.hi = at<double>(ws, P.o_g_hi);
+  G.cnt_p2p = at<uint32_t>(ws, P.o_g_cp);
+  G.cnt_m2p = at<uint32_t>(ws, P.o_g_cm);
+  G.off_p2p = at<uint32_t>(ws, P.o_g_op);
+  G.off_m2p = at<uint32_t>(ws, P.o_g_om);
+  return G;
+}
+
+#define HOT_CHECK(call, what)                           \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return device_error(e_, what); \
+  } while (0)
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+hot_status device_error(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return HOT_EDEVICE;
+}
+
+// read back a few counters (synchronises the stream)
+static hipError_t readback(hipStream_t s, const uint32_t* dev, uint32_t* host, int count) {
+  hipError_t e = hipMemcpyAsync(host, dev, sizeof(uint32_t) * count, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
+                              void* pot, void* ws, size_t ws_bytes, hipStream_t s) {
+  const hot_params& p = c->p;
+  const bool fp32 = p.precision == HOT_FP32;
+  Plan P = make_plan(c, n, ws_bytes);
+  if (ws_bytes < P.total) {
+    g_err = "workspace too small: need " + std::to_string(P.total) + " bytes, got " +
+            std::to_string(ws_bytes);
+    c->stats.ws_bytes_needed = P.total;
+    return HOT_ENOMEM;
+  }
+  if (P.cap_cells >= (size_t)kCellMask) {
+    g_err = "too many cells for 27-bit list entries";
+    return HOT_EUNSUPPORTED;
+  }
+  uint32_t* ctr = at<uint32_t>(ws, P.o_ctr);
+  uint32_t* scan_tmp = at<uint32_t>(ws, P.o_scan);
+  uint64_t* key0 = at<uint64_t>(ws, P.o_key[0]);
+  uint64_t* key1 = at<uint64_t>(ws, P.o_key[1]);
+  uint32_t* idx0 = at<uint32_t>(ws, P.o_idx[0]);
+  uint32_t* idx1 = at<uint32_t>(ws, P.o_idx[1]);
+  double* spos = at<double>(ws, P.o_spos);
+  double* smass = at<double>(ws, P.o_smass);
+  void* srec = at<void>(ws, P.o_srec);
+  double4* near = at<double4>(ws, P.o_acc);
+  uint32_t* tmp = at<uint32_t>(ws, P.o_tmp);
+  Cells C = cells_of(ws, P);
+  Groups G = groups_of(ws, P);
+  uint32_t* host = c->host_buf;
+
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[0], s), "event");
+  HOT_CHECK(hipMemsetAsync(ctr, 0, 4 * CTR_N, s), "memset");
+  HOT_CHECK(launch_keys(pos, n, p.box, c->S, key0, idx0, ctr + CTR_BAD, s), "keys");
+  HOT_CHECK(radix_sort(key0, idx0, key1, idx1, n, at<uint32_t>(ws, P.o_hist), scan_tmp, s),
+            "sort");
+  HOT_CHECK(launch_gather(pos, mass, fp32, n, p.box, idx0, spos, smass, ctr + CTR_BAD, s),
+            "gather");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[1], s), "event");
+
+  // ---- tree, level by level
+  HOT_CHECK(tree_root(C, (uint32_t)n, s), "tree root");
+  std::vector<uint32_t> lvl(kMaxLevel + 3, 0);
+  lvl[0] = 0;
+  lvl[1] = 1;
+  int nlev = 1;
+  for (int l = 0; l < kMaxLevel; ++l) {
+    const uint32_t cnt = lvl[l + 1] - lvl[l];
+    HOT_CHECK(tree_split_level(C, key0, lvl[l], cnt, l, p.leaf_max, tmp, ctr + CTR_TOTAL,
+                               scan_tmp, s),
+              "tree split");
+    HOT_CHECK(readback(s, ctr, host, 2), "readback");
+    if (l == 0 && host[CTR_BAD]) {
+      g_err = (host[CTR_BAD] & 1u) ? "positions must be finite and inside (-L, 2L)"
+                                   : "masses must be finite and >= 0";
+      return HOT_EINVAL;
+    }
+    const uint32_t tot = host[CTR_TOTAL];
+    if (tot == 0) break;
+    if ((size_t)lvl[l + 1] + tot > P.cap_cells) {
+      c->cells_per_particle *= 2.0;
+      c->stats.ws_bytes_needed = make_plan(c, n, 0).total;
+      g_err = "cell capacity exceeded; call hot_workspace_size again and retry";
+      return HOT_EOVERFLOW;
+    }
+    HOT_CHECK(tree_emit_level(C, key0, lvl[l], cnt, l, p.leaf_max, tmp, lvl[l + 1], s),
+              "tree emit");
+    lvl[l + 2] = lvl[l + 1] + tot;
+    nlev = l + 2;
+  }
+  const uint32_t ncells = lvl[nlev];
+  for (int l = nlev - 1; l >= 0; --l)
+    HOT_CHECK(tree_moments_level(C, spos, smass, n, lvl[l], lvl[l + 1] - lvl[l], p.box, p.theta,
+                                 p.order, fp32, s),
+              "moments");
+  uint32_t* gflag = tmp;
+  uint32_t* gid = reinterpret_cast<uint32_t*>(key1);
+  int32_t* gcell_at = reinterpret_cast<int32_t*>(idx1);
+  HOT_CHECK(tree_groups(C, ncells, p.group_max, n, gflag, gid, gcell_at, G, ctr + CTR_NGROUPS,
+                        scan_tmp, s),
+            "groups");
+  HOT_CHECK(tree_srec(C, ncells, spos, smass, n, p.box, srec, fp32, s), "source records");
+  HOT_CHECK(readback(s, ctr, host, 8), "readback");
+  const uint32_t ngroups = host[CTR_NGROUPS];
+  if (ngroups > P.cap_groups) {
+    g_err = "internal: group capacity exceeded";
+    return HOT_EDEVICE;
+  }
+  HOT_CHECK(tree_group_bbox(C, G, ngroups, (uint32_t)P.cap_groups, spos, n, s), "bbox");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
+
+  // ---- walk: count, scan, emit
+  HOT_CHECK(walk_launch(false, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic, nullptr,
+                        nullptr, ctr + CTR_STATUS, s),
+            "walk count");
+  HOT_CHECK(scan_u32(G.cnt_p2p, G.off_p2p, ctr + CTR_TP, ngroups, scan_tmp, s), "scan");
+  HOT_CHECK(scan_u32(G.cnt_m2p, G.off_m2p, ctr + CTR_TM, ngroups, scan_tmp, s), "scan");
+  HOT_CHECK(readback(s, ctr, host, 8), "readback");
+  if (host[CTR_STATUS] & 4u) {
+    g_err = "walk stack overflow (pathological tree)";
+    return HOT_EOVERFLOW;
+  }
+  const size_t tp = host[CTR_TP], tm = host[CTR_TM];
+  if (tp + tm > P.cap_list) {
+    c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)(tp + tm) / (double)n);
+    c->stats.ws_bytes_needed = make_plan(c, n, 0).total;
+    g_err = "interaction-list capacity exceeded; call hot_workspace_size again and retry";
+    return HOT_EOVERFLOW;
+  }
+  uint32_t* p2p_list = at<uint32_t>(ws, P.o_list);
+  uint32_t* m2p_list = p2p_list + tp;
+  HOT_CHECK(walk_launch(true, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic, p2p_list,
+                        m2p_list, ctr + CTR_STATUS, s),
+            "walk emit");
+  HOT_CHECK(count_pairs(C, G, ngroups, p2p_list,
+                        reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
+            "pair count");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
+
+  // ---- interactions
+  HOT_CHECK(p2p_launch(fp32, C, G, ngroups, p.box, p.eps, spos, srec, n, p2p_list, near, s),
+            "direct kernel");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+  HOT_CHECK(m2p_launch(fp32, p.order, C, G, ngroups, p.box, p.eps, spos, n, m2p_list, near, s),
+            "multipole kernel");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
+  HOT_CHECK(far_launch(p.far_order, spos, smass, key0, near, n, idx0, p.box, p.G, c->d_tpsi,
+                       at<double>(ws, P.o_far_part), kFarBlocks, at<double>(ws, P.o_far_mom),
+                       at<double>(ws, P.o_far_lam), p.periodic, fp32, acc, pot, s),
+            "far field");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
+
+  hot_stats& st = c->stats;
+  std::memset(&st, 0, sizeof(st));
+  st.n = (int64_t)n;
+  st.ncells = ncells;
+  st.ngroups = ngroups;
+  st.nlevels = nlev;
+  st.p2p_entries = (int64_t)tp;
+  st.m2p_entries = (int64_t)tm;
+  st.ws_bytes_needed = P.total;
+  c->have_last = 1;
+  c->last_n = n;
+  c->last_stream = s;
+  c->last_plan = P;
+  c->last_ws = ws;
+  c->last_ncells = ncells;
+  c->last_ngroups = ngroups;
+  return HOT_OK;
+}
+
+}  // namespace hot
+
+using namespace hot;
+
+extern "C" {
+
+const char* hot_version(void) { return "libhot 0.1 (gfx950)"; }
+
+hot_status hot_far_table(int far_order, double box, int offset, double* out, size_t count) {
+  if (far_order < 0 || far_order > kMaxFarOrder || !(box > 0.0) || !out || offset < 0 ||
+      offset > 26 || count < (size_t)nt(2 * far_order)) {
+    g_err = "bad argument";
+    return HOT_EINVAL;
+  }
+  const double r0[3] = {(offset / 9 - 1) * 0.5 * box, ((offset / 3) % 3 - 1) * 0.5 * box,
+                        (offset % 3 - 1) * 0.5 * box};
+  psi_taylor_table(2 * far_order, box, r0, out);
+  return HOT_OK;
+}
+
+const char* hot_last_error(void) { return g_err.c_str(); }
+
+hot_status hot_create(const hot_params* params, hot_ctx** out) {
+  if (!out) {
+    g_err = "out is NULL";
+    return HOT_EINVAL;
+  }
+  *out = nullptr;
+  if (!params) {
+    g_err = "params is NULL";
+    return HOT_EINVAL;
+  }
+  std::string why;
+  if (!valid_params(params, &why)) {
+    g_err = why;
+    return HOT_EINVAL;
+  }
+  hot_ctx* c = new hot_ctx();
+  std::memset(c, 0, sizeof(*c));
+  c->p = *params;
+  c->S = 2097152.0 / params->box;
+  c->cells_per_particle = 8.0 / (params->leaf_max + 1) + 0.05;
+  c->list_per_particle = 48.0;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return device_error(e, "hipGetDevice");
+  }
+  const int D = 2 * params->far_order;
+  c->n_tpsi = nt(D);
+  std::vector<double> tab((size_t)27 * c->n_tpsi);
+  if (params->periodic) psi_taylor_tables27(D, params->box, tab.data());
+  e = hipMalloc(&c->d_tpsi, sizeof(double) * tab.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_tpsi, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_buf, 4 * 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    hot_destroy(c);
+    return device_error(e, "context allocation");
+  }
+  c->events_ok = 1;
+  for (int i = 0; i < 8; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = 0;
+  *out = c;
+  return HOT_OK;
+}
+
+void hot_destroy(hot_ctx* c) {
+  if (!c) return;
+  if (c->d_tpsi) (void)hipFree(c->d_tpsi);
+  if (c->host_buf) (void)hipHostFree(c->host_buf);
+  for (int i = 0; i < 8; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+size_t hot_workspace_size(const hot_ctx* c, size_t n) {
+  if (!c) return 0;
+  return make_plan(c, n, 0).total;
+}
+
+hot_status hot_forces(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
+                      void* pot, void* ws, size_t ws_bytes, void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !mass || !acc || !ws) {
+    g_err = "NULL pointer argument";
+    return HOT_EINVAL;
+  }
+  if (n >= (size_t)0xffffffffu) {
+    g_err = "n must be < 2^32";
+    return HOT_EINVAL;
+  }
+  return forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, (hipStream_t)stream);
+}
+
+hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mass, void* acc,
+                   void* pot, double dt, int nsteps, unsigned flags, void* ws, size_t ws_bytes,
+                   void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !vel || !mass || !acc || !ws || nsteps < 0 || !std::isfinite(dt)) {
+    g_err = "bad argument";
+    return HOT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool fp32 = c->p.precision == HOT_FP32;
+  hot_status st;
+  if (!(flags & HOT_ACC_VALID)) {
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s);
+    if (st != HOT_OK) return st;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
+    HOT_CHECK(drift_launch(fp32, pos, vel, n, dt, c->p.box, s), "drift");
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s);
+    if (st != HOT_OK) return st;
+    HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
+  }
+  return HOT_OK;
+}
+
+hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, const void* gacc,
+                   const void* gpot, double* xbar, void* mbar, void* ws, size_t ws_bytes,
+                   void* stream) {
+  (void)c; (void)n; (void)pos; (void)mass; (void)gacc; (void)gpot; (void)xbar; (void)mbar;
+  (void)ws; (void)ws_bytes; (void)stream;
+  g_err = "adjoint not built";
+  return HOT_EUNSUPPORTED;
+}
+
+hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
+  if (!c || !out) {
+    g_err = "NULL argument";
+    return HOT_EINVAL;
+  }
+  hot_ctx* m = const_cast<hot_ctx*>(c);
+  if (m->have_last && m->events_ok) {
+    if (hipEventSynchronize(m->ev[6]) == hipSuccess) {
+      float t[7] = {0};
+      for (int i = 1; i <= 6; ++i) (void)hipEventElapsedTime(&t[i], m->ev[i - 1], m->ev[i]);
+      float tot = 0;
+      (void)hipEventElapsedTime(&tot, m->ev[0], m->ev[6]);
+      m->stats.ms_sort = t[1];
+      m->stats.ms_build = t[2];
+      m->stats.ms_walk = t[3];
+      m->stats.ms_p2p = t[4];
+      m->stats.ms_m2p = t[5];
+      m->stats.ms_far = t[6];
+      m->stats.ms_total = tot;
+    }
+    unsigned long long pr[2] = {0, 0};
+    const uint32_t* ctr = at<uint32_t>(m->last_ws, m->last_plan.o_ctr);
+    if (hipMemcpy(pr, ctr + CTR_PAIRS, sizeof(pr), hipMemcpyDeviceToHost) == hipSuccess) {
+      m->stats.p2p_pairs = (int64_t)pr[0];
+      m->stats.m2p_pairs = (int64_t)pr[1];
+      m->stats.flops_p2p = (double)pr[0] * kP2PFlops;
+      m->stats.flops_m2p = (double)pr[1] * m2p_flops(m->p.order);
+    }
+  }
+  *out = m->stats;
+  return HOT_OK;
+}
+
+hot_status hot_debug_sizes(const hot_ctx* c, int64_t* n, int64_t* ncells, int64_t* ngroups,
+                           int64_t* p2p_entries, int64_t* m2p_entries) {
+  if (!c || !c->have_last) {
+    g_err = "no previous hot_forces call";
+    return HOT_EINVAL;
+  }
+  if (n) *n = (int64_t)c->last_n;
+  if (ncells) *ncells = c->last_ncells;
+  if (ngroups) *ngroups = c->last_ngroups;
+  if (p2p_entries) *p2p_entries = c->stats.p2p_entries;
+  if (m2p_entries) *m2p_entries = c->stats.m2p_entries;
+  return HOT_OK;
+}
+
+hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
+  if (!c || !c->have_last || !o || !ws) {
+    g_err = "no previous hot_forces call or NULL argument";
+    return HOT_EINVAL;
+  }
+  const Plan& P = c->last_plan;
+  hipStream_t s = c->last_stream;
+  HOT_CHECK(hipStreamSynchronize(s), "sync");
+  const size_t n = c->last_n, nc = c->last_ncells, ng = c->last_ngroups;
+  auto cp = [&](void* dst, size_t off, size_t bytes) -> hipError_t {
+    if (!dst || bytes == 0) return hipSuccess;
+    return hipMemcpy(dst, at<char>(ws, off), bytes, hipMemcpyDeviceToHost);
+  };
+  HOT_CHECK(cp(o->sorted_keys, P.o_key[0], 8 * n), "export");
+  HOT_CHECK(cp(o->perm, P.o_idx[0], 4 * n), "export");
+  HOT_CHECK(cp(o->cell_key, P.o_c_key, 8 * nc), "export");
+  HOT_CHECK(cp(o->cell_level, P.o_c_level, 4 * nc), "export");
+  HOT_CHECK(cp(o->cell_first, P.o_c_first, 4 * nc), "export");
+  HOT_CHECK(cp(o->cell_count, P.o_c_count, 4 * nc), "export");
+  if (o->cell_com || o->cell_mass) {
+    std::vector<double> w(4 * nc), mm(4 * nc);
+    HOT_CHECK(cp(w.data(), P.o_c_walk, 32 * nc), "export");
+    HOT_CHECK(cp(mm.data(), P.o_c_mmx, 32 * nc), "export");
+    for (size_t i = 0; i < nc; ++i) {
+      if (o->cell_com)
+        for (int a = 0; a < 3; ++a) o->cell_com[a * nc + i] = w[4 * i + a];
+      if (o->cell_mass) o->cell_mass[i] = mm[4 * i];
+    }
+  }
+  HOT_CHECK(cp(o->group_cell, P.o_g_cell, 4 * ng), "export");
+  std::vector<uint32_t> cnt(ng), off(ng);
+  const size_t tp = c->stats.p2p_entries, tm = c->stats.m2p_entries;
+  for (int kind = 0; kind < 2; ++kind) {
+    int64_t* ooff = kind ? o->m2p_offset : o->p2p_offset;
+    uint32_t* oent = kind ? o->m2p_entry : o->p2p_entry;
+    if (ooff && ng) {
+      HOT_CHECK(cp(off.data(), kind ? P.o_g_om : P.o_g_op, 4 * ng), "export");
+      for (size_t g = 0; g < ng; ++g) ooff[g] = off[g];
+      ooff[ng] = (int64_t)(kind ? tm : tp);
+    } else if (ooff) {
+      ooff[0] = 0;
+    }
+    HOT_CHECK(cp(oent, P.o_list + (kind ? 4 * tp : 0), 4 * (kind ? tm : tp)), "export");
+  }
+  return HOT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Internal declarations of libhot (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hot.h"
+
+namespace hot {
+
+constexpr int kMaxLevel = 21;        // 21 bits per axis in a 64-bit key
+constexpr int kMaxOrder = 4;         // cell multipole order built into the kernels
+constexpr int kMaxFarOrder = 12;     // far-field local expansion order
+constexpr int kImgBits = 5;          // list entry = image << 27 | cell
+constexpr uint32_t kCellMask = (1u << 27) - 1;
+constexpr int kWalkStack = 2048;     // LDS walk stack entries per wave
+constexpr int kSortBits = 8;
+constexpr int kSortBins = 1 << kSortBits;
+constexpr int kSortTile = 4096;      // keys per sort block
+constexpr int kScanBlocks = 1024;    // blocks of the device-wide scan
+
+// ---------------------------------------------------------------------------
+// Compile-time multi-indices (a, b, c), ordered by total degree, then a
+// descending, then b descending.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int nt(int D) { return D < 0 ? 0 : (D + 1) * (D + 2) * (D + 3) / 6; }
+__host__ __device__ constexpr int nte(int d) { return d < 0 ? 0 : (d + 1) * (d + 2) / 2; }
+
+__host__ __device__ constexpr int mi_index(int a, int b, int c) {
+  int d = a + b + c;
+  int off = 0;
+  for (int x = d; x > a; --x) off += d - x + 1;
+  off += (d - a) - b;
+  return nt(d - 1) + off;
+}
+
+template <int D>
+struct MI {
+  static constexpr int N = nt(D);
+  int a[N > 0 ? N : 1], b[N > 0 ? N : 1], c[N > 0 ? N : 1];
+  constexpr MI() : a(), b(), c() {
+    int n = 0;
+    for (int d = 0; d <= D; ++d)
+      for (int x = d; x >= 0; --x)
+        for (int y = d - x; y >= 0; --y) {
+          a[n] = x;
+          b[n] = y;
+          c[n] = d - x - y;
+          ++n;
+        }
+  }
+};
+
+// Sizes of the per-cell multipole-interaction coefficient block for order P.
+// The potential of a cell is written as Phi = rinv * sum_m rho^m P_m(R) with
+// rinv = (R^2+eps^2)^(-1/2), rho = rinv^2 and P_m a polynomial whose
+// homogeneous parts have degrees d = m - j, 0 <= j <= min(m, P - m).  Parts
+// of degree d >= 1 are stored as their gradient coefficients (3 x nte(d-1)),
+// parts of degree 0 as one constant; the dipole part (m = 1, d = 1) vanishes
+// about the centre of mass and is not stored.
+__host__ __device__ constexpr int part_jmax(int P, int m) { return m < P - m ? m : P - m; }
+__host__ __device__ constexpr bool part_stored(int m, int d) { return !(m == 1 && d == 1); }
+__host__ __device__ constexpr int part_size(int d) { return d == 0 ? 1 : 3 * nte(d - 1); }
+__host__ __device__ constexpr int coef_count(int P) {
+  int n = 0;
+  for (int m = 0; m <= P; ++m)
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      int d = m - j;
+      if (part_stored(m, d)) n += part_size(d);
+    }
+  return n;
+}
+// coefficient block padded to a multiple of 4 values (16-byte aligned rows)
+__host__ __device__ constexpr int coef_stride(int P) { return (coef_count(P) + 3) / 4 * 4; }
+
+// Algorithmic flops of one multipole (cell, target) interaction in the
+// formulation above, and of one direct pair (3 sub, 3 fma, rsqrt, 3 mul,
+// 3 fma, 1 add; fma = 2, rsqrt = 1).
+__host__ __device__ constexpr int m2p_flops(int P) {
+  // R (3), u (3 fma = 6), rsqrt (1), rho (1)
+  int f = 3 + 6 + 1 + 1;
+  // monomials of degree 2..P-1 (one multiply each)
+  for (int d = 2; d <= P - 1; ++d) f += nte(d);
+  for (int m = 0; m <= P; ++m)
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      int d = m - j;
+      if (!part_stored(m, d) || d == 0) continue;
+      f += 2 * 3 * nte(d - 1);  // gradient polynomial (fma)
+      f += 2 * 3 + 1;           // R . V (3 fma) and the 1/d scale
+      f += 3 + 1;               // add to V_m and to P_m
+    }
+  // Horner over m for Pv, Q (2 fma each) and Gv (3 fma), then combine
+  f += P * (2 + 2 + 6) + 2 * P;
+  f += 1 + 1 + 1 + 3 * 2 + 3;  // Phi, rho*Q, grad (3 fma), scale by rinv
+  f += 4;                       // accumulate
+  return f;
+}
+constexpr int kP2PFlops = 20;
+
+// ---------------------------------------------------------------------------
+// Device data of one force evaluation (pointers into the caller's workspace).
+// ---------------------------------------------------------------------------
+struct Cells {
+  uint64_t* key;     // Morton key with placeholder bit
+  int32_t* level;
+  uint32_t* first;
+  uint32_t* count;
+  int32_t* child;    // index of the first child (children are contiguous)
+  int32_t* nchild;   // 0 for a leaf
+  int32_t* parent;
+  double4* mmx;      // (m, sum m x, sum m y, sum m z), FP64
+  double4* walk;     // (com.x, com.y, com.z, rcrit)
+  double* mom;       // raw moments about the com, nt(order) x cap (cell-major)
+  void* coef;        // multipole coefficients, coef_stride x cap (cell-major), T
+};
+
+struct Groups {
+  int32_t* cell;
+  double* lo;        // 3 x cap
+  double* hi;        // 3 x cap
+  uint32_t* cnt_p2p;
+  uint32_t* cnt_m2p;
+  uint32_t* off_p2p;
+  uint32_t* off_m2p;
+};
+
+struct Plan {
+  size_t n;
+  size_t cap_cells;
+  size_t cap_groups;
+  size_t cap_list;   // list entries (p2p + m2p)
+  size_t total;      // bytes
+  // offsets of every buffer (bytes from the workspace start)
+  size_t o_key[2], o_idx[2], o_spos, o_smass, o_srec, o_acc, o_tmp;
+  size_t o_scan, o_hist, o_ctr;
+  size_t o_c_key, o_c_level, o_c_first, o_c_count, o_c_child, o_c_nchild, o_c_parent;
+  size_t o_c_mmx, o_c_walk, o_c_mom, o_c_coef;
+  size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om;
+  size_t o_far_part, o_far_mom, o_far_lam;
+  size_t o_list;
+};
+
+}  // namespace hot
+
+// the context (opaque to callers)
+struct hot_ctx {
+  hot_params p;
+  int device;
+  double S;            // 2^21 / L (key quantisation)
+  double* d_tpsi;      // 27 Ewald tables (octant-centre offsets), nt(2 far_order) each
+  double* d_binom;     // binomial table (kMaxFarOrder*2+1)^2, device
+  int n_tpsi;
+  // learned capacities (grow after an overflow)
+  double cells_per_particle;
+  double list_per_particle;
+  // last call
+  hot_stats stats;
+  size_t last_n;
+  int have_last;
+  hipStream_t last_stream;
+  hot::Plan last_plan;
+  void* last_ws;
+  uint32_t last_ncells;
+  uint32_t last_ngroups;
+  uint32_t* host_buf;  // pinned host memory for counter read-backs
+  hipEvent_t ev[8];
+  int events_ok;
+};
+
+namespace hot {
+// host-side Ewald remainder table (ewald_table.cpp)
+void psi_taylor_table(int D, double box, const double r0[3], double* out);
+// the 27 tables about the offsets between octant centres (cubic symmetry)
+void psi_taylor_tables27(int D, double box, double* out);
+// the same with an explicit Ewald split (alpha, real images |n|_inf <= nreal,
+// reciprocal |k|_inf <= kmax)
+void psi_taylor_table_split(int D, double box, const double r0[3], double alpha, int nreal,
+                            int kmax, double* out);
+
+void set_error(const std::string& msg);
+hot_status device_error(hipError_t e, const char* what);
+
+// device-wide exclusive scan of n uint32 values (n may live on the device);
+// out[i] = sum_{k<i} in[i]; *total = sum.  in and out may alias.
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint32_t* total, size_t n,
+                    uint32_t* block_sums, hipStream_t s);
+}  // namespace hot

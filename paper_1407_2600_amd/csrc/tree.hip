@@ -1,0 +1,446 @@
+// Oct-tree over the key-sorted particles (paper Sec. 2.1: the Morton keys
+// implicitly define the tree topology; cells are the internal nodes and carry
+// truncated multipole expansions; groups of nearby sinks share one list).
+//
+// Build: level by level from the root.  A cell with more than leaf_max
+// particles below level 21 is split into its non-empty daughters, found by
+// binary search for the octal digit boundaries inside its contiguous sorted
+// range.  Cells are stored level-major; the daughters of a cell are
+// contiguous and in octant order, so the octant-ordered sums below need no
+// sorting.
+//
+// Moments, bottom-up: cell mass and sum m x in FP64 with separate multiply
+// and add (leaves sum their particles in key order, internal cells their
+// daughters in octant order), centre of mass = sum m x / m, the opening
+// radius s/theta + |com - centre|, and raw Cartesian moments about the centre
+// of mass (leaves directly, internal cells by shifting the daughters'
+// moments).  From the raw moments each cell derives the coefficient block its
+// multipole interactions use.
+#include "hot_internal.h"
+
+namespace hot {
+
+__device__ __forceinline__ void cell_center(uint64_t key, int level, double L, double c[3],
+                                            double* side) {
+  uint32_t ix = 0, iy = 0, iz = 0;
+  for (int b = 0; b < level; ++b) {
+    ix |= (uint32_t)((key >> (3 * b + 2)) & 1ull) << b;
+    iy |= (uint32_t)((key >> (3 * b + 1)) & 1ull) << b;
+    iz |= (uint32_t)((key >> (3 * b)) & 1ull) << b;
+  }
+  double s = ldexp(L, -level);
+  c[0] = ((double)ix + 0.5) * s;
+  c[1] = ((double)iy + 0.5) * s;
+  c[2] = ((double)iz + 0.5) * s;
+  *side = s;
+}
+
+__global__ void k_root(Cells C, uint32_t n) {
+  C.key[0] = 1ull;
+  C.level[0] = 0;
+  C.first[0] = 0;
+  C.count[0] = n;
+  C.child[0] = -1;
+  C.nchild[0] = 0;
+  C.parent[0] = -1;
+}
+
+// first sorted index in [lo, hi) whose octal digit (at `shift`) is >= o
+__device__ __forceinline__ uint32_t digit_lower_bound(const uint64_t* __restrict__ skey,
+                                                      uint32_t lo, uint32_t hi, int shift,
+                                                      uint32_t o) {
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    uint32_t d = (uint32_t)((skey[mid] >> shift) & 7ull);
+    if (d < o)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_split_count(Cells C, const uint64_t* __restrict__ skey,
+                                                     uint32_t beg, uint32_t cnt, int level,
+                                                     int leaf_max, uint32_t* __restrict__ nch) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  uint32_t c = beg + t;
+  uint32_t first = C.first[c], count = C.count[c];
+  uint32_t k = 0;
+  if ((int)count > leaf_max && level < kMaxLevel) {
+    int shift = 3 * (kMaxLevel - level - 1);
+    uint32_t end = first + count;
+    uint32_t b = first;
+    for (uint32_t o = 0; o < 8; ++o) {
+      uint32_t e = (o == 7) ? end : digit_lower_bound(skey, b, end, shift, o + 1);
+      if (e > b) ++k;
+      b = e;
+    }
+  }
+  nch[t] = k;
+}
+
+__global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __restrict__ skey,
+                                                    uint32_t beg, uint32_t cnt, int level,
+                                                    int leaf_max,
+                                                    const uint32_t* __restrict__ choff,
+                                                    uint32_t next) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  uint32_t c = beg + t;
+  uint32_t first = C.first[c], count = C.count[c];
+  if (!((int)count > leaf_max && level < kMaxLevel)) {
+    C.child[c] = -1;
+    C.nchild[c] = 0;
+    return;
+  }
+  int shift = 3 * (kMaxLevel - level - 1);
+  uint32_t end = first + count;
+  uint32_t b = first;
+  uint32_t out = next + choff[t];
+  uint32_t k = 0;
+  uint64_t pk = C.key[c];
+  for (uint32_t o = 0; o < 8; ++o) {
+    uint32_t e = (o == 7) ? end : digit_lower_bound(skey, b, end, shift, o + 1);
+    if (e > b) {
+      uint32_t d = out + k;
+      C.key[d] = (pk << 3) | o;
+      C.level[d] = level + 1;
+      C.first[d] = b;
+      C.count[d] = e - b;
+      C.child[d] = -1;
+      C.nchild[d] = 0;
+      C.parent[d] = (int32_t)c;
+      ++k;
+    }
+    b = e;
+  }
+  C.child[c] = (int32_t)out;
+  C.nchild[c] = (int32_t)k;
+}
+
+// ------------------------------------------------------------------ moments
+template <int P>
+__device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
+  // C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m-j
+  // stored as gradient coefficients (k'_a+1) C_{m,k'+e_a} for d >= 1.
+  constexpr MI<P> mi{};
+  int o = 0;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    double dfact = 1.0;  // (2m-1)!!
+    for (int q = 1; q <= 2 * m - 1; q += 2) dfact *= (double)q;
+#pragma unroll
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      const int d = m - j;
+      if (!part_stored(m, d)) continue;
+      double pre = dfact * ((j & 1) ? -1.0 : 1.0);
+      for (int q = 0; q < j; ++q) pre *= 0.5;
+      auto Cmk = [&](int ka, int kb, int kc) {
+        // sum over |i| = j of M_{k+2i}/i!, divided by k!
+        double s = 0.0;
+        for (int ia = j; ia >= 0; --ia)
+          for (int ib = j - ia; ib >= 0; --ib) {
+            int ic = j - ia - ib;
+            double fi = 1.0;
+            for (int q = 2; q <= ia; ++q) fi *= q;
+            for (int q = 2; q <= ib; ++q) fi *= q;
+            for (int q = 2; q <= ic; ++q) fi *= q;
+            s += M[mi_index(ka + 2 * ia, kb + 2 * ib, kc + 2 * ic)] / fi;
+          }
+        double fk = 1.0;
+        for (int q = 2; q <= ka; ++q) fk *= q;
+        for (int q = 2; q <= kb; ++q) fk *= q;
+        for (int q = 2; q <= kc; ++q) fk *= q;
+        return pre * s / fk;
+      };
+      if (d == 0) {
+        out[o++] = Cmk(0, 0, 0);
+      } else {
+        // gradient coefficients: component a, monomial k' of degree d-1
+        for (int a = 0; a < 3; ++a)
+          for (int x = d - 1; x >= 0; --x)
+            for (int y = d - 1 - x; y >= 0; --y) {
+              int z = d - 1 - x - y;
+              int ka = x + (a == 0), kb = y + (a == 1), kc = z + (a == 2);
+              int ka1 = (a == 0 ? x : a == 1 ? y : z) + 1;
+              out[o++] = ka1 * Cmk(ka, kb, kc);
+            }
+      }
+    }
+  }
+}
+
+
+template <int P, typename T>
+__global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restrict__ spos,
+                                                 const double* __restrict__ smass, size_t n,
+                                                 uint32_t beg, uint32_t cnt, double L,
+                                                 double theta) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const uint32_t c = beg + t;
+  constexpr int NM = nt(P);
+  constexpr MI<P> mi{};
+  double ctr[3], side;
+  cell_center(C.key[c], C.level[c], L, ctr, &side);
+  const int nc = C.nchild[c];
+  const int c0 = C.child[c];
+  const uint32_t f = C.first[c], e = f + C.count[c];
+  double m = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  if (nc == 0) {
+    for (uint32_t s = f; s < e; ++s) {
+      double ms = smass[s];
+      m = m + ms;
+      sx = sx + ms * spos[s];
+      sy = sy + ms * spos[n + s];
+      sz = sz + ms * spos[2 * n + s];
+    }
+  } else {
+    for (int k = 0; k < nc; ++k) {
+      double4 q = C.mmx[c0 + k];
+      m = m + q.x;
+      sx = sx + q.y;
+      sy = sy + q.z;
+      sz = sz + q.w;
+    }
+  }
+  double com[3];
+  if (m != 0.0) {
+    com[0] = sx / m;
+    com[1] = sy / m;
+    com[2] = sz / m;
+  } else {
+    com[0] = ctr[0];
+    com[1] = ctr[1];
+    com[2] = ctr[2];
+  }
+  double dx = com[0] - ctr[0], dy = com[1] - ctr[1], dz = com[2] - ctr[2];
+  double dd = dx * dx;
+  dd = dd + dy * dy;
+  dd = dd + dz * dz;
+  double rcrit = (theta > 0.0) ? side / theta + sqrt(dd) : __builtin_inf();
+  C.mmx[c] = make_double4(m, sx, sy, sz);
+  C.walk[c] = make_double4(com[0], com[1], com[2], rcrit);
+
+  // raw moments about the centre of mass
+  double M[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) M[k] = 0.0;
+  if (nc == 0) {
+    for (uint32_t s = f; s < e; ++s) {
+      double ms = smass[s];
+      double d[3] = {spos[s] - com[0], spos[n + s] - com[1], spos[2 * n + s] - com[2]};
+      double pw[3][P + 1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
+      }
+#pragma unroll
+      for (int k = 0; k < NM; ++k) M[k] += ms * pw[0][mi.a[k]] * pw[1][mi.b[k]] * pw[2][mi.c[k]];
+    }
+  } else {
+    for (int kc = 0; kc < nc; ++kc) {
+      const int ch = c0 + kc;
+      double4 w = C.walk[ch];
+      double d[3] = {w.x - com[0], w.y - com[1], w.z - com[2]};
+      double pw[3][P + 1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
+      }
+      const double* Mc = C.mom + (size_t)ch * NM;
+      double Mch[NM];
+#pragma unroll
+      for (int k = 0; k < NM; ++k) Mch[k] = Mc[k];
+      // M_k += sum_{j <= k} C(k,j) Mc_j d^(k-j)
+#pragma unroll
+      for (int k = 0; k < NM; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+          if (mi.a[j] > mi.a[k] || mi.b[j] > mi.b[k] || mi.c[j] > mi.c[k]) continue;
+          const int ra = mi.a[k] - mi.a[j], rb = mi.b[k] - mi.b[j], rc = mi.c[k] - mi.c[j];
+          double bin = 1.0;
+          for (int q = 0; q < mi.a[j]; ++q) bin = bin * (double)(mi.a[k] - q) / (double)(q + 1);
+          for (int q = 0; q < mi.b[j]; ++q) bin = bin * (double)(mi.b[k] - q) / (double)(q + 1);
+          for (int q = 0; q < mi.c[j]; ++q) bin = bin * (double)(mi.c[k] - q) / (double)(q + 1);
+          acc += bin * Mch[j] * pw[0][ra] * pw[1][rb] * pw[2][rc];
+        }
+        M[k] += acc;
+      }
+    }
+  }
+  double* Mo = C.mom + (size_t)c * NM;
+#pragma unroll
+  for (int k = 0; k < NM; ++k) Mo[k] = M[k];
+  constexpr int NCF = coef_count(P);
+  constexpr int STR = coef_stride(P);
+  double cf[NCF];
+  coef_from_moments<P>(M, cf);
+  T* out = (T*)C.coef + (size_t)c * STR;
+#pragma unroll
+  for (int k = 0; k < NCF; ++k) out[k] = (T)cf[k];
+#pragma unroll
+  for (int k = NCF; k < STR; ++k) out[k] = (T)0;
+}
+
+// ------------------------------------------------------------------- groups
+__global__ void __launch_bounds__(256) k_group_flags(Cells C, uint32_t ncells, int gmax,
+                                                     uint32_t* __restrict__ gflag,
+                                                     int32_t* __restrict__ gcell_at) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const bool elig = ((int)C.count[c] <= gmax) || (C.nchild[c] == 0);
+  bool isg = elig;
+  if (c != 0) {
+    const int p = C.parent[c];
+    isg = elig && !((int)C.count[p] <= gmax);  // a parent is never a leaf
+  }
+  if (isg) {
+    const uint32_t f = C.first[c];
+    gflag[f] = 1u;
+    gcell_at[f] = (int32_t)c;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_group_compact(const uint32_t* __restrict__ gflag,
+                                                       const uint32_t* __restrict__ gid,
+                                                       const int32_t* __restrict__ gcell_at,
+                                                       size_t n, int32_t* __restrict__ gcell) {
+  size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  if (gflag[s]) gcell[gid[s]] = gcell_at[s];
+}
+
+__global__ void __launch_bounds__(256) k_group_bbox(Cells C, Groups G, uint32_t ngroups,
+                                                    uint32_t gcap, const double* __restrict__ spos,
+                                                    size_t n) {
+  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  const int c = G.cell[g];
+  const uint32_t f = C.first[c], e = f + C.count[c];
+  double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+  double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+  for (uint32_t s = f; s < e; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double v = spos[(size_t)a * n + s];
+      lo[a] = v < lo[a] ? v : lo[a];
+      hi[a] = v > hi[a] ? v : hi[a];
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    G.lo[(size_t)a * gcap + g] = lo[a];
+    G.hi[(size_t)a * gcap + g] = hi[a];
+  }
+}
+
+// source records: FP32/FP64 offsets from the leaf centre and the mass
+template <typename T4, typename T>
+__global__ void __launch_bounds__(256) k_srec(Cells C, uint32_t ncells,
+                                              const double* __restrict__ spos,
+                                              const double* __restrict__ smass, size_t n, double L,
+                                              T4* __restrict__ srec) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells || C.nchild[c] != 0) return;
+  double ctr[3], side;
+  cell_center(C.key[c], C.level[c], L, ctr, &side);
+  const uint32_t f = C.first[c], e = f + C.count[c];
+  for (uint32_t s = f; s < e; ++s) {
+    T4 r;
+    r.x = (T)(spos[s] - ctr[0]);
+    r.y = (T)(spos[n + s] - ctr[1]);
+    r.z = (T)(spos[2 * n + s] - ctr[2]);
+    r.w = (T)smass[s];
+    srec[s] = r;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+hipError_t tree_root(const Cells& C, uint32_t n, hipStream_t s) {
+  k_root<<<1, 1, 0, s>>>(C, n);
+  return hipGetLastError();
+}
+
+hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
+                            int level, int leaf_max, uint32_t* nch, uint32_t* total,
+                            uint32_t* scan_tmp, hipStream_t s) {
+  unsigned g = (cnt + 255) / 256;
+  k_split_count<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, nch);
+  return scan_u32(nch, nch, total, cnt, scan_tmp, s);
+}
+
+hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
+                           int level, int leaf_max, const uint32_t* choff, uint32_t next,
+                           hipStream_t s) {
+  unsigned g = (cnt + 255) / 256;
+  k_split_emit<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, choff, next);
+  return hipGetLastError();
+}
+
+template <int P, typename T>
+static void moments_launch(const Cells& C, const double* spos, const double* smass, size_t n,
+                           uint32_t beg, uint32_t cnt, double L, double theta, hipStream_t s) {
+  k_moments<P, T><<<(cnt + 127) / 128, 128, 0, s>>>(C, spos, smass, n, beg, cnt, L, theta);
+}
+
+hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
+                              uint32_t beg, uint32_t cnt, double L, double theta, int order,
+                              bool fp32, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+#define HOT_MOM(P)                                                              \
+  case P:                                                                       \
+    if (fp32)                                                                   \
+      moments_launch<P, float>(C, spos, smass, n, beg, cnt, L, theta, s);       \
+    else                                                                        \
+      moments_launch<P, double>(C, spos, smass, n, beg, cnt, L, theta, s);      \
+    break;
+  switch (order) {
+    HOT_MOM(0)
+    HOT_MOM(1)
+    HOT_MOM(2)
+    HOT_MOM(3)
+    HOT_MOM(4)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef HOT_MOM
+  return hipGetLastError();
+}
+
+hipError_t tree_groups(const Cells& C, uint32_t ncells, int gmax, size_t n, uint32_t* gflag,
+                       uint32_t* gid, int32_t* gcell_at, const Groups& G, uint32_t* ngroups_dev,
+                       uint32_t* scan_tmp, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(gflag, 0, n * sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  k_group_flags<<<(ncells + 255) / 256, 256, 0, s>>>(C, ncells, gmax, gflag, gcell_at);
+  e = scan_u32(gflag, gid, ngroups_dev, n, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  k_group_compact<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(gflag, gid, gcell_at, n, G.cell);
+  return hipGetLastError();
+}
+
+hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
+                           const double* spos, size_t n, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  k_group_bbox<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, gcap, spos, n);
+  return hipGetLastError();
+}
+
+hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
+                     size_t n, double L, void* srec, bool fp32, hipStream_t s) {
+  unsigned g = (ncells + 255) / 256;
+  if (fp32)
+    k_srec<float4, float><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, (float4*)srec);
+  else
+    k_srec<double4, double><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, (double4*)srec);
+  return hipGetLastError();
+}
+
+}  // namespace hot

@@ -1,0 +1,154 @@
+// Tree walk that emits interaction lists (paper Sec. 2.1: the main stage, an
+// independent traversal per sink group with the multipole acceptance test;
+// sinks that are close together share one list, the m x n bundling).
+//
+// One 64-lane wavefront walks for one sink group.  The pending (image, cell)
+// pairs live in an LDS stack; each step pops up to 64 of them, one per lane,
+// and each lane decides for its pair:
+//   - image 0 and the cell is the group itself: skip (the group's own
+//     particles are handled directly by the force kernel);
+//   - image 0 and the cell contains the group: open;
+//   - acceptance test passes: multipole list;
+//   - a leaf: direct list;
+//   - otherwise: open (push the daughters).
+// Ballots and a wave prefix sum place the emitted entries and the pushed
+// daughters without atomics, so the lists are deterministic.  The test is
+//   (s_B/theta + |com_B - centre_B|)^2 < d^2,
+// d the distance from com_B + n L to the group's tight bounding box, in FP64
+// with separate multiply and add, so that every implementation of the same
+// test takes the same decisions.  The first pass counts, the second writes at
+// the scanned offsets.
+#include "hot_internal.h"
+
+namespace hot {
+
+constexpr int kWalkWaves = 4;
+
+template <bool EMIT>
+__global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uint32_t ngroups,
+                                                          uint32_t gcap, double L, int periodic,
+                                                          uint32_t* __restrict__ p2p_list,
+                                                          uint32_t* __restrict__ m2p_list,
+                                                          uint32_t* __restrict__ status) {
+  __shared__ uint32_t stack_all[kWalkWaves][kWalkStack];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWalkWaves + wid);
+  if (g >= ngroups) return;  // whole wavefront leaves; no block barriers below
+  uint32_t* st = stack_all[wid];
+  const int A = G.cell[g];
+  const uint64_t keyA = C.key[A];
+  const int levA = C.level[A];
+  const double lo0 = G.lo[g], lo1 = G.lo[gcap + g], lo2 = G.lo[2 * (size_t)gcap + g];
+  const double hi0 = G.hi[g], hi1 = G.hi[gcap + g], hi2 = G.hi[2 * (size_t)gcap + g];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  uint32_t top;
+  if (periodic) {
+    if (lane < 27) st[lane] = ((uint32_t)lane << 27);
+    top = 27;
+  } else {
+    if (lane == 0) st[0] = (13u << 27);
+    top = 1;
+  }
+  uint32_t np = 0, nm = 0;
+  uint32_t op = 0, om = 0;
+  if (EMIT) {
+    op = G.off_p2p[g];
+    om = G.off_m2p[g];
+  }
+  __builtin_amdgcn_wave_barrier();
+  while (top > 0) {
+    uint32_t room = (kWalkStack - top) / 7;
+    uint32_t k = top < 64 ? top : 64;
+    k = k < room ? k : room;
+    if (k == 0) {
+      if (lane == 0) atomicOr(status, 4u);
+      break;
+    }
+    top -= k;
+    const bool active = (uint32_t)lane < k;
+    const uint32_t e = active ? st[top + lane] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    const int img = (int)(e >> 27);
+    const int B = (int)(e & kCellMask);
+    // 0 none, 1 open, 2 multipole, 3 direct
+    int action = 0;
+    int nch = 0, ch0 = 0;
+    if (active) {
+      const bool zero = (img == 13);
+      if (!(zero && B == A)) {
+        nch = C.nchild[B];
+        ch0 = C.child[B];
+        bool anc = false;
+        if (zero) {
+          const int levB = C.level[B];
+          anc = (levB <= levA) && ((keyA >> (3 * (levA - levB))) == C.key[B]);
+        }
+        if (anc) {
+          action = 1;
+        } else {
+          const double4 w = C.walk[B];
+          const double n0 = (double)(img / 9 - 1), n1 = (double)((img / 3) % 3 - 1),
+                       n2 = (double)(img % 3 - 1);
+          const double c0 = w.x + n0 * L, c1 = w.y + n1 * L, c2 = w.z + n2 * L;
+          double a0 = lo0 - c0, b0 = c0 - hi0;
+          double a1 = lo1 - c1, b1 = c1 - hi1;
+          double a2 = lo2 - c2, b2 = c2 - hi2;
+          double v0 = a0 > b0 ? a0 : b0, v1 = a1 > b1 ? a1 : b1, v2 = a2 > b2 ? a2 : b2;
+          double d0 = v0 > 0.0 ? v0 : 0.0, d1 = v1 > 0.0 ? v1 : 0.0, d2 = v2 > 0.0 ? v2 : 0.0;
+          double dd = d0 * d0;
+          dd = dd + d1 * d1;
+          dd = dd + d2 * d2;
+          const double rc2 = w.w * w.w;
+          if (rc2 < dd)
+            action = 2;
+          else if (nch == 0)
+            action = 3;
+          else
+            action = 1;
+        }
+      }
+    }
+    const uint64_t bm = __ballot(action == 2);
+    const uint64_t bp = __ballot(action == 3);
+    if (EMIT) {
+      if (action == 2) m2p_list[om + nm + (uint32_t)__popcll(bm & below)] = e;
+      if (action == 3) p2p_list[op + np + (uint32_t)__popcll(bp & below)] = e;
+    }
+    nm += (uint32_t)__popcll(bm);
+    np += (uint32_t)__popcll(bp);
+    // push the daughters of opened cells
+    uint32_t cnt = (action == 1) ? (uint32_t)nch : 0u;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
+    }
+    const uint32_t tot = __shfl(inc, 63, 64);
+    const uint32_t pre = inc - cnt;
+    for (uint32_t q = 0; q < cnt; ++q) st[top + pre + q] = ((uint32_t)img << 27) | (uint32_t)(ch0 + q);
+    top += tot;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (!EMIT && lane == 0) {
+    G.cnt_p2p[g] = np;
+    G.cnt_m2p[g] = nm;
+  }
+}
+
+hipError_t walk_launch(bool emit, const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
+                       double L, int periodic, uint32_t* p2p_list, uint32_t* m2p_list,
+                       uint32_t* status, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  unsigned blocks = (ngroups + kWalkWaves - 1) / kWalkWaves;
+  if (emit)
+    k_walk<true><<<blocks, 64 * kWalkWaves, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
+                                                    m2p_list, status);
+  else
+    k_walk<false><<<blocks, 64 * kWalkWaves, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
+                                                     m2p_list, status);
+  return hipGetLastError();
+}
+
+}  // namespace hot

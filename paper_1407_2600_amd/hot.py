@@ -1,0 +1,300 @@
+"""ctypes binding of libhot (include/hot.h): argument marshalling only.
+
+Every step of the force evaluation runs in the HIP library; PyTorch provides
+device memory (tensors) and the stream.  Importing works without a GPU (so the
+symbol table can be checked on a CPU-only machine); any compute call raises
+if the library or a GPU is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhot.so")
+
+HOT_OK, HOT_EINVAL, HOT_ENOMEM, HOT_EOVERFLOW, HOT_EDEVICE, HOT_EUNSUPPORTED = range(6)
+HOT_FP64, HOT_FP32 = 0, 1
+HOT_ACC_VALID = 1
+STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW",
+                4: "HOT_EDEVICE", 5: "HOT_EUNSUPPORTED"}
+
+# symbols declared in include/hot.h
+EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_forces", "hot_kdk",
+            "hot_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
+            "hot_last_error", "hot_version", "hot_far_table"]
+
+
+class HotError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hot_params(C.Structure):
+    _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
+                ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
+                ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
+                ("precision", C.c_int)]
+
+
+class hot_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ncells", C.c_int64), ("ngroups", C.c_int64),
+                ("nlevels", C.c_int64), ("p2p_entries", C.c_int64), ("m2p_entries", C.c_int64),
+                ("p2p_pairs", C.c_int64), ("m2p_pairs", C.c_int64), ("flops_p2p", C.c_double),
+                ("flops_m2p", C.c_double), ("ms_total", C.c_double), ("ms_sort", C.c_double),
+                ("ms_build", C.c_double), ("ms_walk", C.c_double), ("ms_p2p", C.c_double),
+                ("ms_m2p", C.c_double), ("ms_far", C.c_double), ("ws_bytes_needed", C.c_size_t)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class hot_debug(C.Structure):
+    _fields_ = [("sorted_keys", C.c_void_p), ("perm", C.c_void_p), ("cell_key", C.c_void_p),
+                ("cell_level", C.c_void_p), ("cell_first", C.c_void_p),
+                ("cell_count", C.c_void_p), ("cell_com", C.c_void_p), ("cell_mass", C.c_void_p),
+                ("group_cell", C.c_void_p), ("p2p_offset", C.c_void_p),
+                ("p2p_entry", C.c_void_p), ("m2p_offset", C.c_void_p),
+                ("m2p_entry", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                              "python paper_1407_2600_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, sz = C.c_void_p, C.c_size_t
+        L.hot_create.restype = C.c_int
+        L.hot_create.argtypes = [C.POINTER(hot_params), C.POINTER(vp)]
+        L.hot_destroy.argtypes = [vp]
+        L.hot_workspace_size.restype = sz
+        L.hot_workspace_size.argtypes = [vp, sz]
+        L.hot_forces.restype = C.c_int
+        L.hot_forces.argtypes = [vp, sz, vp, vp, vp, vp, vp, sz, vp]
+        L.hot_kdk.restype = C.c_int
+        L.hot_kdk.argtypes = [vp, sz, vp, vp, vp, vp, vp, C.c_double, C.c_int, C.c_uint, vp, sz,
+                              vp]
+        L.hot_vjp.restype = C.c_int
+        L.hot_vjp.argtypes = [vp, sz, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.hot_get_stats.restype = C.c_int
+        L.hot_get_stats.argtypes = [vp, C.POINTER(hot_stats)]
+        L.hot_debug_sizes.restype = C.c_int
+        L.hot_debug_sizes.argtypes = [vp] + [C.POINTER(C.c_int64)] * 5
+        L.hot_debug_export.restype = C.c_int
+        L.hot_debug_export.argtypes = [vp, vp, C.POINTER(hot_debug)]
+        L.hot_last_error.restype = C.c_char_p
+        L.hot_version.restype = C.c_char_p
+        L.hot_far_table.restype = C.c_int
+        L.hot_far_table.argtypes = [C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double), sz]
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != HOT_OK:
+        raise HotError(status, lib().hot_last_error().decode())
+
+
+def make_params(box=1.0, G=1.0, eps=0.0, theta=0.5, order=4, periodic=1, leaf_max=16,
+                group_max=64, far_order=8, precision="fp64", **_ignored) -> hot_params:
+    prec = precision
+    if isinstance(prec, str):
+        prec = {"fp64": HOT_FP64, "fp32": HOT_FP32}[prec]
+    return hot_params(float(box), float(G), float(eps), float(theta), int(order), int(periodic),
+                      int(leaf_max), int(group_max), int(far_order), int(prec))
+
+
+def far_table(far_order: int, box: float = 1.0, offset: int = 13):
+    """The library's Taylor table of the periodic remainder about the octant
+    offset (dx,dy,dz) L/2, offset = (dx+1)*9+(dy+1)*3+(dz+1) (host code)."""
+    import numpy as np
+    n = (2 * far_order + 1) * (2 * far_order + 2) * (2 * far_order + 3) // 6
+    out = np.zeros(n)
+    check(lib().hot_far_table(int(far_order), float(box), int(offset),
+                              out.ctypes.data_as(C.POINTER(C.c_double)), n))
+    return out
+
+
+class Gravity:
+    """One libhot context: parameters, Ewald table and a cached workspace."""
+
+    def __init__(self, device=None, **params):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libhot needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.params = dict(params)
+        self.prm = make_params(**params)
+        self.fp32 = self.prm.precision == HOT_FP32
+        self.dtype = torch.float32 if self.fp32 else torch.float64
+        self.L = lib()
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self.L.hot_create(C.byref(self.prm), C.byref(h)))
+        self.h = h
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and getattr(self, "L", None) is not None:
+            self.L.hot_destroy(h)
+            self.h = None
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _workspace(self, n: int):
+        need = self.L.hot_workspace_size(self.h, n)
+        if self.ws is None or self.ws.numel() < need:
+            self.ws = None
+            self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        return self.ws
+
+    def _check_inputs(self, pos, mass):
+        t = self.torch
+        if pos.device != self.device or mass.device != self.device:
+            raise ValueError("pos and mass must be on the context's device")
+        if pos.dtype != t.float64 or pos.dim() != 2 or pos.shape[0] != 3:
+            raise ValueError("pos must be a (3, N) float64 tensor")
+        if mass.dtype != self.dtype or mass.shape != (pos.shape[1],):
+            raise ValueError(f"mass must be a (N,) {self.dtype} tensor")
+        return pos.contiguous(), mass.contiguous()
+
+    def _call_retry(self, fn, n):
+        for _ in range(6):
+            ws = self._workspace(n)
+            st = fn(ws)
+            if st != HOT_EOVERFLOW:
+                check(st)
+                return
+        check(st)
+
+    def forces(self, pos, mass, out_acc=None, out_pot=None, want_pot=True):
+        """(acc[3,N], pot[N]) in the context's precision."""
+        t = self.torch
+        pos, mass = self._check_inputs(pos, mass)
+        n = pos.shape[1]
+        acc = out_acc if out_acc is not None else t.empty((3, n), dtype=self.dtype,
+                                                          device=self.device)
+        pot = out_pot if out_pot is not None else (
+            t.empty(n, dtype=self.dtype, device=self.device) if want_pot else None)
+        if n == 0:
+            return acc, pot
+        s = self._stream()
+
+        def run(ws):
+            return self.L.hot_forces(self.h, n, C.c_void_p(pos.data_ptr()),
+                                     C.c_void_p(mass.data_ptr()), C.c_void_p(acc.data_ptr()),
+                                     C.c_void_p(pot.data_ptr() if pot is not None else 0),
+                                     C.c_void_p(ws.data_ptr()), ws.numel(), s)
+        self._call_retry(run, n)
+        return acc, pot
+
+    def kdk(self, pos, vel, mass, acc, dt: float, nsteps: int, acc_valid: bool, pot=None):
+        """In-place leapfrog steps on pos (FP64), vel and acc (precision)."""
+        pos_c, mass = self._check_inputs(pos, mass)
+        if not (pos_c.data_ptr() == pos.data_ptr()):
+            raise ValueError("pos must be contiguous (it is updated in place)")
+        for name, a in (("vel", vel), ("acc", acc)):
+            if a.dtype != self.dtype or a.shape != pos.shape or not a.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous (3, N) {self.dtype} tensor")
+        n = pos.shape[1]
+        s = self._stream()
+        flags = HOT_ACC_VALID if acc_valid else 0
+
+        def run(ws):
+            return self.L.hot_kdk(self.h, n, C.c_void_p(pos.data_ptr()),
+                                  C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
+                                  C.c_void_p(acc.data_ptr()),
+                                  C.c_void_p(pot.data_ptr() if pot is not None else 0),
+                                  float(dt), int(nsteps), flags, C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), s)
+        self._call_retry(run, n)
+
+    def vjp(self, pos, mass, gacc, gpot=None):
+        """(xbar[3,N] FP64, mbar[N]) for cotangents of (acc, pot)."""
+        t = self.torch
+        pos, mass = self._check_inputs(pos, mass)
+        n = pos.shape[1]
+        gacc = gacc.to(self.dtype).contiguous()
+        gpot = gpot.to(self.dtype).contiguous() if gpot is not None else None
+        xbar = t.empty((3, n), dtype=t.float64, device=self.device)
+        mbar = t.empty(n, dtype=self.dtype, device=self.device)
+        s = self._stream()
+
+        def run(ws):
+            return self.L.hot_vjp(self.h, n, C.c_void_p(pos.data_ptr()),
+                                  C.c_void_p(mass.data_ptr()), C.c_void_p(gacc.data_ptr()),
+                                  C.c_void_p(gpot.data_ptr() if gpot is not None else 0),
+                                  C.c_void_p(xbar.data_ptr()), C.c_void_p(mbar.data_ptr()),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), s)
+        self._call_retry(run, n)
+        return xbar, mbar
+
+    def stats(self) -> dict:
+        st = hot_stats()
+        check(self.L.hot_get_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def debug_export(self) -> dict:
+        """Host copies of keys, permutation, cells, groups and lists of the
+        last forces() call (numpy arrays)."""
+        import numpy as np
+        sizes = [C.c_int64() for _ in range(5)]
+        check(self.L.hot_debug_sizes(self.h, *[C.byref(x) for x in sizes]))
+        n, nc, ng, tp, tm = [x.value for x in sizes]
+        out = dict(sorted_keys=np.zeros(n, np.uint64), perm=np.zeros(n, np.uint32),
+                   cell_key=np.zeros(nc, np.uint64), cell_level=np.zeros(nc, np.int32),
+                   cell_first=np.zeros(nc, np.int32), cell_count=np.zeros(nc, np.int32),
+                   cell_com=np.zeros((3, nc)), cell_mass=np.zeros(nc),
+                   group_cell=np.zeros(ng, np.int32), p2p_offset=np.zeros(ng + 1, np.int64),
+                   p2p_entry=np.zeros(tp, np.uint32), m2p_offset=np.zeros(ng + 1, np.int64),
+                   m2p_entry=np.zeros(tm, np.uint32))
+        dbg = hot_debug(*[C.c_void_p(out[f].ctypes.data) for f, _ in hot_debug._fields_])
+        check(self.L.hot_debug_export(self.h, C.c_void_p(self.ws.data_ptr()), C.byref(dbg)))
+        return out
+
+
+def _autograd():
+    import torch
+
+    class GravityForces(torch.autograd.Function):
+        """acc, pot = GravityForces.apply(gravity, pos, mass); backward runs
+        the library's adjoint (hot_vjp)."""
+
+        @staticmethod
+        def forward(ctx, grav, pos, mass):
+            acc, pot = grav.forces(pos.detach(), mass.detach())
+            ctx.grav = grav
+            ctx.save_for_backward(pos.detach(), mass.detach())
+            return acc, pot
+
+        @staticmethod
+        def backward(ctx, gacc, gpot):
+            pos, mass = ctx.saved_tensors
+            grav = ctx.grav
+            if gacc is None:
+                gacc = torch.zeros((3, pos.shape[1]), dtype=grav.dtype, device=pos.device)
+            xbar, mbar = grav.vjp(pos, mass, gacc, gpot)
+            return None, xbar, mbar
+
+    return GravityForces
+
+
+_GF = None
+
+
+def gravity_forces(grav: Gravity, pos, mass):
+    """Differentiable forces: (acc, pot) with gradients to pos and mass."""
+    global _GF
+    if _GF is None:
+        _GF = _autograd()
+    return _GF.apply(grav, pos, mass)

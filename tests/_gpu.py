@@ -1,0 +1,79 @@
+"""Helpers shared by the GPU tests: run the library through its binding and
+compare its exported structures with the oracle's, element by element."""
+import numpy as np
+
+import oracle
+
+IMG_SHIFT = 27
+CELL_MASK = (1 << 27) - 1
+
+
+def run_gpu(pos, mass, params, precision="fp64", want_debug=True):
+    import torch
+    from paper_1407_2600_amd import Gravity
+    g = Gravity(**dict(params, precision=precision))
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    p = torch.as_tensor(np.ascontiguousarray(pos), dtype=torch.float64, device="cuda")
+    m = torch.as_tensor(np.ascontiguousarray(mass), dtype=dt, device="cuda")
+    acc, pot = g.forces(p, m)
+    torch.cuda.synchronize()
+    out = dict(acc=acc.double().cpu().numpy(), pot=pot.double().cpu().numpy(),
+               stats=g.stats())
+    if want_debug:
+        out["dbg"] = g.debug_export()
+    out["grav"] = g
+    return out
+
+
+def group_lists_gpu(dbg, kind):
+    """{group cell key: sorted list of (image, cell key)} from the GPU export."""
+    ck = dbg["cell_key"]
+    off = dbg["m2p_offset" if kind else "p2p_offset"]
+    ent = dbg["m2p_entry" if kind else "p2p_entry"]
+    out = {}
+    for g, c in enumerate(dbg["group_cell"]):
+        e = ent[off[g]:off[g + 1]].astype(np.int64)
+        img = e >> IMG_SHIFT
+        cells = ck[e & CELL_MASK]
+        out[int(ck[c])] = sorted(zip(img.tolist(), [int(x) for x in cells]))
+    return out
+
+
+def group_list_oracle(T, cells, g, kind):
+    img, cell = T.group_list(g, kind)
+    return sorted(zip(img.tolist(), [int(x) for x in cells["key"][cell]]))
+
+
+def compare_structure(dbg, T, sample_groups=None):
+    """Bit-exact comparison of keys, order, cells, centres of mass, groups and
+    interaction lists.  With sample_groups, only those oracle groups' lists."""
+    perm_o, sk_o = T.perm()
+    np.testing.assert_array_equal(dbg["sorted_keys"], sk_o)
+    np.testing.assert_array_equal(dbg["perm"].astype(np.int64), perm_o)
+    c = T.cells()
+    nc = len(c["key"])
+    assert len(dbg["cell_key"]) == nc
+    # the library stores cells level-major; order by (first, level) to compare
+    order = np.lexsort((dbg["cell_level"], dbg["cell_first"]))
+    np.testing.assert_array_equal(dbg["cell_key"][order], c["key"])
+    np.testing.assert_array_equal(dbg["cell_level"][order], c["level"])
+    np.testing.assert_array_equal(dbg["cell_first"][order].astype(np.int64), c["first"])
+    np.testing.assert_array_equal(dbg["cell_count"][order].astype(np.int64), c["count"])
+    # centres of mass and masses: same FP64 operations in the same order
+    np.testing.assert_array_equal(dbg["cell_com"][:, order], c["com"])
+    np.testing.assert_array_equal(dbg["cell_mass"][order], c["mass"])
+    gcell_o, _, _ = T.groups()
+    gk_gpu = sorted(int(dbg["cell_key"][x]) for x in dbg["group_cell"])
+    gk_o = sorted(int(c["key"][x]) for x in gcell_o)
+    assert gk_gpu == gk_o
+    for kind in (0, 1):
+        lg = group_lists_gpu(dbg, kind)
+        groups = range(len(gcell_o)) if sample_groups is None else sample_groups
+        for g in groups:
+            key = int(c["key"][gcell_o[g]])
+            lo = group_list_oracle(T, c, g, kind)
+            assert lg[key] == lo, (kind, g, len(lg[key]), len(lo))
+
+
+def rms_err(a, ref):
+    return oracle.rms_rel_error(a, ref)

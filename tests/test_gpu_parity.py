@@ -1,0 +1,199 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs.  Keys, sort order, cells, centres of mass, sink groups and interaction
+lists must be identical bit for bit (both precisions share the FP64 tree);
+accelerations and potentials must match the same-test oracle tree to an rms
+relative error of 1e-5 (FP64 mode) and 2e-5 (FP32 mode)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from _gpu import compare_structure, rms_err, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-5, "fp32": 2e-5}
+
+CASES = [
+    # name, n_side, overrides
+    ("lattice16", 16, {}),
+    ("zeldovich128", 20, {}),                               # 8000: ragged groups
+    ("nfw256", 16, dict(leaf_max=8, group_max=32)),          # clustered, deep tree
+    ("zeldovich128", 14, dict(leaf_max=4, group_max=16, theta=0.7)),
+]
+
+
+def _case(name, ns, over):
+    pos, mass, prm = workloads.make(name, n_side=ns)
+    prm = dict(prm, **over)
+    return pos, mass, prm
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,ns,over", CASES)
+def test_structure_and_forces(name, ns, over, precision):
+    pos, mass, prm = _case(name, ns, over)
+    print(f"case {name} n_side={ns} {over} {precision}", flush=True)
+    T = oracle.Tree(pos, mass, prm)
+    r = run_gpu(pos, mass, prm, precision)
+    compare_structure(r["dbg"], T)
+    acc_o, pot_o = T.forces()
+    ea = rms_err(r["acc"], acc_o)
+    ep = rms_err(r["pot"], pot_o)
+    print(f"  acc err {ea:.3e} pot err {ep:.3e}", flush=True)
+    assert ea <= TOL[precision]
+    assert ep <= TOL[precision]
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
+def test_every_order_fp64(order):
+    pos, mass, prm = _case("zeldovich128", 12, dict(order=order, leaf_max=8, group_max=32))
+    T = oracle.Tree(pos, mass, prm)
+    r = run_gpu(pos, mass, prm, "fp64", want_debug=False)
+    acc_o, pot_o = T.forces()
+    assert rms_err(r["acc"], acc_o) < 1e-10
+    assert rms_err(r["pot"], pot_o) < 1e-10
+
+
+@pytest.mark.parametrize("far_order", [0, 3, 8, 10])
+def test_far_orders_fp64(far_order):
+    pos, mass, prm = _case("lattice16", 10, dict(far_order=far_order, order=4))
+    T = oracle.Tree(pos, mass, prm)
+    r = run_gpu(pos, mass, prm, "fp64", want_debug=False)
+    acc_o, pot_o = T.forces()
+    assert rms_err(r["acc"], acc_o) < 1e-9
+    assert rms_err(r["pot"], pot_o) < 1e-9
+
+
+def test_theta_zero_is_direct_sum():
+    pos, mass, prm = _case("nfw256", 12, dict(theta=0.0, leaf_max=8, group_max=32))
+    T = oracle.Tree(pos, mass, prm)
+    r = run_gpu(pos, mass, prm, "fp64")
+    assert r["dbg"]["m2p_entry"].size == 0
+    a0, p0 = T.direct_near_far(np.arange(pos.shape[1]))
+    assert rms_err(r["acc"], a0) < 1e-12
+    assert rms_err(r["pot"], p0) < 1e-12
+
+
+def test_open_boundaries():
+    rng = np.random.default_rng(21)
+    pos = rng.random((3, 3000))
+    mass = rng.random(3000) / 3000
+    prm = dict(box=1.0, G=1.3, eps=0.003, theta=0.0, order=4, periodic=0, leaf_max=16,
+               group_max=64, far_order=8)
+    a0, p0 = oracle.direct_open(pos, mass, 1.3, 0.003)
+    r = run_gpu(pos, mass, prm, "fp64", want_debug=False)
+    assert rms_err(r["acc"], a0) < 1e-12
+    assert rms_err(r["pot"], p0) < 1e-12
+    prm["theta"] = 0.6
+    T = oracle.Tree(pos, mass, prm)
+    for prec in ("fp64", "fp32"):
+        r = run_gpu(pos, mass, prm, prec)
+        compare_structure(r["dbg"], T)
+        acc_o, pot_o = T.forces()
+        assert rms_err(r["acc"], acc_o) < TOL[prec]
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65])
+def test_tiny_inputs(n):
+    rng = np.random.default_rng(n)
+    pos = rng.random((3, n))
+    mass = np.full(n, 1.0 / n)
+    prm = dict(box=1.0, G=1.0, eps=0.01, theta=0.5, order=4, periodic=1, leaf_max=4,
+               group_max=16, far_order=6)
+    T = oracle.Tree(pos, mass, prm)
+    acc_o, pot_o = T.forces()
+    for prec in ("fp64", "fp32"):
+        r = run_gpu(pos, mass, prm, prec)
+        compare_structure(r["dbg"], T)
+        assert rms_err(r["acc"], acc_o) < TOL[prec]
+        assert rms_err(r["pot"], pot_o) < TOL[prec]
+
+
+def test_coincident_particles_and_large_groups():
+    """Coincident particles force level-21 leaves above leaf_max; a large
+    group_max gives groups of more than 64 targets (several tiles)."""
+    rng = np.random.default_rng(5)
+    pos = rng.random((3, 3000))
+    pos[:, 100:400] = pos[:, 100:101]  # 300 particles at one point
+    pos[:, 1000:1090] = 0.999999999999  # near the upper box edge
+    mass = rng.random(3000) * 1e-3
+    prm = dict(box=1.0, G=1.0, eps=0.01, theta=0.5, order=4, periodic=1, leaf_max=16,
+               group_max=200, far_order=8)
+    T = oracle.Tree(pos, mass, prm)
+    c = T.cells()
+    assert np.any((c["level"] == 21) & (c["count"] > 16))
+    acc_o, pot_o = T.forces()
+    for prec in ("fp64", "fp32"):
+        r = run_gpu(pos, mass, prm, prec)
+        compare_structure(r["dbg"], T)
+        assert rms_err(r["acc"], acc_o) < TOL[prec]
+        assert rms_err(r["pot"], pot_o) < TOL[prec]
+
+
+def test_positions_outside_box_are_wrapped():
+    pos, mass, prm = _case("zeldovich128", 10, {})
+    shifted = pos.copy()
+    shifted[0, ::3] -= 1.0   # in [-L, 0)
+    shifted[1, 1::3] += 1.0  # in [L, 2L)
+    T = oracle.Tree(shifted, mass, prm)
+    r = run_gpu(shifted, mass, prm, "fp64")
+    compare_structure(r["dbg"], T)
+    acc_o, _ = T.forces()
+    assert rms_err(r["acc"], acc_o) < 1e-10
+
+
+def test_invalid_inputs_raise():
+    import torch
+    from paper_1407_2600_amd import Gravity, HotError
+    g = Gravity(box=1.0, eps=0.01)
+    pos = torch.rand((3, 100), dtype=torch.float64, device="cuda")
+    m = torch.full((100,), 0.01, dtype=torch.float64, device="cuda")
+    for bad in (float("nan"), 2.5, -1.5, float("inf")):
+        p = pos.clone()
+        p[1, 7] = bad
+        with pytest.raises(HotError, match="EINVAL"):
+            g.forces(p, m)
+    mm = m.clone()
+    mm[3] = -1.0
+    with pytest.raises(HotError, match="EINVAL"):
+        g.forces(pos, mm)
+    # still usable afterwards
+    acc, pot = g.forces(pos, m)
+    assert torch.isfinite(acc).all()
+    # n = 0 is a no-op
+    acc0, pot0 = g.forces(pos[:, :0].contiguous(), m[:0].contiguous())
+    assert acc0.shape == (3, 0)
+
+
+def test_deterministic_repeat():
+    pos, mass, prm = _case("nfw256", 14, {})
+    for prec in ("fp64", "fp32"):
+        r1 = run_gpu(pos, mass, prm, prec, want_debug=False)
+        r2 = run_gpu(pos, mass, prm, prec, want_debug=False)
+        np.testing.assert_array_equal(r1["acc"], r2["acc"])
+        np.testing.assert_array_equal(r1["pot"], r2["pot"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_full_size_zeldovich128(precision):
+    """The headline workload at its full size (128^3 = 2,097,152 particles):
+    keys, order and cells bit-exact over the whole tree; lists and forces on
+    sampled sink groups against the oracle."""
+    pos, mass, prm = workloads.make("zeldovich128")
+    print(f"full size {precision}: building oracle tree", flush=True)
+    T = oracle.Tree(pos, mass, prm)
+    r = run_gpu(pos, mass, prm, precision)
+    print("  gpu stats", {k: r["stats"][k] for k in ("ncells", "ngroups", "p2p_entries",
+                                                     "m2p_entries")}, flush=True)
+    gcell, _, _ = T.groups()
+    rng = np.random.default_rng(99)
+    sample = np.sort(rng.choice(len(gcell), size=24, replace=False))
+    compare_structure(r["dbg"], T, sample_groups=sample)
+    acc_o, pot_o = T.forces(groups=sample)
+    sel = ~np.isnan(pot_o)
+    ea = rms_err(r["acc"][:, sel], acc_o[:, sel])
+    ep = rms_err(r["pot"][sel], pot_o[sel])
+    print(f"  sampled targets {sel.sum()} acc err {ea:.3e} pot err {ep:.3e}", flush=True)
+    assert ea <= TOL[precision]
+    assert ep <= TOL[precision]

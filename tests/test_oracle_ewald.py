@@ -178,3 +178,85 @@ def test_momentum_conservation_and_translation_invariance():
     acc2, pot2 = oracle.direct_ewald(pos + shift, mass, prm)
     np.testing.assert_allclose(acc2, acc, atol=1e-12 * np.max(np.abs(acc)))
     np.testing.assert_allclose(pot2, pot, atol=1e-12 * np.max(np.abs(pot)))
+
+
+OFFSETS = [(1, 0, 0), (1, 1, 0), (1, 1, 1), (-1, 0, 1)]
+
+
+@pytest.mark.parametrize("off", OFFSETS)
+def test_psi_table_at_reproduces_psi(off):
+    """The table about r0 = off * L/2 must reproduce
+    Psi(r) = psi_E(r) - sum_{|n|inf<=1} 1/|r + nL| near r0, with the
+    truncation error falling like |h|^(D+1)."""
+    L = 1.0
+    r0 = np.array(off, float) * 0.5 * L
+    D = 12
+    T = oracle.psi_table_at(D, r0, L)
+    mi = np.array(oracle.mi_list(D))
+
+    def psi_direct(r):
+        p, _ = oracle.ewald_psi(r, L, 2.0, 5, 12)
+        for nx in (-1, 0, 1):
+            for ny in (-1, 0, 1):
+                for nz in (-1, 0, 1):
+                    p -= 1.0 / np.linalg.norm(r + np.array([nx, ny, nz]) * L)
+        return p
+
+    direction = np.array([0.3, -0.5, 0.8])
+    direction /= np.linalg.norm(direction)
+    errs = []
+    for hs in (0.1, 0.05):
+        h = hs * direction
+        series = np.sum(T * np.prod(h[None, :] ** mi, axis=1))
+        errs.append(abs(series - psi_direct(r0 + h)))
+    assert errs[0] < 1e-9
+    assert errs[1] <= errs[0] + 1e-13
+
+
+@pytest.mark.parametrize("off", OFFSETS)
+def test_psi_table_at_symmetries(off):
+    """Psi is even in each coordinate: reflecting r0 in axis a multiplies
+    T_s by (-1)^{s_a}; inverting r0 multiplies it by (-1)^{|s|}."""
+    L = 1.0
+    D = 10
+    r0 = np.array(off, float) * 0.5 * L
+    T = oracle.psi_table_at(D, r0, L)
+    mi = np.array(oracle.mi_list(D))
+    scale = np.max(np.abs(T))
+    Tm = oracle.psi_table_at(D, -r0, L)
+    np.testing.assert_allclose(Tm, T * (-1.0) ** mi.sum(1), atol=1e-11 * scale)
+    rx = r0 * np.array([-1, 1, 1])
+    Tx = oracle.psi_table_at(D, rx, L)
+    np.testing.assert_allclose(Tx, T * (-1.0) ** mi[:, 0], atol=1e-11 * scale)
+    # permuting the axes of r0 permutes the multi-indices:
+    # Psi(rp + h) with rp = (y0, z0, x0) equals Psi(r0 + (h3, h1, h2)), so
+    # the coefficient of h^(b,c,a) about rp is that of h^(a,b,c) about r0
+    rp = r0[[1, 2, 0]]
+    Tp = oracle.psi_table_at(D, rp, L)
+    idx = {tuple(m): i for i, m in enumerate(mi.tolist())}
+    for i, (a, b, c) in enumerate(mi.tolist()):
+        assert Tp[idx[(b, c, a)]] == pytest.approx(T[i], abs=1e-11 * scale)
+
+
+@pytest.mark.parametrize("off", [(1, 0, 0), (1, 1, 1)])
+def test_psi_table_at_vs_bare_lattice_sum(off):
+    """Degree >= 3 coefficients about r0 are absolutely convergent sums of the
+    bare 1/r coefficients over the images |n|_inf >= 2 (expanded about
+    r0 + nL)."""
+    deg = 8
+    r0 = np.array(off, float) * 0.5
+    T = oracle.psi_table_at(deg, r0, 1.0)
+    mi = oracle.mi_list(deg)
+    sel = [i for i, m in enumerate(mi) if sum(m) == deg]
+    K = 12
+    S = np.zeros(len(mi))
+    for nx in range(-K, K + 1):
+        for ny in range(-K, K + 1):
+            for nz in range(-K, K + 1):
+                if max(abs(nx), abs(ny), abs(nz)) < 2:
+                    continue
+                S += oracle.green_taylor(deg, r0 + np.array([nx, ny, nz], float), 0.0)
+    tail = 4 * np.pi * 3.0 ** deg * (K - 1) ** (2 - deg) / (deg - 2)
+    err = np.max(np.abs(T[sel] - S[sel]))
+    assert err < tail
+    assert err < 1e-4 * np.max(np.abs(T[sel])) + 1e-12

@@ -214,21 +214,21 @@ def test_open_boundary_two_body_and_momentum():
 
 
 def test_far_field_converges_to_ewald():
-    """theta=0 tree (27 softened images + far-field local expansion) against
-    the exact direct Ewald sum: the far-field truncation error falls with the
-    expansion order (measured floors: p=8 ~2.5e-4, p=12 ~8e-6 on this
-    near-lattice set whose forces nearly cancel)."""
+    """theta=0 tree (27 softened images + far-field local expansions about
+    the octant centres) against the exact direct Ewald sum: the truncation
+    error falls with the expansion order (measured on the 16^3 set: p=4
+    1.1e-3, p=6 3.8e-5, p=8 2.9e-7 -- the paper's one part in 1e7)."""
     pos, mass, prm = workloads.make("lattice16", n_side=12)
     n = pos.shape[1]
     tg = np.arange(0, n, 3)
     a1, p1 = oracle.direct_ewald(pos, mass, prm, targets=tg)
     errs = []
-    for pf in (6, 8, 10, 12):
+    for pf in (4, 6, 8):
         T = oracle.Tree(pos, mass, dict(prm, theta=0.0, far_order=pf))
         a0, p0 = T.direct_near_far(tg)
         errs.append(oracle.rms_rel_error(a0, a1))
-    assert all(errs[i + 1] < errs[i] for i in range(3))
-    assert errs[-1] < 3e-5
+    assert all(errs[i + 1] < errs[i] for i in range(2))
+    assert errs[-1] < 2e-6
 
 
 def test_tree_error_falls_with_theta_and_order():
@@ -261,7 +261,7 @@ def test_perfect_lattice_tree_residual():
     res = []
     for th in (0.7, 0.5, 0.3):
         T = oracle.Tree(pos, mass, dict(box=1.0, eps=0.0, theta=th, order=4, leaf_max=8,
-                                        group_max=8, far_order=10))
+                                        group_max=8, far_order=8))
         a, p = T.forces()
         res.append(np.max(np.abs(a)) / ((1.0 / N) * n * n))
     assert res[2] < res[1] < res[0] < 1e-2
