@@ -85,6 +85,7 @@ def lib():
         L.or_tree_pair_count.argtypes = [vp]
         L.or_tree_forces.argtypes = [vp, i64, i64p, dp, dp]
         L.or_tree_far.argtypes = [vp, dp, dp, dp]
+        L.or_tree_vjp.argtypes = [vp, dp, dp, i64, i64p, dp, dp]
         L.or_direct_near_far.argtypes = [vp, i64, i64p, dp, dp]
         L.or_direct_open.argtypes = [i64, dp, dp, C.c_double, C.c_double, dp, dp]
         L.or_direct_ewald.argtypes = [i64, dp, dp, i64, i64p, C.c_double, C.c_double,
@@ -336,6 +337,24 @@ class Tree:
             self.lib.or_tree_forces(self.h, len(g), _p(g, C.c_int64), _p(acc), _p(pot))
         return acc, pot
 
+    def vjp(self, gacc, gpot=None, groups=None):
+        """(xbar[3,N], mbar[N]) for cotangents (gacc[3,N], gpot[N]) of the
+        forces: the gather-form adjoint over the same lists (exact derivative
+        of the direct sum at theta = 0).  With ``groups`` only their particles
+        are filled (NaN elsewhere)."""
+        ga = np.ascontiguousarray(gacc, dtype=np.float64)
+        gp = None if gpot is None else np.ascontiguousarray(gpot, dtype=np.float64)
+        xb = np.full((3, self.n), np.nan)
+        mb = np.full(self.n, np.nan)
+        if groups is None:
+            self.lib.or_tree_vjp(self.h, _p(ga), None if gp is None else _p(gp), -1, None,
+                                 _p(xb), _p(mb))
+        else:
+            g = np.ascontiguousarray(groups, dtype=np.int64)
+            self.lib.or_tree_vjp(self.h, _p(ga), None if gp is None else _p(gp), len(g),
+                                 _p(g, C.c_int64), _p(xb), _p(mb))
+        return xb, mb
+
     def direct_near_far(self, targets):
         t = np.ascontiguousarray(targets, dtype=np.int64)
         acc = np.zeros((3, len(t)))
@@ -349,3 +368,32 @@ def rms_rel_error(a, ref) -> float:
     a = np.asarray(a, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))
+
+
+def wrap_box(x, box: float):
+    """Wrap into [0, L) with the floor form (any displacement)."""
+    x = x - box * np.floor(x / box)
+    x = np.where(x >= box, x - box, x)
+    return np.where(x < 0.0, 0.0, x)
+
+
+def kdk(pos, vel, mass, params: dict, dt: float, nsteps: int, acc=None):
+    """Fixed-step kick-drift-kick leapfrog (the single-rung case of the
+    paper's adaptive symplectic integrator, Sec. 2.1):
+    v += a dt/2; x = wrap(x + v dt); a = forces(x); v += a dt/2.
+    Returns (pos, vel, acc, pot) after nsteps."""
+    box = float(params.get("box", 1.0))
+    periodic = int(params.get("periodic", 1))
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    pot = None
+    if acc is None:
+        acc, pot = Tree(pos, mass, params).forces()
+    for _ in range(nsteps):
+        vel = vel + (0.5 * dt) * acc
+        pos = pos + dt * vel
+        if periodic:
+            pos = wrap_box(pos, box)
+        acc, pot = Tree(pos, mass, params).forces()
+        vel = vel + (0.5 * dt) * acc
+    return pos, vel, acc, pot

@@ -822,3 +822,294 @@ void or_direct_open(int64_t n, const double* pos, const double* mass, double G, 
     if (pot) pot[i] = -G * phi;
   }
 }
+
+/* ======================= adjoint (vector-Jacobian product) ===================
+ * An extension beyond the paper.  For the loss L = sum_i gacc_i . a_i +
+ * gpot_i phi_i, with a_i = G grad_i Phi_i and phi_i = -G Phi_i, the exact
+ * derivatives of the direct sum, written as gathers over each particle's own
+ * near pairs (r = x_k - x_j - nL, H = Hessian of g):
+ *   xbar_k = G sum_j [ H(r) (m_j gacc_k - m_k gacc_j) - grad g(r) (m_j gpot_k + m_k gpot_j) ]
+ *   mbar_k = -G sum_j [ gacc_j . grad g(r) + gpot_j g(r) ]
+ * The tree version evaluates these sums with the forward lists: leaves and the
+ * own group pair by pair, accepted cells through multipole expansions of the
+ * three kinds of source (masses, vector charges gacc_j, scalar charges gpot_j)
+ * about the cell's centre of mass, with Taylor coefficients to degree p+2.
+ * The periodic far field is differentiated exactly: target side through the
+ * local expansions, source side through adjoint local coefficients
+ *   Lbar^t_q = G sum_{i in t} (gacc_i . grad h^q - gpot_i h^q)
+ * carried back to the octant moments and on to each source particle.  At
+ * theta = 0 this is the exact derivative of the 27-image + far-field sum. */
+
+typedef struct {
+  double* Qa;  /* per cell: 3 x nmom moments of the vector charges gacc */
+  double* Qp;  /* per cell: nmom moments of the scalar charges gpot */
+} adj_mom_t;
+
+static void adj_moments(const tree_t* T, const double* sga, const double* sgp, adj_mom_t* A) {
+  int p = T->p.order, nm = T->nmom;
+  int64_t n = T->n;
+  A->Qa = calloc((size_t)T->ncells * 3 * nm, sizeof(double));
+  A->Qp = calloc((size_t)T->ncells * nm, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t ci = 0; ci < T->ncells; ++ci) {
+    const cell_t* c = &T->cells[ci];
+    double* qa = A->Qa + (size_t)ci * 3 * nm;
+    double* qp = A->Qp + (size_t)ci * nm;
+    for (int64_t s = c->first; s < c->first + c->count; ++s) {
+      double d[3] = {T->sx[0][s] - c->com[0], T->sx[1][s] - c->com[1], T->sx[2][s] - c->com[2]};
+      double pw[3][OR_DMAX + 1];
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+        for (int e = 1; e <= p; ++e) pw[a][e] = pw[a][e - 1] * d[a];
+      }
+      for (int k = 0; k < nm; ++k) {
+        int ka, kb, kc;
+        or_mi_get(k, &ka, &kb, &kc);
+        double mono = pw[0][ka] * pw[1][kb] * pw[2][kc];
+        for (int a = 0; a < 3; ++a) qa[a * nm + k] += sga[a * n + s] * mono;
+        qp[k] += sgp[s] * mono;
+      }
+    }
+  }
+}
+
+/* exact pair adjoint: target k (tx, m_k, gacc_k, gpot_k), source j at (sx)
+ * with m_j, gacc_j, gpot_j; r = x_k - x_j */
+static void pair_adj(const double r[3], double eps2, double mk, const double gak[3], double gpk,
+                     double mj, const double gaj[3], double gpj, double xb[3], double* mb) {
+  double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+  double si = 1.0 / sqrt(r2);
+  double si3 = si * si * si, si5 = si3 * si * si;
+  double w[3], rw = 0.0, ra = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    w[a] = mj * gak[a] - mk * gaj[a];
+    rw += r[a] * w[a];
+    ra += r[a] * gaj[a];
+  }
+  double cp = mj * gpk + mk * gpj;
+  for (int a = 0; a < 3; ++a) {
+    /* H w = -w/s^3 + 3 r (r.w)/s^5 ;  -grad g = r/s^3 */
+    xb[a] += -w[a] * si3 + 3.0 * r[a] * rw * si5 + r[a] * si3 * cp;
+  }
+  /* -(gacc_j . grad g + gpot_j g) = (r . gacc_j)/s^3 - gpot_j/s */
+  *mb += ra * si3 - gpj * si;
+}
+
+static int mi3(int a, int b, int c) { return or_mi(a, b, c); }
+
+/* multipole adjoint of one accepted cell for one target */
+static void m2p_adj(const tree_t* T, int64_t bi, const adj_mom_t* AM, const double R[3],
+                    double mk, const double gak[3], double gpk, double xb[3], double* mb) {
+  int p = T->p.order, nm = T->nmom;
+  double Tk[4096];
+  or_green_taylor(p + 2, R, T->p.eps * T->p.eps, Tk);
+  const double* M = T->cells[bi].M;
+  const double* Qa = AM->Qa + (size_t)bi * 3 * nm;
+  const double* Qp = AM->Qp + (size_t)bi * nm;
+  double Hm[3][3] = {{0}}, Gm[3] = {0}, Gp[3] = {0}, psiV = 0.0, Pp = 0.0, GV[3] = {0};
+  for (int k = 0; k < nm; ++k) {
+    int kk[3];
+    or_mi_get(k, &kk[0], &kk[1], &kk[2]);
+    double sg = ((kk[0] + kk[1] + kk[2]) % 2) ? -1.0 : 1.0;
+    for (int a = 0; a < 3; ++a) {
+      int e1[3] = {kk[0], kk[1], kk[2]};
+      e1[a] += 1;
+      double d1 = (double)e1[a] * Tk[mi3(e1[0], e1[1], e1[2])]; /* d_a T_k */
+      Gm[a] += sg * M[k] * d1;
+      Gp[a] += sg * Qp[k] * d1;
+      psiV += sg * Qa[a * nm + k] * d1;
+      for (int b = 0; b < 3; ++b) {
+        int e2[3] = {e1[0], e1[1], e1[2]};
+        e2[b] += 1;
+        /* d_b d_a T_k = (k_a+1) (k+e_a)_b+1 ... T_{k+e_a+e_b} */
+        double d2 = (double)e1[a] * (double)e2[b] * Tk[mi3(e2[0], e2[1], e2[2])];
+        Hm[a][b] += sg * M[k] * d2;
+        GV[b] += sg * Qa[a * nm + k] * d2;
+      }
+    }
+    Pp += sg * Qp[k] * Tk[k];
+  }
+  for (int a = 0; a < 3; ++a) {
+    double hv = Hm[a][0] * gak[0] + Hm[a][1] * gak[1] + Hm[a][2] * gak[2];
+    xb[a] += hv - mk * GV[a] - gpk * Gm[a] - mk * Gp[a];
+  }
+  *mb += -(psiV + Pp);
+}
+
+/* far-field Hessian at x (target side): sum_q Lam_q d_a d_b h^q */
+static void far_hess(const tree_t* T, const double x[3], uint64_t key, double Hf[3][3]) {
+  int pf = T->p.far_order, nq = or_nterms(pf);
+  int t = octant_of(key);
+  double c[3];
+  octant_center(T, t, c);
+  double h[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+  double pw[3][OR_DMAX + 1];
+  for (int a = 0; a < 3; ++a) {
+    pw[a][0] = 1.0;
+    for (int e = 1; e <= pf; ++e) pw[a][e] = pw[a][e - 1] * h[a];
+  }
+  const double* Lm = T->Lam + (size_t)t * nq;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Hf[a][b] = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    int e[3];
+    or_mi_get(q, &e[0], &e[1], &e[2]);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        int f[3] = {e[0], e[1], e[2]};
+        double coef = 1.0;
+        coef *= f[a];
+        if (f[a] == 0) continue;
+        f[a] -= 1;
+        coef *= f[b];
+        if (f[b] == 0) continue;
+        f[b] -= 1;
+        Hf[a][b] += Lm[q] * coef * pw[0][f[0]] * pw[1][f[1]] * pw[2][f[2]];
+      }
+  }
+}
+
+/* Adjoint of or_tree_forces: gacc (3 x n SoA) and gpot (n or NULL) in
+ * original order; writes xbar (3 x n) and mbar (n) in original order for every
+ * particle (ngsel < 0) or for the particles of the listed groups. */
+void or_tree_vjp(void* h, const double* gacc, const double* gpot, int64_t ngsel,
+                 const int64_t* gsel, double* xbar, double* mbar) {
+  tree_t* T = h;
+  int64_t n = T->n;
+  if (n == 0) return;
+  double G = T->p.G, L = T->p.box, eps2 = T->p.eps * T->p.eps;
+  /* cotangents in sorted order */
+  double* sga = malloc(sizeof(double) * 3 * (size_t)n);
+  double* sgp = calloc((size_t)n, sizeof(double));
+  for (int64_t s = 0; s < n; ++s) {
+    int64_t i = T->perm[s];
+    for (int a = 0; a < 3; ++a) sga[a * n + s] = gacc[a * n + i];
+    if (gpot) sgp[s] = gpot[i];
+  }
+  adj_mom_t AM;
+  adj_moments(T, sga, sgp, &AM);
+  if (ngsel < 0) or_tree_walk(T);
+  ensure_lists(T);
+  int64_t ng = ngsel < 0 ? T->ngroups : ngsel;
+
+  /* far field, source side: adjoint local coefficients over all targets */
+  int pf = T->p.far_order, nq = or_nterms(pf), nT = or_nterms(2 * pf);
+  double* Mbar = NULL;
+  if (T->far_ok) {
+    double* Lbar = calloc((size_t)8 * nq, sizeof(double));
+    for (int64_t s = 0; s < n; ++s) {
+      int t = octant_of(T->skey[s]);
+      double c[3];
+      octant_center(T, t, c);
+      double hh[3] = {T->sx[0][s] - c[0], T->sx[1][s] - c[1], T->sx[2][s] - c[2]};
+      double pw[3][OR_DMAX + 1];
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+        for (int e = 1; e <= pf; ++e) pw[a][e] = pw[a][e - 1] * hh[a];
+      }
+      for (int q = 0; q < nq; ++q) {
+        int e[3];
+        or_mi_get(q, &e[0], &e[1], &e[2]);
+        double v = -sgp[s] * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2]];
+        if (e[0]) v += sga[s] * e[0] * pw[0][e[0] - 1] * pw[1][e[1]] * pw[2][e[2]];
+        if (e[1]) v += sga[n + s] * e[1] * pw[0][e[0]] * pw[1][e[1] - 1] * pw[2][e[2]];
+        if (e[2]) v += sga[2 * n + s] * e[2] * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2] - 1];
+        Lbar[(size_t)t * nq + q] += G * v;
+      }
+    }
+    Mbar = calloc((size_t)8 * nq, sizeof(double));
+    for (int so = 0; so < 8; ++so)
+      for (int k = 0; k < nq; ++k) {
+        int ka, kb, kc;
+        or_mi_get(k, &ka, &kb, &kc);
+        double sg = ((ka + kb + kc) % 2) ? -1.0 : 1.0;
+        double acc = 0.0;
+        for (int t = 0; t < 8; ++t) {
+          int dx = ((t >> 2) & 1) - ((so >> 2) & 1), dy = ((t >> 1) & 1) - ((so >> 1) & 1),
+              dz = (t & 1) - (so & 1);
+          const double* Tp = T->Tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * nT;
+          for (int q = 0; q < nq; ++q) {
+            int qa, qb, qc;
+            or_mi_get(q, &qa, &qb, &qc);
+            acc += Lbar[(size_t)t * nq + q] * binom_mi(qa, qb, qc, ka, kb, kc) * sg *
+                   Tp[or_mi(qa + ka, qb + kb, qc + kc)];
+          }
+        }
+        Mbar[(size_t)so * nq + k] = acc;
+      }
+    free(Lbar);
+  }
+
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t gi = 0; gi < ng; ++gi) {
+    int64_t g = ngsel < 0 ? gi : gsel[gi];
+    walk_group(T, g);
+    const cell_t* A = &T->cells[T->groups[g]];
+    for (int64_t s = A->first; s < A->first + A->count; ++s) {
+      double xk[3] = {T->sx[0][s], T->sx[1][s], T->sx[2][s]};
+      double mk = T->sm[s], gak[3] = {sga[s], sga[n + s], sga[2 * n + s]}, gpk = sgp[s];
+      double xb[3] = {0, 0, 0}, mb = 0.0;
+      for (int64_t j = A->first; j < A->first + A->count; ++j) {
+        if (j == s) continue;
+        double r[3] = {xk[0] - T->sx[0][j], xk[1] - T->sx[1][j], xk[2] - T->sx[2][j]};
+        double gaj[3] = {sga[j], sga[n + j], sga[2 * n + j]};
+        pair_adj(r, eps2, mk, gak, gpk, T->sm[j], gaj, sgp[j], xb, &mb);
+      }
+      const list_t* lp = &T->p2p[g];
+      for (int64_t e = 0; e < lp->n; ++e) {
+        int img = lp->img[e];
+        double sh[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
+        const cell_t* B = &T->cells[lp->cell[e]];
+        for (int64_t j = B->first; j < B->first + B->count; ++j) {
+          double r[3] = {xk[0] - (T->sx[0][j] + sh[0]), xk[1] - (T->sx[1][j] + sh[1]),
+                         xk[2] - (T->sx[2][j] + sh[2])};
+          double gaj[3] = {sga[j], sga[n + j], sga[2 * n + j]};
+          pair_adj(r, eps2, mk, gak, gpk, T->sm[j], gaj, sgp[j], xb, &mb);
+        }
+      }
+      const list_t* lm = &T->m2p[g];
+      for (int64_t e = 0; e < lm->n; ++e) {
+        int img = lm->img[e];
+        double sh[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
+        const cell_t* B = &T->cells[lm->cell[e]];
+        double R[3] = {xk[0] - (B->com[0] + sh[0]), xk[1] - (B->com[1] + sh[1]),
+                       xk[2] - (B->com[2] + sh[2])};
+        m2p_adj(T, lm->cell[e], &AM, R, mk, gak, gpk, xb, &mb);
+      }
+      for (int a = 0; a < 3; ++a) xb[a] *= G;
+      mb *= G;
+      if (T->far_ok) {
+        /* target side: G Hf gacc_k - G gpot_k grad Phi_far */
+        double Hf[3][3], pf_, gf[3];
+        far_hess(T, xk, T->skey[s], Hf);
+        far_eval(T, xk, T->skey[s], &pf_, gf);
+        for (int a = 0; a < 3; ++a)
+          xb[a] += G * (Hf[a][0] * gak[0] + Hf[a][1] * gak[1] + Hf[a][2] * gak[2]) -
+                   G * gpk * gf[a];
+        /* source side: m_k sum_k Mbar_k grad s^k, sum_k Mbar_k s^k */
+        int so = octant_of(T->skey[s]);
+        double c[3];
+        octant_center(T, so, c);
+        double hh[3] = {xk[0] - c[0], xk[1] - c[1], xk[2] - c[2]};
+        double pw[3][OR_DMAX + 1];
+        for (int a = 0; a < 3; ++a) {
+          pw[a][0] = 1.0;
+          for (int e = 1; e <= pf; ++e) pw[a][e] = pw[a][e - 1] * hh[a];
+        }
+        const double* Mb = Mbar + (size_t)so * nq;
+        for (int k = 0; k < nq; ++k) {
+          int e[3];
+          or_mi_get(k, &e[0], &e[1], &e[2]);
+          mb += Mb[k] * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2]];
+          if (e[0]) xb[0] += mk * Mb[k] * e[0] * pw[0][e[0] - 1] * pw[1][e[1]] * pw[2][e[2]];
+          if (e[1]) xb[1] += mk * Mb[k] * e[1] * pw[0][e[0]] * pw[1][e[1] - 1] * pw[2][e[2]];
+          if (e[2]) xb[2] += mk * Mb[k] * e[2] * pw[0][e[0]] * pw[1][e[1]] * pw[2][e[2] - 1];
+        }
+      }
+      int64_t i = T->perm[s];
+      for (int a = 0; a < 3; ++a) xbar[a * n + i] = xb[a];
+      mbar[i] = mb;
+    }
+  }
+  free(sga); free(sgp); free(AM.Qa); free(AM.Qp); free(Mbar);
+}
