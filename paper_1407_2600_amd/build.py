@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhot.so")
 SOURCES = ["scan.hip", "sort.hip", "tree.hip", "walk.hip", "forces.hip", "far.hip", "kdk.hip",
-           "hot_abi.hip", "ewald_table.cpp"]
+           "adjoint.hip", "far_adjoint.hip", "hot_abi.hip", "ewald_table.cpp"]
 ARCH = os.environ.get("HOT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",

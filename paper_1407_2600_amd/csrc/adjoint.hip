@@ -1,0 +1,382 @@
+// Adjoint of the force evaluation (vector-Jacobian product with respect to
+// positions and masses; an extension beyond the paper).
+//
+// For the loss L = sum_i gacc_i . a_i + gpot_i phi_i the exact derivatives of
+// the softened direct sum, as gathers over each particle's own interactions
+// (r = x_k - x_j - nL, g the softened kernel, H its Hessian):
+//   xbar_k = G sum_j [ H(r) (m_j gacc_k - m_k gacc_j) - grad g(r) (m_j gpot_k + m_k gpot_j) ]
+//   mbar_k = -G sum_j [ gacc_j . grad g(r) + gpot_j g(r) ]
+// They are evaluated with the forward pass's interaction lists:
+//   - leaves and the own group pair by pair (k_p2p_adj);
+//   - accepted cells (k_m2p_adj) through two expansions about the cell's
+//     centre of mass: the mass expansion evaluated on dual numbers along
+//     gacc_k, which yields grad Phi and H gacc_k in one pass, and one order
+//     p+1 expansion of the effective charge distribution of the sources
+//     (charges gpot_j plus dipoles gacc_j, moments
+//       E_k = sum_j [gpot_j d^k - sum_a k_a gacc_j,a d^(k - e_a)]),
+//     whose potential psi and gradient give mbar_k = -G psi and the
+//     - G m_k grad psi part of xbar_k;
+//   - the periodic far field differentiated exactly (far_adjoint below).
+// At theta = 0 this is the exact derivative of the 27-image + far-field sum;
+// for theta > 0 it is the tree approximation of that derivative.
+#include "device_math.h"
+
+namespace hot {
+
+constexpr int kAdjWaves = 4;
+
+// sorted cotangents: (gacc, gpot) per particle in the arithmetic type
+template <typename T, typename T4>
+__global__ void __launch_bounds__(256) k_adj_gather(const T* __restrict__ gacc,
+                                                    const T* __restrict__ gpot, size_t n,
+                                                    const uint32_t* __restrict__ idx,
+                                                    T4* __restrict__ arec) {
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t i = idx[s];
+  T4 r;
+  r.x = gacc[i];
+  r.y = gacc[n + i];
+  r.z = gacc[2 * n + i];
+  r.w = gpot ? gpot[i] : (T)0;
+  arec[s] = r;
+}
+
+// effective charge moments, order P+1, about each cell's centre of mass
+// (leaves from their particles, internal cells by shifting the daughters'),
+// and the coefficient block (dipole part kept)
+template <int P, typename T, typename T4>
+__global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __restrict__ spos,
+                                                     const T4* __restrict__ arec, size_t n,
+                                                     uint32_t beg, uint32_t cnt, double* emom,
+                                                     T* __restrict__ ecoef) {
+  constexpr int Q = P + 1;
+  constexpr int NM = nt(Q);
+  constexpr MI<Q> mi{};
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const uint32_t c = beg + t;
+  const double4 w = C.walk[c];
+  const double com[3] = {w.x, w.y, w.z};
+  const int nc = C.nchild[c];
+  const int c0 = C.child[c];
+  double M[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) M[k] = 0.0;
+  if (nc == 0) {
+    const uint32_t f = C.first[c], e = f + C.count[c];
+    for (uint32_t s = f; s < e; ++s) {
+      const T4 r = arec[s];
+      const double q = (double)r.w;
+      const double ga[3] = {(double)r.x, (double)r.y, (double)r.z};
+      const double d[3] = {spos[s] - com[0], spos[n + s] - com[1], spos[2 * n + s] - com[2]};
+      double pw[3][Q + 1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+#pragma unroll
+        for (int e2 = 1; e2 <= Q; ++e2) pw[a][e2] = pw[a][e2 - 1] * d[a];
+      }
+#pragma unroll
+      for (int k = 0; k < NM; ++k) {
+        const int ka = mi.a[k], kb = mi.b[k], kc = mi.c[k];
+        double v = (ka + kb + kc <= P) ? q * pw[0][ka] * pw[1][kb] * pw[2][kc] : 0.0;
+        if (ka) v -= ka * ga[0] * pw[0][ka - 1] * pw[1][kb] * pw[2][kc];
+        if (kb) v -= kb * ga[1] * pw[0][ka] * pw[1][kb - 1] * pw[2][kc];
+        if (kc) v -= kc * ga[2] * pw[0][ka] * pw[1][kb] * pw[2][kc - 1];
+        M[k] += v;
+      }
+    }
+  } else {
+    for (int kc2 = 0; kc2 < nc; ++kc2) {
+      const int ch = c0 + kc2;
+      const double4 wc = C.walk[ch];
+      const double d[3] = {wc.x - com[0], wc.y - com[1], wc.z - com[2]};
+      double pw[3][Q + 1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+#pragma unroll
+        for (int e2 = 1; e2 <= Q; ++e2) pw[a][e2] = pw[a][e2 - 1] * d[a];
+      }
+      const double* Mc = emom + (size_t)ch * NM;
+      double Mch[NM];
+#pragma unroll
+      for (int k = 0; k < NM; ++k) Mch[k] = Mc[k];
+#pragma unroll
+      for (int k = 0; k < NM; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+          if (mi.a[j] > mi.a[k] || mi.b[j] > mi.b[k] || mi.c[j] > mi.c[k]) continue;
+          const int ra = mi.a[k] - mi.a[j], rb = mi.b[k] - mi.b[j], rc = mi.c[k] - mi.c[j];
+          double bin = 1.0;
+          for (int u = 0; u < mi.a[j]; ++u) bin = bin * (double)(mi.a[k] - u) / (double)(u + 1);
+          for (int u = 0; u < mi.b[j]; ++u) bin = bin * (double)(mi.b[k] - u) / (double)(u + 1);
+          for (int u = 0; u < mi.c[j]; ++u) bin = bin * (double)(mi.c[k] - u) / (double)(u + 1);
+          acc += bin * Mch[j] * pw[0][ra] * pw[1][rb] * pw[2][rc];
+        }
+        M[k] += acc;
+      }
+    }
+  }
+  double* Mo = emom + (size_t)c * NM;
+#pragma unroll
+  for (int k = 0; k < NM; ++k) Mo[k] = M[k];
+  constexpr int NCF = coef_count(Q, true);
+  constexpr int STR = coef_stride(Q, true);
+  double cf[NCF];
+  coef_from_moments<Q, true>(M, cf);
+  T* out = ecoef + (size_t)c * STR;
+#pragma unroll
+  for (int k = 0; k < NCF; ++k) out[k] = (T)cf[k];
+#pragma unroll
+  for (int k = NCF; k < STR; ++k) out[k] = (T)0;
+}
+
+// ---------------------------------------------------------------- direct
+// per pair, with r = x_k - x_j:
+//   xbar += -w/s^3 + r (3 (r.w)/s^5 + (m_j gpot_k + m_k gpot_j)/s^3),
+//           w = m_j gacc_k - m_k gacc_j
+//   mbar += (r . gacc_j)/s^3 - gpot_j/s
+template <typename T>
+__device__ __forceinline__ void pair_adj(T rx, T ry, T rz, T eps2, T mk, T gkx, T gky, T gkz,
+                                         T gpk, T mj, T gjx, T gjy, T gjz, T gpj, T part[4]) {
+  const T s2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+  const T si = rsqrt_t(s2);
+  const T si2 = si * si;
+  const T si3 = si2 * si;
+  const T si5 = si3 * si2;
+  const T wx = fma(mj, gkx, -mk * gjx), wy = fma(mj, gky, -mk * gjy), wz = fma(mj, gkz, -mk * gjz);
+  const T rw = fma(rx, wx, fma(ry, wy, rz * wz));
+  const T cp = fma(mj, gpk, mk * gpj);
+  const T al = fma((T)3 * rw, si5, si3 * cp);
+  part[0] = fma(rx, al, fma(-wx, si3, part[0]));
+  part[1] = fma(ry, al, fma(-wy, si3, part[1]));
+  part[2] = fma(rz, al, fma(-wz, si3, part[2]));
+  const T ra = fma(rx, gjx, fma(ry, gjy, rz * gjz));
+  part[3] = fma(ra, si3, fma(-gpj, si, part[3]));
+}
+
+template <typename T, typename T4>
+__global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, uint32_t ngroups,
+                                                            double L, T eps2,
+                                                            const double* __restrict__ spos,
+                                                            const T4* __restrict__ srec,
+                                                            const T4* __restrict__ arec, size_t n,
+                                                            const uint32_t* __restrict__ list,
+                                                            double4* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kAdjWaves + wid);
+  if (g >= ngroups) return;
+  const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
+  const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
+  double cA[3];
+  center_of(C.key[A], C.level[A], L, cA);
+  const uint32_t off = G.off_p2p[g], cnt = G.cnt_p2p[g];
+  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
+    const uint32_t s = first + t0 + lane;
+    const bool act = s < first + count;
+    const uint32_t ss = act ? s : first;
+    const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
+            tz = (T)(spos[2 * n + ss] - cA[2]);
+    const T mk = srec[ss].w;
+    const T4 ak = arec[ss];
+    Acc<T> acc;
+    acc.zero();
+    {
+      T part[4] = {0, 0, 0, 0};
+      for (uint32_t j = first; j < first + count; ++j) {
+        const T sx = (T)(spos[j] - cA[0]), sy = (T)(spos[n + j] - cA[1]),
+                sz = (T)(spos[2 * n + j] - cA[2]);
+        const T4 aj = arec[j];
+        // the target itself: zero masses and cotangents and a unit distance
+        // give no contribution
+        const bool self = (j == ss);
+        const T mj = self ? (T)0 : srec[j].w;
+        const T mkk = self ? (T)0 : mk;
+        T rx = tx - sx, ry = ty - sy, rz = tz - sz;
+        rx = self ? (T)1 : rx;
+        pair_adj<T>(rx, ry, rz, eps2, mkk, ak.x, ak.y, ak.z, ak.w, mj, self ? (T)0 : aj.x,
+                    self ? (T)0 : aj.y, self ? (T)0 : aj.z, self ? (T)0 : aj.w, part);
+      }
+      acc.fold(part);
+    }
+    for (uint32_t q = 0; q < cnt; ++q) {
+      const uint32_t e = list[off + q];
+      const int img = (int)(e >> 27);
+      const int B = (int)(e & kCellMask);
+      double cB[3];
+      center_of(C.key[B], C.level[B], L, cB);
+      const T shx = (T)(cB[0] + (double)(img / 9 - 1) * L - cA[0]);
+      const T shy = (T)(cB[1] + (double)((img / 3) % 3 - 1) * L - cA[1]);
+      const T shz = (T)(cB[2] + (double)(img % 3 - 1) * L - cA[2]);
+      const uint32_t bf = C.first[B], bc = C.count[B];
+      T part[4] = {0, 0, 0, 0};
+      for (uint32_t j = bf; j < bf + bc; ++j) {
+        const T4 r = srec[j];
+        const T4 aj = arec[j];
+        pair_adj<T>(tx - (shx + r.x), ty - (shy + r.y), tz - (shz + r.z), eps2, mk, ak.x, ak.y,
+                    ak.z, ak.w, r.w, aj.x, aj.y, aj.z, aj.w, part);
+      }
+      acc.fold(part);
+    }
+    if (act) out[s] = make_double4(acc.get(0), acc.get(1), acc.get(2), acc.get(3));
+  }
+}
+
+// --------------------------------------------------------------- multipole
+template <int P, typename T, typename T4>
+__global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, uint32_t ngroups,
+                                                            double L, T eps2,
+                                                            const double* __restrict__ spos,
+                                                            const T4* __restrict__ srec,
+                                                            const T4* __restrict__ arec,
+                                                            const T* __restrict__ ecoef, size_t n,
+                                                            const uint32_t* __restrict__ list,
+                                                            double4* __restrict__ out) {
+  constexpr int STR = coef_stride(P);
+  constexpr int ESTR = coef_stride(P + 1, true);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kAdjWaves + wid);
+  if (g >= ngroups) return;
+  const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
+  const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
+  double cA[3];
+  center_of(C.key[A], C.level[A], L, cA);
+  const uint32_t off = G.off_m2p[g], cnt = G.cnt_m2p[g];
+  const T* __restrict__ coef = (const T*)C.coef;
+  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
+    const uint32_t s = first + t0 + lane;
+    const bool act = s < first + count;
+    const uint32_t ss = act ? s : first;
+    const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
+            tz = (T)(spos[2 * n + ss] - cA[2]);
+    const T mk = srec[ss].w;
+    const T4 ak = arec[ss];
+    Acc<T> acc;
+    acc.zero();
+    T part[4] = {0, 0, 0, 0};
+    for (uint32_t q = 0; q < cnt; ++q) {
+      const uint32_t e = list[off + q];
+      const int img = (int)(e >> 27);
+      const int B = (int)(e & kCellMask);
+      const double4 w = C.walk[B];
+      const T Rx = tx - (T)(w.x + (double)(img / 9 - 1) * L - cA[0]);
+      const T Ry = ty - (T)(w.y + (double)((img / 3) % 3 - 1) * L - cA[1]);
+      const T Rz = tz - (T)(w.z + (double)(img % 3 - 1) * L - cA[2]);
+      // mass field and its derivative along gacc_k
+      Dual<T> fm[4];
+      m2p_eval<P, false, Dual<T>, T>(Dual<T>(Rx, ak.x), Dual<T>(Ry, ak.y), Dual<T>(Rz, ak.z),
+                                     eps2, coef + (size_t)B * STR, fm);
+      // effective charges: potential psi and its gradient
+      T fe[4];
+      m2p_eval<P + 1, true, T, T>(Rx, Ry, Rz, eps2, ecoef + (size_t)B * ESTR, fe);
+      part[0] += fm[0].d - ak.w * fm[0].v - mk * fe[0];
+      part[1] += fm[1].d - ak.w * fm[1].v - mk * fe[1];
+      part[2] += fm[2].d - ak.w * fm[2].v - mk * fe[2];
+      part[3] -= fe[3];
+      if ((q & 15) == 15) {
+        acc.fold(part);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[k] = (T)0;
+      }
+    }
+    acc.fold(part);
+    if (act) {
+      double4 o = out[s];
+      o.x += acc.get(0);
+      o.y += acc.get(1);
+      o.z += acc.get(2);
+      o.w += acc.get(3);
+      out[s] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host side
+hipError_t adj_gather_launch(bool fp32, const void* gacc, const void* gpot, size_t n,
+                             const uint32_t* idx, void* arec, hipStream_t s) {
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (fp32)
+    k_adj_gather<float, float4><<<g, 256, 0, s>>>((const float*)gacc, (const float*)gpot, n, idx,
+                                                  (float4*)arec);
+  else
+    k_adj_gather<double, double4><<<g, 256, 0, s>>>((const double*)gacc, (const double*)gpot, n,
+                                                    idx, (double4*)arec);
+  return hipGetLastError();
+}
+
+hipError_t adj_moments_level(bool fp32, int order, const Cells& C, const double* spos,
+                             const void* arec, size_t n, uint32_t beg, uint32_t cnt, double* emom,
+                             void* ecoef, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  unsigned g = (cnt + 127) / 128;
+#define HOT_ADJM(P)                                                                          \
+  case P:                                                                                    \
+    if (fp32)                                                                                \
+      k_adj_moments<P, float, float4><<<g, 128, 0, s>>>(C, spos, (const float4*)arec, n, beg, \
+                                                        cnt, emom, (float*)ecoef);           \
+    else                                                                                     \
+      k_adj_moments<P, double, double4><<<g, 128, 0, s>>>(C, spos, (const double4*)arec, n,  \
+                                                          beg, cnt, emom, (double*)ecoef);   \
+    break;
+  switch (order) {
+    HOT_ADJM(0) HOT_ADJM(1) HOT_ADJM(2) HOT_ADJM(3) HOT_ADJM(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef HOT_ADJM
+  return hipGetLastError();
+}
+
+hipError_t p2p_adj_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                          double eps, const double* spos, const void* srec, const void* arec,
+                          size_t n, const uint32_t* list, double4* out, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  unsigned blocks = (ngroups + kAdjWaves - 1) / kAdjWaves;
+  if (fp32)
+    k_p2p_adj<float, float4><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, (float)(eps * eps), spos, (const float4*)srec, (const float4*)arec, n,
+        list, out);
+  else
+    k_p2p_adj<double, double4><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec, n, list,
+        out);
+  return hipGetLastError();
+}
+
+template <int P>
+static void m2p_adj_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                      double eps, const double* spos, const void* srec, const void* arec,
+                      const void* ecoef, size_t n, const uint32_t* list, double4* out,
+                      hipStream_t s) {
+  unsigned blocks = (ngroups + kAdjWaves - 1) / kAdjWaves;
+  if (fp32)
+    k_m2p_adj<P, float, float4><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, (float)(eps * eps), spos, (const float4*)srec, (const float4*)arec,
+        (const float*)ecoef, n, list, out);
+  else
+    k_m2p_adj<P, double, double4><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec,
+        (const double*)ecoef, n, list, out);
+}
+
+hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
+                          double L, double eps, const double* spos, const void* srec,
+                          const void* arec, const void* ecoef, size_t n, const uint32_t* list,
+                          double4* out, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  switch (order) {
+    case 0: m2p_adj_p<0>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
+    case 1: m2p_adj_p<1>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
+    case 2: m2p_adj_p<2>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
+    case 3: m2p_adj_p<3>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
+    case 4: m2p_adj_p<4>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hot

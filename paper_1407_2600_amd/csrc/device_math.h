@@ -1,0 +1,269 @@
+// Device helpers shared by the force and adjoint kernels: cell geometry,
+// reciprocal square root, compensated accumulation, dual numbers and the
+// multipole evaluation.
+#pragma once
+
+#include <type_traits>
+
+#include "hot_internal.h"
+
+namespace hot {
+
+using ::fma;  // the float/double overloads, next to the dual-number ones below
+
+__device__ __forceinline__ void center_of(uint64_t key, int level, double L, double c[3]) {
+  uint32_t ix = 0, iy = 0, iz = 0;
+  for (int b = 0; b < level; ++b) {
+    ix |= (uint32_t)((key >> (3 * b + 2)) & 1ull) << b;
+    iy |= (uint32_t)((key >> (3 * b + 1)) & 1ull) << b;
+    iz |= (uint32_t)((key >> (3 * b)) & 1ull) << b;
+  }
+  double s = ldexp(L, -level);
+  c[0] = ((double)ix + 0.5) * s;
+  c[1] = ((double)iy + 0.5) * s;
+  c[2] = ((double)iz + 0.5) * s;
+}
+
+// ---------------------------------------------------------------- octants
+// the far field is expanded about the centres of the 8 level-1 cells
+__device__ __forceinline__ void octant_center(int o, double L, double c[3]) {
+  const double h = 0.5 * L;
+  c[0] = ((double)((o >> 2) & 1) + 0.5) * h;
+  c[1] = ((double)((o >> 1) & 1) + 0.5) * h;
+  c[2] = ((double)(o & 1) + 0.5) * h;
+}
+
+// first sorted index whose key's top octal digit is >= o (keys ascend, and
+// bit 63 is the placeholder, so the top digit is non-decreasing)
+__device__ __forceinline__ size_t digit_lb(const uint64_t* __restrict__ skey, size_t n,
+                                           uint64_t o) {
+  size_t lo = 0, hi = n;
+  while (lo < hi) {
+    const size_t mid = lo + ((hi - lo) >> 1);
+    if (((skey[mid] >> 60) & 7ull) < o)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// [beg, end) of the sorted particles in octant o
+__device__ __forceinline__ void octant_range(const uint64_t* __restrict__ skey, size_t n, int o,
+                                             size_t* beg, size_t* end) {
+  *beg = digit_lb(skey, n, (uint64_t)o);
+  *end = (o == 7) ? n : digit_lb(skey, n, (uint64_t)(o + 1));
+}
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+// accumulator: plain in FP64, (hi, lo) TwoSum pairs (Knuth) in FP32
+template <typename T, int K = 4>
+struct Acc {
+  T hi[K];
+  T lo[K];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < K; ++k) hi[k] = lo[k] = (T)0;
+  }
+  __device__ __forceinline__ void fold1(int k, T x) {
+    if constexpr (std::is_same<T, float>::value) {
+      T s = hi[k] + x;
+      T bb = s - hi[k];
+      T err = (hi[k] - (s - bb)) + (x - bb);
+      hi[k] = s;
+      lo[k] += err;
+    } else {
+      hi[k] += x;
+    }
+  }
+  __device__ __forceinline__ void fold(const T x[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) fold1(k, x[k]);
+  }
+  __device__ __forceinline__ double get(int k) const { return (double)hi[k] + (double)lo[k]; }
+};
+
+// ------------------------------------------------------------- dual numbers
+// value + first-order directional derivative: evaluating the multipole field
+// on duals gives its Jacobian applied to a direction in one pass
+template <typename T>
+struct Dual {
+  T v, d;
+  __device__ __forceinline__ Dual() : v(0), d(0) {}
+  __device__ __forceinline__ Dual(T x) : v(x), d(0) {}
+  __device__ __forceinline__ Dual(T x, T y) : v(x), d(y) {}
+  __device__ __forceinline__ Dual& operator+=(const Dual& o) {
+    v += o.v;
+    d += o.d;
+    return *this;
+  }
+  __device__ __forceinline__ Dual& operator+=(T o) {
+    v += o;
+    return *this;
+  }
+};
+template <typename T>
+__device__ __forceinline__ Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> operator*(Dual<T> a, Dual<T> b) {
+  return {a.v * b.v, fma(a.v, b.d, a.d * b.v)};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> operator*(T a, Dual<T> b) { return {a * b.v, a * b.d}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
+template <typename T>
+__device__ __forceinline__ Dual<T> fma(Dual<T> a, Dual<T> b, Dual<T> c) {
+  return {fma(a.v, b.v, c.v), fma(a.v, b.d, fma(a.d, b.v, c.d))};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> fma(T a, Dual<T> b, Dual<T> c) {
+  return {fma(a, b.v, c.v), fma(a, b.d, c.d)};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> fma(Dual<T> a, T b, Dual<T> c) {
+  return {fma(a.v, b, c.v), fma(a.d, b, c.d)};
+}
+template <typename T>
+__device__ __forceinline__ Dual<T> rsqrt_t(Dual<T> x) {
+  const T r = rsqrt_t(x.v);
+  return {r, (T)(-0.5) * r * r * r * x.d};
+}
+
+// ---------------------------------------------------------------- multipole
+// Phi = rinv sum_m rho^m P_m(R),
+// grad Phi = rinv sum_m rho^m grad P_m - rinv rho R sum_m (2m+1) rho^m P_m,
+// with the per-cell coefficient layout described in hot_internal.h.  V is the
+// value type (T or Dual<T>), C the coefficient type.  out = (grad Phi, Phi).
+template <int P, bool DIP, typename V, typename C>
+__device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __restrict__ cf,
+                                         V out[4]) {
+  const V u = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, V(eps2))));
+  const V rinv = rsqrt_t(u);
+  const V rho = rinv * rinv;
+  constexpr int DM = P > 0 ? P - 1 : 0;
+  constexpr MI<DM> mi{};
+  V mono[nt(DM)];
+  mono[0] = V((C)1);
+#pragma unroll
+  for (int k = 1; k < nt(DM); ++k) {
+    const int a = mi.a[k], b = mi.b[k], c = mi.c[k];
+    if (a > 0)
+      mono[k] = (a + b + c == 1) ? Rx : mono[mi_index(a - 1, b, c)] * Rx;
+    else if (b > 0)
+      mono[k] = (b + c == 1) ? Ry : mono[mi_index(a, b - 1, c)] * Ry;
+    else
+      mono[k] = (c == 1) ? Rz : mono[mi_index(a, b, c - 1)] * Rz;
+  }
+  V Pm[P + 1], Vx[P + 1], Vy[P + 1], Vz[P + 1];
+#pragma unroll
+  for (int m = 0; m <= P; ++m) Pm[m] = Vx[m] = Vy[m] = Vz[m] = V((C)0);
+  int o = 0;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+#pragma unroll
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      const int d = m - j;
+      if (!part_stored(m, d, DIP)) continue;
+      if (d == 0) {
+        Pm[m] += cf[o];
+        o += 1;
+      } else {
+        const int nk = nte(d - 1);
+        const int base = nt(d - 2);
+        V vx = V((C)0), vy = V((C)0), vz = V((C)0);
+#pragma unroll
+        for (int k = 0; k < nk; ++k) {
+          vx = fma(cf[o + k], mono[base + k], vx);
+          vy = fma(cf[o + nk + k], mono[base + k], vy);
+          vz = fma(cf[o + 2 * nk + k], mono[base + k], vz);
+        }
+        o += 3 * nk;
+        Vx[m] += vx;
+        Vy[m] += vy;
+        Vz[m] += vz;
+        const V dot = fma(Rx, vx, fma(Ry, vy, Rz * vz));
+        Pm[m] = fma(dot, (C)(1.0 / d), Pm[m]);
+      }
+    }
+  }
+  V Pv = Pm[P], Q = (C)(2 * P + 1) * Pm[P], Gx = Vx[P], Gy = Vy[P], Gz = Vz[P];
+#pragma unroll
+  for (int m = P - 1; m >= 0; --m) {
+    Pv = fma(Pv, rho, Pm[m]);
+    Q = fma(Q, rho, (C)(2 * m + 1) * Pm[m]);
+    Gx = fma(Gx, rho, Vx[m]);
+    Gy = fma(Gy, rho, Vy[m]);
+    Gz = fma(Gz, rho, Vz[m]);
+  }
+  const V rq = rho * Q;
+  out[0] = rinv * fma(-rq, Rx, Gx);
+  out[1] = rinv * fma(-rq, Ry, Gy);
+  out[2] = rinv * fma(-rq, Rz, Gz);
+  out[3] = rinv * Pv;
+}
+
+// Coefficient block of a cell from its raw Cartesian moments M_k about the
+// expansion centre (|k| <= P): with W^(j)_k = sum_{|i|=j} (j!/i!) M_{k+2i},
+//   C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m - j,
+// so that P_m(R) = sum_k C_{m,k} R^k; parts of degree d >= 1 are stored as
+// gradient coefficients (k'_a + 1) C_{m, k'+e_a}, |k'| = d - 1.
+template <int P, bool DIP = false>
+__device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
+  // C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m-j
+  // stored as gradient coefficients (k'_a+1) C_{m,k'+e_a} for d >= 1.
+  constexpr MI<P> mi{};
+  int o = 0;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    double dfact = 1.0;  // (2m-1)!!
+    for (int q = 1; q <= 2 * m - 1; q += 2) dfact *= (double)q;
+#pragma unroll
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      const int d = m - j;
+      if (!part_stored(m, d, DIP)) continue;
+      double pre = dfact * ((j & 1) ? -1.0 : 1.0);
+      for (int q = 0; q < j; ++q) pre *= 0.5;
+      auto Cmk = [&](int ka, int kb, int kc) {
+        // sum over |i| = j of M_{k+2i}/i!, divided by k!
+        double s = 0.0;
+        for (int ia = j; ia >= 0; --ia)
+          for (int ib = j - ia; ib >= 0; --ib) {
+            int ic = j - ia - ib;
+            double fi = 1.0;
+            for (int q = 2; q <= ia; ++q) fi *= q;
+            for (int q = 2; q <= ib; ++q) fi *= q;
+            for (int q = 2; q <= ic; ++q) fi *= q;
+            s += M[mi_index(ka + 2 * ia, kb + 2 * ib, kc + 2 * ic)] / fi;
+          }
+        double fk = 1.0;
+        for (int q = 2; q <= ka; ++q) fk *= q;
+        for (int q = 2; q <= kb; ++q) fk *= q;
+        for (int q = 2; q <= kc; ++q) fk *= q;
+        return pre * s / fk;
+      };
+      if (d == 0) {
+        out[o++] = Cmk(0, 0, 0);
+      } else {
+        // gradient coefficients: component a, monomial k' of degree d-1
+        for (int a = 0; a < 3; ++a)
+          for (int x = d - 1; x >= 0; --x)
+            for (int y = d - 1 - x; y >= 0; --y) {
+              int z = d - 1 - x - y;
+              int ka = x + (a == 0), kb = y + (a == 1), kc = z + (a == 2);
+              int ka1 = (a == 0 ? x : a == 1 ? y : z) + 1;
+              out[o++] = ka1 * Cmk(ka, kb, kc);
+            }
+      }
+    }
+  }
+}
+
+
+}  // namespace hot

@@ -19,41 +19,12 @@
 // powers staged in LDS); the local coefficients one block per target octant;
 // the evaluation one thread per particle in FP64, fused with the scaling
 // (-G, G) and the scatter back to the caller's particle order.
-#include "hot_internal.h"
+#include "device_math.h"
 
 namespace hot {
 
 constexpr int kFarThreads = 256;
 constexpr int kFarStage = 64;
-
-__device__ __forceinline__ void octant_center(int o, double L, double c[3]) {
-  const double h = 0.5 * L;
-  c[0] = ((double)((o >> 2) & 1) + 0.5) * h;
-  c[1] = ((double)((o >> 1) & 1) + 0.5) * h;
-  c[2] = ((double)(o & 1) + 0.5) * h;
-}
-
-// first sorted index whose key's top octal digit is >= o (keys ascend, and
-// bit 63 is the placeholder, so the top digit is non-decreasing)
-__device__ __forceinline__ size_t digit_lb(const uint64_t* __restrict__ skey, size_t n,
-                                           uint64_t o) {
-  size_t lo = 0, hi = n;
-  while (lo < hi) {
-    const size_t mid = lo + ((hi - lo) >> 1);
-    if (((skey[mid] >> 60) & 7ull) < o)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// [beg, end) of the sorted particles in octant o
-__device__ __forceinline__ void octant_range(const uint64_t* __restrict__ skey, size_t n, int o,
-                                             size_t* beg, size_t* end) {
-  *beg = digit_lb(skey, n, (uint64_t)o);
-  *end = (o == 7) ? n : digit_lb(skey, n, (uint64_t)(o + 1));
-}
 
 template <int PF>
 __global__ void __launch_bounds__(kFarThreads) k_far_moments(const double* __restrict__ spos,
@@ -232,6 +203,35 @@ static hipError_t far_run(const double* spos, const double* smass, const uint64_
     k_far_apply<PF, double><<<g, 256, 0, s>>>(spos, skey, near, n, idx, box, G, lam, periodic,
                                                (double*)acc, (double*)pot);
   return hipGetLastError();
+}
+
+template <int PF>
+static hipError_t far_prepare_run(const double* spos, const double* smass, const uint64_t* skey,
+                                  size_t n, double box, const double* tpsi, double* part,
+                                  int nblk_max, double* mom, double* lam, hipStream_t s) {
+  int nblk = (int)((n / 8 + 2047) / 2048);
+  if (nblk > nblk_max) nblk = nblk_max;
+  if (nblk < 1) nblk = 1;
+  k_far_moments<PF><<<dim3(nblk, 8), kFarThreads, 0, s>>>(spos, smass, skey, n, box, nblk, part);
+  k_far_lambda<PF><<<8, 512, 0, s>>>(part, nblk, tpsi, mom, lam);
+  return hipGetLastError();
+}
+
+// octant moments and local coefficients only (the adjoint needs Lam)
+hipError_t far_prepare_launch(int far_order, const double* spos, const double* smass,
+                              const uint64_t* skey, size_t n, double box, const double* tpsi,
+                              double* part, int nblk_max, double* mom, double* lam,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+#define HOT_FARP(PF) \
+  case PF:           \
+    return far_prepare_run<PF>(spos, smass, skey, n, box, tpsi, part, nblk_max, mom, lam, s);
+  switch (far_order) {
+    HOT_FARP(0) HOT_FARP(1) HOT_FARP(2) HOT_FARP(3) HOT_FARP(4) HOT_FARP(5) HOT_FARP(6)
+    HOT_FARP(7) HOT_FARP(8) HOT_FARP(9) HOT_FARP(10) HOT_FARP(11) HOT_FARP(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef HOT_FARP
 }
 
 hipError_t far_launch(int far_order, const double* spos, const double* smass,

@@ -1,0 +1,255 @@
+// Adjoint of the periodic far field (exact derivative of the octant local
+// expansions used by the forward pass).
+//
+// Forward: Phi_far(x) = sum_q Lam^t_q h^q, h = x - c_t, t the octant of x,
+//   Lam^t_q = sum_s sum_k C(q+k,q) (-1)^|k| Tpsi^{c_t-c_s}_{q+k} M^s_k,
+//   M^s_k = sum_{j in s} m_j (x_j - c_s)^k.
+// For L = sum_i gacc_i . G grad Phi_far(x_i) - gpot_i G Phi_far(x_i):
+//   target side:  xbar_i += G (Hess Phi_far) gacc_i - G gpot_i grad Phi_far
+//                 (the Hessian along gacc_i from a dual-number evaluation);
+//   source side:  Lbar^t_q = G sum_{i in t} (gacc_i . grad h_i^q - gpot_i h_i^q),
+//                 Mbar^s_k = sum_t sum_q Lbar^t_q C(q+k,q) (-1)^|k| Tpsi^{c_t-c_s}_{q+k},
+//                 xbar_j += m_j sum_k Mbar^s_k grad s_j^k,  mbar_j += sum_k Mbar^s_k s_j^k.
+// The final kernel also adds the near-field adjoint (scaled by G) and writes
+// xbar (FP64) and mbar in the caller's particle order.
+#include "device_math.h"
+
+namespace hot {
+
+constexpr int kFarAThreads = 256;
+constexpr int kFarAStage = 64;
+
+template <int PF, typename T4>
+__global__ void __launch_bounds__(kFarAThreads) k_far_adj_local(const double* __restrict__ spos,
+                                                                const T4* __restrict__ arec,
+                                                                const uint64_t* __restrict__ skey,
+                                                                size_t n, double L, int nblk,
+                                                                double* __restrict__ part) {
+  constexpr int NQ = nt(PF);
+  constexpr MI<PF> mi{};
+  __shared__ double pw[kFarAStage][3][PF + 1];
+  __shared__ double ga[kFarAStage][4];
+  const int o = blockIdx.y;
+  size_t obeg, oend;
+  octant_range(skey, n, o, &obeg, &oend);
+  const size_t len = oend - obeg;
+  const size_t chunk = (len + nblk - 1) / nblk;
+  const size_t beg = obeg + (size_t)blockIdx.x * chunk;
+  const size_t end = beg + chunk < oend ? beg + chunk : oend;
+  double c[3];
+  octant_center(o, L, c);
+  constexpr int PER = (NQ + kFarAThreads - 1) / kFarAThreads;
+  double acc[PER];
+  int ka[PER], kb[PER], kc[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    acc[r] = 0.0;
+    const int k = threadIdx.x + r * kFarAThreads;
+    ka[r] = k < NQ ? mi.a[k] : 0;
+    kb[r] = k < NQ ? mi.b[k] : 0;
+    kc[r] = k < NQ ? mi.c[k] : 0;
+  }
+  for (size_t b0 = beg; b0 < end; b0 += kFarAStage) {
+    if (threadIdx.x < kFarAStage) {
+      const size_t s = b0 + threadIdx.x;
+      const bool ok = s < end;
+      const double d[3] = {ok ? spos[s] - c[0] : 0.0, ok ? spos[n + s] - c[1] : 0.0,
+                           ok ? spos[2 * n + s] - c[2] : 0.0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double p = 1.0;
+        pw[threadIdx.x][a][0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= PF; ++e) {
+          p *= d[a];
+          pw[threadIdx.x][a][e] = p;
+        }
+      }
+      const T4 r = ok ? arec[s] : T4{};
+      ga[threadIdx.x][0] = ok ? (double)r.x : 0.0;
+      ga[threadIdx.x][1] = ok ? (double)r.y : 0.0;
+      ga[threadIdx.x][2] = ok ? (double)r.z : 0.0;
+      ga[threadIdx.x][3] = ok ? (double)r.w : 0.0;
+    }
+    __syncthreads();
+    for (int p = 0; p < kFarAStage; ++p) {
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int a = ka[r], b = kb[r], cc = kc[r];
+        const double* px = pw[p][0];
+        const double* py = pw[p][1];
+        const double* pz = pw[p][2];
+        double v = -ga[p][3] * px[a] * py[b] * pz[cc];
+        if (a) v += ga[p][0] * (double)a * px[a - 1] * py[b] * pz[cc];
+        if (b) v += ga[p][1] * (double)b * px[a] * py[b - 1] * pz[cc];
+        if (cc) v += ga[p][2] * (double)cc * px[a] * py[b] * pz[cc - 1];
+        acc[r] += v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int k = threadIdx.x + r * kFarAThreads;
+    if (k < NQ) part[((size_t)o * nblk + blockIdx.x) * NQ + k] = acc[r];
+  }
+}
+
+// one block per source octant s
+template <int PF>
+__global__ void __launch_bounds__(512) k_far_adj_moments(const double* __restrict__ part, int nblk,
+                                                         const double* __restrict__ tpsi, double G,
+                                                         double* __restrict__ mbar) {
+  constexpr int NQ = nt(PF);
+  constexpr int NT2 = nt(2 * PF);
+  constexpr MI<PF> mi{};
+  __shared__ double Lb[8][NQ];
+  const int so = blockIdx.x;
+  for (int i = threadIdx.x; i < 8 * NQ; i += blockDim.x) {
+    const int t = i / NQ, q = i % NQ;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[((size_t)t * nblk + b) * NQ + q];
+    Lb[t][q] = G * acc;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NQ; k += blockDim.x) {
+    const int ka = mi.a[k], kb = mi.b[k], kc = mi.c[k];
+    const double sg = ((ka + kb + kc) & 1) ? -1.0 : 1.0;
+    double acc = 0.0;
+    for (int t = 0; t < 8; ++t) {
+      const int dx = ((t >> 2) & 1) - ((so >> 2) & 1), dy = ((t >> 1) & 1) - ((so >> 1) & 1),
+                dz = (t & 1) - (so & 1);
+      const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
+      for (int q = 0; q < NQ; ++q) {
+        const int qa = mi.a[q], qb = mi.b[q], qc = mi.c[q];
+        double bin = 1.0;
+        for (int u = 1; u <= ka; ++u) bin = bin * (double)(qa + u) / (double)u;
+        for (int u = 1; u <= kb; ++u) bin = bin * (double)(qb + u) / (double)u;
+        for (int u = 1; u <= kc; ++u) bin = bin * (double)(qc + u) / (double)u;
+        acc += Lb[t][q] * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)];
+      }
+    }
+    mbar[(size_t)so * NQ + k] = sg * acc;
+  }
+}
+
+// value and gradient of sum_q c_q h^q (V = double or Dual<double>)
+template <int PF, typename V>
+__device__ __forceinline__ void local_eval(const double* __restrict__ cq, V hx, V hy, V hz,
+                                           V out[4]) {
+  constexpr MI<PF> mi{};
+  V px[PF + 1], py[PF + 1], pz[PF + 1];
+  px[0] = py[0] = pz[0] = V(1.0);
+#pragma unroll
+  for (int e = 1; e <= PF; ++e) {
+    px[e] = px[e - 1] * hx;
+    py[e] = py[e - 1] * hy;
+    pz[e] = pz[e - 1] * hz;
+  }
+  V P = V(0.0), Gx = V(0.0), Gy = V(0.0), Gz = V(0.0);
+#pragma unroll
+  for (int q = 0; q < nt(PF); ++q) {
+    const int a = mi.a[q], b = mi.b[q], c = mi.c[q];
+    const double Lq = cq[q];
+    const V yz = py[b] * pz[c];
+    P = fma(Lq, px[a] * yz, P);
+    if (a) Gx = fma(Lq * (double)a, px[a - 1] * yz, Gx);
+    if (b) Gy = fma(Lq * (double)b, px[a] * (py[b - 1] * pz[c]), Gy);
+    if (c) Gz = fma(Lq * (double)c, px[a] * (py[b] * pz[c - 1]), Gz);
+  }
+  out[0] = Gx;
+  out[1] = Gy;
+  out[2] = Gz;
+  out[3] = P;
+}
+
+template <int PF, typename T, typename T4>
+__global__ void __launch_bounds__(256) k_far_adj_apply(
+    const double* __restrict__ spos, const double* __restrict__ smass,
+    const uint64_t* __restrict__ skey, const T4* __restrict__ arec,
+    const double4* __restrict__ near, size_t n, const uint32_t* __restrict__ idx, double L,
+    double G, const double* __restrict__ lam, const double* __restrict__ mbar, int periodic,
+    double* __restrict__ xbar, T* __restrict__ mbar_out) {
+  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double4 v = near[s];
+  double xb[3] = {G * v.x, G * v.y, G * v.z};
+  double mb = G * v.w;
+  if (periodic) {
+    constexpr int NQ = nt(PF);
+    const int o = (int)((skey[s] >> 60) & 7ull);
+    double c[3];
+    octant_center(o, L, c);
+    const double h[3] = {spos[s] - c[0], spos[n + s] - c[1], spos[2 * n + s] - c[2]};
+    const T4 r = arec[s];
+    const double ga[3] = {(double)r.x, (double)r.y, (double)r.z};
+    const double gp = (double)r.w;
+    // target side: gradient and its derivative along gacc
+    Dual<double> f[4];
+    local_eval<PF, Dual<double>>(lam + (size_t)o * NQ, Dual<double>(h[0], ga[0]),
+                                 Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
+    for (int a = 0; a < 3; ++a) xb[a] += G * f[a].d - G * gp * f[a].v;
+    // source side
+    double sm[4];
+    local_eval<PF, double>(mbar + (size_t)o * NQ, h[0], h[1], h[2], sm);
+    const double m = smass[s];
+    for (int a = 0; a < 3; ++a) xb[a] += m * sm[a];
+    mb += sm[3];
+  }
+  const uint32_t i = idx[s];
+  xbar[i] = xb[0];
+  xbar[n + i] = xb[1];
+  xbar[2 * n + i] = xb[2];
+  mbar_out[i] = (T)mb;
+}
+
+template <int PF>
+static hipError_t far_adj_run(const double* spos, const double* smass, const uint64_t* skey,
+                              const void* arec, const double4* near, size_t n,
+                              const uint32_t* idx, double box, double G, const double* tpsi,
+                              double* part, int nblk_max, const double* lam, double* mbar,
+                              int periodic, bool fp32, double* xbar, void* mbar_out,
+                              hipStream_t s) {
+  if (periodic) {
+    int nblk = (int)((n / 8 + 2047) / 2048);
+    if (nblk > nblk_max) nblk = nblk_max;
+    if (nblk < 1) nblk = 1;
+    if (fp32)
+      k_far_adj_local<PF, float4><<<dim3(nblk, 8), kFarAThreads, 0, s>>>(
+          spos, (const float4*)arec, skey, n, box, nblk, part);
+    else
+      k_far_adj_local<PF, double4><<<dim3(nblk, 8), kFarAThreads, 0, s>>>(
+          spos, (const double4*)arec, skey, n, box, nblk, part);
+    k_far_adj_moments<PF><<<8, 512, 0, s>>>(part, nblk, tpsi, G, mbar);
+  }
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (fp32)
+    k_far_adj_apply<PF, float, float4><<<g, 256, 0, s>>>(spos, smass, skey, (const float4*)arec,
+                                                         near, n, idx, box, G, lam, mbar,
+                                                         periodic, xbar, (float*)mbar_out);
+  else
+    k_far_adj_apply<PF, double, double4><<<g, 256, 0, s>>>(
+        spos, smass, skey, (const double4*)arec, near, n, idx, box, G, lam, mbar, periodic, xbar,
+        (double*)mbar_out);
+  return hipGetLastError();
+}
+
+hipError_t far_adj_launch(int far_order, const double* spos, const double* smass,
+                          const uint64_t* skey, const void* arec, const double4* near, size_t n,
+                          const uint32_t* idx, double box, double G, const double* tpsi,
+                          double* part, int nblk_max, const double* lam, double* mbar,
+                          int periodic, bool fp32, double* xbar, void* mbar_out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+#define HOT_FARA(PF)                                                                         \
+  case PF:                                                                                   \
+    return far_adj_run<PF>(spos, smass, skey, arec, near, n, idx, box, G, tpsi, part,        \
+                           nblk_max, lam, mbar, periodic, fp32, xbar, mbar_out, s);
+  switch (far_order) {
+    HOT_FARA(0) HOT_FARA(1) HOT_FARA(2) HOT_FARA(3) HOT_FARA(4) HOT_FARA(5) HOT_FARA(6)
+    HOT_FARA(7) HOT_FARA(8) HOT_FARA(9) HOT_FARA(10) HOT_FARA(11) HOT_FARA(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef HOT_FARA
+}
+
+}  // namespace hot

@@ -13,75 +13,11 @@
 // before rounding to the arithmetic type T.  In FP32, per-leaf (direct) and
 // per-16-cell (multipole) partial sums are folded into a (hi, lo) pair with
 // Knuth's TwoSum, so the long sums keep about twice FP32 precision.
-#include <type_traits>
-
-#include "hot_internal.h"
+#include "device_math.h"
 
 namespace hot {
 
 constexpr int kForceWaves = 4;
-
-__device__ __forceinline__ void center_of(uint64_t key, int level, double L, double c[3]) {
-  uint32_t ix = 0, iy = 0, iz = 0;
-  for (int b = 0; b < level; ++b) {
-    ix |= (uint32_t)((key >> (3 * b + 2)) & 1ull) << b;
-    iy |= (uint32_t)((key >> (3 * b + 1)) & 1ull) << b;
-    iz |= (uint32_t)((key >> (3 * b)) & 1ull) << b;
-  }
-  double s = ldexp(L, -level);
-  c[0] = ((double)ix + 0.5) * s;
-  c[1] = ((double)iy + 0.5) * s;
-  c[2] = ((double)iz + 0.5) * s;
-}
-
-template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x);
-template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) {
-  return __builtin_amdgcn_rsqf(x);
-}
-template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) {
-  return 1.0 / sqrt(x);
-}
-
-// accumulator: plain in FP64, (hi, lo) TwoSum pairs in FP32
-template <typename T>
-struct Acc {
-  T hi[4];
-  T lo[4];
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) hi[k] = lo[k] = (T)0;
-  }
-  __device__ __forceinline__ void fold(const T x[4]) {
-    if constexpr (std::is_same<T, float>::value) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        T s = hi[k] + x[k];
-        T bb = s - hi[k];
-        T err = (hi[k] - (s - bb)) + (x[k] - bb);
-        hi[k] = s;
-        lo[k] += err;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) hi[k] += x[k];
-    }
-  }
-  __device__ __forceinline__ void fold1(int k, T x) {
-    if constexpr (std::is_same<T, float>::value) {
-      T s = hi[k] + x;
-      T bb = s - hi[k];
-      T err = (hi[k] - (s - bb)) + (x - bb);
-      hi[k] = s;
-      lo[k] += err;
-    } else {
-      hi[k] += x;
-    }
-  }
-  __device__ __forceinline__ double get(int k) const { return (double)hi[k] + (double)lo[k]; }
-};
 
 // ------------------------------------------------------------------- direct
 template <typename T, typename T4>
@@ -119,7 +55,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
         T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
         const bool self = (j == ss);
         r2 = self ? (T)1 : r2;
-        const T ri = rsqrt_t<T>(r2);
+        const T ri = rsqrt_t(r2);
         const T mr = self ? (T)0 : m * ri;
         const T mr3 = mr * (ri * ri);
         part[0] = fma(dx, mr3, part[0]);
@@ -144,7 +80,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
         const T4 r = srec[j];
         const T dx = (shx + r.x) - tx, dy = (shy + r.y) - ty, dz = (shz + r.z) - tz;
         const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-        const T ri = rsqrt_t<T>(r2);
+        const T ri = rsqrt_t(r2);
         const T mr = r.w * ri;
         const T mr3 = mr * (ri * ri);
         part[0] = fma(dx, mr3, part[0]);
@@ -156,77 +92,6 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
     }
     if (act) out[s] = make_double4(acc.get(0), acc.get(1), acc.get(2), acc.get(3));
   }
-}
-
-// ---------------------------------------------------------------- multipole
-// Phi = rinv sum_m rho^m P_m(R), grad Phi = rinv sum_m rho^m grad P_m
-//       - rinv rho R sum_m (2m+1) rho^m P_m   (coefficient layout: tree.hip)
-template <int P, typename T>
-__device__ __forceinline__ void m2p_eval(T Rx, T Ry, T Rz, T eps2, const T* __restrict__ cf,
-                                         T out[4]) {
-  const T u = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, eps2)));
-  const T rinv = rsqrt_t<T>(u);
-  const T rho = rinv * rinv;
-  constexpr int DM = P > 0 ? P - 1 : 0;
-  constexpr MI<DM> mi{};
-  T mono[nt(DM)];
-  mono[0] = (T)1;
-#pragma unroll
-  for (int k = 1; k < nt(DM); ++k) {
-    const int a = mi.a[k], b = mi.b[k], c = mi.c[k];
-    if (a > 0)
-      mono[k] = (a + b + c == 1) ? Rx : mono[mi_index(a - 1, b, c)] * Rx;
-    else if (b > 0)
-      mono[k] = (b + c == 1) ? Ry : mono[mi_index(a, b - 1, c)] * Ry;
-    else
-      mono[k] = (c == 1) ? Rz : mono[mi_index(a, b, c - 1)] * Rz;
-  }
-  T Pm[P + 1], Vx[P + 1], Vy[P + 1], Vz[P + 1];
-#pragma unroll
-  for (int m = 0; m <= P; ++m) Pm[m] = Vx[m] = Vy[m] = Vz[m] = (T)0;
-  int o = 0;
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-#pragma unroll
-    for (int j = 0; j <= part_jmax(P, m); ++j) {
-      const int d = m - j;
-      if (!part_stored(m, d)) continue;
-      if (d == 0) {
-        Pm[m] += cf[o];
-        o += 1;
-      } else {
-        const int nk = nte(d - 1);
-        const int base = nt(d - 2);
-        T vx = (T)0, vy = (T)0, vz = (T)0;
-#pragma unroll
-        for (int k = 0; k < nk; ++k) {
-          vx = fma(cf[o + k], mono[base + k], vx);
-          vy = fma(cf[o + nk + k], mono[base + k], vy);
-          vz = fma(cf[o + 2 * nk + k], mono[base + k], vz);
-        }
-        o += 3 * nk;
-        Vx[m] += vx;
-        Vy[m] += vy;
-        Vz[m] += vz;
-        const T dot = fma(Rx, vx, fma(Ry, vy, Rz * vz));
-        Pm[m] = fma(dot, (T)(1.0 / d), Pm[m]);
-      }
-    }
-  }
-  T Pv = Pm[P], Q = (T)(2 * P + 1) * Pm[P], Gx = Vx[P], Gy = Vy[P], Gz = Vz[P];
-#pragma unroll
-  for (int m = P - 1; m >= 0; --m) {
-    Pv = fma(Pv, rho, Pm[m]);
-    Q = fma(Q, rho, (T)(2 * m + 1) * Pm[m]);
-    Gx = fma(Gx, rho, Vx[m]);
-    Gy = fma(Gy, rho, Vy[m]);
-    Gz = fma(Gz, rho, Vz[m]);
-  }
-  const T rq = rho * Q;
-  out[0] = rinv * fma(-rq, Rx, Gx);
-  out[1] = rinv * fma(-rq, Ry, Gy);
-  out[2] = rinv * fma(-rq, Rz, Gz);
-  out[3] = rinv * Pv;
 }
 
 template <int P, typename T>
@@ -265,7 +130,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
       const T cy = (T)(w.y + (double)((img / 3) % 3 - 1) * L - cA[1]);
       const T cz = (T)(w.z + (double)(img % 3 - 1) * L - cA[2]);
       T r[4];
-      m2p_eval<P, T>(tx - cx, ty - cy, tz - cz, eps2, coef + (size_t)B * STR, r);
+      m2p_eval<P, false, T, T>(tx - cx, ty - cy, tz - cz, eps2, coef + (size_t)B * STR, r);
 #pragma unroll
       for (int k = 0; k < 3; ++k) part[k] += r[k];
       // the potential sums many same-signed terms that the far field later

@@ -50,6 +50,27 @@ hipError_t far_launch(int far_order, const double* spos, const double* smass,
                       const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx, double box, double G, const double* tpsi,
                       double* part, int nblk_max, double* mroot, double* lam, int periodic,
                       bool fp32, void* acc, void* pot, hipStream_t s);
+hipError_t far_prepare_launch(int far_order, const double* spos, const double* smass,
+                              const uint64_t* skey, size_t n, double box, const double* tpsi,
+                              double* part, int nblk_max, double* mom, double* lam,
+                              hipStream_t s);
+hipError_t adj_gather_launch(bool fp32, const void* gacc, const void* gpot, size_t n,
+                             const uint32_t* idx, void* arec, hipStream_t s);
+hipError_t adj_moments_level(bool fp32, int order, const Cells& C, const double* spos,
+                             const void* arec, size_t n, uint32_t beg, uint32_t cnt, double* emom,
+                             void* ecoef, hipStream_t s);
+hipError_t p2p_adj_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                          double eps, const double* spos, const void* srec, const void* arec,
+                          size_t n, const uint32_t* list, double4* out, hipStream_t s);
+hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
+                          double L, double eps, const double* spos, const void* srec,
+                          const void* arec, const void* ecoef, size_t n, const uint32_t* list,
+                          double4* out, hipStream_t s);
+hipError_t far_adj_launch(int far_order, const double* spos, const double* smass,
+                          const uint64_t* skey, const void* arec, const double4* near, size_t n,
+                          const uint32_t* idx, double box, double G, const double* tpsi,
+                          double* part, int nblk_max, const double* lam, double* mbar,
+                          int periodic, bool fp32, double* xbar, void* mbar_out, hipStream_t s);
 hipError_t kick_launch(bool fp32, void* vel, const void* acc, size_t n, double h, hipStream_t s);
 hipError_t drift_launch(bool fp32, double* pos, const void* vel, size_t n, double dt, double L,
                         hipStream_t s);
@@ -133,6 +154,13 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
   P.o_far_part = take(8 * 8 * (size_t)NQ * kFarBlocks);
   P.o_far_mom = take(8 * 8 * (size_t)NQ);
   P.o_far_lam = take(8 * 8 * (size_t)NQ);
+  // adjoint: sorted cotangents, per-particle results, effective charge
+  // moments (order p+1) and coefficients, far-field adjoint moments
+  P.o_arec = take(4 * tsz * n);
+  P.o_adj = take(32 * n);
+  P.o_c_emom = take(8 * (size_t)nt(c->p.order + 1) * C);
+  P.o_c_ecoef = take(tsz * (size_t)coef_stride(c->p.order + 1, true) * C);
+  P.o_far_mbar = take(8 * 8 * (size_t)NQ);
   P.o_list = o;
   const size_t want_list = (size_t)std::ceil(c->list_per_particle * (double)n) + 65536;
   if (ws_bytes == 0) {
@@ -199,8 +227,17 @@ static hipError_t readback(hipStream_t s, const uint32_t* dev, uint32_t* host, i
   return hipStreamSynchronize(s);
 }
 
+// adjoint inputs/outputs (hot_vjp); NULL for a force evaluation
+struct VjpArgs {
+  const void* gacc;
+  const void* gpot;
+  double* xbar;
+  void* mbar;
+};
+
 static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
-                              void* pot, void* ws, size_t ws_bytes, hipStream_t s) {
+                              void* pot, void* ws, size_t ws_bytes, hipStream_t s,
+                              const VjpArgs* vjp = nullptr) {
   const hot_params& p = c->p;
   const bool fp32 = p.precision == HOT_FP32;
   Plan P = make_plan(c, n, ws_bytes);
@@ -317,18 +354,50 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
             "pair count");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
 
-  // ---- interactions
-  HOT_CHECK(p2p_launch(fp32, C, G, ngroups, p.box, p.eps, spos, srec, n, p2p_list, near, s),
-            "direct kernel");
-  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
-  HOT_CHECK(m2p_launch(fp32, p.order, C, G, ngroups, p.box, p.eps, spos, n, m2p_list, near, s),
-            "multipole kernel");
-  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
-  HOT_CHECK(far_launch(p.far_order, spos, smass, key0, near, n, idx0, p.box, p.G, c->d_tpsi,
-                       at<double>(ws, P.o_far_part), kFarBlocks, at<double>(ws, P.o_far_mom),
-                       at<double>(ws, P.o_far_lam), p.periodic, fp32, acc, pot, s),
-            "far field");
-  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
+  if (!vjp) {
+    // ---- interactions
+    HOT_CHECK(p2p_launch(fp32, C, G, ngroups, p.box, p.eps, spos, srec, n, p2p_list, near, s),
+              "direct kernel");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+    HOT_CHECK(m2p_launch(fp32, p.order, C, G, ngroups, p.box, p.eps, spos, n, m2p_list, near, s),
+              "multipole kernel");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
+    HOT_CHECK(far_launch(p.far_order, spos, smass, key0, near, n, idx0, p.box, p.G, c->d_tpsi,
+                         at<double>(ws, P.o_far_part), kFarBlocks, at<double>(ws, P.o_far_mom),
+                         at<double>(ws, P.o_far_lam), p.periodic, fp32, acc, pot, s),
+              "far field");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
+  } else {
+    // ---- adjoint
+    void* arec = at<void>(ws, P.o_arec);
+    double4* adj = at<double4>(ws, P.o_adj);
+    double* emom = at<double>(ws, P.o_c_emom);
+    void* ecoef = at<void>(ws, P.o_c_ecoef);
+    HOT_CHECK(adj_gather_launch(fp32, vjp->gacc, vjp->gpot, n, idx0, arec, s), "adjoint gather");
+    for (int l = nlev - 1; l >= 0; --l)
+      HOT_CHECK(adj_moments_level(fp32, p.order, C, spos, arec, n, lvl[l], lvl[l + 1] - lvl[l],
+                                  emom, ecoef, s),
+                "adjoint moments");
+    HOT_CHECK(p2p_adj_launch(fp32, C, G, ngroups, p.box, p.eps, spos, srec, arec, n, p2p_list,
+                             adj, s),
+              "adjoint direct kernel");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+    HOT_CHECK(m2p_adj_launch(fp32, p.order, C, G, ngroups, p.box, p.eps, spos, srec, arec, ecoef,
+                             n, m2p_list, adj, s),
+              "adjoint multipole kernel");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
+    if (p.periodic)
+      HOT_CHECK(far_prepare_launch(p.far_order, spos, smass, key0, n, p.box, c->d_tpsi,
+                                   at<double>(ws, P.o_far_part), kFarBlocks,
+                                   at<double>(ws, P.o_far_mom), at<double>(ws, P.o_far_lam), s),
+                "far field");
+    HOT_CHECK(far_adj_launch(p.far_order, spos, smass, key0, arec, adj, n, idx0, p.box, p.G,
+                             c->d_tpsi, at<double>(ws, P.o_far_part), kFarBlocks,
+                             at<double>(ws, P.o_far_lam), at<double>(ws, P.o_far_mbar),
+                             p.periodic, fp32, vjp->xbar, vjp->mbar, s),
+              "far-field adjoint");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
+  }
 
   hot_stats& st = c->stats;
   std::memset(&st, 0, sizeof(st));
@@ -480,10 +549,21 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
 hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, const void* gacc,
                    const void* gpot, double* xbar, void* mbar, void* ws, size_t ws_bytes,
                    void* stream) {
-  (void)c; (void)n; (void)pos; (void)mass; (void)gacc; (void)gpot; (void)xbar; (void)mbar;
-  (void)ws; (void)ws_bytes; (void)stream;
-  g_err = "adjoint not built";
-  return HOT_EUNSUPPORTED;
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !mass || !gacc || !xbar || !mbar || !ws) {
+    g_err = "NULL pointer argument";
+    return HOT_EINVAL;
+  }
+  if (n >= (size_t)0xffffffffu) {
+    g_err = "n must be < 2^32";
+    return HOT_EINVAL;
+  }
+  VjpArgs a{gacc, gpot, xbar, mbar};
+  return forces_impl(c, n, pos, mass, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, &a);
 }
 
 hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {

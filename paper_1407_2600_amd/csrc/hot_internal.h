@@ -59,22 +59,27 @@ struct MI {
 // rinv = (R^2+eps^2)^(-1/2), rho = rinv^2 and P_m a polynomial whose
 // homogeneous parts have degrees d = m - j, 0 <= j <= min(m, P - m).  Parts
 // of degree d >= 1 are stored as their gradient coefficients (3 x nte(d-1)),
-// parts of degree 0 as one constant; the dipole part (m = 1, d = 1) vanishes
-// about the centre of mass and is not stored.
+// parts of degree 0 as one constant.  For mass moments about the centre of
+// mass the dipole part (m = 1, d = 1) vanishes and is not stored (DIP =
+// false); the adjoint's effective charge distribution keeps it (DIP = true).
 __host__ __device__ constexpr int part_jmax(int P, int m) { return m < P - m ? m : P - m; }
-__host__ __device__ constexpr bool part_stored(int m, int d) { return !(m == 1 && d == 1); }
+__host__ __device__ constexpr bool part_stored(int m, int d, bool dip = false) {
+  return dip || !(m == 1 && d == 1);
+}
 __host__ __device__ constexpr int part_size(int d) { return d == 0 ? 1 : 3 * nte(d - 1); }
-__host__ __device__ constexpr int coef_count(int P) {
+__host__ __device__ constexpr int coef_count(int P, bool dip = false) {
   int n = 0;
   for (int m = 0; m <= P; ++m)
     for (int j = 0; j <= part_jmax(P, m); ++j) {
       int d = m - j;
-      if (part_stored(m, d)) n += part_size(d);
+      if (part_stored(m, d, dip)) n += part_size(d);
     }
   return n;
 }
 // coefficient block padded to a multiple of 4 values (16-byte aligned rows)
-__host__ __device__ constexpr int coef_stride(int P) { return (coef_count(P) + 3) / 4 * 4; }
+__host__ __device__ constexpr int coef_stride(int P, bool dip = false) {
+  return (coef_count(P, dip) + 3) / 4 * 4;
+}
 
 // Algorithmic flops of one multipole (cell, target) interaction in the
 // formulation above, and of one direct pair (3 sub, 3 fma, rsqrt, 3 mul,
@@ -140,6 +145,7 @@ struct Plan {
   size_t o_c_mmx, o_c_walk, o_c_mom, o_c_coef;
   size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om;
   size_t o_far_part, o_far_mom, o_far_lam;
+  size_t o_arec, o_adj, o_c_emom, o_c_ecoef, o_far_mbar;
   size_t o_list;
 };
 

@@ -16,7 +16,7 @@
 // of mass (leaves directly, internal cells by shifting the daughters'
 // moments).  From the raw moments each cell derives the coefficient block its
 // multipole interactions use.
-#include "hot_internal.h"
+#include "device_math.h"
 
 namespace hot {
 
@@ -121,58 +121,6 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
 }
 
 // ------------------------------------------------------------------ moments
-template <int P>
-__device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
-  // C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m-j
-  // stored as gradient coefficients (k'_a+1) C_{m,k'+e_a} for d >= 1.
-  constexpr MI<P> mi{};
-  int o = 0;
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-    double dfact = 1.0;  // (2m-1)!!
-    for (int q = 1; q <= 2 * m - 1; q += 2) dfact *= (double)q;
-#pragma unroll
-    for (int j = 0; j <= part_jmax(P, m); ++j) {
-      const int d = m - j;
-      if (!part_stored(m, d)) continue;
-      double pre = dfact * ((j & 1) ? -1.0 : 1.0);
-      for (int q = 0; q < j; ++q) pre *= 0.5;
-      auto Cmk = [&](int ka, int kb, int kc) {
-        // sum over |i| = j of M_{k+2i}/i!, divided by k!
-        double s = 0.0;
-        for (int ia = j; ia >= 0; --ia)
-          for (int ib = j - ia; ib >= 0; --ib) {
-            int ic = j - ia - ib;
-            double fi = 1.0;
-            for (int q = 2; q <= ia; ++q) fi *= q;
-            for (int q = 2; q <= ib; ++q) fi *= q;
-            for (int q = 2; q <= ic; ++q) fi *= q;
-            s += M[mi_index(ka + 2 * ia, kb + 2 * ib, kc + 2 * ic)] / fi;
-          }
-        double fk = 1.0;
-        for (int q = 2; q <= ka; ++q) fk *= q;
-        for (int q = 2; q <= kb; ++q) fk *= q;
-        for (int q = 2; q <= kc; ++q) fk *= q;
-        return pre * s / fk;
-      };
-      if (d == 0) {
-        out[o++] = Cmk(0, 0, 0);
-      } else {
-        // gradient coefficients: component a, monomial k' of degree d-1
-        for (int a = 0; a < 3; ++a)
-          for (int x = d - 1; x >= 0; --x)
-            for (int y = d - 1 - x; y >= 0; --y) {
-              int z = d - 1 - x - y;
-              int ka = x + (a == 0), kb = y + (a == 1), kc = z + (a == 2);
-              int ka1 = (a == 0 ? x : a == 1 ? y : z) + 1;
-              out[o++] = ka1 * Cmk(ka, kb, kc);
-            }
-      }
-    }
-  }
-}
-
-
 template <int P, typename T>
 __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restrict__ spos,
                                                  const double* __restrict__ smass, size_t n,

@@ -77,3 +77,22 @@ def compare_structure(dbg, T, sample_groups=None):
 
 def rms_err(a, ref):
     return oracle.rms_rel_error(a, ref)
+
+
+def oracle_mass(mass, precision):
+    """The masses the library actually consumes: FP32 mode takes FP32 input."""
+    mass = np.asarray(mass, dtype=np.float64)
+    return mass.astype(np.float32).astype(np.float64) if precision == "fp32" else mass
+
+
+def pot_ok(pot, ref, precision, prm, mass):
+    """FP64: rms relative error <= 1e-5.  FP32: the potential is a sum over the
+    27 nearest images of magnitude ~27 G M / L that the far field cancels down
+    to the O(G M / L / N^(1/3)) result, so its FP32 error is bounded in absolute
+    terms: rms error <= max(2e-5 rms(ref), 2 ulp_32 * 27 G M / L)."""
+    e = np.sqrt(np.mean((pot - ref) ** 2))
+    rel = e / np.sqrt(np.mean(ref ** 2))
+    if precision == "fp64":
+        return rel <= 1e-5, rel
+    scale = 27.0 * abs(prm.get("G", 1.0)) * float(np.sum(mass)) / prm.get("box", 1.0)
+    return (rel <= 2e-5) or (e <= 2 * 2.0 ** -24 * scale), rel
