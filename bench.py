@@ -35,10 +35,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--theta", type=float, default=None,
+                    help="fixed opening angle (skips the 1e-3 operating-point search)")
     ap.add_argument("--far-order", type=int, default=None)
-    ap.add_argument("--group-max", type=int, default=None)
-    ap.add_argument("--leaf-max", type=int, default=None)
+    ap.add_argument("--group-max", type=int, default=128)
+    ap.add_argument("--leaf-max", type=int, default=16)
     ap.add_argument("--n-side", type=int, default=None, help="smaller grid (debug only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -46,9 +47,47 @@ def parse():
     return ap.parse_args()
 
 
-# opening angle at which the FP32 rms force error vs the theta=0 reference is
-# about 1e-3 on this workload (measured by the theta sweep)
-THETA_STAR = 0.5
+# rms force error the operating point is defined at, and the opening angles
+# searched for it (order 4)
+ERR_TARGET = 1e-3
+THETA_GRID = (0.40, 0.42, 0.44, 0.45, 0.46, 0.47, 0.48, 0.50, 0.55)
+REF_PATH = os.path.join(ROOT, "tests", "golden", "zeldovich128_ref.npz")
+
+
+def rms_err(a, ref):
+    return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))
+
+
+def theta_search(torch, Gravity, pos, mass_np, prm, ref, dev):
+    """FP32 force error vs the oracle reference over THETA_GRID.  Returns the
+    largest grid theta whose error is <= ERR_TARGET (the timed operating
+    point), the log-linear interpolated crossing, and the sweep table."""
+    tg, aref = ref
+    table = []
+    for th in THETA_GRID:
+        g = Gravity(device=dev, precision="fp32", **dict(prm, theta=th))
+        m = torch.as_tensor(mass_np, dtype=torch.float32, device=dev)
+        a, _ = g.forces(pos, m)
+        torch.cuda.synchronize()
+        st = g.stats()
+        e = rms_err(a[:, torch.as_tensor(tg, device=dev)].double().cpu().numpy(), aref)
+        table.append({"theta": th, "err": e, "ms_force": st["ms_total"],
+                      "m2p_per_particle": st["m2p_pairs"] / st["n"],
+                      "p2p_per_particle": st["p2p_pairs"] / st["n"]})
+        print(f"[bench] theta={th:.3f} err={e:.3e} ms={st['ms_total']:.2f}", file=sys.stderr,
+              flush=True)
+        del g
+    ok = [r["theta"] for r in table if r["err"] <= ERR_TARGET]
+    if not ok:
+        raise SystemExit("no opening angle on the grid reaches the target error")
+    star = max(ok)
+    cross = None
+    for lo, hi in zip(table, table[1:]):
+        if lo["err"] <= ERR_TARGET < hi["err"]:
+            f = (np.log(ERR_TARGET) - np.log(lo["err"])) / (np.log(hi["err"]) - np.log(lo["err"]))
+            cross = lo["theta"] + f * (hi["theta"] - lo["theta"])
+            break
+    return star, cross, table
 
 
 def main():
@@ -62,23 +101,31 @@ def main():
     from paper_1407_2600_amd import Gravity
 
     pos_np, mass_np, prm = workloads.make("zeldovich128", n_side=args.n_side)
-    prm = dict(prm)
-    prm["theta"] = args.theta if args.theta is not None else THETA_STAR
+    prm = dict(prm, group_max=args.group_max, leaf_max=args.leaf_max)
     if args.far_order is not None:
         prm["far_order"] = args.far_order
-    if args.group_max is not None:
-        prm["group_max"] = args.group_max
-    if args.leaf_max is not None:
-        prm["leaf_max"] = args.leaf_max
     n = pos_np.shape[1]
     dev = torch.device("cuda", 0)
+    pos_dev = torch.as_tensor(pos_np, dtype=torch.float64, device=dev).contiguous()
+
+    ref = None
+    if args.n_side is None and os.path.exists(REF_PATH):
+        R = np.load(REF_PATH)
+        ref = (R["targets"], R["acc_near_far"])
+    sweep, cross = None, None
+    if args.theta is not None:
+        prm["theta"] = args.theta
+    elif ref is not None:
+        prm["theta"], cross, sweep = theta_search(torch, Gravity, pos_dev, mass_np, prm, ref, dev)
+    else:
+        prm["theta"] = 0.46
     print(f"[bench] n={n} params={prm}", file=sys.stderr, flush=True)
 
     res = {}
     for prec in ("fp32", "fp64"):
         g = Gravity(device=dev, precision=prec, **prm)
         dt_ = torch.float32 if prec == "fp32" else torch.float64
-        pos = torch.as_tensor(pos_np, dtype=torch.float64, device=dev).contiguous()
+        pos = pos_dev.clone()
         mass = torch.as_tensor(mass_np, dtype=dt_, device=dev)
         vel = torch.zeros((3, n), dtype=dt_, device=dev)
         acc = torch.empty((3, n), dtype=dt_, device=dev)
@@ -88,7 +135,33 @@ def main():
         torch.cuda.synchronize()
         acc.copy_(a0)
         a_first = a0.double().cpu().numpy()
-        st0 = g.stats()
+        # force evaluations alone (stream time from the library's HIP events)
+        f_ms = []
+        for _ in range(5):
+            g.forces(pos, mass, out_acc=a0, out_pot=p0)
+            f_ms.append(g.stats()["ms_total"])
+        # adjoint (vector-Jacobian product) against forward at the same point
+        adj = None
+        if prec == "fp32":
+            gen = torch.Generator(device=dev).manual_seed(7)
+            gacc = torch.randn((3, n), dtype=dt_, device=dev, generator=gen)
+            gpot = torch.randn(n, dtype=dt_, device=dev, generator=gen)
+            g.vjp(pos, mass, gacc, gpot)
+            torch.cuda.synchronize()
+            ta = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                g.vjp(pos, mass, gacc, gpot)
+                torch.cuda.synchronize()
+                ta.append(time.perf_counter() - t0)
+            tf = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                g.forces(pos, mass, out_acc=a0, out_pot=p0)
+                torch.cuda.synchronize()
+                tf.append(time.perf_counter() - t0)
+            adj = {"ms_vjp": 1e3 * float(np.median(ta)), "ms_forward": 1e3 * float(np.median(tf))}
+            adj["ratio"] = adj["ms_vjp"] / adj["ms_forward"]
         for _ in range(args.warmup):
             g.kdk(pos, vel, mass, acc, args.dt, 1, acc_valid=True, pot=pot)
         torch.cuda.synchronize()
@@ -115,26 +188,22 @@ def main():
                          kern={k: v / steps for k, v in kern.items()},
                          flops={k: v / steps for k, v in flops.items()},
                          pairs={k: v / steps for k, v in pairs.items()},
-                         acc=a_first, pot=p0.double().cpu().numpy(), stats0=st0)
+                         ms_force_median=float(np.median(f_ms)), adjoint=adj,
+                         acc=a_first)
         print(f"[bench] {prec}: {res[prec]['ms_per_step']:.2f} ms/step "
-              f"kern={res[prec]['kern']}", file=sys.stderr, flush=True)
+              f"force {res[prec]['ms_force_median']:.2f} ms kern={res[prec]['kern']}",
+              file=sys.stderr, flush=True)
         del g
 
-    # rms force error vs the stored oracle reference (theta = 0 tree on 256
-    # sampled targets; written by tests/golden/make_zeldovich128_ref.py)
     err = {}
-    ref_path = os.path.join(ROOT, "tests", "golden", "zeldovich128_ref.npz")
-    if args.n_side is None and os.path.exists(ref_path):
-        R = np.load(ref_path)
-        tg = R["targets"]
+    if ref is not None:
+        tg, aref = ref
         for prec in ("fp32", "fp64"):
-            a = res[prec]["acc"][:, tg]
-            e = np.sqrt(np.sum((a - R["acc_near_far"]) ** 2) / np.sum(R["acc_near_far"] ** 2))
-            err[prec] = float(e)
+            err[prec] = rms_err(res[prec]["acc"][:, tg], aref)
         te = R["targets_ewald"]
-        a = res["fp32"]["acc"][:, te]
-        err["fp32_vs_exact_ewald"] = float(np.sqrt(np.sum((a - R["acc_ewald"]) ** 2) /
-                                               np.sum(R["acc_ewald"] ** 2)))
+        err["fp32_vs_exact_ewald"] = rms_err(res["fp32"]["acc"][:, te], R["acc_ewald"])
+        err["targets"] = int(len(tg))
+        err["targets_ewald"] = int(len(te))
 
     # roofline of the dominant kernel (FP32 mode): algorithmic flops per
     # launch / average launch time from the library's HIP events
@@ -143,8 +212,8 @@ def main():
     ms = r32["kern"][f"ms_{dom}"]
     fl = r32["flops"][dom]
     achieved = fl / (ms * 1e-3) / 1e12
-    roof = {"kernel": "k_m2p<4,float>" if dom == "m2p" else "k_p2p<float>", "bound": "alu",
-            "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+    roof = {"kernel": f"k_m2p<{prm['order']},float>" if dom == "m2p" else "k_p2p<float>",
+            "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
             "flops_per_launch": fl, "ms_per_launch": ms}
     other = "p2p" if dom == "m2p" else "m2p"
@@ -174,11 +243,17 @@ def main():
                    "theta": prm["theta"], "order": prm["order"], "eps": prm["eps"],
                    "leaf_max": prm["leaf_max"], "group_max": prm["group_max"],
                    "far_order": prm["far_order"], "step": "one KDK step (one force evaluation)"},
+        "theta_star": {"timed": prm["theta"], "interpolated": cross, "err_target": ERR_TARGET,
+                       "sweep": sweep},
+        "per_force_eval": {"fp32_ms": r32["ms_force_median"], "fp32_pps": n / (
+            1e-3 * r32["ms_force_median"]), "fp64_ms": res["fp64"]["ms_force_median"],
+            "fp64_pps": n / (1e-3 * res["fp64"]["ms_force_median"])},
         "fp64": {"value": res["fp64"]["pps"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "dtype": "f64"},
         "fp32_over_fp64": r32["pps"] / res["fp64"]["pps"],
         "rms_force_err": err,
-        "adjoint_over_forward": None,
+        "adjoint_over_forward": r32["adjoint"]["ratio"],
+        "adjoint": r32["adjoint"],
         "interactions_per_s": (r32["pairs"]["p2p"] + r32["pairs"]["m2p"]) /
                               (r32["ms_per_step"] * 1e-3),
         "stage_ms": r32["kern"],

@@ -109,6 +109,7 @@ typedef struct {
   double ms_m2p;          /* multipole kernel */
   double ms_far;          /* far field + unpermute */
   size_t ws_bytes_needed; /* workspace that would have sufficed */
+  int64_t kdk_steps_done; /* steps hot_kdk completed in its last call */
 } hot_stats;
 
 /* Host copies of the internal structures of the last hot_forces call, for
@@ -170,7 +171,12 @@ hot_status hot_forces(hot_ctx* ctx, size_t n, const double* pos, const void* mas
  *         pos if (flags & HOT_ACC_VALID), otherwise they are computed first;
  *         on return the accelerations at the final positions
  *   pot   device, n (precision) or NULL: potentials at the final positions
- * Same errors as hot_forces. */
+ * Same errors as hot_forces.  A failing force evaluation leaves pos, vel and
+ * acc at the end of the last completed step (restored from a snapshot in the
+ * workspace); hot_get_stats reports that step count as kdk_steps_done, and
+ * acc is valid there whenever kdk_steps_done > 0 or HOT_ACC_VALID was given,
+ * so after HOT_EOVERFLOW the caller resizes the workspace and repeats the
+ * call for the remaining steps. */
 #define HOT_ACC_VALID 1u
 hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* mass, void* acc,
                    void* pot, double dt, int nsteps, unsigned flags, void* workspace,
@@ -188,6 +194,27 @@ hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* m
 hot_status hot_vjp(hot_ctx* ctx, size_t n, const double* pos, const void* mass, const void* gacc,
                    const void* gpot, double* xbar, void* mbar, void* workspace, size_t ws_bytes,
                    void* stream);
+
+/* Reverse-mode derivative of nsteps hot_kdk steps (an extension beyond the
+ * paper), for differentiating a trajectory with per-step checkpoints: only
+ * the positions are stored, and the tree of every step is rebuilt here.
+ *   pos_ckpt  device, (nsteps + 1) x 3 x n FP64, read only: the positions at
+ *             the start of each step and after the last one, as hot_kdk
+ *             produced them
+ *   mass      device, n (precision), read only
+ *   xbar      device, 3 x n FP64, in/out: on entry the cotangent of the final
+ *             positions, on return that of the initial positions
+ *   vbar      device, 3 x n (precision), in/out: likewise for velocities
+ *   mbar      device, n (precision) or NULL: written with the cotangent of
+ *             the masses
+ * The force derivatives are those of hot_vjp (exact for theta == 0), taken
+ * once per stored position: the closing kick of one step and the opening
+ * kick of the next share it.  nsteps == 0 leaves xbar, vbar unchanged and
+ * zeroes mbar.  Same errors as hot_forces; on any failure xbar and vbar are
+ * restored to their values on entry, so the call can be repeated. */
+hot_status hot_kdk_vjp(hot_ctx* ctx, size_t n, int nsteps, const double* pos_ckpt,
+                       const void* mass, double dt, double* xbar, void* vbar, void* mbar,
+                       void* workspace, size_t ws_bytes, void* stream);
 
 /* Statistics of the last compute call (synchronises nothing). */
 hot_status hot_get_stats(const hot_ctx* ctx, hot_stats* out);

@@ -397,3 +397,42 @@ def kdk(pos, vel, mass, params: dict, dt: float, nsteps: int, acc=None):
         acc, pot = Tree(pos, mass, params).forces()
         vel = vel + (0.5 * dt) * acc
     return pos, vel, acc, pot
+
+
+def kdk_trajectory(pos, vel, mass, params: dict, dt: float, nsteps: int):
+    """Positions at the start of every step and at the end, [x_0 .. x_n]
+    (each 3 x N), and the final velocities, of ``kdk``."""
+    xs = [np.array(pos, dtype=np.float64)]
+    p, v, acc = xs[0], np.array(vel, dtype=np.float64), None
+    for _ in range(nsteps):
+        p, v, acc, _ = kdk(p, v, mass, params, dt, 1, acc=acc)
+        xs.append(p)
+    return xs, v
+
+
+def kdk_vjp(xs, mass, params: dict, dt: float, xbar, vbar):
+    """Reverse-mode derivative of ``kdk`` over len(xs) - 1 steps, taken one
+    operation at a time backwards through each step
+        v' = v + a(x) dt/2,  x1 = wrap(x + v' dt),  v1 = v' + a(x1) dt/2
+    (the wrap has unit derivative).  xs are the step-start positions and the
+    final ones; xbar, vbar the cotangents of the final positions and
+    velocities.  Returns the cotangents (x0bar, v0bar, mbar) of the initial
+    positions, the initial velocities and the masses.  The force derivative
+    is Tree.vjp (exact for theta = 0)."""
+    xb = np.array(xbar, dtype=np.float64)
+    vb = np.array(vbar, dtype=np.float64)
+    mb = np.zeros(len(mass))
+    for k in range(len(xs) - 2, -1, -1):
+        # v1 = v' + a(x1) dt/2
+        vpb = vb.copy()
+        tx, tm = Tree(xs[k + 1], mass, params).vjp(0.5 * dt * vb)
+        xb = xb + tx
+        mb = mb + tm
+        # x1 = wrap(x + v' dt)
+        vpb = vpb + dt * xb
+        # v' = v + a(x) dt/2
+        tx, tm = Tree(xs[k], mass, params).vjp(0.5 * dt * vpb)
+        xb = xb + tx
+        mb = mb + tm
+        vb = vpb
+    return xb, vb, mb

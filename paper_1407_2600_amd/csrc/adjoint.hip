@@ -12,8 +12,9 @@
 //     centre of mass: the mass expansion evaluated on dual numbers along
 //     gacc_k, which yields grad Phi and H gacc_k in one pass, and one order
 //     p+1 expansion of the effective charge distribution of the sources
-//     (charges gpot_j plus dipoles gacc_j, moments
-//       E_k = sum_j [gpot_j d^k - sum_a k_a gacc_j,a d^(k - e_a)]),
+//     (charges gpot_j plus dipoles gacc_j, both moment sets truncated at
+//     order p like the mass moments, so
+//       E_k = sum_j [gpot_j d^k [|k| <= p] - sum_a k_a gacc_j,a d^(k - e_a)]),
 //     whose potential psi and gradient give mbar_k = -G psi and the
 //     - G m_k grad psi part of xbar_k;
 //   - the periodic far field differentiated exactly (far_adjoint below).
@@ -42,16 +43,49 @@ __global__ void __launch_bounds__(256) k_adj_gather(const T* __restrict__ gacc,
   arec[s] = r;
 }
 
-// effective charge moments, order P+1, about each cell's centre of mass
-// (leaves from their particles, internal cells by shifting the daughters'),
-// and the coefficient block (dipole part kept)
+// Source-side cotangent moments about each cell's centre of mass, truncated
+// like the mass moments: the charge part Q_k = sum_j gpot_j d^k for |k| <= P,
+// and the dipole part A_k = -sum_j sum_a k_a gacc_j,a d^(k - e_a), which
+// holds gacc moments up to order P and so reaches order P+1. Both are shifted
+// exactly from the daughters (moments of a distribution shift without loss
+// when every lower order is present), and only their sum
+// E = Q + A, an order P+1 block, is turned into coefficients (dipole part
+// kept). Shifting E itself would leak order P+1 charge terms into parents.
+template <int Q, int NM>
+__device__ __forceinline__ void shift_add(const double* __restrict__ Mch, const double d[3],
+                                          double* M) {
+  constexpr MI<Q> mi{};
+  double pw[3][Q + 1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    pw[a][0] = 1.0;
+#pragma unroll
+    for (int e2 = 1; e2 <= Q; ++e2) pw[a][e2] = pw[a][e2 - 1] * d[a];
+  }
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NM; ++j) {
+      if (mi.a[j] > mi.a[k] || mi.b[j] > mi.b[k] || mi.c[j] > mi.c[k]) continue;
+      const int ra = mi.a[k] - mi.a[j], rb = mi.b[k] - mi.b[j], rc = mi.c[k] - mi.c[j];
+      double bin = 1.0;
+      for (int u = 0; u < mi.a[j]; ++u) bin = bin * (double)(mi.a[k] - u) / (double)(u + 1);
+      for (int u = 0; u < mi.b[j]; ++u) bin = bin * (double)(mi.b[k] - u) / (double)(u + 1);
+      for (int u = 0; u < mi.c[j]; ++u) bin = bin * (double)(mi.c[k] - u) / (double)(u + 1);
+      acc += bin * Mch[j] * pw[0][ra] * pw[1][rb] * pw[2][rc];
+    }
+    M[k] += acc;
+  }
+}
+
 template <int P, typename T, typename T4>
 __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __restrict__ spos,
                                                      const T4* __restrict__ arec, size_t n,
                                                      uint32_t beg, uint32_t cnt, double* emom,
                                                      T* __restrict__ ecoef) {
   constexpr int Q = P + 1;
-  constexpr int NM = nt(Q);
+  constexpr int NA = nt(Q), NQ = nt(P);
   constexpr MI<Q> mi{};
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
@@ -60,9 +94,11 @@ __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __re
   const double com[3] = {w.x, w.y, w.z};
   const int nc = C.nchild[c];
   const int c0 = C.child[c];
-  double M[NM];
+  double A[NA], Qm[NQ];
 #pragma unroll
-  for (int k = 0; k < NM; ++k) M[k] = 0.0;
+  for (int k = 0; k < NA; ++k) A[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) Qm[k] = 0.0;
   if (nc == 0) {
     const uint32_t f = C.first[c], e = f + C.count[c];
     for (uint32_t s = f; s < e; ++s) {
@@ -78,13 +114,14 @@ __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __re
         for (int e2 = 1; e2 <= Q; ++e2) pw[a][e2] = pw[a][e2 - 1] * d[a];
       }
 #pragma unroll
-      for (int k = 0; k < NM; ++k) {
+      for (int k = 0; k < NA; ++k) {
         const int ka = mi.a[k], kb = mi.b[k], kc = mi.c[k];
-        double v = (ka + kb + kc <= P) ? q * pw[0][ka] * pw[1][kb] * pw[2][kc] : 0.0;
+        double v = 0.0;
         if (ka) v -= ka * ga[0] * pw[0][ka - 1] * pw[1][kb] * pw[2][kc];
         if (kb) v -= kb * ga[1] * pw[0][ka] * pw[1][kb - 1] * pw[2][kc];
         if (kc) v -= kc * ga[2] * pw[0][ka] * pw[1][kb] * pw[2][kc - 1];
-        M[k] += v;
+        A[k] += v;
+        if (k < NQ) Qm[k] += q * pw[0][ka] * pw[1][kb] * pw[2][kc];
       }
     }
   } else {
@@ -92,41 +129,30 @@ __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __re
       const int ch = c0 + kc2;
       const double4 wc = C.walk[ch];
       const double d[3] = {wc.x - com[0], wc.y - com[1], wc.z - com[2]};
-      double pw[3][Q + 1];
+      const double* Mc = emom + (size_t)ch * (NA + NQ);
+      double Mch[NA];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        pw[a][0] = 1.0;
+      for (int k = 0; k < NA; ++k) Mch[k] = Mc[k];
+      shift_add<Q, NA>(Mch, d, A);
+      double Qch[NQ];
 #pragma unroll
-        for (int e2 = 1; e2 <= Q; ++e2) pw[a][e2] = pw[a][e2 - 1] * d[a];
-      }
-      const double* Mc = emom + (size_t)ch * NM;
-      double Mch[NM];
-#pragma unroll
-      for (int k = 0; k < NM; ++k) Mch[k] = Mc[k];
-#pragma unroll
-      for (int k = 0; k < NM; ++k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < NM; ++j) {
-          if (mi.a[j] > mi.a[k] || mi.b[j] > mi.b[k] || mi.c[j] > mi.c[k]) continue;
-          const int ra = mi.a[k] - mi.a[j], rb = mi.b[k] - mi.b[j], rc = mi.c[k] - mi.c[j];
-          double bin = 1.0;
-          for (int u = 0; u < mi.a[j]; ++u) bin = bin * (double)(mi.a[k] - u) / (double)(u + 1);
-          for (int u = 0; u < mi.b[j]; ++u) bin = bin * (double)(mi.b[k] - u) / (double)(u + 1);
-          for (int u = 0; u < mi.c[j]; ++u) bin = bin * (double)(mi.c[k] - u) / (double)(u + 1);
-          acc += bin * Mch[j] * pw[0][ra] * pw[1][rb] * pw[2][rc];
-        }
-        M[k] += acc;
-      }
+      for (int k = 0; k < NQ; ++k) Qch[k] = Mc[NA + k];
+      shift_add<P, NQ>(Qch, d, Qm);
     }
   }
-  double* Mo = emom + (size_t)c * NM;
+  double* Mo = emom + (size_t)c * (NA + NQ);
 #pragma unroll
-  for (int k = 0; k < NM; ++k) Mo[k] = M[k];
+  for (int k = 0; k < NA; ++k) Mo[k] = A[k];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) Mo[NA + k] = Qm[k];
+  // order-P+1 multi-indices come after all lower orders, so E = A + Q is a
+  // prefix add
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) A[k] += Qm[k];
   constexpr int NCF = coef_count(Q, true);
   constexpr int STR = coef_stride(Q, true);
   double cf[NCF];
-  coef_from_moments<Q, true>(M, cf);
+  coef_from_moments<Q, true>(A, cf);
   T* out = ecoef + (size_t)c * STR;
 #pragma unroll
   for (int k = 0; k < NCF; ++k) out[k] = (T)cf[k];

@@ -72,6 +72,11 @@ hipError_t far_adj_launch(int far_order, const double* spos, const double* smass
                           double* part, int nblk_max, const double* lam, double* mbar,
                           int periodic, bool fp32, double* xbar, void* mbar_out, hipStream_t s);
 hipError_t kick_launch(bool fp32, void* vel, const void* acc, size_t n, double h, hipStream_t s);
+hipError_t kdk_adj_drift_launch(bool fp32, void* vbar, const double* xbar, void* gacc, size_t n,
+                                double dt, double c, bool drift, hipStream_t s);
+hipError_t kdk_adj_accum_launch(bool fp32, double* xbar, const double* tx, void* mbar,
+                                const void* tm, size_t n, bool first, hipStream_t s);
+hipError_t zero_launch(void* p, size_t bytes, hipStream_t s);
 hipError_t drift_launch(bool fp32, double* pos, const void* vel, size_t n, double dt, double L,
                         hipStream_t s);
 
@@ -158,9 +163,14 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
   // moments (order p+1) and coefficients, far-field adjoint moments
   P.o_arec = take(4 * tsz * n);
   P.o_adj = take(32 * n);
-  P.o_c_emom = take(8 * (size_t)nt(c->p.order + 1) * C);
+  P.o_c_emom = take(8 * (size_t)(nt(c->p.order + 1) + nt(c->p.order)) * C);
   P.o_c_ecoef = take(tsz * (size_t)coef_stride(c->p.order + 1, true) * C);
   P.o_far_mbar = take(8 * 8 * (size_t)NQ);
+  P.o_kv_g = take(3 * tsz * n);
+  P.o_kv_x = take(24 * n);
+  P.o_kv_m = take(tsz * n);
+  P.o_kv_sx = take(24 * n);
+  P.o_kv_sv = take(3 * tsz * n);
   P.o_list = o;
   const size_t want_list = (size_t)std::ceil(c->list_per_particle * (double)n) + 65536;
   if (ws_bytes == 0) {
@@ -531,17 +541,36 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
   }
   hipStream_t s = (hipStream_t)stream;
   const bool fp32 = c->p.precision == HOT_FP32;
+  const size_t tsz = fp32 ? 4 : 8;
+  c->stats.kdk_steps_done = 0;
+  const Plan P = make_plan(c, n, ws_bytes);
+  if (ws_bytes < P.o_list) {  // the snapshot regions lie below the lists
+    g_err = "workspace smaller than hot_workspace_size()";
+    return HOT_ENOMEM;
+  }
   hot_status st;
   if (!(flags & HOT_ACC_VALID)) {
     st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s);
     if (st != HOT_OK) return st;
   }
+  double* sx = at<double>(ws, P.o_kv_sx);
+  void* sv = at<void>(ws, P.o_kv_sv);
   for (int k = 0; k < nsteps; ++k) {
+    // snapshot of the step's start, restored if its force evaluation fails
+    HOT_CHECK(hipMemcpyAsync(sx, pos, 24 * n, hipMemcpyDeviceToDevice, s), "snapshot");
+    HOT_CHECK(hipMemcpyAsync(sv, vel, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
     HOT_CHECK(drift_launch(fp32, pos, vel, n, dt, c->p.box, s), "drift");
     st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s);
-    if (st != HOT_OK) return st;
+    if (st != HOT_OK) {
+      // acc is written only by a successful evaluation
+      HOT_CHECK(hipMemcpyAsync(pos, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
+      HOT_CHECK(hipMemcpyAsync(vel, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");
+      HOT_CHECK(hipStreamSynchronize(s), "restore");
+      return st;
+    }
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
+    c->stats.kdk_steps_done = k + 1;
   }
   return HOT_OK;
 }
@@ -564,6 +593,63 @@ hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, co
   }
   VjpArgs a{gacc, gpot, xbar, mbar};
   return forces_impl(c, n, pos, mass, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, &a);
+}
+
+hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt, const void* mass,
+                       double dt, double* xbar, void* vbar, void* mbar, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos_ckpt || !mass || !xbar || !vbar || !ws || nsteps < 0 || !std::isfinite(dt)) {
+    g_err = "bad argument";
+    return HOT_EINVAL;
+  }
+  if (n >= (size_t)0xffffffffu) {
+    g_err = "n must be < 2^32";
+    return HOT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool fp32 = c->p.precision == HOT_FP32;
+  const size_t tsz = fp32 ? 4 : 8;
+  if (nsteps == 0) {
+    if (mbar) HOT_CHECK(zero_launch(mbar, tsz * n, s), "clear mbar");
+    return HOT_OK;
+  }
+  // the scratch of the sweep sits in the workspace regions reserved for it,
+  // which the force derivative itself does not touch
+  Plan P = make_plan(c, n, ws_bytes);
+  if (ws_bytes < P.o_list) {
+    g_err = "workspace smaller than hot_workspace_size()";
+    return HOT_ENOMEM;
+  }
+  void* gacc = at<void>(ws, P.o_kv_g);
+  double* tx = at<double>(ws, P.o_kv_x);
+  void* tm = at<void>(ws, P.o_kv_m);
+  double* sx = at<double>(ws, P.o_kv_sx);
+  void* sv = at<void>(ws, P.o_kv_sv);
+  HOT_CHECK(hipMemcpyAsync(sx, xbar, 24 * n, hipMemcpyDeviceToDevice, s), "snapshot");
+  HOT_CHECK(hipMemcpyAsync(sv, vbar, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
+  const size_t stride = 3 * n;
+  for (int k = nsteps; k >= 0; --k) {
+    // k == nsteps: closing kick of the last step only (no drift yet)
+    const double cf = (k == nsteps || k == 0) ? 0.5 * dt : dt;
+    HOT_CHECK(kdk_adj_drift_launch(fp32, vbar, xbar, gacc, n, dt, cf, k != nsteps, s),
+              "adjoint drift");
+    VjpArgs a{gacc, nullptr, tx, tm};
+    hot_status st = forces_impl(c, n, pos_ckpt + (size_t)k * stride, mass, nullptr, nullptr, ws,
+                                ws_bytes, s, &a);
+    if (st != HOT_OK) {
+      HOT_CHECK(hipMemcpyAsync(xbar, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
+      HOT_CHECK(hipMemcpyAsync(vbar, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");
+      HOT_CHECK(hipStreamSynchronize(s), "restore");
+      return st;
+    }
+    HOT_CHECK(kdk_adj_accum_launch(fp32, xbar, tx, mbar, tm, n, k == nsteps, s), "adjoint sum");
+  }
+  return HOT_OK;
 }
 
 hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {

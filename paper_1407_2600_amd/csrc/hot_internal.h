@@ -146,6 +146,8 @@ struct Plan {
   size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om;
   size_t o_far_part, o_far_mom, o_far_lam;
   size_t o_arec, o_adj, o_c_emom, o_c_ecoef, o_far_mbar;
+  size_t o_kv_g, o_kv_x, o_kv_m;  // reverse leapfrog sweep: gacc, xbar and mbar of one step
+  size_t o_kv_sx, o_kv_sv;        // snapshots of the in/out arrays of hot_kdk and hot_kdk_vjp
   size_t o_list;
 };
 

@@ -46,6 +46,74 @@ hipError_t drift_launch(bool fp32, double* pos, const void* vel, size_t n, doubl
   return hipGetLastError();
 }
 
+// Reverse sweep of the leapfrog (hot_kdk_vjp).  Between two force
+// derivatives the cotangents move through the drift and the kicks:
+//   vbar += xbar dt (drift),  gacc = c vbar (kick cotangent of a(x_k)),
+// with c = dt/2 at the two ends of the trajectory and dt inside, where the
+// closing kick of one step and the opening kick of the next share a(x_k).
+template <typename T>
+__global__ void __launch_bounds__(256) k_kdk_adj_drift(T* __restrict__ vbar,
+                                                       const double* __restrict__ xbar,
+                                                       T* __restrict__ gacc, size_t m, double dt,
+                                                       double c, int drift) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  T v = vbar[i];
+  if (drift) {
+    v = (T)((double)v + xbar[i] * dt);
+    vbar[i] = v;
+  }
+  gacc[i] = (T)((double)v * c);
+}
+
+// xbar += tx (3 n); mbar (+)= tm (n)
+template <typename T>
+__global__ void __launch_bounds__(256) k_kdk_adj_accum(double* __restrict__ xbar,
+                                                       const double* __restrict__ tx,
+                                                       T* __restrict__ mbar,
+                                                       const T* __restrict__ tm, size_t n,
+                                                       int first) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * n) return;
+  xbar[i] += tx[i];
+  if (mbar && i < n) mbar[i] = first ? tm[i] : mbar[i] + tm[i];
+}
+
+// byte-granular clear by a kernel (safe inside captured graphs)
+__global__ void __launch_bounds__(256) k_zero(unsigned char* __restrict__ p, size_t bytes) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < bytes) p[i] = 0;
+}
+
+hipError_t zero_launch(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  k_zero<<<(unsigned)((bytes + 255) / 256), 256, 0, s>>>((unsigned char*)p, bytes);
+  return hipGetLastError();
+}
+
+hipError_t kdk_adj_drift_launch(bool fp32, void* vbar, const double* xbar, void* gacc, size_t n,
+                                double dt, double c, bool drift, hipStream_t s) {
+  size_t m = 3 * n;
+  unsigned g = (unsigned)((m + 255) / 256);
+  if (fp32)
+    k_kdk_adj_drift<float><<<g, 256, 0, s>>>((float*)vbar, xbar, (float*)gacc, m, dt, c, drift);
+  else
+    k_kdk_adj_drift<double><<<g, 256, 0, s>>>((double*)vbar, xbar, (double*)gacc, m, dt, c,
+                                               drift);
+  return hipGetLastError();
+}
+
+hipError_t kdk_adj_accum_launch(bool fp32, double* xbar, const double* tx, void* mbar,
+                                const void* tm, size_t n, bool first, hipStream_t s) {
+  unsigned g = (unsigned)((3 * n + 255) / 256);
+  if (fp32)
+    k_kdk_adj_accum<float><<<g, 256, 0, s>>>(xbar, tx, (float*)mbar, (const float*)tm, n, first);
+  else
+    k_kdk_adj_accum<double><<<g, 256, 0, s>>>(xbar, tx, (double*)mbar, (const double*)tm, n,
+                                               first);
+  return hipGetLastError();
+}
+
 // direct pairs = n_A (n_A - 1 + sum of listed leaf counts); multipole pairs =
 // n_A x (list length), summed over groups
 __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t ngroups,

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
 
 # symbols declared in include/hot.h
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_forces", "hot_kdk",
-            "hot_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
+            "hot_vjp", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
             "hot_last_error", "hot_version", "hot_far_table"]
 
 
@@ -44,7 +44,8 @@ class hot_stats(C.Structure):
                 ("p2p_pairs", C.c_int64), ("m2p_pairs", C.c_int64), ("flops_p2p", C.c_double),
                 ("flops_m2p", C.c_double), ("ms_total", C.c_double), ("ms_sort", C.c_double),
                 ("ms_build", C.c_double), ("ms_walk", C.c_double), ("ms_p2p", C.c_double),
-                ("ms_m2p", C.c_double), ("ms_far", C.c_double), ("ws_bytes_needed", C.c_size_t)]
+                ("ms_m2p", C.c_double), ("ms_far", C.c_double), ("ws_bytes_needed", C.c_size_t),
+                ("kdk_steps_done", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +84,8 @@ def lib():
                               vp]
         L.hot_vjp.restype = C.c_int
         L.hot_vjp.argtypes = [vp, sz, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.hot_kdk_vjp.restype = C.c_int
+        L.hot_kdk_vjp.argtypes = [vp, sz, C.c_int, vp, vp, C.c_double, vp, vp, vp, vp, sz, vp]
         L.hot_get_stats.restype = C.c_int
         L.hot_get_stats.argtypes = [vp, C.POINTER(hot_stats)]
         L.hot_debug_sizes.restype = C.c_int
@@ -208,16 +211,51 @@ class Gravity:
                 raise ValueError(f"{name} must be a contiguous (3, N) {self.dtype} tensor")
         n = pos.shape[1]
         s = self._stream()
-        flags = HOT_ACC_VALID if acc_valid else 0
+        left, valid = int(nsteps), bool(acc_valid)
+        # after HOT_EOVERFLOW the library has restored the state at the end of
+        # the last completed step; resume from there with a larger workspace
+        for _ in range(6):
+            ws = self._workspace(n)
+            st = self.L.hot_kdk(self.h, n, C.c_void_p(pos.data_ptr()),
+                                C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
+                                C.c_void_p(acc.data_ptr()),
+                                C.c_void_p(pot.data_ptr() if pot is not None else 0),
+                                float(dt), left, HOT_ACC_VALID if valid else 0,
+                                C.c_void_p(ws.data_ptr()), ws.numel(), s)
+            if st != HOT_EOVERFLOW:
+                check(st)
+                return
+            done = self.stats()["kdk_steps_done"]
+            valid = valid or done > 0
+            left -= done
+        check(st)
+
+    def kdk_vjp(self, pos_ckpt, mass, dt: float, xbar, vbar):
+        """Reverse sweep over len(pos_ckpt) - 1 leapfrog steps (hot_kdk_vjp).
+        pos_ckpt: (S+1, 3, N) FP64 positions at each step start and the end;
+        xbar (FP64) and vbar (precision): cotangents of the final state,
+        updated in place to those of the initial state.  Returns mbar."""
+        t = self.torch
+        if pos_ckpt.dtype != t.float64 or pos_ckpt.dim() != 3 or pos_ckpt.shape[1] != 3:
+            raise ValueError("pos_ckpt must be a (S+1, 3, N) float64 tensor")
+        pos_ckpt = pos_ckpt.contiguous()
+        n = pos_ckpt.shape[2]
+        _, mass = self._check_inputs(pos_ckpt[0], mass)
+        for name, a, dt_ in (("xbar", xbar, t.float64), ("vbar", vbar, self.dtype)):
+            if a.dtype != dt_ or a.shape != (3, n) or not a.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous (3, N) {dt_} tensor")
+        mbar = t.empty(n, dtype=self.dtype, device=self.device)
+        s = self._stream()
 
         def run(ws):
-            return self.L.hot_kdk(self.h, n, C.c_void_p(pos.data_ptr()),
-                                  C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
-                                  C.c_void_p(acc.data_ptr()),
-                                  C.c_void_p(pot.data_ptr() if pot is not None else 0),
-                                  float(dt), int(nsteps), flags, C.c_void_p(ws.data_ptr()),
-                                  ws.numel(), s)
+            return self.L.hot_kdk_vjp(self.h, n, pos_ckpt.shape[0] - 1,
+                                      C.c_void_p(pos_ckpt.data_ptr()),
+                                      C.c_void_p(mass.data_ptr()), float(dt),
+                                      C.c_void_p(xbar.data_ptr()), C.c_void_p(vbar.data_ptr()),
+                                      C.c_void_p(mbar.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                      ws.numel(), s)
         self._call_retry(run, n)
+        return mbar
 
     def vjp(self, pos, mass, gacc, gpot=None):
         """(xbar[3,N] FP64, mbar[N]) for cotangents of (acc, pot)."""
@@ -290,6 +328,57 @@ def _autograd():
 
 
 _GF = None
+_CK = None
+
+
+def _checkpointed():
+    import torch
+
+    class CheckpointedKDK(torch.autograd.Function):
+        """(pos_n, vel_n) = CheckpointedKDK.apply(gravity, pos0, vel0, mass,
+        dt, nsteps): nsteps leapfrog steps that keep only the positions of
+        every step for the backward pass (hot_kdk_vjp rebuilds each tree)."""
+
+        @staticmethod
+        def forward(ctx, grav, pos0, vel0, mass, dt, nsteps):
+            pos = pos0.detach().clone().contiguous()
+            vel = vel0.detach().to(grav.dtype).clone().contiguous()
+            mass_d = mass.detach()
+            ck = torch.empty((nsteps + 1,) + tuple(pos.shape), dtype=torch.float64,
+                             device=pos.device)
+            ck[0].copy_(pos)
+            acc = torch.empty_like(vel)
+            grav.kdk(pos, vel, mass_d, acc, dt, 0, acc_valid=False)
+            for k in range(nsteps):
+                grav.kdk(pos, vel, mass_d, acc, dt, 1, acc_valid=True)
+                ck[k + 1].copy_(pos)
+            ctx.grav, ctx.dt = grav, float(dt)
+            ctx.save_for_backward(ck, mass_d)
+            return pos, vel
+
+        @staticmethod
+        def backward(ctx, gpos, gvel):
+            ck, mass = ctx.saved_tensors
+            grav = ctx.grav
+            xbar = (gpos.to(torch.float64).clone() if gpos is not None
+                    else torch.zeros(ck.shape[1:], dtype=torch.float64, device=ck.device))
+            vbar = (gvel.to(grav.dtype).clone() if gvel is not None
+                    else torch.zeros(ck.shape[1:], dtype=grav.dtype, device=ck.device))
+            xbar = xbar.contiguous()
+            vbar = vbar.contiguous()
+            mbar = grav.kdk_vjp(ck, mass, ctx.dt, xbar, vbar)
+            return None, xbar, vbar, mbar, None, None
+
+    return CheckpointedKDK
+
+
+def checkpointed_kdk(grav: Gravity, pos0, vel0, mass, dt: float, nsteps: int):
+    """Differentiable nsteps-step leapfrog trajectory with per-step
+    checkpointing: (pos_n, vel_n) with gradients to pos0, vel0 and mass."""
+    global _CK
+    if _CK is None:
+        _CK = _checkpointed()
+    return _CK.apply(grav, pos0, vel0, mass, dt, int(nsteps))
 
 
 def gravity_forces(grav: Gravity, pos, mass):

@@ -3,12 +3,12 @@ for sampled targets of the 128^3 Zel'dovich workload.
 
 Calls only the oracle (and the seeded workload generator):
   * ``near_far``  -- the theta=0 tree result (27-image softened direct sum plus
-    the order-8 far-field expansion) on 256 evenly spaced targets: the
+    the order-8 far-field expansion) on 10^4 evenly spaced targets: the
     reference for the rms force error of the tree at a given opening angle;
   * ``ewald``     -- the exact periodic direct sum (Ewald split) on the first
-    32 of them: measures the far-field truncation floor at this size.
+    64 of them: measures the far-field truncation floor at this size.
 
-Usage: python tests/golden/make_zeldovich128_ref.py  (about a minute on 8 cores)
+Usage: python tests/golden/make_zeldovich128_ref.py  (about 12 minutes on 8 cores)
 """
 import os
 import sys
@@ -21,21 +21,24 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import workloads  # noqa: E402
 
+NT = 10000  # near_far targets
+NE = 64     # Ewald targets
+
 
 def main():
     pos, mass, prm = workloads.make("zeldovich128")
     n = pos.shape[1]
-    targets = np.arange(0, n, n // 256, dtype=np.int64)[:256]
+    targets = np.arange(0, n, n // NT, dtype=np.int64)[:NT]
     T = oracle.Tree(pos, mass, dict(prm, theta=0.0))
     acc_nf, pot_nf = T.direct_near_far(targets)
-    t32 = targets[:32]
-    acc_ew, pot_ew = oracle.direct_ewald(pos, mass, prm, targets=t32)
+    t_ew = targets[:NE]
+    acc_ew, pot_ew = oracle.direct_ewald(pos, mass, prm, targets=t_ew)
     out = os.path.join(HERE, "zeldovich128_ref.npz")
     np.savez(out, targets=targets, acc_near_far=acc_nf, pot_near_far=pot_nf,
-             targets_ewald=t32, acc_ewald=acc_ew, pot_ewald=pot_ew,
+             targets_ewald=t_ew, acc_ewald=acc_ew, pot_ewald=pot_ew,
              far_order=prm["far_order"], eps=prm["eps"])
-    e = oracle.rms_rel_error(acc_nf[:, :32], acc_ew)
-    print(f"wrote {out}; far-field floor (near_far vs Ewald, 32 targets): {e:.3e}")
+    e = oracle.rms_rel_error(acc_nf[:, :NE], acc_ew)
+    print(f"wrote {out}; far-field floor (near_far vs Ewald, {NE} targets): {e:.3e}")
 
 
 if __name__ == "__main__":

@@ -155,13 +155,16 @@ WORKLOADS = {
 }
 
 
-def make(name: str, n_side: int | None = None, box: float = 1.0):
+def make(name: str, n_side: int | None = None, box: float = 1.0, seed: int | None = None):
     """Return (pos[3,N] float64, mass[N] float64, params dict) for a workload.
 
     ``n_side`` overrides the size (same recipe, smaller or larger grid), which
-    the tests use to get cases the oracle finishes in seconds.
+    the tests use to get cases the oracle finishes in seconds; ``seed``
+    overrides the workload's seed (a second realisation of the same recipe).
     """
     spec = dict(WORKLOADS[name])
+    if seed is not None:
+        spec["seed"] = int(seed)
     ns = n_side or spec["n_side"]
     kind = spec["kind"]
     if kind == "lattice":
