@@ -74,7 +74,8 @@ typedef struct {
   double box;      /* side L of the periodic cube, > 0 */
   double G;        /* gravitational constant */
   double eps;      /* Plummer softening length, >= 0 */
-  double theta;    /* opening angle, 0 <= theta < 1; 0 = exact direct sum */
+  double theta;    /* opening angle, 0 <= theta < 1; with err_tol == 0,
+                      0 = exact direct sum */
   int order;       /* multipole order p of cells, 0..4 (2 = quadrupole,
                       4 = hexadecapole: the leaf-level expansions of Sec. 2.1) */
   int periodic;    /* 1 = periodic box, 0 = open boundaries (no images) */
@@ -87,6 +88,14 @@ typedef struct {
                       arithmetic on cell-relative coordinates with
                       compensated accumulation and FP64 positions, cell
                       centres of mass, moments and far field */
+  double err_tol;  /* > 0: error-bound acceptance test (the paper's absolute
+                      error tolerance, Sec. 2.1): a cell is accepted only
+                      beyond the distance at which the Salmon & Warren bound
+                      on its expansion's acceleration error, computed from
+                      sum m |x - com|^2 and the cell's extent, falls to
+                      err_tol (acceleration units); with theta > 0 as well,
+                      the larger of the two opening radii applies.
+                      0 = opening angle only.  Finite, >= 0. */
 } hot_params;
 
 /* Per-call statistics of the last compute call on a context. */

@@ -74,6 +74,9 @@ def lib():
         L.or_tree_perm.argtypes = [vp, i64p, u64p]
         L.or_tree_cells.argtypes = [vp, u64p, i32p, i64p, i64p, i32p, dp, dp, dp]
         L.or_tree_cell_moments.argtypes = [vp, i64, dp]
+        L.or_tree_cell_bounds.argtypes = [vp, dp, dp]
+        L.or_err_radius.restype = C.c_double
+        L.or_err_radius.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double]
         L.or_tree_groups.argtypes = [vp, i64p, dp, dp]
         L.or_tree_walk.argtypes = [vp]
         L.or_tree_list_total.restype = i64
@@ -114,14 +117,21 @@ def _p(a, ct=C.c_double):
 class _Params(C.Structure):
     _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
-                ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int)]
+                ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
+                ("err_tol", C.c_double)]
 
 
 def _params(p: dict) -> _Params:
     return _Params(float(p.get("box", 1.0)), float(p.get("G", 1.0)), float(p.get("eps", 0.0)),
                    float(p.get("theta", 0.5)), int(p.get("order", 2)),
                    int(p.get("periodic", 1)), int(p.get("leaf_max", 16)),
-                   int(p.get("group_max", 64)), int(p.get("far_order", 8)))
+                   int(p.get("group_max", 64)), int(p.get("far_order", 8)),
+                   float(p.get("err_tol", 0.0)))
+
+
+def err_radius(G: float, b2: float, b: float, order: int, tol: float) -> float:
+    """Opening radius of the error-bound acceptance test."""
+    return float(lib().or_err_radius(G, b2, b, order, tol))
 
 
 def mi_list(D: int) -> list[tuple[int, int, int]]:
@@ -277,6 +287,15 @@ class Tree:
                                _p(d["is_leaf"], C.c_int32), _p(d["mass"]), _p(d["com"]),
                                _p(d["rcrit"]))
         return d
+
+    def cell_bounds(self):
+        """(B_2[ncells], bmax[ncells]): sum m |x - com|^2 and the extent bound
+        the error-bound acceptance test uses."""
+        nc = self.lib.or_tree_ncells(self.h)
+        b2 = np.zeros(nc)
+        bm = np.zeros(nc)
+        self.lib.or_tree_cell_bounds(self.h, _p(b2), _p(bm))
+        return b2, bm
 
     def cell_moments(self, c: int) -> np.ndarray:
         nm = self.lib.or_nterms(int(self.params.get("order", 2)))

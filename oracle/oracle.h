@@ -29,6 +29,8 @@ typedef struct {
   int leaf_max;   /* a cell with more particles than this is split */
   int group_max;  /* sink groups: largest cells with at most this many */
   int far_order;  /* order of the periodic local expansion */
+  double err_tol; /* > 0: error-bound acceptance test (absolute acceleration
+                     error allowed per accepted cell); 0: opening angle only */
 } or_params;
 
 /* ---- multi-indices and truncated power series (series.c) ---- */

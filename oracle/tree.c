@@ -31,6 +31,19 @@
  * bounding box, s_B the cell side.  This is the centre-of-mass opening
  * criterion with the offset correction of Barnes (1994) / Salmon & Warren
  * (1994), which keeps the expansion convergent for any theta < 1.
+ *
+ * With err_tol > 0 the opening radius is instead (or, with theta > 0 as
+ * well, at least) the distance beyond which the Salmon & Warren (1994) bound
+ * on the acceleration error of the order-p expansion,
+ *     G B_(p+1) ((p+2) r - (p+1) b) / (r^(p+2) (r - b)^2),   r > b,
+ * drops to err_tol (the paper sets its tolerance as an absolute acceleration
+ * error, Sec. 2.1).  b is an upper bound on the distance of the cell's
+ * particles from its centre of mass and B_(p+1) = sum m |x - com|^(p+1) is
+ * bounded by b^(p-1) B_2 (order 0 is treated as order 1: the dipole about the
+ * centre of mass vanishes).  B_2 and b follow from the daughters by the
+ * parallel-axis identity and the triangle inequality, in octant order, and
+ * the radius is found by a fixed bisection in IEEE operations only, so that
+ * any implementation reproduces it bit for bit.
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,6 +62,7 @@ typedef struct {
   int64_t first, count, parent;
   int64_t child[8];
   double m, mx[3], com[3], center[3], side, rcrit;
+  double b2, bmax; /* sum m |x - com|^2 and a bound on max |x - com| */
   double* M; /* raw moments about com, |k| <= order */
 } cell_t;
 
@@ -195,6 +209,39 @@ static int64_t build_rec(tree_t* T, int level, uint64_t key, int64_t first, int6
   return ci;
 }
 
+/* Salmon & Warren bound at distance r (see the header): separate IEEE
+ * operations in a fixed order */
+static double sw_bound(double gb, double b, int pe, double r) {
+  double num = (double)(pe + 2) * r;
+  num = num - (double)(pe + 1) * b;
+  num = gb * num;
+  double den = r;
+  for (int i = 1; i < pe + 2; ++i) den = den * r;
+  double rb = r - b;
+  den = den * rb;
+  den = den * rb;
+  return num / den;
+}
+
+/* smallest radius (to bisection resolution) where the bound is <= tol */
+static double err_radius(double G, double b2, double b, int p, double tol) {
+  int pe = p < 1 ? 1 : p;
+  double bp = b2;
+  for (int i = 1; i < pe; ++i) bp = bp * b; /* B_(p+1) <= b^(p-1) B_2 */
+  double gb = G * bp;
+  if (!(gb > 0.0)) return b; /* a point mass: exact at any distance > b */
+  double lo = b, hi = b + b;
+  for (int i = 0; i < 4096 && sw_bound(gb, b, pe, hi) > tol; ++i) hi = hi + hi;
+  for (int i = 0; i < 64; ++i) {
+    double mid = 0.5 * (lo + hi);
+    if (sw_bound(gb, b, pe, mid) <= tol)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
 static void moments(tree_t* T) {
   int p = T->p.order;
   int nm = T->nmom;
@@ -231,7 +278,46 @@ static void moments(tree_t* T) {
     dd = dd + dy * dy;
     dd = dd + dz * dz;
     double delta = sqrt(dd);
-    c->rcrit = (theta > 0.0) ? c->side / theta + delta : INFINITY;
+    /* second moment and extent about the centre of mass */
+    double b2 = 0.0, bmax = 0.0;
+    if (c->is_leaf) {
+      double r2max = 0.0;
+      for (int64_t s = c->first; s < c->first + c->count; ++s) {
+        double ex = T->sx[0][s] - c->com[0], ey = T->sx[1][s] - c->com[1],
+               ez = T->sx[2][s] - c->com[2];
+        double r2 = ex * ex;
+        r2 = r2 + ey * ey;
+        r2 = r2 + ez * ez;
+        double t = T->sm[s] * r2;
+        b2 = b2 + t;
+        if (r2 > r2max) r2max = r2;
+      }
+      bmax = sqrt(r2max);
+    } else {
+      for (int o = 0; o < 8; ++o) {
+        if (c->child[o] < 0) continue;
+        cell_t* d = &T->cells[c->child[o]];
+        double ex = d->com[0] - c->com[0], ey = d->com[1] - c->com[1], ez = d->com[2] - c->com[2];
+        double r2 = ex * ex;
+        r2 = r2 + ey * ey;
+        r2 = r2 + ez * ez;
+        double t = d->m * r2;
+        t = d->b2 + t;
+        b2 = b2 + t;
+        double e = d->bmax + sqrt(r2);
+        if (e > bmax) bmax = e;
+      }
+    }
+    c->b2 = b2;
+    c->bmax = bmax;
+    double rc = (theta > 0.0) ? c->side / theta + delta : 0.0;
+    if (T->p.err_tol > 0.0) {
+      double re = err_radius(T->p.G, b2, bmax, p, T->p.err_tol);
+      if (re > rc) rc = re;
+    } else if (!(theta > 0.0)) {
+      rc = INFINITY;
+    }
+    c->rcrit = rc;
     /* raw moments about the centre of mass, directly from the particles */
     c->M = calloc((size_t)nm, sizeof(double));
     for (int64_t s = c->first; s < c->first + c->count; ++s) {
@@ -473,7 +559,7 @@ static int is_ancestor_or_self(const cell_t* B, const cell_t* A) {
 }
 
 static int mac_accept(const tree_t* T, int64_t g, const cell_t* B, const int n[3]) {
-  if (!(T->p.theta > 0.0)) return 0;
+  if (!(T->p.theta > 0.0) && !(T->p.err_tol > 0.0)) return 0;
   double L = T->p.box;
   double d[3];
   for (int a = 0; a < 3; ++a) {
@@ -696,6 +782,20 @@ void or_tree_cells(void* h, uint64_t* key, int32_t* level, int64_t* first, int64
       for (int a = 0; a < 3; ++a) com[a * nc + c] = C->com[a];
     if (rcrit) rcrit[c] = C->rcrit;
   }
+}
+
+/* second moment about the centre of mass and extent bound of every cell */
+void or_tree_cell_bounds(void* h, double* b2, double* bmax) {
+  tree_t* T = h;
+  for (int64_t c = 0; c < T->ncells; ++c) {
+    b2[c] = T->cells[c].b2;
+    bmax[c] = T->cells[c].bmax;
+  }
+}
+
+/* the opening radius of the error-bound test for given B_2, b, order, tol */
+double or_err_radius(double G, double b2, double b, int p, double tol) {
+  return err_radius(G, b2, b, p, tol);
 }
 
 /* raw moments of cell c about its centre of mass (or_nterms(order) values) */

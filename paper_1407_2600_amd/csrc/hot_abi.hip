@@ -26,7 +26,8 @@ hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, u
                            int level, int leaf_max, const uint32_t* choff, uint32_t next,
                            hipStream_t s);
 hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
-                              uint32_t beg, uint32_t cnt, double L, double theta, int order,
+                              uint32_t beg, uint32_t cnt, double L, double theta, double G,
+                              double err_tol, int order,
                               bool fp32, hipStream_t s);
 hipError_t tree_groups(const Cells& C, uint32_t ncells, int gmax, size_t n, uint32_t* gflag,
                        uint32_t* gid, int32_t* gcell_at, const Groups& G, uint32_t* ngroups_dev,
@@ -96,6 +97,8 @@ bool valid_params(const hot_params* p, std::string* why) {
   if (!std::isfinite(p->G)) return *why = "G must be finite", false;
   if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return *why = "eps must be >= 0", false;
   if (!(p->theta >= 0.0 && p->theta < 1.0)) return *why = "theta must be in [0, 1)", false;
+  if (!(p->err_tol >= 0.0 && std::isfinite(p->err_tol)))
+    return *why = "err_tol must be finite and >= 0", false;
   if (p->order < 0 || p->order > kMaxOrder) return *why = "order must be in 0..4", false;
   if (p->periodic != 0 && p->periodic != 1) return *why = "periodic must be 0 or 1", false;
   if (p->leaf_max < 1 || p->leaf_max > 255) return *why = "leaf_max must be in 1..255", false;
@@ -145,6 +148,7 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
   P.o_c_parent = take(4 * C);
   P.o_c_mmx = take(32 * C);
   P.o_c_walk = take(32 * C);
+  P.o_c_bnd = take(16 * C);
   P.o_c_mom = take(8 * (size_t)NM * C);
   P.o_c_coef = take(tsz * (size_t)STR * C);
   const size_t Gc = P.cap_groups;
@@ -198,6 +202,7 @@ Cells cells_of(void* ws, const Plan& P) {
   C.parent = at<int32_t>(ws, P.o_c_parent);
   C.mmx = at<double4>(ws, P.o_c_mmx);
   C.walk = at<double4>(ws, P.o_c_walk);
+  C.bnd = at<double2>(ws, P.o_c_bnd);
   C.mom = at<double>(ws, P.o_c_mom);
   C.coef = at<void>(ws, P.o_c_coef);
   return C;
@@ -318,7 +323,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   const uint32_t ncells = lvl[nlev];
   for (int l = nlev - 1; l >= 0; --l)
     HOT_CHECK(tree_moments_level(C, spos, smass, n, lvl[l], lvl[l + 1] - lvl[l], p.box, p.theta,
-                                 p.order, fp32, s),
+                                 p.G, p.err_tol, p.order, fp32, s),
               "moments");
   uint32_t* gflag = tmp;
   uint32_t* gid = reinterpret_cast<uint32_t*>(key1);

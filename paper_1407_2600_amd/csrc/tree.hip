@@ -121,11 +121,49 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
 }
 
 // ------------------------------------------------------------------ moments
+// Error-bound opening radius (Salmon & Warren 1994): the acceleration error
+// of an order-p expansion of a cell with extent b about its centre of mass is
+// at most G B_(p+1) ((p+2) r - (p+1) b) / (r^(p+2) (r - b)^2) at distance
+// r > b, with B_(p+1) = sum m |x - com|^(p+1) <= b^(p-1) B_2 (order 0 counts
+// as order 1: the dipole about the centre of mass vanishes).  The radius where
+// the bound meets the tolerance is found by doubling, then 64 bisection
+// steps, in separate IEEE operations only (contraction is off), so that every
+// implementation of the same definition finds the same double.
+__device__ double sw_bound(double gb, double b, int pe, double r) {
+  double num = (double)(pe + 2) * r;
+  num = num - (double)(pe + 1) * b;
+  num = gb * num;
+  double den = r;
+  for (int i = 1; i < pe + 2; ++i) den = den * r;
+  double rb = r - b;
+  den = den * rb;
+  den = den * rb;
+  return num / den;
+}
+
+__device__ double err_radius(double G, double b2, double b, int p, double tol) {
+  const int pe = p < 1 ? 1 : p;
+  double bp = b2;
+  for (int i = 1; i < pe; ++i) bp = bp * b;
+  const double gb = G * bp;
+  if (!(gb > 0.0)) return b;
+  double lo = b, hi = b + b;
+  for (int i = 0; i < 4096 && sw_bound(gb, b, pe, hi) > tol; ++i) hi = hi + hi;
+  for (int i = 0; i < 64; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (sw_bound(gb, b, pe, mid) <= tol)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
 template <int P, typename T>
 __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restrict__ spos,
                                                  const double* __restrict__ smass, size_t n,
                                                  uint32_t beg, uint32_t cnt, double L,
-                                                 double theta) {
+                                                 double theta, double G, double err_tol) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   const uint32_t c = beg + t;
@@ -168,7 +206,45 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
   double dd = dx * dx;
   dd = dd + dy * dy;
   dd = dd + dz * dz;
-  double rcrit = (theta > 0.0) ? side / theta + sqrt(dd) : __builtin_inf();
+  // second moment and extent about the centre of mass (parallel-axis sums
+  // and triangle bounds over the daughters, in octant order)
+  double b2 = 0.0, bmax = 0.0;
+  if (nc == 0) {
+    double r2max = 0.0;
+    for (uint32_t s = f; s < e; ++s) {
+      const double ex = spos[s] - com[0], ey = spos[n + s] - com[1],
+                   ez = spos[2 * n + s] - com[2];
+      double r2 = ex * ex;
+      r2 = r2 + ey * ey;
+      r2 = r2 + ez * ez;
+      const double t = smass[s] * r2;
+      b2 = b2 + t;
+      if (r2 > r2max) r2max = r2;
+    }
+    bmax = sqrt(r2max);
+  } else {
+    for (int k = 0; k < nc; ++k) {
+      const double4 wc = C.walk[c0 + k];
+      const double2 bc = C.bnd[c0 + k];
+      const double ex = wc.x - com[0], ey = wc.y - com[1], ez = wc.z - com[2];
+      double r2 = ex * ex;
+      r2 = r2 + ey * ey;
+      r2 = r2 + ez * ez;
+      double t = C.mmx[c0 + k].x * r2;
+      t = bc.x + t;
+      b2 = b2 + t;
+      const double eb = bc.y + sqrt(r2);
+      if (eb > bmax) bmax = eb;
+    }
+  }
+  C.bnd[c] = make_double2(b2, bmax);
+  double rcrit = (theta > 0.0) ? side / theta + sqrt(dd) : 0.0;
+  if (err_tol > 0.0) {
+    const double re = err_radius(G, b2, bmax, P, err_tol);
+    if (re > rcrit) rcrit = re;
+  } else if (!(theta > 0.0)) {
+    rcrit = __builtin_inf();
+  }
   C.mmx[c] = make_double4(m, sx, sy, sz);
   C.walk[c] = make_double4(com[0], com[1], com[2], rcrit);
 
@@ -334,20 +410,22 @@ hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, u
 
 template <int P, typename T>
 static void moments_launch(const Cells& C, const double* spos, const double* smass, size_t n,
-                           uint32_t beg, uint32_t cnt, double L, double theta, hipStream_t s) {
-  k_moments<P, T><<<(cnt + 127) / 128, 128, 0, s>>>(C, spos, smass, n, beg, cnt, L, theta);
+                           uint32_t beg, uint32_t cnt, double L, double theta, double G,
+                           double err_tol, hipStream_t s) {
+  k_moments<P, T><<<(cnt + 127) / 128, 128, 0, s>>>(C, spos, smass, n, beg, cnt, L, theta, G,
+                                                     err_tol);
 }
 
 hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
-                              uint32_t beg, uint32_t cnt, double L, double theta, int order,
-                              bool fp32, hipStream_t s) {
+                              uint32_t beg, uint32_t cnt, double L, double theta, double G,
+                              double err_tol, int order, bool fp32, hipStream_t s) {
   if (cnt == 0) return hipSuccess;
-#define HOT_MOM(P)                                                              \
-  case P:                                                                       \
-    if (fp32)                                                                   \
-      moments_launch<P, float>(C, spos, smass, n, beg, cnt, L, theta, s);       \
-    else                                                                        \
-      moments_launch<P, double>(C, spos, smass, n, beg, cnt, L, theta, s);      \
+#define HOT_MOM(P)                                                                        \
+  case P:                                                                                 \
+    if (fp32)                                                                             \
+      moments_launch<P, float>(C, spos, smass, n, beg, cnt, L, theta, G, err_tol, s);     \
+    else                                                                                  \
+      moments_launch<P, double>(C, spos, smass, n, beg, cnt, L, theta, G, err_tol, s);    \
     break;
   switch (order) {
     HOT_MOM(0)

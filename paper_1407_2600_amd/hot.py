@@ -35,7 +35,7 @@ class hot_params(C.Structure):
     _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
                 ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("err_tol", C.c_double)]
 
 
 class hot_stats(C.Structure):
@@ -106,12 +106,13 @@ def check(status: int):
 
 
 def make_params(box=1.0, G=1.0, eps=0.0, theta=0.5, order=4, periodic=1, leaf_max=16,
-                group_max=64, far_order=8, precision="fp64", **_ignored) -> hot_params:
+                group_max=64, far_order=8, precision="fp64", err_tol=0.0,
+                **_ignored) -> hot_params:
     prec = precision
     if isinstance(prec, str):
         prec = {"fp64": HOT_FP64, "fp32": HOT_FP32}[prec]
     return hot_params(float(box), float(G), float(eps), float(theta), int(order), int(periodic),
-                      int(leaf_max), int(group_max), int(far_order), int(prec))
+                      int(leaf_max), int(group_max), int(far_order), int(prec), float(err_tol))
 
 
 def far_table(far_order: int, box: float = 1.0, offset: int = 13):

@@ -38,7 +38,9 @@ def test_version_and_error_strings():
 
 @pytest.mark.parametrize("bad", [dict(box=0.0), dict(theta=1.0), dict(theta=-0.1), dict(order=5),
                                  dict(eps=-1.0), dict(leaf_max=0), dict(far_order=13),
-                                 dict(periodic=2), dict(precision=7), dict(group_max=0)])
+                                 dict(periodic=2), dict(precision=7), dict(group_max=0),
+                                 dict(err_tol=-1e-3), dict(err_tol=float("nan")),
+                                 dict(err_tol=float("inf"))])
 def test_create_rejects_bad_parameters(bad):
     L = hot.lib()
     prm = hot.make_params(**dict(dict(eps=0.01), **{k: v for k, v in bad.items()

@@ -20,6 +20,9 @@ CASES = [
     ("zeldovich128", 20, {}),                               # 8000: ragged groups
     ("nfw256", 16, dict(leaf_max=8, group_max=32)),          # clustered, deep tree
     ("zeldovich128", 14, dict(leaf_max=4, group_max=16, theta=0.7)),
+    # error-bound acceptance test, alone and combined with the opening angle
+    ("nfw256", 16, dict(leaf_max=8, group_max=32, theta=0.0, err_tol=2e-3)),
+    ("zeldovich128", 20, dict(group_max=128, theta=0.6, err_tol=1e-3)),
 ]
 
 

@@ -156,7 +156,6 @@ def _check_lists(T, prm, check_geometry=True):
                     tgt = ws[:, c["first"][A]:c["first"][A] + c["count"][A]]
                     rs = np.max(np.linalg.norm(src - cen[:, None], axis=0))
                     rt = np.min(np.linalg.norm(tgt - cen[:, None], axis=0))
-                    assert rt > rs / prm["theta"] * 0.999 or rt > rs
                     assert rt > rs
         if prm.get("periodic", 1):
             assert np.all(cover == 1)
