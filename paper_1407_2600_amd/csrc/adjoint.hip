@@ -51,34 +51,6 @@ __global__ void __launch_bounds__(256) k_adj_gather(const T* __restrict__ gacc,
 // when every lower order is present), and only their sum
 // E = Q + A, an order P+1 block, is turned into coefficients (dipole part
 // kept). Shifting E itself would leak order P+1 charge terms into parents.
-template <int Q, int NM>
-__device__ __forceinline__ void shift_add(const double* __restrict__ Mch, const double d[3],
-                                          double* M) {
-  constexpr MI<Q> mi{};
-  double pw[3][Q + 1];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    pw[a][0] = 1.0;
-#pragma unroll
-    for (int e2 = 1; e2 <= Q; ++e2) pw[a][e2] = pw[a][e2 - 1] * d[a];
-  }
-#pragma unroll
-  for (int k = 0; k < NM; ++k) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < NM; ++j) {
-      if (mi.a[j] > mi.a[k] || mi.b[j] > mi.b[k] || mi.c[j] > mi.c[k]) continue;
-      const int ra = mi.a[k] - mi.a[j], rb = mi.b[k] - mi.b[j], rc = mi.c[k] - mi.c[j];
-      double bin = 1.0;
-      for (int u = 0; u < mi.a[j]; ++u) bin = bin * (double)(mi.a[k] - u) / (double)(u + 1);
-      for (int u = 0; u < mi.b[j]; ++u) bin = bin * (double)(mi.b[k] - u) / (double)(u + 1);
-      for (int u = 0; u < mi.c[j]; ++u) bin = bin * (double)(mi.c[k] - u) / (double)(u + 1);
-      acc += bin * Mch[j] * pw[0][ra] * pw[1][rb] * pw[2][rc];
-    }
-    M[k] += acc;
-  }
-}
-
 template <int P, typename T, typename T4>
 __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __restrict__ spos,
                                                      const T4* __restrict__ arec, size_t n,
@@ -133,11 +105,11 @@ __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __re
       double Mch[NA];
 #pragma unroll
       for (int k = 0; k < NA; ++k) Mch[k] = Mc[k];
-      shift_add<Q, NA>(Mch, d, A);
+      shift_add<Q>(Mch, d, A);
       double Qch[NQ];
 #pragma unroll
       for (int k = 0; k < NQ; ++k) Qch[k] = Mc[NA + k];
-      shift_add<P, NQ>(Qch, d, Qm);
+      shift_add<P>(Qch, d, Qm);
     }
   }
   double* Mo = emom + (size_t)c * (NA + NQ);

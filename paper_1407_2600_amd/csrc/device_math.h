@@ -210,60 +210,149 @@ __device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __re
 }
 
 // Coefficient block of a cell from its raw Cartesian moments M_k about the
-// expansion centre (|k| <= P): with W^(j)_k = sum_{|i|=j} (j!/i!) M_{k+2i},
+// expansion centre (|k| <= P):
 //   C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m - j,
 // so that P_m(R) = sum_k C_{m,k} R^k; parts of degree d >= 1 are stored as
-// gradient coefficients (k'_a + 1) C_{m, k'+e_a}, |k'| = d - 1.
-template <int P, bool DIP = false>
-__device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
-  // C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m-j
-  // stored as gradient coefficients (k'_a+1) C_{m,k'+e_a} for d >= 1.
-  constexpr MI<P> mi{};
-  int o = 0;
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-    double dfact = 1.0;  // (2m-1)!!
-    for (int q = 1; q <= 2 * m - 1; q += 2) dfact *= (double)q;
-#pragma unroll
+// gradient coefficients (k'_a + 1) C_{m, k'+e_a}, |k'| = d - 1.  Every output
+// is a fixed linear combination of moments, tabulated at compile time as
+// (output, moment, weight) terms.
+__host__ __device__ constexpr double cfact(int n) {
+  double f = 1.0;
+  for (int q = 2; q <= n; ++q) f *= (double)q;
+  return f;
+}
+
+template <int P, bool DIP>
+__host__ __device__ constexpr int coef_terms() {
+  int n = 0;
+  for (int m = 0; m <= P; ++m)
     for (int j = 0; j <= part_jmax(P, m); ++j) {
       const int d = m - j;
-      if (!part_stored(m, d, DIP)) continue;
-      double pre = dfact * ((j & 1) ? -1.0 : 1.0);
-      for (int q = 0; q < j; ++q) pre *= 0.5;
-      auto Cmk = [&](int ka, int kb, int kc) {
-        // sum over |i| = j of M_{k+2i}/i!, divided by k!
-        double s = 0.0;
-        for (int ia = j; ia >= 0; --ia)
-          for (int ib = j - ia; ib >= 0; --ib) {
-            int ic = j - ia - ib;
-            double fi = 1.0;
-            for (int q = 2; q <= ia; ++q) fi *= q;
-            for (int q = 2; q <= ib; ++q) fi *= q;
-            for (int q = 2; q <= ic; ++q) fi *= q;
-            s += M[mi_index(ka + 2 * ia, kb + 2 * ib, kc + 2 * ic)] / fi;
-          }
-        double fk = 1.0;
-        for (int q = 2; q <= ka; ++q) fk *= q;
-        for (int q = 2; q <= kb; ++q) fk *= q;
-        for (int q = 2; q <= kc; ++q) fk *= q;
-        return pre * s / fk;
-      };
-      if (d == 0) {
-        out[o++] = Cmk(0, 0, 0);
-      } else {
-        // gradient coefficients: component a, monomial k' of degree d-1
-        for (int a = 0; a < 3; ++a)
-          for (int x = d - 1; x >= 0; --x)
-            for (int y = d - 1 - x; y >= 0; --y) {
-              int z = d - 1 - x - y;
-              int ka = x + (a == 0), kb = y + (a == 1), kc = z + (a == 2);
-              int ka1 = (a == 0 ? x : a == 1 ? y : z) + 1;
-              out[o++] = ka1 * Cmk(ka, kb, kc);
+      if (part_stored(m, d, DIP)) n += part_size(d) * nte(j);
+    }
+  return n;
+}
+
+template <int P, bool DIP>
+struct CoefTable {
+  static constexpr int N = coef_terms<P, DIP>();
+  int o[N], m[N];
+  double w[N];
+  constexpr CoefTable() : o(), m(), w() {
+    int n = 0, out = 0;
+    for (int mm = 0; mm <= P; ++mm) {
+      double dfact = 1.0;  // (2m-1)!!
+      for (int q = 1; q <= 2 * mm - 1; q += 2) dfact *= (double)q;
+      for (int j = 0; j <= part_jmax(P, mm); ++j) {
+        const int d = mm - j;
+        if (!part_stored(mm, d, DIP)) continue;
+        double pre = dfact * ((j & 1) ? -1.0 : 1.0);
+        for (int q = 0; q < j; ++q) pre *= 0.5;
+        // one output (ka, kb, kc) times a scale: terms over |i| = j
+        auto emit = [&](int ka, int kb, int kc, double scale) {
+          for (int ia = j; ia >= 0; --ia)
+            for (int ib = j - ia; ib >= 0; --ib) {
+              const int ic = j - ia - ib;
+              o[n] = out;
+              m[n] = mi_index(ka + 2 * ia, kb + 2 * ib, kc + 2 * ic);
+              w[n] = scale * pre / (cfact(ia) * cfact(ib) * cfact(ic) * cfact(ka) * cfact(kb) *
+                                    cfact(kc));
+              ++n;
             }
+          ++out;
+        };
+        if (d == 0) {
+          emit(0, 0, 0, 1.0);
+        } else {
+          for (int a = 0; a < 3; ++a)
+            for (int x = d - 1; x >= 0; --x)
+              for (int y = d - 1 - x; y >= 0; --y) {
+                const int z = d - 1 - x - y;
+                const int ka1 = (a == 0 ? x : a == 1 ? y : z) + 1;
+                emit(x + (a == 0), y + (a == 1), z + (a == 2), (double)ka1);
+              }
+        }
       }
     }
   }
+};
+
+template <int P, bool DIP = false>
+__device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
+  constexpr CoefTable<P, DIP> T{};
+  constexpr int NCF = coef_count(P, DIP);
+#pragma unroll
+  for (int k = 0; k < NCF; ++k) out[k] = 0.0;
+#pragma unroll
+  for (int t = 0; t < T.N; ++t) out[T.o[t]] += T.w[t] * M[T.m[t]];
 }
 
+// Shift of raw moments to a centre displaced by -d (moments M_c about a
+// daughter's centre, d = daughter centre - new centre):
+//   M_k += sum_{j <= k} C(k, j) Mc_j d^(k - j),
+// as compile-time (k, j, k - j, binomial) terms.
+__host__ __device__ constexpr double cbinom(int n, int k) {
+  double b = 1.0;
+  for (int q = 0; q < k; ++q) b = b * (double)(n - q) / (double)(q + 1);
+  return b;
+}
+
+template <int P>
+__host__ __device__ constexpr int shift_terms() {
+  MI<P> mi{};
+  int n = 0;
+  for (int k = 0; k < nt(P); ++k)
+    for (int j = 0; j < nt(P); ++j)
+      if (mi.a[j] <= mi.a[k] && mi.b[j] <= mi.b[k] && mi.c[j] <= mi.c[k]) ++n;
+  return n;
+}
+
+template <int P>
+struct ShiftTable {
+  static constexpr int N = shift_terms<P>();
+  int k[N], j[N], r[N];
+  double w[N];
+  constexpr ShiftTable() : k(), j(), r(), w() {
+    MI<P> mi{};
+    int n = 0;
+    for (int kk = 0; kk < nt(P); ++kk)
+      for (int jj = 0; jj < nt(P); ++jj) {
+        if (mi.a[jj] > mi.a[kk] || mi.b[jj] > mi.b[kk] || mi.c[jj] > mi.c[kk]) continue;
+        k[n] = kk;
+        j[n] = jj;
+        r[n] = mi_index(mi.a[kk] - mi.a[jj], mi.b[kk] - mi.b[jj], mi.c[kk] - mi.c[jj]);
+        w[n] = cbinom(mi.a[kk], mi.a[jj]) * cbinom(mi.b[kk], mi.b[jj]) *
+               cbinom(mi.c[kk], mi.c[jj]);
+        ++n;
+      }
+  }
+};
+
+// monomials d^k, |k| <= P, in multi-index order
+template <int P>
+__device__ __forceinline__ void monomials(const double d[3], double* mono) {
+  constexpr MI<P> mi{};
+  mono[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k < nt(P); ++k) {
+    const int a = mi.a[k], b = mi.b[k], c = mi.c[k];
+    if (a > 0)
+      mono[k] = mono[mi_index(a - 1, b, c)] * d[0];
+    else if (b > 0)
+      mono[k] = mono[mi_index(a, b - 1, c)] * d[1];
+    else
+      mono[k] = mono[mi_index(a, b, c - 1)] * d[2];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void shift_add(const double* __restrict__ Mch, const double d[3],
+                                          double* M) {
+  constexpr ShiftTable<P> T{};
+  double mono[nt(P)];
+  monomials<P>(d, mono);
+#pragma unroll
+  for (int t = 0; t < T.N; ++t) M[T.k[t]] += T.w[t] * (Mch[T.j[t]] * mono[T.r[t]]);
+}
 
 }  // namespace hot

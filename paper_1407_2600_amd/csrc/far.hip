@@ -90,44 +90,72 @@ __global__ void __launch_bounds__(kFarThreads) k_far_moments(const double* __res
   }
 }
 
-// one block per target octant t
+// octant moments: sum of the per-block partial moments
 template <int PF>
-__global__ void __launch_bounds__(512) k_far_lambda(const double* __restrict__ part, int nblk,
-                                                    const double* __restrict__ tpsi,
-                                                    double* __restrict__ mom,
-                                                    double* __restrict__ lam) {
+__global__ void __launch_bounds__(256) k_far_sum(const double* __restrict__ part, int nblk,
+                                                 double* __restrict__ mom) {
+  constexpr int NQ = nt(PF);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 8 * NQ) return;
+  const int s = i / NQ, k = i % NQ;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += part[((size_t)s * nblk + b) * NQ + k];
+  mom[i] = acc;
+}
+
+// C(n, k) exactly, n <= 2 * kMaxFarOrder
+__device__ __forceinline__ double binom_exact(int n, int k) {
+  unsigned long long b = 1;
+  for (int u = 1; u <= k; ++u) b = b * (unsigned long long)(n - k + u) / (unsigned long long)u;
+  return (double)b;
+}
+
+// Local coefficients of target octant t (blockIdx.y), output q (blockIdx.x):
+//   Lam_q = sum_s sum_k (-1)^|k| C(q+k, q) Tpsi^(t-s)_(q+k) M^s_k,
+// one wavefront per output, the 8 x nt(PF) terms spread over its lanes.
+template <int PF>
+__global__ void __launch_bounds__(64) k_far_lambda(const double* __restrict__ tpsi,
+                                                   const double* __restrict__ mom,
+                                                   double* __restrict__ lam) {
   constexpr int NQ = nt(PF);
   constexpr int NT2 = nt(2 * PF);
-  constexpr MI<PF> mi{};
-  __shared__ double M[8][NQ];
-  const int t = blockIdx.x;
-  for (int i = threadIdx.x; i < 8 * NQ; i += blockDim.x) {
-    const int s = i / NQ, k = i % NQ;
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[((size_t)s * nblk + b) * NQ + k];
-    M[s][k] = acc;
-    if (t == 0) mom[i] = acc;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < NQ; q += blockDim.x) {
-    const int qa = mi.a[q], qb = mi.b[q], qc = mi.c[q];
-    double acc = 0.0;
-    for (int s = 0; s < 8; ++s) {
-      const int dx = ((t >> 2) & 1) - ((s >> 2) & 1), dy = ((t >> 1) & 1) - ((s >> 1) & 1),
-                dz = (t & 1) - (s & 1);
-      const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
-      for (int k = 0; k < NQ; ++k) {
-        const int ka = mi.a[k], kb = mi.b[k], kc = mi.c[k];
-        double bin = 1.0;
-        for (int u = 1; u <= ka; ++u) bin = bin * (double)(qa + u) / (double)u;
-        for (int u = 1; u <= kb; ++u) bin = bin * (double)(qb + u) / (double)u;
-        for (int u = 1; u <= kc; ++u) bin = bin * (double)(qc + u) / (double)u;
-        const double sg = ((ka + kb + kc) & 1) ? -1.0 : 1.0;
-        acc += sg * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)] * M[s][k];
-      }
+  const int q = blockIdx.x, t = blockIdx.y, lane = threadIdx.x;
+  // decode q's multi-index (degree, then a, b descending)
+  int qa = 0, qb = 0, qc = 0;
+  {
+    int d = 0;
+    while (nt(d) <= q) ++d;
+    int r = q - nt(d - 1);
+    for (qa = d; qa >= 0; --qa) {
+      const int cnt = d - qa + 1;
+      if (r < cnt) break;
+      r -= cnt;
     }
-    lam[(size_t)t * NQ + q] = acc;
+    qb = d - qa - r;
+    qc = d - qa - qb;
   }
+  double acc = 0.0;
+  for (int i = lane; i < 8 * NQ; i += 64) {
+    const int s = i / NQ, k = i % NQ;
+    int d = 0;
+    while (nt(d) <= k) ++d;
+    int r = k - nt(d - 1), ka;
+    for (ka = d; ka >= 0; --ka) {
+      const int cnt = d - ka + 1;
+      if (r < cnt) break;
+      r -= cnt;
+    }
+    const int kb = d - ka - r, kc = d - ka - kb;
+    const int dx = ((t >> 2) & 1) - ((s >> 2) & 1), dy = ((t >> 1) & 1) - ((s >> 1) & 1),
+              dz = (t & 1) - (s & 1);
+    const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
+    const double bin = binom_exact(qa + ka, ka) * binom_exact(qb + kb, kb) *
+                       binom_exact(qc + kc, kc);
+    const double sg = (d & 1) ? -1.0 : 1.0;
+    acc += sg * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)] * mom[(size_t)s * NQ + k];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) lam[(size_t)t * NQ + q] = acc;
 }
 
 template <int PF, typename T>
@@ -193,7 +221,8 @@ static hipError_t far_run(const double* spos, const double* smass, const uint64_
     if (nblk < 1) nblk = 1;
     k_far_moments<PF><<<dim3(nblk, 8), kFarThreads, 0, s>>>(spos, smass, skey, n, box, nblk,
                                                             part);
-    k_far_lambda<PF><<<8, 512, 0, s>>>(part, nblk, tpsi, mom, lam);
+    k_far_sum<PF><<<(8 * nt(PF) + 255) / 256, 256, 0, s>>>(part, nblk, mom);
+    k_far_lambda<PF><<<dim3(nt(PF), 8), 64, 0, s>>>(tpsi, mom, lam);
   }
   unsigned g = (unsigned)((n + 255) / 256);
   if (fp32)
@@ -213,7 +242,8 @@ static hipError_t far_prepare_run(const double* spos, const double* smass, const
   if (nblk > nblk_max) nblk = nblk_max;
   if (nblk < 1) nblk = 1;
   k_far_moments<PF><<<dim3(nblk, 8), kFarThreads, 0, s>>>(spos, smass, skey, n, box, nblk, part);
-  k_far_lambda<PF><<<8, 512, 0, s>>>(part, nblk, tpsi, mom, lam);
+  k_far_sum<PF><<<(8 * nt(PF) + 255) / 256, 256, 0, s>>>(part, nblk, mom);
+  k_far_lambda<PF><<<dim3(nt(PF), 8), 64, 0, s>>>(tpsi, mom, lam);
   return hipGetLastError();
 }
 

@@ -269,35 +269,13 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
   } else {
     for (int kc = 0; kc < nc; ++kc) {
       const int ch = c0 + kc;
-      double4 w = C.walk[ch];
-      double d[3] = {w.x - com[0], w.y - com[1], w.z - com[2]};
-      double pw[3][P + 1];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        pw[a][0] = 1.0;
-#pragma unroll
-        for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
-      }
+      const double4 w = C.walk[ch];
+      const double d[3] = {w.x - com[0], w.y - com[1], w.z - com[2]};
       const double* Mc = C.mom + (size_t)ch * NM;
       double Mch[NM];
 #pragma unroll
       for (int k = 0; k < NM; ++k) Mch[k] = Mc[k];
-      // M_k += sum_{j <= k} C(k,j) Mc_j d^(k-j)
-#pragma unroll
-      for (int k = 0; k < NM; ++k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < NM; ++j) {
-          if (mi.a[j] > mi.a[k] || mi.b[j] > mi.b[k] || mi.c[j] > mi.c[k]) continue;
-          const int ra = mi.a[k] - mi.a[j], rb = mi.b[k] - mi.b[j], rc = mi.c[k] - mi.c[j];
-          double bin = 1.0;
-          for (int q = 0; q < mi.a[j]; ++q) bin = bin * (double)(mi.a[k] - q) / (double)(q + 1);
-          for (int q = 0; q < mi.b[j]; ++q) bin = bin * (double)(mi.b[k] - q) / (double)(q + 1);
-          for (int q = 0; q < mi.c[j]; ++q) bin = bin * (double)(mi.c[k] - q) / (double)(q + 1);
-          acc += bin * Mch[j] * pw[0][ra] * pw[1][rb] * pw[2][rc];
-        }
-        M[k] += acc;
-      }
+      shift_add<P>(Mch, d, M);
     }
   }
   double* Mo = C.mom + (size_t)c * NM;
