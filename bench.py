@@ -61,6 +61,27 @@ THETA_CAPS = (0.0, 0.6, 0.7, 0.8)
 THETA_GRID = (0.40, 0.44, 0.46, 0.47, 0.48, 0.50)
 REF_PATH = os.path.join(ROOT, "tests", "golden", "zeldovich128_ref.npz")
 
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE/WRITE_SIZE
+# counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
+# They hold only for the sources and the configuration they were taken with;
+# otherwise the roofline reports traffic as null.
+TRAFFIC = {"kernel": "k_m2p<4,float>", "bytes_per_launch": 5.988e9,
+           "config": {"theta": 0.8, "err_tol": 0.005, "order": 4, "leaf_max": 16,
+                      "group_max": 128, "far_order": 8},
+           "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
+           "sha256": "f20ddf24872dce785ea8995949b2e1722dd6992c9ea8b5fd88773424c5162909"}
+
+
+def measured_traffic(prm):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1407_2600_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    same = h.hexdigest() == TRAFFIC["sha256"] and all(
+        prm.get(k) == v for k, v in TRAFFIC["config"].items())
+    return TRAFFIC["bytes_per_launch"] if same else None
+
 
 def rms_err(a, ref):
     return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))
@@ -236,7 +257,8 @@ def main():
     achieved = fl / (ms * 1e-3) / 1e12
     roof = {"kernel": f"k_m2p<{prm['order']},float>" if dom == "m2p" else "k_p2p<float>",
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": measured_traffic(prm) if dom == "m2p" and prm["order"] == 4 else None,
             "flops_per_launch": fl, "ms_per_launch": ms}
     other = "p2p" if dom == "m2p" else "m2p"
     roof_other = {"kernel": other, "achieved": r32["flops"][other] /
