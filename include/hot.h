@@ -29,7 +29,8 @@
  *    on the 27 nearest images and the unsoftened Ewald kernel (neutralising
  *    background) on all others; a particle's own periodic images contribute.
  *  - Scratch memory comes from the caller: every compute call takes a device
- *    workspace of at least hot_workspace_size(ctx, n) bytes, aligned to 256
+ *    workspace of at least hot_workspace_size_min(ctx, n) bytes (preferably
+ *    hot_workspace_size(ctx, n)), aligned to 256
  *    bytes.  The library never allocates device memory in a compute call; it
  *    owns only the context (parameters, the Ewald table, a few device
  *    constants), created by hot_create and released by hot_destroy.
@@ -41,8 +42,8 @@
  *  - Errors are status codes; nothing throws across the ABI.  A message for
  *    the last failure on the calling thread is in hot_last_error().  Inputs
  *    are never modified, except the in/out arrays of hot_kdk.
- *  - HOT_EOVERFLOW means a data-dependent capacity (cells or interaction
- *    lists) did not fit in the workspace.  The context records what was
+ *  - HOT_EOVERFLOW means a data-dependent capacity (cells, or the lists of a
+ *    single sink group) did not fit in the workspace.  The context records what was
  *    needed; call hot_workspace_size again (it now returns a larger size),
  *    allocate that much and repeat the call.  Nothing was written to outputs.
  *  - One context may be used by one host thread at a time.
@@ -119,6 +120,8 @@ typedef struct {
   double ms_far;          /* far field + unpermute */
   size_t ws_bytes_needed; /* workspace that would have sufficed */
   int64_t kdk_steps_done; /* steps hot_kdk completed in its last call */
+  int64_t list_chunks;    /* group ranges the interaction lists were processed
+                             in (1 unless they exceeded the list region) */
 } hot_stats;
 
 /* Host copies of the internal structures of the last hot_forces call, for
@@ -153,9 +156,17 @@ hot_status hot_create(const hot_params* params, hot_ctx** out);
 /* Release a context (NULL is allowed). */
 void hot_destroy(hot_ctx* ctx);
 
-/* Bytes of device workspace a compute call needs for n particles.  Grows
- * after a HOT_EOVERFLOW so that a retry fits.  0 if ctx is NULL. */
+/* Preferred bytes of device workspace for a compute call on n particles:
+ * room for all interaction lists at once (up to 4 GiB of lists).  Grows
+ * after a call that needed more, so the next call fits.  0 if ctx is NULL. */
 size_t hot_workspace_size(const hot_ctx* ctx, size_t n);
+
+/* Smallest workspace a compute call accepts for n particles: every per-
+ * particle and per-cell structure plus 1 MiB of list space.  Between this and
+ * hot_workspace_size the interaction lists are built and consumed in chunks
+ * of consecutive sink groups (paper Sec. 2.1: groups are independent), which
+ * gives the same results.  0 if ctx is NULL. */
+size_t hot_workspace_size_min(const hot_ctx* ctx, size_t n);
 
 /* Accelerations and potentials of n particles (paper Sec. 2.1: the force
  * evaluation of one timestep).

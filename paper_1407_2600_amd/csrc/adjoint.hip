@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
                                                             const T4* __restrict__ srec,
                                                             const T4* __restrict__ arec,
                                                             const T* __restrict__ ecoef, size_t n,
-                                                            const uint32_t* __restrict__ list,
+                                                            const uint4* __restrict__ list,
                                                             double4* __restrict__ out) {
   constexpr int STR = coef_stride(P);
   constexpr int ESTR = coef_stride(P + 1, true);
@@ -258,13 +258,9 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
     acc.zero();
     T part[4] = {0, 0, 0, 0};
     for (uint32_t q = 0; q < cnt; ++q) {
-      const uint32_t e = list[off + q];
-      const int img = (int)(e >> 27);
-      const int B = (int)(e & kCellMask);
-      const double4 w = C.walk[B];
-      const T Rx = tx - (T)(w.x + (double)(img / 9 - 1) * L - cA[0]);
-      const T Ry = ty - (T)(w.y + (double)((img / 3) % 3 - 1) * L - cA[1]);
-      const T Rz = tz - (T)(w.z + (double)(img % 3 - 1) * L - cA[2]);
+      T c[3];
+      const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+      const T Rx = tx - c[0], Ry = ty - c[1], Rz = tz - c[2];
       // mass field and its derivative along gacc_k
       Dual<T> fm[4];
       m2p_eval<P, false, Dual<T>, T>(Dual<T>(Rx, ak.x), Dual<T>(Ry, ak.y), Dual<T>(Rz, ak.z),
@@ -348,7 +344,7 @@ hipError_t p2p_adj_launch(bool fp32, const Cells& C, const Groups& G, uint32_t n
 template <int P>
 static void m2p_adj_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
                       double eps, const double* spos, const void* srec, const void* arec,
-                      const void* ecoef, size_t n, const uint32_t* list, double4* out,
+                      const void* ecoef, size_t n, const uint4* list, double4* out,
                       hipStream_t s) {
   unsigned blocks = (ngroups + kAdjWaves - 1) / kAdjWaves;
   if (fp32)
@@ -363,7 +359,7 @@ static void m2p_adj_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngrou
 
 hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                           double L, double eps, const double* spos, const void* srec,
-                          const void* arec, const void* ecoef, size_t n, const uint32_t* list,
+                          const void* arec, const void* ecoef, size_t n, const uint4* list,
                           double4* out, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   switch (order) {

@@ -209,6 +209,29 @@ __device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __re
   out[3] = rinv * Pv;
 }
 
+// One multipole-list record (16 bytes): the (image << 27) | cell entry in w,
+// and in x, y, z the offset of the cell's image-shifted centre of mass from
+// the sink group's cell centre, evaluated in FP64 by the walk and rounded to
+// FP32 once.  FP32 kernels use that offset; FP64 kernels evaluate it again in
+// FP64 from the entry.
+template <typename T>
+__device__ __forceinline__ int m2p_record(const uint4 r, const double4* __restrict__ walk,
+                                          double L, const double cA[3], T c[3]) {
+  const int B = (int)(r.w & kCellMask);
+  if constexpr (sizeof(T) == 4) {
+    c[0] = __uint_as_float(r.x);
+    c[1] = __uint_as_float(r.y);
+    c[2] = __uint_as_float(r.z);
+  } else {
+    const int img = (int)(r.w >> 27);
+    const double4 w = walk[B];
+    c[0] = (T)(w.x + (double)(img / 9 - 1) * L - cA[0]);
+    c[1] = (T)(w.y + (double)((img / 3) % 3 - 1) * L - cA[1]);
+    c[2] = (T)(w.z + (double)(img % 3 - 1) * L - cA[2]);
+  }
+  return B;
+}
+
 // Coefficient block of a cell from its raw Cartesian moments M_k about the
 // expansion centre (|k| <= P):
 //   C_{m,k} = (2m-1)!! (-1)^j / (2^j k!) sum_{|i|=j} M_{k+2i} / i!,  |k| = m - j,

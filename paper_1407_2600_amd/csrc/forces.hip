@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
                                                           double L, T eps2,
                                                           const double* __restrict__ spos,
                                                           size_t n,
-                                                          const uint32_t* __restrict__ list,
+                                                          const uint4* __restrict__ list,
                                                           double4* __restrict__ out) {
   constexpr int STR = coef_stride(P);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -122,15 +122,10 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
     acc.zero();
     T part[4] = {0, 0, 0, 0};
     for (uint32_t q = 0; q < cnt; ++q) {
-      const uint32_t e = list[off + q];
-      const int img = (int)(e >> 27);
-      const int B = (int)(e & kCellMask);
-      const double4 w = C.walk[B];
-      const T cx = (T)(w.x + (double)(img / 9 - 1) * L - cA[0]);
-      const T cy = (T)(w.y + (double)((img / 3) % 3 - 1) * L - cA[1]);
-      const T cz = (T)(w.z + (double)(img % 3 - 1) * L - cA[2]);
+      T c[3];
+      const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
       T r[4];
-      m2p_eval<P, false, T, T>(tx - cx, ty - cy, tz - cz, eps2, coef + (size_t)B * STR, r);
+      m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, coef + (size_t)B * STR, r);
 #pragma unroll
       for (int k = 0; k < 3; ++k) part[k] += r[k];
       // the potential sums many same-signed terms that the far field later
@@ -170,7 +165,7 @@ hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngrou
 
 template <int P>
 static void m2p_launch_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
-                         double eps, const double* spos, size_t n, const uint32_t* list,
+                         double eps, const double* spos, size_t n, const uint4* list,
                          double4* out, hipStream_t s) {
   unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
   if (fp32)
@@ -182,7 +177,7 @@ static void m2p_launch_p(bool fp32, const Cells& C, const Groups& G, uint32_t ng
 }
 
 hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
-                      double L, double eps, const double* spos, size_t n, const uint32_t* list,
+                      double L, double eps, const double* spos, size_t n, const uint4* list,
                       double4* out, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   switch (order) {

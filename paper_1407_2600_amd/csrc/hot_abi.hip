@@ -38,14 +38,16 @@ hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const 
                      size_t n, double L, void* srec, bool fp32, hipStream_t s);
 hipError_t walk_launch(bool emit, const Cells& C, const Groups& G, uint32_t ngroups,
                        uint32_t gcap, double L, int periodic, uint32_t* p2p_list,
-                       uint32_t* m2p_list, uint32_t* status, hipStream_t s);
+                       uint4* m2p_list, uint32_t* status, hipStream_t s);
+hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
+                      hipStream_t s);
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* p2p_list,
                        unsigned long long* out, hipStream_t s);
 hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
                       double eps, const double* spos, const void* srec, size_t n,
                       const uint32_t* list, double4* out, hipStream_t s);
 hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
-                      double L, double eps, const double* spos, size_t n, const uint32_t* list,
+                      double L, double eps, const double* spos, size_t n, const uint4* list,
                       double4* out, hipStream_t s);
 hipError_t far_launch(int far_order, const double* spos, const double* smass,
                       const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx, double box, double G, const double* tpsi,
@@ -65,7 +67,7 @@ hipError_t p2p_adj_launch(bool fp32, const Cells& C, const Groups& G, uint32_t n
                           size_t n, const uint32_t* list, double4* out, hipStream_t s);
 hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                           double L, double eps, const double* spos, const void* srec,
-                          const void* arec, const void* ecoef, size_t n, const uint32_t* list,
+                          const void* arec, const void* ecoef, size_t n, const uint4* list,
                           double4* out, hipStream_t s);
 hipError_t far_adj_launch(int far_order, const double* spos, const double* smass,
                           const uint64_t* skey, const void* arec, const double4* near, size_t n,
@@ -90,7 +92,13 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
-       CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_N = 64 };
+       CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
+       CTR_MAXW = 16, CTR_READ = 20, CTR_N = 64 };
+// largest list region requested for one evaluation (4-byte words); larger
+// list sets are processed in chunks of consecutive groups
+constexpr size_t kListMaxWords = size_t(1) << 30;
+// smallest list region accepted (bytes)
+constexpr size_t kListMinBytes = size_t(1) << 20;
 
 bool valid_params(const hot_params* p, std::string* why) {
   if (!(p->box > 0.0) || !std::isfinite(p->box)) return *why = "box must be finite and > 0", false;
@@ -176,7 +184,8 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
   P.o_kv_sx = take(24 * n);
   P.o_kv_sv = take(3 * tsz * n);
   P.o_list = o;
-  const size_t want_list = (size_t)std::ceil(c->list_per_particle * (double)n) + 65536;
+  const size_t want_list =
+      std::min((size_t)std::ceil(c->list_per_particle * (double)n) + 65536, kListMaxWords);
   if (ws_bytes == 0) {
     P.cap_list = want_list;
   } else {
@@ -256,9 +265,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   const hot_params& p = c->p;
   const bool fp32 = p.precision == HOT_FP32;
   Plan P = make_plan(c, n, ws_bytes);
-  if (ws_bytes < P.total) {
-    g_err = "workspace too small: need " + std::to_string(P.total) + " bytes, got " +
-            std::to_string(ws_bytes);
+  if (ws_bytes < P.o_list + kListMinBytes) {
+    g_err = "workspace too small: need at least " + std::to_string(P.o_list + kListMinBytes) +
+            " bytes (" + std::to_string(P.total) + " preferred), got " + std::to_string(ws_bytes);
     c->stats.ws_bytes_needed = P.total;
     return HOT_ENOMEM;
   }
@@ -282,7 +291,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   uint32_t* host = c->host_buf;
 
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[0], s), "event");
-  HOT_CHECK(hipMemsetAsync(ctr, 0, 4 * CTR_N, s), "memset");
+  HOT_CHECK(zero_launch(ctr, 4 * CTR_N, s), "clear counters");
   HOT_CHECK(launch_keys(pos, n, p.box, c->S, key0, idx0, ctr + CTR_BAD, s), "keys");
   HOT_CHECK(radix_sort(key0, idx0, key1, idx1, n, at<uint32_t>(ws, P.o_hist), scan_tmp, s),
             "sort");
@@ -341,66 +350,121 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   HOT_CHECK(tree_group_bbox(C, G, ngroups, (uint32_t)P.cap_groups, spos, n, s), "bbox");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
 
-  // ---- walk: count, scan, emit
+  // ---- walk: count pass over all groups
   HOT_CHECK(walk_launch(false, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic, nullptr,
                         nullptr, ctr + CTR_STATUS, s),
             "walk count");
-  HOT_CHECK(scan_u32(G.cnt_p2p, G.off_p2p, ctr + CTR_TP, ngroups, scan_tmp, s), "scan");
-  HOT_CHECK(scan_u32(G.cnt_m2p, G.off_m2p, ctr + CTR_TM, ngroups, scan_tmp, s), "scan");
-  HOT_CHECK(readback(s, ctr, host, 8), "readback");
+  HOT_CHECK(sum_counts(G, ngroups, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
+                       ctr + CTR_MAXW, s),
+            "list totals");
+  HOT_CHECK(readback(s, ctr, host, CTR_READ), "readback");
   if (host[CTR_STATUS] & 4u) {
     g_err = "walk stack overflow (pathological tree)";
     return HOT_EOVERFLOW;
   }
-  const size_t tp = host[CTR_TP], tm = host[CTR_TM];
-  if (tp + tm > P.cap_list) {
-    c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)(tp + tm) / (double)n);
+  unsigned long long sums[2];
+  std::memcpy(sums, host + CTR_SUMS, sizeof(sums));
+  const size_t tp = sums[0], tm = sums[1];
+  const size_t maxw = host[CTR_MAXW];
+  // list words: direct entries 1, multipole records 4, plus 16-byte alignment
+  const size_t words = tp + 4 * tm + 4;
+  c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)words / (double)n);
+  if (maxw + 4 > P.cap_list) {
     c->stats.ws_bytes_needed = make_plan(c, n, 0).total;
-    g_err = "interaction-list capacity exceeded; call hot_workspace_size again and retry";
+    g_err = "interaction-list capacity below one group's lists; call hot_workspace_size again";
     return HOT_EOVERFLOW;
   }
-  uint32_t* p2p_list = at<uint32_t>(ws, P.o_list);
-  uint32_t* m2p_list = p2p_list + tp;
-  HOT_CHECK(walk_launch(true, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic, p2p_list,
-                        m2p_list, ctr + CTR_STATUS, s),
-            "walk emit");
-  HOT_CHECK(count_pairs(C, G, ngroups, p2p_list,
-                        reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
-            "pair count");
-  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
-
-  if (!vjp) {
-    // ---- interactions
-    HOT_CHECK(p2p_launch(fp32, C, G, ngroups, p.box, p.eps, spos, srec, n, p2p_list, near, s),
-              "direct kernel");
-    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
-    HOT_CHECK(m2p_launch(fp32, p.order, C, G, ngroups, p.box, p.eps, spos, n, m2p_list, near, s),
-              "multipole kernel");
-    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
-    HOT_CHECK(far_launch(p.far_order, spos, smass, key0, near, n, idx0, p.box, p.G, c->d_tpsi,
-                         at<double>(ws, P.o_far_part), kFarBlocks, at<double>(ws, P.o_far_mom),
-                         at<double>(ws, P.o_far_lam), p.periodic, fp32, acc, pot, s),
-              "far field");
-    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
+  // chunks of consecutive groups whose lists fit the list region together
+  struct Chunk {
+    uint32_t g0, g1;
+    size_t tp, tm;
+  };
+  std::vector<Chunk> chunks;
+  if (words <= P.cap_list) {
+    chunks.push_back({0, ngroups, tp, tm});
   } else {
-    // ---- adjoint
-    void* arec = at<void>(ws, P.o_arec);
-    double4* adj = at<double4>(ws, P.o_adj);
+    std::vector<uint32_t> cp(ngroups), cm(ngroups);
+    HOT_CHECK(hipMemcpyAsync(cp.data(), G.cnt_p2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
+              "readback");
+    HOT_CHECK(hipMemcpyAsync(cm.data(), G.cnt_m2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
+              "readback");
+    HOT_CHECK(hipStreamSynchronize(s), "readback");
+    Chunk ch{0, 0, 0, 0};
+    for (uint32_t g = 0; g < ngroups; ++g) {
+      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g]) + 4 > P.cap_list) {
+        chunks.push_back(ch);
+        ch = Chunk{g, g, 0, 0};
+      }
+      ch.g1 = g + 1;
+      ch.tp += cp[g];
+      ch.tm += cm[g];
+    }
+    chunks.push_back(ch);
+  }
+
+  void* arec = nullptr;
+  double4* adj = nullptr;
+  void* ecoef = nullptr;
+  if (vjp) {
+    // adjoint: sorted cotangents and the cotangent moments of every cell
+    arec = at<void>(ws, P.o_arec);
+    adj = at<double4>(ws, P.o_adj);
     double* emom = at<double>(ws, P.o_c_emom);
-    void* ecoef = at<void>(ws, P.o_c_ecoef);
+    ecoef = at<void>(ws, P.o_c_ecoef);
     HOT_CHECK(adj_gather_launch(fp32, vjp->gacc, vjp->gpot, n, idx0, arec, s), "adjoint gather");
     for (int l = nlev - 1; l >= 0; --l)
       HOT_CHECK(adj_moments_level(fp32, p.order, C, spos, arec, n, lvl[l], lvl[l + 1] - lvl[l],
                                   emom, ecoef, s),
                 "adjoint moments");
-    HOT_CHECK(p2p_adj_launch(fp32, C, G, ngroups, p.box, p.eps, spos, srec, arec, n, p2p_list,
-                             adj, s),
-              "adjoint direct kernel");
-    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
-    HOT_CHECK(m2p_adj_launch(fp32, p.order, C, G, ngroups, p.box, p.eps, spos, srec, arec, ecoef,
-                             n, m2p_list, adj, s),
-              "adjoint multipole kernel");
-    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
+  }
+  const bool single = chunks.size() == 1;
+  if (!single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
+  uint32_t* p2p_list = at<uint32_t>(ws, P.o_list);
+  for (const Chunk& k : chunks) {
+    const uint32_t ng = k.g1 - k.g0;
+    Groups Gk = G;  // the chunk's groups (the box arrays keep their stride)
+    Gk.cell += k.g0;
+    Gk.lo += k.g0;
+    Gk.hi += k.g0;
+    Gk.cnt_p2p += k.g0;
+    Gk.cnt_m2p += k.g0;
+    Gk.off_p2p += k.g0;
+    Gk.off_m2p += k.g0;
+    uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
+    HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
+    HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
+    HOT_CHECK(walk_launch(true, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic, p2p_list,
+                          m2p_list, ctr + CTR_STATUS, s),
+              "walk emit");
+    HOT_CHECK(count_pairs(C, Gk, ng, p2p_list,
+                          reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
+              "pair count");
+    if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
+    if (!vjp) {
+      HOT_CHECK(p2p_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list, near, s),
+                "direct kernel");
+      if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+      HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, n, m2p_list, near, s),
+                "multipole kernel");
+    } else {
+      HOT_CHECK(p2p_adj_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, arec, n, p2p_list, adj,
+                               s),
+                "adjoint direct kernel");
+      if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+      HOT_CHECK(m2p_adj_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, srec, arec, ecoef, n,
+                               m2p_list, adj, s),
+                "adjoint multipole kernel");
+    }
+  }
+  if (!single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
+
+  if (!vjp) {
+    HOT_CHECK(far_launch(p.far_order, spos, smass, key0, near, n, idx0, p.box, p.G, c->d_tpsi,
+                         at<double>(ws, P.o_far_part), kFarBlocks, at<double>(ws, P.o_far_mom),
+                         at<double>(ws, P.o_far_lam), p.periodic, fp32, acc, pot, s),
+              "far field");
+  } else {
     if (p.periodic)
       HOT_CHECK(far_prepare_launch(p.far_order, spos, smass, key0, n, p.box, c->d_tpsi,
                                    at<double>(ws, P.o_far_part), kFarBlocks,
@@ -411,8 +475,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                              at<double>(ws, P.o_far_lam), at<double>(ws, P.o_far_mbar),
                              p.periodic, fp32, vjp->xbar, vjp->mbar, s),
               "far-field adjoint");
-    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
   }
+  if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
+  c->last_chunks = (int)chunks.size();
 
   hot_stats& st = c->stats;
   std::memset(&st, 0, sizeof(st));
@@ -422,6 +487,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   st.nlevels = nlev;
   st.p2p_entries = (int64_t)tp;
   st.m2p_entries = (int64_t)tm;
+  st.list_chunks = (int64_t)chunks.size();
   st.ws_bytes_needed = P.total;
   c->have_last = 1;
   c->last_n = n;
@@ -514,6 +580,11 @@ size_t hot_workspace_size(const hot_ctx* c, size_t n) {
   return make_plan(c, n, 0).total;
 }
 
+size_t hot_workspace_size_min(const hot_ctx* c, size_t n) {
+  if (!c) return 0;
+  return make_plan(c, n, 0).o_list + kListMinBytes;
+}
+
 hot_status hot_forces(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
                       void* pot, void* ws, size_t ws_bytes, void* stream) {
   if (!c) {
@@ -549,8 +620,8 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
   const size_t tsz = fp32 ? 4 : 8;
   c->stats.kdk_steps_done = 0;
   const Plan P = make_plan(c, n, ws_bytes);
-  if (ws_bytes < P.o_list) {  // the snapshot regions lie below the lists
-    g_err = "workspace smaller than hot_workspace_size()";
+  if (ws_bytes < P.o_list + kListMinBytes) {  // the snapshot regions lie below the lists
+    g_err = "workspace smaller than hot_workspace_size_min()";
     return HOT_ENOMEM;
   }
   hot_status st;
@@ -626,8 +697,8 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
   // the scratch of the sweep sits in the workspace regions reserved for it,
   // which the force derivative itself does not touch
   Plan P = make_plan(c, n, ws_bytes);
-  if (ws_bytes < P.o_list) {
-    g_err = "workspace smaller than hot_workspace_size()";
+  if (ws_bytes < P.o_list + kListMinBytes) {
+    g_err = "workspace smaller than hot_workspace_size_min()";
     return HOT_ENOMEM;
   }
   void* gacc = at<void>(ws, P.o_kv_g);
@@ -709,6 +780,10 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
     g_err = "no previous hot_forces call or NULL argument";
     return HOT_EINVAL;
   }
+  if (c->last_chunks != 1) {
+    g_err = "the last evaluation processed its lists in chunks; they are not all in memory";
+    return HOT_EINVAL;
+  }
   const Plan& P = c->last_plan;
   hipStream_t s = c->last_stream;
   HOT_CHECK(hipStreamSynchronize(s), "sync");
@@ -746,7 +821,15 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
     } else if (ooff) {
       ooff[0] = 0;
     }
-    HOT_CHECK(cp(oent, P.o_list + (kind ? 4 * tp : 0), 4 * (kind ? tm : tp)), "export");
+    if (!oent) continue;
+    if (kind == 0) {
+      HOT_CHECK(cp(oent, P.o_list, 4 * tp), "export");
+    } else {
+      // multipole records: the entry is the last word of each 16 bytes
+      std::vector<uint32_t> rec(4 * tm);
+      HOT_CHECK(cp(rec.data(), P.o_list + 4 * ((tp + 3) & ~size_t(3)), 16 * tm), "export");
+      for (size_t i = 0; i < tm; ++i) oent[i] = rec[4 * i + 3];
+    }
   }
   return HOT_OK;
 }

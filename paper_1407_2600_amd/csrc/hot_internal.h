@@ -175,6 +175,7 @@ struct hot_ctx {
   uint32_t last_ncells;
   uint32_t last_ngroups;
   uint32_t* host_buf;  // pinned host memory for counter read-backs
+  int last_chunks;     // list chunks of the last evaluation
   hipEvent_t ev[8];
   int events_ok;
 };

@@ -18,7 +18,7 @@
 // with separate multiply and add, so that every implementation of the same
 // test takes the same decisions.  The first pass counts, the second writes at
 // the scanned offsets.
-#include "hot_internal.h"
+#include "device_math.h"
 
 namespace hot {
 
@@ -28,7 +28,7 @@ template <bool EMIT>
 __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uint32_t ngroups,
                                                           uint32_t gcap, double L, int periodic,
                                                           uint32_t* __restrict__ p2p_list,
-                                                          uint32_t* __restrict__ m2p_list,
+                                                          uint4* __restrict__ m2p_list,
                                                           uint32_t* __restrict__ status) {
   __shared__ uint32_t stack_all[kWalkWaves][kWalkStack];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -41,6 +41,8 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   const double lo0 = G.lo[g], lo1 = G.lo[gcap + g], lo2 = G.lo[2 * (size_t)gcap + g];
   const double hi0 = G.hi[g], hi1 = G.hi[gcap + g], hi2 = G.hi[2 * (size_t)gcap + g];
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  double cA[3];
+  center_of(keyA, levA, L, cA);
 
   uint32_t top;
   if (periodic) {
@@ -74,6 +76,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     // 0 none, 1 open, 2 multipole, 3 direct
     int action = 0;
     int nch = 0, ch0 = 0;
+    double cc0 = 0.0, cc1 = 0.0, cc2 = 0.0;  // image-shifted centre of mass
     if (active) {
       const bool zero = (img == 13);
       if (!(zero && B == A)) {
@@ -91,6 +94,9 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
           const double n0 = (double)(img / 9 - 1), n1 = (double)((img / 3) % 3 - 1),
                        n2 = (double)(img % 3 - 1);
           const double c0 = w.x + n0 * L, c1 = w.y + n1 * L, c2 = w.z + n2 * L;
+          cc0 = c0;
+          cc1 = c1;
+          cc2 = c2;
           double a0 = lo0 - c0, b0 = c0 - hi0;
           double a1 = lo1 - c1, b1 = c1 - hi1;
           double a2 = lo2 - c2, b2 = c2 - hi2;
@@ -112,7 +118,10 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     const uint64_t bm = __ballot(action == 2);
     const uint64_t bp = __ballot(action == 3);
     if (EMIT) {
-      if (action == 2) m2p_list[om + nm + (uint32_t)__popcll(bm & below)] = e;
+      if (action == 2)
+        m2p_list[om + nm + (uint32_t)__popcll(bm & below)] =
+            make_uint4(__float_as_uint((float)(cc0 - cA[0])), __float_as_uint((float)(cc1 - cA[1])),
+                       __float_as_uint((float)(cc2 - cA[2])), e);
       if (action == 3) p2p_list[op + np + (uint32_t)__popcll(bp & below)] = e;
     }
     nm += (uint32_t)__popcll(bm);
@@ -137,8 +146,41 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   }
 }
 
+// 64-bit totals of the per-group list counts, and the largest group's list
+// size in 4-byte words (a direct entry is one word, a multipole record four)
+__global__ void __launch_bounds__(256) k_sum_counts(Groups G, uint32_t ngroups,
+                                                    unsigned long long* __restrict__ sums,
+                                                    uint32_t* __restrict__ maxw) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long p = 0, m = 0;
+  uint32_t w = 0;
+  if (g < ngroups) {
+    p = G.cnt_p2p[g];
+    m = G.cnt_m2p[g];
+    w = (uint32_t)(p + 4 * m);
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    p += __shfl_down(p, d, 64);
+    m += __shfl_down(m, d, 64);
+    const uint32_t o = __shfl_down(w, d, 64);
+    w = o > w ? o : w;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&sums[0], p);
+    atomicAdd(&sums[1], m);
+    atomicMax(maxw, w);
+  }
+}
+
+hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
+                      hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  k_sum_counts<<<(ngroups + 255) / 256, 256, 0, s>>>(G, ngroups, sums, maxw);
+  return hipGetLastError();
+}
+
 hipError_t walk_launch(bool emit, const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
-                       double L, int periodic, uint32_t* p2p_list, uint32_t* m2p_list,
+                       double L, int periodic, uint32_t* p2p_list, uint4* m2p_list,
                        uint32_t* status, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   unsigned blocks = (ngroups + kWalkWaves - 1) / kWalkWaves;

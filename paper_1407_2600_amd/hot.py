@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
                 4: "HOT_EDEVICE", 5: "HOT_EUNSUPPORTED"}
 
 # symbols declared in include/hot.h
-EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_forces", "hot_kdk",
+EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
+            "hot_forces", "hot_kdk",
             "hot_vjp", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
             "hot_last_error", "hot_version", "hot_far_table"]
 
@@ -45,7 +46,7 @@ class hot_stats(C.Structure):
                 ("flops_m2p", C.c_double), ("ms_total", C.c_double), ("ms_sort", C.c_double),
                 ("ms_build", C.c_double), ("ms_walk", C.c_double), ("ms_p2p", C.c_double),
                 ("ms_m2p", C.c_double), ("ms_far", C.c_double), ("ws_bytes_needed", C.c_size_t),
-                ("kdk_steps_done", C.c_int64)]
+                ("kdk_steps_done", C.c_int64), ("list_chunks", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +78,8 @@ def lib():
         L.hot_destroy.argtypes = [vp]
         L.hot_workspace_size.restype = sz
         L.hot_workspace_size.argtypes = [vp, sz]
+        L.hot_workspace_size_min.restype = sz
+        L.hot_workspace_size_min.argtypes = [vp, sz]
         L.hot_forces.restype = C.c_int
         L.hot_forces.argtypes = [vp, sz, vp, vp, vp, vp, vp, sz, vp]
         L.hot_kdk.restype = C.c_int
@@ -129,7 +132,10 @@ def far_table(far_order: int, box: float = 1.0, offset: int = 13):
 class Gravity:
     """One libhot context: parameters, Ewald table and a cached workspace."""
 
-    def __init__(self, device=None, **params):
+    def __init__(self, device=None, workspace_bytes=None, **params):
+        """workspace_bytes caps the device workspace (at least the library's
+        minimum is used); interaction lists that do not fit are processed in
+        chunks of sink groups."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libhot needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -145,6 +151,7 @@ class Gravity:
             check(self.L.hot_create(C.byref(self.prm), C.byref(h)))
         self.h = h
         self.ws = None
+        self.ws_cap = workspace_bytes
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -157,6 +164,8 @@ class Gravity:
 
     def _workspace(self, n: int):
         need = self.L.hot_workspace_size(self.h, n)
+        if self.ws_cap is not None:
+            need = max(min(need, int(self.ws_cap)), self.L.hot_workspace_size_min(self.h, n))
         if self.ws is None or self.ws.numel() < need:
             self.ws = None
             self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
