@@ -107,6 +107,8 @@ struct Dual {
 template <typename T>
 __device__ __forceinline__ Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
 template <typename T>
+__device__ __forceinline__ Dual<T> operator+(Dual<T> a, T b) { return {a.v + b, a.d}; }
+template <typename T>
 __device__ __forceinline__ Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
 template <typename T>
 __device__ __forceinline__ Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
@@ -161,9 +163,15 @@ __device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __re
     else
       mono[k] = (c == 1) ? Rz : mono[mi_index(a, b, c - 1)] * Rz;
   }
+  // accumulators take their first contribution by assignment (which parts
+  // exist is known at compile time), so no addition of zero is emitted
   V Pm[P + 1], Vx[P + 1], Vy[P + 1], Vz[P + 1];
+  bool hasP[P + 1], hasV[P + 1];
 #pragma unroll
-  for (int m = 0; m <= P; ++m) Pm[m] = Vx[m] = Vy[m] = Vz[m] = V((C)0);
+  for (int m = 0; m <= P; ++m) {
+    Pm[m] = Vx[m] = Vy[m] = Vz[m] = V((C)0);
+    hasP[m] = hasV[m] = false;
+  }
   int o = 0;
 #pragma unroll
   for (int m = 0; m <= P; ++m) {
@@ -172,24 +180,34 @@ __device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __re
       const int d = m - j;
       if (!part_stored(m, d, DIP)) continue;
       if (d == 0) {
-        Pm[m] += cf[o];
+        Pm[m] = hasP[m] ? Pm[m] + cf[o] : V(cf[o]);
+        hasP[m] = true;
         o += 1;
       } else {
         const int nk = nte(d - 1);
         const int base = nt(d - 2);
-        V vx = V((C)0), vy = V((C)0), vz = V((C)0);
+        V vx = cf[o] * mono[base], vy = cf[o + nk] * mono[base],
+          vz = cf[o + 2 * nk] * mono[base];
 #pragma unroll
-        for (int k = 0; k < nk; ++k) {
+        for (int k = 1; k < nk; ++k) {
           vx = fma(cf[o + k], mono[base + k], vx);
           vy = fma(cf[o + nk + k], mono[base + k], vy);
           vz = fma(cf[o + 2 * nk + k], mono[base + k], vz);
         }
         o += 3 * nk;
-        Vx[m] += vx;
-        Vy[m] += vy;
-        Vz[m] += vz;
+        if (hasV[m]) {
+          Vx[m] += vx;
+          Vy[m] += vy;
+          Vz[m] += vz;
+        } else {
+          Vx[m] = vx;
+          Vy[m] = vy;
+          Vz[m] = vz;
+        }
+        hasV[m] = true;
         const V dot = fma(Rx, vx, fma(Ry, vy, Rz * vz));
-        Pm[m] = fma(dot, (C)(1.0 / d), Pm[m]);
+        Pm[m] = hasP[m] ? fma(dot, (C)(1.0 / d), Pm[m]) : dot * (C)(1.0 / d);
+        hasP[m] = true;
       }
     }
   }

@@ -97,40 +97,64 @@ __global__ void __launch_bounds__(kFarAThreads) k_far_adj_local(const double* __
 
 // one block per source octant s
 template <int PF>
-__global__ void __launch_bounds__(512) k_far_adj_moments(const double* __restrict__ part, int nblk,
-                                                         const double* __restrict__ tpsi, double G,
-                                                         double* __restrict__ mbar) {
+__global__ void __launch_bounds__(256) k_far_adj_sum(const double* __restrict__ part, int nblk,
+                                                     double G, double* __restrict__ lb) {
+  constexpr int NQ = nt(PF);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 8 * NQ) return;
+  const int t = i / NQ, q = i % NQ;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += part[((size_t)t * nblk + b) * NQ + q];
+  lb[i] = G * acc;
+}
+
+__device__ __forceinline__ double binom_exact_a(int n, int k) {
+  unsigned long long b = 1;
+  for (int u = 1; u <= k; ++u) b = b * (unsigned long long)(n - k + u) / (unsigned long long)u;
+  return (double)b;
+}
+
+__device__ __forceinline__ void mi_decode(int k, int* a, int* b, int* c) {
+  int d = 0;
+  while (nt(d) <= k) ++d;
+  int r = k - nt(d - 1), x;
+  for (x = d; x >= 0; --x) {
+    const int cnt = d - x + 1;
+    if (r < cnt) break;
+    r -= cnt;
+  }
+  *a = x;
+  *b = d - x - r;
+  *c = d - *a - *b;
+}
+
+// Source-octant moment cotangents (the adjoint of the local coefficients):
+//   mbar^so_k = (-1)^|k| sum_t sum_q Lb^t_q C(q+k, k) Tpsi^(t-so)_(q+k),
+// one wavefront per (so = blockIdx.y, k = blockIdx.x), the 8 x nt(PF) terms
+// spread over its lanes.
+template <int PF>
+__global__ void __launch_bounds__(64) k_far_adj_moments(const double* __restrict__ lb,
+                                                        const double* __restrict__ tpsi,
+                                                        double* __restrict__ mbar) {
   constexpr int NQ = nt(PF);
   constexpr int NT2 = nt(2 * PF);
-  constexpr MI<PF> mi{};
-  __shared__ double Lb[8][NQ];
-  const int so = blockIdx.x;
-  for (int i = threadIdx.x; i < 8 * NQ; i += blockDim.x) {
+  const int k = blockIdx.x, so = blockIdx.y, lane = threadIdx.x;
+  int ka, kb, kc;
+  mi_decode(k, &ka, &kb, &kc);
+  double acc = 0.0;
+  for (int i = lane; i < 8 * NQ; i += 64) {
     const int t = i / NQ, q = i % NQ;
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += part[((size_t)t * nblk + b) * NQ + q];
-    Lb[t][q] = G * acc;
+    int qa, qb, qc;
+    mi_decode(q, &qa, &qb, &qc);
+    const int dx = ((t >> 2) & 1) - ((so >> 2) & 1), dy = ((t >> 1) & 1) - ((so >> 1) & 1),
+              dz = (t & 1) - (so & 1);
+    const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
+    const double bin = binom_exact_a(qa + ka, ka) * binom_exact_a(qb + kb, kb) *
+                       binom_exact_a(qc + kc, kc);
+    acc += lb[(size_t)t * NQ + q] * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)];
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NQ; k += blockDim.x) {
-    const int ka = mi.a[k], kb = mi.b[k], kc = mi.c[k];
-    const double sg = ((ka + kb + kc) & 1) ? -1.0 : 1.0;
-    double acc = 0.0;
-    for (int t = 0; t < 8; ++t) {
-      const int dx = ((t >> 2) & 1) - ((so >> 2) & 1), dy = ((t >> 1) & 1) - ((so >> 1) & 1),
-                dz = (t & 1) - (so & 1);
-      const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
-      for (int q = 0; q < NQ; ++q) {
-        const int qa = mi.a[q], qb = mi.b[q], qc = mi.c[q];
-        double bin = 1.0;
-        for (int u = 1; u <= ka; ++u) bin = bin * (double)(qa + u) / (double)u;
-        for (int u = 1; u <= kb; ++u) bin = bin * (double)(qb + u) / (double)u;
-        for (int u = 1; u <= kc; ++u) bin = bin * (double)(qc + u) / (double)u;
-        acc += Lb[t][q] * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)];
-      }
-    }
-    mbar[(size_t)so * NQ + k] = sg * acc;
-  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) mbar[(size_t)so * NQ + k] = (((ka + kb + kc) & 1) ? -1.0 : 1.0) * acc;
 }
 
 // value and gradient of sum_q c_q h^q (V = double or Dual<double>)
@@ -207,9 +231,9 @@ template <int PF>
 static hipError_t far_adj_run(const double* spos, const double* smass, const uint64_t* skey,
                               const void* arec, const double4* near, size_t n,
                               const uint32_t* idx, double box, double G, const double* tpsi,
-                              double* part, int nblk_max, const double* lam, double* mbar,
-                              int periodic, bool fp32, double* xbar, void* mbar_out,
-                              hipStream_t s) {
+                              double* part, int nblk_max, const double* lam, double* lb,
+                              double* mbar, int periodic, bool fp32, double* xbar,
+                              void* mbar_out, hipStream_t s) {
   if (periodic) {
     int nblk = (int)((n / 8 + 2047) / 2048);
     if (nblk > nblk_max) nblk = nblk_max;
@@ -220,7 +244,8 @@ static hipError_t far_adj_run(const double* spos, const double* smass, const uin
     else
       k_far_adj_local<PF, double4><<<dim3(nblk, 8), kFarAThreads, 0, s>>>(
           spos, (const double4*)arec, skey, n, box, nblk, part);
-    k_far_adj_moments<PF><<<8, 512, 0, s>>>(part, nblk, tpsi, G, mbar);
+    k_far_adj_sum<PF><<<(8 * nt(PF) + 255) / 256, 256, 0, s>>>(part, nblk, G, lb);
+    k_far_adj_moments<PF><<<dim3(nt(PF), 8), 64, 0, s>>>(lb, tpsi, mbar);
   }
   unsigned g = (unsigned)((n + 255) / 256);
   if (fp32)
@@ -237,13 +262,14 @@ static hipError_t far_adj_run(const double* spos, const double* smass, const uin
 hipError_t far_adj_launch(int far_order, const double* spos, const double* smass,
                           const uint64_t* skey, const void* arec, const double4* near, size_t n,
                           const uint32_t* idx, double box, double G, const double* tpsi,
-                          double* part, int nblk_max, const double* lam, double* mbar,
-                          int periodic, bool fp32, double* xbar, void* mbar_out, hipStream_t s) {
+                          double* part, int nblk_max, const double* lam, double* lb,
+                          double* mbar, int periodic, bool fp32, double* xbar, void* mbar_out,
+                          hipStream_t s) {
   if (n == 0) return hipSuccess;
 #define HOT_FARA(PF)                                                                         \
   case PF:                                                                                   \
     return far_adj_run<PF>(spos, smass, skey, arec, near, n, idx, box, G, tpsi, part,        \
-                           nblk_max, lam, mbar, periodic, fp32, xbar, mbar_out, s);
+                           nblk_max, lam, lb, mbar, periodic, fp32, xbar, mbar_out, s);
   switch (far_order) {
     HOT_FARA(0) HOT_FARA(1) HOT_FARA(2) HOT_FARA(3) HOT_FARA(4) HOT_FARA(5) HOT_FARA(6)
     HOT_FARA(7) HOT_FARA(8) HOT_FARA(9) HOT_FARA(10) HOT_FARA(11) HOT_FARA(12)

@@ -72,7 +72,7 @@ hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G,
 hipError_t far_adj_launch(int far_order, const double* spos, const double* smass,
                           const uint64_t* skey, const void* arec, const double4* near, size_t n,
                           const uint32_t* idx, double box, double G, const double* tpsi,
-                          double* part, int nblk_max, const double* lam, double* mbar,
+                          double* part, int nblk_max, const double* lam, double* lb, double* mbar,
                           int periodic, bool fp32, double* xbar, void* mbar_out, hipStream_t s);
 hipError_t kick_launch(bool fp32, void* vel, const void* acc, size_t n, double h, hipStream_t s);
 hipError_t kdk_adj_drift_launch(bool fp32, void* vbar, const double* xbar, void* gacc, size_t n,
@@ -185,7 +185,8 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
   P.o_kv_sv = take(3 * tsz * n);
   P.o_list = o;
   const size_t want_list =
-      std::min((size_t)std::ceil(c->list_per_particle * (double)n) + 65536, kListMaxWords);
+      std::max(std::min((size_t)std::ceil(c->list_per_particle * (double)n) + 65536, kListMaxWords),
+               kListMinBytes / 4);
   if (ws_bytes == 0) {
     P.cap_list = want_list;
   } else {
@@ -472,7 +473,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                 "far field");
     HOT_CHECK(far_adj_launch(p.far_order, spos, smass, key0, arec, adj, n, idx0, p.box, p.G,
                              c->d_tpsi, at<double>(ws, P.o_far_part), kFarBlocks,
-                             at<double>(ws, P.o_far_lam), at<double>(ws, P.o_far_mbar),
+                             at<double>(ws, P.o_far_lam), at<double>(ws, P.o_far_mom),
+                             at<double>(ws, P.o_far_mbar),
                              p.periodic, fp32, vjp->xbar, vjp->mbar, s),
               "far-field adjoint");
   }
@@ -541,7 +543,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   c->p = *params;
   c->S = 2097152.0 / params->box;
   c->cells_per_particle = 8.0 / (params->leaf_max + 1) + 0.05;
-  c->list_per_particle = 48.0;
+  c->list_per_particle = 96.0;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;

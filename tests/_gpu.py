@@ -17,6 +17,13 @@ def run_gpu(pos, mass, params, precision="fp64", want_debug=True):
     m = torch.as_tensor(np.ascontiguousarray(mass), dtype=dt, device="cuda")
     acc, pot = g.forces(p, m)
     torch.cuda.synchronize()
+    if want_debug and g.stats()["list_chunks"] > 1:
+        # a new context may process its first lists in chunks (same results);
+        # the structures are exported from a single-pass evaluation
+        acc2, pot2 = g.forces(p, m)
+        torch.cuda.synchronize()
+        assert g.stats()["list_chunks"] == 1
+        assert torch.equal(acc, acc2) and torch.equal(pot, pot2)
     out = dict(acc=acc.double().cpu().numpy(), pot=pot.double().cpu().numpy(),
                stats=g.stats())
     if want_debug:
