@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--group-max", type=int, default=128)
     ap.add_argument("--leaf-max", type=int, default=16)
     ap.add_argument("--n-side", type=int, default=None, help="smaller grid (debug only)")
+    ap.add_argument("--workload", default="zeldovich128", choices=sorted(WORKLOADS),
+                    help="zeldovich128 (the headline workload) or nfw256 (clustered)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--dt", type=float, default=0.01)
@@ -58,27 +60,39 @@ def parse():
 ERR_TARGET = 1e-3
 ERR_TOL_GRID = (2e-3, 3e-3, 4e-3, 5e-3, 6e-3, 8e-3)
 THETA_CAPS = (0.0, 0.6, 0.7, 0.8)
-THETA_GRID = (0.40, 0.44, 0.46, 0.47, 0.48, 0.50)
-REF_PATH = os.path.join(ROOT, "tests", "golden", "zeldovich128_ref.npz")
+# per workload: the oracle reference and the opening angles searched
+WORKLOADS = {
+    "zeldovich128": dict(
+        ref="zeldovich128_ref.npz", thetas=(0.40, 0.44, 0.46, 0.47, 0.48, 0.50),
+        data="synthetic (seeded Zel'dovich field standing in for the paper's 2LPT ICs)",
+        desc="zeldovich {s}^3={n} particles, periodic unit box, P(k)~k^-1.5, rms displacement "
+             "0.5 spacing"),
+    "nfw256": dict(
+        ref="nfw256_ref.npz", thetas=(0.3, 0.5, 0.7),
+        data="synthetic (seeded NFW halos, dN/dM~M^-1.9, c=8, plus uniform background, standing "
+             "in for the paper's clustered late-time particle distributions)",
+        desc="clustered {s}^3={n} particles: 70% in NFW halos of 1e2..1e5 particles, 30% "
+             "uniform, periodic unit box"),
+}
 
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE/WRITE_SIZE
 # counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
 # They hold only for the sources and the configuration they were taken with;
 # otherwise the roofline reports traffic as null.
-TRAFFIC = {"kernel": "k_m2p<4,float>", "bytes_per_launch": 7.176e+09,
+TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 7.176e+09,
            "config": {"theta": 0.8, "err_tol": 0.005, "order": 4, "leaf_max": 16,
                       "group_max": 128, "far_order": 8},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
            "sha256": "198d667f5db27b9926d1d58552ce82fc181ed803c414e67549e6e33018bd6b57"}
 
 
-def measured_traffic(prm):
+def measured_traffic(prm, workload):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC["sources"]:
         with open(os.path.join(ROOT, "paper_1407_2600_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    same = h.hexdigest() == TRAFFIC["sha256"] and all(
+    same = workload == TRAFFIC["workload"] and h.hexdigest() == TRAFFIC["sha256"] and all(
         prm.get(k) == v for k, v in TRAFFIC["config"].items())
     return TRAFFIC["bytes_per_launch"] if same else None
 
@@ -104,7 +118,7 @@ def evaluate(torch, Gravity, pos, mass_np, prm, ref, dev):
             "p2p_per_particle": st["p2p_pairs"] / st["n"]}
 
 
-def operating_point(torch, Gravity, pos, mass_np, prm, ref, dev):
+def operating_point(torch, Gravity, pos, mass_np, prm, ref, dev, thetas):
     """The fastest searched configuration whose FP32 rms force error is at
     most ERR_TARGET, and the tables of both searches."""
     err_rows, theta_rows = [], []
@@ -114,7 +128,7 @@ def operating_point(torch, Gravity, pos, mass_np, prm, ref, dev):
             err_rows.append(r)
             print(f"[bench] err_tol={tol:.0e} theta_cap={cap:.2f} err={r['err']:.3e} "
                   f"ms={r['ms_force']:.2f}", file=sys.stderr, flush=True)
-    for th in THETA_GRID:
+    for th in thetas:
         r = evaluate(torch, Gravity, pos, mass_np, dict(prm, theta=th, err_tol=0.0), ref, dev)
         theta_rows.append(r)
         print(f"[bench] theta={th:.3f} err={r['err']:.3e} ms={r['ms_force']:.2f}",
@@ -138,7 +152,8 @@ def main():
     import workloads
     from paper_1407_2600_amd import Gravity
 
-    pos_np, mass_np, prm = workloads.make("zeldovich128", n_side=args.n_side)
+    W = WORKLOADS[args.workload]
+    pos_np, mass_np, prm = workloads.make(args.workload, n_side=args.n_side)
     prm = dict(prm, group_max=args.group_max, leaf_max=args.leaf_max)
     if args.far_order is not None:
         prm["far_order"] = args.far_order
@@ -147,8 +162,9 @@ def main():
     pos_dev = torch.as_tensor(pos_np, dtype=torch.float64, device=dev).contiguous()
 
     ref = None
-    if args.n_side is None and os.path.exists(REF_PATH):
-        R = np.load(REF_PATH)
+    ref_path = os.path.join(ROOT, "tests", "golden", W["ref"])
+    if args.n_side is None and os.path.exists(ref_path):
+        R = np.load(ref_path)
         ref = (R["targets"], R["acc_near_far"])
     search = None
     if args.theta is not None or args.err_tol is not None:
@@ -156,7 +172,7 @@ def main():
         prm["err_tol"] = args.err_tol if args.err_tol is not None else 0.0
     elif ref is not None:
         best, theta_star, err_rows, theta_rows = operating_point(torch, Gravity, pos_dev, mass_np,
-                                                                 prm, ref, dev)
+                                                                 prm, ref, dev, W["thetas"])
         prm["theta"], prm["err_tol"] = best["theta"], best["err_tol"]
         search = {"err_target": ERR_TARGET, "chosen": best, "theta_only_star": theta_star,
                   "error_bound_test": err_rows, "opening_angle_test": theta_rows}
@@ -232,6 +248,7 @@ def main():
                          flops={k: v / steps for k, v in flops.items()},
                          pairs={k: v / steps for k, v in pairs.items()},
                          ms_force_median=float(np.median(f_ms)), adjoint=adj,
+                         workspace_bytes=int(g.ws.numel()),
                          acc=a_first)
         print(f"[bench] {prec}: {res[prec]['ms_per_step']:.2f} ms/step "
               f"force {res[prec]['ms_force_median']:.2f} ms kern={res[prec]['kern']}",
@@ -258,7 +275,8 @@ def main():
     roof = {"kernel": f"k_m2p<{prm['order']},float>" if dom == "m2p" else "k_p2p<float>",
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": measured_traffic(prm) if dom == "m2p" and prm["order"] == 4 else None,
+            "traffic": (measured_traffic(prm, args.workload)
+                        if dom == "m2p" and prm["order"] == 4 else None),
             "flops_per_launch": fl, "ms_per_launch": ms}
     other = "p2p" if dom == "m2p" else "m2p"
     roof_other = {"kernel": other, "achieved": r32["flops"][other] /
@@ -266,7 +284,7 @@ def main():
                   "ms_per_launch": r32["kern"][f"ms_{other}"]}
 
     cpu = None
-    if not args.no_cpu_baseline and args.n_side is None:
+    if not args.no_cpu_baseline and args.n_side is None and args.workload == "zeldovich128":
         cpu = cpu_baseline(pos_np, mass_np, prm, args.cpu_seconds)
 
     out = {
@@ -281,9 +299,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Zel'dovich field standing in for the paper's 2LPT ICs)",
-        "config": {"workload": f"zeldovich {round(n ** (1 / 3))}^3={n} particles, periodic unit "
-                               "box, P(k)~k^-1.5, rms displacement 0.5 spacing",
+        "data": W["data"],
+        "config": {"workload": W["desc"].format(s=round(n ** (1 / 3)), n=n),
                    "theta": prm["theta"], "err_tol": prm["err_tol"], "order": prm["order"],
                    "eps": prm["eps"],
                    "leaf_max": prm["leaf_max"], "group_max": prm["group_max"],
@@ -295,6 +312,8 @@ def main():
         "fp64": {"value": res["fp64"]["pps"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "dtype": "f64"},
         "fp32_over_fp64": r32["pps"] / res["fp64"]["pps"],
+        "workspace_bytes": {"fp32": r32["workspace_bytes"],
+                            "fp64": res["fp64"]["workspace_bytes"]},
         "rms_force_err": err,
         "adjoint_over_forward": r32["adjoint"]["ratio"],
         "adjoint": r32["adjoint"],

@@ -245,7 +245,9 @@ hot_status hot_debug_sizes(const hot_ctx* ctx, int64_t* n, int64_t* ncells, int6
 
 /* Copy the internal structures of the last hot_forces call to host buffers
  * (synchronises the stream of that call).  The workspace of that call must
- * still hold its contents.  HOT_EINVAL if no hot_forces call preceded. */
+ * still hold its contents.  HOT_EINVAL if no hot_forces call preceded, or if
+ * list buffers are requested after a call that processed its lists in chunks
+ * (hot_stats.list_chunks > 1). */
 hot_status hot_debug_export(hot_ctx* ctx, void* workspace, hot_debug* out);
 
 /* A Taylor table of the periodic far field, as built by hot_create:

@@ -782,7 +782,7 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
     g_err = "no previous hot_forces call or NULL argument";
     return HOT_EINVAL;
   }
-  if (c->last_chunks != 1) {
+  if (c->last_chunks != 1 && (o->p2p_offset || o->p2p_entry || o->m2p_offset || o->m2p_entry)) {
     g_err = "the last evaluation processed its lists in chunks; they are not all in memory";
     return HOT_EINVAL;
   }

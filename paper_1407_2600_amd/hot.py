@@ -292,13 +292,15 @@ class Gravity:
         check(self.L.hot_get_stats(self.h, C.byref(st)))
         return st.as_dict()
 
-    def debug_export(self) -> dict:
-        """Host copies of keys, permutation, cells, groups and lists of the
-        last forces() call (numpy arrays)."""
+    def debug_export(self, lists: bool = True) -> dict:
+        """Host copies of keys, permutation, cells, groups and (unless lists
+        is False) the interaction lists of the last forces() call."""
         import numpy as np
         sizes = [C.c_int64() for _ in range(5)]
         check(self.L.hot_debug_sizes(self.h, *[C.byref(x) for x in sizes]))
         n, nc, ng, tp, tm = [x.value for x in sizes]
+        if not lists:
+            tp = tm = 0
         out = dict(sorted_keys=np.zeros(n, np.uint64), perm=np.zeros(n, np.uint32),
                    cell_key=np.zeros(nc, np.uint64), cell_level=np.zeros(nc, np.int32),
                    cell_first=np.zeros(nc, np.int32), cell_count=np.zeros(nc, np.int32),
@@ -306,7 +308,9 @@ class Gravity:
                    group_cell=np.zeros(ng, np.int32), p2p_offset=np.zeros(ng + 1, np.int64),
                    p2p_entry=np.zeros(tp, np.uint32), m2p_offset=np.zeros(ng + 1, np.int64),
                    m2p_entry=np.zeros(tm, np.uint32))
-        dbg = hot_debug(*[C.c_void_p(out[f].ctypes.data) for f, _ in hot_debug._fields_])
+        skip = () if lists else ("p2p_offset", "p2p_entry", "m2p_offset", "m2p_entry")
+        dbg = hot_debug(*[C.c_void_p(None if f in skip else out[f].ctypes.data)
+                          for f, _ in hot_debug._fields_])
         check(self.L.hot_debug_export(self.h, C.c_void_p(self.ws.data_ptr()), C.byref(dbg)))
         return out
 

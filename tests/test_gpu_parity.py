@@ -181,22 +181,31 @@ def test_deterministic_repeat():
         np.testing.assert_array_equal(r1["pot"], r2["pot"])
 
 
+# the benchmark's launch configuration (error-bound test at the 1e-3
+# operating point) at the workloads' full sizes
+FULL = [("zeldovich128", True), ("nfw256", False)]
+BENCH_PRM = dict(theta=0.8, err_tol=5e-3, group_max=128, leaf_max=16)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_full_size_zeldovich128(precision):
-    """The headline workload at its full size (128^3 = 2,097,152 particles):
-    keys, order and cells bit-exact over the whole tree; lists and forces on
-    sampled sink groups against the oracle."""
-    pos, mass, prm = workloads.make("zeldovich128")
-    print(f"full size {precision}: building oracle tree", flush=True)
+@pytest.mark.parametrize("name,lists", FULL)
+def test_full_size(name, lists, precision):
+    """Full size (128^3 = 2,097,152 and 256^3 = 16,777,216 particles): keys,
+    order and cells bit-exact over the whole tree; lists (where their export
+    fits in host memory) and forces on sampled sink groups against the
+    oracle."""
+    pos, mass, prm = workloads.make(name)
+    prm = dict(prm, **BENCH_PRM)
+    print(f"full size {name} {precision}: building oracle tree", flush=True)
     mo = oracle_mass(mass, precision)
     T = oracle.Tree(pos, mo, prm)
-    r = run_gpu(pos, mass, prm, precision)
+    r = run_gpu(pos, mass, prm, precision, lists=lists)
     print("  gpu stats", {k: r["stats"][k] for k in ("ncells", "ngroups", "p2p_entries",
-                                                     "m2p_entries")}, flush=True)
+                                                     "m2p_entries", "list_chunks")}, flush=True)
     gcell, _, _ = T.groups()
     rng = np.random.default_rng(99)
     sample = np.sort(rng.choice(len(gcell), size=24, replace=False))
-    compare_structure(r["dbg"], T, sample_groups=sample)
+    compare_structure(r["dbg"], T, sample_groups=sample, lists=lists)
     acc_o, pot_o = T.forces(groups=sample)
     sel = ~np.isnan(pot_o)
     ea = rms_err(r["acc"][:, sel], acc_o[:, sel])
