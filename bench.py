@@ -58,7 +58,9 @@ def parse():
 # searched for it (order 4): the error-bound acceptance test over tolerances
 # (with an optional opening-angle cap), and the opening angle alone
 ERR_TARGET = 1e-3
-ERR_TOL_GRID = (2e-3, 3e-3, 4e-3, 5e-3, 6e-3, 8e-3)
+# error-bound tolerances as fractions of the reference's rms acceleration
+# (the paper states its tolerance relative to the rms acceleration)
+ETA_GRID = (0.04, 0.06, 0.08, 0.09, 0.10, 0.11, 0.12)
 THETA_CAPS = (0.0, 0.6, 0.7, 0.8)
 # per workload: the oracle reference and the opening angles searched
 WORKLOADS = {
@@ -122,11 +124,13 @@ def operating_point(torch, Gravity, pos, mass_np, prm, ref, dev, thetas):
     """The fastest searched configuration whose FP32 rms force error is at
     most ERR_TARGET, and the tables of both searches."""
     err_rows, theta_rows = [], []
+    a_rms = float(np.sqrt(np.mean(np.sum(ref[1] ** 2, axis=0))))
     for cap in THETA_CAPS:
-        for tol in ERR_TOL_GRID:
+        for eta in ETA_GRID:
+            tol = float(f"{eta * a_rms:.3g}")
             r = evaluate(torch, Gravity, pos, mass_np, dict(prm, theta=cap, err_tol=tol), ref, dev)
             err_rows.append(r)
-            print(f"[bench] err_tol={tol:.0e} theta_cap={cap:.2f} err={r['err']:.3e} "
+            print(f"[bench] err_tol={tol:.3g} theta_cap={cap:.2f} err={r['err']:.3e} "
                   f"ms={r['ms_force']:.2f}", file=sys.stderr, flush=True)
     for th in thetas:
         r = evaluate(torch, Gravity, pos, mass_np, dict(prm, theta=th, err_tol=0.0), ref, dev)

@@ -96,7 +96,10 @@ typedef struct {
                       sum m |x - com|^2 and the cell's extent, falls to
                       err_tol (acceleration units); with theta > 0 as well,
                       the larger of the two opening radii applies.
-                      0 = opening angle only.  Finite, >= 0. */
+                      0 = opening angle only.  Finite, >= 0.  A
+                      fixed fraction (about 0.1) of the rms acceleration
+                      of the previous step keeps the rms force error near
+                      1e-3 of the rms acceleration. */
 } hot_params;
 
 /* Per-call statistics of the last compute call on a context. */

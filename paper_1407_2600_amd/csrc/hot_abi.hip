@@ -360,8 +360,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
             "list totals");
   HOT_CHECK(readback(s, ctr, host, CTR_READ), "readback");
   if (host[CTR_STATUS] & 4u) {
-    g_err = "walk stack overflow (pathological tree)";
-    return HOT_EOVERFLOW;
+    g_err = "tree-walk stack overflow: a sink group has more pending cells than the walk "
+            "stack holds (reduce group_max or the opening radius)";
+    return HOT_EUNSUPPORTED;
   }
   unsigned long long sums[2];
   std::memcpy(sums, host + CTR_SUMS, sizeof(sums));
