@@ -60,7 +60,8 @@ def parse():
 ERR_TARGET = 1e-3
 # error-bound tolerances as fractions of the reference's rms acceleration
 # (the paper states its tolerance relative to the rms acceleration)
-ETA_GRID = (0.04, 0.06, 0.08, 0.09, 0.10, 0.11, 0.12)
+ETA_GRID = {"zeldovich128": (0.04, 0.06, 0.08, 0.09, 0.10, 0.11, 0.12),
+            "nfw256": (0.12, 0.2, 0.3, 0.5, 0.8, 1.2)}
 THETA_CAPS = (0.0, 0.6, 0.7, 0.8)
 # per workload: the oracle reference and the opening angles searched
 WORKLOADS = {
@@ -120,13 +121,13 @@ def evaluate(torch, Gravity, pos, mass_np, prm, ref, dev):
             "p2p_per_particle": st["p2p_pairs"] / st["n"]}
 
 
-def operating_point(torch, Gravity, pos, mass_np, prm, ref, dev, thetas):
+def operating_point(torch, Gravity, pos, mass_np, prm, ref, dev, thetas, etas):
     """The fastest searched configuration whose FP32 rms force error is at
     most ERR_TARGET, and the tables of both searches."""
     err_rows, theta_rows = [], []
     a_rms = float(np.sqrt(np.mean(np.sum(ref[1] ** 2, axis=0))))
     for cap in THETA_CAPS:
-        for eta in ETA_GRID:
+        for eta in etas:
             tol = float(f"{eta * a_rms:.3g}")
             r = evaluate(torch, Gravity, pos, mass_np, dict(prm, theta=cap, err_tol=tol), ref, dev)
             err_rows.append(r)
@@ -176,7 +177,8 @@ def main():
         prm["err_tol"] = args.err_tol if args.err_tol is not None else 0.0
     elif ref is not None:
         best, theta_star, err_rows, theta_rows = operating_point(torch, Gravity, pos_dev, mass_np,
-                                                                 prm, ref, dev, W["thetas"])
+                                                                 prm, ref, dev, W["thetas"],
+                                                                 ETA_GRID[args.workload])
         prm["theta"], prm["err_tol"] = best["theta"], best["err_tol"]
         search = {"err_target": ERR_TARGET, "chosen": best, "theta_only_star": theta_star,
                   "error_bound_test": err_rows, "opening_angle_test": theta_rows}

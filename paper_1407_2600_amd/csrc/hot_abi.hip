@@ -36,7 +36,7 @@ hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, ui
                            const double* spos, size_t n, hipStream_t s);
 hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
                      size_t n, double L, void* srec, bool fp32, hipStream_t s);
-hipError_t walk_launch(bool emit, const Cells& C, const Groups& G, uint32_t ngroups,
+hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
                        uint32_t gcap, double L, int periodic, uint32_t* p2p_list,
                        uint4* m2p_list, uint32_t* status, hipStream_t s);
 hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
@@ -351,18 +351,26 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   HOT_CHECK(tree_group_bbox(C, G, ngroups, (uint32_t)P.cap_groups, spos, n, s), "bbox");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
 
-  // ---- walk: count pass over all groups
-  HOT_CHECK(walk_launch(false, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic, nullptr,
-                        nullptr, ctr + CTR_STATUS, s),
-            "walk count");
-  HOT_CHECK(sum_counts(G, ngroups, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
-                       ctr + CTR_MAXW, s),
-            "list totals");
-  HOT_CHECK(readback(s, ctr, host, CTR_READ), "readback");
-  if (host[CTR_STATUS] & 4u) {
-    g_err = "tree-walk stack overflow: a sink group has more pending cells than the walk "
-            "stack holds (reduce group_max or the opening radius)";
-    return HOT_EUNSUPPORTED;
+  // ---- walk: count pass over all groups (again with the larger stack if
+  // some group's pending cells overflowed the default one)
+  bool big = false;
+  for (;;) {
+    HOT_CHECK(walk_launch(false, big, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic,
+                          nullptr, nullptr, ctr + CTR_STATUS, s),
+              "walk count");
+    HOT_CHECK(sum_counts(G, ngroups, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
+                         ctr + CTR_MAXW, s),
+              "list totals");
+    HOT_CHECK(readback(s, ctr, host, CTR_READ), "readback");
+    if (!(host[CTR_STATUS] & 4u)) break;
+    if (big) {
+      g_err = "tree-walk stack overflow: a sink group has more pending cells than the walk "
+              "stack holds (reduce group_max or the opening radius)";
+      return HOT_EUNSUPPORTED;
+    }
+    big = true;
+    HOT_CHECK(zero_launch(ctr + CTR_STATUS, 4, s), "clear status");
+    HOT_CHECK(zero_launch(ctr + CTR_SUMS, 4 * (CTR_READ - CTR_SUMS), s), "clear totals");
   }
   unsigned long long sums[2];
   std::memcpy(sums, host + CTR_SUMS, sizeof(sums));
@@ -435,8 +443,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
     HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
     HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
-    HOT_CHECK(walk_launch(true, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic, p2p_list,
-                          m2p_list, ctr + CTR_STATUS, s),
+    HOT_CHECK(walk_launch(true, big, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic,
+                          p2p_list, m2p_list, ctr + CTR_STATUS, s),
               "walk emit");
     HOT_CHECK(count_pairs(C, Gk, ng, p2p_list,
                           reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
@@ -543,7 +551,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   std::memset(c, 0, sizeof(*c));
   c->p = *params;
   c->S = 2097152.0 / params->box;
-  c->cells_per_particle = 8.0 / (params->leaf_max + 1) + 0.05;
+  c->cells_per_particle = 3.0 / params->leaf_max + 0.02;  // grows on overflow
   c->list_per_particle = 96.0;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {

@@ -16,7 +16,8 @@ constexpr int kMaxOrder = 4;         // cell multipole order built into the kern
 constexpr int kMaxFarOrder = 12;     // far-field local expansion order
 constexpr int kImgBits = 5;          // list entry = image << 27 | cell
 constexpr uint32_t kCellMask = (1u << 27) - 1;
-constexpr int kWalkStack = 4096;     // LDS walk stack entries per wave (4 waves: 64 KiB)
+constexpr int kWalkStack = 2048;     // LDS walk stack entries per wave
+constexpr int kWalkStackBig = 4096;  // fallback for groups with very many pending cells
 constexpr int kSortBits = 8;
 constexpr int kSortBins = 1 << kSortBits;
 constexpr int kSortTile = 4096;      // keys per sort block

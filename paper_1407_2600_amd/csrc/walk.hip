@@ -24,13 +24,13 @@ namespace hot {
 
 constexpr int kWalkWaves = 4;
 
-template <bool EMIT>
+template <bool EMIT, int STACK>
 __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uint32_t ngroups,
                                                           uint32_t gcap, double L, int periodic,
                                                           uint32_t* __restrict__ p2p_list,
                                                           uint4* __restrict__ m2p_list,
                                                           uint32_t* __restrict__ status) {
-  __shared__ uint32_t stack_all[kWalkWaves][kWalkStack];
+  __shared__ uint32_t stack_all[kWalkWaves][STACK];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWalkWaves + wid);
   if (g >= ngroups) return;  // whole wavefront leaves; no block barriers below
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   }
   __builtin_amdgcn_wave_barrier();
   while (top > 0) {
-    uint32_t room = (kWalkStack - top) / 7;
+    uint32_t room = (STACK - top) / 7;
     uint32_t k = top < 64 ? top : 64;
     k = k < room ? k : room;
     if (k == 0) {
@@ -179,17 +179,24 @@ hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sum
   return hipGetLastError();
 }
 
-hipError_t walk_launch(bool emit, const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
-                       double L, int periodic, uint32_t* p2p_list, uint4* m2p_list,
+hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
+                       uint32_t gcap, double L, int periodic, uint32_t* p2p_list, uint4* m2p_list,
                        uint32_t* status, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  unsigned blocks = (ngroups + kWalkWaves - 1) / kWalkWaves;
-  if (emit)
-    k_walk<true><<<blocks, 64 * kWalkWaves, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
-                                                    m2p_list, status);
+  const unsigned blocks = (ngroups + kWalkWaves - 1) / kWalkWaves;
+  const unsigned th = 64 * kWalkWaves;
+  if (emit && big)
+    k_walk<true, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
+                                                      m2p_list, status);
+  else if (emit)
+    k_walk<true, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
+                                                   m2p_list, status);
+  else if (big)
+    k_walk<false, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
+                                                       m2p_list, status);
   else
-    k_walk<false><<<blocks, 64 * kWalkWaves, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
-                                                     m2p_list, status);
+    k_walk<false, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
+                                                    m2p_list, status);
   return hipGetLastError();
 }
 
