@@ -82,11 +82,11 @@ WORKLOADS = {
 # counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
 # They hold only for the sources and the configuration they were taken with;
 # otherwise the roofline reports traffic as null.
-TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 7.176e+09,
-           "config": {"theta": 0.8, "err_tol": 0.005, "order": 4, "leaf_max": 16,
+TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 7.303e+09,
+           "config": {"theta": 0.7, "err_tol": 0.00488, "order": 4, "leaf_max": 16,
                       "group_max": 128, "far_order": 8},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
-           "sha256": "198d667f5db27b9926d1d58552ce82fc181ed803c414e67549e6e33018bd6b57"}
+           "sha256": "d26a890d8995ea453e1bce9620967a3609304eb9249d5caa1cc07e34adc792fd"}
 
 
 def measured_traffic(prm, workload):
