@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
                                                             const uint32_t* __restrict__ list,
                                                             double4* __restrict__ out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kAdjWaves + wid);
+  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kAdjWaves + wid);
   if (g >= ngroups) return;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
   constexpr int STR = coef_stride(P);
   constexpr int ESTR = coef_stride(P + 1, true);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kAdjWaves + wid);
+  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kAdjWaves + wid);
   if (g >= ngroups) return;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);

@@ -20,7 +20,15 @@ namespace hot {
 constexpr int kForceWaves = 4;
 
 // ------------------------------------------------------------------- direct
-template <typename T, typename T4>
+// Direct interactions of one sink group per wavefront, targets in lanes, in
+// passes of up to 64 targets: first the group's own particles (image 0,
+// without the target itself), then every listed leaf with its image shift.
+// TAIL selects the passes as in k_m2p: the main launch takes the passes over
+// more than 32 targets with wave-uniform sources; the tail launch takes a
+// last pass of at most 32 targets and splits the wave into 2 or 4 sub-groups
+// that share out the sources and list entries, adding their partial sums at
+// the end.  This kernel writes (not adds) the accumulators.
+template <typename T, typename T4, bool TAIL>
 __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uint32_t ngroups,
                                                           double L, T eps2,
                                                           const double* __restrict__ spos,
@@ -28,17 +36,26 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
                                                           const uint32_t* __restrict__ list,
                                                           double4* __restrict__ out) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kForceWaves + wid);
+  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
+  const uint32_t tail0 = count - count % 64;
+  const bool has_tail = count % 64 != 0 && count % 64 <= 32;
+  if (TAIL && !has_tail) return;
   double cA[3];
   center_of(C.key[A], C.level[A], L, cA);
   const uint32_t off = G.off_p2p[g], cnt = G.cnt_p2p[g];
-  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
-    const uint32_t s = first + t0 + lane;
-    const bool act = s < first + count;
+  for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
+    const uint32_t rem = count - t0;
+    if (!TAIL && rem <= 32) break;
+    const uint32_t split = !TAIL ? 1u : rem <= 16 ? 4u : 2u;  // wave-uniform
+    const int width = 64 / (int)split;
+    const uint32_t sub = (uint32_t)(lane / width);
+    const int tl = lane % width;
+    const uint32_t s = first + t0 + tl;
+    const bool act = (uint32_t)tl < rem;
     const uint32_t ss = act ? s : first;
     const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
             tz = (T)(spos[2 * n + ss] - cA[2]);
@@ -47,7 +64,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
     // own group (image 0), excluding the target itself
     {
       T part[4] = {0, 0, 0, 0};
-      for (uint32_t j = first; j < first + count; ++j) {
+      for (uint32_t j = first + sub; j < first + count; j += split) {
         const T sx = (T)(spos[j] - cA[0]), sy = (T)(spos[n + j] - cA[1]),
                 sz = (T)(spos[2 * n + j] - cA[2]);
         const T m = srec[j].w;
@@ -65,7 +82,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
       }
       acc.fold(part);
     }
-    for (uint32_t q = 0; q < cnt; ++q) {
+    for (uint32_t q = sub; q < cnt; q += split) {
       const uint32_t e = list[off + q];
       const int img = (int)(e >> 27);
       const int B = (int)(e & kCellMask);
@@ -90,11 +107,52 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
       }
       acc.fold(part);
     }
-    if (act) out[s] = make_double4(acc.get(0), acc.get(1), acc.get(2), acc.get(3));
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = acc.get(k);
+    for (int w = width; w < 64; w <<= 1)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], w, 64);
+    if (act && sub == 0) out[s] = make_double4(v[0], v[1], v[2], v[3]);
   }
 }
 
-template <int P, typename T>
+// one cell's coefficient block into registers with 16-byte loads (blocks are
+// padded to a multiple of 4 values and 16-byte aligned)
+template <typename T, int N>
+__device__ __forceinline__ void load_block(const T* __restrict__ p, T* out) {
+  if constexpr (sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+      const float4 v = q[i];
+      out[4 * i] = v.x;
+      out[4 * i + 1] = v.y;
+      out[4 * i + 2] = v.z;
+      out[4 * i + 3] = v.w;
+    }
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      const double2 v = q[i];
+      out[2 * i] = v.x;
+      out[2 * i + 1] = v.y;
+    }
+  }
+}
+
+// Multipole interactions of one sink group per wavefront, targets in lanes,
+// in passes of up to 64 targets.  TAIL = false: the passes over more than 32
+// targets, each walking the list once with every entry wave-uniform (scalar
+// loads of the record and the cell's coefficients).  TAIL = true: the last
+// pass when it has at most 32 targets (the remainder of a group of 65..96,
+// or a small group); the wave splits into 2 or 4 sub-groups of 32 or 16 lanes
+// that take every 2nd or 4th list entry with per-lane loads, and the partial
+// sums are added across the sub-groups at the end, so the lanes a short pass
+// would leave idle do the work.  Separate launches keep the register budget
+// (and occupancy) of the main pass independent of the tail's.
+template <int P, typename T, bool TAIL>
 __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uint32_t ngroups,
                                                           double L, T eps2,
                                                           const double* __restrict__ spos,
@@ -103,7 +161,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
                                                           double4* __restrict__ out) {
   constexpr int STR = coef_stride(P);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kForceWaves + wid);
+  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
@@ -112,38 +170,73 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
   center_of(C.key[A], C.level[A], L, cA);
   const uint32_t off = G.off_m2p[g], cnt = G.cnt_m2p[g];
   const T* __restrict__ coef = (const T*)C.coef;
-  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
-    const uint32_t s = first + t0 + lane;
-    const bool act = s < first + count;
+  const uint32_t tail0 = count - count % 64;  // start of a pass of < 64 targets
+  const bool has_tail = count % 64 != 0 && count % 64 <= 32;
+  if (TAIL && !has_tail) return;
+  for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
+    const uint32_t rem = count - t0;
+    if (!TAIL && rem <= 32) break;
+    const int split = !TAIL ? 1 : rem <= 16 ? 4 : 2;  // wave-uniform
+    const int width = 64 / split;
+    const int sub = lane / width, tl = lane % width;
+    const uint32_t s = first + t0 + tl;
+    const bool act = (uint32_t)tl < rem;
     const uint32_t ss = act ? s : first;
     const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
             tz = (T)(spos[2 * n + ss] - cA[2]);
     Acc<T> acc;
     acc.zero();
     T part[4] = {0, 0, 0, 0};
-    for (uint32_t q = 0; q < cnt; ++q) {
-      T c[3];
-      const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-      T r[4];
-      m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, coef + (size_t)B * STR, r);
+    if (!TAIL) {
+      for (uint32_t q = 0; q < cnt; ++q) {
+        T c[3];
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        T r[4];
+        m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, coef + (size_t)B * STR,
+                                 r);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) part[k] += r[k];
-      // the potential sums many same-signed terms that the far field later
-      // cancels almost entirely: fold every term
-      acc.fold1(3, r[3]);
-      if ((q & 15) == 15) {
-        acc.fold(part);
+        for (int k = 0; k < 3; ++k) part[k] += r[k];
+        // the potential sums many same-signed terms that the far field later
+        // cancels almost entirely: fold every term
+        acc.fold1(3, r[3]);
+        if ((q & 15) == 15) {
+          acc.fold(part);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) part[k] = (T)0;
+          for (int k = 0; k < 3; ++k) part[k] = (T)0;
+        }
+      }
+    } else {
+      uint32_t it = 0;
+      for (uint32_t q = (uint32_t)sub; q < cnt; q += (uint32_t)split) {
+        T c[3];
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        T cf[STR];
+        load_block<T, STR>(coef + (size_t)B * STR, cf);
+        T r[4];
+        m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, cf, r);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) part[k] += r[k];
+        acc.fold1(3, r[3]);
+        if ((++it & 15) == 0) {
+          acc.fold(part);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) part[k] = (T)0;
+        }
       }
     }
     acc.fold(part);
-    if (act) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = acc.get(k);
+    for (int w = width; w < 64; w <<= 1)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], w, 64);
+    if (act && sub == 0) {
       double4 o = out[s];
-      o.x += acc.get(0);
-      o.y += acc.get(1);
-      o.z += acc.get(2);
-      o.w += acc.get(3);
+      o.x += v[0];
+      o.y += v[1];
+      o.z += v[2];
+      o.w += v[3];
       out[s] = o;
     }
   }
@@ -154,12 +247,18 @@ hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngrou
                       const uint32_t* list, double4* out, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
-  if (fp32)
-    k_p2p<float, float4><<<blocks, 64 * kForceWaves, 0, s>>>(
-        C, G, ngroups, L, (float)(eps * eps), spos, (const float4*)srec, n, list, out);
-  else
-    k_p2p<double, double4><<<blocks, 64 * kForceWaves, 0, s>>>(
+  if (fp32) {
+    const float e2 = (float)(eps * eps);
+    k_p2p<float, float4, false><<<blocks, 64 * kForceWaves, 0, s>>>(
+        C, G, ngroups, L, e2, spos, (const float4*)srec, n, list, out);
+    k_p2p<float, float4, true><<<blocks, 64 * kForceWaves, 0, s>>>(
+        C, G, ngroups, L, e2, spos, (const float4*)srec, n, list, out);
+  } else {
+    k_p2p<double, double4, false><<<blocks, 64 * kForceWaves, 0, s>>>(
         C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n, list, out);
+    k_p2p<double, double4, true><<<blocks, 64 * kForceWaves, 0, s>>>(
+        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n, list, out);
+  }
   return hipGetLastError();
 }
 
@@ -168,12 +267,17 @@ static void m2p_launch_p(bool fp32, const Cells& C, const Groups& G, uint32_t ng
                          double eps, const double* spos, size_t n, const uint4* list,
                          double4* out, hipStream_t s) {
   unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
-  if (fp32)
-    k_m2p<P, float><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, (float)(eps * eps),
-                                                         spos, n, list, out);
-  else
-    k_m2p<P, double><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps * eps, spos, n,
-                                                          list, out);
+  if (fp32) {
+    k_m2p<P, float, false><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, (float)(eps * eps),
+                                                               spos, n, list, out);
+    k_m2p<P, float, true><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, (float)(eps * eps),
+                                                              spos, n, list, out);
+  } else {
+    k_m2p<P, double, false><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps * eps, spos,
+                                                                n, list, out);
+    k_m2p<P, double, true><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps * eps, spos,
+                                                               n, list, out);
+  }
 }
 
 hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,

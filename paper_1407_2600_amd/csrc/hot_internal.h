@@ -106,6 +106,19 @@ __host__ __device__ constexpr int m2p_flops(int P) {
 }
 constexpr int kP2PFlops = 20;
 
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its
+// own L2.  Kernels that give each wave one sink group renumber their blocks
+// so that every XCD receives one contiguous range of block indices:
+// neighbouring groups, which share most of their interaction lists, then
+// read the same cells through the same L2.  A bijection on [0, gridDim.x).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t b = blockIdx.x, nb = gridDim.x;
+  const uint32_t x = b % kXcds, i = b / kXcds;
+  const uint32_t q = nb / kXcds, r = nb % kXcds;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // ---------------------------------------------------------------------------
 // Device data of one force evaluation (pointers into the caller's workspace).
 // ---------------------------------------------------------------------------

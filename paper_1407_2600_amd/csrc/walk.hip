@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
                                                           uint32_t* __restrict__ status) {
   __shared__ uint32_t stack_all[kWalkWaves][STACK];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWalkWaves + wid);
+  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kWalkWaves + wid);
   if (g >= ngroups) return;  // whole wavefront leaves; no block barriers below
   uint32_t* st = stack_all[wid];
   const int A = G.cell[g];
