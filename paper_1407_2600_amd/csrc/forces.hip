@@ -160,6 +160,10 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
                                                           const uint4* __restrict__ list,
                                                           double4* __restrict__ out) {
   constexpr int STR = coef_stride(P);
+  // tail-pass staging: per wave, up to 4 entries' offsets, cells and blocks
+  __shared__ T tail_cf[TAIL ? kForceWaves : 1][4][TAIL ? STR : 1];
+  __shared__ T tail_c[TAIL ? kForceWaves : 1][4][4];
+  __shared__ int tail_b[TAIL ? kForceWaves : 1][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
@@ -206,22 +210,41 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
         }
       }
     } else {
+      // each round stages the next `split` entries' offsets and coefficient
+      // blocks in this wave's LDS slots with coalesced loads; every sub-group
+      // then reads its own block (a broadcast within the sub-group)
+      T* cbuf = &tail_cf[wid][0][0];
       uint32_t it = 0;
-      for (uint32_t q = (uint32_t)sub; q < cnt; q += (uint32_t)split) {
-        T c[3];
-        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-        T cf[STR];
-        load_block<T, STR>(coef + (size_t)B * STR, cf);
-        T r[4];
-        m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, cf, r);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) part[k] += r[k];
-        acc.fold1(3, r[3]);
-        if ((++it & 15) == 0) {
-          acc.fold(part);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) part[k] = (T)0;
+      for (uint32_t q0 = 0; q0 < cnt; q0 += (uint32_t)split) {
+        const uint32_t ne = cnt - q0 < (uint32_t)split ? cnt - q0 : (uint32_t)split;
+        if ((uint32_t)lane < ne) {
+          T c[3];
+          const int B = m2p_record<T>(list[off + q0 + lane], C.walk, L, cA, c);
+          tail_c[wid][lane][0] = c[0];
+          tail_c[wid][lane][1] = c[1];
+          tail_c[wid][lane][2] = c[2];
+          tail_b[wid][lane] = B;
         }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = (uint32_t)lane; i < ne * STR; i += 64) {
+          const uint32_t e = i / STR, k = i % STR;
+          cbuf[i] = coef[(size_t)tail_b[wid][e] * STR + k];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (sub < ne) {
+          T r[4];
+          m2p_eval<P, false, T, T>(tx - tail_c[wid][sub][0], ty - tail_c[wid][sub][1],
+                                   tz - tail_c[wid][sub][2], eps2, cbuf + (size_t)sub * STR, r);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) part[k] += r[k];
+          acc.fold1(3, r[3]);
+          if ((++it & 15) == 0) {
+            acc.fold(part);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) part[k] = (T)0;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
     acc.fold(part);
