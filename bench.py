@@ -289,6 +289,11 @@ def main():
                   (r32["kern"][f"ms_{other}"] * 1e-3) / 1e12,
                   "ms_per_launch": r32["kern"][f"ms_{other}"]}
 
+    traj = None
+    if args.n_side is None and args.workload == "zeldovich128":
+        traj = trajectory_adjoint(torch, dev)
+        print(f"[bench] trajectory adjoint: {traj}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline and args.n_side is None and args.workload == "zeldovich128":
         cpu = cpu_baseline(pos_np, mass_np, prm, args.cpu_seconds)
@@ -323,6 +328,7 @@ def main():
         "rms_force_err": err,
         "adjoint_over_forward": r32["adjoint"]["ratio"],
         "adjoint": r32["adjoint"],
+        "trajectory_adjoint": traj,
         "interactions_per_s": (r32["pairs"]["p2p"] + r32["pairs"]["m2p"]) /
                               (r32["ms_per_step"] * 1e-3),
         "stage_ms": r32["kern"],
@@ -333,6 +339,43 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def trajectory_adjoint(torch, dev, precision="fp64", nsteps=10, dt=0.01):
+    """The differentiation workload: 64^3 Zel'dovich particles at rest, 10
+    KDK steps with per-step checkpoints, loss = sum of squared minimum-image
+    distances to a second seed's end state; forward and backward times."""
+    import workloads
+    from paper_1407_2600_amd import Gravity, checkpointed_kdk
+    pos, mass, prm = workloads.make("adjoint64")
+    pos_t, _, _ = workloads.make("adjoint64", seed=workloads.WORKLOADS["adjoint64"]["seed"] + 100)
+    g = Gravity(device=dev, precision=precision, **prm)
+    dt_ = torch.float32 if precision == "fp32" else torch.float64
+    M = torch.as_tensor(mass, dtype=dt_, device=dev)
+    V0 = torch.zeros((3, pos.shape[1]), dtype=dt_, device=dev)
+    with torch.no_grad():
+        xt, _ = checkpointed_kdk(g, torch.as_tensor(pos_t, device=dev), V0, M, dt, nsteps)
+    L = float(prm["box"])
+    times = []
+    for _ in range(2):  # the first round sizes the workspace
+        P = torch.as_tensor(pos, device=dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xf, _ = checkpointed_kdk(g, P, V0, M, dt, nsteps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        d = xf - xt
+        d = d - L * torch.round(d / L)
+        (d * d).sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = times[-1]
+    return {"workload": f"zeldovich 64^3={pos.shape[1]} particles at rest, {nsteps} KDK steps "
+                        f"dt={dt}, theta={prm['theta']}, order {prm['order']}, "
+                        "per-step position checkpoints",
+            "precision": precision, "ms_forward": 1e3 * fwd, "ms_backward": 1e3 * bwd,
+            "backward_over_forward": bwd / fwd}
 
 
 def cpu_baseline(pos, mass, prm, seconds):

@@ -148,9 +148,9 @@ __device__ __forceinline__ void load_block(const T* __restrict__ p, T* out) {
 // loads of the record and the cell's coefficients).  TAIL = true: the last
 // pass when it has at most 32 targets (the remainder of a group of 65..96,
 // or a small group); the wave splits into 2 or 4 sub-groups of 32 or 16 lanes
-// that take every 2nd or 4th list entry with per-lane loads, and the partial
-// sums are added across the sub-groups at the end, so the lanes a short pass
-// would leave idle do the work.  Separate launches keep the register budget
+// that take every 2nd or 4th list entry, and the partial sums are added
+// across the sub-groups at the end, so the lanes a short pass would leave
+// idle do the work.  Separate launches keep the register budget
 // (and occupancy) of the main pass independent of the tail's.
 template <int P, typename T, bool TAIL>
 __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uint32_t ngroups,
@@ -161,9 +161,10 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
                                                           double4* __restrict__ out) {
   constexpr int STR = coef_stride(P);
   // tail-pass staging: per wave, up to 4 entries' offsets, cells and blocks
-  __shared__ T tail_cf[TAIL ? kForceWaves : 1][4][TAIL ? STR : 1];
-  __shared__ T tail_c[TAIL ? kForceWaves : 1][4][4];
-  __shared__ int tail_b[TAIL ? kForceWaves : 1][4];
+  constexpr bool kStage = TAIL && sizeof(T) == 8;
+  __shared__ T tail_cf[kStage ? kForceWaves : 1][4][kStage ? STR : 1];
+  __shared__ T tail_c[kStage ? kForceWaves : 1][4][4];
+  __shared__ int tail_b[kStage ? kForceWaves : 1][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
@@ -209,10 +210,31 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
           for (int k = 0; k < 3; ++k) part[k] = (T)0;
         }
       }
+    } else if constexpr (sizeof(T) == 4) {
+      // FP32: each sub-group loads its own entries' records and 288-byte
+      // coefficient blocks with 16-byte per-lane loads (measured faster than
+      // staging them through LDS for FP32 blocks)
+      uint32_t it = 0;
+      for (uint32_t q = (uint32_t)sub; q < cnt; q += (uint32_t)split) {
+        T c[3];
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        T cf[STR];
+        load_block<T, STR>(coef + (size_t)B * STR, cf);
+        T r[4];
+        m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, cf, r);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) part[k] += r[k];
+        acc.fold1(3, r[3]);
+        if ((++it & 15) == 0) {
+          acc.fold(part);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) part[k] = (T)0;
+        }
+      }
     } else {
-      // each round stages the next `split` entries' offsets and coefficient
-      // blocks in this wave's LDS slots with coalesced loads; every sub-group
-      // then reads its own block (a broadcast within the sub-group)
+      // FP64: each round stages the next `split` entries' offsets and
+      // coefficient blocks in this wave's LDS slots with coalesced loads;
+      // every sub-group then reads its own block (a broadcast within it)
       T* cbuf = &tail_cf[wid][0][0];
       uint32_t it = 0;
       for (uint32_t q0 = 0; q0 < cnt; q0 += (uint32_t)split) {
