@@ -82,11 +82,11 @@ WORKLOADS = {
 # counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
 # They hold only for the sources and the configuration they were taken with;
 # otherwise the roofline reports traffic as null.
-TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 7.303e+09,
+TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 2.686e+09,
            "config": {"theta": 0.7, "err_tol": 0.00488, "order": 4, "leaf_max": 16,
                       "group_max": 128, "far_order": 8},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
-           "sha256": "d26a890d8995ea453e1bce9620967a3609304eb9249d5caa1cc07e34adc792fd"}
+           "sha256": "f3e1983c75e272955c444cf345a21e02ee2900d568266f99f032aa2a1adad8c8"}
 
 
 def measured_traffic(prm, workload):
@@ -291,7 +291,7 @@ def main():
 
     traj = None
     if args.n_side is None and args.workload == "zeldovich128":
-        traj = trajectory_adjoint(torch, dev)
+        traj = {prec: trajectory_adjoint(torch, dev, prec) for prec in ("fp32", "fp64")}
         print(f"[bench] trajectory adjoint: {traj}", file=sys.stderr, flush=True)
 
     cpu = None

@@ -225,7 +225,13 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
 }
 
 // --------------------------------------------------------------- multipole
-template <int P, typename T, typename T4>
+// Passes of up to 64 targets as in the forward kernel: TAIL = false takes the
+// passes over more than 32 targets with wave-uniform (scalar) loads; TAIL =
+// true takes a last pass of at most 32 targets and splits the wave into 2 or
+// 4 sub-groups that share out the list entries, each round staging the
+// entries' mass and effective-charge coefficient blocks through LDS with
+// coalesced loads, and adds the sub-groups' partial sums at the end.
+template <int P, typename T, typename T4, bool TAIL>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, uint32_t ngroups,
                                                             double L, T eps2,
                                                             const double* __restrict__ spos,
@@ -236,19 +242,32 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
                                                             double4* __restrict__ out) {
   constexpr int STR = coef_stride(P);
   constexpr int ESTR = coef_stride(P + 1, true);
+  __shared__ T tl_cf[TAIL ? kAdjWaves : 1][4][TAIL ? STR : 1];
+  __shared__ T tl_ef[TAIL ? kAdjWaves : 1][4][TAIL ? ESTR : 1];
+  __shared__ T tl_c[TAIL ? kAdjWaves : 1][4][4];
+  __shared__ int tl_b[TAIL ? kAdjWaves : 1][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kAdjWaves + wid);
   if (g >= ngroups) return;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
+  const uint32_t tail0 = count - count % 64;
+  const bool has_tail = count % 64 != 0 && count % 64 <= 32;
+  if (TAIL && !has_tail) return;
   double cA[3];
   center_of(C.key[A], C.level[A], L, cA);
   const uint32_t off = G.off_m2p[g], cnt = G.cnt_m2p[g];
   const T* __restrict__ coef = (const T*)C.coef;
-  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
-    const uint32_t s = first + t0 + lane;
-    const bool act = s < first + count;
+  for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
+    const uint32_t rem = count - t0;
+    if (!TAIL && rem <= 32) break;
+    const uint32_t split = !TAIL ? 1u : rem <= 16 ? 4u : 2u;  // wave-uniform
+    const int width = 64 / (int)split;
+    const uint32_t sub = (uint32_t)(lane / width);
+    const int tl = lane % width;
+    const uint32_t s = first + t0 + tl;
+    const bool act = (uint32_t)tl < rem;
     const uint32_t ss = act ? s : first;
     const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
             tz = (T)(spos[2 * n + ss] - cA[2]);
@@ -257,34 +276,75 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
     Acc<T> acc;
     acc.zero();
     T part[4] = {0, 0, 0, 0};
-    for (uint32_t q = 0; q < cnt; ++q) {
-      T c[3];
-      const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-      const T Rx = tx - c[0], Ry = ty - c[1], Rz = tz - c[2];
-      // mass field and its derivative along gacc_k
+    // one (target, cell) term: the mass field and its derivative along gacc_k
+    // (dual numbers), and the effective charges' potential and gradient
+    auto term = [&](T Rx, T Ry, T Rz, const T* cf, const T* ef) {
       Dual<T> fm[4];
       m2p_eval<P, false, Dual<T>, T>(Dual<T>(Rx, ak.x), Dual<T>(Ry, ak.y), Dual<T>(Rz, ak.z),
-                                     eps2, coef + (size_t)B * STR, fm);
-      // effective charges: potential psi and its gradient
+                                     eps2, cf, fm);
       T fe[4];
-      m2p_eval<P + 1, true, T, T>(Rx, Ry, Rz, eps2, ecoef + (size_t)B * ESTR, fe);
+      m2p_eval<P + 1, true, T, T>(Rx, Ry, Rz, eps2, ef, fe);
       part[0] += fm[0].d - ak.w * fm[0].v - mk * fe[0];
       part[1] += fm[1].d - ak.w * fm[1].v - mk * fe[1];
       part[2] += fm[2].d - ak.w * fm[2].v - mk * fe[2];
       part[3] -= fe[3];
-      if ((q & 15) == 15) {
-        acc.fold(part);
+    };
+    if (!TAIL) {
+      for (uint32_t q = 0; q < cnt; ++q) {
+        T c[3];
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        term(tx - c[0], ty - c[1], tz - c[2], coef + (size_t)B * STR, ecoef + (size_t)B * ESTR);
+        if ((q & 15) == 15) {
+          acc.fold(part);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) part[k] = (T)0;
+          for (int k = 0; k < 4; ++k) part[k] = (T)0;
+        }
+      }
+    } else {
+      T* cbuf = &tl_cf[wid][0][0];
+      T* ebuf = &tl_ef[wid][0][0];
+      uint32_t it = 0;
+      for (uint32_t q0 = 0; q0 < cnt; q0 += split) {
+        const uint32_t ne = cnt - q0 < split ? cnt - q0 : split;
+        if ((uint32_t)lane < ne) {
+          T c[3];
+          const int B = m2p_record<T>(list[off + q0 + lane], C.walk, L, cA, c);
+          tl_c[wid][lane][0] = c[0];
+          tl_c[wid][lane][1] = c[1];
+          tl_c[wid][lane][2] = c[2];
+          tl_b[wid][lane] = B;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = (uint32_t)lane; i < ne * STR; i += 64)
+          cbuf[i] = coef[(size_t)tl_b[wid][i / STR] * STR + i % STR];
+        for (uint32_t i = (uint32_t)lane; i < ne * ESTR; i += 64)
+          ebuf[i] = ecoef[(size_t)tl_b[wid][i / ESTR] * ESTR + i % ESTR];
+        __builtin_amdgcn_wave_barrier();
+        if (sub < ne) {
+          term(tx - tl_c[wid][sub][0], ty - tl_c[wid][sub][1], tz - tl_c[wid][sub][2],
+               cbuf + (size_t)sub * STR, ebuf + (size_t)sub * ESTR);
+          if ((++it & 15) == 0) {
+            acc.fold(part);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) part[k] = (T)0;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
     acc.fold(part);
-    if (act) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = acc.get(k);
+    for (int w = width; w < 64; w <<= 1)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], w, 64);
+    if (act && sub == 0) {
       double4 o = out[s];
-      o.x += acc.get(0);
-      o.y += acc.get(1);
-      o.z += acc.get(2);
-      o.w += acc.get(3);
+      o.x += v[0];
+      o.y += v[1];
+      o.z += v[2];
+      o.w += v[3];
       out[s] = o;
     }
   }
@@ -347,14 +407,22 @@ static void m2p_adj_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngrou
                       const void* ecoef, size_t n, const uint4* list, double4* out,
                       hipStream_t s) {
   unsigned blocks = (ngroups + kAdjWaves - 1) / kAdjWaves;
-  if (fp32)
-    k_m2p_adj<P, float, float4><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, (float)(eps * eps), spos, (const float4*)srec, (const float4*)arec,
+  if (fp32) {
+    const float e2 = (float)(eps * eps);
+    k_m2p_adj<P, float, float4, false><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, e2, spos, (const float4*)srec, (const float4*)arec,
         (const float*)ecoef, n, list, out);
-  else
-    k_m2p_adj<P, double, double4><<<blocks, 64 * kAdjWaves, 0, s>>>(
+    k_m2p_adj<P, float, float4, true><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, e2, spos, (const float4*)srec, (const float4*)arec,
+        (const float*)ecoef, n, list, out);
+  } else {
+    k_m2p_adj<P, double, double4, false><<<blocks, 64 * kAdjWaves, 0, s>>>(
         C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec,
         (const double*)ecoef, n, list, out);
+    k_m2p_adj<P, double, double4, true><<<blocks, 64 * kAdjWaves, 0, s>>>(
+        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec,
+        (const double*)ecoef, n, list, out);
+  }
 }
 
 hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
