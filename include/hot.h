@@ -159,17 +159,25 @@ hot_status hot_create(const hot_params* params, hot_ctx** out);
 /* Release a context (NULL is allowed). */
 void hot_destroy(hot_ctx* ctx);
 
-/* Preferred bytes of device workspace for a compute call on n particles:
- * room for all interaction lists at once (up to 4 GiB of lists).  Grows
+/* Preferred bytes of device workspace for any compute call on n particles:
+ * every structure, and room for all interaction lists at once (up to 4 GiB
+ * of lists).  Grows
  * after a call that needed more, so the next call fits.  0 if ctx is NULL. */
 size_t hot_workspace_size(const hot_ctx* ctx, size_t n);
 
-/* Smallest workspace a compute call accepts for n particles: every per-
- * particle and per-cell structure plus 1 MiB of list space.  Between this and
- * hot_workspace_size the interaction lists are built and consumed in chunks
- * of consecutive sink groups (paper Sec. 2.1: groups are independent), which
- * gives the same results.  0 if ctx is NULL. */
-size_t hot_workspace_size_min(const hot_ctx* ctx, size_t n);
+/* Smallest workspace the given calls accept for n particles (calls: a
+ * bitwise OR of HOT_CALL_*): the structures those calls use plus 1 MiB of
+ * list space.  hot_forces needs only the forward structures; hot_kdk adds
+ * state snapshots; hot_vjp adds the adjoint's cotangent structures;
+ * hot_kdk_vjp needs both.  Between this and hot_workspace_size the
+ * interaction lists are built and consumed in chunks of consecutive sink
+ * groups (paper Sec. 2.1: groups are independent), which gives the same
+ * results.  0 if ctx is NULL. */
+#define HOT_CALL_FORCES 1u
+#define HOT_CALL_KDK 2u
+#define HOT_CALL_VJP 4u
+#define HOT_CALL_KDK_VJP 8u
+size_t hot_workspace_size_min(const hot_ctx* ctx, size_t n, unsigned calls);
 
 /* Accelerations and potentials of n particles (paper Sec. 2.1: the force
  * evaluation of one timestep).

@@ -99,6 +99,8 @@ enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_
 constexpr size_t kListMaxWords = size_t(1) << 30;
 // smallest list region accepted (bytes)
 constexpr size_t kListMinBytes = size_t(1) << 20;
+// workspace regions a call needs beyond the forward ones
+constexpr unsigned kNeedAdjoint = 1, kNeedKdk = 2;
 
 bool valid_params(const hot_params* p, std::string* why) {
   if (!(p->box > 0.0) || !std::isfinite(p->box)) return *why = "box must be finite and > 0", false;
@@ -118,7 +120,7 @@ bool valid_params(const hot_params* p, std::string* why) {
   return true;
 }
 
-Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
+Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes, unsigned need) {
   Plan P{};
   P.n = n;
   const bool fp32 = c->p.precision == HOT_FP32;
@@ -171,28 +173,45 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes) {
   P.o_far_part = take(8 * 8 * (size_t)NQ * kFarBlocks);
   P.o_far_mom = take(8 * 8 * (size_t)NQ);
   P.o_far_lam = take(8 * 8 * (size_t)NQ);
-  // adjoint: sorted cotangents, per-particle results, effective charge
-  // moments (order p+1) and coefficients, far-field adjoint moments
-  P.o_arec = take(4 * tsz * n);
-  P.o_adj = take(32 * n);
-  P.o_c_emom = take(8 * (size_t)(nt(c->p.order + 1) + nt(c->p.order)) * C);
-  P.o_c_ecoef = take(tsz * (size_t)coef_stride(c->p.order + 1, true) * C);
-  P.o_far_mbar = take(8 * 8 * (size_t)NQ);
-  P.o_kv_g = take(3 * tsz * n);
-  P.o_kv_x = take(24 * n);
-  P.o_kv_m = take(tsz * n);
-  P.o_kv_sx = take(24 * n);
-  P.o_kv_sv = take(3 * tsz * n);
+  // ---- list region, then the regions only some calls use, carved from the
+  // top of the workspace so that a forward-only caller need not provide them
   P.o_list = o;
   const size_t want_list =
       std::max(std::min((size_t)std::ceil(c->list_per_particle * (double)n) + 65536, kListMaxWords),
                kListMinBytes / 4);
-  if (ws_bytes == 0) {
-    P.cap_list = want_list;
-  } else {
-    P.cap_list = ws_bytes > o ? (ws_bytes - o) / 4 : 0;
+  const size_t C2 = P.cap_cells;
+  // adjoint: sorted cotangents, per-particle results, cotangent moments
+  // (charges order p, gacc-derived order p+1) and coefficients, far-field
+  // adjoint moments
+  const size_t sz_arec = up(4 * tsz * n), sz_adj = up(32 * n);
+  const size_t sz_emom = up(8 * (size_t)(nt(c->p.order + 1) + nt(c->p.order)) * C2);
+  const size_t sz_ecoef = up(tsz * (size_t)coef_stride(c->p.order + 1, true) * C2);
+  const size_t sz_fmbar = up(8 * 8 * (size_t)NQ);
+  const size_t bytes_a = sz_arec + sz_adj + sz_emom + sz_ecoef + sz_fmbar;
+  // leapfrog: reverse-sweep scratch and the in/out snapshots
+  const size_t sz_g = up(3 * tsz * n), sz_x = up(24 * n), sz_m = up(tsz * n);
+  const size_t sz_sx = up(24 * n), sz_sv = up(3 * tsz * n);
+  const size_t bytes_k = sz_g + sz_x + sz_m + sz_sx + sz_sv;
+  P.total = o + up(4 * want_list) + bytes_a + bytes_k;
+  const size_t top = ((need & kNeedAdjoint) ? bytes_a : 0) + ((need & kNeedKdk) ? bytes_k : 0);
+  P.min_total = o + kListMinBytes + top;
+  size_t t = ws_bytes == 0 ? P.total : (ws_bytes & ~size_t(255));
+  if (t < o + top) t = o + top;  // (the caller's size is checked against min_total)
+  if (need & kNeedKdk) {
+    P.o_kv_sv = (t -= sz_sv);
+    P.o_kv_sx = (t -= sz_sx);
+    P.o_kv_m = (t -= sz_m);
+    P.o_kv_x = (t -= sz_x);
+    P.o_kv_g = (t -= sz_g);
   }
-  P.total = o + up(4 * want_list);
+  if (need & kNeedAdjoint) {
+    P.o_far_mbar = (t -= sz_fmbar);
+    P.o_c_ecoef = (t -= sz_ecoef);
+    P.o_c_emom = (t -= sz_emom);
+    P.o_adj = (t -= sz_adj);
+    P.o_arec = (t -= sz_arec);
+  }
+  P.cap_list = ws_bytes == 0 ? want_list : (t - o) / 4;
   return P;
 }
 
@@ -260,14 +279,16 @@ struct VjpArgs {
   void* mbar;
 };
 
+// need: the optional workspace regions of the calling entry point (the
+// layout must be the same for every evaluation within one call)
 static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
-                              void* pot, void* ws, size_t ws_bytes, hipStream_t s,
+                              void* pot, void* ws, size_t ws_bytes, hipStream_t s, unsigned need,
                               const VjpArgs* vjp = nullptr) {
   const hot_params& p = c->p;
   const bool fp32 = p.precision == HOT_FP32;
-  Plan P = make_plan(c, n, ws_bytes);
-  if (ws_bytes < P.o_list + kListMinBytes) {
-    g_err = "workspace too small: need at least " + std::to_string(P.o_list + kListMinBytes) +
+  Plan P = make_plan(c, n, ws_bytes, need);
+  if (ws_bytes < P.min_total) {
+    g_err = "workspace too small: need at least " + std::to_string(P.min_total) +
             " bytes (" + std::to_string(P.total) + " preferred), got " + std::to_string(ws_bytes);
     c->stats.ws_bytes_needed = P.total;
     return HOT_ENOMEM;
@@ -321,7 +342,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     if (tot == 0) break;
     if ((size_t)lvl[l + 1] + tot > P.cap_cells) {
       c->cells_per_particle *= 2.0;
-      c->stats.ws_bytes_needed = make_plan(c, n, 0).total;
+      c->stats.ws_bytes_needed = make_plan(c, n, 0, need).total;
       g_err = "cell capacity exceeded; call hot_workspace_size again and retry";
       return HOT_EOVERFLOW;
     }
@@ -380,7 +401,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   const size_t words = tp + 4 * tm + 4;
   c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)words / (double)n);
   if (maxw + 4 > P.cap_list) {
-    c->stats.ws_bytes_needed = make_plan(c, n, 0).total;
+    c->stats.ws_bytes_needed = make_plan(c, n, 0, need).total;
     g_err = "interaction-list capacity below one group's lists; call hot_workspace_size again";
     return HOT_EOVERFLOW;
   }
@@ -588,12 +609,15 @@ void hot_destroy(hot_ctx* c) {
 
 size_t hot_workspace_size(const hot_ctx* c, size_t n) {
   if (!c) return 0;
-  return make_plan(c, n, 0).total;
+  return make_plan(c, n, 0, kNeedAdjoint | kNeedKdk).total;
 }
 
-size_t hot_workspace_size_min(const hot_ctx* c, size_t n) {
+size_t hot_workspace_size_min(const hot_ctx* c, size_t n, unsigned calls) {
   if (!c) return 0;
-  return make_plan(c, n, 0).o_list + kListMinBytes;
+  unsigned need = 0;
+  if (calls & (HOT_CALL_VJP | HOT_CALL_KDK_VJP)) need |= kNeedAdjoint;
+  if (calls & (HOT_CALL_KDK | HOT_CALL_KDK_VJP)) need |= kNeedKdk;
+  return make_plan(c, n, 0, need).min_total;
 }
 
 hot_status hot_forces(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
@@ -611,7 +635,7 @@ hot_status hot_forces(hot_ctx* c, size_t n, const double* pos, const void* mass,
     g_err = "n must be < 2^32";
     return HOT_EINVAL;
   }
-  return forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, (hipStream_t)stream);
+  return forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, (hipStream_t)stream, 0);
 }
 
 hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mass, void* acc,
@@ -630,14 +654,14 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
   const bool fp32 = c->p.precision == HOT_FP32;
   const size_t tsz = fp32 ? 4 : 8;
   c->stats.kdk_steps_done = 0;
-  const Plan P = make_plan(c, n, ws_bytes);
-  if (ws_bytes < P.o_list + kListMinBytes) {  // the snapshot regions lie below the lists
-    g_err = "workspace smaller than hot_workspace_size_min()";
+  const Plan P = make_plan(c, n, ws_bytes, kNeedKdk);
+  if (ws_bytes < P.min_total) {
+    g_err = "workspace smaller than hot_workspace_size_min(HOT_CALL_KDK)";
     return HOT_ENOMEM;
   }
   hot_status st;
   if (!(flags & HOT_ACC_VALID)) {
-    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s);
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, kNeedKdk);
     if (st != HOT_OK) return st;
   }
   double* sx = at<double>(ws, P.o_kv_sx);
@@ -648,7 +672,7 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
     HOT_CHECK(hipMemcpyAsync(sv, vel, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
     HOT_CHECK(drift_launch(fp32, pos, vel, n, dt, c->p.box, s), "drift");
-    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s);
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, kNeedKdk);
     if (st != HOT_OK) {
       // acc is written only by a successful evaluation
       HOT_CHECK(hipMemcpyAsync(pos, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
@@ -679,7 +703,8 @@ hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, co
     return HOT_EINVAL;
   }
   VjpArgs a{gacc, gpot, xbar, mbar};
-  return forces_impl(c, n, pos, mass, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, &a);
+  return forces_impl(c, n, pos, mass, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream,
+                     kNeedAdjoint, &a);
 }
 
 hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt, const void* mass,
@@ -707,9 +732,9 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
   }
   // the scratch of the sweep sits in the workspace regions reserved for it,
   // which the force derivative itself does not touch
-  Plan P = make_plan(c, n, ws_bytes);
-  if (ws_bytes < P.o_list + kListMinBytes) {
-    g_err = "workspace smaller than hot_workspace_size_min()";
+  Plan P = make_plan(c, n, ws_bytes, kNeedAdjoint | kNeedKdk);
+  if (ws_bytes < P.min_total) {
+    g_err = "workspace smaller than hot_workspace_size_min(HOT_CALL_KDK_VJP)";
     return HOT_ENOMEM;
   }
   void* gacc = at<void>(ws, P.o_kv_g);
@@ -727,7 +752,8 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
               "adjoint drift");
     VjpArgs a{gacc, nullptr, tx, tm};
     hot_status st = forces_impl(c, n, pos_ckpt + (size_t)k * stride, mass, nullptr, nullptr, ws,
-                                ws_bytes, s, &a);
+                                ws_bytes, s,
+                                kNeedAdjoint | kNeedKdk, &a);
     if (st != HOT_OK) {
       HOT_CHECK(hipMemcpyAsync(xbar, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
       HOT_CHECK(hipMemcpyAsync(vbar, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");

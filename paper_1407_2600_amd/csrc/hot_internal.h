@@ -151,8 +151,9 @@ struct Plan {
   size_t n;
   size_t cap_cells;
   size_t cap_groups;
-  size_t cap_list;   // list entries (p2p + m2p)
-  size_t total;      // bytes
+  size_t cap_list;   // list region in 4-byte words
+  size_t total;      // preferred bytes: every region, lists at their hinted size
+  size_t min_total;  // smallest workspace for the call the plan was made for
   // offsets of every buffer (bytes from the workspace start)
   size_t o_key[2], o_idx[2], o_spos, o_smass, o_srec, o_acc, o_tmp;
   size_t o_scan, o_hist, o_ctr;

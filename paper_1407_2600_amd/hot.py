@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhot.so")
 HOT_OK, HOT_EINVAL, HOT_ENOMEM, HOT_EOVERFLOW, HOT_EDEVICE, HOT_EUNSUPPORTED = range(6)
 HOT_FP64, HOT_FP32 = 0, 1
 HOT_ACC_VALID = 1
+HOT_CALL_FORCES, HOT_CALL_KDK, HOT_CALL_VJP, HOT_CALL_KDK_VJP = 1, 2, 4, 8
 STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW",
                 4: "HOT_EDEVICE", 5: "HOT_EUNSUPPORTED"}
 
@@ -79,7 +80,7 @@ def lib():
         L.hot_workspace_size.restype = sz
         L.hot_workspace_size.argtypes = [vp, sz]
         L.hot_workspace_size_min.restype = sz
-        L.hot_workspace_size_min.argtypes = [vp, sz]
+        L.hot_workspace_size_min.argtypes = [vp, sz, C.c_uint]
         L.hot_forces.restype = C.c_int
         L.hot_forces.argtypes = [vp, sz, vp, vp, vp, vp, vp, sz, vp]
         L.hot_kdk.restype = C.c_int
@@ -162,10 +163,11 @@ class Gravity:
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
 
-    def _workspace(self, n: int):
+    def _workspace(self, n: int, calls: int = HOT_CALL_FORCES):
         need = self.L.hot_workspace_size(self.h, n)
         if self.ws_cap is not None:
-            need = max(min(need, int(self.ws_cap)), self.L.hot_workspace_size_min(self.h, n))
+            need = max(min(need, int(self.ws_cap)),
+                       self.L.hot_workspace_size_min(self.h, n, calls))
         if self.ws is None or self.ws.numel() < need:
             self.ws = None
             self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
@@ -181,9 +183,9 @@ class Gravity:
             raise ValueError(f"mass must be a (N,) {self.dtype} tensor")
         return pos.contiguous(), mass.contiguous()
 
-    def _call_retry(self, fn, n):
+    def _call_retry(self, fn, n, calls=HOT_CALL_FORCES):
         for _ in range(6):
-            ws = self._workspace(n)
+            ws = self._workspace(n, calls)
             st = fn(ws)
             if st != HOT_EOVERFLOW:
                 check(st)
@@ -225,7 +227,7 @@ class Gravity:
         # after HOT_EOVERFLOW the library has restored the state at the end of
         # the last completed step; resume from there with a larger workspace
         for _ in range(6):
-            ws = self._workspace(n)
+            ws = self._workspace(n, HOT_CALL_KDK)
             st = self.L.hot_kdk(self.h, n, C.c_void_p(pos.data_ptr()),
                                 C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
                                 C.c_void_p(acc.data_ptr()),
@@ -264,7 +266,7 @@ class Gravity:
                                       C.c_void_p(xbar.data_ptr()), C.c_void_p(vbar.data_ptr()),
                                       C.c_void_p(mbar.data_ptr()), C.c_void_p(ws.data_ptr()),
                                       ws.numel(), s)
-        self._call_retry(run, n)
+        self._call_retry(run, n, HOT_CALL_KDK_VJP)
         return mbar
 
     def vjp(self, pos, mass, gacc, gpot=None):
@@ -284,7 +286,7 @@ class Gravity:
                                   C.c_void_p(gpot.data_ptr() if gpot is not None else 0),
                                   C.c_void_p(xbar.data_ptr()), C.c_void_p(mbar.data_ptr()),
                                   C.c_void_p(ws.data_ptr()), ws.numel(), s)
-        self._call_retry(run, n)
+        self._call_retry(run, n, HOT_CALL_VJP)
         return xbar, mbar
 
     def stats(self) -> dict:

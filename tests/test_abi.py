@@ -58,7 +58,7 @@ def test_null_arguments():
     L = hot.lib()
     assert L.hot_forces(None, 10, None, None, None, None, None, 0, None) == hot.HOT_EINVAL
     assert L.hot_workspace_size(None, 100) == 0
-    assert L.hot_workspace_size_min(None, 100) == 0
+    assert L.hot_workspace_size_min(None, 100, 1) == 0
     assert L.hot_get_stats(None, None) == hot.HOT_EINVAL
     L.hot_destroy(None)
 

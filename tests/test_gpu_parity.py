@@ -233,7 +233,7 @@ def test_chunked_lists_match_single_pass(precision):
     torch.cuda.synchronize()
     s1 = g1.stats()
     assert s1["list_chunks"] == 1
-    wmin = g1.L.hot_workspace_size_min(g1.h, pos.shape[1])
+    wmin = g1.L.hot_workspace_size_min(g1.h, pos.shape[1], 1)
     g2 = Gravity(precision=precision, workspace_bytes=wmin, **prm)
     a2, p2 = g2.forces(P, M)
     torch.cuda.synchronize()
