@@ -207,8 +207,12 @@ hot_status hot_forces(hot_ctx* ctx, size_t n, const double* pos, const void* mas
  * workspace); hot_get_stats reports that step count as kdk_steps_done, and
  * acc is valid there whenever kdk_steps_done > 0 or HOT_ACC_VALID was given,
  * so after HOT_EOVERFLOW the caller resizes the workspace and repeats the
- * call for the remaining steps. */
+ * call for the remaining steps.  With HOT_KDK_NO_SNAPSHOT no snapshot is
+ * kept (the workspace needs only hot_workspace_size_min(HOT_CALL_FORCES),
+ * 36 bytes per particle less), and after a failure pos and vel are
+ * undefined. */
 #define HOT_ACC_VALID 1u
+#define HOT_KDK_NO_SNAPSHOT 2u
 hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* mass, void* acc,
                    void* pot, double dt, int nsteps, unsigned flags, void* workspace,
                    size_t ws_bytes, void* stream);

@@ -100,7 +100,7 @@ constexpr size_t kListMaxWords = size_t(1) << 30;
 // smallest list region accepted (bytes)
 constexpr size_t kListMinBytes = size_t(1) << 20;
 // workspace regions a call needs beyond the forward ones
-constexpr unsigned kNeedAdjoint = 1, kNeedKdk = 2;
+constexpr unsigned kNeedAdjoint = 1, kNeedSnapshot = 2, kNeedReverse = 4;
 
 bool valid_params(const hot_params* p, std::string* why) {
   if (!(p->box > 0.0) || !std::isfinite(p->box)) return *why = "box must be finite and > 0", false;
@@ -188,18 +188,22 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes, unsigned need) {
   const size_t sz_ecoef = up(tsz * (size_t)coef_stride(c->p.order + 1, true) * C2);
   const size_t sz_fmbar = up(8 * 8 * (size_t)NQ);
   const size_t bytes_a = sz_arec + sz_adj + sz_emom + sz_ecoef + sz_fmbar;
-  // leapfrog: reverse-sweep scratch and the in/out snapshots
-  const size_t sz_g = up(3 * tsz * n), sz_x = up(24 * n), sz_m = up(tsz * n);
+  // leapfrog: the in/out snapshots, and the reverse sweep's scratch
   const size_t sz_sx = up(24 * n), sz_sv = up(3 * tsz * n);
-  const size_t bytes_k = sz_g + sz_x + sz_m + sz_sx + sz_sv;
-  P.total = o + up(4 * want_list) + bytes_a + bytes_k;
-  const size_t top = ((need & kNeedAdjoint) ? bytes_a : 0) + ((need & kNeedKdk) ? bytes_k : 0);
+  const size_t sz_g = up(3 * tsz * n), sz_x = up(24 * n), sz_m = up(tsz * n);
+  const size_t bytes_s = sz_sx + sz_sv, bytes_r = sz_g + sz_x + sz_m;
+  P.total = o + up(4 * want_list) + bytes_a + bytes_s + bytes_r;
+  const size_t top = ((need & kNeedAdjoint) ? bytes_a : 0) +
+                     ((need & kNeedSnapshot) ? bytes_s : 0) +
+                     ((need & kNeedReverse) ? bytes_r : 0);
   P.min_total = o + kListMinBytes + top;
   size_t t = ws_bytes == 0 ? P.total : (ws_bytes & ~size_t(255));
   if (t < o + top) t = o + top;  // (the caller's size is checked against min_total)
-  if (need & kNeedKdk) {
+  if (need & kNeedSnapshot) {
     P.o_kv_sv = (t -= sz_sv);
     P.o_kv_sx = (t -= sz_sx);
+  }
+  if (need & kNeedReverse) {
     P.o_kv_m = (t -= sz_m);
     P.o_kv_x = (t -= sz_x);
     P.o_kv_g = (t -= sz_g);
@@ -341,7 +345,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     const uint32_t tot = host[CTR_TOTAL];
     if (tot == 0) break;
     if ((size_t)lvl[l + 1] + tot > P.cap_cells) {
-      c->cells_per_particle *= 2.0;
+      c->cells_per_particle = std::min(2.0 * c->cells_per_particle,
+                                       (double)(kCellMask - 4096) / (double)n);
       c->stats.ws_bytes_needed = make_plan(c, n, 0, need).total;
       g_err = "cell capacity exceeded; call hot_workspace_size again and retry";
       return HOT_EOVERFLOW;
@@ -572,7 +577,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   std::memset(c, 0, sizeof(*c));
   c->p = *params;
   c->S = 2097152.0 / params->box;
-  c->cells_per_particle = 3.0 / params->leaf_max + 0.02;  // grows on overflow
+  c->cells_per_particle = 2.4 / params->leaf_max + 0.01;  // grows on overflow
   c->list_per_particle = 96.0;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
@@ -609,14 +614,15 @@ void hot_destroy(hot_ctx* c) {
 
 size_t hot_workspace_size(const hot_ctx* c, size_t n) {
   if (!c) return 0;
-  return make_plan(c, n, 0, kNeedAdjoint | kNeedKdk).total;
+  return make_plan(c, n, 0, kNeedAdjoint | kNeedSnapshot | kNeedReverse).total;
 }
 
 size_t hot_workspace_size_min(const hot_ctx* c, size_t n, unsigned calls) {
   if (!c) return 0;
   unsigned need = 0;
   if (calls & (HOT_CALL_VJP | HOT_CALL_KDK_VJP)) need |= kNeedAdjoint;
-  if (calls & (HOT_CALL_KDK | HOT_CALL_KDK_VJP)) need |= kNeedKdk;
+  if (calls & (HOT_CALL_KDK | HOT_CALL_KDK_VJP)) need |= kNeedSnapshot;
+  if (calls & HOT_CALL_KDK_VJP) need |= kNeedReverse;
   return make_plan(c, n, 0, need).min_total;
 }
 
@@ -654,30 +660,36 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
   const bool fp32 = c->p.precision == HOT_FP32;
   const size_t tsz = fp32 ? 4 : 8;
   c->stats.kdk_steps_done = 0;
-  const Plan P = make_plan(c, n, ws_bytes, kNeedKdk);
+  const bool snap = !(flags & HOT_KDK_NO_SNAPSHOT);
+  const unsigned need = snap ? kNeedSnapshot : 0;
+  const Plan P = make_plan(c, n, ws_bytes, need);
   if (ws_bytes < P.min_total) {
     g_err = "workspace smaller than hot_workspace_size_min(HOT_CALL_KDK)";
     return HOT_ENOMEM;
   }
   hot_status st;
   if (!(flags & HOT_ACC_VALID)) {
-    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, kNeedKdk);
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, need);
     if (st != HOT_OK) return st;
   }
-  double* sx = at<double>(ws, P.o_kv_sx);
-  void* sv = at<void>(ws, P.o_kv_sv);
+  double* sx = snap ? at<double>(ws, P.o_kv_sx) : nullptr;
+  void* sv = snap ? at<void>(ws, P.o_kv_sv) : nullptr;
   for (int k = 0; k < nsteps; ++k) {
     // snapshot of the step's start, restored if its force evaluation fails
-    HOT_CHECK(hipMemcpyAsync(sx, pos, 24 * n, hipMemcpyDeviceToDevice, s), "snapshot");
-    HOT_CHECK(hipMemcpyAsync(sv, vel, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
+    if (snap) {
+      HOT_CHECK(hipMemcpyAsync(sx, pos, 24 * n, hipMemcpyDeviceToDevice, s), "snapshot");
+      HOT_CHECK(hipMemcpyAsync(sv, vel, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
+    }
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
     HOT_CHECK(drift_launch(fp32, pos, vel, n, dt, c->p.box, s), "drift");
-    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, kNeedKdk);
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, need);
     if (st != HOT_OK) {
       // acc is written only by a successful evaluation
-      HOT_CHECK(hipMemcpyAsync(pos, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
-      HOT_CHECK(hipMemcpyAsync(vel, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");
-      HOT_CHECK(hipStreamSynchronize(s), "restore");
+      if (snap) {
+        HOT_CHECK(hipMemcpyAsync(pos, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
+        HOT_CHECK(hipMemcpyAsync(vel, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");
+        HOT_CHECK(hipStreamSynchronize(s), "restore");
+      }
       return st;
     }
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
@@ -732,7 +744,7 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
   }
   // the scratch of the sweep sits in the workspace regions reserved for it,
   // which the force derivative itself does not touch
-  Plan P = make_plan(c, n, ws_bytes, kNeedAdjoint | kNeedKdk);
+  Plan P = make_plan(c, n, ws_bytes, kNeedAdjoint | kNeedSnapshot | kNeedReverse);
   if (ws_bytes < P.min_total) {
     g_err = "workspace smaller than hot_workspace_size_min(HOT_CALL_KDK_VJP)";
     return HOT_ENOMEM;
@@ -753,7 +765,7 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
     VjpArgs a{gacc, nullptr, tx, tm};
     hot_status st = forces_impl(c, n, pos_ckpt + (size_t)k * stride, mass, nullptr, nullptr, ws,
                                 ws_bytes, s,
-                                kNeedAdjoint | kNeedKdk, &a);
+                                kNeedAdjoint | kNeedSnapshot | kNeedReverse, &a);
     if (st != HOT_OK) {
       HOT_CHECK(hipMemcpyAsync(xbar, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
       HOT_CHECK(hipMemcpyAsync(vbar, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");

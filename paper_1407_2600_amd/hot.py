@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhot.so")
 HOT_OK, HOT_EINVAL, HOT_ENOMEM, HOT_EOVERFLOW, HOT_EDEVICE, HOT_EUNSUPPORTED = range(6)
 HOT_FP64, HOT_FP32 = 0, 1
 HOT_ACC_VALID = 1
+HOT_KDK_NO_SNAPSHOT = 2
 HOT_CALL_FORCES, HOT_CALL_KDK, HOT_CALL_VJP, HOT_CALL_KDK_VJP = 1, 2, 4, 8
 STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW",
                 4: "HOT_EDEVICE", 5: "HOT_EUNSUPPORTED"}
@@ -213,8 +214,11 @@ class Gravity:
         self._call_retry(run, n)
         return acc, pot
 
-    def kdk(self, pos, vel, mass, acc, dt: float, nsteps: int, acc_valid: bool, pot=None):
-        """In-place leapfrog steps on pos (FP64), vel and acc (precision)."""
+    def kdk(self, pos, vel, mass, acc, dt: float, nsteps: int, acc_valid: bool, pot=None,
+            snapshot: bool = True):
+        """In-place leapfrog steps on pos (FP64), vel and acc (precision).
+        snapshot=False saves 36 bytes per particle of workspace; a failed
+        step then raises with pos and vel undefined (no resumption)."""
         pos_c, mass = self._check_inputs(pos, mass)
         if not (pos_c.data_ptr() == pos.data_ptr()):
             raise ValueError("pos must be contiguous (it is updated in place)")
@@ -227,14 +231,16 @@ class Gravity:
         # after HOT_EOVERFLOW the library has restored the state at the end of
         # the last completed step; resume from there with a larger workspace
         for _ in range(6):
-            ws = self._workspace(n, HOT_CALL_KDK)
+            ws = self._workspace(n, HOT_CALL_KDK if snapshot else HOT_CALL_FORCES)
             st = self.L.hot_kdk(self.h, n, C.c_void_p(pos.data_ptr()),
                                 C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
                                 C.c_void_p(acc.data_ptr()),
                                 C.c_void_p(pot.data_ptr() if pot is not None else 0),
-                                float(dt), left, HOT_ACC_VALID if valid else 0,
+                                float(dt), left,
+                                (HOT_ACC_VALID if valid else 0) |
+                                (0 if snapshot else HOT_KDK_NO_SNAPSHOT),
                                 C.c_void_p(ws.data_ptr()), ws.numel(), s)
-            if st != HOT_EOVERFLOW:
+            if st != HOT_EOVERFLOW or not snapshot:
                 check(st)
                 return
             done = self.stats()["kdk_steps_done"]

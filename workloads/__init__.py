@@ -25,7 +25,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["lattice_jitter", "zeldovich", "nfw_background", "uniform", "make", "WORKLOADS"]
+__all__ = ["lattice_jitter", "zeldovich", "zeldovich_torch", "nfw_background", "uniform", "make",
+           "WORKLOADS"]
 
 
 def _spacing(n_side: int, box: float) -> float:
@@ -93,6 +94,51 @@ def zeldovich(n_side: int, seed: int, slope: float = -1.5, rms_frac: float = 0.5
     disp *= (rms_frac * a) / rms
     q = lattice_jitter(n, seed, sigma_frac=0.0, box=box)
     return _wrap(q + disp, box)
+
+
+def zeldovich_torch(n_side: int, seed: int, slope: float = -1.5, rms_frac: float = 0.5,
+                    box: float = 1.0, device="cuda"):
+    """The recipe of ``zeldovich`` evaluated with torch on a device, for grids
+    too large for host memory (1024^3: about 60 GB of FP64 temporaries).
+    torch's generator draws a different realisation of the same field (same
+    spectrum, cut, normalisation and lattice order).  Returns a (3, n^3)
+    FP64 tensor on the device."""
+    import torch
+    n = n_side
+    a = _spacing(n, box)
+    f64 = torch.float64
+    gen = torch.Generator(device=device).manual_seed(seed)
+    w = torch.randn((n, n, n), generator=gen, dtype=f64, device=device)
+    dk = torch.fft.rfftn(w)
+    del w
+    kx = torch.fft.fftfreq(n, d=1.0 / n, dtype=f64, device=device)
+    kz = torch.fft.rfftfreq(n, d=1.0 / n, dtype=f64, device=device)
+    KX, KY, KZ = kx[:, None, None], kx[None, :, None], kz[None, None, :]
+    k2 = KX * KX + KY * KY + KZ * KZ
+    kny = n // 2
+    keep = (k2 > 0) & (k2 <= kny * kny)
+    keep &= (KX.abs() < kny) & (KY.abs() < kny) & (KZ.abs() < kny)
+    dk *= torch.where(keep, k2.clamp_min(1.0) ** (slope / 4.0), torch.zeros_like(k2))
+    del keep
+    inv_k2 = torch.where(k2 > 0, 1.0 / k2.clamp_min(1.0), torch.zeros_like(k2))
+    del k2
+    dk *= inv_k2
+    del inv_k2
+    pos = torch.empty((3, n ** 3), dtype=f64, device=device)
+    for axis, K in enumerate((KX, KY, KZ)):
+        psik = dk * (1j * K)
+        pos[axis] = torch.fft.irfftn(psik, s=(n, n, n), dim=(0, 1, 2)).reshape(-1)
+        del psik
+    del dk
+    rms = torch.sqrt(torch.mean(torch.sum(pos * pos, dim=0)))
+    pos *= (rms_frac * a) / rms
+    g = (torch.arange(n, dtype=f64, device=device) + 0.5) * a
+    pos[0] += g[:, None, None].expand(n, n, n).reshape(-1)
+    pos[1] += g[None, :, None].expand(n, n, n).reshape(-1)
+    pos[2] += g[None, None, :].expand(n, n, n).reshape(-1)
+    pos = torch.remainder(pos, box)
+    pos[pos >= box] -= box
+    return pos
 
 
 def _nfw_radii(rng, count: int, c: float) -> np.ndarray:
