@@ -416,7 +416,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     size_t tp, tm;
   };
   std::vector<Chunk> chunks;
-  if (words <= P.cap_list) {
+  // a chunk's list offsets are 32-bit words (direct) and records (multipole)
+  const size_t cap = std::min(P.cap_list, (size_t)UINT32_MAX - 64);
+  if (words <= cap) {
     chunks.push_back({0, ngroups, tp, tm});
   } else {
     std::vector<uint32_t> cp(ngroups), cm(ngroups);
@@ -427,7 +429,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     HOT_CHECK(hipStreamSynchronize(s), "readback");
     Chunk ch{0, 0, 0, 0};
     for (uint32_t g = 0; g < ngroups; ++g) {
-      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g]) + 4 > P.cap_list) {
+      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g]) + 4 > cap) {
         chunks.push_back(ch);
         ch = Chunk{g, g, 0, 0};
       }
@@ -577,7 +579,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   std::memset(c, 0, sizeof(*c));
   c->p = *params;
   c->S = 2097152.0 / params->box;
-  c->cells_per_particle = 2.4 / params->leaf_max + 0.01;  // grows on overflow
+  c->cells_per_particle = 4.0 / params->leaf_max + 0.02;  // grows on overflow
   c->list_per_particle = 96.0;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {

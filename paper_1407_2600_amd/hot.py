@@ -134,10 +134,11 @@ def far_table(far_order: int, box: float = 1.0, offset: int = 13):
 class Gravity:
     """One libhot context: parameters, Ewald table and a cached workspace."""
 
-    def __init__(self, device=None, workspace_bytes=None, **params):
+    def __init__(self, device=None, workspace_bytes=None, list_bytes=None, **params):
         """workspace_bytes caps the device workspace (at least the library's
-        minimum is used); interaction lists that do not fit are processed in
-        chunks of sink groups."""
+        minimum for the call is used); list_bytes instead sizes it as that
+        minimum plus a list region of this many bytes.  Interaction lists
+        that do not fit are processed in chunks of sink groups."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libhot needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -154,6 +155,7 @@ class Gravity:
         self.h = h
         self.ws = None
         self.ws_cap = workspace_bytes
+        self.list_bytes = list_bytes
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -166,9 +168,11 @@ class Gravity:
 
     def _workspace(self, n: int, calls: int = HOT_CALL_FORCES):
         need = self.L.hot_workspace_size(self.h, n)
+        lo = self.L.hot_workspace_size_min(self.h, n, calls)
+        if self.list_bytes is not None:
+            need = min(need, lo + int(self.list_bytes))
         if self.ws_cap is not None:
-            need = max(min(need, int(self.ws_cap)),
-                       self.L.hot_workspace_size_min(self.h, n, calls))
+            need = max(min(need, int(self.ws_cap)), lo)
         if self.ws is None or self.ws.numel() < need:
             self.ws = None
             self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)

@@ -137,7 +137,8 @@ def zeldovich_torch(n_side: int, seed: int, slope: float = -1.5, rms_frac: float
     pos[1] += g[None, :, None].expand(n, n, n).reshape(-1)
     pos[2] += g[None, None, :].expand(n, n, n).reshape(-1)
     pos = torch.remainder(pos, box)
-    pos[pos >= box] -= box
+    for r in pos:  # row by row and without a mask index (over 2^31 elements at 1024^3)
+        r.sub_((r >= box).to(f64) * box)
     return pos
 
 
