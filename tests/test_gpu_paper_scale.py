@@ -1,0 +1,150 @@
+"""Parity at the paper-scale workload: 1024^3 Zel'dovich particles (rms
+displacement 1.5 spacings, generated on the GPU), in the launch configuration
+of the 1024^3 benchmark (order 4, leaf 64, group 128, theta cap 0.8 with the
+error-bound test, FP32 mixed mode).
+
+* The first 2^24 particles of the set, as a problem of their own: keys, order,
+  cells and groups bit-exact against the oracle's tree, forces on sampled
+  groups within the FP32 tolerance.
+* The whole set (1.07e9 particles, lists in chunks): keys of sampled
+  particles against the oracle's key function, order and permutation checked
+  over all particles, and sampled cells' subtrees against the oracle's tree of
+  those cells' particles alone (a cell's subtree depends only on its
+  particles: its ancestors hold the same particles, so they split down to
+  it)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from _gpu import compare_structure, oracle_mass, pot_ok, rms_err, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+N_SIDE = 1024
+# the benchmark's operating point at this size: err_tol = 0.06 of the rms
+# acceleration (0.0186) for an rms force error of ~1e-3
+LAUNCH = dict(box=1.0, G=1.0, eps=0.02 / N_SIDE, order=4, periodic=1, leaf_max=64, group_max=128,
+              far_order=8, theta=0.8, err_tol=1.12e-3)
+LIST_BYTES = 16 << 30
+
+
+def _generate():
+    import torch
+    spec = workloads.WORKLOADS["zeldovich1024"]
+    pos = workloads.zeldovich_torch(N_SIDE, spec["seed"], rms_frac=spec["rms_frac"],
+                                    device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return pos
+
+
+@pytest.fixture
+def release_gpu_memory():
+    import torch
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_first_2_24_particles(release_gpu_memory):
+    import torch
+    print("paper scale subsample: generating 1024^3", flush=True)
+    pos_all = _generate()
+    k = 1 << 24
+    pos = pos_all[:, :k].contiguous().cpu().numpy()
+    del pos_all
+    torch.cuda.empty_cache()
+    mass = np.full(k, 1.0 / N_SIDE ** 3)
+    mo = oracle_mass(mass, "fp32")
+    print("  building the oracle tree", flush=True)
+    T = oracle.Tree(pos, mo, LAUNCH)
+    r = run_gpu(pos, mass, LAUNCH, "fp32", lists=False)
+    print("  gpu stats", {x: r["stats"][x] for x in ("ncells", "ngroups", "m2p_entries",
+                                                     "list_chunks")}, flush=True)
+    compare_structure(r["dbg"], T, lists=False)
+    gcell, _, _ = T.groups()
+    sample = np.sort(np.random.default_rng(123).choice(len(gcell), size=16, replace=False))
+    acc_o, pot_o = T.forces(groups=sample)
+    sel = ~np.isnan(pot_o)
+    ea = rms_err(r["acc"][:, sel], acc_o[:, sel])
+    ok, ep = pot_ok(r["pot"][sel], pot_o[sel], "fp32", LAUNCH, mo)
+    print(f"  sampled targets {sel.sum()} acc err {ea:.3e} pot err {ep:.3e}", flush=True)
+    assert sel.sum() > 0
+    assert ea <= 2e-5
+    assert ok
+
+
+def test_full_set_sampled_structure(release_gpu_memory):
+    import torch
+    from paper_1407_2600_amd import Gravity
+    print("paper scale full set: generating 1024^3", flush=True)
+    pos = _generate()
+    n = pos.shape[1]
+    mass = torch.full((n,), 1.0 / n, dtype=torch.float32, device="cuda")
+    g = Gravity(precision="fp32", list_bytes=LIST_BYTES, **LAUNCH)
+    acc, pot = g.forces(pos, mass)
+    torch.cuda.synchronize()
+    st = g.stats()
+    print("  gpu stats", {x: st[x] for x in ("ncells", "ngroups", "m2p_entries", "list_chunks",
+                                             "ms_total")}, flush=True)
+    assert st["list_chunks"] > 1
+    assert bool(torch.isfinite(acc).all()) and bool(torch.isfinite(pot).all())
+    del acc, pot
+    dbg = g.debug_export(lists=False)
+    del g
+    torch.cuda.empty_cache()
+    sk, perm = dbg["sorted_keys"], dbg["perm"]
+    print("  checking order and permutation", flush=True)
+    step = 1 << 27
+    for i in range(0, n - 1, step):
+        a = sk[i:min(i + step + 1, n)]
+        assert np.all(a[1:] >= a[:-1])
+    seen = np.zeros(n, dtype=bool)
+    seen[perm] = True
+    assert seen.all()
+    del seen
+    # keys of sampled particles against the oracle's key function
+    rng = np.random.default_rng(7)
+    s = np.sort(rng.choice(n, size=10000, replace=False))
+    idx = torch.as_tensor(perm[s].astype(np.int64), device="cuda")
+    ps = pos[:, idx].cpu().numpy()
+    np.testing.assert_array_equal(sk[s], oracle.keys(ps, LAUNCH["box"])[0])
+    # sampled cells' subtrees
+    print("  checking sampled subtrees", flush=True)
+    order = np.lexsort((dbg["cell_level"], dbg["cell_first"]))
+    F = dbg["cell_first"][order].astype(np.int64)
+    Lv = dbg["cell_level"][order]
+    Cn = dbg["cell_count"][order].astype(np.int64)
+    is_group = np.zeros(len(order), dtype=bool)
+    is_group[dbg["group_cell"]] = True
+    is_group = is_group[order]
+    cand = np.nonzero((Cn > LAUNCH["group_max"]) & (Cn <= 4096))[0]
+    picks = np.sort(rng.choice(cand, size=12, replace=False))
+    m32 = np.float64(np.float32(1.0 / n))
+    for i in picks:
+        f, c, lev = int(F[i]), int(Cn[i]), int(Lv[i])
+        ids = np.sort(perm[f:f + c].astype(np.int64))  # ties keep the original order
+        sub = pos[:, torch.as_tensor(ids, device="cuda")].cpu().numpy()
+        T = oracle.Tree(sub, np.full(c, m32), LAUNCH)
+        perm_o, sk_o = T.perm()
+        np.testing.assert_array_equal(sk[f:f + c], sk_o)
+        np.testing.assert_array_equal(perm[f:f + c].astype(np.int64), ids[perm_o])
+        co = T.cells()
+        keep = co["level"] >= lev
+        lo, hi = np.searchsorted(F, f), np.searchsorted(F, f + c)
+        j = np.arange(lo, hi)
+        j = j[Lv[j] >= lev]
+        oj = order[j]
+        assert len(j) == int(keep.sum())
+        np.testing.assert_array_equal(dbg["cell_key"][oj], co["key"][keep])
+        np.testing.assert_array_equal(Lv[j], co["level"][keep])
+        np.testing.assert_array_equal(F[j] - f, co["first"][keep])
+        np.testing.assert_array_equal(Cn[j], co["count"][keep])
+        np.testing.assert_array_equal(dbg["cell_com"][:, oj], co["com"][:, keep])
+        np.testing.assert_array_equal(dbg["cell_mass"][oj], co["mass"][keep])
+        gcell_o, _, _ = T.groups()
+        gk_o = sorted(int(co["key"][x]) for x in gcell_o)
+        gk = sorted(int(x) for x in dbg["cell_key"][oj[is_group[j]]])
+        assert gk == gk_o
+    print(f"  {len(picks)} subtrees match", flush=True)
