@@ -156,6 +156,43 @@ __device__ __forceinline__ void pair_adj(T rx, T ry, T rz, T eps2, T mk, T gkx, 
   part[3] = fma(ra, si3, fma(-gpj, si, part[3]));
 }
 
+// Sources and their cotangents go through a per-wavefront LDS stage as in the
+// forward direct kernel (list read 64 entries at a time, one per lane; the
+// entries' sources concatenated by a prefix sum over the lanes); partial sums
+// are folded per leaf image.
+constexpr int kAdjStage = 128;
+
+template <typename T, typename T4, bool OWN>
+__device__ __forceinline__ void p2p_adj_staged(const T4* __restrict__ st,
+                                               const T4* __restrict__ sa, int a, int b, T tx,
+                                               T ty, T tz, T eps2, T mk, const T4& ak,
+                                               uint32_t self_slot, Acc<T>& acc) {
+  for (int b0 = a; b0 < b; b0 += 64) {
+    const int b1 = b0 + 64 < b ? b0 + 64 : b;
+    T part[4] = {0, 0, 0, 0};
+#pragma unroll 2
+    for (int j = b0; j < b1; ++j) {
+      const T4 r = st[j];
+      const T4 aj = sa[j];
+      if constexpr (OWN) {
+        // the target itself: zero masses and cotangents and a unit distance
+        // give no contribution
+        const bool self = (uint32_t)j == self_slot;
+        const T mj = self ? (T)0 : r.w;
+        const T mkk = self ? (T)0 : mk;
+        T rx = tx - r.x, ry = ty - r.y, rz = tz - r.z;
+        rx = self ? (T)1 : rx;
+        pair_adj<T>(rx, ry, rz, eps2, mkk, ak.x, ak.y, ak.z, ak.w, mj, self ? (T)0 : aj.x,
+                    self ? (T)0 : aj.y, self ? (T)0 : aj.z, self ? (T)0 : aj.w, part);
+      } else {
+        pair_adj<T>(tx - r.x, ty - r.y, tz - r.z, eps2, mk, ak.x, ak.y, ak.z, ak.w, r.w, aj.x,
+                    aj.y, aj.z, aj.w, part);
+      }
+    }
+    acc.fold(part);
+  }
+}
+
 template <typename T, typename T4>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, uint32_t ngroups,
                                                             double L, T eps2,
@@ -164,9 +201,19 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
                                                             const T4* __restrict__ arec, size_t n,
                                                             const uint32_t* __restrict__ list,
                                                             double4* __restrict__ out) {
+  __shared__ T4 stage_all[kAdjWaves][kAdjStage];
+  __shared__ T4 astage_all[kAdjWaves][kAdjStage];
+  __shared__ uint32_t incl_all[kAdjWaves][64];
+  __shared__ uint32_t bf_all[kAdjWaves][64];
+  __shared__ T sh_all[kAdjWaves][3][64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kAdjWaves + wid);
   if (g >= ngroups) return;
+  T4* st = stage_all[wid];
+  T4* sa = astage_all[wid];
+  uint32_t* e_incl = incl_all[wid];
+  uint32_t* e_bf = bf_all[wid];
+  T(*e_sh)[64] = sh_all[wid];
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
@@ -183,42 +230,84 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
     const T4 ak = arec[ss];
     Acc<T> acc;
     acc.zero();
-    {
-      T part[4] = {0, 0, 0, 0};
-      for (uint32_t j = first; j < first + count; ++j) {
-        const T sx = (T)(spos[j] - cA[0]), sy = (T)(spos[n + j] - cA[1]),
-                sz = (T)(spos[2 * n + j] - cA[2]);
-        const T4 aj = arec[j];
-        // the target itself: zero masses and cotangents and a unit distance
-        // give no contribution
-        const bool self = (j == ss);
-        const T mj = self ? (T)0 : srec[j].w;
-        const T mkk = self ? (T)0 : mk;
-        T rx = tx - sx, ry = ty - sy, rz = tz - sz;
-        rx = self ? (T)1 : rx;
-        pair_adj<T>(rx, ry, rz, eps2, mkk, ak.x, ak.y, ak.z, ak.w, mj, self ? (T)0 : aj.x,
-                    self ? (T)0 : aj.y, self ? (T)0 : aj.z, self ? (T)0 : aj.w, part);
+    // own group (image 0)
+    for (uint32_t s0 = 0; s0 < count; s0 += kAdjStage) {
+      const int nb =
+          (int)(count - s0 < (uint32_t)kAdjStage ? count - s0 : (uint32_t)kAdjStage);
+      wave_sync();
+      for (int k = lane; k < nb; k += 64) {
+        const uint32_t j = first + s0 + (uint32_t)k;
+        T4 r;
+        r.x = (T)(spos[j] - cA[0]);
+        r.y = (T)(spos[n + j] - cA[1]);
+        r.z = (T)(spos[2 * n + j] - cA[2]);
+        r.w = srec[j].w;
+        st[k] = r;
+        sa[k] = arec[j];
       }
-      acc.fold(part);
+      wave_sync();
+      p2p_adj_staged<T, T4, true>(st, sa, 0, nb, tx, ty, tz, eps2, mk, ak, ss - first - s0, acc);
     }
-    for (uint32_t q = 0; q < cnt; ++q) {
-      const uint32_t e = list[off + q];
-      const int img = (int)(e >> 27);
-      const int B = (int)(e & kCellMask);
-      double cB[3];
-      center_of(C.key[B], C.level[B], L, cB);
-      const T shx = (T)(cB[0] + (double)(img / 9 - 1) * L - cA[0]);
-      const T shy = (T)(cB[1] + (double)((img / 3) % 3 - 1) * L - cA[1]);
-      const T shz = (T)(cB[2] + (double)(img % 3 - 1) * L - cA[2]);
-      const uint32_t bf = C.first[B], bc = C.count[B];
-      T part[4] = {0, 0, 0, 0};
-      for (uint32_t j = bf; j < bf + bc; ++j) {
-        const T4 r = srec[j];
-        const T4 aj = arec[j];
-        pair_adj<T>(tx - (shx + r.x), ty - (shy + r.y), tz - (shz + r.z), eps2, mk, ak.x, ak.y,
-                    ak.z, ak.w, r.w, aj.x, aj.y, aj.z, aj.w, part);
+    // listed leaves, 64 entries at a time
+    for (uint32_t q0 = 0; q0 < cnt; q0 += 64) {
+      const uint32_t ne = cnt - q0 < 64u ? cnt - q0 : 64u;
+      uint32_t bc = 0, bf = 0;
+      T sx = 0, sy = 0, sz = 0;
+      if ((uint32_t)lane < ne) {
+        const uint32_t e = list[off + q0 + (uint32_t)lane];
+        const int img = (int)(e >> 27);
+        const int B = (int)(e & kCellMask);
+        double cB[3];
+        center_of(C.key[B], C.level[B], L, cB);
+        sx = (T)(cB[0] + (double)(img / 9 - 1) * L - cA[0]);
+        sy = (T)(cB[1] + (double)((img / 3) % 3 - 1) * L - cA[1]);
+        sz = (T)(cB[2] + (double)(img % 3 - 1) * L - cA[2]);
+        bf = C.first[B];
+        bc = C.count[B];
       }
-      acc.fold(part);
+      const uint32_t incl = wave_incl_scan(bc, lane);
+      const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+      wave_sync();
+      e_incl[lane] = incl;
+      e_bf[lane] = bf - (incl - bc);  // source index = e_bf + stream position
+      e_sh[0][lane] = sx;
+      e_sh[1][lane] = sy;
+      e_sh[2][lane] = sz;
+      uint32_t ecur = 0;  // first entry of the batch (wave-uniform)
+      for (uint32_t s0 = 0; s0 < total; s0 += kAdjStage) {
+        const int nb =
+            (int)(total - s0 < (uint32_t)kAdjStage ? total - s0 : (uint32_t)kAdjStage);
+        wave_sync();
+        for (int k = lane; k < nb; k += 64) {
+          const uint32_t slot = s0 + (uint32_t)k;
+          int e = 0;  // the entry holding this stream position
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1)
+            if (e_incl[e + step - 1] <= slot) e += step;
+          const uint32_t j = e_bf[e] + slot;
+          const T4 r = srec[j];
+          T4 v;
+          v.x = e_sh[0][e] + r.x;
+          v.y = e_sh[1][e] + r.y;
+          v.z = e_sh[2][e] + r.z;
+          v.w = r.w;
+          st[k] = v;
+          sa[k] = arec[j];
+        }
+        wave_sync();
+        const uint32_t s1 = s0 + (uint32_t)nb;
+        uint32_t lo = ecur ? __builtin_amdgcn_readfirstlane(e_incl[ecur - 1]) : 0u;
+        for (;;) {
+          const uint32_t hi = __builtin_amdgcn_readfirstlane(e_incl[ecur]);
+          const int a = (int)((lo > s0 ? lo : s0) - s0);
+          const int b = (int)((hi < s1 ? hi : s1) - s0);
+          p2p_adj_staged<T, T4, false>(st, sa, a, b, tx, ty, tz, eps2, mk, ak, 0u, acc);
+          if (hi > s1) break;  // the entry continues in the next batch
+          lo = hi;
+          ++ecur;
+          if (hi == s1) break;
+        }
+      }
     }
     if (act) out[s] = make_double4(acc.get(0), acc.get(1), acc.get(2), acc.get(3));
   }

@@ -5,8 +5,8 @@
 // One 64-lane wavefront handles one sink group: each lane holds one target
 // (tiles of 64 for larger groups) in registers, and the wavefront steps
 // through the group's list together, so every source particle or cell record
-// is wave-uniform and is read once per wavefront through the scalar cache
-// into scalar registers, feeding all 64 targets.
+// is wave-uniform and is read once per wavefront (source particles through an
+// LDS stage, cell records through the scalar cache), feeding all 64 targets.
 //
 // Precision: coordinates are relative to the group's cell centre; positions,
 // cell centres and centres of mass are FP64 and are differenced in FP64
@@ -23,11 +23,58 @@ constexpr int kForceWaves = 4;
 // Direct interactions of one sink group per wavefront, targets in lanes, in
 // passes of up to 64 targets: first the group's own particles (image 0,
 // without the target itself), then every listed leaf with its image shift.
+// Sources go through a per-wavefront LDS stage of kStage records {x, y, z, m}
+// relative to the group's cell centre: the list is read 64 entries at a time,
+// one entry per lane (leaf range and image-shifted leaf centre, in FP64, then
+// rounded), a prefix sum over the lanes concatenates the entries' sources,
+// and the lanes fill the stage from that concatenated stream before all
+// targets read each staged source with a broadcast LDS load.
 // TAIL selects the passes as in k_m2p: the main launch takes the passes over
-// more than 32 targets with wave-uniform sources; the tail launch takes a
-// last pass of at most 32 targets and splits the wave into 2 or 4 sub-groups
-// that share out the sources and list entries, adding their partial sums at
-// the end.  This kernel writes (not adds) the accumulators.
+// more than 32 targets; the tail launch takes a last pass of at most 32
+// targets and splits the wave into 2 or 4 sub-groups that share out the
+// staged sources, adding their partial sums at the end.  Partial sums over
+// one leaf image (at most 64 of its sources) are folded into the
+// accumulators.  This kernel writes (not adds) the accumulators.
+constexpr int kStage = 256;
+
+// staged sources [a, b) against this lane's target; the partial sums are
+// folded every 64 sources and at the end
+template <typename T, typename T4, bool OWN>
+__device__ __forceinline__ void p2p_staged(const T4* __restrict__ st, int a, int b, uint32_t sub,
+                                           uint32_t split, T tx, T ty, T tz, T eps2,
+                                           uint32_t self_slot, Acc<T>& acc) {
+  for (int b0 = a; b0 < b; b0 += 64) {
+    const int b1 = b0 + 64 < b ? b0 + 64 : b;
+    T part[4] = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int j = b0 + (int)sub; j < b1; j += (int)split) {
+      const T4 r = st[j];
+      const T dx = r.x - tx, dy = r.y - ty, dz = r.z - tz;
+      T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+      if constexpr (OWN) {
+        const bool self = (uint32_t)j == self_slot;
+        r2 = self ? (T)1 : r2;
+        const T ri = rsqrt_t(r2);
+        const T mr = self ? (T)0 : r.w * ri;
+        const T mr3 = mr * (ri * ri);
+        part[0] = fma(dx, mr3, part[0]);
+        part[1] = fma(dy, mr3, part[1]);
+        part[2] = fma(dz, mr3, part[2]);
+        part[3] += mr;
+      } else {
+        const T ri = rsqrt_t(r2);
+        const T mr = r.w * ri;
+        const T mr3 = mr * (ri * ri);
+        part[0] = fma(dx, mr3, part[0]);
+        part[1] = fma(dy, mr3, part[1]);
+        part[2] = fma(dz, mr3, part[2]);
+        part[3] += mr;
+      }
+    }
+    acc.fold(part);
+  }
+}
+
 template <typename T, typename T4, bool TAIL>
 __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uint32_t ngroups,
                                                           double L, T eps2,
@@ -35,9 +82,17 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
                                                           const T4* __restrict__ srec, size_t n,
                                                           const uint32_t* __restrict__ list,
                                                           double4* __restrict__ out) {
+  __shared__ T4 stage_all[kForceWaves][kStage];
+  __shared__ uint32_t incl_all[kForceWaves][64];
+  __shared__ uint32_t bf_all[kForceWaves][64];
+  __shared__ T sh_all[kForceWaves][3][64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
+  T4* st = stage_all[wid];
+  uint32_t* e_incl = incl_all[wid];
+  uint32_t* e_bf = bf_all[wid];
+  T(*e_sh)[64] = sh_all[wid];
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
@@ -62,50 +117,81 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
     Acc<T> acc;
     acc.zero();
     // own group (image 0), excluding the target itself
-    {
-      T part[4] = {0, 0, 0, 0};
-      for (uint32_t j = first + sub; j < first + count; j += split) {
-        const T sx = (T)(spos[j] - cA[0]), sy = (T)(spos[n + j] - cA[1]),
-                sz = (T)(spos[2 * n + j] - cA[2]);
-        const T m = srec[j].w;
-        const T dx = sx - tx, dy = sy - ty, dz = sz - tz;
-        T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-        const bool self = (j == ss);
-        r2 = self ? (T)1 : r2;
-        const T ri = rsqrt_t(r2);
-        const T mr = self ? (T)0 : m * ri;
-        const T mr3 = mr * (ri * ri);
-        part[0] = fma(dx, mr3, part[0]);
-        part[1] = fma(dy, mr3, part[1]);
-        part[2] = fma(dz, mr3, part[2]);
-        part[3] += mr;
+    for (uint32_t s0 = 0; s0 < count; s0 += kStage) {
+      const int nb = (int)(count - s0 < (uint32_t)kStage ? count - s0 : (uint32_t)kStage);
+      wave_sync();
+      for (int k = lane; k < nb; k += 64) {
+        const uint32_t j = first + s0 + (uint32_t)k;
+        T4 r;
+        r.x = (T)(spos[j] - cA[0]);
+        r.y = (T)(spos[n + j] - cA[1]);
+        r.z = (T)(spos[2 * n + j] - cA[2]);
+        r.w = srec[j].w;
+        st[k] = r;
       }
-      acc.fold(part);
+      wave_sync();
+      p2p_staged<T, T4, true>(st, 0, nb, sub, split, tx, ty, tz, eps2, ss - first - s0, acc);
     }
-    for (uint32_t q = sub; q < cnt; q += split) {
-      const uint32_t e = list[off + q];
-      const int img = (int)(e >> 27);
-      const int B = (int)(e & kCellMask);
-      double cB[3];
-      center_of(C.key[B], C.level[B], L, cB);
-      const T shx = (T)(cB[0] + (double)(img / 9 - 1) * L - cA[0]);
-      const T shy = (T)(cB[1] + (double)((img / 3) % 3 - 1) * L - cA[1]);
-      const T shz = (T)(cB[2] + (double)(img % 3 - 1) * L - cA[2]);
-      const uint32_t bf = C.first[B], bc = C.count[B];
-      T part[4] = {0, 0, 0, 0};
-      for (uint32_t j = bf; j < bf + bc; ++j) {
-        const T4 r = srec[j];
-        const T dx = (shx + r.x) - tx, dy = (shy + r.y) - ty, dz = (shz + r.z) - tz;
-        const T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-        const T ri = rsqrt_t(r2);
-        const T mr = r.w * ri;
-        const T mr3 = mr * (ri * ri);
-        part[0] = fma(dx, mr3, part[0]);
-        part[1] = fma(dy, mr3, part[1]);
-        part[2] = fma(dz, mr3, part[2]);
-        part[3] += mr;
+    // listed leaves, 64 entries at a time
+    for (uint32_t q0 = 0; q0 < cnt; q0 += 64) {
+      const uint32_t ne = cnt - q0 < 64u ? cnt - q0 : 64u;
+      uint32_t bc = 0, bf = 0;
+      T sx = 0, sy = 0, sz = 0;
+      if ((uint32_t)lane < ne) {
+        const uint32_t e = list[off + q0 + (uint32_t)lane];
+        const int img = (int)(e >> 27);
+        const int B = (int)(e & kCellMask);
+        double cB[3];
+        center_of(C.key[B], C.level[B], L, cB);
+        sx = (T)(cB[0] + (double)(img / 9 - 1) * L - cA[0]);
+        sy = (T)(cB[1] + (double)((img / 3) % 3 - 1) * L - cA[1]);
+        sz = (T)(cB[2] + (double)(img % 3 - 1) * L - cA[2]);
+        bf = C.first[B];
+        bc = C.count[B];
       }
-      acc.fold(part);
+      const uint32_t incl = wave_incl_scan(bc, lane);
+      const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+      wave_sync();
+      e_incl[lane] = incl;
+      e_bf[lane] = bf - (incl - bc);  // source index = e_bf + stream position
+      e_sh[0][lane] = sx;
+      e_sh[1][lane] = sy;
+      e_sh[2][lane] = sz;
+      uint32_t ecur = 0;  // first entry of the batch (wave-uniform)
+      for (uint32_t s0 = 0; s0 < total; s0 += kStage) {
+        const int nb = (int)(total - s0 < (uint32_t)kStage ? total - s0 : (uint32_t)kStage);
+        wave_sync();
+        for (int k = lane; k < nb; k += 64) {
+          const uint32_t slot = s0 + (uint32_t)k;
+          // the entry holding this stream position: the first with incl > slot
+          int e = 0;
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1)
+            if (e_incl[e + step - 1] <= slot) e += step;
+          const T4 r = srec[e_bf[e] + slot];
+          T4 v;
+          v.x = e_sh[0][e] + r.x;
+          v.y = e_sh[1][e] + r.y;
+          v.z = e_sh[2][e] + r.z;
+          v.w = r.w;
+          st[k] = v;
+        }
+        wave_sync();
+        // one leaf image at a time, so that each is folded on its own (the
+        // images of one leaf can cancel to far below their size)
+        const uint32_t s1 = s0 + (uint32_t)nb;
+        uint32_t lo = ecur ? __builtin_amdgcn_readfirstlane(e_incl[ecur - 1]) : 0u;
+        for (;;) {
+          const uint32_t hi = __builtin_amdgcn_readfirstlane(e_incl[ecur]);
+          const int a = (int)((lo > s0 ? lo : s0) - s0);
+          const int b = (int)((hi < s1 ? hi : s1) - s0);
+          p2p_staged<T, T4, false>(st, a, b, sub, split, tx, ty, tz, eps2, 0u, acc);
+          if (hi > s1) break;  // the entry continues in the next batch
+          lo = hi;
+          ++ecur;
+          if (hi == s1) break;
+        }
+      }
     }
     double v[4];
 #pragma unroll
