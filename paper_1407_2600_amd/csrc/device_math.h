@@ -72,6 +72,48 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
   return v;
 }
 
+// ---------------------------------------------------------- far-field help
+// Moment sums over particles split the (a, b) exponent pairs of x^a y^b z^c
+// among kFarWaves wavefronts (pair q goes to wavefront q mod kFarWaves).
+constexpr int kFarWaves = 4;
+
+template <int PF>
+struct FarPairs {
+  static constexpr int N = (PF + 1) * (PF + 2) / 2;
+  int a[N], b[N];
+  constexpr FarPairs() : a(), b() {
+    int k = 0;
+    for (int x = 0; x <= PF; ++x)
+      for (int y = 0; y <= PF - x; ++y) {
+        a[k] = x;
+        b[k] = y;
+        ++k;
+      }
+  }
+};
+
+// number of moments wavefront W accumulates
+template <int PF>
+__host__ __device__ constexpr int far_wave_terms(int W) {
+  constexpr FarPairs<PF> fp{};
+  int t = 0;
+  for (int q = W; q < FarPairs<PF>::N; q += kFarWaves) t += PF - fp.a[q] - fp.b[q] + 1;
+  return t;
+}
+
+// binomial coefficients C(n, k), n <= 2 * 12, exact in FP64 (built at
+// compile time from Pascal's rule)
+struct BinomTable {
+  double v[25][25];
+  constexpr BinomTable() : v() {
+    for (int i = 0; i < 25; ++i) {
+      v[i][0] = 1.0;
+      for (int k = 1; k <= i; ++k) v[i][k] = v[i - 1][k - 1] + (k < i ? v[i - 1][k] : 0.0);
+    }
+  }
+};
+__constant__ constexpr BinomTable kBinom{};
+
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 

@@ -15,78 +15,90 @@
 // of the expansions and makes the truncation error orders of magnitude
 // smaller at the same order.  Octant s holds a contiguous range of the sorted
 // particles (its keys share the top octal digit), found by binary search.
-// The moments are a blocked reduction (one coefficient per thread, particle
-// powers staged in LDS); the local coefficients one block per target octant;
-// the evaluation one thread per particle in FP64, fused with the scaling
-// (-G, G) and the scatter back to the caller's particle order.
+// The moments are a blocked reduction (particles in lanes, moments in
+// registers); the local coefficients one wavefront per coefficient; the
+// evaluation one thread per particle in FP64, fused with the scaling (-G, G)
+// and the scatter back to the caller's particle order.
 #include "device_math.h"
 
 namespace hot {
 
-constexpr int kFarThreads = 256;
-constexpr int kFarStage = 64;
+// Octant moments, per block of one octant's particles: each lane takes one
+// particle at a time and each of the 4 wavefronts a fixed share of the
+// (a, b) exponent pairs, accumulating m x^a y^b z^c for every c of its pairs
+// in registers; at the end the lanes' sums are added across the wavefront.
+template <int PF, int W>
+__device__ __forceinline__ void far_moments_wave(const double* __restrict__ spos,
+                                                 const double* __restrict__ smass, size_t n,
+                                                 size_t beg, size_t end, const double c[3],
+                                                 int lane, double* __restrict__ out) {
+  constexpr FarPairs<PF> fp{};
+  constexpr int NP = FarPairs<PF>::N;
+  constexpr int NA = far_wave_terms<PF>(W);
+  if constexpr (NA > 0) {
+    double acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+    for (size_t s = beg + (size_t)lane; s < end; s += 64) {
+      const double dx = spos[s] - c[0], dy = spos[n + s] - c[1], dz = spos[2 * n + s] - c[2];
+      const double m = smass[s];
+      double px[PF + 1], py[PF + 1], pz[PF + 1];
+      px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+      for (int e = 1; e <= PF; ++e) {
+        px[e] = px[e - 1] * dx;
+        py[e] = py[e - 1] * dy;
+        pz[e] = pz[e - 1] * dz;
+      }
+      int o = 0;
+#pragma unroll
+      for (int q = W; q < NP; q += kFarWaves) {
+        const double w = m * px[fp.a[q]] * py[fp.b[q]];
+#pragma unroll
+        for (int e = 0; e <= PF - fp.a[q] - fp.b[q]; ++e) {
+          acc[o] = fma(w, pz[e], acc[o]);
+          ++o;
+        }
+      }
+    }
+    int o = 0;
+#pragma unroll
+    for (int q = W; q < NP; q += kFarWaves) {
+#pragma unroll
+      for (int e = 0; e <= PF - fp.a[q] - fp.b[q]; ++e) {
+        double v = acc[o];
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0) out[mi_index(fp.a[q], fp.b[q], e)] = v;
+        ++o;
+      }
+    }
+  }
+}
 
 template <int PF>
-__global__ void __launch_bounds__(kFarThreads) k_far_moments(const double* __restrict__ spos,
-                                                              const double* __restrict__ smass,
-                                                              const uint64_t* __restrict__ skey,
-                                                              size_t n, double L, int nblk,
-                                                              double* __restrict__ part) {
+__global__ void __launch_bounds__(64 * kFarWaves) k_far_moments(const double* __restrict__ spos,
+                                                                const double* __restrict__ smass,
+                                                                const uint64_t* __restrict__ skey,
+                                                                size_t n, double L, int nblk,
+                                                                double* __restrict__ part) {
   constexpr int NQ = nt(PF);
-  constexpr MI<PF> mi{};
-  __shared__ double pw[kFarStage][3][PF + 1];
-  __shared__ double ms[kFarStage];
   const int o = blockIdx.y;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   size_t obeg, oend;
   octant_range(skey, n, o, &obeg, &oend);
   const size_t len = oend - obeg;
   const size_t chunk = (len + nblk - 1) / nblk;
-  const size_t beg = obeg + (size_t)blockIdx.x * chunk;
+  const size_t beg = obeg + (size_t)blockIdx.x * chunk < oend ? obeg + (size_t)blockIdx.x * chunk
+                                                              : oend;
   const size_t end = beg + chunk < oend ? beg + chunk : oend;
   double c[3];
   octant_center(o, L, c);
-  constexpr int PER = (NQ + kFarThreads - 1) / kFarThreads;
-  double acc[PER];
-  int ka[PER], kb[PER], kc[PER];
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    acc[r] = 0.0;
-    const int k = threadIdx.x + r * kFarThreads;
-    ka[r] = k < NQ ? mi.a[k] : 0;
-    kb[r] = k < NQ ? mi.b[k] : 0;
-    kc[r] = k < NQ ? mi.c[k] : 0;
-  }
-  for (size_t b0 = beg; b0 < end; b0 += kFarStage) {
-    if (threadIdx.x < kFarStage) {
-      const size_t s = b0 + threadIdx.x;
-      const bool ok = s < end;
-      const double d[3] = {ok ? spos[s] - c[0] : 0.0, ok ? spos[n + s] - c[1] : 0.0,
-                           ok ? spos[2 * n + s] - c[2] : 0.0};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double p = 1.0;
-        pw[threadIdx.x][a][0] = 1.0;
-#pragma unroll
-        for (int e = 1; e <= PF; ++e) {
-          p *= d[a];
-          pw[threadIdx.x][a][e] = p;
-        }
-      }
-      ms[threadIdx.x] = ok ? smass[s] : 0.0;
-    }
-    __syncthreads();
-    for (int p = 0; p < kFarStage; ++p) {
-      const double m = ms[p];
-#pragma unroll
-      for (int r = 0; r < PER; ++r)
-        acc[r] += m * pw[p][0][ka[r]] * pw[p][1][kb[r]] * pw[p][2][kc[r]];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int k = threadIdx.x + r * kFarThreads;
-    if (k < NQ) part[((size_t)o * nblk + blockIdx.x) * NQ + k] = acc[r];
+  double* out = part + ((size_t)o * nblk + blockIdx.x) * NQ;
+  switch (wid) {
+    case 0: far_moments_wave<PF, 0>(spos, smass, n, beg, end, c, lane, out); break;
+    case 1: far_moments_wave<PF, 1>(spos, smass, n, beg, end, c, lane, out); break;
+    case 2: far_moments_wave<PF, 2>(spos, smass, n, beg, end, c, lane, out); break;
+    default: far_moments_wave<PF, 3>(spos, smass, n, beg, end, c, lane, out); break;
   }
 }
 
@@ -101,13 +113,6 @@ __global__ void __launch_bounds__(256) k_far_sum(const double* __restrict__ part
   double acc = 0.0;
   for (int b = 0; b < nblk; ++b) acc += part[((size_t)s * nblk + b) * NQ + k];
   mom[i] = acc;
-}
-
-// C(n, k) exactly, n <= 2 * kMaxFarOrder
-__device__ __forceinline__ double binom_exact(int n, int k) {
-  unsigned long long b = 1;
-  for (int u = 1; u <= k; ++u) b = b * (unsigned long long)(n - k + u) / (unsigned long long)u;
-  return (double)b;
 }
 
 // Local coefficients of target octant t (blockIdx.y), output q (blockIdx.x):
@@ -149,8 +154,7 @@ __global__ void __launch_bounds__(64) k_far_lambda(const double* __restrict__ tp
     const int dx = ((t >> 2) & 1) - ((s >> 2) & 1), dy = ((t >> 1) & 1) - ((s >> 1) & 1),
               dz = (t & 1) - (s & 1);
     const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
-    const double bin = binom_exact(qa + ka, ka) * binom_exact(qb + kb, kb) *
-                       binom_exact(qc + kc, kc);
+    const double bin = kBinom.v[qa + ka][ka] * kBinom.v[qb + kb][kb] * kBinom.v[qc + kc][kc];
     const double sg = (d & 1) ? -1.0 : 1.0;
     acc += sg * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)] * mom[(size_t)s * NQ + k];
   }
@@ -185,18 +189,26 @@ __global__ void __launch_bounds__(256) k_far_apply(const double* __restrict__ sp
       py[e] = py[e - 1] * h[1];
       pz[e] = pz[e - 1] * h[2];
     }
-    const double* lm = lam + (size_t)o * NQ;
     double P = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
+    auto eval = [&](const double* __restrict__ lm) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int a = mi.a[q], b = mi.b[q], c3 = mi.c[q];
-      const double Lq = lm[q];
-      const double yz = py[b] * pz[c3];
-      P = fma(Lq, px[a] * yz, P);
-      if (a) Gx = fma(Lq * (double)a, px[a - 1] * yz, Gx);
-      if (b) Gy = fma(Lq * (double)b, px[a] * py[b - 1] * pz[c3], Gy);
-      if (c3) Gz = fma(Lq * (double)c3, px[a] * py[b] * pz[c3 - 1], Gz);
-    }
+      for (int q = 0; q < NQ; ++q) {
+        const int a = mi.a[q], b = mi.b[q], c3 = mi.c[q];
+        const double Lq = lm[q];
+        const double yz = py[b] * pz[c3];
+        P = fma(Lq, px[a] * yz, P);
+        if (a) Gx = fma(Lq * (double)a, px[a - 1] * yz, Gx);
+        if (b) Gy = fma(Lq * (double)b, px[a] * py[b - 1] * pz[c3], Gy);
+        if (c3) Gz = fma(Lq * (double)c3, px[a] * py[b] * pz[c3 - 1], Gz);
+      }
+    };
+    // where the whole wavefront lies in one octant (all but at most 7
+    // wavefronts) the coefficients are wave-uniform: scalar loads
+    const int o0 = __builtin_amdgcn_readfirstlane(o);
+    if (__all(o == o0))
+      eval(lam + (size_t)o0 * NQ);
+    else
+      eval(lam + (size_t)o * NQ);
     phi += P;
     gx += Gx;
     gy += Gy;
@@ -219,7 +231,7 @@ static hipError_t far_run(const double* spos, const double* smass, const uint64_
     int nblk = (int)((n / 8 + 2047) / 2048);
     if (nblk > nblk_max) nblk = nblk_max;
     if (nblk < 1) nblk = 1;
-    k_far_moments<PF><<<dim3(nblk, 8), kFarThreads, 0, s>>>(spos, smass, skey, n, box, nblk,
+    k_far_moments<PF><<<dim3(nblk, 8), 64 * kFarWaves, 0, s>>>(spos, smass, skey, n, box, nblk,
                                                             part);
     k_far_sum<PF><<<(8 * nt(PF) + 255) / 256, 256, 0, s>>>(part, nblk, mom);
     k_far_lambda<PF><<<dim3(nt(PF), 8), 64, 0, s>>>(tpsi, mom, lam);
@@ -241,7 +253,7 @@ static hipError_t far_prepare_run(const double* spos, const double* smass, const
   int nblk = (int)((n / 8 + 2047) / 2048);
   if (nblk > nblk_max) nblk = nblk_max;
   if (nblk < 1) nblk = 1;
-  k_far_moments<PF><<<dim3(nblk, 8), kFarThreads, 0, s>>>(spos, smass, skey, n, box, nblk, part);
+  k_far_moments<PF><<<dim3(nblk, 8), 64 * kFarWaves, 0, s>>>(spos, smass, skey, n, box, nblk, part);
   k_far_sum<PF><<<(8 * nt(PF) + 255) / 256, 256, 0, s>>>(part, nblk, mom);
   k_far_lambda<PF><<<dim3(nt(PF), 8), 64, 0, s>>>(tpsi, mom, lam);
   return hipGetLastError();

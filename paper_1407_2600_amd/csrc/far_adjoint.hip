@@ -16,82 +16,92 @@
 
 namespace hot {
 
-constexpr int kFarAThreads = 256;
-constexpr int kFarAStage = 64;
+// Target-octant cotangents of the local coefficients,
+//   Lbar^t_q = sum_{i in t} (gacc_i . grad h_i^q - gpot_i h_i^q),
+// per block of one octant's particles, laid out like the forward moments:
+// particles in lanes, each wavefront a fixed share of the (a, b) pairs. For a
+// pair, u0 = x^a y^b (-gpot) + a gx x^(a-1) y^b + b gy x^a y^(b-1) and
+// u1 = gz x^a y^b give the term of z-exponent c as u0 z^c + u1 c z^(c-1).
+template <int PF, int W, typename T4>
+__device__ __forceinline__ void far_adj_local_wave(const double* __restrict__ spos,
+                                                   const T4* __restrict__ arec, size_t n,
+                                                   size_t beg, size_t end, const double c[3],
+                                                   int lane, double* __restrict__ out) {
+  constexpr FarPairs<PF> fp{};
+  constexpr int NP = FarPairs<PF>::N;
+  constexpr int NA = far_wave_terms<PF>(W);
+  if constexpr (NA > 0) {
+    double acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+    for (size_t s = beg + (size_t)lane; s < end; s += 64) {
+      const double dx = spos[s] - c[0], dy = spos[n + s] - c[1], dz = spos[2 * n + s] - c[2];
+      const T4 r = arec[s];
+      const double gx = (double)r.x, gy = (double)r.y, gz = (double)r.z, gp = (double)r.w;
+      double px[PF + 1], py[PF + 1], pz[PF + 1], dpz[PF + 1];
+      px[0] = py[0] = pz[0] = 1.0;
+      dpz[0] = 0.0;
+#pragma unroll
+      for (int e = 1; e <= PF; ++e) {
+        px[e] = px[e - 1] * dx;
+        py[e] = py[e - 1] * dy;
+        pz[e] = pz[e - 1] * dz;
+        dpz[e] = (double)e * pz[e - 1];
+      }
+      int o = 0;
+#pragma unroll
+      for (int q = W; q < NP; q += kFarWaves) {
+        const int qa = fp.a[q], qb = fp.b[q];
+        const double xy = px[qa] * py[qb];
+        double u0 = -gp * xy;
+        if (qa) u0 = fma(gx * (double)qa, px[qa - 1] * py[qb], u0);
+        if (qb) u0 = fma(gy * (double)qb, px[qa] * py[qb - 1], u0);
+        const double u1 = gz * xy;
+#pragma unroll
+        for (int e = 0; e <= PF - qa - qb; ++e) {
+          acc[o] += fma(u0, pz[e], u1 * dpz[e]);
+          ++o;
+        }
+      }
+    }
+    int o = 0;
+#pragma unroll
+    for (int q = W; q < NP; q += kFarWaves) {
+#pragma unroll
+      for (int e = 0; e <= PF - fp.a[q] - fp.b[q]; ++e) {
+        double v = acc[o];
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0) out[mi_index(fp.a[q], fp.b[q], e)] = v;
+        ++o;
+      }
+    }
+  }
+}
 
 template <int PF, typename T4>
-__global__ void __launch_bounds__(kFarAThreads) k_far_adj_local(const double* __restrict__ spos,
-                                                                const T4* __restrict__ arec,
-                                                                const uint64_t* __restrict__ skey,
-                                                                size_t n, double L, int nblk,
-                                                                double* __restrict__ part) {
+__global__ void __launch_bounds__(64 * kFarWaves) k_far_adj_local(const double* __restrict__ spos,
+                                                                  const T4* __restrict__ arec,
+                                                                  const uint64_t* __restrict__ skey,
+                                                                  size_t n, double L, int nblk,
+                                                                  double* __restrict__ part) {
   constexpr int NQ = nt(PF);
-  constexpr MI<PF> mi{};
-  __shared__ double pw[kFarAStage][3][PF + 1];
-  __shared__ double ga[kFarAStage][4];
   const int o = blockIdx.y;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   size_t obeg, oend;
   octant_range(skey, n, o, &obeg, &oend);
   const size_t len = oend - obeg;
   const size_t chunk = (len + nblk - 1) / nblk;
-  const size_t beg = obeg + (size_t)blockIdx.x * chunk;
+  const size_t beg = obeg + (size_t)blockIdx.x * chunk < oend ? obeg + (size_t)blockIdx.x * chunk
+                                                              : oend;
   const size_t end = beg + chunk < oend ? beg + chunk : oend;
   double c[3];
   octant_center(o, L, c);
-  constexpr int PER = (NQ + kFarAThreads - 1) / kFarAThreads;
-  double acc[PER];
-  int ka[PER], kb[PER], kc[PER];
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    acc[r] = 0.0;
-    const int k = threadIdx.x + r * kFarAThreads;
-    ka[r] = k < NQ ? mi.a[k] : 0;
-    kb[r] = k < NQ ? mi.b[k] : 0;
-    kc[r] = k < NQ ? mi.c[k] : 0;
-  }
-  for (size_t b0 = beg; b0 < end; b0 += kFarAStage) {
-    if (threadIdx.x < kFarAStage) {
-      const size_t s = b0 + threadIdx.x;
-      const bool ok = s < end;
-      const double d[3] = {ok ? spos[s] - c[0] : 0.0, ok ? spos[n + s] - c[1] : 0.0,
-                           ok ? spos[2 * n + s] - c[2] : 0.0};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        double p = 1.0;
-        pw[threadIdx.x][a][0] = 1.0;
-#pragma unroll
-        for (int e = 1; e <= PF; ++e) {
-          p *= d[a];
-          pw[threadIdx.x][a][e] = p;
-        }
-      }
-      const T4 r = ok ? arec[s] : T4{};
-      ga[threadIdx.x][0] = ok ? (double)r.x : 0.0;
-      ga[threadIdx.x][1] = ok ? (double)r.y : 0.0;
-      ga[threadIdx.x][2] = ok ? (double)r.z : 0.0;
-      ga[threadIdx.x][3] = ok ? (double)r.w : 0.0;
-    }
-    __syncthreads();
-    for (int p = 0; p < kFarAStage; ++p) {
-#pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int a = ka[r], b = kb[r], cc = kc[r];
-        const double* px = pw[p][0];
-        const double* py = pw[p][1];
-        const double* pz = pw[p][2];
-        double v = -ga[p][3] * px[a] * py[b] * pz[cc];
-        if (a) v += ga[p][0] * (double)a * px[a - 1] * py[b] * pz[cc];
-        if (b) v += ga[p][1] * (double)b * px[a] * py[b - 1] * pz[cc];
-        if (cc) v += ga[p][2] * (double)cc * px[a] * py[b] * pz[cc - 1];
-        acc[r] += v;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int k = threadIdx.x + r * kFarAThreads;
-    if (k < NQ) part[((size_t)o * nblk + blockIdx.x) * NQ + k] = acc[r];
+  double* out = part + ((size_t)o * nblk + blockIdx.x) * NQ;
+  switch (wid) {
+    case 0: far_adj_local_wave<PF, 0, T4>(spos, arec, n, beg, end, c, lane, out); break;
+    case 1: far_adj_local_wave<PF, 1, T4>(spos, arec, n, beg, end, c, lane, out); break;
+    case 2: far_adj_local_wave<PF, 2, T4>(spos, arec, n, beg, end, c, lane, out); break;
+    default: far_adj_local_wave<PF, 3, T4>(spos, arec, n, beg, end, c, lane, out); break;
   }
 }
 
@@ -106,12 +116,6 @@ __global__ void __launch_bounds__(256) k_far_adj_sum(const double* __restrict__ 
   double acc = 0.0;
   for (int b = 0; b < nblk; ++b) acc += part[((size_t)t * nblk + b) * NQ + q];
   lb[i] = G * acc;
-}
-
-__device__ __forceinline__ double binom_exact_a(int n, int k) {
-  unsigned long long b = 1;
-  for (int u = 1; u <= k; ++u) b = b * (unsigned long long)(n - k + u) / (unsigned long long)u;
-  return (double)b;
 }
 
 __device__ __forceinline__ void mi_decode(int k, int* a, int* b, int* c) {
@@ -149,8 +153,7 @@ __global__ void __launch_bounds__(64) k_far_adj_moments(const double* __restrict
     const int dx = ((t >> 2) & 1) - ((so >> 2) & 1), dy = ((t >> 1) & 1) - ((so >> 1) & 1),
               dz = (t & 1) - (so & 1);
     const double* Tp = tpsi + (size_t)((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * NT2;
-    const double bin = binom_exact_a(qa + ka, ka) * binom_exact_a(qb + kb, kb) *
-                       binom_exact_a(qc + kc, kc);
+    const double bin = kBinom.v[qa + ka][ka] * kBinom.v[qb + kb][kb] * kBinom.v[qc + kc][kc];
     acc += lb[(size_t)t * NQ + q] * bin * Tp[mi_index(qa + ka, qb + kb, qc + kc)];
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
@@ -208,14 +211,23 @@ __global__ void __launch_bounds__(256) k_far_adj_apply(
     const T4 r = arec[s];
     const double ga[3] = {(double)r.x, (double)r.y, (double)r.z};
     const double gp = (double)r.w;
-    // target side: gradient and its derivative along gacc
+    // target side: gradient and its derivative along gacc; source side.
+    // Where the whole wavefront lies in one octant (all but at most 7
+    // wavefronts), the coefficient pointers are wave-uniform and the
+    // coefficients come through the scalar cache.
     Dual<double> f[4];
-    local_eval<PF, Dual<double>>(lam + (size_t)o * NQ, Dual<double>(h[0], ga[0]),
-                                 Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
-    for (int a = 0; a < 3; ++a) xb[a] += G * f[a].d - G * gp * f[a].v;
-    // source side
     double sm[4];
-    local_eval<PF, double>(mbar + (size_t)o * NQ, h[0], h[1], h[2], sm);
+    const int o0 = __builtin_amdgcn_readfirstlane(o);
+    if (__all(o == o0)) {
+      local_eval<PF, Dual<double>>(lam + (size_t)o0 * NQ, Dual<double>(h[0], ga[0]),
+                                   Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
+      local_eval<PF, double>(mbar + (size_t)o0 * NQ, h[0], h[1], h[2], sm);
+    } else {
+      local_eval<PF, Dual<double>>(lam + (size_t)o * NQ, Dual<double>(h[0], ga[0]),
+                                   Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
+      local_eval<PF, double>(mbar + (size_t)o * NQ, h[0], h[1], h[2], sm);
+    }
+    for (int a = 0; a < 3; ++a) xb[a] += G * f[a].d - G * gp * f[a].v;
     const double m = smass[s];
     for (int a = 0; a < 3; ++a) xb[a] += m * sm[a];
     mb += sm[3];
@@ -239,10 +251,10 @@ static hipError_t far_adj_run(const double* spos, const double* smass, const uin
     if (nblk > nblk_max) nblk = nblk_max;
     if (nblk < 1) nblk = 1;
     if (fp32)
-      k_far_adj_local<PF, float4><<<dim3(nblk, 8), kFarAThreads, 0, s>>>(
+      k_far_adj_local<PF, float4><<<dim3(nblk, 8), 64 * kFarWaves, 0, s>>>(
           spos, (const float4*)arec, skey, n, box, nblk, part);
     else
-      k_far_adj_local<PF, double4><<<dim3(nblk, 8), kFarAThreads, 0, s>>>(
+      k_far_adj_local<PF, double4><<<dim3(nblk, 8), 64 * kFarWaves, 0, s>>>(
           spos, (const double4*)arec, skey, n, box, nblk, part);
     k_far_adj_sum<PF><<<(8 * nt(PF) + 255) / 256, 256, 0, s>>>(part, nblk, G, lb);
     k_far_adj_moments<PF><<<dim3(nt(PF), 8), 64, 0, s>>>(lb, tpsi, mbar);
