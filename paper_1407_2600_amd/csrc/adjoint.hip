@@ -164,14 +164,15 @@ constexpr int kAdjStage = 128;
 
 template <typename T, typename T4, bool OWN>
 __device__ __forceinline__ void p2p_adj_staged(const T4* __restrict__ st,
-                                               const T4* __restrict__ sa, int a, int b, T tx,
-                                               T ty, T tz, T eps2, T mk, const T4& ak,
-                                               uint32_t self_slot, Acc<T>& acc) {
+                                               const T4* __restrict__ sa, int a, int b,
+                                               uint32_t sub, uint32_t split, T tx, T ty, T tz,
+                                               T eps2, T mk, const T4& ak, uint32_t self_slot,
+                                               Acc<T>& acc) {
   for (int b0 = a; b0 < b; b0 += 64) {
     const int b1 = b0 + 64 < b ? b0 + 64 : b;
     T part[4] = {0, 0, 0, 0};
 #pragma unroll 2
-    for (int j = b0; j < b1; ++j) {
+    for (int j = b0 + (int)sub; j < b1; j += (int)split) {
       const T4 r = st[j];
       const T4 aj = sa[j];
       if constexpr (OWN) {
@@ -193,7 +194,11 @@ __device__ __forceinline__ void p2p_adj_staged(const T4* __restrict__ st,
   }
 }
 
-template <typename T, typename T4>
+// TAIL selects the passes as in the forward direct kernel: the main launch
+// takes the passes over more than 32 targets, the tail launch a last pass of
+// at most 32 targets with the wave split into 2 or 4 sub-groups that share
+// out the staged sources.
+template <typename T, typename T4, bool TAIL>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, uint32_t ngroups,
                                                             double L, T eps2,
                                                             const double* __restrict__ spos,
@@ -220,9 +225,18 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
   double cA[3];
   center_of(C.key[A], C.level[A], L, cA);
   const uint32_t off = G.off_p2p[g], cnt = G.cnt_p2p[g];
-  for (uint32_t t0 = 0; t0 < count; t0 += 64) {
-    const uint32_t s = first + t0 + lane;
-    const bool act = s < first + count;
+  const uint32_t tail0 = count - count % 64;
+  const bool has_tail = count % 64 != 0 && count % 64 <= 32;
+  if (TAIL && !has_tail) return;
+  for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
+    const uint32_t rem = count - t0;
+    if (!TAIL && rem <= 32) break;
+    const uint32_t split = !TAIL ? 1u : rem <= 16 ? 4u : 2u;  // wave-uniform
+    const int width = 64 / (int)split;
+    const uint32_t sub = (uint32_t)(lane / width);
+    const int tl = lane % width;
+    const uint32_t s = first + t0 + tl;
+    const bool act = (uint32_t)tl < rem;
     const uint32_t ss = act ? s : first;
     const T tx = (T)(spos[ss] - cA[0]), ty = (T)(spos[n + ss] - cA[1]),
             tz = (T)(spos[2 * n + ss] - cA[2]);
@@ -246,7 +260,8 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
         sa[k] = arec[j];
       }
       wave_sync();
-      p2p_adj_staged<T, T4, true>(st, sa, 0, nb, tx, ty, tz, eps2, mk, ak, ss - first - s0, acc);
+      p2p_adj_staged<T, T4, true>(st, sa, 0, nb, sub, split, tx, ty, tz, eps2, mk, ak,
+                                  ss - first - s0, acc);
     }
     // listed leaves, 64 entries at a time
     for (uint32_t q0 = 0; q0 < cnt; q0 += 64) {
@@ -301,7 +316,8 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
           const uint32_t hi = __builtin_amdgcn_readfirstlane(e_incl[ecur]);
           const int a = (int)((lo > s0 ? lo : s0) - s0);
           const int b = (int)((hi < s1 ? hi : s1) - s0);
-          p2p_adj_staged<T, T4, false>(st, sa, a, b, tx, ty, tz, eps2, mk, ak, 0u, acc);
+          p2p_adj_staged<T, T4, false>(st, sa, a, b, sub, split, tx, ty, tz, eps2, mk, ak, 0u,
+                                       acc);
           if (hi > s1) break;  // the entry continues in the next batch
           lo = hi;
           ++ecur;
@@ -309,7 +325,13 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
         }
       }
     }
-    if (act) out[s] = make_double4(acc.get(0), acc.get(1), acc.get(2), acc.get(3));
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = acc.get(k);
+    for (int w = width; w < 64; w <<= 1)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], w, 64);
+    if (act && sub == 0) out[s] = make_double4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -321,23 +343,26 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
 // entries' mass and effective-charge coefficient blocks through LDS with
 // coalesced loads, and adds the sub-groups' partial sums at the end.
 template <int P, typename T, typename T4, bool TAIL>
-__global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, uint32_t ngroups,
-                                                            double L, T eps2,
-                                                            const double* __restrict__ spos,
-                                                            const T4* __restrict__ srec,
-                                                            const T4* __restrict__ arec,
-                                                            const T* __restrict__ ecoef, size_t n,
-                                                            const uint4* __restrict__ list,
-                                                            double4* __restrict__ out) {
+__device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
+                                              double L, T eps2,
+                                              const double* __restrict__ spos,
+                                              const T4* __restrict__ srec,
+                                              const T4* __restrict__ arec,
+                                              const T* __restrict__ ecoef, size_t n,
+                                              const uint4* __restrict__ list,
+                                              double4* __restrict__ out){
   constexpr int STR = coef_stride(P);
   constexpr int ESTR = coef_stride(P + 1, true);
-  __shared__ T tl_cf[TAIL ? kAdjWaves : 1][4][TAIL ? STR : 1];
-  __shared__ T tl_ef[TAIL ? kAdjWaves : 1][4][TAIL ? ESTR : 1];
-  __shared__ T tl_c[TAIL ? kAdjWaves : 1][4][4];
-  __shared__ int tl_b[TAIL ? kAdjWaves : 1][4];
+  constexpr bool kLdsTail = TAIL && sizeof(T) == 8;
+  __shared__ T tl_cf[kLdsTail ? kAdjWaves : 1][4][kLdsTail ? STR : 1];
+  __shared__ T tl_ef[kLdsTail ? kAdjWaves : 1][4][kLdsTail ? ESTR : 1];
+  __shared__ T tl_c[kLdsTail ? kAdjWaves : 1][4][4];
+  __shared__ int tl_b[kLdsTail ? kAdjWaves : 1][4];
+  // tail pass: the block's wavefronts share out one group's list and add
+  // their results through LDS in a fixed order
+  __shared__ double tl_red[TAIL ? kAdjWaves : 1][TAIL ? 32 : 1][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kAdjWaves + wid);
-  if (g >= ngroups) return;
+  const uint32_t nw = TAIL ? kAdjWaves : 1, w0 = TAIL ? (uint32_t)wid : 0;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
@@ -367,12 +392,10 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
     T part[4] = {0, 0, 0, 0};
     // one (target, cell) term: the mass field and its derivative along gacc_k
     // (dual numbers), and the effective charges' potential and gradient
-    auto term = [&](T Rx, T Ry, T Rz, const T* cf, const T* ef) {
+    auto term = [&](T Rx, T Ry, T Rz, const auto& cf, const auto& ef) {
       Dual<T> fm[4];
-      m2p_eval<P, false, Dual<T>, T>(Dual<T>(Rx, ak.x), Dual<T>(Ry, ak.y), Dual<T>(Rz, ak.z),
-                                     eps2, cf, fm);
       T fe[4];
-      m2p_eval<P + 1, true, T, T>(Rx, Ry, Rz, eps2, ef, fe);
+      m2p_eval_adj<P, T>(Rx, Ry, Rz, ak.x, ak.y, ak.z, eps2, as_src<T>(cf), as_src<T>(ef), fm, fe);
       part[0] += fm[0].d - ak.w * fm[0].v - mk * fe[0];
       part[1] += fm[1].d - ak.w * fm[1].v - mk * fe[1];
       part[2] += fm[2].d - ak.w * fm[2].v - mk * fe[2];
@@ -389,11 +412,51 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
           for (int k = 0; k < 4; ++k) part[k] = (T)0;
         }
       }
+    } else if constexpr (sizeof(T) == 4) {
+      // FP32: each 16-lane row holds its sub-group's entry's two coefficient
+      // blocks spread over the row (row broadcasts feed them to its lanes),
+      // and loads the sub-group's next entry while this one is evaluated
+      constexpr int NC = (STR + 15) / 16, NE = (ESTR + 15) / 16;
+      const int rl = lane & 15;
+      const uint32_t step = nw * split;
+      RowCoef<NC> cf;
+      RowCoef<NE> ef;
+      T c[3] = {0, 0, 0};
+      uint32_t q = w0 * split + sub;
+      if (q < cnt) {
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        cf.load(coef + (size_t)B * STR, STR, rl);
+        ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+      }
+      uint32_t it = 0;
+      while (q < cnt) {
+        const uint32_t qn = q + step;
+        RowCoef<NC> cf2;
+        RowCoef<NE> ef2;
+        T c2[3] = {0, 0, 0};
+        if (qn < cnt) {
+          const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
+          cf2.load(coef + (size_t)B * STR, STR, rl);
+          ef2.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+        }
+        term(tx - c[0], ty - c[1], tz - c[2], cf, ef);
+        if ((++it & 15) == 0) {
+          acc.fold(part);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) part[k] = (T)0;
+        }
+        cf = cf2;
+        ef = ef2;
+        c[0] = c2[0];
+        c[1] = c2[1];
+        c[2] = c2[2];
+        q = qn;
+      }
     } else {
       T* cbuf = &tl_cf[wid][0][0];
       T* ebuf = &tl_ef[wid][0][0];
       uint32_t it = 0;
-      for (uint32_t q0 = 0; q0 < cnt; q0 += split) {
+      for (uint32_t q0 = w0 * split; q0 < cnt; q0 += nw * split) {
         const uint32_t ne = cnt - q0 < split ? cnt - q0 : split;
         if ((uint32_t)lane < ne) {
           T c[3];
@@ -403,12 +466,12 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
           tl_c[wid][lane][2] = c[2];
           tl_b[wid][lane] = B;
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (uint32_t i = (uint32_t)lane; i < ne * STR; i += 64)
           cbuf[i] = coef[(size_t)tl_b[wid][i / STR] * STR + i % STR];
         for (uint32_t i = (uint32_t)lane; i < ne * ESTR; i += 64)
           ebuf[i] = ecoef[(size_t)tl_b[wid][i / ESTR] * ESTR + i % ESTR];
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         if (sub < ne) {
           term(tx - tl_c[wid][sub][0], ty - tl_c[wid][sub][1], tz - tl_c[wid][sub][2],
                cbuf + (size_t)sub * STR, ebuf + (size_t)sub * ESTR);
@@ -418,7 +481,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
             for (int k = 0; k < 4; ++k) part[k] = (T)0;
           }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
       }
     }
     acc.fold(part);
@@ -428,7 +491,20 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, u
     for (int w = width; w < 64; w <<= 1)
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], w, 64);
-    if (act && sub == 0) {
+    if constexpr (TAIL) {
+      if (sub == 0 && tl < 32)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tl_red[wid][tl][k] = v[k];
+      __syncthreads();
+      if (wid == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          v[k] = tl_red[0][tl < 32 ? tl : 0][k];
+          for (int w = 1; w < kAdjWaves; ++w) v[k] += tl_red[w][tl < 32 ? tl : 0][k];
+        }
+      }
+    }
+    if (act && sub == 0 && w0 == 0) {
       double4 o = out[s];
       o.x += v[0];
       o.y += v[1];
@@ -474,60 +550,98 @@ hipError_t adj_moments_level(bool fp32, int order, const Cells& C, const double*
   return hipGetLastError();
 }
 
+template <typename T, typename T4>
+static hipError_t p2p_adj_t(const Cells& C, const Groups& G, uint32_t ngroups, double L, T eps2,
+                            const double* spos, const T4* srec, const T4* arec, size_t n,
+                            const uint32_t* list, double4* out, hipStream_t s,
+                            const SideStream& side) {
+  const unsigned nb = (ngroups + kAdjWaves - 1) / kAdjWaves;
+  hipStream_t st;
+  hipError_t e = side_fork(side, s, &st);
+  if (e != hipSuccess) return e;
+  k_p2p_adj<T, T4, true><<<nb, 64 * kAdjWaves, 0, st>>>(C, G, ngroups, L, eps2, spos, srec, arec,
+                                                        n, list, out);
+  k_p2p_adj<T, T4, false><<<nb, 64 * kAdjWaves, 0, s>>>(C, G, ngroups, L, eps2, spos, srec, arec,
+                                                         n, list, out);
+  e = hipGetLastError();
+  return e != hipSuccess ? e : side_join(side, s);
+}
+
 hipError_t p2p_adj_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
                           double eps, const double* spos, const void* srec, const void* arec,
-                          size_t n, const uint32_t* list, double4* out, hipStream_t s) {
+                          size_t n, const uint32_t* list, double4* out, hipStream_t s,
+                          const SideStream& side) {
   if (ngroups == 0) return hipSuccess;
-  unsigned blocks = (ngroups + kAdjWaves - 1) / kAdjWaves;
   if (fp32)
-    k_p2p_adj<float, float4><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, (float)(eps * eps), spos, (const float4*)srec, (const float4*)arec, n,
-        list, out);
-  else
-    k_p2p_adj<double, double4><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec, n, list,
-        out);
-  return hipGetLastError();
+    return p2p_adj_t<float, float4>(C, G, ngroups, L, (float)(eps * eps), spos,
+                                    (const float4*)srec, (const float4*)arec, n, list, out, s,
+                                    side);
+  return p2p_adj_t<double, double4>(C, G, ngroups, L, eps * eps, spos, (const double4*)srec,
+                                    (const double4*)arec, n, list, out, s, side);
+}
+
+// Main passes one group per wavefront, tail passes one group per block; the
+// tail pass goes on the side stream (as for the forward kernels).
+template <int P, typename T, typename T4, bool TAIL>
+__global__ void __launch_bounds__(64 * kAdjWaves) k_m2p_adj(Cells C, Groups G, uint32_t ngroups,
+                                                            double L, T eps2,
+                                                            const double* __restrict__ spos,
+                                                            const T4* __restrict__ srec,
+                                                            const T4* __restrict__ arec,
+                                                            const T* __restrict__ ecoef, size_t n,
+                                                            const uint4* __restrict__ list,
+                                                            double4* __restrict__ out) {
+  const int wid = threadIdx.x >> 6;
+  const uint32_t g =
+      __builtin_amdgcn_readfirstlane(TAIL ? xcd_block() : xcd_block() * kAdjWaves + wid);
+  if (g >= ngroups) return;
+  m2p_adj_group<P, T, T4, TAIL>(g, C, G, L, eps2, spos, srec, arec, ecoef, n, list, out);
+}
+
+template <int P, typename T, typename T4>
+static hipError_t m2p_adj_t(const Cells& C, const Groups& G, uint32_t ngroups, double L, T eps2,
+                            const double* spos, const T4* srec, const T4* arec, const T* ecoef,
+                            size_t n, const uint4* list, double4* out, hipStream_t s,
+                            const SideStream& side) {
+  const unsigned nb = (ngroups + kAdjWaves - 1) / kAdjWaves;
+  hipStream_t st;
+  hipError_t e = side_fork(side, s, &st);
+  if (e != hipSuccess) return e;
+  k_m2p_adj<P, T, T4, true><<<ngroups, 64 * kAdjWaves, 0, st>>>(C, G, ngroups, L, eps2, spos,
+                                                                 srec, arec, ecoef, n, list, out);
+  k_m2p_adj<P, T, T4, false><<<nb, 64 * kAdjWaves, 0, s>>>(C, G, ngroups, L, eps2, spos, srec,
+                                                            arec, ecoef, n, list, out);
+  e = hipGetLastError();
+  return e != hipSuccess ? e : side_join(side, s);
 }
 
 template <int P>
-static void m2p_adj_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
-                      double eps, const double* spos, const void* srec, const void* arec,
-                      const void* ecoef, size_t n, const uint4* list, double4* out,
-                      hipStream_t s) {
-  unsigned blocks = (ngroups + kAdjWaves - 1) / kAdjWaves;
-  if (fp32) {
-    const float e2 = (float)(eps * eps);
-    k_m2p_adj<P, float, float4, false><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, e2, spos, (const float4*)srec, (const float4*)arec,
-        (const float*)ecoef, n, list, out);
-    k_m2p_adj<P, float, float4, true><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, e2, spos, (const float4*)srec, (const float4*)arec,
-        (const float*)ecoef, n, list, out);
-  } else {
-    k_m2p_adj<P, double, double4, false><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec,
-        (const double*)ecoef, n, list, out);
-    k_m2p_adj<P, double, double4, true><<<blocks, 64 * kAdjWaves, 0, s>>>(
-        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, (const double4*)arec,
-        (const double*)ecoef, n, list, out);
-  }
+static hipError_t m2p_adj_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups,
+                            double L, double eps, const double* spos, const void* srec,
+                            const void* arec, const void* ecoef, size_t n, const uint4* list,
+                            double4* out, hipStream_t s, const SideStream& side) {
+  if (fp32)
+    return m2p_adj_t<P, float, float4>(C, G, ngroups, L, (float)(eps * eps), spos,
+                                       (const float4*)srec, (const float4*)arec,
+                                       (const float*)ecoef, n, list, out, s, side);
+  return m2p_adj_t<P, double, double4>(C, G, ngroups, L, eps * eps, spos, (const double4*)srec,
+                                       (const double4*)arec, (const double*)ecoef, n, list, out,
+                                       s, side);
 }
 
 hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                           double L, double eps, const double* spos, const void* srec,
                           const void* arec, const void* ecoef, size_t n, const uint4* list,
-                          double4* out, hipStream_t s) {
+                          double4* out, hipStream_t s, const SideStream& side) {
   if (ngroups == 0) return hipSuccess;
   switch (order) {
-    case 0: m2p_adj_p<0>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
-    case 1: m2p_adj_p<1>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
-    case 2: m2p_adj_p<2>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
-    case 3: m2p_adj_p<3>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
-    case 4: m2p_adj_p<4>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s); break;
+#define HOT_MADJ(P) \
+  case P:           \
+    return m2p_adj_p<P>(fp32, C, G, ngroups, L, eps, spos, srec, arec, ecoef, n, list, out, s, side);
+    HOT_MADJ(0) HOT_MADJ(1) HOT_MADJ(2) HOT_MADJ(3) HOT_MADJ(4)
+#undef HOT_MADJ
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace hot

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "hot_internal.h"
 
@@ -197,23 +198,81 @@ __device__ __forceinline__ Dual<T> rsqrt_t(Dual<T> x) {
   return {r, (T)(-0.5) * r * r * r * x.d};
 }
 
+// ------------------------------------------------------ coefficient sources
+// compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (N > 0) static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// a coefficient block in memory
+template <typename C>
+struct PtrCoef {
+  const C* __restrict__ p;
+  template <int I>
+  __device__ __forceinline__ C get() const {
+    return p[I];
+  }
+};
+
+// A coefficient block held by one 16-lane row: lane l of the row holds
+// coefficients l, l + 16, l + 32, ...; coefficient I reaches every lane of the
+// row by a DPP row broadcast from lane I % 16.
+template <int NR>
+struct RowCoef {
+  float r[NR];
+  template <int I>
+  __device__ __forceinline__ float get() const {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, r[I >> 4]), 0x150 + (I & 15), 0xF,
+                                        0xF, true));
+  }
+  // the block at p (n values), read by the calling row (rl = lane within it)
+  __device__ __forceinline__ void load(const float* __restrict__ p, int n, int rl) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) r[j] = rl + 16 * j < n ? p[rl + 16 * j] : 0.0f;
+  }
+};
+
+// a coefficient source from a pointer (or a RowCoef as it is)
+template <typename C>
+__device__ __forceinline__ PtrCoef<C> as_src(const C* p) {
+  return PtrCoef<C>{p};
+}
+template <typename C, int NR>
+__device__ __forceinline__ const RowCoef<NR>& as_src(const RowCoef<NR>& r) {
+  return r;
+}
+
+// offset of part (m, j) in a coefficient block
+__host__ __device__ constexpr int part_offset(int P, bool dip, int m0, int j0) {
+  int o = 0;
+  for (int m = 0; m <= P; ++m)
+    for (int j = 0; j <= part_jmax(P, m); ++j) {
+      if (m == m0 && j == j0) return o;
+      if (part_stored(m, m - j, dip)) o += part_size(m - j);
+    }
+  return o;
+}
+
 // ---------------------------------------------------------------- multipole
 // Phi = rinv sum_m rho^m P_m(R),
 // grad Phi = rinv sum_m rho^m grad P_m - rinv rho R sum_m (2m+1) rho^m P_m,
 // with the per-cell coefficient layout described in hot_internal.h.  V is the
-// value type (T or Dual<T>), C the coefficient type.  out = (grad Phi, Phi).
-template <int P, bool DIP, typename V, typename C>
-__device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __restrict__ cf,
-                                         V out[4]) {
-  const V u = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, V(eps2))));
-  const V rinv = rsqrt_t(u);
-  const V rho = rinv * rinv;
-  constexpr int DM = P > 0 ? P - 1 : 0;
-  constexpr MI<DM> mi{};
-  V mono[nt(DM)];
-  mono[0] = V((C)1);
+// value type (T or Dual<T>), C the coefficient type, CF the coefficient
+// source (PtrCoef or RowCoef).  out = (grad Phi, Phi).
+// monomials R^k, |k| <= D, in multi-index order; entries below K0 are
+// already filled in (a caller may pass lower-degree monomials it has)
+template <int D, int K0 = 1, typename V>
+__device__ __forceinline__ void monomials(V Rx, V Ry, V Rz, V* mono) {
+  constexpr MI<D> mi{};
+  if constexpr (K0 == 0) mono[0] = V(1);
 #pragma unroll
-  for (int k = 1; k < nt(DM); ++k) {
+  for (int k = K0 > 1 ? K0 : 1; k < nt(D); ++k) {
     const int a = mi.a[k], b = mi.b[k], c = mi.c[k];
     if (a > 0)
       mono[k] = (a + b + c == 1) ? Rx : mono[mi_index(a - 1, b, c)] * Rx;
@@ -222,54 +281,82 @@ __device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __re
     else
       mono[k] = (c == 1) ? Rz : mono[mi_index(a, b, c - 1)] * Rz;
   }
+}
+
+// the evaluation given rinv, rho and the monomials of degree <= max(P-1, 0)
+template <int P, bool DIP, typename V, typename C, typename CF>
+__device__ __forceinline__ void m2p_eval_pre(V Rx, V Ry, V Rz, V rinv, V rho, const V* mono,
+                                             const CF& cf, V out[4]) {
   // accumulators take their first contribution by assignment (which parts
   // exist is known at compile time), so no addition of zero is emitted
   V Pm[P + 1], Vx[P + 1], Vy[P + 1], Vz[P + 1];
-  bool hasP[P + 1], hasV[P + 1];
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-    Pm[m] = Vx[m] = Vy[m] = Vz[m] = V((C)0);
-    hasP[m] = hasV[m] = false;
-  }
-  int o = 0;
-#pragma unroll
-  for (int m = 0; m <= P; ++m) {
-#pragma unroll
-    for (int j = 0; j <= part_jmax(P, m); ++j) {
-      const int d = m - j;
-      if (!part_stored(m, d, DIP)) continue;
-      if (d == 0) {
-        Pm[m] = hasP[m] ? Pm[m] + cf[o] : V(cf[o]);
-        hasP[m] = true;
-        o += 1;
-      } else {
-        const int nk = nte(d - 1);
-        const int base = nt(d - 2);
-        V vx = cf[o] * mono[base], vy = cf[o + nk] * mono[base],
-          vz = cf[o + 2 * nk] * mono[base];
-#pragma unroll
-        for (int k = 1; k < nk; ++k) {
-          vx = fma(cf[o + k], mono[base + k], vx);
-          vy = fma(cf[o + nk + k], mono[base + k], vy);
-          vz = fma(cf[o + 2 * nk + k], mono[base + k], vz);
-        }
-        o += 3 * nk;
-        if (hasV[m]) {
-          Vx[m] += vx;
-          Vy[m] += vy;
-          Vz[m] += vz;
+  static_for<P + 1>([&](auto M) {
+    constexpr int m = M;
+    constexpr int J = part_jmax(P, m);
+    static_for<J + 1>([&](auto JJ) {
+      constexpr int j = JJ;
+      constexpr int d = m - j;
+      // does an earlier part of this m exist (then accumulate)?
+      constexpr bool firstP = [] {
+        for (int i = 0; i < j; ++i)
+          if (part_stored(m, m - i, DIP)) return false;
+        return true;
+      }();
+      constexpr bool firstV = [] {
+        for (int i = 0; i < j; ++i)
+          if (part_stored(m, m - i, DIP) && m - i > 0) return false;
+        return true;
+      }();
+      if constexpr (part_stored(m, d, DIP)) {
+        constexpr int o = part_offset(P, DIP, m, j);
+        if constexpr (d == 0) {
+          const C c0 = cf.template get<o>();
+          if constexpr (firstP)
+            Pm[m] = V(c0);
+          else
+            Pm[m] = Pm[m] + c0;
         } else {
-          Vx[m] = vx;
-          Vy[m] = vy;
-          Vz[m] = vz;
+          constexpr int nk = nte(d - 1);
+          constexpr int base = nt(d - 2);
+          V vx = cf.template get<o>() * mono[base], vy = cf.template get<o + nk>() * mono[base],
+            vz = cf.template get<o + 2 * nk>() * mono[base];
+          static_for<nk - 1>([&](auto KK) {
+            constexpr int k = KK + 1;
+            vx = fma(cf.template get<o + k>(), mono[base + k], vx);
+            vy = fma(cf.template get<o + nk + k>(), mono[base + k], vy);
+            vz = fma(cf.template get<o + 2 * nk + k>(), mono[base + k], vz);
+          });
+          if constexpr (firstV) {
+            Vx[m] = vx;
+            Vy[m] = vy;
+            Vz[m] = vz;
+          } else {
+            Vx[m] += vx;
+            Vy[m] += vy;
+            Vz[m] += vz;
+          }
+          const V dot = fma(Rx, vx, fma(Ry, vy, Rz * vz));
+          if constexpr (firstP)
+            Pm[m] = dot * (C)(1.0 / d);
+          else
+            Pm[m] = fma(dot, (C)(1.0 / d), Pm[m]);
         }
-        hasV[m] = true;
-        const V dot = fma(Rx, vx, fma(Ry, vy, Rz * vz));
-        Pm[m] = hasP[m] ? fma(dot, (C)(1.0 / d), Pm[m]) : dot * (C)(1.0 / d);
-        hasP[m] = true;
       }
-    }
-  }
+    });
+    // parts that do not exist for this m leave zero accumulators
+    constexpr bool anyP = [] {
+      for (int i = 0; i <= J; ++i)
+        if (part_stored(m, m - i, DIP)) return true;
+      return false;
+    }();
+    constexpr bool anyV = [] {
+      for (int i = 0; i <= J; ++i)
+        if (part_stored(m, m - i, DIP) && m - i > 0) return true;
+      return false;
+    }();
+    if constexpr (!anyP) Pm[m] = V((C)0);
+    if constexpr (!anyV) Vx[m] = Vy[m] = Vz[m] = V((C)0);
+  });
   V Pv = Pm[P], Q = (C)(2 * P + 1) * Pm[P], Gx = Vx[P], Gy = Vy[P], Gz = Vz[P];
 #pragma unroll
   for (int m = P - 1; m >= 0; --m) {
@@ -284,6 +371,54 @@ __device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __re
   out[1] = rinv * fma(-rq, Ry, Gy);
   out[2] = rinv * fma(-rq, Rz, Gz);
   out[3] = rinv * Pv;
+}
+
+template <int P, bool DIP, typename V, typename C, typename CF>
+__device__ __forceinline__ void m2p_eval_src(V Rx, V Ry, V Rz, C eps2, const CF& cf, V out[4]) {
+  const V u = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, V(eps2))));
+  const V rinv = rsqrt_t(u);
+  const V rho = rinv * rinv;
+  constexpr int DM = P > 0 ? P - 1 : 0;
+  V mono[nt(DM)];
+  mono[0] = V((C)1);
+  monomials<DM>(Rx, Ry, Rz, mono);
+  m2p_eval_pre<P, DIP, V, C>(Rx, Ry, Rz, rinv, rho, mono, cf, out);
+}
+
+template <int P, bool DIP, typename V, typename C>
+__device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const C* __restrict__ cf,
+                                         V out[4]) {
+  m2p_eval_src<P, DIP, V, C>(Rx, Ry, Rz, eps2, PtrCoef<C>{cf}, out);
+}
+template <int P, bool DIP, typename V, typename C, int NR>
+__device__ __forceinline__ void m2p_eval(V Rx, V Ry, V Rz, C eps2, const RowCoef<NR>& cf,
+                                         V out[4]) {
+  m2p_eval_src<P, DIP, V, C>(Rx, Ry, Rz, eps2, cf, out);
+}
+
+// The two multipole evaluations of one adjoint (target, cell) term at the
+// same R: the order-P mass expansion on dual numbers along g (field and its
+// derivative along g) and the order-P+1 expansion with dipole parts of the
+// effective charges (plain).  The plain one reuses the value parts of the
+// dual distance and monomials, which are the same operations.
+template <int P, typename T, typename CF, typename EF>
+__device__ __forceinline__ void m2p_eval_adj(T Rx, T Ry, T Rz, T gx, T gy, T gz, T eps2,
+                                             const CF& cf, const EF& ef, Dual<T> fm[4],
+                                             T fe[4]) {
+  const Dual<T> X(Rx, gx), Y(Ry, gy), Z(Rz, gz);
+  const Dual<T> u = fma(X, X, fma(Y, Y, fma(Z, Z, Dual<T>(eps2))));
+  const Dual<T> rinv = rsqrt_t(u);
+  const Dual<T> rho = rinv * rinv;
+  constexpr int DM = P > 0 ? P - 1 : 0;
+  Dual<T> mono[nt(DM)];
+  mono[0] = Dual<T>((T)1);
+  monomials<DM>(X, Y, Z, mono);
+  m2p_eval_pre<P, false, Dual<T>, T>(X, Y, Z, rinv, rho, mono, cf, fm);
+  T m5[nt(P)];
+#pragma unroll
+  for (int k = 0; k < nt(DM); ++k) m5[k] = mono[k].v;
+  monomials<P, (P > 0 ? nt(DM) : 1)>(Rx, Ry, Rz, m5);
+  m2p_eval_pre<P + 1, true, T, T>(Rx, Ry, Rz, rinv.v, rho.v, m5, ef, fe);
 }
 
 // One multipole-list record (16 bytes): the (image << 27) | cell entry in w,

@@ -75,24 +75,28 @@ __device__ __forceinline__ void p2p_staged(const T4* __restrict__ st, int a, int
   }
 }
 
+// the per-wavefront LDS of the direct kernels
+template <typename T, typename T4, int W, int S>
+struct SourceStage {
+  T4 st[W][S];
+  uint32_t incl[W][64];
+  uint32_t bf[W][64];
+  T sh[W][3][64];
+};
+
 template <typename T, typename T4, bool TAIL>
-__global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uint32_t ngroups,
-                                                          double L, T eps2,
-                                                          const double* __restrict__ spos,
-                                                          const T4* __restrict__ srec, size_t n,
-                                                          const uint32_t* __restrict__ list,
-                                                          double4* __restrict__ out) {
-  __shared__ T4 stage_all[kForceWaves][kStage];
-  __shared__ uint32_t incl_all[kForceWaves][64];
-  __shared__ uint32_t bf_all[kForceWaves][64];
-  __shared__ T sh_all[kForceWaves][3][64];
+__device__ __forceinline__ void p2p_group(uint32_t g, SourceStage<T, T4, kForceWaves, kStage>& lds,
+                                          Cells C, Groups G,
+                                          double L, T eps2,
+                                          const double* __restrict__ spos,
+                                          const T4* __restrict__ srec, size_t n,
+                                          const uint32_t* __restrict__ list,
+                                          double4* __restrict__ out){
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
-  if (g >= ngroups) return;
-  T4* st = stage_all[wid];
-  uint32_t* e_incl = incl_all[wid];
-  uint32_t* e_bf = bf_all[wid];
-  T(*e_sh)[64] = sh_all[wid];
+  T4* st = lds.st[wid];
+  uint32_t* e_incl = lds.incl[wid];
+  uint32_t* e_bf = lds.bf[wid];
+  T(*e_sh)[64] = lds.sh[wid];
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
@@ -203,30 +207,6 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
   }
 }
 
-// one cell's coefficient block into registers with 16-byte loads (blocks are
-// padded to a multiple of 4 values and 16-byte aligned)
-template <typename T, int N>
-__device__ __forceinline__ void load_block(const T* __restrict__ p, T* out) {
-  if constexpr (sizeof(T) == 4) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int i = 0; i < N / 4; ++i) {
-      const float4 v = q[i];
-      out[4 * i] = v.x;
-      out[4 * i + 1] = v.y;
-      out[4 * i + 2] = v.z;
-      out[4 * i + 3] = v.w;
-    }
-  } else {
-    const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-    for (int i = 0; i < N / 2; ++i) {
-      const double2 v = q[i];
-      out[2 * i] = v.x;
-      out[2 * i + 1] = v.y;
-    }
-  }
-}
 
 // Multipole interactions of one sink group per wavefront, targets in lanes,
 // in passes of up to 64 targets.  TAIL = false: the passes over more than 32
@@ -239,21 +219,23 @@ __device__ __forceinline__ void load_block(const T* __restrict__ p, T* out) {
 // idle do the work.  Separate launches keep the register budget
 // (and occupancy) of the main pass independent of the tail's.
 template <int P, typename T, bool TAIL>
-__global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uint32_t ngroups,
-                                                          double L, T eps2,
-                                                          const double* __restrict__ spos,
-                                                          size_t n,
-                                                          const uint4* __restrict__ list,
-                                                          double4* __restrict__ out) {
+__device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
+                                          double L, T eps2,
+                                          const double* __restrict__ spos,
+                                          size_t n,
+                                          const uint4* __restrict__ list,
+                                          double4* __restrict__ out){
   constexpr int STR = coef_stride(P);
   // tail-pass staging: per wave, up to 4 entries' offsets, cells and blocks
-  constexpr bool kStage = TAIL && sizeof(T) == 8;
-  __shared__ T tail_cf[kStage ? kForceWaves : 1][4][kStage ? STR : 1];
-  __shared__ T tail_c[kStage ? kForceWaves : 1][4][4];
-  __shared__ int tail_b[kStage ? kForceWaves : 1][4];
+  constexpr bool kLdsTail = TAIL && sizeof(T) == 8;
+  __shared__ T tail_cf[kLdsTail ? kForceWaves : 1][4][kLdsTail ? STR : 1];
+  __shared__ T tail_c[kLdsTail ? kForceWaves : 1][4][4];
+  __shared__ int tail_b[kLdsTail ? kForceWaves : 1][4];
+  // tail pass: the block's wavefronts share out one group's list and add
+  // their results through LDS in a fixed order
+  __shared__ double tail_red[TAIL ? kForceWaves : 1][TAIL ? 32 : 1][4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
-  if (g >= ngroups) return;
+  const uint32_t nw = TAIL ? kForceWaves : 1, w0 = TAIL ? (uint32_t)wid : 0;
   const int A = __builtin_amdgcn_readfirstlane(G.cell[g]);
   const uint32_t first = __builtin_amdgcn_readfirstlane(C.first[A]);
   const uint32_t count = __builtin_amdgcn_readfirstlane(C.count[A]);
@@ -297,15 +279,28 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
         }
       }
     } else if constexpr (sizeof(T) == 4) {
-      // FP32: each sub-group loads its own entries' records and 288-byte
-      // coefficient blocks with 16-byte per-lane loads (measured faster than
-      // staging them through LDS for FP32 blocks)
-      uint32_t it = 0;
-      for (uint32_t q = (uint32_t)sub; q < cnt; q += (uint32_t)split) {
-        T c[3];
+      // FP32: each 16-lane row holds its sub-group's entry's coefficient
+      // block spread over the row (row broadcasts feed it to its lanes), and
+      // loads the sub-group's next entry while this one is evaluated
+      constexpr int NC = (STR + 15) / 16;
+      const int rl = lane & 15;
+      const uint32_t step = nw * split;
+      RowCoef<NC> cf;
+      T c[3] = {0, 0, 0};
+      uint32_t q = w0 * split + (uint32_t)sub;
+      if (q < cnt) {
         const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-        T cf[STR];
-        load_block<T, STR>(coef + (size_t)B * STR, cf);
+        cf.load(coef + (size_t)B * STR, STR, rl);
+      }
+      uint32_t it = 0;
+      while (q < cnt) {
+        const uint32_t qn = q + step;
+        RowCoef<NC> cf2;
+        T c2[3] = {0, 0, 0};
+        if (qn < cnt) {
+          const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
+          cf2.load(coef + (size_t)B * STR, STR, rl);
+        }
         T r[4];
         m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, cf, r);
 #pragma unroll
@@ -316,6 +311,11 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
 #pragma unroll
           for (int k = 0; k < 3; ++k) part[k] = (T)0;
         }
+        cf = cf2;
+        c[0] = c2[0];
+        c[1] = c2[1];
+        c[2] = c2[2];
+        q = qn;
       }
     } else {
       // FP64: each round stages the next `split` entries' offsets and
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
       // every sub-group then reads its own block (a broadcast within it)
       T* cbuf = &tail_cf[wid][0][0];
       uint32_t it = 0;
-      for (uint32_t q0 = 0; q0 < cnt; q0 += (uint32_t)split) {
+      for (uint32_t q0 = w0 * split; q0 < cnt; q0 += nw * split) {
         const uint32_t ne = cnt - q0 < (uint32_t)split ? cnt - q0 : (uint32_t)split;
         if ((uint32_t)lane < ne) {
           T c[3];
@@ -333,12 +333,12 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
           tail_c[wid][lane][2] = c[2];
           tail_b[wid][lane] = B;
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (uint32_t i = (uint32_t)lane; i < ne * STR; i += 64) {
           const uint32_t e = i / STR, k = i % STR;
           cbuf[i] = coef[(size_t)tail_b[wid][e] * STR + k];
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         if (sub < ne) {
           T r[4];
           m2p_eval<P, false, T, T>(tx - tail_c[wid][sub][0], ty - tail_c[wid][sub][1],
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
             for (int k = 0; k < 3; ++k) part[k] = (T)0;
           }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
       }
     }
     acc.fold(part);
@@ -362,7 +362,20 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
     for (int w = width; w < 64; w <<= 1)
 #pragma unroll
       for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], w, 64);
-    if (act && sub == 0) {
+    if constexpr (TAIL) {
+      if (sub == 0 && tl < 32)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tail_red[wid][tl][k] = v[k];
+      __syncthreads();
+      if (wid == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          v[k] = tail_red[0][tl < 32 ? tl : 0][k];
+          for (int w = 1; w < kForceWaves; ++w) v[k] += tail_red[w][tl < 32 ? tl : 0][k];
+        }
+      }
+    }
+    if (act && sub == 0 && w0 == 0) {
       double4 o = out[s];
       o.x += v[0];
       o.y += v[1];
@@ -373,57 +386,104 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
   }
 }
 
+// Main and tail passes are separate kernels (the tail pass needs more
+// registers), launched tail first on the context's side stream so that its
+// few long, lightly occupied wavefronts run beside the main passes.
+template <typename T, typename T4, bool TAIL>
+__global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uint32_t ngroups,
+                                                          double L, T eps2,
+                                                          const double* __restrict__ spos,
+                                                          const T4* __restrict__ srec, size_t n,
+                                                          const uint32_t* __restrict__ list,
+                                                          double4* __restrict__ out) {
+  __shared__ SourceStage<T, T4, kForceWaves, kStage> lds;
+  const int wid = threadIdx.x >> 6;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
+  if (g >= ngroups) return;
+  p2p_group<T, T4, TAIL>(g, lds, C, G, L, eps2, spos, srec, n, list, out);
+}
+
+// main passes one group per wavefront; tail passes one group per block
+template <int P, typename T, bool TAIL>
+__global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uint32_t ngroups,
+                                                          double L, T eps2,
+                                                          const double* __restrict__ spos,
+                                                          size_t n,
+                                                          const uint4* __restrict__ list,
+                                                          double4* __restrict__ out) {
+  const int wid = threadIdx.x >> 6;
+  const uint32_t g =
+      __builtin_amdgcn_readfirstlane(TAIL ? xcd_block() : xcd_block() * kForceWaves + wid);
+  if (g >= ngroups) return;
+  m2p_group<P, T, TAIL>(g, C, G, L, eps2, spos, n, list, out);
+}
+
+template <typename T, typename T4>
+static hipError_t p2p_launch_t(const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                               T eps2, const double* spos, const T4* srec, size_t n,
+                               const uint32_t* list, double4* out, hipStream_t s,
+                               const SideStream& side) {
+  const unsigned nb = (ngroups + kForceWaves - 1) / kForceWaves;
+  hipStream_t st;
+  hipError_t e = side_fork(side, s, &st);
+  if (e != hipSuccess) return e;
+  k_p2p<T, T4, true><<<nb, 64 * kForceWaves, 0, st>>>(C, G, ngroups, L, eps2, spos, srec, n,
+                                                      list, out);
+  k_p2p<T, T4, false><<<nb, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps2, spos, srec, n,
+                                                       list, out);
+  e = hipGetLastError();
+  return e != hipSuccess ? e : side_join(side, s);
+}
+
 hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
                       double eps, const double* spos, const void* srec, size_t n,
-                      const uint32_t* list, double4* out, hipStream_t s) {
+                      const uint32_t* list, double4* out, hipStream_t s, const SideStream& side) {
   if (ngroups == 0) return hipSuccess;
-  unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
-  if (fp32) {
-    const float e2 = (float)(eps * eps);
-    k_p2p<float, float4, false><<<blocks, 64 * kForceWaves, 0, s>>>(
-        C, G, ngroups, L, e2, spos, (const float4*)srec, n, list, out);
-    k_p2p<float, float4, true><<<blocks, 64 * kForceWaves, 0, s>>>(
-        C, G, ngroups, L, e2, spos, (const float4*)srec, n, list, out);
-  } else {
-    k_p2p<double, double4, false><<<blocks, 64 * kForceWaves, 0, s>>>(
-        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n, list, out);
-    k_p2p<double, double4, true><<<blocks, 64 * kForceWaves, 0, s>>>(
-        C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n, list, out);
-  }
-  return hipGetLastError();
+  if (fp32)
+    return p2p_launch_t<float, float4>(C, G, ngroups, L, (float)(eps * eps), spos,
+                                       (const float4*)srec, n, list, out, s, side);
+  return p2p_launch_t<double, double4>(C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n,
+                                       list, out, s, side);
+}
+
+template <int P, typename T>
+static hipError_t m2p_launch_t(const Cells& C, const Groups& G, uint32_t ngroups, double L,
+                               T eps2, const double* spos, size_t n, const uint4* list,
+                               double4* out, hipStream_t s, const SideStream& side) {
+  const unsigned nb = (ngroups + kForceWaves - 1) / kForceWaves;
+  hipStream_t st;
+  hipError_t e = side_fork(side, s, &st);
+  if (e != hipSuccess) return e;
+  k_m2p<P, T, true><<<ngroups, 64 * kForceWaves, 0, st>>>(C, G, ngroups, L, eps2, spos, n, list,
+                                                           out);
+  k_m2p<P, T, false><<<nb, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps2, spos, n, list, out);
+  e = hipGetLastError();
+  return e != hipSuccess ? e : side_join(side, s);
 }
 
 template <int P>
-static void m2p_launch_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
-                         double eps, const double* spos, size_t n, const uint4* list,
-                         double4* out, hipStream_t s) {
-  unsigned blocks = (ngroups + kForceWaves - 1) / kForceWaves;
-  if (fp32) {
-    k_m2p<P, float, false><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, (float)(eps * eps),
-                                                               spos, n, list, out);
-    k_m2p<P, float, true><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, (float)(eps * eps),
-                                                              spos, n, list, out);
-  } else {
-    k_m2p<P, double, false><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps * eps, spos,
-                                                                n, list, out);
-    k_m2p<P, double, true><<<blocks, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps * eps, spos,
-                                                               n, list, out);
-  }
+static hipError_t m2p_launch_p(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups,
+                               double L, double eps, const double* spos, size_t n,
+                               const uint4* list, double4* out, hipStream_t s,
+                               const SideStream& side) {
+  if (fp32)
+    return m2p_launch_t<P, float>(C, G, ngroups, L, (float)(eps * eps), spos, n, list, out, s,
+                                  side);
+  return m2p_launch_t<P, double>(C, G, ngroups, L, eps * eps, spos, n, list, out, s, side);
 }
 
 hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                       double L, double eps, const double* spos, size_t n, const uint4* list,
-                      double4* out, hipStream_t s) {
+                      double4* out, hipStream_t s, const SideStream& side) {
   if (ngroups == 0) return hipSuccess;
   switch (order) {
-    case 0: m2p_launch_p<0>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
-    case 1: m2p_launch_p<1>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
-    case 2: m2p_launch_p<2>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
-    case 3: m2p_launch_p<3>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
-    case 4: m2p_launch_p<4>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s); break;
+    case 0: return m2p_launch_p<0>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s, side);
+    case 1: return m2p_launch_p<1>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s, side);
+    case 2: return m2p_launch_p<2>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s, side);
+    case 3: return m2p_launch_p<3>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s, side);
+    case 4: return m2p_launch_p<4>(fp32, C, G, ngroups, L, eps, spos, n, list, out, s, side);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace hot

@@ -45,10 +45,10 @@ hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const 
                        unsigned long long* out, hipStream_t s);
 hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
                       double eps, const double* spos, const void* srec, size_t n,
-                      const uint32_t* list, double4* out, hipStream_t s);
+                      const uint32_t* list, double4* out, hipStream_t s, const SideStream& side);
 hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                       double L, double eps, const double* spos, size_t n, const uint4* list,
-                      double4* out, hipStream_t s);
+                      double4* out, hipStream_t s, const SideStream& side);
 hipError_t far_launch(int far_order, const double* spos, const double* smass,
                       const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx, double box, double G, const double* tpsi,
                       double* part, int nblk_max, double* mroot, double* lam, int periodic,
@@ -64,11 +64,12 @@ hipError_t adj_moments_level(bool fp32, int order, const Cells& C, const double*
                              void* ecoef, hipStream_t s);
 hipError_t p2p_adj_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
                           double eps, const double* spos, const void* srec, const void* arec,
-                          size_t n, const uint32_t* list, double4* out, hipStream_t s);
+                          size_t n, const uint32_t* list, double4* out, hipStream_t s,
+                          const SideStream& side);
 hipError_t m2p_adj_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                           double L, double eps, const double* spos, const void* srec,
                           const void* arec, const void* ecoef, size_t n, const uint4* list,
-                          double4* out, hipStream_t s);
+                          double4* out, hipStream_t s, const SideStream& side);
 hipError_t far_adj_launch(int far_order, const double* spos, const double* smass,
                           const uint64_t* skey, const void* arec, const double4* near, size_t n,
                           const uint32_t* idx, double box, double G, const double* tpsi,
@@ -479,18 +480,20 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
               "pair count");
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
     if (!vjp) {
-      HOT_CHECK(p2p_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list, near, s),
+      HOT_CHECK(p2p_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list, near, s,
+                           c->side),
                 "direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
-      HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, n, m2p_list, near, s),
+      HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, n, m2p_list, near, s,
+                           c->side),
                 "multipole kernel");
     } else {
       HOT_CHECK(p2p_adj_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, arec, n, p2p_list, adj,
-                               s),
+                               s, c->side),
                 "adjoint direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
       HOT_CHECK(m2p_adj_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, srec, arec, ecoef, n,
-                               m2p_list, adj, s),
+                               m2p_list, adj, s, c->side),
                 "adjoint multipole kernel");
     }
   }
@@ -601,6 +604,14 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   c->events_ok = 1;
   for (int i = 0; i < 8; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = 0;
+  if (hipStreamCreateWithFlags(&c->side.st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->side.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->side.join, hipEventDisableTiming) != hipSuccess) {
+    if (c->side.st) (void)hipStreamDestroy(c->side.st);
+    if (c->side.fork) (void)hipEventDestroy(c->side.fork);
+    c->side = hot::SideStream{};
+    (void)hipGetLastError();
+  }
   *out = c;
   return HOT_OK;
 }
@@ -611,6 +622,9 @@ void hot_destroy(hot_ctx* c) {
   if (c->host_buf) (void)hipHostFree(c->host_buf);
   for (int i = 0; i < 8; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->side.st) (void)hipStreamDestroy(c->side.st);
+  if (c->side.fork) (void)hipEventDestroy(c->side.fork);
+  if (c->side.join) (void)hipEventDestroy(c->side.join);
   delete c;
 }
 

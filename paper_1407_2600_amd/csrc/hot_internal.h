@@ -112,12 +112,12 @@ constexpr int kP2PFlops = 20;
 // neighbouring groups, which share most of their interaction lists, then
 // read the same cells through the same L2.  A bijection on [0, gridDim.x).
 constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_block() {
-  const uint32_t b = blockIdx.x, nb = gridDim.x;
+__device__ __forceinline__ uint32_t xcd_index(uint32_t b, uint32_t nb) {
   const uint32_t x = b % kXcds, i = b / kXcds;
   const uint32_t q = nb / kXcds, r = nb % kXcds;
   return x * q + (x < r ? x : r) + i;
 }
+__device__ __forceinline__ uint32_t xcd_block() { return xcd_index(blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Device data of one force evaluation (pointers into the caller's workspace).
@@ -170,6 +170,36 @@ struct Plan {
 }  // namespace hot
 
 // the context (opaque to callers)
+namespace hot {
+// A second stream of the context on which the force kernels' tail passes run
+// beside their main passes (forked from and joined back to the caller's
+// stream with two events).  Absent (null stream) if it could not be created;
+// then the passes run one after the other on the caller's stream.
+struct SideStream {
+  hipStream_t st;
+  hipEvent_t fork, join;
+};
+
+// the stream the tail pass goes on: the side stream, after it has waited for
+// the work already queued on s (or s itself without a side stream)
+inline hipError_t side_fork(const SideStream& side, hipStream_t s, hipStream_t* out) {
+  *out = s;
+  if (!side.st) return hipSuccess;
+  hipError_t e = hipEventRecord(side.fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(side.st, side.fork, 0);
+  if (e == hipSuccess) *out = side.st;
+  return e;
+}
+
+// s waits for the tail pass queued on the side stream
+inline hipError_t side_join(const SideStream& side, hipStream_t s) {
+  if (!side.st) return hipSuccess;
+  hipError_t e = hipEventRecord(side.join, side.st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, side.join, 0);
+  return e;
+}
+}  // namespace hot
+
 struct hot_ctx {
   hot_params p;
   int device;
@@ -193,6 +223,7 @@ struct hot_ctx {
   int last_chunks;     // list chunks of the last evaluation
   hipEvent_t ev[8];
   int events_ok;
+  hot::SideStream side;
 };
 
 namespace hot {

@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     op = G.off_p2p[g];
     om = G.off_m2p[g];
   }
-  __builtin_amdgcn_wave_barrier();
+  wave_sync();
   while (top > 0) {
     uint32_t room = (STACK - top) / 7;
     uint32_t k = top < 64 ? top : 64;
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     top -= k;
     const bool active = (uint32_t)lane < k;
     const uint32_t e = active ? st[top + lane] : 0u;
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     const int img = (int)(e >> 27);
     const int B = (int)(e & kCellMask);
     // 0 none, 1 open, 2 multipole, 3 direct
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     const uint32_t pre = inc - cnt;
     for (uint32_t q = 0; q < cnt; ++q) st[top + pre + q] = ((uint32_t)img << 27) | (uint32_t)(ch0 + q);
     top += tot;
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
   }
   if (!EMIT && lane == 0) {
     G.cnt_p2p[g] = np;
