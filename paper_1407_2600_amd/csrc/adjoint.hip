@@ -121,15 +121,7 @@ __global__ void __launch_bounds__(128) k_adj_moments(Cells C, const double* __re
   // prefix add
 #pragma unroll
   for (int k = 0; k < NQ; ++k) A[k] += Qm[k];
-  constexpr int NCF = coef_count(Q, true);
-  constexpr int STR = coef_stride(Q, true);
-  double cf[NCF];
-  coef_from_moments<Q, true>(A, cf);
-  T* out = ecoef + (size_t)c * STR;
-#pragma unroll
-  for (int k = 0; k < NCF; ++k) out[k] = (T)cf[k];
-#pragma unroll
-  for (int k = NCF; k < STR; ++k) out[k] = (T)0;
+  coef_store<Q, true, T>(A, ecoef + (size_t)c * coef_stride(Q, true));
 }
 
 // ---------------------------------------------------------------- direct

@@ -512,6 +512,37 @@ struct CoefTable {
   }
 };
 
+// first table term of output k (terms are in output order)
+template <int P, bool DIP>
+__host__ __device__ constexpr int coef_term_start(int k) {
+  constexpr CoefTable<P, DIP> t{};
+  int n = 0;
+  while (n < t.N && t.o[n] < k) ++n;
+  return n;
+}
+
+// the coefficient block of moments M, each coefficient stored to out as soon
+// as it is summed (same terms and order as coef_from_moments), then the
+// padding
+template <int P, bool DIP, typename T>
+__device__ __forceinline__ void coef_store(const double* __restrict__ M, T* __restrict__ out) {
+  constexpr CoefTable<P, DIP> tab{};
+  constexpr int NCF = coef_count(P, DIP);
+  constexpr int STR = coef_stride(P, DIP);
+  static_for<NCF>([&](auto K) {
+    constexpr int k = K;
+    constexpr int a = coef_term_start<P, DIP>(k), b = coef_term_start<P, DIP>(k + 1);
+    double v = 0.0;
+    static_for<b - a>([&](auto I) {
+      constexpr int t = a + I;
+      v += tab.w[t] * M[tab.m[t]];
+    });
+    out[k] = (T)v;
+  });
+#pragma unroll
+  for (int k = NCF; k < STR; ++k) out[k] = (T)0;
+}
+
 template <int P, bool DIP = false>
 __device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
   constexpr CoefTable<P, DIP> T{};

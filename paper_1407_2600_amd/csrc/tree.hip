@@ -281,15 +281,7 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
   double* Mo = C.mom + (size_t)c * NM;
 #pragma unroll
   for (int k = 0; k < NM; ++k) Mo[k] = M[k];
-  constexpr int NCF = coef_count(P);
-  constexpr int STR = coef_stride(P);
-  double cf[NCF];
-  coef_from_moments<P>(M, cf);
-  T* out = (T*)C.coef + (size_t)c * STR;
-#pragma unroll
-  for (int k = 0; k < NCF; ++k) out[k] = (T)cf[k];
-#pragma unroll
-  for (int k = NCF; k < STR; ++k) out[k] = (T)0;
+  coef_store<P, false, T>(M, (T*)C.coef + (size_t)c * coef_stride(P));
 }
 
 // ------------------------------------------------------------------- groups
