@@ -209,6 +209,39 @@ __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (N > 0) static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// value and gradient of sum_q c_q h^q over |q| <= PF (multi-index order), by
+// nested Horner schemes in z, then y, then x, each carrying the partial
+// derivatives it needs; V = double or Dual<double>.  out = (grad, value).
+template <int PF, typename V>
+__device__ __forceinline__ void local_horner(const double* __restrict__ cq, V hx, V hy, V hz,
+                                             V out[4]) {
+  V X = V(0.0), Xx = V(0.0), Xy = V(0.0), Xz = V(0.0);
+  static_for<PF + 1>([&](auto AA) {
+    constexpr int a = PF - AA;
+    V Y = V(0.0), Yy = V(0.0), Yz = V(0.0);
+    static_for<PF - a + 1>([&](auto BB) {
+      constexpr int b = PF - a - BB;
+      V Z = V(cq[mi_index(a, b, PF - a - b)]), Zz = V(0.0);
+      static_for<PF - a - b>([&](auto CC) {
+        constexpr int c = PF - a - b - 1 - CC;
+        Zz = fma(Zz, hz, Z);
+        Z = fma(Z, hz, V(cq[mi_index(a, b, c)]));
+      });
+      Yy = fma(Yy, hy, Y);
+      Yz = fma(Yz, hy, Zz);
+      Y = fma(Y, hy, Z);
+    });
+    Xx = fma(Xx, hx, X);
+    Xy = fma(Xy, hx, Yy);
+    Xz = fma(Xz, hx, Yz);
+    X = fma(X, hx, Y);
+  });
+  out[0] = Xx;
+  out[1] = Xy;
+  out[2] = Xz;
+  out[3] = X;
+}
+
 // a coefficient block in memory
 template <typename C>
 struct PtrCoef {

@@ -176,39 +176,19 @@ __global__ void __launch_bounds__(256) k_far_apply(const double* __restrict__ sp
   double phi = v.w, gx = v.x, gy = v.y, gz = v.z;
   if (periodic) {
     constexpr int NQ = nt(PF);
-    constexpr MI<PF> mi{};
     const int o = (int)((skey[s] >> 60) & 7ull);
     double c[3];
     octant_center(o, L, c);
     const double h[3] = {spos[s] - c[0], spos[n + s] - c[1], spos[2 * n + s] - c[2]};
-    double px[PF + 1], py[PF + 1], pz[PF + 1];
-    px[0] = py[0] = pz[0] = 1.0;
-#pragma unroll
-    for (int e = 1; e <= PF; ++e) {
-      px[e] = px[e - 1] * h[0];
-      py[e] = py[e - 1] * h[1];
-      pz[e] = pz[e - 1] * h[2];
-    }
-    double P = 0.0, Gx = 0.0, Gy = 0.0, Gz = 0.0;
-    auto eval = [&](const double* __restrict__ lm) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int a = mi.a[q], b = mi.b[q], c3 = mi.c[q];
-        const double Lq = lm[q];
-        const double yz = py[b] * pz[c3];
-        P = fma(Lq, px[a] * yz, P);
-        if (a) Gx = fma(Lq * (double)a, px[a - 1] * yz, Gx);
-        if (b) Gy = fma(Lq * (double)b, px[a] * py[b - 1] * pz[c3], Gy);
-        if (c3) Gz = fma(Lq * (double)c3, px[a] * py[b] * pz[c3 - 1], Gz);
-      }
-    };
+    double r[4];
     // where the whole wavefront lies in one octant (all but at most 7
     // wavefronts) the coefficients are wave-uniform: scalar loads
     const int o0 = __builtin_amdgcn_readfirstlane(o);
     if (__all(o == o0))
-      eval(lam + (size_t)o0 * NQ);
+      local_horner<PF, double>(lam + (size_t)o0 * NQ, h[0], h[1], h[2], r);
     else
-      eval(lam + (size_t)o * NQ);
+      local_horner<PF, double>(lam + (size_t)o * NQ, h[0], h[1], h[2], r);
+    const double P = r[3], Gx = r[0], Gy = r[1], Gz = r[2];
     phi += P;
     gx += Gx;
     gy += Gy;

@@ -160,36 +160,6 @@ __global__ void __launch_bounds__(64) k_far_adj_moments(const double* __restrict
   if (lane == 0) mbar[(size_t)so * NQ + k] = (((ka + kb + kc) & 1) ? -1.0 : 1.0) * acc;
 }
 
-// value and gradient of sum_q c_q h^q (V = double or Dual<double>)
-template <int PF, typename V>
-__device__ __forceinline__ void local_eval(const double* __restrict__ cq, V hx, V hy, V hz,
-                                           V out[4]) {
-  constexpr MI<PF> mi{};
-  V px[PF + 1], py[PF + 1], pz[PF + 1];
-  px[0] = py[0] = pz[0] = V(1.0);
-#pragma unroll
-  for (int e = 1; e <= PF; ++e) {
-    px[e] = px[e - 1] * hx;
-    py[e] = py[e - 1] * hy;
-    pz[e] = pz[e - 1] * hz;
-  }
-  V P = V(0.0), Gx = V(0.0), Gy = V(0.0), Gz = V(0.0);
-#pragma unroll
-  for (int q = 0; q < nt(PF); ++q) {
-    const int a = mi.a[q], b = mi.b[q], c = mi.c[q];
-    const double Lq = cq[q];
-    const V yz = py[b] * pz[c];
-    P = fma(Lq, px[a] * yz, P);
-    if (a) Gx = fma(Lq * (double)a, px[a - 1] * yz, Gx);
-    if (b) Gy = fma(Lq * (double)b, px[a] * (py[b - 1] * pz[c]), Gy);
-    if (c) Gz = fma(Lq * (double)c, px[a] * (py[b] * pz[c - 1]), Gz);
-  }
-  out[0] = Gx;
-  out[1] = Gy;
-  out[2] = Gz;
-  out[3] = P;
-}
-
 template <int PF, typename T, typename T4>
 __global__ void __launch_bounds__(256) k_far_adj_apply(
     const double* __restrict__ spos, const double* __restrict__ smass,
@@ -219,13 +189,13 @@ __global__ void __launch_bounds__(256) k_far_adj_apply(
     double sm[4];
     const int o0 = __builtin_amdgcn_readfirstlane(o);
     if (__all(o == o0)) {
-      local_eval<PF, Dual<double>>(lam + (size_t)o0 * NQ, Dual<double>(h[0], ga[0]),
+      local_horner<PF, Dual<double>>(lam + (size_t)o0 * NQ, Dual<double>(h[0], ga[0]),
                                    Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
-      local_eval<PF, double>(mbar + (size_t)o0 * NQ, h[0], h[1], h[2], sm);
+      local_horner<PF, double>(mbar + (size_t)o0 * NQ, h[0], h[1], h[2], sm);
     } else {
-      local_eval<PF, Dual<double>>(lam + (size_t)o * NQ, Dual<double>(h[0], ga[0]),
+      local_horner<PF, Dual<double>>(lam + (size_t)o * NQ, Dual<double>(h[0], ga[0]),
                                    Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
-      local_eval<PF, double>(mbar + (size_t)o * NQ, h[0], h[1], h[2], sm);
+      local_horner<PF, double>(mbar + (size_t)o * NQ, h[0], h[1], h[2], sm);
     }
     for (int a = 0; a < 3; ++a) xb[a] += G * f[a].d - G * gp * f[a].v;
     const double m = smass[s];
