@@ -55,7 +55,23 @@ def parse():
                     help="skip the differentiation-workload timing")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain 256 MiB device copy (three times), the reference the HBM "
+                         "byte counters are scaled by")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of a known size: 256 MiB read and 256 MiB written
+    per copy, three copies."""
+    import torch
+    x = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": x.numel() * 4, "copies": 3}))
 
 
 # rms force error the operating point is defined at, and the parameter grids
@@ -94,11 +110,11 @@ WORKLOADS = {
 # counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
 # They hold only for the sources and the configuration they were taken with;
 # otherwise the roofline reports traffic as null.
-TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 2.678e+09,
+TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 2.662e+09,
            "config": {"theta": 0.8, "err_tol": 0.00488, "order": 4, "leaf_max": 16,
                       "group_max": 128, "far_order": 8},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
-           "sha256": "f3e1983c75e272955c444cf345a21e02ee2900d568266f99f032aa2a1adad8c8"}
+           "sha256": "47c86cea694c5f77b1a0ed6350360643f7abbe4f47c950dee281913dd4a76b36"}
 
 
 def measured_traffic(prm, workload):
@@ -164,6 +180,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.workload == "zeldovich1024":
         return paper_scale(args)
     import torch
