@@ -33,12 +33,18 @@
  *    hot_workspace_size(ctx, n)), aligned to 256
  *    bytes.  The library never allocates device memory in a compute call; it
  *    owns only the context (parameters, the Ewald table, a few device
- *    constants), created by hot_create and released by hot_destroy.
+ *    constants, and a second HIP stream with two events), created by
+ *    hot_create and released by hot_destroy.
  *  - Calls are enqueued on the caller's HIP stream (hipStream_t passed as
  *    void*; NULL = the default stream).  A compute call synchronises that
  *    stream a few times to size its launches (tree levels, list totals) and
  *    returns after the last kernel is enqueued; outputs are ready once the
- *    stream is synchronised.
+ *    stream is synchronised.  The force kernels' tail passes (the last <= 32
+ *    targets of a sink group) run on the context's second stream, which
+ *    waits for the caller's stream through an event before them, and the
+ *    caller's stream waits for them through another event before anything
+ *    that reads their results: all ordering stays on the device and follows
+ *    the caller's stream.
  *  - Errors are status codes; nothing throws across the ABI.  A message for
  *    the last failure on the calling thread is in hot_last_error().  Inputs
  *    are never modified, except the in/out arrays of hot_kdk.
@@ -153,7 +159,10 @@ typedef struct hot_ctx hot_ctx;
 
 /* Create a context.  Validates the parameters (HOT_EINVAL), builds the
  * far-field Ewald table on the host in FP64 and uploads it (HOT_EDEVICE on
- * a HIP failure).  Uses the current HIP device.  *out is NULL on failure. */
+ * a HIP failure), and creates the context's second stream (default
+ * priority) and its two events on the current HIP device; if those cannot
+ * be created the tail passes run on the caller's stream after the main
+ * passes instead.  *out is NULL on failure. */
 hot_status hot_create(const hot_params* params, hot_ctx** out);
 
 /* Release a context (NULL is allowed). */
