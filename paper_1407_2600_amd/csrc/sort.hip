@@ -10,7 +10,8 @@
 // Sort: least-significant-digit radix sort of (key, index) with 8-bit digits.
 // Each pass builds per-tile digit histograms in LDS, scans them digit-major
 // across tiles, and scatters with a stable in-tile rank computed from wave
-// ballots, so equal keys keep their original order.
+// ballots, so equal keys keep their original order; each tile is put in
+// digit order in LDS first and written out run by run.
 #include "hot_internal.h"
 
 namespace hot {
@@ -75,52 +76,85 @@ __global__ void __launch_bounds__(kT) k_hist(const uint64_t* __restrict__ key, s
   hist[(size_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one tile: stable tile-local ranks (wave ballots, per-wave digit
+// counts) place the tile's keys in LDS in digit order; the tile is then
+// written out in that order, so consecutive threads write consecutive
+// addresses of each digit's run in the output.
 __global__ void __launch_bounds__(kT) k_scatter(const uint64_t* __restrict__ kin,
                                                 const uint32_t* __restrict__ vin, size_t n,
                                                 int shift, const uint32_t* __restrict__ off,
                                                 int nblk, uint64_t* __restrict__ kout,
                                                 uint32_t* __restrict__ vout) {
-  __shared__ uint32_t base[kSortBins];
+  __shared__ uint32_t base[kSortBins];  // output offset of this tile's digit d
+  __shared__ uint32_t loff[kSortBins];  // tile-local offset of digit d, advanced per round
+  __shared__ uint32_t lbeg[kSortBins];  // tile-local offset of digit d
   __shared__ uint32_t wcnt[kT / 64][kSortBins];
+  __shared__ uint64_t sk[kSortTile];
+  __shared__ uint32_t sv[kSortTile];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  base[t] = off[(size_t)t * nblk + blockIdx.x];
+  const size_t beg = (size_t)blockIdx.x * kSortTile;
+  const uint32_t tn = (uint32_t)(n - beg < (size_t)kSortTile ? n - beg : (size_t)kSortTile);
+  // this tile's count of digit t: the next entry of the digit-major scanned
+  // histogram (the same digit's next tile, or the next digit's first tile)
+  const size_t e = (size_t)t * nblk + blockIdx.x;
+  const uint32_t o0 = off[e];
+  const uint32_t o1 = (e + 1 < (size_t)kSortBins * nblk) ? off[e + 1] : (uint32_t)n;
+  base[t] = o0;
+  // exclusive scan of the counts over the 256 digits (one per thread)
+  uint32_t c = o1 - o0;
+  wcnt[0][t] = c;
+  __syncthreads();
+  for (int d = 1; d < kSortBins; d <<= 1) {
+    const uint32_t u = t >= d ? wcnt[0][t - d] : 0u;
+    __syncthreads();
+    c += u;
+    wcnt[0][t] = c;
+    __syncthreads();
+  }
+  loff[t] = c - (o1 - o0);
+  lbeg[t] = c - (o1 - o0);
   for (int w = 0; w < kT / 64; ++w) wcnt[w][t] = 0;
   __syncthreads();
-  size_t beg = (size_t)blockIdx.x * kSortTile;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kRounds; ++r) {
-    size_t i = beg + (size_t)r * kT + t;
-    bool valid = i < n;
-    uint64_t k = valid ? kin[i] : 0ull;
-    uint32_t v = valid ? vin[i] : 0u;
-    uint32_t d = valid ? (uint32_t)((k >> shift) & (kSortBins - 1)) : 0u;
+    const uint32_t li = (uint32_t)(r * kT + t);
+    const bool valid = li < tn;
+    const uint64_t k = valid ? kin[beg + li] : 0ull;
+    const uint32_t v = valid ? vin[beg + li] : 0u;
+    const uint32_t d = valid ? (uint32_t)((k >> shift) & (kSortBins - 1)) : 0u;
     // lanes of this wave with the same digit
     uint64_t same = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kSortBits; ++b) {
-      uint64_t bb = __ballot((d >> b) & 1u);
+      const uint64_t bb = __ballot((d >> b) & 1u);
       same &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    uint32_t rank = (uint32_t)__popcll(same & below);
-    bool leader = valid && ((same & below) == 0ull);
+    const uint32_t rank = (uint32_t)__popcll(same & below);
+    const bool leader = valid && ((same & below) == 0ull);
     if (leader) wcnt[wid][d] = (uint32_t)__popcll(same);
     __syncthreads();
     if (valid) {
-      uint32_t pre = base[d];
+      uint32_t pre = loff[d];
       for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
-      size_t dst = pre + rank;
-      kout[dst] = k;
-      vout[dst] = v;
+      sk[pre + rank] = k;
+      sv[pre + rank] = v;
     }
     __syncthreads();
-    // advance the per-digit bases and clear the wave counts
+    // advance the per-digit tile offsets and clear the wave counts
     uint32_t add = 0;
     for (int w = 0; w < kT / 64; ++w) {
       add += wcnt[w][t];
       wcnt[w][t] = 0;
     }
-    base[t] += add;
+    loff[t] += add;
     __syncthreads();
+  }
+  for (uint32_t j = (uint32_t)t; j < tn; j += kT) {
+    const uint64_t k = sk[j];
+    const uint32_t d = (uint32_t)((k >> shift) & (kSortBins - 1));
+    const size_t dst = (size_t)base[d] + (j - lbeg[d]);
+    kout[dst] = k;
+    vout[dst] = sv[j];
   }
 }
 }  // namespace
