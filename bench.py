@@ -128,6 +128,30 @@ def measured_traffic(prm, workload):
     return TRAFFIC["bytes_per_launch"] if same else None
 
 
+# Algorithmic HBM bytes of the bandwidth-bound stages (FP32 mode): the keys,
+# sort and gather stage per particle (keys 36 B, 8 radix passes of 24 B,
+# gather 56 B), and the build stage per particle and per cell (tree levels
+# 12 B + 48 B/cell, moments and coefficient blocks 28 B + 600 B/cell, groups
+# and source records 60 B).
+SORT_BYTES_PER_PARTICLE = 36 + 8 * 24 + 56
+BUILD_BYTES_PER_PARTICLE = 12 + 28 + 60
+BUILD_BYTES_PER_CELL = 48 + 600
+
+
+def stage_bandwidth(n, ncells, kern):
+    """Achieved algorithmic GB/s of the sort and build stages against the
+    8 TB/s HBM peak (both are one-pass streaming stages, several launches
+    each, and at small sizes bound by launch latency rather than bytes)."""
+    sort_b = SORT_BYTES_PER_PARTICLE * n
+    build_b = BUILD_BYTES_PER_PARTICLE * n + BUILD_BYTES_PER_CELL * ncells
+    out = {"unit": "GB/s", "peak": 8000.0}
+    for name, b, ms in (("sort", sort_b, kern["ms_sort"]), ("build", build_b, kern["ms_build"])):
+        gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else None
+        out[name] = {"bytes": b, "ms": ms, "achieved": gbs,
+                     "frac": gbs / 8000.0 if gbs is not None else None}
+    return out
+
+
 def rms_err(a, ref):
     return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))
 
@@ -267,6 +291,7 @@ def main():
                                  "ms_total")}
         flops = {"p2p": 0.0, "m2p": 0.0}
         pairs = {"p2p": 0, "m2p": 0}
+        ncells = 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -274,6 +299,7 @@ def main():
             st = g.stats()  # stage times of this step's force evaluation (HIP events)
             for k in kern:
                 kern[k] += st[k]
+            ncells += st["ncells"]
             flops["p2p"] += st["flops_p2p"]
             flops["m2p"] += st["flops_m2p"]
             pairs["p2p"] += st["p2p_pairs"]
@@ -285,6 +311,7 @@ def main():
                          kern={k: v / steps for k, v in kern.items()},
                          flops={k: v / steps for k, v in flops.items()},
                          pairs={k: v / steps for k, v in pairs.items()},
+                         ncells=ncells / steps,
                          ms_force_median=float(np.median(f_ms)), adjoint=adj,
                          workspace_bytes=int(g.ws.numel()),
                          acc=a_first)
@@ -364,6 +391,7 @@ def main():
         "interactions_per_s": (r32["pairs"]["p2p"] + r32["pairs"]["m2p"]) /
                               (r32["ms_per_step"] * 1e-3),
         "stage_ms": r32["kern"],
+        "stage_bandwidth": stage_bandwidth(n, r32["ncells"], r32["kern"]),
         "stage_ms_fp64": res["fp64"]["kern"],
         "pairs_per_step": r32["pairs"],
         "roofline": roof,
@@ -491,6 +519,7 @@ def paper_scale(args):
                                    "targets": 10000},
         "per_force_eval": {"fp32_ms": 1e3 * dtf, "fp32_pps": n / dtf},
         "stage_ms": kern, "pairs_per_step": pairs,
+        "stage_bandwidth": stage_bandwidth(n, stf["ncells"], kern),
         "interactions_per_s": (pairs["p2p"] + pairs["m2p"]) / el,
         "list_chunks": stf["list_chunks"], "workspace_bytes": ws,
         "a_rms": a_rms,
