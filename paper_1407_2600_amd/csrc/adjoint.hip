@@ -350,6 +350,9 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
   __shared__ T tl_ef[kLdsTail ? kAdjWaves : 1][4][kLdsTail ? ESTR : 1];
   __shared__ T tl_c[kLdsTail ? kAdjWaves : 1][4][4];
   __shared__ int tl_b[kLdsTail ? kAdjWaves : 1][4];
+  // FP32 tail: one effective-charge block per sub-group
+  __shared__ __align__(16) T tl_ef32[TAIL && !kLdsTail ? kAdjWaves : 1][4]
+                                     [TAIL && !kLdsTail ? ESTR : 1];
   // tail pass: the block's wavefronts share out one group's list and add
   // their results through LDS in a fixed order
   __shared__ double tl_red[TAIL ? kAdjWaves : 1][TAIL ? 32 : 1][4];
@@ -405,12 +408,16 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
         }
       }
     } else if constexpr (sizeof(T) == 4) {
-      // FP32: each 16-lane row holds its sub-group's entry's two coefficient
-      // blocks spread over the row (row broadcasts feed them to its lanes),
-      // and loads the sub-group's next entry while this one is evaluated
+      // FP32: each 16-lane row holds its sub-group's entry's mass-expansion
+      // block spread over the row (row broadcasts feed it to its lanes); the
+      // entry's effective-charge block goes to the sub-group's LDS slot and
+      // is read from there.  The sub-group's next entry is loaded while this
+      // one is evaluated.
       constexpr int NC = (STR + 15) / 16, NE = (ESTR + 15) / 16;
       const int rl = lane & 15;
       const uint32_t step = nw * split;
+      T* eslot = &tl_ef32[wid][sub][0];
+      const bool writer = (lane & (width - 1)) < 16;  // the sub-group's first row
       RowCoef<NC> cf;
       RowCoef<NE> ef;
       T c[3] = {0, 0, 0};
@@ -422,23 +429,27 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
       }
       uint32_t it = 0;
       while (q < cnt) {
+        if (writer)
+#pragma unroll
+          for (int j = 0; j < NE; ++j)
+            if (rl + 16 * j < ESTR) eslot[rl + 16 * j] = ef.r[j];
+        wave_sync();
         const uint32_t qn = q + step;
         RowCoef<NC> cf2;
-        RowCoef<NE> ef2;
         T c2[3] = {0, 0, 0};
         if (qn < cnt) {
           const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
           cf2.load(coef + (size_t)B * STR, STR, rl);
-          ef2.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+          ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
         }
-        term(tx - c[0], ty - c[1], tz - c[2], cf, ef);
+        term(tx - c[0], ty - c[1], tz - c[2], cf, (const T*)eslot);
         if ((++it & 15) == 0) {
           acc.fold(part);
 #pragma unroll
           for (int k = 0; k < 4; ++k) part[k] = (T)0;
         }
+        wave_sync();
         cf = cf2;
-        ef = ef2;
         c[0] = c2[0];
         c[1] = c2[1];
         c[2] = c2[2];
