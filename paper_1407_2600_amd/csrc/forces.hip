@@ -231,6 +231,9 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
   __shared__ T tail_cf[kLdsTail ? kForceWaves : 1][4][kLdsTail ? STR : 1];
   __shared__ T tail_c[kLdsTail ? kForceWaves : 1][4][4];
   __shared__ int tail_b[kLdsTail ? kForceWaves : 1][4];
+  // FP32 tail: one coefficient block per sub-group
+  __shared__ __align__(16) T tail_cf32[TAIL && !kLdsTail ? kForceWaves : 1][4]
+                                      [TAIL && !kLdsTail ? STR : 1];
   // tail pass: the block's wavefronts share out one group's list and add
   // their results through LDS in a fixed order
   __shared__ double tail_red[TAIL ? kForceWaves : 1][TAIL ? 32 : 1][4];
@@ -279,12 +282,15 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
         }
       }
     } else if constexpr (sizeof(T) == 4) {
-      // FP32: each 16-lane row holds its sub-group's entry's coefficient
-      // block spread over the row (row broadcasts feed it to its lanes), and
-      // loads the sub-group's next entry while this one is evaluated
+      // FP32: each 16-lane row loads its sub-group's entry's coefficient
+      // block spread over the row; the sub-group's first row puts it in the
+      // sub-group's LDS slot, from which every lane reads it.  The next
+      // entry is loaded while this one is evaluated.
       constexpr int NC = (STR + 15) / 16;
       const int rl = lane & 15;
       const uint32_t step = nw * split;
+      T* cslot = &tail_cf32[wid][sub][0];
+      const bool writer = (lane & (width - 1)) < 16;
       RowCoef<NC> cf;
       T c[3] = {0, 0, 0};
       uint32_t q = w0 * split + (uint32_t)sub;
@@ -294,15 +300,19 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
       }
       uint32_t it = 0;
       while (q < cnt) {
+        if (writer)
+#pragma unroll
+          for (int j = 0; j < NC; ++j)
+            if (rl + 16 * j < STR) cslot[rl + 16 * j] = cf.r[j];
+        wave_sync();
         const uint32_t qn = q + step;
-        RowCoef<NC> cf2;
         T c2[3] = {0, 0, 0};
         if (qn < cnt) {
           const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
-          cf2.load(coef + (size_t)B * STR, STR, rl);
+          cf.load(coef + (size_t)B * STR, STR, rl);
         }
         T r[4];
-        m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, cf, r);
+        m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, (const T*)cslot, r);
 #pragma unroll
         for (int k = 0; k < 3; ++k) part[k] += r[k];
         acc.fold1(3, r[3]);
@@ -311,7 +321,7 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
 #pragma unroll
           for (int k = 0; k < 3; ++k) part[k] = (T)0;
         }
-        cf = cf2;
+        wave_sync();
         c[0] = c2[0];
         c[1] = c2[1];
         c[2] = c2[2];
