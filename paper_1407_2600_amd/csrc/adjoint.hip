@@ -345,14 +345,12 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
                                               double4* __restrict__ out){
   constexpr int STR = coef_stride(P);
   constexpr int ESTR = coef_stride(P + 1, true);
-  constexpr bool kLdsTail = TAIL && sizeof(T) == 8;
-  __shared__ T tl_cf[kLdsTail ? kAdjWaves : 1][4][kLdsTail ? STR : 1];
-  __shared__ T tl_ef[kLdsTail ? kAdjWaves : 1][4][kLdsTail ? ESTR : 1];
-  __shared__ T tl_c[kLdsTail ? kAdjWaves : 1][4][4];
-  __shared__ int tl_b[kLdsTail ? kAdjWaves : 1][4];
-  // FP32 tail: one effective-charge block per sub-group
-  __shared__ __align__(16) T tl_ef32[TAIL && !kLdsTail ? kAdjWaves : 1][4]
-                                     [TAIL && !kLdsTail ? ESTR : 1];
+  // tail pass: per sub-group of each wavefront, the entry's blocks in LDS
+  // (FP32: the effective-charge block; FP64: both)
+  constexpr bool k64 = TAIL && sizeof(T) == 8, k32 = TAIL && sizeof(T) == 4;
+  __shared__ __align__(16) T tl_cf64[k64 ? kAdjWaves : 1][4][k64 ? STR : 1];
+  __shared__ __align__(16) T tl_ef64[k64 ? kAdjWaves : 1][4][k64 ? ESTR : 1];
+  __shared__ __align__(16) T tl_ef32[k32 ? kAdjWaves : 1][4][k32 ? ESTR : 1];
   // tail pass: the block's wavefronts share out one group's list and add
   // their results through LDS in a fixed order
   __shared__ double tl_red[TAIL ? kAdjWaves : 1][TAIL ? 32 : 1][4];
@@ -456,35 +454,49 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
         q = qn;
       }
     } else {
-      T* cbuf = &tl_cf[wid][0][0];
-      T* ebuf = &tl_ef[wid][0][0];
+      // FP64: both blocks through the sub-group's LDS slots (as the FP32
+      // effective-charge block), the next entry loaded while this one is
+      // evaluated
+      constexpr int NC = (STR + 15) / 16, NE = (ESTR + 15) / 16;
+      const int rl = lane & 15;
+      const uint32_t step = nw * split;
+      T* cslot = &tl_cf64[wid][sub][0];
+      T* eslot = &tl_ef64[wid][sub][0];
+      const bool writer = (lane & (width - 1)) < 16;
+      RowBlock<T, NC> cf;
+      RowBlock<T, NE> ef;
+      T c[3] = {0, 0, 0};
+      uint32_t q = w0 * split + sub;
+      if (q < cnt) {
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        cf.load(coef + (size_t)B * STR, STR, rl);
+        ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+      }
       uint32_t it = 0;
-      for (uint32_t q0 = w0 * split; q0 < cnt; q0 += nw * split) {
-        const uint32_t ne = cnt - q0 < split ? cnt - q0 : split;
-        if ((uint32_t)lane < ne) {
-          T c[3];
-          const int B = m2p_record<T>(list[off + q0 + lane], C.walk, L, cA, c);
-          tl_c[wid][lane][0] = c[0];
-          tl_c[wid][lane][1] = c[1];
-          tl_c[wid][lane][2] = c[2];
-          tl_b[wid][lane] = B;
+      while (q < cnt) {
+        if (writer) {
+          cf.store(cslot, STR, rl);
+          ef.store(eslot, ESTR, rl);
         }
         wave_sync();
-        for (uint32_t i = (uint32_t)lane; i < ne * STR; i += 64)
-          cbuf[i] = coef[(size_t)tl_b[wid][i / STR] * STR + i % STR];
-        for (uint32_t i = (uint32_t)lane; i < ne * ESTR; i += 64)
-          ebuf[i] = ecoef[(size_t)tl_b[wid][i / ESTR] * ESTR + i % ESTR];
-        wave_sync();
-        if (sub < ne) {
-          term(tx - tl_c[wid][sub][0], ty - tl_c[wid][sub][1], tz - tl_c[wid][sub][2],
-               cbuf + (size_t)sub * STR, ebuf + (size_t)sub * ESTR);
-          if ((++it & 15) == 0) {
-            acc.fold(part);
+        const uint32_t qn = q + step;
+        T c2[3] = {0, 0, 0};
+        if (qn < cnt) {
+          const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
+          cf.load(coef + (size_t)B * STR, STR, rl);
+          ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+        }
+        term(tx - c[0], ty - c[1], tz - c[2], (const T*)cslot, (const T*)eslot);
+        if ((++it & 15) == 0) {
+          acc.fold(part);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) part[k] = (T)0;
-          }
+          for (int k = 0; k < 4; ++k) part[k] = (T)0;
         }
         wave_sync();
+        c[0] = c2[0];
+        c[1] = c2[1];
+        c[2] = c2[2];
+        q = qn;
       }
     }
     acc.fold(part);

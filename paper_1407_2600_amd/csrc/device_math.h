@@ -271,6 +271,22 @@ struct RowCoef {
   }
 };
 
+// A coefficient block read by one 16-lane row into registers (lane l of the
+// row holds values l, l + 16, ...), on its way to an LDS slot.
+template <typename T, int NR>
+struct RowBlock {
+  T r[NR];
+  __device__ __forceinline__ void load(const T* __restrict__ p, int n, int rl) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) r[j] = rl + 16 * j < n ? p[rl + 16 * j] : (T)0;
+  }
+  __device__ __forceinline__ void store(T* __restrict__ slot, int n, int rl) const {
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+      if (rl + 16 * j < n) slot[rl + 16 * j] = r[j];
+  }
+};
+
 // a coefficient source from a pointer (or a RowCoef as it is)
 template <typename C>
 __device__ __forceinline__ PtrCoef<C> as_src(const C* p) {

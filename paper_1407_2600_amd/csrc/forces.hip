@@ -226,14 +226,8 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
                                           const uint4* __restrict__ list,
                                           double4* __restrict__ out){
   constexpr int STR = coef_stride(P);
-  // tail-pass staging: per wave, up to 4 entries' offsets, cells and blocks
-  constexpr bool kLdsTail = TAIL && sizeof(T) == 8;
-  __shared__ T tail_cf[kLdsTail ? kForceWaves : 1][4][kLdsTail ? STR : 1];
-  __shared__ T tail_c[kLdsTail ? kForceWaves : 1][4][4];
-  __shared__ int tail_b[kLdsTail ? kForceWaves : 1][4];
-  // FP32 tail: one coefficient block per sub-group
-  __shared__ __align__(16) T tail_cf32[TAIL && !kLdsTail ? kForceWaves : 1][4]
-                                      [TAIL && !kLdsTail ? STR : 1];
+  // tail pass: one coefficient block per sub-group of each wavefront
+  __shared__ __align__(16) T tail_cf[TAIL ? kForceWaves : 1][4][TAIL ? STR : 1];
   // tail pass: the block's wavefronts share out one group's list and add
   // their results through LDS in a fixed order
   __shared__ double tail_red[TAIL ? kForceWaves : 1][TAIL ? 32 : 1][4];
@@ -281,17 +275,17 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
           for (int k = 0; k < 3; ++k) part[k] = (T)0;
         }
       }
-    } else if constexpr (sizeof(T) == 4) {
-      // FP32: each 16-lane row loads its sub-group's entry's coefficient
-      // block spread over the row; the sub-group's first row puts it in the
+    } else {
+      // each 16-lane row loads its sub-group's entry's coefficient block
+      // spread over the row; the sub-group's first row puts it in the
       // sub-group's LDS slot, from which every lane reads it.  The next
       // entry is loaded while this one is evaluated.
       constexpr int NC = (STR + 15) / 16;
       const int rl = lane & 15;
       const uint32_t step = nw * split;
-      T* cslot = &tail_cf32[wid][sub][0];
+      T* cslot = &tail_cf[wid][sub][0];
       const bool writer = (lane & (width - 1)) < 16;
-      RowCoef<NC> cf;
+      RowBlock<T, NC> cf;
       T c[3] = {0, 0, 0};
       uint32_t q = w0 * split + (uint32_t)sub;
       if (q < cnt) {
@@ -300,10 +294,7 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
       }
       uint32_t it = 0;
       while (q < cnt) {
-        if (writer)
-#pragma unroll
-          for (int j = 0; j < NC; ++j)
-            if (rl + 16 * j < STR) cslot[rl + 16 * j] = cf.r[j];
+        if (writer) cf.store(cslot, STR, rl);
         wave_sync();
         const uint32_t qn = q + step;
         T c2[3] = {0, 0, 0};
@@ -326,43 +317,6 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
         c[1] = c2[1];
         c[2] = c2[2];
         q = qn;
-      }
-    } else {
-      // FP64: each round stages the next `split` entries' offsets and
-      // coefficient blocks in this wave's LDS slots with coalesced loads;
-      // every sub-group then reads its own block (a broadcast within it)
-      T* cbuf = &tail_cf[wid][0][0];
-      uint32_t it = 0;
-      for (uint32_t q0 = w0 * split; q0 < cnt; q0 += nw * split) {
-        const uint32_t ne = cnt - q0 < (uint32_t)split ? cnt - q0 : (uint32_t)split;
-        if ((uint32_t)lane < ne) {
-          T c[3];
-          const int B = m2p_record<T>(list[off + q0 + lane], C.walk, L, cA, c);
-          tail_c[wid][lane][0] = c[0];
-          tail_c[wid][lane][1] = c[1];
-          tail_c[wid][lane][2] = c[2];
-          tail_b[wid][lane] = B;
-        }
-        wave_sync();
-        for (uint32_t i = (uint32_t)lane; i < ne * STR; i += 64) {
-          const uint32_t e = i / STR, k = i % STR;
-          cbuf[i] = coef[(size_t)tail_b[wid][e] * STR + k];
-        }
-        wave_sync();
-        if (sub < ne) {
-          T r[4];
-          m2p_eval<P, false, T, T>(tx - tail_c[wid][sub][0], ty - tail_c[wid][sub][1],
-                                   tz - tail_c[wid][sub][2], eps2, cbuf + (size_t)sub * STR, r);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) part[k] += r[k];
-          acc.fold1(3, r[3]);
-          if ((++it & 15) == 0) {
-            acc.fold(part);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) part[k] = (T)0;
-          }
-        }
-        wave_sync();
       }
     }
     acc.fold(part);
