@@ -571,8 +571,7 @@ __host__ __device__ constexpr int coef_term_start(int k) {
 }
 
 // the coefficient block of moments M, each coefficient stored to out as soon
-// as it is summed (same terms and order as coef_from_moments), then the
-// padding
+// as it is summed (the table's terms in order, from zero), then the padding
 template <int P, bool DIP, typename T>
 __device__ __forceinline__ void coef_store(const double* __restrict__ M, T* __restrict__ out) {
   constexpr CoefTable<P, DIP> tab{};
@@ -592,15 +591,6 @@ __device__ __forceinline__ void coef_store(const double* __restrict__ M, T* __re
   for (int k = NCF; k < STR; ++k) out[k] = (T)0;
 }
 
-template <int P, bool DIP = false>
-__device__ __forceinline__ void coef_from_moments(const double* __restrict__ M, double* out) {
-  constexpr CoefTable<P, DIP> T{};
-  constexpr int NCF = coef_count(P, DIP);
-#pragma unroll
-  for (int k = 0; k < NCF; ++k) out[k] = 0.0;
-#pragma unroll
-  for (int t = 0; t < T.N; ++t) out[T.o[t]] += T.w[t] * M[T.m[t]];
-}
 
 // Shift of raw moments to a centre displaced by -d (moments M_c about a
 // daughter's centre, d = daughter centre - new centre):

@@ -24,7 +24,7 @@ hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, 
                             uint32_t* scan_tmp, hipStream_t s);
 hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
                            int level, int leaf_max, const uint32_t* choff, uint32_t next,
-                           hipStream_t s);
+                           uint32_t cap, hipStream_t s);
 hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
                               uint32_t beg, uint32_t cnt, double L, double theta, double G,
                               double err_tol, int order,
@@ -337,6 +337,11 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     HOT_CHECK(tree_split_level(C, key0, lvl[l], cnt, l, p.leaf_max, tmp, ctr + CTR_TOTAL,
                                scan_tmp, s),
               "tree split");
+    // the emit pass goes ahead of the read-back (it writes nothing beyond the
+    // cell capacity; an overflow fails the call below)
+    HOT_CHECK(tree_emit_level(C, key0, lvl[l], cnt, l, p.leaf_max, tmp, lvl[l + 1],
+                              (uint32_t)std::min(P.cap_cells, (size_t)UINT32_MAX), s),
+              "tree emit");
     HOT_CHECK(readback(s, ctr, host, 2), "readback");
     if (l == 0 && host[CTR_BAD]) {
       g_err = (host[CTR_BAD] & 1u) ? "positions must be finite and inside (-L, 2L)"
@@ -352,8 +357,6 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
       g_err = "cell capacity exceeded; call hot_workspace_size again and retry";
       return HOT_EOVERFLOW;
     }
-    HOT_CHECK(tree_emit_level(C, key0, lvl[l], cnt, l, p.leaf_max, tmp, lvl[l + 1], s),
-              "tree emit");
     lvl[l + 2] = lvl[l + 1] + tot;
     nlev = l + 2;
   }

@@ -205,7 +205,6 @@ struct hot_ctx {
   int device;
   double S;            // 2^21 / L (key quantisation)
   double* d_tpsi;      // 27 Ewald tables (octant-centre offsets), nt(2 far_order) each
-  double* d_binom;     // binomial table (kMaxFarOrder*2+1)^2, device
   int n_tpsi;
   // learned capacities (grow after an overflow)
   double cells_per_particle;

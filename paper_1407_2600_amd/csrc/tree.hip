@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
                                                     uint32_t beg, uint32_t cnt, int level,
                                                     int leaf_max,
                                                     const uint32_t* __restrict__ choff,
-                                                    uint32_t next) {
+                                                    uint32_t next, uint32_t cap) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   uint32_t c = beg + t;
@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
     uint32_t e = (o == 7) ? end : digit_lower_bound(skey, b, end, shift, o + 1);
     if (e > b) {
       uint32_t d = out + k;
+      if (d >= cap) break;  // over capacity: the host sees the total and fails the call
       C.key[d] = (pk << 3) | o;
       C.level[d] = level + 1;
       C.first[d] = b;
@@ -372,9 +373,9 @@ hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, 
 
 hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
                            int level, int leaf_max, const uint32_t* choff, uint32_t next,
-                           hipStream_t s) {
+                           uint32_t cap, hipStream_t s) {
   unsigned g = (cnt + 255) / 256;
-  k_split_emit<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, choff, next);
+  k_split_emit<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, choff, next, cap);
   return hipGetLastError();
 }
 
