@@ -271,19 +271,19 @@ struct RowCoef {
   }
 };
 
-// A coefficient block read by one 16-lane row into registers (lane l of the
-// row holds values l, l + 16, ...), on its way to an LDS slot.
+// A coefficient block read by w lanes into registers (lane l of them holds
+// values l, l + w, ...; w = 16 unless given), on its way to an LDS slot.
 template <typename T, int NR>
 struct RowBlock {
   T r[NR];
-  __device__ __forceinline__ void load(const T* __restrict__ p, int n, int rl) {
+  __device__ __forceinline__ void load(const T* __restrict__ p, int n, int rl, int w = 16) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) r[j] = rl + 16 * j < n ? p[rl + 16 * j] : (T)0;
+    for (int j = 0; j < NR; ++j) r[j] = rl + w * j < n ? p[rl + w * j] : (T)0;
   }
-  __device__ __forceinline__ void store(T* __restrict__ slot, int n, int rl) const {
+  __device__ __forceinline__ void store(T* __restrict__ slot, int n, int rl, int w = 16) const {
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-      if (rl + 16 * j < n) slot[rl + 16 * j] = r[j];
+      if (rl + w * j < n) slot[rl + w * j] = r[j];
   }
 };
 

@@ -31,7 +31,7 @@ constexpr int kForceWaves = 4;
 // targets read each staged source with a broadcast LDS load.
 // TAIL selects the passes as in k_m2p: the main launch takes the passes over
 // more than 32 targets; the tail launch takes a last pass of at most 32
-// targets and splits the wave into 2 or 4 sub-groups that share out the
+// targets and splits the wave into 2, 4 or 8 sub-groups that share out the
 // staged sources, adding their partial sums at the end.  Partial sums over
 // one leaf image (at most 64 of its sources) are folded into the
 // accumulators.  This kernel writes (not adds) the accumulators.
@@ -109,7 +109,7 @@ __device__ __forceinline__ void p2p_group(uint32_t g, SourceStage<T, T4, kForceW
   for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
     const uint32_t rem = count - t0;
     if (!TAIL && rem <= 32) break;
-    const uint32_t split = !TAIL ? 1u : rem <= 16 ? 4u : 2u;  // wave-uniform
+    const uint32_t split = !TAIL ? 1u : rem <= 8 ? 8u : rem <= 16 ? 4u : 2u;  // wave-uniform
     const int width = 64 / (int)split;
     const uint32_t sub = (uint32_t)(lane / width);
     const int tl = lane % width;
@@ -213,11 +213,12 @@ __device__ __forceinline__ void p2p_group(uint32_t g, SourceStage<T, T4, kForceW
 // targets, each walking the list once with every entry wave-uniform (scalar
 // loads of the record and the cell's coefficients).  TAIL = true: the last
 // pass when it has at most 32 targets (the remainder of a group of 65..96,
-// or a small group); the wave splits into 2 or 4 sub-groups of 32 or 16 lanes
-// that take every 2nd or 4th list entry, and the partial sums are added
-// across the sub-groups at the end, so the lanes a short pass would leave
-// idle do the work.  Separate launches keep the register budget
-// (and occupancy) of the main pass independent of the tail's.
+// or a small group), one group per block: the block's 4 wavefronts each
+// split into 2, 4 or 8 sub-groups of 32, 16 or 8 lanes, the sub-groups take
+// every 8th, 16th or 32nd list entry, and the partial sums are added across
+// sub-groups and wavefronts at the end, so the lanes a short pass would leave
+// idle do the work.  Separate launches keep the register budget (and
+// occupancy) of the main pass independent of the tail's.
 template <int P, typename T, bool TAIL>
 __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
                                           double L, T eps2,
@@ -227,7 +228,7 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
                                           double4* __restrict__ out){
   constexpr int STR = coef_stride(P);
   // tail pass: one coefficient block per sub-group of each wavefront
-  __shared__ __align__(16) T tail_cf[TAIL ? kForceWaves : 1][4][TAIL ? STR : 1];
+  __shared__ __align__(16) T tail_cf[TAIL ? kForceWaves : 1][8][TAIL ? STR : 1];
   // tail pass: the block's wavefronts share out one group's list and add
   // their results through LDS in a fixed order
   __shared__ double tail_red[TAIL ? kForceWaves : 1][TAIL ? 32 : 1][4];
@@ -246,7 +247,7 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
   for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
     const uint32_t rem = count - t0;
     if (!TAIL && rem <= 32) break;
-    const int split = !TAIL ? 1 : rem <= 16 ? 4 : 2;  // wave-uniform
+    const int split = !TAIL ? 1 : rem <= 8 ? 8 : rem <= 16 ? 4 : 2;  // wave-uniform
     const int width = 64 / split;
     const int sub = lane / width, tl = lane % width;
     const uint32_t s = first + t0 + tl;
@@ -280,27 +281,28 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
       // spread over the row; the sub-group's first row puts it in the
       // sub-group's LDS slot, from which every lane reads it.  The next
       // entry is loaded while this one is evaluated.
-      constexpr int NC = (STR + 15) / 16;
-      const int rl = lane & 15;
+      constexpr int NC = (STR + 7) / 8;  // values per loading lane (8 or 16 of them)
+      const int wl = width < 16 ? width : 16;  // the sub-group's loading lanes
+      const int rl = lane & (wl - 1);
       const uint32_t step = nw * split;
       T* cslot = &tail_cf[wid][sub][0];
-      const bool writer = (lane & (width - 1)) < 16;
+      const bool writer = (lane & (width - 1)) < wl;
       RowBlock<T, NC> cf;
       T c[3] = {0, 0, 0};
       uint32_t q = w0 * split + (uint32_t)sub;
       if (q < cnt) {
         const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-        cf.load(coef + (size_t)B * STR, STR, rl);
+        cf.load(coef + (size_t)B * STR, STR, rl, wl);
       }
       uint32_t it = 0;
       while (q < cnt) {
-        if (writer) cf.store(cslot, STR, rl);
+        if (writer) cf.store(cslot, STR, rl, wl);
         wave_sync();
         const uint32_t qn = q + step;
         T c2[3] = {0, 0, 0};
         if (qn < cnt) {
           const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
-          cf.load(coef + (size_t)B * STR, STR, rl);
+          cf.load(coef + (size_t)B * STR, STR, rl, wl);
         }
         T r[4];
         m2p_eval<P, false, T, T>(tx - c[0], ty - c[1], tz - c[2], eps2, (const T*)cslot, r);
