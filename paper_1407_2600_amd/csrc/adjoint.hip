@@ -188,7 +188,7 @@ __device__ __forceinline__ void p2p_adj_staged(const T4* __restrict__ st,
 
 // TAIL selects the passes as in the forward direct kernel: the main launch
 // takes the passes over more than 32 targets, the tail launch a last pass of
-// at most 32 targets with the wave split into 2 or 4 sub-groups that share
+// at most 32 targets with the wave split into 2, 4 or 8 sub-groups that share
 // out the staged sources.
 template <typename T, typename T4, bool TAIL>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, uint32_t ngroups,
