@@ -188,7 +188,7 @@ __device__ __forceinline__ void p2p_adj_staged(const T4* __restrict__ st,
 
 // TAIL selects the passes as in the forward direct kernel: the main launch
 // takes the passes over more than 32 targets, the tail launch a last pass of
-// at most 32 targets with the wave split into 2, 4 or 8 sub-groups that share
+// at most 32 targets with the wave split into 2 or 4 sub-groups that share
 // out the staged sources.
 template <typename T, typename T4, bool TAIL>
 __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, uint32_t ngroups,
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_p2p_adj(Cells C, Groups G, u
   for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
     const uint32_t rem = count - t0;
     if (!TAIL && rem <= 32) break;
-    const uint32_t split = !TAIL ? 1u : rem <= 8 ? 8u : rem <= 16 ? 4u : 2u;  // wave-uniform
+    const uint32_t split = !TAIL ? 1u : rem <= 16 ? 4u : 2u;  // wave-uniform
     const int width = 64 / (int)split;
     const uint32_t sub = (uint32_t)(lane / width);
     const int tl = lane % width;
@@ -348,9 +348,9 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
   // tail pass: per sub-group of each wavefront, the entry's blocks in LDS
   // (FP32: the effective-charge block; FP64: both)
   constexpr bool k64 = TAIL && sizeof(T) == 8, k32 = TAIL && sizeof(T) == 4;
-  constexpr bool kt = k64 || k32;
-  __shared__ __align__(16) T tl_cf[kt ? kAdjWaves : 1][kt ? 8 : 1][kt ? STR : 1];
-  __shared__ __align__(16) T tl_ef[kt ? kAdjWaves : 1][kt ? 8 : 1][kt ? ESTR : 1];
+  __shared__ __align__(16) T tl_cf64[k64 ? kAdjWaves : 1][4][k64 ? STR : 1];
+  __shared__ __align__(16) T tl_ef64[k64 ? kAdjWaves : 1][4][k64 ? ESTR : 1];
+  __shared__ __align__(16) T tl_ef32[k32 ? kAdjWaves : 1][4][k32 ? ESTR : 1];
   // tail pass: the block's wavefronts share out one group's list and add
   // their results through LDS in a fixed order
   __shared__ double tl_red[TAIL ? kAdjWaves : 1][TAIL ? 32 : 1][4];
@@ -369,7 +369,7 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
   for (uint32_t t0 = TAIL ? tail0 : 0; t0 < count; t0 += 64) {
     const uint32_t rem = count - t0;
     if (!TAIL && rem <= 32) break;
-    const uint32_t split = !TAIL ? 1u : rem <= 8 ? 8u : rem <= 16 ? 4u : 2u;  // wave-uniform
+    const uint32_t split = !TAIL ? 1u : rem <= 16 ? 4u : 2u;  // wave-uniform
     const int width = 64 / (int)split;
     const uint32_t sub = (uint32_t)(lane / width);
     const int tl = lane % width;
@@ -405,109 +405,98 @@ __device__ __forceinline__ void m2p_adj_group(uint32_t g, Cells C, Groups G,
           for (int k = 0; k < 4; ++k) part[k] = (T)0;
         }
       }
-    } else {
-      // both blocks through the sub-group's LDS slots: each block is loaded by
-      // the sub-group's first 16 lanes (all 8 of an 8-lane sub-group), put in
-      // the slots and read from there; the next entry is loaded while this
-      // one is evaluated
-      auto lds_both = [&]() {
-        constexpr int NC = (STR + 7) / 8, NE = (ESTR + 7) / 8;
-        const int wl = width < 16 ? width : 16;
-        const int rl = lane & (wl - 1);
-        const uint32_t step = nw * split;
-        T* cslot = &tl_cf[wid][sub][0];
-        T* eslot = &tl_ef[wid][sub][0];
-        const bool writer = (lane & (width - 1)) < wl;
-        RowBlock<T, NC> cf;
-        RowBlock<T, NE> ef;
-        T c[3] = {0, 0, 0};
-        uint32_t q = w0 * split + sub;
-        if (q < cnt) {
-          const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-          cf.load(coef + (size_t)B * STR, STR, rl, wl);
-          ef.load(ecoef + (size_t)B * ESTR, ESTR, rl, wl);
-        }
-        uint32_t it = 0;
-        while (q < cnt) {
-          if (writer) {
-            cf.store(cslot, STR, rl, wl);
-            ef.store(eslot, ESTR, rl, wl);
-          }
-          wave_sync();
-          const uint32_t qn = q + step;
-          T c2[3] = {0, 0, 0};
-          if (qn < cnt) {
-            const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
-            cf.load(coef + (size_t)B * STR, STR, rl, wl);
-            ef.load(ecoef + (size_t)B * ESTR, ESTR, rl, wl);
-          }
-          term(tx - c[0], ty - c[1], tz - c[2], (const T*)cslot, (const T*)eslot);
-          if ((++it & 15) == 0) {
-            acc.fold(part);
+    } else if constexpr (sizeof(T) == 4) {
+      // FP32: each 16-lane row holds its sub-group's entry's mass-expansion
+      // block spread over the row (row broadcasts feed it to its lanes); the
+      // entry's effective-charge block goes to the sub-group's LDS slot and
+      // is read from there.  The sub-group's next entry is loaded while this
+      // one is evaluated.
+      constexpr int NC = (STR + 15) / 16, NE = (ESTR + 15) / 16;
+      const int rl = lane & 15;
+      const uint32_t step = nw * split;
+      T* eslot = &tl_ef32[wid][sub][0];
+      const bool writer = (lane & (width - 1)) < 16;  // the sub-group's first row
+      RowCoef<NC> cf;
+      RowCoef<NE> ef;
+      T c[3] = {0, 0, 0};
+      uint32_t q = w0 * split + sub;
+      if (q < cnt) {
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        cf.load(coef + (size_t)B * STR, STR, rl);
+        ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+      }
+      uint32_t it = 0;
+      while (q < cnt) {
+        if (writer)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) part[k] = (T)0;
-          }
-          wave_sync();
-          c[0] = c2[0];
-          c[1] = c2[1];
-          c[2] = c2[2];
-          q = qn;
+          for (int j = 0; j < NE; ++j)
+            if (rl + 16 * j < ESTR) eslot[rl + 16 * j] = ef.r[j];
+        wave_sync();
+        const uint32_t qn = q + step;
+        RowCoef<NC> cf2;
+        T c2[3] = {0, 0, 0};
+        if (qn < cnt) {
+          const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
+          cf2.load(coef + (size_t)B * STR, STR, rl);
+          ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
         }
-      };
-      if constexpr (sizeof(T) == 4) {
-        if (split == 8) {
-          lds_both();
-        } else {
-            // FP32: each 16-lane row holds its sub-group's entry's mass-expansion
-            // block spread over the row (row broadcasts feed it to its lanes); the
-            // entry's effective-charge block goes to the sub-group's LDS slot and
-            // is read from there.  The sub-group's next entry is loaded while this
-            // one is evaluated.
-            constexpr int NC = (STR + 15) / 16, NE = (ESTR + 15) / 16;
-            const int rl = lane & 15;
-            const uint32_t step = nw * split;
-            T* eslot = &tl_ef[wid][sub][0];
-            const bool writer = (lane & (width - 1)) < 16;  // the sub-group's first row
-            RowCoef<NC> cf;
-            RowCoef<NE> ef;
-            T c[3] = {0, 0, 0};
-            uint32_t q = w0 * split + sub;
-            if (q < cnt) {
-              const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
-              cf.load(coef + (size_t)B * STR, STR, rl);
-              ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
-            }
-            uint32_t it = 0;
-            while (q < cnt) {
-              if (writer)
-      #pragma unroll
-                for (int j = 0; j < NE; ++j)
-                  if (rl + 16 * j < ESTR) eslot[rl + 16 * j] = ef.r[j];
-              wave_sync();
-              const uint32_t qn = q + step;
-              RowCoef<NC> cf2;
-              T c2[3] = {0, 0, 0};
-              if (qn < cnt) {
-                const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
-                cf2.load(coef + (size_t)B * STR, STR, rl);
-                ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
-              }
-              term(tx - c[0], ty - c[1], tz - c[2], cf, (const T*)eslot);
-              if ((++it & 15) == 0) {
-                acc.fold(part);
-      #pragma unroll
-                for (int k = 0; k < 4; ++k) part[k] = (T)0;
-              }
-              wave_sync();
-              cf = cf2;
-              c[0] = c2[0];
-              c[1] = c2[1];
-              c[2] = c2[2];
-              q = qn;
-            }
+        term(tx - c[0], ty - c[1], tz - c[2], cf, (const T*)eslot);
+        if ((++it & 15) == 0) {
+          acc.fold(part);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) part[k] = (T)0;
         }
-      } else {
-        lds_both();
+        wave_sync();
+        cf = cf2;
+        c[0] = c2[0];
+        c[1] = c2[1];
+        c[2] = c2[2];
+        q = qn;
+      }
+    } else {
+      // FP64: both blocks through the sub-group's LDS slots (as the FP32
+      // effective-charge block), the next entry loaded while this one is
+      // evaluated
+      constexpr int NC = (STR + 15) / 16, NE = (ESTR + 15) / 16;
+      const int rl = lane & 15;
+      const uint32_t step = nw * split;
+      T* cslot = &tl_cf64[wid][sub][0];
+      T* eslot = &tl_ef64[wid][sub][0];
+      const bool writer = (lane & (width - 1)) < 16;
+      RowBlock<T, NC> cf;
+      RowBlock<T, NE> ef;
+      T c[3] = {0, 0, 0};
+      uint32_t q = w0 * split + sub;
+      if (q < cnt) {
+        const int B = m2p_record<T>(list[off + q], C.walk, L, cA, c);
+        cf.load(coef + (size_t)B * STR, STR, rl);
+        ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+      }
+      uint32_t it = 0;
+      while (q < cnt) {
+        if (writer) {
+          cf.store(cslot, STR, rl);
+          ef.store(eslot, ESTR, rl);
+        }
+        wave_sync();
+        const uint32_t qn = q + step;
+        T c2[3] = {0, 0, 0};
+        if (qn < cnt) {
+          const int B = m2p_record<T>(list[off + qn], C.walk, L, cA, c2);
+          cf.load(coef + (size_t)B * STR, STR, rl);
+          ef.load(ecoef + (size_t)B * ESTR, ESTR, rl);
+        }
+        term(tx - c[0], ty - c[1], tz - c[2], (const T*)cslot, (const T*)eslot);
+        if ((++it & 15) == 0) {
+          acc.fold(part);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) part[k] = (T)0;
+        }
+        wave_sync();
+        c[0] = c2[0];
+        c[1] = c2[1];
+        c[2] = c2[2];
+        q = qn;
       }
     }
     acc.fold(part);
