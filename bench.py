@@ -43,8 +43,10 @@ def parse():
     ap.add_argument("--err-tol", type=float, default=None,
                     help="fixed error-bound tolerance (skips the search)")
     ap.add_argument("--far-order", type=int, default=None)
-    ap.add_argument("--group-max", type=int, default=128)
-    ap.add_argument("--leaf-max", type=int, default=16)
+    ap.add_argument("--group-max", type=int, default=None,
+                    help="sink-group size (default: the workload's, 128 or 256)")
+    ap.add_argument("--leaf-max", type=int, default=None,
+                    help="source-leaf size (default: the workload's, 16 or 32)")
     ap.add_argument("--n-side", type=int, default=None, help="smaller grid (debug only)")
     ap.add_argument("--workload", default="zeldovich128",
                     choices=sorted(WORKLOADS) + ["zeldovich1024"],
@@ -81,7 +83,7 @@ ERR_TARGET = 1e-3
 # error-bound tolerances as fractions of the reference's rms acceleration
 # (the paper states its tolerance relative to the rms acceleration)
 ETA_GRID = {"zeldovich128": (0.04, 0.06, 0.08, 0.09, 0.10, 0.11, 0.12),
-            "nfw256": (0.12, 0.2, 0.3, 0.5, 0.8, 1.2)}
+            "nfw256": (0.12, 0.2, 0.3, 0.5, 0.8, 1.2, 1.6, 2.4)}
 THETA_CAPS = (0.0, 0.6, 0.7, 0.8)
 # error-bound tolerances tried for the 1024^3 run, as fractions of its rms
 # acceleration, in order until the error estimate is at most ERR_TARGET
@@ -91,15 +93,18 @@ ETA_PAPER_SCALE = (0.08, 0.07, 0.06, 0.05)
 # processed in chunks of groups that fit it)
 PAPER_SCALE_LIST_BYTES = 16 << 30
 
-# per workload: the oracle reference and the opening angles searched
+# per workload: the oracle reference, the opening angles searched and the leaf
+# and group sizes (the clustered set runs faster, at lower error, with larger
+# ones: its sparse background otherwise splits into many small groups)
 WORKLOADS = {
     "zeldovich128": dict(
         ref="zeldovich128_ref.npz", thetas=(0.40, 0.44, 0.46, 0.47, 0.48, 0.50),
+        leaf_max=16, group_max=128,
         data="synthetic (seeded Zel'dovich field standing in for the paper's 2LPT ICs)",
         desc="zeldovich {s}^3={n} particles, periodic unit box, P(k)~k^-1.5, rms displacement "
              "0.5 spacing"),
     "nfw256": dict(
-        ref="nfw256_ref.npz", thetas=(0.3, 0.5, 0.7),
+        ref="nfw256_ref.npz", thetas=(0.3, 0.5, 0.7), leaf_max=32, group_max=256,
         data="synthetic (seeded NFW halos, dN/dM~M^-1.9, c=8, plus uniform background, standing "
              "in for the paper's clustered late-time particle distributions)",
         desc="clustered {s}^3={n} particles: 70% in NFW halos of 1e2..1e5 particles, 30% "
@@ -110,7 +115,7 @@ WORKLOADS = {
 # counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
 # They hold only for the sources and the configuration they were taken with;
 # otherwise the roofline reports traffic as null.
-TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 2.652e+09,
+TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 2.653e+09,
            "config": {"theta": 0.8, "err_tol": 0.00488, "order": 4, "leaf_max": 16,
                       "group_max": 128, "far_order": 8},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
@@ -215,7 +220,8 @@ def main():
 
     W = WORKLOADS[args.workload]
     pos_np, mass_np, prm = workloads.make(args.workload, n_side=args.n_side)
-    prm = dict(prm, group_max=args.group_max, leaf_max=args.leaf_max)
+    prm = dict(prm, group_max=args.group_max or W["group_max"],
+               leaf_max=args.leaf_max or W["leaf_max"])
     if args.far_order is not None:
         prm["far_order"] = args.far_order
     n = pos_np.shape[1]

@@ -181,10 +181,11 @@ def test_deterministic_repeat():
         np.testing.assert_array_equal(r1["pot"], r2["pot"])
 
 
-# the benchmark's launch configuration (error-bound test at the 1e-3
+# the benchmark's launch configurations (error-bound test at the 1e-3
 # operating point) at the workloads' full sizes
 FULL = [("zeldovich128", True), ("nfw256", False)]
-BENCH_PRM = dict(theta=0.8, err_tol=5e-3, group_max=128, leaf_max=16)
+BENCH_PRM = {"zeldovich128": dict(theta=0.8, err_tol=5e-3, group_max=128, leaf_max=16),
+             "nfw256": dict(theta=0.0, err_tol=103.0, group_max=256, leaf_max=32)}
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -195,7 +196,7 @@ def test_full_size(name, lists, precision):
     fits in host memory) and forces on sampled sink groups against the
     oracle."""
     pos, mass, prm = workloads.make(name)
-    prm = dict(prm, **BENCH_PRM)
+    prm = dict(prm, **BENCH_PRM[name])
     print(f"full size {name} {precision}: building oracle tree", flush=True)
     mo = oracle_mass(mass, precision)
     T = oracle.Tree(pos, mo, prm)
