@@ -1,0 +1,54 @@
+"""Host logic of bench.py that needs no GPU: the one-GPU refusal, the
+per-workload launch defaults, and the guard that reports the HBM traffic of
+the dominant kernel only for the sources and configuration it was measured
+with."""
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_workload_defaults():
+    b = _bench()
+    for name, w in b.WORKLOADS.items():
+        assert 1 <= w["leaf_max"] <= 255 and w["leaf_max"] <= w["group_max"] <= 4096
+        assert name in b.ETA_GRID and len(b.ETA_GRID[name]) > 0
+        assert os.path.exists(os.path.join(ROOT, "tests", "golden", w["ref"]))
+    # the headline workload's defaults are the configuration its counters were taken at
+    cfg = b.TRAFFIC["config"]
+    w = b.WORKLOADS[b.TRAFFIC["workload"]]
+    assert (w["leaf_max"], w["group_max"]) == (cfg["leaf_max"], cfg["group_max"])
+
+
+def test_traffic_reported_only_for_its_configuration():
+    b = _bench()
+    prm = dict(b.TRAFFIC["config"], box=1.0, G=1.0, periodic=1)
+    wl = b.TRAFFIC["workload"]
+    assert b.measured_traffic(prm, wl) == b.TRAFFIC["bytes_per_launch"]
+    assert b.measured_traffic(dict(prm, group_max=prm["group_max"] * 2), wl) is None
+    assert b.measured_traffic(dict(prm, err_tol=prm["err_tol"] * 1.5), wl) is None
+    assert b.measured_traffic(prm, "nfw256") is None
+    saved = b.TRAFFIC["sha256"]
+    try:
+        b.TRAFFIC["sha256"] = "0" * 64  # sources changed since the counter runs
+        assert b.measured_traffic(prm, wl) is None
+    finally:
+        b.TRAFFIC["sha256"] = saved
