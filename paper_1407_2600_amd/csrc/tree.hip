@@ -60,25 +60,49 @@ __device__ __forceinline__ uint32_t digit_lower_bound(const uint64_t* __restrict
   return lo;
 }
 
+// Eight lanes per cell, lane o finding where octant o starts in the cell's
+// sorted range (the eight searches run side by side instead of one after the
+// other, which shortens the dependent-load chain of the few large cells at
+// the top levels); octant o ends where octant o + 1 starts, read from the
+// next lane.  The eight lanes of a cell are consecutive lanes of one wave.
+struct OctantSplit {
+  uint32_t c, lo, e;
+  bool split, nonempty;
+  uint32_t mask;  // non-empty octants of the cell (bit o)
+};
+
+__device__ __forceinline__ OctantSplit octant_split(const Cells& C,
+                                                    const uint64_t* __restrict__ skey,
+                                                    uint64_t ci, uint32_t o, uint32_t beg,
+                                                    uint32_t cnt, int level, int leaf_max) {
+  OctantSplit r{0, 0, 0, false, false, 0};
+  if (ci < cnt) {
+    r.c = beg + (uint32_t)ci;
+    const uint32_t first = C.first[r.c], count = C.count[r.c];
+    r.split = (int)count > leaf_max && level < kMaxLevel;
+    if (r.split) {
+      const int shift = 3 * (kMaxLevel - level - 1);
+      r.e = first + count;
+      r.lo = o == 0 ? first : digit_lower_bound(skey, first, r.e, shift, o);
+    }
+  }
+  // every lane takes part in the exchange and the vote
+  const uint32_t next = __shfl_down(r.lo, 1, 8);
+  if (o < 7) r.e = next;
+  r.nonempty = r.split && r.e > r.lo;
+  const unsigned long long votes = __ballot(r.nonempty);
+  r.mask = (uint32_t)((votes >> (__lane_id() & ~7u)) & 0xffull);
+  return r;
+}
+
 __global__ void __launch_bounds__(256) k_split_count(Cells C, const uint64_t* __restrict__ skey,
                                                      uint32_t beg, uint32_t cnt, int level,
                                                      int leaf_max, uint32_t* __restrict__ nch) {
-  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  uint32_t c = beg + t;
-  uint32_t first = C.first[c], count = C.count[c];
-  uint32_t k = 0;
-  if ((int)count > leaf_max && level < kMaxLevel) {
-    int shift = 3 * (kMaxLevel - level - 1);
-    uint32_t end = first + count;
-    uint32_t b = first;
-    for (uint32_t o = 0; o < 8; ++o) {
-      uint32_t e = (o == 7) ? end : digit_lower_bound(skey, b, end, shift, o + 1);
-      if (e > b) ++k;
-      b = e;
-    }
-  }
-  nch[t] = k;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t ci = t >> 3;
+  const uint32_t o = (uint32_t)(t & 7);
+  const OctantSplit r = octant_split(C, skey, ci, o, beg, cnt, level, leaf_max);
+  if (ci < cnt && o == 0) nch[ci] = (uint32_t)__popc(r.mask);
 }
 
 __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __restrict__ skey,
@@ -86,39 +110,36 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
                                                     int leaf_max,
                                                     const uint32_t* __restrict__ choff,
                                                     uint32_t next, uint32_t cap) {
-  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  uint32_t c = beg + t;
-  uint32_t first = C.first[c], count = C.count[c];
-  if (!((int)count > leaf_max && level < kMaxLevel)) {
-    C.child[c] = -1;
-    C.nchild[c] = 0;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t ci = t >> 3;
+  const uint32_t o = (uint32_t)(t & 7);
+  const OctantSplit r = octant_split(C, skey, ci, o, beg, cnt, level, leaf_max);
+  if (ci >= cnt) return;
+  const uint32_t c = r.c;
+  if (!r.split) {
+    if (o == 0) {
+      C.child[c] = -1;
+      C.nchild[c] = 0;
+    }
     return;
   }
-  int shift = 3 * (kMaxLevel - level - 1);
-  uint32_t end = first + count;
-  uint32_t b = first;
-  uint32_t out = next + choff[t];
-  uint32_t k = 0;
-  uint64_t pk = C.key[c];
-  for (uint32_t o = 0; o < 8; ++o) {
-    uint32_t e = (o == 7) ? end : digit_lower_bound(skey, b, end, shift, o + 1);
-    if (e > b) {
-      uint32_t d = out + k;
-      if (d >= cap) break;  // over capacity: the host sees the total and fails the call
-      C.key[d] = (pk << 3) | o;
+  const uint32_t out = next + choff[ci];
+  if (r.nonempty) {
+    const uint32_t d = out + (uint32_t)__popc(r.mask & ((1u << o) - 1u));
+    if (d < cap) {  // over capacity: the host sees the total and fails the call
+      C.key[d] = (C.key[c] << 3) | o;
       C.level[d] = level + 1;
-      C.first[d] = b;
-      C.count[d] = e - b;
+      C.first[d] = r.lo;
+      C.count[d] = r.e - r.lo;
       C.child[d] = -1;
       C.nchild[d] = 0;
       C.parent[d] = (int32_t)c;
-      ++k;
     }
-    b = e;
   }
-  C.child[c] = (int32_t)out;
-  C.nchild[c] = (int32_t)k;
+  if (o == 0) {
+    C.child[c] = (int32_t)out;
+    C.nchild[c] = (int32_t)__popc(r.mask);
+  }
 }
 
 // ------------------------------------------------------------------ moments
@@ -366,7 +387,7 @@ hipError_t tree_root(const Cells& C, uint32_t n, hipStream_t s) {
 hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
                             int level, int leaf_max, uint32_t* nch, uint32_t* total,
                             uint32_t* scan_tmp, hipStream_t s) {
-  unsigned g = (cnt + 255) / 256;
+  const unsigned g = (unsigned)((8 * (size_t)cnt + 255) / 256);  // eight lanes per cell
   k_split_count<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, nch);
   return scan_u32(nch, nch, total, cnt, scan_tmp, s);
 }
@@ -374,7 +395,7 @@ hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, 
 hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
                            int level, int leaf_max, const uint32_t* choff, uint32_t next,
                            uint32_t cap, hipStream_t s) {
-  unsigned g = (cnt + 255) / 256;
+  const unsigned g = (unsigned)((8 * (size_t)cnt + 255) / 256);  // eight lanes per cell
   k_split_emit<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, choff, next, cap);
   return hipGetLastError();
 }
