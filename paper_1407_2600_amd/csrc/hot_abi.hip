@@ -286,9 +286,11 @@ struct VjpArgs {
 
 // need: the optional workspace regions of the calling entry point (the
 // layout must be the same for every evaluation within one call)
+// after_forces: an adjoint may use the tree and lists the workspace holds
+// from the context's last evaluation (hot_vjp_after_forces)
 static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
                               void* pot, void* ws, size_t ws_bytes, hipStream_t s, unsigned need,
-                              const VjpArgs* vjp = nullptr) {
+                              const VjpArgs* vjp = nullptr, bool after_forces = false) {
   const hot_params& p = c->p;
   const bool fp32 = p.precision == HOT_FP32;
   Plan P = make_plan(c, n, ws_bytes, need);
@@ -317,7 +319,36 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   Groups G = groups_of(ws, P);
   uint32_t* host = c->host_buf;
 
+  const hot_ctx::TreeRecord& R = c->tree;
+  const bool use_tree = after_forces && vjp && R.valid && R.pos == pos && R.mass == mass &&
+                        R.n == n && R.ws == ws && R.ws_bytes == ws_bytes && R.stream == s &&
+                        R.o_list == P.o_list && R.cap_cells == P.cap_cells &&
+                        R.words <= P.cap_list;
+  c->tree.valid = 0;  // this call writes the workspace; recorded again at the end
+  std::vector<uint32_t> lvl(kMaxLevel + 3, 0);
+  int nlev = 1;
+  uint32_t ncells = 0, ngroups = 0;
+  bool big = false;
+  size_t tp = 0, tm = 0;
+  struct Chunk {
+    uint32_t g0, g1;
+    size_t tp, tm;
+  };
+  std::vector<Chunk> chunks;
+
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[0], s), "event");
+  if (use_tree) {
+    // keys, order, cells, groups and lists as the recorded evaluation left them
+    std::copy(R.lvl, R.lvl + kMaxLevel + 3, lvl.begin());
+    nlev = R.nlev;
+    ncells = R.ncells;
+    ngroups = R.ngroups;
+    tp = R.tp;
+    tm = R.tm;
+    chunks.push_back({0, ngroups, tp, tm});
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[1], s), "event");
+    if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
+  } else {
   HOT_CHECK(zero_launch(ctr, 4 * CTR_N, s), "clear counters");
   HOT_CHECK(launch_keys(pos, n, p.box, c->S, key0, idx0, ctr + CTR_BAD, s), "keys");
   HOT_CHECK(radix_sort(key0, idx0, key1, idx1, n, at<uint32_t>(ws, P.o_hist), scan_tmp, s),
@@ -328,10 +359,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
 
   // ---- tree, level by level
   HOT_CHECK(tree_root(C, (uint32_t)n, s), "tree root");
-  std::vector<uint32_t> lvl(kMaxLevel + 3, 0);
   lvl[0] = 0;
   lvl[1] = 1;
-  int nlev = 1;
   for (int l = 0; l < kMaxLevel; ++l) {
     const uint32_t cnt = lvl[l + 1] - lvl[l];
     HOT_CHECK(tree_split_level(C, key0, lvl[l], cnt, l, p.leaf_max, tmp, ctr + CTR_TOTAL,
@@ -360,7 +389,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     lvl[l + 2] = lvl[l + 1] + tot;
     nlev = l + 2;
   }
-  const uint32_t ncells = lvl[nlev];
+  ncells = lvl[nlev];
   for (int l = nlev - 1; l >= 0; --l)
     HOT_CHECK(tree_moments_level(C, spos, smass, n, lvl[l], lvl[l + 1] - lvl[l], p.box, p.theta,
                                  p.G, p.err_tol, p.order, fp32, s),
@@ -373,7 +402,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
             "groups");
   HOT_CHECK(tree_srec(C, ncells, spos, smass, n, p.box, srec, fp32, s), "source records");
   HOT_CHECK(readback(s, ctr, host, 8), "readback");
-  const uint32_t ngroups = host[CTR_NGROUPS];
+  ngroups = host[CTR_NGROUPS];
   if (ngroups > P.cap_groups) {
     g_err = "internal: group capacity exceeded";
     return HOT_EDEVICE;
@@ -383,7 +412,6 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
 
   // ---- walk: count pass over all groups (again with the larger stack if
   // some group's pending cells overflowed the default one)
-  bool big = false;
   for (;;) {
     HOT_CHECK(walk_launch(false, big, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic,
                           nullptr, nullptr, ctr + CTR_STATUS, s),
@@ -404,7 +432,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   }
   unsigned long long sums[2];
   std::memcpy(sums, host + CTR_SUMS, sizeof(sums));
-  const size_t tp = sums[0], tm = sums[1];
+  tp = sums[0];
+  tm = sums[1];
   const size_t maxw = host[CTR_MAXW];
   // list words: direct entries 1, multipole records 4, plus 16-byte alignment
   const size_t words = tp + 4 * tm + 4;
@@ -415,11 +444,6 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     return HOT_EOVERFLOW;
   }
   // chunks of consecutive groups whose lists fit the list region together
-  struct Chunk {
-    uint32_t g0, g1;
-    size_t tp, tm;
-  };
-  std::vector<Chunk> chunks;
   // a chunk's list offsets are 32-bit words (direct) and records (multipole)
   const size_t cap = std::min(P.cap_list, (size_t)UINT32_MAX - 64);
   if (words <= cap) {
@@ -443,6 +467,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     }
     chunks.push_back(ch);
   }
+  }  // !use_tree
 
   void* arec = nullptr;
   double4* adj = nullptr;
@@ -473,14 +498,16 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     Gk.off_p2p += k.g0;
     Gk.off_m2p += k.g0;
     uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
-    HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
-    HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
-    HOT_CHECK(walk_launch(true, big, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic,
-                          p2p_list, m2p_list, ctr + CTR_STATUS, s),
-              "walk emit");
-    HOT_CHECK(count_pairs(C, Gk, ng, p2p_list,
-                          reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
-              "pair count");
+    if (!use_tree) {
+      HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
+      HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
+      HOT_CHECK(walk_launch(true, big, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic,
+                            p2p_list, m2p_list, ctr + CTR_STATUS, s),
+                "walk emit");
+      HOT_CHECK(count_pairs(C, Gk, ng, p2p_list,
+                            reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
+                "pair count");
+    }
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
     if (!vjp) {
       HOT_CHECK(p2p_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list, near, s,
@@ -541,6 +568,25 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   c->last_ws = ws;
   c->last_ncells = ncells;
   c->last_ngroups = ngroups;
+  if (chunks.size() == 1) {
+    hot_ctx::TreeRecord& T = c->tree;
+    T.pos = pos;
+    T.mass = mass;
+    T.n = n;
+    T.ws = ws;
+    T.ws_bytes = ws_bytes;
+    T.stream = s;
+    T.words = tp + 4 * tm + 4;
+    T.o_list = P.o_list;
+    T.cap_cells = P.cap_cells;
+    std::copy(lvl.begin(), lvl.end(), T.lvl);
+    T.nlev = nlev;
+    T.ncells = ncells;
+    T.ngroups = ngroups;
+    T.tp = tp;
+    T.tm = tm;
+    T.valid = 1;
+  }
   return HOT_OK;
 }
 
@@ -736,6 +782,27 @@ hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, co
   VjpArgs a{gacc, gpot, xbar, mbar};
   return forces_impl(c, n, pos, mass, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream,
                      kNeedAdjoint, &a);
+}
+
+hot_status hot_vjp_after_forces(hot_ctx* c, size_t n, const double* pos, const void* mass,
+                                const void* gacc, const void* gpot, double* xbar, void* mbar,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !mass || !gacc || !xbar || !mbar || !ws) {
+    g_err = "NULL pointer argument";
+    return HOT_EINVAL;
+  }
+  if (n >= (size_t)0xffffffffu) {
+    g_err = "n must be < 2^32";
+    return HOT_EINVAL;
+  }
+  VjpArgs a{gacc, gpot, xbar, mbar};
+  return forces_impl(c, n, pos, mass, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream,
+                     kNeedAdjoint, &a, true);
 }
 
 hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt, const void* mass,

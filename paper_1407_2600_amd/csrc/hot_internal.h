@@ -220,6 +220,19 @@ struct hot_ctx {
   uint32_t last_ngroups;
   uint32_t* host_buf;  // pinned host memory for counter read-backs
   int last_chunks;     // list chunks of the last evaluation
+  // the tree and lists the workspace holds (hot_vjp_after_forces)
+  struct TreeRecord {
+    int valid;
+    const double* pos;
+    const void* mass;
+    size_t n, ws_bytes, words, o_list, cap_cells;
+    void* ws;
+    hipStream_t stream;
+    uint32_t lvl[hot::kMaxLevel + 3];
+    int nlev;
+    uint32_t ncells, ngroups;
+    size_t tp, tm;
+  } tree;
   hipEvent_t ev[8];
   int events_ok;
   hot::SideStream side;

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
 # symbols declared in include/hot.h
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
             "hot_forces", "hot_kdk",
-            "hot_vjp", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
+            "hot_vjp", "hot_vjp_after_forces", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
             "hot_last_error", "hot_version", "hot_far_table"]
 
 
@@ -89,6 +89,8 @@ def lib():
                               vp]
         L.hot_vjp.restype = C.c_int
         L.hot_vjp.argtypes = [vp, sz, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.hot_vjp_after_forces.restype = C.c_int
+        L.hot_vjp_after_forces.argtypes = [vp, sz, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.hot_kdk_vjp.restype = C.c_int
         L.hot_kdk_vjp.argtypes = [vp, sz, C.c_int, vp, vp, C.c_double, vp, vp, vp, vp, sz, vp]
         L.hot_get_stats.restype = C.c_int
@@ -279,8 +281,11 @@ class Gravity:
         self._call_retry(run, n, HOT_CALL_KDK_VJP)
         return mbar
 
-    def vjp(self, pos, mass, gacc, gpot=None):
-        """(xbar[3,N] FP64, mbar[N]) for cotangents of (acc, pot)."""
+    def vjp(self, pos, mass, gacc, gpot=None, after_forces=False):
+        """(xbar[3,N] FP64, mbar[N]) for cotangents of (acc, pot).  With
+        after_forces the caller guarantees that pos and mass hold the values
+        of this object's last evaluation, whose tree and lists the library
+        then reuses when it can (hot_vjp_after_forces)."""
         t = self.torch
         pos, mass = self._check_inputs(pos, mass)
         n = pos.shape[1]
@@ -290,8 +295,10 @@ class Gravity:
         mbar = t.empty(n, dtype=self.dtype, device=self.device)
         s = self._stream()
 
+        fn = self.L.hot_vjp_after_forces if after_forces else self.L.hot_vjp
+
         def run(ws):
-            return self.L.hot_vjp(self.h, n, C.c_void_p(pos.data_ptr()),
+            return fn(self.h, n, C.c_void_p(pos.data_ptr()),
                                   C.c_void_p(mass.data_ptr()), C.c_void_p(gacc.data_ptr()),
                                   C.c_void_p(gpot.data_ptr() if gpot is not None else 0),
                                   C.c_void_p(xbar.data_ptr()), C.c_void_p(mbar.data_ptr()),
@@ -347,7 +354,10 @@ def _autograd():
             grav = ctx.grav
             if gacc is None:
                 gacc = torch.zeros((3, pos.shape[1]), dtype=grav.dtype, device=pos.device)
-            xbar, mbar = grav.vjp(pos, mass, gacc, gpot)
+            # the saved tensors' version check guarantees unchanged positions
+            # and masses; the library reuses the forward's tree and lists when
+            # no other evaluation on this object came in between
+            xbar, mbar = grav.vjp(pos, mass, gacc, gpot, after_forces=True)
             return None, xbar, mbar
 
     return GravityForces

@@ -114,3 +114,43 @@ def test_autograd_function_backward():
     xo, mbo = oracle.Tree(pos, mass, prm).vjp(ga, gp)
     assert oracle.rms_rel_error(P.grad.cpu().numpy(), xo) < 1e-9
     assert oracle.rms_rel_error(M.grad.cpu().numpy(), mbo) < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_vjp_after_forces_matches_vjp(precision):
+    """hot_vjp_after_forces after a force evaluation at the same point uses
+    that evaluation's tree and lists and gives bit-identical results to
+    hot_vjp (same lists, same summation order), also when repeated; after an
+    evaluation at other positions it builds its own tree and again matches;
+    and the adjoint still matches the oracle's."""
+    import torch
+    from paper_1407_2600_amd import Gravity
+    pos, mass, prm, ga, gp = _case(n_side=20, theta=0.6, leaf_max=8, group_max=48)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    g = Gravity(precision=precision, **prm)
+    P = torch.as_tensor(pos, dtype=torch.float64, device="cuda")
+    M = torch.as_tensor(mass, dtype=dt, device="cuda")
+    GA = torch.as_tensor(ga, dtype=dt, device="cuda")
+    GP = torch.as_tensor(gp, dtype=dt, device="cuda")
+    P2 = torch.remainder(P + 0.013, 1.0)
+    print(f"vjp after forces {precision}: n={pos.shape[1]}", flush=True)
+    xr, mr = g.vjp(P, M, GA, GP)
+    xr2, mr2 = g.vjp(P2, M, GA, GP)
+    ref = [(xr.cpu().numpy(), mr.double().cpu().numpy()),
+           (xr2.cpu().numpy(), mr2.double().cpu().numpy())]
+    for pp, (xe, me) in ((P, ref[0]), (P2, ref[1])):
+        g.forces(pp, M)
+        for _ in range(2):
+            xb, mb = g.vjp(pp, M, GA, GP, after_forces=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(xb.cpu().numpy(), xe)
+            np.testing.assert_array_equal(mb.double().cpu().numpy(), me)
+    # the last evaluation was at P2: at P the library rebuilds the tree
+    xb, mb = g.vjp(P, M, GA, GP, after_forces=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(xb.cpu().numpy(), ref[0][0])
+    np.testing.assert_array_equal(mb.double().cpu().numpy(), ref[0][1])
+    gao, gpo = _oracle_inputs(ga, gp, precision)
+    xo, mbo = oracle.Tree(pos, oracle_mass(mass, precision), prm).vjp(gao, gpo)
+    assert oracle.rms_rel_error(ref[0][0], xo) <= TOL[precision]
+    assert oracle.rms_rel_error(ref[0][1], mbo) <= TOL[precision]
