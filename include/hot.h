@@ -239,17 +239,19 @@ hot_status hot_vjp(hot_ctx* ctx, size_t n, const double* pos, const void* mass, 
                    const void* gpot, double* xbar, void* mbar, void* workspace, size_t ws_bytes,
                    void* stream);
 
-/* hot_vjp for a backward pass that follows its forward evaluation: when the
- * context's last successful hot_forces, hot_kdk evaluation or hot_vjp on
- * this context ran with the same pos, mass, n, workspace (pointer and size)
- * and stream, processed its interaction lists in one pass, and those lists
- * lie below the adjoint's workspace regions, the keys, tree, groups and
- * lists it left in the workspace are used as they are (the adjoint runs on
- * the same lists; the derivatives are those of that evaluation).  Otherwise
- * it is hot_vjp.  The caller guarantees that pos and mass hold the values of
- * that evaluation and that the workspace was not written in between; the
- * library compares only pointers and sizes.  Arguments, results and errors
- * as hot_vjp. */
+/* hot_vjp for a backward pass that follows its forward evaluation (an
+ * extension beyond the paper).  When the last evaluation that completed on
+ * this context (by any entry point: a force evaluation of hot_forces or
+ * hot_kdk, or an adjoint) ran with the same pos, mass, n, workspace (pointer
+ * and size) and stream, processed its interaction lists in one pass, and
+ * those lists lie below the adjoint's workspace regions, the keys, tree,
+ * groups and lists it left in the workspace are used as they are: the
+ * adjoint runs on the same lists, so the result is bit-identical to
+ * hot_vjp's.  Otherwise it is hot_vjp.  The caller guarantees that pos and
+ * mass still hold the values of that evaluation and that nothing else wrote
+ * the workspace in between (no other context shares it); the library
+ * compares only pointers and sizes.  Arguments, results and errors as
+ * hot_vjp. */
 hot_status hot_vjp_after_forces(hot_ctx* ctx, size_t n, const double* pos, const void* mass,
                                 const void* gacc, const void* gpot, double* xbar, void* mbar,
                                 void* workspace, size_t ws_bytes, void* stream);
