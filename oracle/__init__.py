@@ -13,16 +13,19 @@ What it computes (paper Sec. 2.1, "2HOT"):
   the textbook Ewald split (real space + structure factors);
 * ``Tree``           -- the same-acceptance-test FP64 tree: Morton keys, sort,
   oct-tree, moments, sink groups, 27-image walk, direct and multipole
-  interactions, and the periodic far field as a local expansion of the Ewald
-  remainder about the box centre (the paper's high-order periodic expansion);
+  interactions, and the periodic far field as local expansions of the Ewald
+  remainder about the centres of the box's 8 octants (the paper's high-order
+  periodic expansion);
 * ``direct_near_far`` -- the tree result at theta=0 for sampled targets
   (27-image softened direct sum plus far field);
 * ``green_taylor``, ``psi_table``, ``ewald_psi``, ``ewald_xi``,
   ``multipole_eval``, ``direct_open`` -- the building blocks, exposed so the
   tests can pin each one to closed forms.
 
-Functions with no pin of their own are marked "parity unpinned" where they are
-defined; every function here is pinned by ``tests/test_oracle_*.py``.
+Every function here is pinned by ``tests/test_oracle_*.py`` against closed
+forms, literature constants, brute force or limits (the tree's accelerations
+and potentials against the direct Ewald sum, whose potential is pinned by the
+Madelung constant); none is "parity unpinned".
 """
 from __future__ import annotations
 

@@ -106,3 +106,17 @@ def test_kdk_vjp_zero_steps_and_free_drift():
     np.testing.assert_allclose(xb, cx, rtol=0, atol=1e-15)
     np.testing.assert_allclose(vb, cv + 4 * 0.01 * cx, rtol=1e-14, atol=1e-15)
     np.testing.assert_allclose(mb, 0.0, atol=1e-15)
+
+
+def test_wrap_box_lands_in_box_and_keeps_residue():
+    """wrap_box maps any coordinate into [0, L) by a whole number of box
+    lengths (values within rounding of L land on 0)."""
+    rng = np.random.default_rng(3)
+    L = 1.3
+    x = np.concatenate([rng.normal(0.0, 5.0, 500), [0.0, L, -L, 2 * L, -1e-18, L * (1 - 1e-17)]])
+    w = oracle.wrap_box(x, L)
+    assert np.all((w >= 0.0) & (w < L))
+    k = (x - w) / L
+    np.testing.assert_allclose(k, np.round(k), atol=1e-9)
+    inside = (x >= 0.0) & (x < L)
+    np.testing.assert_array_equal(w[inside], x[inside])

@@ -264,3 +264,116 @@ def test_perfect_lattice_tree_residual():
         a, p = T.forces()
         res.append(np.max(np.abs(a)) / ((1.0 / N) * n * n))
     assert res[2] < res[1] < res[0] < 1e-2
+
+
+def test_tree_potential_matches_ewald():
+    """The tree's potential against the exact periodic sum (the plain
+    definition, pinned itself by the Madelung constant): the 27-image softened
+    sum plus the far field about the octant centres reaches the direct Ewald
+    potential to the far-field floor, for targets in every octant.  This pins
+    the far field's constant terms (one per octant pair, which enter the
+    potential alone) and the self-image term Psi(0) carried by the octant
+    moments (paper Sec. 2.1: periodic local expansion, background
+    subtraction)."""
+    pos, mass, prm = workloads.make("lattice16", n_side=12)
+    n = pos.shape[1]
+    tg = np.arange(0, n, 3)
+    a1, p1 = oracle.direct_ewald(pos, mass, prm, targets=tg)
+    errs = []
+    for pf in (4, 6, 8):
+        T = oracle.Tree(pos, mass, dict(prm, theta=0.0, far_order=pf))
+        _, p0 = T.direct_near_far(tg)
+        errs.append(oracle.rms_rel_error(p0, p1))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] <= 1e-6
+    # the whole tree pipeline at theta = 0 (walk, direct lists, far field)
+    T = oracle.Tree(pos, mass, dict(prm, theta=0.0, far_order=8))
+    _, pt = T.forces()
+    assert oracle.rms_rel_error(pt[tg], p1) <= 1e-6
+    # every octant holds targets and sources
+    octs = (pos[0, tg] >= 0.5) * 4 + (pos[1, tg] >= 0.5) * 2 + (pos[2, tg] >= 0.5)
+    assert len(np.unique(octs)) == 8
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_perfect_lattice_potential_is_madelung(n):
+    """Unsoftened simple-cubic lattice of n^3 equal masses m: every particle
+    has phi = -G m xi n / L (xi the lattice's self constant, from the
+    literature); the theta = 0 tree reaches it to the far-field floor and the
+    tree at theta > 0 to its own (small, falling) approximation error."""
+    xi = -2.837297479
+    g = (np.arange(n) + 0.5) / n
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    N = pos.shape[1]
+    m = 1.0 / N
+    want = -m * xi * n
+    prm = dict(box=1.0, G=1.0, eps=0.0, order=4, leaf_max=8, group_max=8, far_order=8)
+    T = oracle.Tree(pos, np.full(N, m), dict(prm, theta=0.0))
+    _, p0 = T.direct_near_far(np.arange(N))
+    assert np.max(np.abs(p0 - want)) <= 1e-7 * abs(want)
+    res = []
+    for th in (0.7, 0.5, 0.3):
+        _, p = oracle.Tree(pos, np.full(N, m), dict(prm, theta=th)).forces()
+        res.append(np.max(np.abs(p - want)) / abs(want))
+    assert res[2] < res[1] < res[0] < 1e-2
+
+
+def test_pair_count_closed_form_and_lists():
+    """Direct pairs: at theta = 0 every (target, source image) pair but the
+    self pair is direct, N (27 N - 1) periodic and N (N - 1) open; at theta >
+    0 the count equals the sum over groups of targets x (own sources + listed
+    leaves' sources), counted from the lists by brute force."""
+    pos, mass, prm = workloads.make("nfw256", n_side=8)
+    n = pos.shape[1]
+    for periodic, want in ((1, n * (27 * n - 1)), (0, n * (n - 1))):
+        T = oracle.Tree(pos, mass, dict(prm, theta=0.0, periodic=periodic, leaf_max=8,
+                                        group_max=32))
+        assert T.pair_count() == want
+    T = oracle.Tree(pos, mass, dict(prm, theta=0.5, leaf_max=8, group_max=32))
+    c = T.cells()
+    gcell, _, _ = T.groups()
+    off, _, cell = T.lists(0)
+    want = 0
+    for g, A in enumerate(gcell):
+        src = c["count"][A] - 1 + int(np.sum(c["count"][cell[off[g]:off[g + 1]]]))
+        want += int(c["count"][A]) * src
+    assert T.pair_count() == want
+
+
+def test_far_field_moments_and_local_coefficients():
+    """Octant moments M^o_k = sum_{j in o} m_j (x_j - c_o)^k by brute force,
+    and the local coefficients of one particle: sum_q Lam_q h^q at a target
+    in every octant equals m Psi(x - y), the Ewald potential minus the 27
+    nearest bare images, to the order-8 truncation."""
+    rng = np.random.default_rng(31)
+    pos = rng.random((3, 200))
+    mass = rng.random(200)
+    prm = dict(box=1.0, G=1.0, eps=0.0, theta=0.5, order=2, leaf_max=8, group_max=16,
+               far_order=6)
+    T = oracle.Tree(pos, mass, prm)
+    _, M, _ = T.far()
+    mi = oracle.mi_list(6)
+    octs = (pos[0] >= 0.5) * 4 + (pos[1] >= 0.5) * 2 + (pos[2] >= 0.5)
+    for o in range(8):
+        cen = 0.25 + 0.5 * np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1])
+        d = pos[:, octs == o] - cen[:, None]
+        want = [np.sum(mass[octs == o] * d[0] ** a * d[1] ** b * d[2] ** cc) for a, b, cc in mi]
+        np.testing.assert_allclose(M[o], want, rtol=1e-12, atol=1e-14)
+    # one source particle: the local coefficients reproduce m Psi
+    y = np.array([0.31, 0.72, 0.44])
+    m = 0.7
+    T1 = oracle.Tree(y[:, None], np.array([m]), dict(prm, far_order=8))
+    _, _, Lam = T1.far()
+    mi8 = oracle.mi_list(8)
+    for o in range(8):
+        cen = 0.25 + 0.5 * np.array([(o >> 2) & 1, (o >> 1) & 1, o & 1])
+        x = cen + np.array([0.11, -0.07, 0.09])
+        h = x - cen
+        phi = sum(Lam[o, k] * h[0] ** a * h[1] ** b * h[2] ** cc for k, (a, b, cc) in
+                  enumerate(mi8))
+        r = x - y
+        psi_e, _ = oracle.ewald_psi(r)
+        bare = sum(1.0 / np.linalg.norm(r + np.array([i, j, k]))
+                   for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1))
+        assert phi == pytest.approx(m * (psi_e - bare), rel=1e-6, abs=1e-7)
