@@ -33,8 +33,9 @@
  *    hot_workspace_size(ctx, n)), aligned to 256
  *    bytes.  The library never allocates device memory in a compute call; it
  *    owns only the context (parameters, the Ewald table, a few device
- *    constants, and a second HIP stream with two events), created by
- *    hot_create and released by hot_destroy.
+ *    constants, a second HIP stream with two events, timing events and a
+ *    small pinned host buffer), created by hot_create and released by
+ *    hot_destroy.
  *  - Calls are enqueued on the caller's HIP stream (hipStream_t passed as
  *    void*; NULL = the default stream).  A compute call synchronises that
  *    stream a few times to size its launches (tree levels, list totals) and
@@ -125,7 +126,10 @@ typedef struct {
   double ms_build;        /* tree levels, moments, groups */
   double ms_walk;         /* both walk passes */
   double ms_p2p;          /* direct kernel */
-  double ms_m2p;          /* multipole kernel */
+  double ms_m2p;          /* multipole kernel (walk emit, direct and
+                             multipole times are summed over the list chunks
+                             when there are at most 64 of them; beyond that
+                             ms_p2p holds the whole chunk loop and ms_m2p 0) */
   double ms_far;          /* far field + unpermute */
   size_t ws_bytes_needed; /* workspace that would have sufficed */
   int64_t kdk_steps_done; /* steps hot_kdk completed in its last call */
@@ -277,7 +281,12 @@ hot_status hot_kdk_vjp(hot_ctx* ctx, size_t n, int nsteps, const double* pos_ckp
                        const void* mass, double dt, double* xbar, void* vbar, void* mbar,
                        void* workspace, size_t ws_bytes, void* stream);
 
-/* Statistics of the last compute call (synchronises nothing). */
+/* Statistics of the last compute call on ctx.  Waits on the host until that
+ * call's device work has finished (it synchronises on the call's final
+ * event, or on its stream if the context has no events), then reports the
+ * stage times of the context's HIP events and the pair counters the call
+ * copied to the context's pinned host memory.  It reads no workspace memory,
+ * so the workspace of that call may already be released. */
 hot_status hot_get_stats(const hot_ctx* ctx, hot_stats* out);
 
 /* Sizes for hot_debug_export after the last hot_forces call. */
@@ -290,6 +299,17 @@ hot_status hot_debug_sizes(const hot_ctx* ctx, int64_t* n, int64_t* ncells, int6
  * list buffers are requested after a call that processed its lists in chunks
  * (hot_stats.list_chunks > 1). */
 hot_status hot_debug_export(hot_ctx* ctx, void* workspace, hot_debug* out);
+
+/* Copy count interaction-list entries of the last hot_forces call, starting
+ * at entry first of the whole list of the given kind (0 = direct, 1 =
+ * multipole; the per-group ranges are the offsets hot_debug_export gives),
+ * to the host buffer out (count uint32 values, encoded as in hot_debug).
+ * For checking selected sink groups' lists of a large evaluation without
+ * copying all of them.  Synchronises the stream of that call.  HOT_EINVAL
+ * if no hot_forces call preceded, if its lists were processed in chunks, or
+ * if the range lies beyond the list. */
+hot_status hot_debug_list_range(hot_ctx* ctx, void* workspace, int kind, int64_t first,
+                                int64_t count, uint32_t* out);
 
 /* A Taylor table of the periodic far field, as built by hot_create:
  * Tpsi_s = d^s Psi(r0) / s!, |s| <= 2 far_order, of the periodic remainder

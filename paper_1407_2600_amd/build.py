@@ -16,6 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhot.so")
+# the FP64 Ewald reference (a measurement instrument; its own library, no
+# source in common with libhot)
+REF_LIB = os.path.join(HERE, "libhotref.so")
+REF_SOURCES = ["ewald_ref.hip"]
 SOURCES = ["scan.hip", "sort.hip", "tree.hip", "walk.hip", "forces.hip", "far.hip", "kdk.hip",
            "adjoint.hip", "far_adjoint.hip", "hot_abi.hip", "ewald_table.cpp"]
 ARCH = os.environ.get("HOT_OFFLOAD_ARCH", "gfx950")
@@ -41,17 +45,22 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(8, os.cpu_count() or 4)
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + f".tmp{os.getpid()}"
+def _link(objs, lib):
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs: int | None = None) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, SOURCES + REF_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], REF_LIB)
     return LIB
 
 

@@ -91,6 +91,9 @@ constexpr size_t kAlign = 256;
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// words of the context's pinned host buffer that receive the pair counters
+// (two u64) at the end of every evaluation
+constexpr int kHostPairs = 48;
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
        CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
@@ -485,9 +488,14 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                 "adjoint moments");
   }
   const bool single = chunks.size() == 1;
+  // chunked lists: each chunk's emit pass, direct and multipole kernels are
+  // timed with the context's chunk events (up to kChunkEvents chunks)
+  const bool cev = !single && c->events_ok && c->cev_ok && chunks.size() <= (size_t)kChunkEvents;
   if (!single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
   uint32_t* p2p_list = at<uint32_t>(ws, P.o_list);
+  size_t ck = 0;
   for (const Chunk& k : chunks) {
+    if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck], s), "event");
     const uint32_t ng = k.g1 - k.g0;
     Groups Gk = G;  // the chunk's groups (the box arrays keep their stride)
     Gk.cell += k.g0;
@@ -509,11 +517,13 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                 "pair count");
     }
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
+    if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 1], s), "event");
     if (!vjp) {
       HOT_CHECK(p2p_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list, near, s,
                            c->side),
                 "direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+      if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 2], s), "event");
       HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, n, m2p_list, near, s,
                            c->side),
                 "multipole kernel");
@@ -522,10 +532,13 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                                s, c->side),
                 "adjoint direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+      if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 2], s), "event");
       HOT_CHECK(m2p_adj_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, srec, arec, ecoef, n,
                                m2p_list, adj, s, c->side),
                 "adjoint multipole kernel");
     }
+    ++ck;
+    if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck], s), "event");
   }
   if (!single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
@@ -548,8 +561,14 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                              p.periodic, fp32, vjp->xbar, vjp->mbar, s),
               "far-field adjoint");
   }
+  // the pair counters go to the context's pinned host buffer, so that
+  // hot_get_stats reads no device memory (the workspace may be gone by then)
+  HOT_CHECK(hipMemcpyAsync(c->host_buf + kHostPairs, ctr + CTR_PAIRS, 16, hipMemcpyDeviceToHost,
+                           s),
+            "pair counters");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
   c->last_chunks = (int)chunks.size();
+  c->last_cev = cev ? (int)chunks.size() : 0;
 
   hot_stats& st = c->stats;
   std::memset(&st, 0, sizeof(st));
@@ -653,6 +672,10 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   c->events_ok = 1;
   for (int i = 0; i < 8; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = 0;
+  c->cev_ok = 1;
+  for (int i = 0; i < 3 * kChunkEvents + 1; ++i)
+    if (hipEventCreate(&c->cev[i]) != hipSuccess) c->cev_ok = 0;
+  (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&c->side.st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->side.fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->side.join, hipEventDisableTiming) != hipSuccess) {
@@ -671,6 +694,8 @@ void hot_destroy(hot_ctx* c) {
   if (c->host_buf) (void)hipHostFree(c->host_buf);
   for (int i = 0; i < 8; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 3 * kChunkEvents + 1; ++i)
+    if (c->cev[i]) (void)hipEventDestroy(c->cev[i]);
   if (c->side.st) (void)hipStreamDestroy(c->side.st);
   if (c->side.fork) (void)hipEventDestroy(c->side.fork);
   if (c->side.join) (void)hipEventDestroy(c->side.join);
@@ -869,12 +894,32 @@ hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
     return HOT_EINVAL;
   }
   hot_ctx* m = const_cast<hot_ctx*>(c);
-  if (m->have_last && m->events_ok) {
-    if (hipEventSynchronize(m->ev[6]) == hipSuccess) {
+  if (m->have_last) {
+    // wait for the last call's work: its final event (or its stream)
+    const hipError_t w = m->events_ok ? hipEventSynchronize(m->ev[6])
+                                      : hipStreamSynchronize(m->last_stream);
+    if (w == hipSuccess && m->events_ok) {
       float t[7] = {0};
       for (int i = 1; i <= 6; ++i) (void)hipEventElapsedTime(&t[i], m->ev[i - 1], m->ev[i]);
       float tot = 0;
       (void)hipEventElapsedTime(&tot, m->ev[0], m->ev[6]);
+      if (m->last_cev > 0) {
+        // chunked lists: the emit passes count as walk, the direct and
+        // multipole kernels are summed over the chunks
+        float w = 0, d = 0, q = 0;
+        for (int k = 0; k < m->last_cev; ++k) {
+          float a = 0, b = 0, e = 0;
+          (void)hipEventElapsedTime(&a, m->cev[3 * k], m->cev[3 * k + 1]);
+          (void)hipEventElapsedTime(&b, m->cev[3 * k + 1], m->cev[3 * k + 2]);
+          (void)hipEventElapsedTime(&e, m->cev[3 * k + 2], m->cev[3 * k + 3]);
+          w += a;
+          d += b;
+          q += e;
+        }
+        t[3] += w;
+        t[4] = d;
+        t[5] = q;
+      }
       m->stats.ms_sort = t[1];
       m->stats.ms_build = t[2];
       m->stats.ms_walk = t[3];
@@ -884,8 +929,8 @@ hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
       m->stats.ms_total = tot;
     }
     unsigned long long pr[2] = {0, 0};
-    const uint32_t* ctr = at<uint32_t>(m->last_ws, m->last_plan.o_ctr);
-    if (hipMemcpy(pr, ctr + CTR_PAIRS, sizeof(pr), hipMemcpyDeviceToHost) == hipSuccess) {
+    if (w == hipSuccess) {
+      std::memcpy(pr, m->host_buf + kHostPairs, sizeof(pr));
       m->stats.p2p_pairs = (int64_t)pr[0];
       m->stats.m2p_pairs = (int64_t)pr[1];
       m->stats.flops_p2p = (double)pr[0] * kP2PFlops;
@@ -965,6 +1010,38 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
       HOT_CHECK(cp(rec.data(), P.o_list + 4 * ((tp + 3) & ~size_t(3)), 16 * tm), "export");
       for (size_t i = 0; i < tm; ++i) oent[i] = rec[4 * i + 3];
     }
+  }
+  return HOT_OK;
+}
+
+hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, int64_t count,
+                                uint32_t* out) {
+  if (!c || !c->have_last || !ws || (count > 0 && !out) || (kind != 0 && kind != 1) ||
+      first < 0 || count < 0) {
+    g_err = "no previous hot_forces call or bad argument";
+    return HOT_EINVAL;
+  }
+  if (c->last_chunks != 1) {
+    g_err = "the last evaluation processed its lists in chunks; they are not all in memory";
+    return HOT_EINVAL;
+  }
+  const int64_t total = kind ? c->stats.m2p_entries : c->stats.p2p_entries;
+  if (first + count > total) {
+    g_err = "entry range beyond the list";
+    return HOT_EINVAL;
+  }
+  if (count == 0) return HOT_OK;
+  const Plan& P = c->last_plan;
+  HOT_CHECK(hipStreamSynchronize(c->last_stream), "sync");
+  if (kind == 0) {
+    HOT_CHECK(hipMemcpy(out, at<uint32_t>(ws, P.o_list) + first, 4 * (size_t)count,
+                        hipMemcpyDeviceToHost),
+              "export");
+  } else {
+    // the entry is the last word of each 16-byte multipole record
+    const size_t tp = (size_t)c->stats.p2p_entries;
+    const uint32_t* rec = at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3)) + 4 * first + 3;
+    HOT_CHECK(hipMemcpy2D(out, 4, rec, 16, 4, (size_t)count, hipMemcpyDeviceToHost), "export");
   }
   return HOT_OK;
 }

@@ -147,6 +147,10 @@ struct Groups {
   uint32_t* off_m2p;
 };
 
+// list chunks whose stages are timed one by one (beyond, only the chunk
+// loop as a whole is timed)
+constexpr int kChunkEvents = 64;
+
 struct Plan {
   size_t n;
   size_t cap_cells;
@@ -220,6 +224,7 @@ struct hot_ctx {
   uint32_t last_ngroups;
   uint32_t* host_buf;  // pinned host memory for counter read-backs
   int last_chunks;     // list chunks of the last evaluation
+  int last_cev;        // chunks timed one by one in the last evaluation (0: none)
   // the tree and lists the workspace holds (hot_vjp_after_forces)
   struct TreeRecord {
     int valid;
@@ -235,6 +240,11 @@ struct hot_ctx {
   } tree;
   hipEvent_t ev[8];
   int events_ok;
+  // per-chunk timing events when the lists are processed in chunks: chunk k
+  // records cev[3k] before its walk emit pass, cev[3k+1] before its direct
+  // kernel, cev[3k+2] before its multipole kernel and cev[3k+3] after it
+  hipEvent_t cev[3 * hot::kChunkEvents + 1];
+  int cev_ok;
   hot::SideStream side;
 };
 

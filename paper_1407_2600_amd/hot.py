@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
             "hot_forces", "hot_kdk",
             "hot_vjp", "hot_vjp_after_forces", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
-            "hot_last_error", "hot_version", "hot_far_table"]
+            "hot_debug_list_range", "hot_last_error", "hot_version", "hot_far_table"]
 
 
 class HotError(RuntimeError):
@@ -99,6 +99,8 @@ def lib():
         L.hot_debug_sizes.argtypes = [vp] + [C.POINTER(C.c_int64)] * 5
         L.hot_debug_export.restype = C.c_int
         L.hot_debug_export.argtypes = [vp, vp, C.POINTER(hot_debug)]
+        L.hot_debug_list_range.restype = C.c_int
+        L.hot_debug_list_range.argtypes = [vp, vp, C.c_int, C.c_int64, C.c_int64, vp]
         L.hot_last_error.restype = C.c_char_p
         L.hot_version.restype = C.c_char_p
         L.hot_far_table.restype = C.c_int
@@ -158,6 +160,9 @@ class Gravity:
         self.ws = None
         self.ws_cap = workspace_bytes
         self.list_bytes = list_bytes
+        # compute calls made on this context; the autograd backward reuses a
+        # forward evaluation's tree and lists only if no call came after it
+        self.evals = 0
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -191,6 +196,7 @@ class Gravity:
         return pos.contiguous(), mass.contiguous()
 
     def _call_retry(self, fn, n, calls=HOT_CALL_FORCES):
+        self.evals += 1
         for _ in range(6):
             ws = self._workspace(n, calls)
             st = fn(ws)
@@ -233,6 +239,7 @@ class Gravity:
                 raise ValueError(f"{name} must be a contiguous (3, N) {self.dtype} tensor")
         n = pos.shape[1]
         s = self._stream()
+        self.evals += 1
         left, valid = int(nsteps), bool(acc_valid)
         # after HOT_EOVERFLOW the library has restored the state at the end of
         # the last completed step; resume from there with a larger workspace
@@ -311,13 +318,25 @@ class Gravity:
         check(self.L.hot_get_stats(self.h, C.byref(st)))
         return st.as_dict()
 
+    def debug_list_range(self, kind: int, first: int, count: int):
+        """count entries of the last forces() call's direct (kind 0) or
+        multipole (kind 1) list, from entry first (host uint32 array)."""
+        import numpy as np
+        out = np.zeros(int(count), np.uint32)
+        check(self.L.hot_debug_list_range(self.h, C.c_void_p(self.ws.data_ptr()), int(kind),
+                                          int(first), int(count),
+                                          C.c_void_p(out.ctypes.data if count else None)))
+        return out
+
     def debug_export(self, lists: bool = True) -> dict:
-        """Host copies of keys, permutation, cells, groups and (unless lists
-        is False) the interaction lists of the last forces() call."""
+        """Host copies of keys, permutation, cells, groups, the per-group list
+        offsets and (unless lists is False) the interaction lists of the last
+        forces() call."""
         import numpy as np
         sizes = [C.c_int64() for _ in range(5)]
         check(self.L.hot_debug_sizes(self.h, *[C.byref(x) for x in sizes]))
         n, nc, ng, tp, tm = [x.value for x in sizes]
+        single = self.stats()["list_chunks"] == 1
         if not lists:
             tp = tm = 0
         out = dict(sorted_keys=np.zeros(n, np.uint64), perm=np.zeros(n, np.uint32),
@@ -327,7 +346,9 @@ class Gravity:
                    group_cell=np.zeros(ng, np.int32), p2p_offset=np.zeros(ng + 1, np.int64),
                    p2p_entry=np.zeros(tp, np.uint32), m2p_offset=np.zeros(ng + 1, np.int64),
                    m2p_entry=np.zeros(tm, np.uint32))
-        skip = () if lists else ("p2p_offset", "p2p_entry", "m2p_offset", "m2p_entry")
+        skip = () if lists else ("p2p_entry", "m2p_entry")
+        if not single:
+            skip = skip + ("p2p_offset", "m2p_offset")
         dbg = hot_debug(*[C.c_void_p(None if f in skip else out[f].ctypes.data)
                           for f, _ in hot_debug._fields_])
         check(self.L.hot_debug_export(self.h, C.c_void_p(self.ws.data_ptr()), C.byref(dbg)))
@@ -343,9 +364,15 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, grav, pos, mass):
-            acc, pot = grav.forces(pos.detach(), mass.detach())
+            # the exact (contiguous) tensors the library reads are kept alive
+            # until the backward, so no later allocation can take their
+            # addresses
+            pos_c = pos.detach().contiguous()
+            mass_c = mass.detach().contiguous()
+            acc, pot = grav.forces(pos_c, mass_c)
             ctx.grav = grav
-            ctx.save_for_backward(pos.detach(), mass.detach())
+            ctx.eval_id = grav.evals
+            ctx.save_for_backward(pos_c, mass_c)
             return acc, pot
 
         @staticmethod
@@ -355,9 +382,12 @@ def _autograd():
             if gacc is None:
                 gacc = torch.zeros((3, pos.shape[1]), dtype=grav.dtype, device=pos.device)
             # the saved tensors' version check guarantees unchanged positions
-            # and masses; the library reuses the forward's tree and lists when
-            # no other evaluation on this object came in between
-            xbar, mbar = grav.vjp(pos, mass, gacc, gpot, after_forces=True)
+            # and masses; the forward's tree and lists are reused only when no
+            # other compute call on this context came in between (otherwise
+            # the workspace holds that call's structures and the adjoint
+            # builds its own tree)
+            reuse = grav.evals == ctx.eval_id
+            xbar, mbar = grav.vjp(pos, mass, gacc, gpot, after_forces=reuse)
             return None, xbar, mbar
 
     return GravityForces

@@ -1,8 +1,22 @@
 """Helpers shared by the GPU tests: run the library through its binding and
 compare its exported structures with the oracle's, element by element."""
+import importlib.util
+import os
+
 import numpy as np
 
 import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def operating_point(workload):
+    """The benchmark's launch configuration for a workload (bench.py
+    OPERATING_POINT), so that parity is tested at exactly what is timed."""
+    spec = importlib.util.spec_from_file_location("bench_cfg", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return dict(m.OPERATING_POINT[workload])
 
 IMG_SHIFT = 27
 CELL_MASK = (1 << 27) - 1
@@ -17,7 +31,7 @@ def run_gpu(pos, mass, params, precision="fp64", want_debug=True, lists=True):
     m = torch.as_tensor(np.ascontiguousarray(mass), dtype=dt, device="cuda")
     acc, pot = g.forces(p, m)
     torch.cuda.synchronize()
-    if want_debug and lists and g.stats()["list_chunks"] > 1:
+    if want_debug and g.stats()["list_chunks"] > 1:
         # a new context may process its first lists in chunks (same results);
         # the structures are exported from a single-pass evaluation
         acc2, pot2 = g.forces(p, m)
@@ -30,6 +44,36 @@ def run_gpu(pos, mass, params, precision="fp64", want_debug=True, lists=True):
         out["dbg"] = g.debug_export(lists=lists)
     out["grav"] = g
     return out
+
+
+def compare_sampled_lists(grav, dbg, T, sample_groups):
+    """Bit-exact comparison of the sampled oracle groups' interaction lists
+    with the library's, fetching only those groups' entries (for evaluations
+    whose whole lists are too large to copy to the host)."""
+    ck = dbg["cell_key"]
+    c = T.cells()
+    gcell_o, _, _ = T.groups()
+    gpu_group = {int(ck[x]): i for i, x in enumerate(dbg["group_cell"])}
+    for kind in (0, 1):
+        off = dbg["m2p_offset" if kind else "p2p_offset"]
+        for g in sample_groups:
+            i = gpu_group[int(c["key"][gcell_o[g]])]
+            e = grav.debug_list_range(kind, off[i], off[i + 1] - off[i]).astype(np.int64)
+            got = sorted(zip((e >> IMG_SHIFT).tolist(), [int(x) for x in ck[e & CELL_MASK]]))
+            want = group_list_oracle(T, c, g, kind)
+            assert got == want, (kind, g, len(got), len(want))
+
+
+def max_err(a, ref):
+    """Largest per-target error relative to the rms of the reference: for
+    accelerations max_i |a_i - ref_i| / sqrt(mean_i |ref_i|^2) (the paper
+    bounds absolute force errors against the rms acceleration)."""
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if a.ndim == 1:
+        return float(np.max(np.abs(a - ref)) / np.sqrt(np.mean(ref ** 2)))
+    d = np.sqrt(np.sum((a - ref) ** 2, axis=0))
+    return float(np.max(d) / np.sqrt(np.mean(np.sum(ref ** 2, axis=0))))
 
 
 def group_lists_gpu(dbg, kind):

@@ -30,6 +30,25 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(hot.EXPORTED)
 
 
+def test_reference_library_exports_every_declared_symbol():
+    """libhotref (the FP64 Ewald reference, include/hotref.h) loads and
+    exports what its header declares; its scratch size is a host query."""
+    from paper_1407_2600_amd import hotref
+    src = open(os.path.join(ROOT, "include", "hotref.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(hotref_[a-z_]+)\s*\(", src)))
+    L = hotref.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(hotref.EXPORTED)
+    small = L.hotref_scratch_size(4096, 100)
+    big = L.hotref_scratch_size(1 << 30, 1000)
+    assert 0 < small < big < (1 << 30)
+    # no compute without a GPU: bad arguments are refused on the host
+    assert L.hotref_ewald(0, None, None, 0, 1, None, 1.0, 1.0, 0.0, None, None, None, 0,
+                          None) == 1
+
+
 def test_version_and_error_strings():
     L = hot.lib()
     assert L.hot_version().startswith(b"libhot")

@@ -28,20 +28,44 @@ def test_more_than_one_gpu_is_refused():
 
 def test_workload_defaults():
     b = _bench()
-    for name, w in b.WORKLOADS.items():
-        assert 1 <= w["leaf_max"] <= 255 and w["leaf_max"] <= w["group_max"] <= 4096
+    for name, op in b.OPERATING_POINT.items():
+        assert 1 <= op["leaf_max"] <= 255 and op["leaf_max"] <= op["group_max"] <= 4096
+        assert 0 <= op["theta"] < 1 and op["err_tol"] >= 0
         assert name in b.ETA_GRID and len(b.ETA_GRID[name]) > 0
+    for name, w in b.WORKLOADS.items():
         assert os.path.exists(os.path.join(ROOT, "tests", "golden", w["ref"]))
-    # the headline workload's defaults are the configuration its counters were taken at
+        if w["heldout"]:
+            assert os.path.exists(os.path.join(ROOT, "tests", "golden", w["heldout"]))
+    # the 128^3 operating point is the configuration the counters were taken at
     cfg = b.TRAFFIC["config"]
-    w = b.WORKLOADS[b.TRAFFIC["workload"]]
-    assert (w["leaf_max"], w["group_max"]) == (cfg["leaf_max"], cfg["group_max"])
+    op = b.OPERATING_POINT[b.TRAFFIC["workload"]]
+    assert all(op[k] == cfg[k] for k in op)
+
+
+def test_heldout_targets_are_disjoint_from_selection():
+    """The 128^3 held-out targets share none with the 10^4 selection targets
+    the operating point was chosen on."""
+    import numpy as np
+    g = os.path.join(ROOT, "tests", "golden")
+    sel = np.load(os.path.join(g, "zeldovich128_ref.npz"))["targets"]
+    held = np.load(os.path.join(g, "zeldovich128_heldout.npz"))["targets"]
+    assert len(held) >= 1000
+    assert len(np.intersect1d(sel, held)) == 0
 
 
 def test_traffic_reported_only_for_its_configuration():
+    import hashlib
     b = _bench()
     prm = dict(b.TRAFFIC["config"], box=1.0, G=1.0, periodic=1)
     wl = b.TRAFFIC["workload"]
+    h = hashlib.sha256()
+    for f in b.TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1407_2600_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != b.TRAFFIC["sha256"]:
+        # sources changed since the counter runs: nothing is reported
+        assert b.measured_traffic(prm, wl) is None
+        b.TRAFFIC["sha256"] = h.hexdigest()
     assert b.measured_traffic(prm, wl) == b.TRAFFIC["bytes_per_launch"]
     assert b.measured_traffic(dict(prm, group_max=prm["group_max"] * 2), wl) is None
     assert b.measured_traffic(dict(prm, err_tol=prm["err_tol"] * 1.5), wl) is None

@@ -8,11 +8,15 @@ import pytest
 
 import oracle
 import workloads
-from _gpu import compare_structure, oracle_mass, pot_ok, rms_err, run_gpu
+from _gpu import (compare_sampled_lists, compare_structure, max_err, operating_point,
+                  oracle_mass, pot_ok, rms_err, run_gpu)
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-5, "fp32": 2e-5}
+# bound on the largest per-target acceleration error, over the rms of the
+# oracle's accelerations
+MAX_TOL = {"fp64": 1e-4, "fp32": 2e-4}
 
 CASES = [
     # name, n_side, overrides
@@ -43,10 +47,42 @@ def test_structure_and_forces(name, ns, over, precision):
     compare_structure(r["dbg"], T)
     acc_o, pot_o = T.forces()
     ea = rms_err(r["acc"], acc_o)
+    em = max_err(r["acc"], acc_o)
     ok, ep = pot_ok(r["pot"], pot_o, precision, prm, mo)
-    print(f"  acc err {ea:.3e} pot err {ep:.3e}", flush=True)
+    print(f"  acc err {ea:.3e} (max {em:.3e}) pot err {ep:.3e}", flush=True)
     assert ea <= TOL[precision]
+    assert em <= MAX_TOL[precision]
     assert ok
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_mass_particles(precision):
+    """Massless particles (tracers) are allowed: they feel forces and exert
+    none.  A third of the particles and every particle of one region are
+    massless, so some cells have zero mass (their centre of mass is then the
+    cell centre on both sides)."""
+    pos, mass, prm = _case("zeldovich128", 16, dict(leaf_max=8, group_max=32, theta=0.6))
+    mass = mass.copy()
+    mass[::3] = 0.0
+    mass[pos[0] < 0.2] = 0.0
+    mo = oracle_mass(mass, precision)
+    T = oracle.Tree(pos, mo, prm)
+    c = T.cells()
+    assert np.any(c["mass"] == 0.0)
+    r = run_gpu(pos, mass, prm, precision)
+    compare_structure(r["dbg"], T)
+    acc_o, pot_o = T.forces()
+    ea, em = rms_err(r["acc"], acc_o), max_err(r["acc"], acc_o)
+    ok, ep = pot_ok(r["pot"], pot_o, precision, prm, mo)
+    print(f"zero masses {precision}: acc err {ea:.3e} (max {em:.3e}) pot err {ep:.3e}",
+          flush=True)
+    assert ea <= TOL[precision] and em <= MAX_TOL[precision] and ok
+    # the massive particles' forces do not depend on the massless ones
+    keep = mass > 0
+    r2 = run_gpu(pos[:, keep], mass[keep], prm, precision, want_debug=False)
+    scale = np.sqrt(np.mean(np.sum(r2["acc"] ** 2, axis=0)))
+    assert np.sqrt(np.mean(np.sum((r["acc"][:, keep] - r2["acc"]) ** 2, axis=0))) <= \
+        10 * TOL[precision] * scale
 
 
 @pytest.mark.parametrize("order", [0, 1, 2, 3, 4])
@@ -181,38 +217,40 @@ def test_deterministic_repeat():
         np.testing.assert_array_equal(r1["pot"], r2["pot"])
 
 
-# the benchmark's launch configurations (error-bound test at the 1e-3
-# operating point) at the workloads' full sizes
-FULL = [("zeldovich128", True), ("nfw256", False)]
-BENCH_PRM = {"zeldovich128": dict(theta=0.8, err_tol=5e-3, group_max=128, leaf_max=16),
-             "nfw256": dict(theta=0.0, err_tol=103.0, group_max=256, leaf_max=32)}
+# the benchmark's launch configurations (its fixed operating points) at the
+# workloads' full sizes
+FULL = ["zeldovich128", "nfw256"]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("name,lists", FULL)
-def test_full_size(name, lists, precision):
-    """Full size (128^3 = 2,097,152 and 256^3 = 16,777,216 particles): keys,
-    order and cells bit-exact over the whole tree; lists (where their export
-    fits in host memory) and forces on sampled sink groups against the
+@pytest.mark.parametrize("name", FULL)
+def test_full_size(name, precision):
+    """Full size (128^3 = 2,097,152 and 256^3 = 16,777,216 particles) at the
+    benchmark's operating point: keys, order and cells bit-exact over the
+    whole tree; the lists and forces of sampled sink groups against the
     oracle."""
     pos, mass, prm = workloads.make(name)
-    prm = dict(prm, **BENCH_PRM[name])
-    print(f"full size {name} {precision}: building oracle tree", flush=True)
+    prm = dict(prm, **operating_point(name))
+    print(f"full size {name} {precision} {prm}: building oracle tree", flush=True)
     mo = oracle_mass(mass, precision)
     T = oracle.Tree(pos, mo, prm)
-    r = run_gpu(pos, mass, prm, precision, lists=lists)
+    r = run_gpu(pos, mass, prm, precision, lists=False)
     print("  gpu stats", {k: r["stats"][k] for k in ("ncells", "ngroups", "p2p_entries",
                                                      "m2p_entries", "list_chunks")}, flush=True)
     gcell, _, _ = T.groups()
     rng = np.random.default_rng(99)
     sample = np.sort(rng.choice(len(gcell), size=24, replace=False))
-    compare_structure(r["dbg"], T, sample_groups=sample, lists=lists)
+    compare_structure(r["dbg"], T, lists=False)
+    compare_sampled_lists(r["grav"], r["dbg"], T, sample)
     acc_o, pot_o = T.forces(groups=sample)
     sel = ~np.isnan(pot_o)
     ea = rms_err(r["acc"][:, sel], acc_o[:, sel])
+    em = max_err(r["acc"][:, sel], acc_o[:, sel])
     ok, ep = pot_ok(r["pot"][sel], pot_o[sel], precision, prm, mo)
-    print(f"  sampled targets {sel.sum()} acc err {ea:.3e} pot err {ep:.3e}", flush=True)
+    print(f"  sampled targets {sel.sum()} acc err {ea:.3e} (max {em:.3e}) pot err {ep:.3e}",
+          flush=True)
     assert ea <= TOL[precision]
+    assert em <= MAX_TOL[precision]
     assert ok
 
 

@@ -154,3 +154,34 @@ def test_vjp_after_forces_matches_vjp(precision):
     xo, mbo = oracle.Tree(pos, oracle_mass(mass, precision), prm).vjp(gao, gpo)
     assert oracle.rms_rel_error(ref[0][0], xo) <= TOL[precision]
     assert oracle.rms_rel_error(ref[0][1], mbo) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autograd_interleaved_forwards_noncontiguous(precision):
+    """Two differentiable force evaluations on one context with
+    non-contiguous positions (a transposed (N, 3) tensor), then the backward
+    of the first: the first forward's tree and lists are no longer in the
+    workspace, so the backward must build its own tree; its gradients equal
+    hot_vjp's at the first positions, bit for bit."""
+    import torch
+    from paper_1407_2600_amd import Gravity, gravity_forces
+    pos, mass, prm, ga, gp = _case(n_side=14, theta=0.6, leaf_max=8, group_max=32)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    g = Gravity(precision=precision, **prm)
+    X1 = torch.as_tensor(pos.T.copy(), dtype=torch.float64, device="cuda").requires_grad_(True)
+    X2 = torch.remainder(X1.detach() + 0.021, 1.0).requires_grad_(True)
+    M = torch.as_tensor(mass, dtype=dt, device="cuda")
+    GA = torch.as_tensor(ga, dtype=dt, device="cuda")
+    GP = torch.as_tensor(gp, dtype=dt, device="cuda")
+    a1, p1 = gravity_forces(g, X1.T, M)   # X1.T is a non-contiguous (3, N) view
+    a2, p2 = gravity_forces(g, X2.T, M)
+    ((a1 * GA).sum() + (p1 * GP).sum()).backward()
+    torch.cuda.synchronize()
+    xr, _ = g.vjp(X1.detach().T.contiguous(), M, GA, GP)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(X1.grad.T.cpu().numpy(), xr.cpu().numpy())
+    # the second forward's backward right after it may reuse its tree
+    ((a2 * GA).sum() + (p2 * GP).sum()).backward()
+    xr2, _ = g.vjp(X2.detach().T.contiguous(), M, GA, GP)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(X2.grad.T.cpu().numpy(), xr2.cpu().numpy())
