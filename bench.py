@@ -110,7 +110,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the differentiation-workload timing")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 256 MiB device copy (three times), the reference the HBM "
@@ -648,12 +648,12 @@ def cpu_baseline(seconds):
     prm = dict(prm, **OPERATING_POINT["zeldovich128"])
     n = pos.shape[1]
 
-    def sampled(secs):
+    def sampled(secs, ncal):
         t0 = time.perf_counter()
         T = oracle.Tree(pos, mass, dict(prm))
         t_build = time.perf_counter() - t0
         ng = oracle.lib().or_tree_ngroups(T.h)
-        g0 = np.arange(0, ng, max(1, ng // 64))[:64]
+        g0 = np.arange(0, ng, max(1, ng // ncal))[:ncal]
         t0 = time.perf_counter()
         _, p = T.forces(groups=g0)
         t_cal = time.perf_counter() - t0
@@ -681,11 +681,11 @@ def cpu_baseline(seconds):
         return {"particles": p1.shape[1], "median_s": float(np.median(ts)),
                 "value": p1.shape[1] / float(np.median(ts))}
 
-    rate, desc = sampled(seconds)
+    rate, desc = sampled(seconds, 64)
     c1 = c1_full()
     one = None
     if _omp_threads(1):
-        r1, d1 = sampled(seconds / 2)
+        r1, d1 = sampled(seconds / 2, 8)
         one = {"value": r1, "cores": 1, "sample": d1, "c1_full": c1_full()}
         _omp_threads(threads)
     return {"value": rate, "unit": "particles/s", "cores": threads, "kind": "oracle",
