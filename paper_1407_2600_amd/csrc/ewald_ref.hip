@@ -25,6 +25,7 @@
 // pair term is at most 1.5 eps^2/|R|^2 ~ 3 eps^2/L^2 of it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -96,7 +97,7 @@ Sizes plan(size_t n, size_t nt) {
   z.o_h = take(4 * 3 * z.nh);
   z.o_w = take(8 * z.nh);
   z.o_sf = take(16 * z.nh);
-  z.o_kpart = take(16 * z.nh * z.nkc);
+  z.o_kpart = take(std::max<size_t>(16 * z.nh * z.nkc, 8 * 1024));  // also the mass partials
   const size_t ntt = (nt + kTT - 1) / kTT;
   z.o_rpart = take(32 * kTT * ntt * z.nrc);
   z.total = o;
@@ -330,18 +331,36 @@ __global__ void __launch_bounds__(256) k_finish(const double* __restrict__ pos, 
   }
 }
 
+// total mass: per-block partial sums (grid-stride), then one block adds them
+constexpr int kMassBlocks = 1024;
+
 template <typename M>
-__global__ void k_mass_sum(const M* __restrict__ mass, size_t n, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_mass_part(const M* __restrict__ mass, size_t n,
+                                                   double* __restrict__ part) {
   __shared__ double red[256];
   double s = 0.0;
-  for (size_t j = threadIdx.x; j < n; j += 256) s += mass_at(mass, j);
+  for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (size_t)kMassBlocks * 256)
+    s += mass_at(mass, j);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
     if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_mass_total(double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < kMassBlocks; j += 256) s += part[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[0] = red[0];
 }
 
 template <typename M>
@@ -358,12 +377,14 @@ hotref_status run(size_t n, const double* pos, const M* mass, size_t nt, const i
   double* d_rp = reinterpret_cast<double*>(ws + z.o_rpart);
   hipError_t e = hipMemcpyAsync(d_h, h.data(), 4 * h.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_w, w.data(), 8 * w.size(), hipMemcpyHostToDevice, s);
-  // the total mass for the background term: reuse the first structure-factor
-  // slot's space before the structure factors are written
+  // the total mass for the background term, summed in the structure-factor
+  // partial-sum region before the structure factors are computed
   double mtot = 0.0;
   if (e == hipSuccess) {
-    k_mass_sum<M><<<1, 256, 0, s>>>(mass, n, reinterpret_cast<double*>(d_sf));
-    e = hipMemcpyAsync(&mtot, d_sf, 8, hipMemcpyDeviceToHost, s);
+    double* part = reinterpret_cast<double*>(d_kp);
+    k_mass_part<M><<<kMassBlocks, 256, 0, s>>>(mass, n, part);
+    k_mass_total<<<1, 256, 0, s>>>(part);
+    e = hipMemcpyAsync(&mtot, part, 8, hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host tables stay alive until here
   if (e != hipSuccess) {
