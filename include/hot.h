@@ -206,6 +206,27 @@ size_t hot_workspace_size_min(const hot_ctx* ctx, size_t n, unsigned calls);
 hot_status hot_forces(hot_ctx* ctx, size_t n, const double* pos, const void* mass, void* acc,
                       void* pot, void* workspace, size_t ws_bytes, void* stream);
 
+/* hot_forces without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as hot_forces,
+ * bit-identical results; the scratch is a fixed 256 MiB array in device
+ * memory that the library holds on every GPU it has run on (allocated when
+ * the library's code object is loaded there, released at process exit).
+ * Nothing is allocated: no hipMalloc, hipFree or allocating library call.
+ * The forward structures for n particles must fit the array (FP32 mode,
+ * order 4, leaf 16: about 750,000 particles; less in FP64 mode or with
+ * smaller leaves); larger n gives HOT_ENOMEM with the size it would need.
+ * The interaction lists take the rest and are built and consumed in chunks
+ * of sink groups when they do not fit (same results).  The call runs on the
+ * context's device, which must be current (HOT_EINVAL otherwise).  Every
+ * call on one GPU, from any context or thread, shares that GPU's array and
+ * leaves its contents behind: calls that overlap in time on one GPU (other
+ * host threads, or streams that are not ordered after each other) race and
+ * give undefined results; calls ordered on one stream are safe.  A later
+ * hot_vjp_after_forces does not reuse this call's tree. */
+hot_status hot_forces_noalloc(hot_ctx* ctx, size_t n, const double* pos, const void* mass,
+                              void* acc, void* pot, void* stream);
+
 /* nsteps fixed-step kick-drift-kick leapfrog steps of length dt:
  * v += a dt/2; x = wrap(x + v dt); a = forces(x); v += a dt/2.
  *   pos   device, 3 x n FP64, in/out (wrapped into [0, L) on return)

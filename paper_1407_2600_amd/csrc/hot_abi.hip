@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,8 +85,35 @@ hipError_t zero_launch(void* p, size_t bytes, hipStream_t s);
 hipError_t drift_launch(bool fp32, double* pos, const void* vel, size_t n, double dt, double L,
                         hipStream_t s);
 
+// Device scratch of hot_forces_noalloc: one array per GPU the library runs on
+// (allocated when the code object is loaded there, held until the process
+// ends).  Host code uses it only through the device address that
+// hipGetSymbolAddress returns for the current device (scratch_ptr below).
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 thread_local std::string g_err;
+
+// per-device address of `scratch`, resolved once per device at context
+// creation (with that device current)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+bool g_scratch_done[kMaxDevices];
+
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_done[dev]) return;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  g_scratch_ptr[dev] = (e == hipSuccess) ? p : nullptr;
+  g_scratch_done[dev] = true;
+  if (e != hipSuccess) (void)hipGetLastError();
+}
 constexpr int kFarBlocks = 64;  // far-moment blocks per octant
 constexpr size_t kAlign = 256;
 
@@ -657,6 +685,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
     delete c;
     return device_error(e, "hipGetDevice");
   }
+  resolve_scratch(c->device);
   const int D = 2 * params->far_order;
   c->n_tpsi = nt(D);
   std::vector<double> tab((size_t)27 * c->n_tpsi);
@@ -732,6 +761,53 @@ hot_status hot_forces(hot_ctx* c, size_t n, const double* pos, const void* mass,
     return HOT_EINVAL;
   }
   return forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, (hipStream_t)stream, 0);
+}
+
+hot_status hot_forces_noalloc(hot_ctx* c, size_t n, const double* pos, const void* mass,
+                              void* acc, void* pot, void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !mass || !acc) {
+    g_err = "NULL pointer argument";
+    return HOT_EINVAL;
+  }
+  if (n >= (size_t)0xffffffffu) {
+    g_err = "n must be < 2^32";
+    return HOT_EINVAL;
+  }
+  int dev = -1;
+  HOT_CHECK(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != c->device) {
+    g_err = "the current device is not the context's device";
+    return HOT_EINVAL;
+  }
+  if (dev >= kMaxDevices || !g_scratch_done[dev] || !g_scratch_ptr[dev]) {
+    g_err = std::string("no-allocation scratch unavailable on this device: ") +
+            ((dev < kMaxDevices && g_scratch_done[dev]) ? hipGetErrorString(g_scratch_err[dev])
+                                                        : "not resolved");
+    return HOT_EDEVICE;
+  }
+  void* ws = g_scratch_ptr[dev];
+  // the structures must fit the fixed array; the interaction lists take what
+  // is left and are processed in chunks of sink groups when they do not fit
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    const Plan P = make_plan(c, n, kNoAllocBytes, 0);
+    if (P.min_total > kNoAllocBytes) {
+      g_err = "n = " + std::to_string(n) + " needs " + std::to_string(P.min_total) +
+              " bytes of scratch; hot_forces_noalloc has " + std::to_string(kNoAllocBytes) +
+              " (use hot_forces with a workspace)";
+      return HOT_ENOMEM;
+    }
+    const hot_status st =
+        forces_impl(c, n, pos, mass, acc, pot, ws, kNoAllocBytes, (hipStream_t)stream, 0);
+    if (st != HOT_EOVERFLOW) return st;
+    // a learned capacity grew (cells, or one group's lists): retry if the
+    // structures still fit
+  }
+  return HOT_EOVERFLOW;
 }
 
 hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mass, void* acc,

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
 
 # symbols declared in include/hot.h
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
-            "hot_forces", "hot_kdk",
+            "hot_forces", "hot_forces_noalloc", "hot_kdk",
             "hot_vjp", "hot_vjp_after_forces", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
             "hot_debug_list_range", "hot_last_error", "hot_version", "hot_far_table"]
 
@@ -84,6 +84,8 @@ def lib():
         L.hot_workspace_size_min.argtypes = [vp, sz, C.c_uint]
         L.hot_forces.restype = C.c_int
         L.hot_forces.argtypes = [vp, sz, vp, vp, vp, vp, vp, sz, vp]
+        L.hot_forces_noalloc.restype = C.c_int
+        L.hot_forces_noalloc.argtypes = [vp, sz, vp, vp, vp, vp, vp]
         L.hot_kdk.restype = C.c_int
         L.hot_kdk.argtypes = [vp, sz, vp, vp, vp, vp, vp, C.c_double, C.c_int, C.c_uint, vp, sz,
                               vp]
@@ -225,6 +227,27 @@ class Gravity:
                                      C.c_void_p(ws.data_ptr()), ws.numel(), s)
         self._call_retry(run, n)
         return acc, pot
+
+    def forces_noalloc(self, pos, mass, out_acc, out_pot=None):
+        """forces() through hot_forces_noalloc: the library's fixed device
+        scratch instead of a workspace; the caller passes the outputs, so
+        nothing is allocated."""
+        pos, mass = self._check_inputs(pos, mass)
+        n = pos.shape[1]
+        for name, a, shape in (("out_acc", out_acc, (3, n)), ("out_pot", out_pot, (n,))):
+            if a is not None and (a.dtype != self.dtype or tuple(a.shape) != shape or
+                                  not a.is_contiguous() or a.device != self.device):
+                raise ValueError(f"{name} must be a contiguous {shape} {self.dtype} tensor "
+                                 "on the context's device")
+        if out_acc is None:
+            raise ValueError("out_acc is required")
+        self.evals += 1
+        check(self.L.hot_forces_noalloc(self.h, n, C.c_void_p(pos.data_ptr()),
+                                        C.c_void_p(mass.data_ptr()),
+                                        C.c_void_p(out_acc.data_ptr()),
+                                        C.c_void_p(out_pot.data_ptr() if out_pot is not None
+                                                   else 0), self._stream()))
+        return out_acc, out_pot
 
     def kdk(self, pos, vel, mass, acc, dt: float, nsteps: int, acc_valid: bool, pot=None,
             snapshot: bool = True):
