@@ -37,7 +37,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["series.c", "ewald.c", "tree.c"]
+_SOURCES = ["series.c", "kernel.c", "ewald.c", "tree.c"]
 
 
 def build(force: bool = True) -> str:
@@ -93,9 +93,12 @@ def lib():
         L.or_tree_far.argtypes = [vp, dp, dp, dp]
         L.or_tree_vjp.argtypes = [vp, dp, dp, i64, i64p, dp, dp]
         L.or_direct_near_far.argtypes = [vp, i64, i64p, dp, dp]
-        L.or_direct_open.argtypes = [i64, dp, dp, C.c_double, C.c_double, dp, dp]
+        L.or_direct_open.argtypes = [i64, dp, dp, C.c_double, C.c_double, C.c_int, dp, dp]
+        L.or_pair_kernel.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
+        L.or_k1_radius.restype = C.c_double
+        L.or_k1_radius.argtypes = [C.c_double]
         L.or_direct_ewald.argtypes = [i64, dp, dp, i64, i64p, C.c_double, C.c_double,
-                                      C.c_double, C.c_double, C.c_int, C.c_int, dp, dp]
+                                      C.c_double, C.c_int, C.c_double, C.c_int, C.c_int, dp, dp]
         L.or_keys.argtypes = [i64, dp, C.c_double, u64p, dp]
         L.or_sort.argtypes = [i64, u64p, i64p]
         L.or_green_taylor.argtypes = [C.c_int, dp, C.c_double, dp]
@@ -121,7 +124,14 @@ class _Params(C.Structure):
     _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
                 ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
-                ("err_tol", C.c_double)]
+                ("err_tol", C.c_double), ("kernel", C.c_int)]
+
+# softening kernels: Plummer, or Dehnen's compensating K1 (kernel.c)
+KERNELS = {"plummer": 0, "k1": 1, 0: 0, 1: 1}
+
+
+def kernel_id(p: dict) -> int:
+    return KERNELS[p.get("kernel", 0)]
 
 
 def _params(p: dict) -> _Params:
@@ -129,7 +139,20 @@ def _params(p: dict) -> _Params:
                    float(p.get("theta", 0.5)), int(p.get("order", 2)),
                    int(p.get("periodic", 1)), int(p.get("leaf_max", 16)),
                    int(p.get("group_max", 64)), int(p.get("far_order", 8)),
-                   float(p.get("err_tol", 0.0)))
+                   float(p.get("err_tol", 0.0)), kernel_id(p))
+
+
+def pair_kernel(kernel, r2: float, eps: float):
+    """(g, f) of one pair at squared separation r2: potential -G m g and
+    acceleration -G m r f toward the source (kernel.c)."""
+    g, f = C.c_double(), C.c_double()
+    lib().or_pair_kernel(KERNELS[kernel], float(r2), float(eps), C.byref(g), C.byref(f))
+    return g.value, f.value
+
+
+def k1_radius(eps: float) -> float:
+    """Support radius of the K1 kernel for Plummer-equivalent softening eps."""
+    return lib().or_k1_radius(float(eps))
 
 
 def err_radius(G: float, b2: float, b: float, order: int, tol: float) -> float:
@@ -205,7 +228,7 @@ def multipole_eval(pos, mass, order: int, eps: float, x):
     return phi[0], g
 
 
-def direct_open(pos, mass, G: float = 1.0, eps: float = 0.0):
+def direct_open(pos, mass, G: float = 1.0, eps: float = 0.0, kernel=0):
     """Open-boundary softened direct sum; returns (acc[3,N], pot[N])."""
     L = lib()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
@@ -213,7 +236,7 @@ def direct_open(pos, mass, G: float = 1.0, eps: float = 0.0):
     n = pos.shape[1]
     acc = np.zeros((3, n))
     pot = np.zeros(n)
-    L.or_direct_open(n, _p(pos), _p(mass), G, eps, _p(acc), _p(pot))
+    L.or_direct_open(n, _p(pos), _p(mass), G, eps, KERNELS[kernel], _p(acc), _p(pot))
     return acc, pot
 
 
@@ -239,8 +262,8 @@ def direct_ewald(pos, mass, params: dict, targets=None, alpha: float | None = No
     acc = np.zeros((3, nt))
     pot = np.zeros(nt)
     L.or_direct_ewald(n, _p(pos), _p(mass), nt, _p(targets, C.c_int64), box,
-                      float(params.get("G", 1.0)), float(params.get("eps", 0.0)), alpha,
-                      nreal, kmax, _p(acc), _p(pot))
+                      float(params.get("G", 1.0)), float(params.get("eps", 0.0)),
+                      kernel_id(params), alpha, nreal, kmax, _p(acc), _p(pot))
     return acc, pot
 
 
@@ -363,7 +386,9 @@ class Tree:
         """(xbar[3,N], mbar[N]) for cotangents (gacc[3,N], gpot[N]) of the
         forces: the gather-form adjoint over the same lists (exact derivative
         of the direct sum at theta = 0).  With ``groups`` only their particles
-        are filled (NaN elsewhere)."""
+        are filled (NaN elsewhere).  Plummer softening only."""
+        if kernel_id(self.params) != 0:
+            raise NotImplementedError("the adjoint is built for Plummer softening only")
         ga = np.ascontiguousarray(gacc, dtype=np.float64)
         gp = None if gpot is None else np.ascontiguousarray(gpot, dtype=np.float64)
         xb = np.full((3, self.n), np.nan)

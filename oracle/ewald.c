@@ -271,7 +271,7 @@ static double wrapL(double x, double L) {
  * images the tree walks); all further images are unsoftened.  The reciprocal
  * part uses structure factors S(k) = sum_j m_j exp(2 pi i k.x_j / L). */
 void or_direct_ewald(int64_t n, const double* pos, const double* mass, int64_t nt,
-                     const int64_t* tgt, double L, double G, double eps, double alpha,
+                     const int64_t* tgt, double L, double G, double eps, int kernel, double alpha,
                      int nreal, int kmax, double* acc, double* pot) {
   double* x[3];
   for (int a = 0; a < 3; ++a) {
@@ -325,14 +325,16 @@ void or_direct_ewald(int64_t n, const double* pos, const double* mass, int64_t n
     free(lre); free(lim); free(ec); free(es);
   }
   double xi = or_ewald_xi(L, alpha, nreal + 2, kmax);
-  double eps2 = eps * eps;
+  const int soft = eps > 0.0;
   /* self images of the softening correction */
   double self_soft = 0.0;
   for (int img = 0; img < 27; ++img) {
     if (img == 13) continue;
     double d[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    self_soft += 1.0 / sqrt(r2 + eps2) - 1.0 / sqrt(r2);
+    double gs, fs;
+    or_pair_kernel(kernel, r2, eps, &gs, &fs);
+    self_soft += gs - 1.0 / sqrt(r2);
   }
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t t = 0; t < nt; ++t) {
@@ -368,14 +370,16 @@ void or_direct_ewald(int64_t n, const double* pos, const double* mass, int64_t n
             phi += mass[j] * e;
             for (int a = 0; a < 3; ++a) g[a] += mass[j] * dd * d[a] / rho;
           }
-      if (eps2 > 0.0) {
+      if (soft) {
+        /* the softened kernel replaces the bare one on the 27 near images */
         for (int img = 0; img < 27; ++img) {
           double d[3] = {r[0] - (img / 9 - 1) * L, r[1] - ((img / 3) % 3 - 1) * L,
                          r[2] - (img % 3 - 1) * L};
           double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-          double se = 1.0 / sqrt(r2 + eps2), s0 = 1.0 / sqrt(r2);
+          double se, fe, s0 = 1.0 / sqrt(r2);
+          or_pair_kernel(kernel, r2, eps, &se, &fe);
           phi += mass[j] * (se - s0);
-          double f = -(se * se * se - s0 * s0 * s0);
+          double f = -(fe - s0 * s0 * s0);
           for (int a = 0; a < 3; ++a) g[a] += mass[j] * f * d[a];
         }
       }

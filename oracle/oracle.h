@@ -31,7 +31,15 @@ typedef struct {
   int far_order;  /* order of the periodic local expansion */
   double err_tol; /* > 0: error-bound acceptance test (absolute acceleration
                      error allowed per accepted cell); 0: opening angle only */
+  int kernel;     /* softening: 0 Plummer (eps), 1 Dehnen K1 of radius
+                     (945/256) eps (Plummer-equivalent eps; kernel.c) */
 } or_params;
+
+/* ---- softening kernels (kernel.c) ---- */
+/* pair functions g (potential) and f (force / r) at squared separation r2 */
+void or_pair_kernel(int kernel, double r2, double eps, double* g, double* f);
+/* support radius h of the K1 kernel for Plummer-equivalent softening eps */
+double or_k1_radius(double eps);
 
 /* ---- multi-indices and truncated power series (series.c) ---- */
 void or_mi_init(void);

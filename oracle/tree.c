@@ -317,6 +317,13 @@ static void moments(tree_t* T) {
     } else if (!(theta > 0.0)) {
       rc = INFINITY;
     }
+    /* K1: accept only where every particle of the cell lies beyond the
+     * kernel radius from every target, so that its Newtonian expansion is
+     * the interaction it stands for */
+    if (T->p.kernel == 1) {
+      double rk = bmax + or_k1_radius(T->p.eps);
+      if (rk > rc) rc = rk;
+    }
     c->rcrit = rc;
     /* raw moments about the centre of mass, directly from the particles */
     c->M = calloc((size_t)nm, sizeof(double));
@@ -630,21 +637,31 @@ int64_t or_tree_group_list(void* h, int64_t g, int kind, int32_t* img, int64_t* 
 
 /* ---------------- forces ---------------- */
 
+/* one source of mass m at (sx, sy, sz) acting on the target: Phi += m g,
+ * grad Phi += m (source - target) f, with the softening kernel's g and f */
 static void pair_add(double tx, double ty, double tz, double sx, double sy, double sz, double m,
-                     double eps2, double* phi, double g[3]) {
+                     int kernel, double eps, double* phi, double g[3]) {
   double d[3] = {sx - tx, sy - ty, sz - tz};
-  double s2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
-  double si = 1.0 / sqrt(s2);
-  double si3 = si * si * si;
-  *phi += m * si;
-  for (int a = 0; a < 3; ++a) g[a] += m * d[a] * si3;
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double gv, fv;
+  or_pair_kernel(kernel, r2, eps, &gv, &fv);
+  *phi += m * gv;
+  for (int a = 0; a < 3; ++a) g[a] += m * d[a] * fv;
+}
+
+/* multipole interactions expand the softened Green's function for Plummer
+ * softening (so that a one-particle cell equals its direct interaction) and
+ * the Newtonian one for the compact K1 kernel, whose cells are accepted only
+ * when all their particles lie beyond its radius from every target */
+static double m2p_eps2(const tree_t* T) {
+  return T->p.kernel == 1 ? 0.0 : T->p.eps * T->p.eps;
 }
 
 static void m2p_add(const tree_t* T, const cell_t* B, const double R[3], double* phi,
                     double g[3]) {
   int p = T->p.order;
   double Tk[4096];
-  or_green_taylor(p + 1, R, T->p.eps * T->p.eps, Tk);
+  or_green_taylor(p + 1, R, m2p_eps2(T), Tk);
   for (int k = 0; k < T->nmom; ++k) {
     int ka, kb, kc;
     or_mi_get(k, &ka, &kb, &kc);
@@ -661,12 +678,13 @@ static void m2p_add(const tree_t* T, const cell_t* B, const double R[3], double*
  * particle s of group g */
 static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, double g_out[3]) {
   const cell_t* A = &T->cells[T->groups[g]];
-  double L = T->p.box, eps2 = T->p.eps * T->p.eps;
+  double L = T->p.box, eps = T->p.eps;
+  int kern = T->p.kernel;
   double tx = T->sx[0][s], ty = T->sx[1][s], tz = T->sx[2][s];
   double phi = 0.0, gr[3] = {0, 0, 0};
   for (int64_t j = A->first; j < A->first + A->count; ++j) {
     if (j == s) continue;
-    pair_add(tx, ty, tz, T->sx[0][j], T->sx[1][j], T->sx[2][j], T->sm[j], eps2, &phi, gr);
+    pair_add(tx, ty, tz, T->sx[0][j], T->sx[1][j], T->sx[2][j], T->sm[j], kern, eps, &phi, gr);
   }
   const list_t* lp = &T->p2p[g];
   for (int64_t e = 0; e < lp->n; ++e) {
@@ -675,7 +693,7 @@ static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, 
     const cell_t* B = &T->cells[lp->cell[e]];
     for (int64_t j = B->first; j < B->first + B->count; ++j)
       pair_add(tx, ty, tz, T->sx[0][j] + sh[0], T->sx[1][j] + sh[1], T->sx[2][j] + sh[2],
-               T->sm[j], eps2, &phi, gr);
+               T->sm[j], kern, eps, &phi, gr);
   }
   const list_t* lm = &T->m2p[g];
   for (int64_t e = 0; e < lm->n; ++e) {
@@ -726,7 +744,8 @@ void or_tree_forces(void* h, int64_t ngsel, const int64_t* gsel, double* acc, do
  * targets given by original index: the tree result at theta = 0. */
 void or_direct_near_far(void* h, int64_t nt, const int64_t* tgt, double* acc, double* pot) {
   tree_t* T = h;
-  double L = T->p.box, eps2 = T->p.eps * T->p.eps, G = T->p.G;
+  double L = T->p.box, eps = T->p.eps, G = T->p.G;
+  int kern = T->p.kernel;
   int64_t n = T->n;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t t = 0; t < nt; ++t) {
@@ -739,7 +758,7 @@ void or_direct_near_far(void* h, int64_t nt, const int64_t* tgt, double* acc, do
       for (int64_t j = 0; j < n; ++j) {
         if (img == 13 && j == i) continue;
         pair_add(tx, ty, tz, T->x[0][j] + sh[0], T->x[1][j] + sh[1], T->x[2][j] + sh[2],
-                 T->mass[j], eps2, &phi, gr);
+                 T->mass[j], kern, eps, &phi, gr);
       }
     }
     if (T->far_ok) {
@@ -908,15 +927,14 @@ void or_multipole_eval(int64_t n, const double* pos, const double* mass, int ord
 
 /* plain open-boundary direct sum (no images): the textbook softened sum */
 void or_direct_open(int64_t n, const double* pos, const double* mass, double G, double eps,
-                    double* acc, double* pot) {
-  double eps2 = eps * eps;
+                    int kernel, double* acc, double* pot) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double phi = 0, gr[3] = {0, 0, 0};
     for (int64_t j = 0; j < n; ++j) {
       if (j == i) continue;
       pair_add(pos[i], pos[n + i], pos[2 * n + i], pos[j], pos[n + j], pos[2 * n + j], mass[j],
-               eps2, &phi, gr);
+               kernel, eps, &phi, gr);
     }
     for (int a = 0; a < 3; ++a) acc[a * n + i] = G * gr[a];
     if (pot) pot[i] = -G * phi;
