@@ -112,6 +112,9 @@ def parse():
                     help="skip the differentiation-workload timing")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only the vector-ALU throughput probe (the measured issue ceiling of the "
+                         "force kernels' unpacked FP32 arithmetic)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only a plain 256 MiB device copy (three times), the reference the HBM "
                          "byte counters are scaled by")
@@ -139,7 +142,7 @@ TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_la
            "config": {"theta": 0.8, "err_tol": 0.00488, "order": 4, "leaf_max": 16,
                       "group_max": 128, "far_order": 8},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
-           "sha256": "013e8da3be00607e2b1fe6c5853e9c5ad41aa4f33916c48136f2ccdccf3dcfba"}
+           "sha256": "22df6af90525981603b753e0b2c219851a9740ca8d62de1a5c2bada096a21fef"}
 
 
 def measured_traffic(prm, workload):
@@ -555,6 +558,14 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         return copy_calibration()
+    if args.valu_probe:
+        from paper_1407_2600_amd.hotref import valu_probe
+        r = valu_probe()
+        for v in r.values():
+            # per SIMD (1024 on the chip) per ns; unpacked FP32 lane-flops of an fma
+            v["per_simd_per_ns"] = v["wave_instr_per_s"] / 1024 / 1e9
+        print(json.dumps({"valu_probe": r}))
+        return
     if args.workload != "zeldovich1024":
         print(json.dumps(workload_main(args)))
         return

@@ -25,8 +25,9 @@
  *    [0, L) internally.  Values outside that range, NaN or Inf give
  *    HOT_EINVAL.  Masses must be >= 0.
  *  - Units: potential phi_i = -G sum_j m_j g(x_i - x_j) and acceleration
- *    a_i = -grad phi_i, with the Plummer kernel g(r) = (|r|^2+eps^2)^(-1/2)
- *    on the 27 nearest images and the unsoftened Ewald kernel (neutralising
+ *    a_i = -grad phi_i, with the softened kernel g (Plummer,
+ *    g(r) = (|r|^2+eps^2)^(-1/2), or K1; see hot_params.kernel) on the 27
+ *    nearest images and the unsoftened Ewald kernel (neutralising
  *    background) on all others; a particle's own periodic images contribute.
  *  - Scratch memory comes from the caller: every compute call takes a device
  *    workspace of at least hot_workspace_size_min(ctx, n) bytes (preferably
@@ -107,7 +108,21 @@ typedef struct {
                       fixed fraction (about 0.1) of the rms acceleration
                       of the previous step keeps the rms force error near
                       1e-3 of the rms acceleration. */
+  int kernel;      /* softening kernel (paper Sec. 2.1): HOT_KERNEL_PLUMMER,
+                      or HOT_KERNEL_K1, Dehnen's compensating kernel, read as
+                      the compact density ~ (1 - x^2)^2 (1 - 11 x^2/5),
+                      x = r/h < 1, of radius h = (945/256) eps, so that eps
+                      is its Plummer-equivalent softening (equal central
+                      potential); exactly Newtonian beyond h.  With K1,
+                      multipole interactions use the Newtonian expansion and
+                      a cell is accepted only if all its particles lie
+                      farther than h from every target of the group; eps
+                      must be > 0.  The adjoints (hot_vjp, hot_kdk_vjp) are
+                      built for Plummer softening only. */
 } hot_params;
+
+#define HOT_KERNEL_PLUMMER 0
+#define HOT_KERNEL_K1 1
 
 /* Per-call statistics of the last compute call on a context. */
 typedef struct {
@@ -259,7 +274,8 @@ hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* m
  * for the tree approximation of the forces at the same parameters (the
  * exact derivative of the direct sum when theta == 0).  gacc, gpot and mbar
  * use the precision type; xbar is FP64.  Same errors as hot_forces;
- * HOT_EUNSUPPORTED if the build lacks the adjoint for the order. */
+ * HOT_EUNSUPPORTED if the build lacks the adjoint for the order, or with the
+ * K1 softening kernel. */
 hot_status hot_vjp(hot_ctx* ctx, size_t n, const double* pos, const void* mass, const void* gacc,
                    const void* gpot, double* xbar, void* mbar, void* workspace, size_t ws_bytes,
                    void* stream);

@@ -60,6 +60,19 @@ hotref_status hotref_ewald(size_t n, const double* pos, const void* mass, int ma
                            double eps, double* acc, double* pot, void* scratch,
                            size_t scratch_bytes, void* stream);
 
+/* Vector-ALU throughput probe: runs one kind of wavefront-wide independent
+ * arithmetic chains on the default stream (kind 0: FP32 fma, 1: FP32 mul,
+ * 2: FP32 add, 3: FP32 fma/mul/add in turn, 4: FP32 fma with one reciprocal
+ * square root per 16 operations, 5: FP64 fma, 6: FP32 fma accumulating
+ * into the chain), repeats times after one
+ * 20 warm-up launches, and reports the mean ms per launch and the wave instructions of
+ * one launch.  scratch: device, >= hotref_valu_probe_scratch() bytes
+ * (written).  Synchronises the default stream.  It measures the issue
+ * ceiling the force kernels' unpacked FP32 arithmetic runs against. */
+size_t hotref_valu_probe_scratch(void);
+hotref_status hotref_valu_probe(int kind, void* scratch, size_t scratch_bytes, int repeats,
+                                double* ms, double* wave_instructions);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* hotref_last_error(void);
 

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libhot.so")
 # the FP64 Ewald reference (a measurement instrument; its own library, no
 # source in common with libhot)
 REF_LIB = os.path.join(HERE, "libhotref.so")
-REF_SOURCES = ["ewald_ref.hip"]
+REF_SOURCES = ["ewald_ref.hip", "valu_probe.hip"]
 SOURCES = ["scan.hip", "sort.hip", "tree.hip", "walk.hip", "forces.hip", "far.hip", "kdk.hip",
            "adjoint.hip", "far_adjoint.hip", "hot_abi.hip", "ewald_table.cpp"]
 ARCH = os.environ.get("HOT_OFFLOAD_ARCH", "gfx950")

@@ -37,11 +37,39 @@ constexpr int kForceWaves = 4;
 // accumulators.  This kernel writes (not adds) the accumulators.
 constexpr int kStage = 256;
 
+// Softening of the direct kernel.  Plummer: g = (r^2 + e2)^(-1/2), f = g^3.
+// Dehnen's compensating K1 (paper Sec. 2.1), compact density
+// ~ (1 - x^2)^2 (1 - 11 x^2/5) of radius h, x = r/h: inside h
+//   g = (945 - 2100 x^2 + 2646 x^4 - 1620 x^6 + 385 x^8) / (256 h),
+//   f = (525 - 1323 x^2 + 1215 x^4 - 385 x^6) / (32 h^3),
+// beyond it exactly Newtonian (g = 1/r, f = 1/r^3).  A source of mass m adds
+// m g to the potential sum and m f (source - target) to the force sum.
+template <typename T>
+struct Soft {
+  T e2;   // Plummer eps^2 (0 with K1)
+  T h2;   // K1: h^2
+  T ih2;  // K1: 1/h^2
+  T cg;   // K1: 1/(256 h)
+  T cf;   // K1: 1/(32 h^3)
+};
+
+template <typename T>
+__device__ __forceinline__ void k1_gf(T r2, const Soft<T>& sf, T& g, T& f) {
+  const bool in = r2 < sf.h2;
+  const T x2 = r2 * sf.ih2;
+  const T gp = fma(fma(fma(fma((T)385, x2, (T)-1620), x2, (T)2646), x2, (T)-2100), x2, (T)945) *
+               sf.cg;
+  const T fp = fma(fma(fma((T)-385, x2, (T)1215), x2, (T)-1323), x2, (T)525) * sf.cf;
+  const T ri = rsqrt_t(in ? (T)1 : r2);
+  g = in ? gp : ri;
+  f = in ? fp : ri * (ri * ri);
+}
+
 // staged sources [a, b) against this lane's target; the partial sums are
 // folded every 64 sources and at the end
-template <typename T, typename T4, bool OWN>
+template <typename T, typename T4, bool OWN, bool K1>
 __device__ __forceinline__ void p2p_staged(const T4* __restrict__ st, int a, int b, uint32_t sub,
-                                           uint32_t split, T tx, T ty, T tz, T eps2,
+                                           uint32_t split, T tx, T ty, T tz, const Soft<T>& sf,
                                            uint32_t self_slot, Acc<T>& acc) {
   for (int b0 = a; b0 < b; b0 += 64) {
     const int b1 = b0 + 64 < b ? b0 + 64 : b;
@@ -50,26 +78,33 @@ __device__ __forceinline__ void p2p_staged(const T4* __restrict__ st, int a, int
     for (int j = b0 + (int)sub; j < b1; j += (int)split) {
       const T4 r = st[j];
       const T dx = r.x - tx, dy = r.y - ty, dz = r.z - tz;
-      T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-      if constexpr (OWN) {
+      T r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, sf.e2)));
+      T mr, mr3;
+      if constexpr (K1) {
+        T g, f;
+        k1_gf(r2, sf, g, f);
+        mr = r.w * g;
+        mr3 = r.w * f;
+        if constexpr (OWN) {
+          const bool self = (uint32_t)j == self_slot;
+          mr = self ? (T)0 : mr;
+          mr3 = self ? (T)0 : mr3;
+        }
+      } else if constexpr (OWN) {
         const bool self = (uint32_t)j == self_slot;
         r2 = self ? (T)1 : r2;
         const T ri = rsqrt_t(r2);
-        const T mr = self ? (T)0 : r.w * ri;
-        const T mr3 = mr * (ri * ri);
-        part[0] = fma(dx, mr3, part[0]);
-        part[1] = fma(dy, mr3, part[1]);
-        part[2] = fma(dz, mr3, part[2]);
-        part[3] += mr;
+        mr = self ? (T)0 : r.w * ri;
+        mr3 = mr * (ri * ri);
       } else {
         const T ri = rsqrt_t(r2);
-        const T mr = r.w * ri;
-        const T mr3 = mr * (ri * ri);
-        part[0] = fma(dx, mr3, part[0]);
-        part[1] = fma(dy, mr3, part[1]);
-        part[2] = fma(dz, mr3, part[2]);
-        part[3] += mr;
+        mr = r.w * ri;
+        mr3 = mr * (ri * ri);
       }
+      part[0] = fma(dx, mr3, part[0]);
+      part[1] = fma(dy, mr3, part[1]);
+      part[2] = fma(dz, mr3, part[2]);
+      part[3] += mr;
     }
     acc.fold(part);
   }
@@ -84,10 +119,10 @@ struct SourceStage {
   T sh[W][3][64];
 };
 
-template <typename T, typename T4, bool TAIL>
+template <typename T, typename T4, bool TAIL, bool K1>
 __device__ __forceinline__ void p2p_group(uint32_t g, SourceStage<T, T4, kForceWaves, kStage>& lds,
                                           Cells C, Groups G,
-                                          double L, T eps2,
+                                          double L, Soft<T> sf,
                                           const double* __restrict__ spos,
                                           const T4* __restrict__ srec, size_t n,
                                           const uint32_t* __restrict__ list,
@@ -134,7 +169,7 @@ __device__ __forceinline__ void p2p_group(uint32_t g, SourceStage<T, T4, kForceW
         st[k] = r;
       }
       wave_sync();
-      p2p_staged<T, T4, true>(st, 0, nb, sub, split, tx, ty, tz, eps2, ss - first - s0, acc);
+      p2p_staged<T, T4, true, K1>(st, 0, nb, sub, split, tx, ty, tz, sf, ss - first - s0, acc);
     }
     // listed leaves, 64 entries at a time
     for (uint32_t q0 = 0; q0 < cnt; q0 += 64) {
@@ -189,7 +224,7 @@ __device__ __forceinline__ void p2p_group(uint32_t g, SourceStage<T, T4, kForceW
           const uint32_t hi = __builtin_amdgcn_readfirstlane(e_incl[ecur]);
           const int a = (int)((lo > s0 ? lo : s0) - s0);
           const int b = (int)((hi < s1 ? hi : s1) - s0);
-          p2p_staged<T, T4, false>(st, a, b, sub, split, tx, ty, tz, eps2, 0u, acc);
+          p2p_staged<T, T4, false, K1>(st, a, b, sub, split, tx, ty, tz, sf, 0u, acc);
           if (hi > s1) break;  // the entry continues in the next batch
           lo = hi;
           ++ecur;
@@ -355,9 +390,9 @@ __device__ __forceinline__ void m2p_group(uint32_t g, Cells C, Groups G,
 // Main and tail passes are separate kernels (the tail pass needs more
 // registers), launched tail first on the context's side stream so that its
 // few long, lightly occupied wavefronts run beside the main passes.
-template <typename T, typename T4, bool TAIL>
+template <typename T, typename T4, bool TAIL, bool K1>
 __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uint32_t ngroups,
-                                                          double L, T eps2,
+                                                          double L, Soft<T> sf,
                                                           const double* __restrict__ spos,
                                                           const T4* __restrict__ srec, size_t n,
                                                           const uint32_t* __restrict__ list,
@@ -366,7 +401,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
   const int wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
-  p2p_group<T, T4, TAIL>(g, lds, C, G, L, eps2, spos, srec, n, list, out);
+  p2p_group<T, T4, TAIL, K1>(g, lds, C, G, L, sf, spos, srec, n, list, out);
 }
 
 // main passes one group per wavefront; tail passes one group per block
@@ -384,31 +419,51 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
   m2p_group<P, T, TAIL>(g, C, G, L, eps2, spos, n, list, out);
 }
 
-template <typename T, typename T4>
+template <typename T, typename T4, bool K1>
 static hipError_t p2p_launch_t(const Cells& C, const Groups& G, uint32_t ngroups, double L,
-                               T eps2, const double* spos, const T4* srec, size_t n,
+                               Soft<T> sf, const double* spos, const T4* srec, size_t n,
                                const uint32_t* list, double4* out, hipStream_t s,
                                const SideStream& side) {
   const unsigned nb = (ngroups + kForceWaves - 1) / kForceWaves;
   hipStream_t st;
   hipError_t e = side_fork(side, s, &st);
   if (e != hipSuccess) return e;
-  k_p2p<T, T4, true><<<nb, 64 * kForceWaves, 0, st>>>(C, G, ngroups, L, eps2, spos, srec, n,
-                                                      list, out);
-  k_p2p<T, T4, false><<<nb, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, eps2, spos, srec, n,
-                                                       list, out);
+  k_p2p<T, T4, true, K1><<<nb, 64 * kForceWaves, 0, st>>>(C, G, ngroups, L, sf, spos, srec, n,
+                                                          list, out);
+  k_p2p<T, T4, false, K1><<<nb, 64 * kForceWaves, 0, s>>>(C, G, ngroups, L, sf, spos, srec, n,
+                                                           list, out);
   e = hipGetLastError();
   return e != hipSuccess ? e : side_join(side, s);
 }
 
-hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
-                      double eps, const double* spos, const void* srec, size_t n,
+template <typename T, typename T4>
+static hipError_t p2p_launch_k(bool k1, const Cells& C, const Groups& G, uint32_t ngroups,
+                               double L, double eps, const double* spos, const T4* srec, size_t n,
+                               const uint32_t* list, double4* out, hipStream_t s,
+                               const SideStream& side) {
+  Soft<T> sf{};
+  if (!k1) {
+    sf.e2 = (T)(eps * eps);
+    return p2p_launch_t<T, T4, false>(C, G, ngroups, L, sf, spos, srec, n, list, out, s, side);
+  }
+  const double h = k1_radius(eps);
+  sf.h2 = (T)(h * h);
+  sf.ih2 = (T)(1.0 / (h * h));
+  sf.cg = (T)(1.0 / (256.0 * h));
+  sf.cf = (T)(1.0 / (32.0 * h * h * h));
+  return p2p_launch_t<T, T4, true>(C, G, ngroups, L, sf, spos, srec, n, list, out, s, side);
+}
+
+hipError_t p2p_launch(bool fp32, int kernel, const Cells& C, const Groups& G, uint32_t ngroups,
+                      double L, double eps, const double* spos, const void* srec, size_t n,
                       const uint32_t* list, double4* out, hipStream_t s, const SideStream& side) {
   if (ngroups == 0) return hipSuccess;
+  const bool k1 = kernel == HOT_KERNEL_K1;
+  if (k1 && !(eps > 0.0)) return hipErrorInvalidValue;
   if (fp32)
-    return p2p_launch_t<float, float4>(C, G, ngroups, L, (float)(eps * eps), spos,
-                                       (const float4*)srec, n, list, out, s, side);
-  return p2p_launch_t<double, double4>(C, G, ngroups, L, eps * eps, spos, (const double4*)srec, n,
+    return p2p_launch_k<float, float4>(k1, C, G, ngroups, L, eps, spos, (const float4*)srec, n,
+                                       list, out, s, side);
+  return p2p_launch_k<double, double4>(k1, C, G, ngroups, L, eps, spos, (const double4*)srec, n,
                                        list, out, s, side);
 }
 

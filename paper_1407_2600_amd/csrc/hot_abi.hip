@@ -28,7 +28,7 @@ hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, u
                            uint32_t cap, hipStream_t s);
 hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
                               uint32_t beg, uint32_t cnt, double L, double theta, double G,
-                              double err_tol, int order,
+                              double err_tol, double k1h, int order,
                               bool fp32, hipStream_t s);
 hipError_t tree_groups(const Cells& C, uint32_t ncells, int gmax, size_t n, uint32_t* gflag,
                        uint32_t* gid, int32_t* gcell_at, const Groups& G, uint32_t* ngroups_dev,
@@ -44,8 +44,8 @@ hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sum
                       hipStream_t s);
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* p2p_list,
                        unsigned long long* out, hipStream_t s);
-hipError_t p2p_launch(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups, double L,
-                      double eps, const double* spos, const void* srec, size_t n,
+hipError_t p2p_launch(bool fp32, int kernel, const Cells& C, const Groups& G, uint32_t ngroups,
+                      double L, double eps, const double* spos, const void* srec, size_t n,
                       const uint32_t* list, double4* out, hipStream_t s, const SideStream& side);
 hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uint32_t ngroups,
                       double L, double eps, const double* spos, size_t n, const uint4* list,
@@ -149,6 +149,10 @@ bool valid_params(const hot_params* p, std::string* why) {
     return *why = "far_order must be in 0..12", false;
   if (p->precision != HOT_FP64 && p->precision != HOT_FP32)
     return *why = "precision must be HOT_FP64 or HOT_FP32", false;
+  if (p->kernel != HOT_KERNEL_PLUMMER && p->kernel != HOT_KERNEL_K1)
+    return *why = "kernel must be HOT_KERNEL_PLUMMER or HOT_KERNEL_K1", false;
+  if (p->kernel == HOT_KERNEL_K1 && !(p->eps > 0.0))
+    return *why = "the K1 kernel needs eps > 0", false;
   return true;
 }
 
@@ -421,9 +425,11 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     nlev = l + 2;
   }
   ncells = lvl[nlev];
+  // K1: cells are accepted only beyond their extent plus the kernel radius
+  const double k1h = p.kernel == HOT_KERNEL_K1 ? k1_radius(p.eps) : -1.0;
   for (int l = nlev - 1; l >= 0; --l)
     HOT_CHECK(tree_moments_level(C, spos, smass, n, lvl[l], lvl[l + 1] - lvl[l], p.box, p.theta,
-                                 p.G, p.err_tol, p.order, fp32, s),
+                                 p.G, p.err_tol, k1h, p.order, fp32, s),
               "moments");
   uint32_t* gflag = tmp;
   uint32_t* gid = reinterpret_cast<uint32_t*>(key1);
@@ -547,12 +553,15 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
     if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 1], s), "event");
     if (!vjp) {
-      HOT_CHECK(p2p_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list, near, s,
-                           c->side),
+      HOT_CHECK(p2p_launch(fp32, p.kernel, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list,
+                           near, s, c->side),
                 "direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
       if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 2], s), "event");
-      HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, n, m2p_list, near, s,
+      // multipoles expand the softened kernel for Plummer, the Newtonian one
+      // for K1 (accepted cells lie beyond its radius)
+      HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box,
+                           p.kernel == HOT_KERNEL_K1 ? 0.0 : p.eps, spos, n, m2p_list, near, s,
                            c->side),
                 "multipole kernel");
     } else {
@@ -871,6 +880,10 @@ hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, co
     g_err = "ctx is NULL";
     return HOT_EINVAL;
   }
+  if (c->p.kernel != HOT_KERNEL_PLUMMER) {
+    g_err = "the adjoint is built for Plummer softening only";
+    return HOT_EUNSUPPORTED;
+  }
   if (n == 0) return HOT_OK;
   if (!pos || !mass || !gacc || !xbar || !mbar || !ws) {
     g_err = "NULL pointer argument";
@@ -892,6 +905,10 @@ hot_status hot_vjp_after_forces(hot_ctx* c, size_t n, const double* pos, const v
     g_err = "ctx is NULL";
     return HOT_EINVAL;
   }
+  if (c->p.kernel != HOT_KERNEL_PLUMMER) {
+    g_err = "the adjoint is built for Plummer softening only";
+    return HOT_EUNSUPPORTED;
+  }
   if (n == 0) return HOT_OK;
   if (!pos || !mass || !gacc || !xbar || !mbar || !ws) {
     g_err = "NULL pointer argument";
@@ -912,6 +929,10 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
   if (!c) {
     g_err = "ctx is NULL";
     return HOT_EINVAL;
+  }
+  if (c->p.kernel != HOT_KERNEL_PLUMMER) {
+    g_err = "the adjoint is built for Plummer softening only";
+    return HOT_EUNSUPPORTED;
   }
   if (n == 0) return HOT_OK;
   if (!pos_ckpt || !mass || !xbar || !vbar || !ws || nsteps < 0 || !std::isfinite(dt)) {

@@ -12,6 +12,9 @@
 namespace hot {
 
 constexpr int kMaxLevel = 21;        // 21 bits per axis in a 64-bit key
+// support radius of the K1 softening kernel for the Plummer-equivalent
+// softening eps (equal central potential: g(0) = 945/(256 h) = 1/eps)
+inline double k1_radius(double eps) { return (945.0 / 256.0) * eps; }
 constexpr int kMaxOrder = 4;         // cell multipole order built into the kernels
 constexpr int kMaxFarOrder = 12;     // far-field local expansion order
 constexpr int kImgBits = 5;          // list entry = image << 27 | cell

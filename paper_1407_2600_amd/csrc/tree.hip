@@ -185,7 +185,8 @@ template <int P, typename T>
 __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restrict__ spos,
                                                  const double* __restrict__ smass, size_t n,
                                                  uint32_t beg, uint32_t cnt, double L,
-                                                 double theta, double G, double err_tol) {
+                                                 double theta, double G, double err_tol,
+                                                 double k1h) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   const uint32_t c = beg + t;
@@ -266,6 +267,11 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
     if (re > rcrit) rcrit = re;
   } else if (!(theta > 0.0)) {
     rcrit = __builtin_inf();
+  }
+  // K1 softening: all of the cell's particles beyond the kernel radius
+  if (k1h >= 0.0) {
+    const double rk = bmax + k1h;
+    if (rk > rcrit) rcrit = rk;
   }
   C.mmx[c] = make_double4(m, sx, sy, sz);
   C.walk[c] = make_double4(com[0], com[1], com[2], rcrit);
@@ -403,21 +409,21 @@ hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, u
 template <int P, typename T>
 static void moments_launch(const Cells& C, const double* spos, const double* smass, size_t n,
                            uint32_t beg, uint32_t cnt, double L, double theta, double G,
-                           double err_tol, hipStream_t s) {
+                           double err_tol, double k1h, hipStream_t s) {
   k_moments<P, T><<<(cnt + 127) / 128, 128, 0, s>>>(C, spos, smass, n, beg, cnt, L, theta, G,
-                                                     err_tol);
+                                                     err_tol, k1h);
 }
 
 hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
                               uint32_t beg, uint32_t cnt, double L, double theta, double G,
-                              double err_tol, int order, bool fp32, hipStream_t s) {
+                              double err_tol, double k1h, int order, bool fp32, hipStream_t s) {
   if (cnt == 0) return hipSuccess;
-#define HOT_MOM(P)                                                                        \
-  case P:                                                                                 \
-    if (fp32)                                                                             \
-      moments_launch<P, float>(C, spos, smass, n, beg, cnt, L, theta, G, err_tol, s);     \
-    else                                                                                  \
-      moments_launch<P, double>(C, spos, smass, n, beg, cnt, L, theta, G, err_tol, s);    \
+#define HOT_MOM(P)                                                                          \
+  case P:                                                                                   \
+    if (fp32)                                                                               \
+      moments_launch<P, float>(C, spos, smass, n, beg, cnt, L, theta, G, err_tol, k1h, s);  \
+    else                                                                                    \
+      moments_launch<P, double>(C, spos, smass, n, beg, cnt, L, theta, G, err_tol, k1h, s); \
     break;
   switch (order) {
     HOT_MOM(0)

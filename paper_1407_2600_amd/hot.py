@@ -38,7 +38,7 @@ class hot_params(C.Structure):
     _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
                 ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
-                ("precision", C.c_int), ("err_tol", C.c_double)]
+                ("precision", C.c_int), ("err_tol", C.c_double), ("kernel", C.c_int)]
 
 
 class hot_stats(C.Structure):
@@ -116,14 +116,19 @@ def check(status: int):
         raise HotError(status, lib().hot_last_error().decode())
 
 
+HOT_KERNEL_PLUMMER, HOT_KERNEL_K1 = 0, 1
+KERNELS = {"plummer": HOT_KERNEL_PLUMMER, "k1": HOT_KERNEL_K1, 0: 0, 1: 1}
+
+
 def make_params(box=1.0, G=1.0, eps=0.0, theta=0.5, order=4, periodic=1, leaf_max=16,
-                group_max=64, far_order=8, precision="fp64", err_tol=0.0,
+                group_max=64, far_order=8, precision="fp64", err_tol=0.0, kernel="plummer",
                 **_ignored) -> hot_params:
     prec = precision
     if isinstance(prec, str):
         prec = {"fp64": HOT_FP64, "fp32": HOT_FP32}[prec]
     return hot_params(float(box), float(G), float(eps), float(theta), int(order), int(periodic),
-                      int(leaf_max), int(group_max), int(far_order), int(prec), float(err_tol))
+                      int(leaf_max), int(group_max), int(far_order), int(prec), float(err_tol),
+                      KERNELS[kernel])
 
 
 def far_table(far_order: int, box: float = 1.0, offset: int = 13):

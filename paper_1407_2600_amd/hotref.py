@@ -9,7 +9,8 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhotref.so")
-EXPORTED = ["hotref_scratch_size", "hotref_ewald", "hotref_last_error"]
+EXPORTED = ["hotref_scratch_size", "hotref_ewald", "hotref_valu_probe_scratch",
+            "hotref_valu_probe", "hotref_last_error"]
 
 _lib = None
 
@@ -27,6 +28,10 @@ def lib():
         L.hotref_ewald.argtypes = [sz, vp, vp, C.c_int, sz, vp, C.c_double, C.c_double,
                                    C.c_double, vp, vp, vp, sz, vp]
         L.hotref_last_error.restype = C.c_char_p
+        L.hotref_valu_probe_scratch.restype = sz
+        L.hotref_valu_probe.restype = C.c_int
+        L.hotref_valu_probe.argtypes = [C.c_int, vp, sz, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -63,3 +68,25 @@ def ewald_reference(pos, mass, targets, box=1.0, G=1.0, eps=0.0):
     torch.cuda.current_stream(dev).synchronize()
     del scratch
     return acc, pot
+
+
+PROBE_KINDS = {0: "fp32 fma", 1: "fp32 mul", 2: "fp32 add", 3: "fp32 fma/mul/add",
+               4: "fp32 fma + rsq per 16", 5: "fp64 fma", 6: "fp32 fma accumulate"}
+
+
+def valu_probe(repeats: int = 5) -> dict:
+    """Wave instructions per second of each probe kind on the current GPU."""
+    import torch
+    L = lib()
+    buf = torch.empty(L.hotref_valu_probe_scratch(), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for kind, name in PROBE_KINDS.items():
+        ms, wi = C.c_double(), C.c_double()
+        st = L.hotref_valu_probe(kind, C.c_void_p(buf.data_ptr()), buf.numel(), int(repeats),
+                                 C.byref(ms), C.byref(wi))
+        if st != 0:
+            raise RuntimeError(f"hotref_valu_probe({kind}) failed ({st})")
+        out[name] = {"ms": ms.value, "wave_instructions": wi.value,
+                     "wave_instr_per_s": wi.value / (ms.value * 1e-3)}
+    return out

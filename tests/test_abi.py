@@ -59,13 +59,17 @@ def test_version_and_error_strings():
                                  dict(eps=-1.0), dict(leaf_max=0), dict(far_order=13),
                                  dict(periodic=2), dict(precision=7), dict(group_max=0),
                                  dict(err_tol=-1e-3), dict(err_tol=float("nan")),
-                                 dict(err_tol=float("inf"))])
+                                 dict(err_tol=float("inf")), dict(kernel=2),
+                                 dict(kernel="k1", eps=0.0)])
 def test_create_rejects_bad_parameters(bad):
     L = hot.lib()
     prm = hot.make_params(**dict(dict(eps=0.01), **{k: v for k, v in bad.items()
-                                                    if k != "precision"}))
+                                                    if k not in ("precision", "kernel") or
+                                                    v in hot.KERNELS}))
     if "precision" in bad:
         prm.precision = bad["precision"]
+    if bad.get("kernel") not in (None, *hot.KERNELS):
+        prm.kernel = bad["kernel"]
     h = C.c_void_p(123)
     st = L.hot_create(C.byref(prm), C.byref(h))
     assert st == hot.HOT_EINVAL
