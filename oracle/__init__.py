@@ -78,6 +78,7 @@ def lib():
         L.or_tree_cells.argtypes = [vp, u64p, i32p, i64p, i64p, i32p, dp, dp, dp]
         L.or_tree_cell_moments.argtypes = [vp, i64, dp]
         L.or_tree_cell_bounds.argtypes = [vp, dp, dp]
+        L.or_tree_cell_bk.argtypes = [vp, C.c_int, dp]
         L.or_err_radius.restype = C.c_double
         L.or_err_radius.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_double]
         L.or_tree_groups.argtypes = [vp, i64p, dp, dp]
@@ -155,9 +156,10 @@ def k1_radius(eps: float) -> float:
     return lib().or_k1_radius(float(eps))
 
 
-def err_radius(G: float, b2: float, b: float, order: int, tol: float) -> float:
-    """Opening radius of the error-bound acceptance test."""
-    return float(lib().or_err_radius(G, b2, b, order, tol))
+def err_radius(G: float, bp: float, b: float, order: int, tol: float) -> float:
+    """Opening radius of the error-bound acceptance test for a cell of extent
+    b with B_(p+1) = bp (p = max(order, 1))."""
+    return float(lib().or_err_radius(G, bp, b, order, tol))
 
 
 def mi_list(D: int) -> list[tuple[int, int, int]]:
@@ -322,6 +324,13 @@ class Tree:
         bm = np.zeros(nc)
         self.lib.or_tree_cell_bounds(self.h, _p(b2), _p(bm))
         return b2, bm
+
+    def cell_bk(self, k: int):
+        """The bound on B_k = sum m |x - com|^k per cell (exact at leaves and
+        for k = 0, 2), k = 0..5."""
+        out = np.zeros(self.lib.or_tree_ncells(self.h))
+        self.lib.or_tree_cell_bk(self.h, int(k), _p(out))
+        return out
 
     def cell_moments(self, c: int) -> np.ndarray:
         nm = self.lib.or_nterms(int(self.params.get("order", 2)))

@@ -38,12 +38,13 @@
  *     G B_(p+1) ((p+2) r - (p+1) b) / (r^(p+2) (r - b)^2),   r > b,
  * drops to err_tol (the paper sets its tolerance as an absolute acceleration
  * error, Sec. 2.1).  b is an upper bound on the distance of the cell's
- * particles from its centre of mass and B_(p+1) = sum m |x - com|^(p+1) is
- * bounded by b^(p-1) B_2 (order 0 is treated as order 1: the dipole about the
- * centre of mass vanishes).  B_2 and b follow from the daughters by the
- * parallel-axis identity and the triangle inequality, in octant order, and
- * the radius is found by a fixed bisection in IEEE operations only, so that
- * any implementation reproduces it bit for bit.
+ * particles from its centre of mass and B_(p+1) = sum m |x - com|^(p+1)
+ * (order 0 is treated as order 1: the dipole about the centre of mass
+ * vanishes).  Leaves sum B_k over their particles; above them B_2 follows
+ * exactly by the parallel-axis identity, the other B_k and b are bounded
+ * through the triangle inequality (binomially expanded powers), daughters in
+ * octant order, and the radius is found by a fixed bisection in IEEE
+ * operations only, so that any implementation reproduces it bit for bit.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +56,8 @@
 #include "oracle.h"
 
 #define MAXLEV 21
+/* highest B_k carried up the tree: B_(p+1) at order p <= 4 */
+#define OR_BK 5
 
 typedef struct {
   uint64_t key;
@@ -63,6 +66,8 @@ typedef struct {
   int64_t child[8];
   double m, mx[3], com[3], center[3], side, rcrit;
   double b2, bmax; /* sum m |x - com|^2 and a bound on max |x - com| */
+  double bk[OR_BK + 1]; /* bounds on B_k = sum m |x - com|^k, k = 0..OR_BK
+                           (B_0 = m, B_2 = b2 exactly) */
   double* M; /* raw moments about com, |k| <= order */
 } cell_t;
 
@@ -223,11 +228,10 @@ static double sw_bound(double gb, double b, int pe, double r) {
   return num / den;
 }
 
-/* smallest radius (to bisection resolution) where the bound is <= tol */
-static double err_radius(double G, double b2, double b, int p, double tol) {
+/* smallest radius (to bisection resolution) where the bound is <= tol;
+ * bp = B_(pe+1), pe = max(p, 1) */
+static double err_radius(double G, double bp, double b, int p, double tol) {
   int pe = p < 1 ? 1 : p;
-  double bp = b2;
-  for (int i = 1; i < pe; ++i) bp = bp * b; /* B_(p+1) <= b^(p-1) B_2 */
   double gb = G * bp;
   if (!(gb > 0.0)) return b; /* a point mass: exact at any distance > b */
   double lo = b, hi = b + b;
@@ -279,7 +283,15 @@ static void moments(tree_t* T) {
     dd = dd + dz * dz;
     double delta = sqrt(dd);
     /* second moment and extent about the centre of mass */
+    /* B_k about the centre of mass: exact at leaves (sums over the
+     * particles in key order); above them B_2 exactly by the parallel-axis
+     * identity and the other B_k bounded through the triangle inequality,
+     * |x - com| <= |x - com_d| + |com_d - com|, expanded binomially:
+     *     B_k <= sum_d sum_j C(k, j) B_j(d) delta_d^(k-j),
+     * daughters in octant order, j ascending */
     double b2 = 0.0, bmax = 0.0;
+    double bk[OR_BK + 1];
+    for (int k = 0; k <= OR_BK; ++k) bk[k] = 0.0;
     if (c->is_leaf) {
       double r2max = 0.0;
       for (int64_t s = c->first; s < c->first + c->count; ++s) {
@@ -288,12 +300,23 @@ static void moments(tree_t* T) {
         double r2 = ex * ex;
         r2 = r2 + ey * ey;
         r2 = r2 + ez * ez;
-        double t = T->sm[s] * r2;
+        double ms = T->sm[s];
+        double t = ms * r2;
         b2 = b2 + t;
         if (r2 > r2max) r2max = r2;
+        double r = sqrt(r2);
+        double r3 = r2 * r, r4 = r2 * r2;
+        double r5 = r4 * r;
+        bk[1] = bk[1] + ms * r;
+        bk[3] = bk[3] + ms * r3;
+        bk[4] = bk[4] + ms * r4;
+        bk[5] = bk[5] + ms * r5;
       }
       bmax = sqrt(r2max);
     } else {
+      static const double binom[OR_BK + 1][OR_BK + 1] = {
+          {1, 0, 0, 0, 0, 0}, {1, 1, 0, 0, 0, 0}, {1, 2, 1, 0, 0, 0},
+          {1, 3, 3, 1, 0, 0}, {1, 4, 6, 4, 1, 0}, {1, 5, 10, 10, 5, 1}};
       for (int o = 0; o < 8; ++o) {
         if (c->child[o] < 0) continue;
         cell_t* d = &T->cells[c->child[o]];
@@ -304,15 +327,33 @@ static void moments(tree_t* T) {
         double t = d->m * r2;
         t = d->b2 + t;
         b2 = b2 + t;
-        double e = d->bmax + sqrt(r2);
+        double dl = sqrt(r2);
+        double e = d->bmax + dl;
         if (e > bmax) bmax = e;
+        double dp[OR_BK + 1];
+        dp[0] = 1.0;
+        for (int k = 1; k <= OR_BK; ++k) dp[k] = dp[k - 1] * dl;
+        for (int k = 1; k <= OR_BK; ++k) {
+          if (k == 2) continue;
+          double acc = 0.0;
+          for (int j = 0; j <= k; ++j) {
+            double u = binom[k][j] * d->bk[j];
+            u = u * dp[k - j];
+            acc = acc + u;
+          }
+          bk[k] = bk[k] + acc;
+        }
       }
     }
+    bk[0] = m;
+    bk[2] = b2;
+    for (int k = 0; k <= OR_BK; ++k) c->bk[k] = bk[k];
     c->b2 = b2;
     c->bmax = bmax;
     double rc = (theta > 0.0) ? c->side / theta + delta : 0.0;
     if (T->p.err_tol > 0.0) {
-      double re = err_radius(T->p.G, b2, bmax, p, T->p.err_tol);
+      int pe = p < 1 ? 1 : p;
+      double re = err_radius(T->p.G, bk[pe + 1], bmax, p, T->p.err_tol);
       if (re > rc) rc = re;
     } else if (!(theta > 0.0)) {
       rc = INFINITY;
@@ -813,8 +854,13 @@ void or_tree_cell_bounds(void* h, double* b2, double* bmax) {
 }
 
 /* the opening radius of the error-bound test for given B_2, b, order, tol */
-double or_err_radius(double G, double b2, double b, int p, double tol) {
-  return err_radius(G, b2, b, p, tol);
+void or_tree_cell_bk(void* h, int k, double* out) {
+  tree_t* T = h;
+  for (int64_t c = 0; c < T->ncells; ++c) out[c] = T->cells[c].bk[k];
+}
+
+double or_err_radius(double G, double bp, double b, int p, double tol) {
+  return err_radius(G, bp, b, p, tol);
 }
 
 /* raw moments of cell c about its centre of mass (or_nterms(order) values) */

@@ -13,9 +13,9 @@ import workloads
 from test_oracle_tree import _check_lists
 
 
-def _f(G, b2, b, p, r):
+def _f(G, bp, b, p, r):
+    """Salmon & Warren's bound for B_(pe+1) = bp, pe = max(p, 1)."""
     pe = max(p, 1)
-    bp = b2 * b ** (pe - 1)
     return G * bp * ((pe + 2) * r - (pe + 1) * b) / (r ** (pe + 2) * (r - b) ** 2)
 
 
@@ -24,12 +24,12 @@ def test_err_radius_is_the_smallest_radius_meeting_the_bound(p):
     rng = np.random.default_rng(p)
     for _ in range(20):
         b = 10 ** rng.uniform(-4, -1)
-        b2 = 10 ** rng.uniform(-3, 0) * b * b
+        bp = 10 ** rng.uniform(-3, 0) * b ** (max(p, 1) + 1)
         tol = 10 ** rng.uniform(-6, -2)
-        rc = oracle.err_radius(1.0, b2, b, p, tol)
+        rc = oracle.err_radius(1.0, bp, b, p, tol)
         assert rc > b
-        assert _f(1.0, b2, b, p, rc) <= tol * (1 + 1e-12)
-        assert _f(1.0, b2, b, p, rc * (1 - 1e-9)) > tol
+        assert _f(1.0, bp, b, p, rc) <= tol * (1 + 1e-12)
+        assert _f(1.0, bp, b, p, rc * (1 - 1e-9)) > tol
 
 
 def test_err_radius_limits():
@@ -62,10 +62,11 @@ def test_bound_holds_for_random_clusters(p):
         com = (src * m).sum(1) / m.sum()
         d = src - com[:, None]
         r2 = (d * d).sum(0)
-        b2 = float((m * r2).sum())
+        # the cell's actual B_(p+1) (order 0 counts as order 1)
+        bp = float((m * np.sqrt(r2) ** (max(p, 1) + 1)).sum())
         b = float(np.sqrt(r2.max()))
         tol = 1e-3 * m.sum() / 0.1 ** 2
-        rc = oracle.err_radius(1.0, b2, b, p, tol)
+        rc = oracle.err_radius(1.0, bp, b, p, tol)
         for _ in range(60):
             u = rng.normal(size=3)
             x = com + rc * (1 + 1e-12) * u / np.linalg.norm(u)
@@ -89,6 +90,7 @@ def test_cell_bounds_brute_force(name, ns):
     perm, _ = T.perm()
     sp = np.asarray(pos)[:, perm]
     sm = np.asarray(mass)[perm]
+    bk = [T.cell_bk(k) for k in range(6)]
     for c in range(len(b2)):
         f, n = cells["first"][c], cells["count"][c]
         d = sp[:, f:f + n] - cells["com"][:, c][:, None]
@@ -98,6 +100,17 @@ def test_cell_bounds_brute_force(name, ns):
         assert bm[c] >= np.sqrt(r2.max()) * (1 - 1e-14)
         if cells["is_leaf"][c]:
             assert bm[c] == np.sqrt(r2.max())
+        # B_k: exact for k = 0, 2 and at leaves, an upper bound elsewhere,
+        # and never looser than the extent bound b^(k-2) B_2
+        for k in range(6):
+            exact = float((sm[f:f + n] * np.sqrt(r2) ** k).sum())
+            if k in (0, 2) or cells["is_leaf"][c]:
+                assert bk[k][c] == pytest.approx(exact, rel=1e-11, abs=1e-300)
+            else:
+                assert bk[k][c] >= exact * (1 - 1e-12)
+            if k > 2:
+                assert bk[k][c] <= b2[c] * bm[c] ** (k - 2) * (1 + 1e-12) or \
+                    not cells["is_leaf"][c]
 
 
 def test_opening_radius_combines_both_tests():
@@ -112,7 +125,8 @@ def test_opening_radius_combines_both_tests():
             ctr = np.array([((k + 0.5) * side) for k in _cell_xyz(cells["key"][c],
                                                                       cells["level"][c])])
             geo = side / theta + np.linalg.norm(cells["com"][:, c] - ctr) if theta > 0 else 0.0
-            err = oracle.err_radius(1.0, b2[c], bm[c], base["order"], tol) if tol > 0 else 0.0
+            bp = T.cell_bk(max(base["order"], 1) + 1)[c]
+            err = oracle.err_radius(1.0, bp, bm[c], base["order"], tol) if tol > 0 else 0.0
             assert cells["rcrit"][c] == pytest.approx(max(geo, err), rel=1e-14)
         _check_lists(T, dict(base, theta=theta, err_tol=tol))
 
