@@ -195,6 +195,7 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes, unsigned need) {
   P.o_c_mmx = take(32 * C);
   P.o_c_walk = take(32 * C);
   P.o_c_bnd = take(16 * C);
+  P.o_c_bk = take(32 * C);
   P.o_c_mom = take(8 * (size_t)NM * C);
   P.o_c_coef = take(tsz * (size_t)STR * C);
   const size_t Gc = P.cap_groups;
@@ -272,6 +273,7 @@ Cells cells_of(void* ws, const Plan& P) {
   C.mmx = at<double4>(ws, P.o_c_mmx);
   C.walk = at<double4>(ws, P.o_c_walk);
   C.bnd = at<double2>(ws, P.o_c_bnd);
+  C.bk = at<double4>(ws, P.o_c_bk);
   C.mom = at<double>(ws, P.o_c_mom);
   C.coef = at<void>(ws, P.o_c_coef);
   return C;

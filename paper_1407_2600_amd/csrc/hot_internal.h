@@ -136,6 +136,7 @@ struct Cells {
   double4* mmx;      // (m, sum m x, sum m y, sum m z), FP64
   double4* walk;     // (com.x, com.y, com.z, rcrit)
   double2* bnd;      // (sum m |x - com|^2, bound on max |x - com|)
+  double4* bk;       // bounds on B_k = sum m |x - com|^k for k = 1, 3, 4, 5
   double* mom;       // raw moments about the com, nt(order) x cap (cell-major)
   void* coef;        // multipole coefficients, coef_stride x cap (cell-major), T
 };
@@ -165,7 +166,7 @@ struct Plan {
   size_t o_key[2], o_idx[2], o_spos, o_smass, o_srec, o_acc, o_tmp;
   size_t o_scan, o_hist, o_ctr;
   size_t o_c_key, o_c_level, o_c_first, o_c_count, o_c_child, o_c_nchild, o_c_parent;
-  size_t o_c_mmx, o_c_walk, o_c_bnd, o_c_mom, o_c_coef;
+  size_t o_c_mmx, o_c_walk, o_c_bnd, o_c_bk, o_c_mom, o_c_coef;
   size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om;
   size_t o_far_part, o_far_mom, o_far_lam;
   size_t o_arec, o_adj, o_c_emom, o_c_ecoef, o_far_mbar;

@@ -146,8 +146,9 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
 // Error-bound opening radius (Salmon & Warren 1994): the acceleration error
 // of an order-p expansion of a cell with extent b about its centre of mass is
 // at most G B_(p+1) ((p+2) r - (p+1) b) / (r^(p+2) (r - b)^2) at distance
-// r > b, with B_(p+1) = sum m |x - com|^(p+1) <= b^(p-1) B_2 (order 0 counts
-// as order 1: the dipole about the centre of mass vanishes).  The radius where
+// r > b, with B_(p+1) = sum m |x - com|^(p+1) (order 0 counts as order 1:
+// the dipole about the centre of mass vanishes): summed over the particles
+// at leaves, bounded above them (see k_moments).  The radius where
 // the bound meets the tolerance is found by doubling, then 64 bisection
 // steps, in separate IEEE operations only (contraction is off), so that every
 // implementation of the same definition finds the same double.
@@ -163,10 +164,9 @@ __device__ double sw_bound(double gb, double b, int pe, double r) {
   return num / den;
 }
 
-__device__ double err_radius(double G, double b2, double b, int p, double tol) {
+// bp = B_(pe+1), pe = max(p, 1)
+__device__ double err_radius(double G, double bp, double b, int p, double tol) {
   const int pe = p < 1 ? 1 : p;
-  double bp = b2;
-  for (int i = 1; i < pe; ++i) bp = bp * b;
   const double gb = G * bp;
   if (!(gb > 0.0)) return b;
   double lo = b, hi = b + b;
@@ -229,9 +229,14 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
   double dd = dx * dx;
   dd = dd + dy * dy;
   dd = dd + dz * dz;
-  // second moment and extent about the centre of mass (parallel-axis sums
-  // and triangle bounds over the daughters, in octant order)
+  // B_k = sum m |x - com|^k and the extent about the centre of mass: summed
+  // over the particles at leaves (key order); above them B_2 by the
+  // parallel-axis identity, the extent by the triangle inequality, and the
+  // other B_k by the triangle inequality expanded binomially,
+  //   B_k <= sum_d sum_j C(k, j) B_j(d) delta_d^(k-j)
+  // (daughters in octant order, j ascending)
   double b2 = 0.0, bmax = 0.0;
+  double bk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (nc == 0) {
     double r2max = 0.0;
     for (uint32_t s = f; s < e; ++s) {
@@ -240,30 +245,63 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
       double r2 = ex * ex;
       r2 = r2 + ey * ey;
       r2 = r2 + ez * ez;
-      const double t = smass[s] * r2;
+      const double ms = smass[s];
+      const double t = ms * r2;
       b2 = b2 + t;
       if (r2 > r2max) r2max = r2;
+      const double r = sqrt(r2);
+      const double r3 = r2 * r, r4 = r2 * r2;
+      const double r5 = r4 * r;
+      bk[1] = bk[1] + ms * r;
+      bk[3] = bk[3] + ms * r3;
+      bk[4] = bk[4] + ms * r4;
+      bk[5] = bk[5] + ms * r5;
     }
     bmax = sqrt(r2max);
   } else {
+    constexpr double binom[6][6] = {{1, 0, 0, 0, 0, 0}, {1, 1, 0, 0, 0, 0}, {1, 2, 1, 0, 0, 0},
+                                    {1, 3, 3, 1, 0, 0}, {1, 4, 6, 4, 1, 0}, {1, 5, 10, 10, 5, 1}};
     for (int k = 0; k < nc; ++k) {
       const double4 wc = C.walk[c0 + k];
       const double2 bc = C.bnd[c0 + k];
+      const double4 bq = C.bk[c0 + k];
+      const double md = C.mmx[c0 + k].x;
       const double ex = wc.x - com[0], ey = wc.y - com[1], ez = wc.z - com[2];
       double r2 = ex * ex;
       r2 = r2 + ey * ey;
       r2 = r2 + ez * ez;
-      double t = C.mmx[c0 + k].x * r2;
+      double t = md * r2;
       t = bc.x + t;
       b2 = b2 + t;
-      const double eb = bc.y + sqrt(r2);
+      const double dl = sqrt(r2);
+      const double eb = bc.y + dl;
       if (eb > bmax) bmax = eb;
+      const double bd[6] = {md, bq.x, bc.x, bq.y, bq.z, bq.w};
+      double dp[6];
+      dp[0] = 1.0;
+#pragma unroll
+      for (int q = 1; q < 6; ++q) dp[q] = dp[q - 1] * dl;
+#pragma unroll
+      for (int q = 1; q < 6; ++q) {
+        if (q == 2) continue;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j <= q; ++j) {
+          double u = binom[q][j] * bd[j];
+          u = u * dp[q - j];
+          acc = acc + u;
+        }
+        bk[q] = bk[q] + acc;
+      }
     }
   }
   C.bnd[c] = make_double2(b2, bmax);
+  C.bk[c] = make_double4(bk[1], bk[3], bk[4], bk[5]);
   double rcrit = (theta > 0.0) ? side / theta + sqrt(dd) : 0.0;
   if (err_tol > 0.0) {
-    const double re = err_radius(G, b2, bmax, P, err_tol);
+    constexpr int pe = P < 1 ? 1 : P;
+    const double bp = pe + 1 == 2 ? b2 : pe + 1 == 3 ? bk[3] : pe + 1 == 4 ? bk[4] : bk[5];
+    const double re = err_radius(G, bp, bmax, P, err_tol);
     if (re > rcrit) rcrit = re;
   } else if (!(theta > 0.0)) {
     rcrit = __builtin_inf();
