@@ -39,8 +39,9 @@
  *    hot_destroy.
  *  - Calls are enqueued on the caller's HIP stream (hipStream_t passed as
  *    void*; NULL = the default stream).  A compute call synchronises that
- *    stream a few times to size its launches (tree levels, list totals) and
- *    returns after the last kernel is enqueued; outputs are ready once the
+ *    stream to size its launches: once per tree level (the next level's
+ *    cell count), after the sink groups and after the walk's count pass
+ *    (group and list totals); it returns after the last kernel is enqueued; outputs are ready once the
  *    stream is synchronised.  The force kernels' tail passes (the last <= 32
  *    targets of a sink group) run on the context's second stream, which
  *    waits for the caller's stream through an event before them, and the
@@ -336,6 +337,22 @@ hot_status hot_debug_sizes(const hot_ctx* ctx, int64_t* n, int64_t* ncells, int6
  * list buffers are requested after a call that processed its lists in chunks
  * (hot_stats.list_chunks > 1). */
 hot_status hot_debug_export(hot_ctx* ctx, void* workspace, hot_debug* out);
+
+/* Look up cells by key in the hashed oct-tree of the last force evaluation
+ * (paper Sec. 2.1: a key is translated into its cell's storage through a
+ * hash table).  Every evaluation builds the table from its cells: open
+ * addressing, linear probing, at least twice as many slots as cells.
+ *   workspace  the workspace of that evaluation, still holding its contents
+ *   keys       device, nq uint64 cell keys (Morton key with placeholder bit:
+ *              root 1, daughter = parent << 3 | octant)
+ *   cells      device, nq int32, written: the cell's index in the library's
+ *              cell order (the order of hot_debug's cell arrays), or -1 if
+ *              the tree has no such cell
+ * Enqueued on stream; results are ready once it is synchronised.
+ * HOT_EINVAL if no evaluation preceded, on NULL pointers with nq > 0, or if
+ * workspace is not the last evaluation's. */
+hot_status hot_cell_lookup(hot_ctx* ctx, void* workspace, size_t nq, const uint64_t* keys,
+                           int32_t* cells, void* stream);
 
 /* Copy count interaction-list entries of the last hot_forces call, starting
  * at entry first of the whole list of the given kind (0 = direct, 1 =

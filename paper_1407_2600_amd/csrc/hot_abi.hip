@@ -26,6 +26,10 @@ hipError_t tree_split_level(const Cells& C, const uint64_t* skey, uint32_t beg, 
 hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, uint32_t cnt,
                            int level, int leaf_max, const uint32_t* choff, uint32_t next,
                            uint32_t cap, hipStream_t s);
+hipError_t tree_hash_build(const Cells& C, uint32_t ncells, uint64_t* hkey, uint32_t* hval,
+                           size_t hcap, hipStream_t s);
+hipError_t hash_lookup(const uint64_t* hkey, const uint32_t* hval, size_t hcap, const uint64_t* q,
+                       size_t nq, int32_t* out, hipStream_t s);
 hipError_t tree_moments_level(const Cells& C, const double* spos, const double* smass, size_t n,
                               uint32_t beg, uint32_t cnt, double L, double theta, double G,
                               double err_tol, double k1h, int order,
@@ -121,7 +125,7 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // words of the context's pinned host buffer that receive the pair counters
 // (two u64) at the end of every evaluation
-constexpr int kHostPairs = 48;
+constexpr int kHostPairs = 56;
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
        CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
@@ -198,6 +202,11 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes, unsigned need) {
   P.o_c_bk = take(32 * C);
   P.o_c_mom = take(8 * (size_t)NM * C);
   P.o_c_coef = take(tsz * (size_t)STR * C);
+  // key -> cell hash: a power of two of slots, at least twice the cells
+  P.hcap = 1024;
+  while (P.hcap < 2 * C) P.hcap <<= 1;
+  P.o_h_key = take(8 * P.hcap);
+  P.o_h_val = take(4 * P.hcap);
   const size_t Gc = P.cap_groups;
   P.o_g_cell = take(4 * Gc);
   P.o_g_lo = take(24 * Gc);
@@ -427,6 +436,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     nlev = l + 2;
   }
   ncells = lvl[nlev];
+  HOT_CHECK(tree_hash_build(C, ncells, at<uint64_t>(ws, P.o_h_key), at<uint32_t>(ws, P.o_h_val),
+                            P.hcap, s),
+            "key hash");
   // K1: cells are accepted only beyond their extent plus the kernel radius
   const double k1h = p.kernel == HOT_KERNEL_K1 ? k1_radius(p.eps) : -1.0;
   for (int l = nlev - 1; l >= 0; --l)
@@ -1110,6 +1122,28 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
       for (size_t i = 0; i < tm; ++i) oent[i] = rec[4 * i + 3];
     }
   }
+  return HOT_OK;
+}
+
+hot_status hot_cell_lookup(hot_ctx* c, void* ws, size_t nq, const uint64_t* keys, int32_t* cells,
+                           void* stream) {
+  if (!c || !c->have_last || !ws) {
+    g_err = "no previous force evaluation or NULL workspace";
+    return HOT_EINVAL;
+  }
+  if (nq == 0) return HOT_OK;
+  if (!keys || !cells) {
+    g_err = "NULL pointer argument";
+    return HOT_EINVAL;
+  }
+  if (ws != c->last_ws) {
+    g_err = "the workspace is not that of the last evaluation";
+    return HOT_EINVAL;
+  }
+  const Plan& P = c->last_plan;
+  HOT_CHECK(hash_lookup(at<uint64_t>(ws, P.o_h_key), at<uint32_t>(ws, P.o_h_val), P.hcap, keys, nq,
+                        cells, (hipStream_t)stream),
+            "key lookup");
   return HOT_OK;
 }
 

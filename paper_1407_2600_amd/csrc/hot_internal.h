@@ -167,6 +167,7 @@ struct Plan {
   size_t o_scan, o_hist, o_ctr;
   size_t o_c_key, o_c_level, o_c_first, o_c_count, o_c_child, o_c_nchild, o_c_parent;
   size_t o_c_mmx, o_c_walk, o_c_bnd, o_c_bk, o_c_mom, o_c_coef;
+  size_t hcap, o_h_key, o_h_val;  // key -> cell hash (slots, key and value arrays)
   size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om;
   size_t o_far_part, o_far_mom, o_far_lam;
   size_t o_arec, o_adj, o_c_emom, o_c_ecoef, o_far_mbar;

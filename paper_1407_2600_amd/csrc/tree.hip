@@ -7,7 +7,8 @@
 // binary search for the octal digit boundaries inside its contiguous sorted
 // range.  Cells are stored level-major; the daughters of a cell are
 // contiguous and in octant order, so the octant-ordered sums below need no
-// sorting.
+// sorting.  A hash table from key to cell (the paper's hashed oct-tree) is
+// filled once the cells are known.
 //
 // Moments, bottom-up: cell mass and sum m x in FP64 with separate multiply
 // and add (leaves sum their particles in key order, internal cells their
@@ -16,6 +17,8 @@
 // of mass (leaves directly, internal cells by shifting the daughters'
 // moments).  From the raw moments each cell derives the coefficient block its
 // multipole interactions use.
+#include <algorithm>
+
 #include "device_math.h"
 
 namespace hot {
@@ -140,6 +143,70 @@ __global__ void __launch_bounds__(256) k_split_emit(Cells C, const uint64_t* __r
     C.child[c] = (int32_t)out;
     C.nchild[c] = (int32_t)__popc(r.mask);
   }
+}
+
+// ----------------------------------------------------------- key -> cell hash
+// The hashed oct-tree (paper Sec. 2.1): a table from a cell's key to its
+// index, open addressing with linear probing over a power-of-two number of
+// slots (at least twice the cells).  An empty slot holds key 0, which no cell
+// has (every key carries the placeholder bit).  Insertion is one thread per
+// cell with a compare-and-swap on the slot's key; slots are therefore filled
+// in no fixed order, but every key maps to its one cell.
+__device__ __forceinline__ uint64_t key_hash(uint64_t k) {
+  // a 64-bit finaliser (xor-shift and odd-constant multiply rounds)
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__global__ void __launch_bounds__(256) k_hash_clear(uint64_t* __restrict__ hkey, size_t hcap) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < hcap;
+       i += (size_t)gridDim.x * 256)
+    hkey[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(256) k_hash_insert(Cells C, uint32_t ncells,
+                                                     unsigned long long* hkey,
+                                                     uint32_t* __restrict__ hval, uint64_t mask) {
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncells) return;
+  const unsigned long long k = C.key[c];
+  uint64_t h = key_hash(k) & mask;
+  for (uint64_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long prev = atomicCAS(hkey + h, 0ull, k);
+    if (prev == 0ull || prev == k) {
+      hval[h] = c;
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hash_lookup(const uint64_t* __restrict__ hkey,
+                                                     const uint32_t* __restrict__ hval,
+                                                     uint64_t mask,
+                                                     const uint64_t* __restrict__ q, size_t nq,
+                                                     int32_t* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nq) return;
+  const uint64_t k = q[i];
+  int32_t r = -1;
+  if (k != 0ull) {
+    uint64_t h = key_hash(k) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+      const uint64_t s = hkey[h];
+      if (s == k) {
+        r = (int32_t)hval[h];
+        break;
+      }
+      if (s == 0ull) break;
+      h = (h + 1) & mask;
+    }
+  }
+  out[i] = r;
 }
 
 // ------------------------------------------------------------------ moments
@@ -441,6 +508,24 @@ hipError_t tree_emit_level(const Cells& C, const uint64_t* skey, uint32_t beg, u
                            uint32_t cap, hipStream_t s) {
   const unsigned g = (unsigned)((8 * (size_t)cnt + 255) / 256);  // eight lanes per cell
   k_split_emit<<<g, 256, 0, s>>>(C, skey, beg, cnt, level, leaf_max, choff, next, cap);
+  return hipGetLastError();
+}
+
+hipError_t tree_hash_build(const Cells& C, uint32_t ncells, uint64_t* hkey, uint32_t* hval,
+                           size_t hcap, hipStream_t s) {
+  const unsigned gc = (unsigned)std::min<size_t>((hcap + 255) / 256, 65536);
+  k_hash_clear<<<gc, 256, 0, s>>>(hkey, hcap);
+  if (ncells)
+    k_hash_insert<<<(ncells + 255) / 256, 256, 0, s>>>(C, ncells, (unsigned long long*)hkey, hval,
+                                                       (uint64_t)hcap - 1);
+  return hipGetLastError();
+}
+
+hipError_t hash_lookup(const uint64_t* hkey, const uint32_t* hval, size_t hcap, const uint64_t* q,
+                       size_t nq, int32_t* out, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  k_hash_lookup<<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(hkey, hval, (uint64_t)hcap - 1, q, nq,
+                                                             out);
   return hipGetLastError();
 }
 

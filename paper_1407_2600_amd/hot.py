@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
             "hot_forces", "hot_forces_noalloc", "hot_kdk",
             "hot_vjp", "hot_vjp_after_forces", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
-            "hot_debug_list_range", "hot_last_error", "hot_version", "hot_far_table"]
+            "hot_debug_list_range", "hot_cell_lookup", "hot_last_error", "hot_version",
+            "hot_far_table"]
 
 
 class HotError(RuntimeError):
@@ -101,6 +102,8 @@ def lib():
         L.hot_debug_sizes.argtypes = [vp] + [C.POINTER(C.c_int64)] * 5
         L.hot_debug_export.restype = C.c_int
         L.hot_debug_export.argtypes = [vp, vp, C.POINTER(hot_debug)]
+        L.hot_cell_lookup.restype = C.c_int
+        L.hot_cell_lookup.argtypes = [vp, vp, sz, vp, vp, vp]
         L.hot_debug_list_range.restype = C.c_int
         L.hot_debug_list_range.argtypes = [vp, vp, C.c_int, C.c_int64, C.c_int64, vp]
         L.hot_last_error.restype = C.c_char_p
@@ -345,6 +348,18 @@ class Gravity:
         st = hot_stats()
         check(self.L.hot_get_stats(self.h, C.byref(st)))
         return st.as_dict()
+
+    def cell_lookup(self, keys):
+        """Cell index (library order) of each key in the last evaluation's
+        hashed oct-tree, -1 where the tree has no such cell.  keys: int64
+        tensor on the device holding the uint64 key bit patterns."""
+        t = self.torch
+        keys = keys.to(self.device, dtype=t.int64).contiguous()
+        out = t.empty(keys.numel(), dtype=t.int32, device=self.device)
+        check(self.L.hot_cell_lookup(self.h, C.c_void_p(self.ws.data_ptr()), keys.numel(),
+                                     C.c_void_p(keys.data_ptr()), C.c_void_p(out.data_ptr()),
+                                     self._stream()))
+        return out
 
     def debug_list_range(self, kind: int, first: int, count: int):
         """count entries of the last forces() call's direct (kind 0) or
