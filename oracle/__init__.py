@@ -455,6 +455,70 @@ def kdk(pos, vel, mass, params: dict, dt: float, nsteps: int, acc=None):
     return pos, vel, acc, pot
 
 
+def rung_of(acc, dt: float, max_rung: int, eta: float, eps: float):
+    """Block-timestep rung of each particle from its acceleration: the
+    largest step dt/2^r, r <= max_rung, not above eta sqrt(eps/|a|) (the
+    acceleration criterion of multiple-timestep tree codes)."""
+    acc = np.asarray(acc, dtype=np.float64)
+    a2 = acc[0] * acc[0]
+    a2 = a2 + acc[1] * acc[1]
+    a2 = a2 + acc[2] * acc[2]
+    with np.errstate(divide="ignore"):
+        want = eta * np.sqrt(eps / np.sqrt(a2))
+    r = np.zeros(acc.shape[1], dtype=np.int64)
+    for k in range(max_rung):
+        r += (np.ldexp(dt, -r) > want) & (r == k)
+    return r
+
+
+def _ctz(q: int) -> int:
+    return (q & -q).bit_length() - 1
+
+
+def kdk_block(pos, vel, mass, params: dict, dt: float, max_rung: int, eta: float, nsteps: int,
+              acc=None, pot=None, rung=None, fixed: bool = False):
+    """Block (multiple) timesteps, the paper's adaptive symplectic integrator
+    (Sec. 2.1) read as hierarchical kick-drift-kick on power-of-two rungs:
+    particle i steps dt/2^rung_i; time advances in substeps dt/2^max_rung
+    through which every particle drifts; at each substep boundary the
+    particles whose step ends there take their new acceleration, a closing
+    half kick and (unless fixed) a new rung no coarser than the steps that
+    can start there; the particles starting a step take an opening half
+    kick.  Returns (pos, vel, acc, pot, rung)."""
+    box = float(params.get("box", 1.0))
+    periodic = int(params.get("periodic", 1))
+    eps = float(params.get("eps", 0.0))
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    if acc is None:
+        acc, pot = Tree(pos, mass, params).forces()
+    acc = np.array(acc, dtype=np.float64)
+    pot = None if pot is None else np.array(pot, dtype=np.float64)
+    rung = (rung_of(acc, dt, max_rung, eta, eps) if rung is None
+            else np.array(rung, dtype=np.int64))
+    S = 1 << max_rung
+    sub = np.ldexp(dt, -max_rung)
+    for _ in range(nsteps):
+        for q in range(S):
+            rstart = 0 if q == 0 else max_rung - _ctz(q)
+            m = rung >= rstart
+            vel[:, m] = vel[:, m] + acc[:, m] * (0.5 * np.ldexp(dt, -rung[m]))
+            pos = pos + vel * sub
+            if periodic:
+                pos = wrap_box(pos, box)
+            rend = 0 if q + 1 == S else max_rung - _ctz(q + 1)
+            a_new, p_new = Tree(pos, mass, params).forces()
+            m = rung >= rend
+            acc[:, m] = a_new[:, m]
+            if pot is None:
+                pot = np.zeros(pos.shape[1])
+            pot[m] = p_new[m]
+            vel[:, m] = vel[:, m] + acc[:, m] * (0.5 * np.ldexp(dt, -rung[m]))
+            if not fixed:
+                rung[m] = np.maximum(rung_of(acc[:, m], dt, max_rung, eta, eps), rend)
+    return pos, vel, acc, pot, rung
+
+
 def kdk_trajectory(pos, vel, mass, params: dict, dt: float, nsteps: int):
     """Positions at the start of every step and at the end, [x_0 .. x_n]
     (each 3 x N), and the final velocities, of ``kdk``."""
