@@ -11,8 +11,8 @@
  * high-order local expansions of the Ewald-summed remainder about the centres
  * of the box's 8 octants (Sec. 2.1, the p=8 periodic local expansion), which
  * also subtracts the uniform background density.  A kick-drift-kick step wraps the force
- * evaluation (Sec. 2.1 uses an adaptive symplectic integrator; this library
- * offers the fixed-step leapfrog).
+ * evaluation, with fixed steps or with power-of-two block timesteps (Sec. 2.1:
+ * the adaptive symplectic integrator).
  *
  * Conventions for every call
  * --------------------------
@@ -266,6 +266,40 @@ hot_status hot_forces_noalloc(hot_ctx* ctx, size_t n, const double* pos, const v
 hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* mass, void* acc,
                    void* pot, double dt, int nsteps, unsigned flags, void* workspace,
                    size_t ws_bytes, void* stream);
+
+/* Block (multiple) timesteps: nsteps steps of length dt of the paper's
+ * adaptive symplectic integrator (Sec. 2.1), read as hierarchical
+ * kick-drift-kick on power-of-two rungs.  Particle i advances in steps of
+ * dt / 2^rung[i], rung 0..max_rung; time moves in substeps of
+ * dt / 2^max_rung, through which every particle drifts.  At each substep
+ * boundary the particles whose step ends there get new accelerations (one
+ * force evaluation whose lists and kernels cover only the sink groups that
+ * hold such a particle; the tree is built from all particles at the current
+ * positions), a closing half kick, and, unless HOT_RUNG_FIXED, a new rung:
+ * the largest step dt / 2^r not above eta sqrt(eps / |a|), but no larger
+ * than the steps that can start at this boundary.  Particles starting a
+ * step get an opening half kick with their current acceleration.  A
+ * boundary where no particle is due only drifts (the largest rung is read
+ * back after every rung update, one stream synchronisation).  With fixed
+ * rungs the scheme is time-reversible; max_rung = 0 is hot_kdk's leapfrog.
+ *   pos, vel, mass, acc, pot  as hot_kdk (acc/pot of a particle are those of
+ *         its last force evaluation)
+ *   rung  device, n uint8, in/out: on entry the rungs if (flags &
+ *         HOT_RUNG_VALID), otherwise computed from acc first; on return the
+ *         rungs for the next step
+ *   dt    the step of rung 0; max_rung 0..16; eta > 0 the step parameter
+ * flags: HOT_ACC_VALID, HOT_RUNG_VALID, HOT_RUNG_FIXED.  The workspace must
+ * hold hot_workspace_size_min(ctx, n, HOT_CALL_FORCES).  Errors as
+ * hot_forces; after a failure pos, vel, acc and rung are undefined (no
+ * snapshot is kept; size the workspace with a hot_forces call on the same
+ * particles first).  hot_get_stats reports the last substep's force
+ * evaluation and the completed steps. */
+#define HOT_RUNG_VALID 4u
+#define HOT_RUNG_FIXED 8u
+hot_status hot_kdk_block(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* mass,
+                         void* acc, void* pot, uint8_t* rung, double dt, int max_rung, double eta,
+                         int nsteps, unsigned flags, void* workspace, size_t ws_bytes,
+                         void* stream);
 
 /* Vector-Jacobian product of hot_forces (an extension beyond the paper):
  * given cotangents gacc (3 x n) and gpot (n, or NULL for zero) of the

@@ -484,7 +484,8 @@ def kdk_block(pos, vel, mass, params: dict, dt: float, max_rung: int, eta: float
     particles whose step ends there take their new acceleration, a closing
     half kick and (unless fixed) a new rung no coarser than the steps that
     can start there; the particles starting a step take an opening half
-    kick.  Returns (pos, vel, acc, pot, rung)."""
+    kick.  A substep boundary where no particle is due only drifts.  Returns
+    (pos, vel, acc, pot, rung, force evaluations)."""
     box = float(params.get("box", 1.0))
     periodic = int(params.get("periodic", 1))
     eps = float(params.get("eps", 0.0))
@@ -498,6 +499,7 @@ def kdk_block(pos, vel, mass, params: dict, dt: float, max_rung: int, eta: float
             else np.array(rung, dtype=np.int64))
     S = 1 << max_rung
     sub = np.ldexp(dt, -max_rung)
+    nev = 0
     for _ in range(nsteps):
         for q in range(S):
             rstart = 0 if q == 0 else max_rung - _ctz(q)
@@ -507,8 +509,11 @@ def kdk_block(pos, vel, mass, params: dict, dt: float, max_rung: int, eta: float
             if periodic:
                 pos = wrap_box(pos, box)
             rend = 0 if q + 1 == S else max_rung - _ctz(q + 1)
-            a_new, p_new = Tree(pos, mass, params).forces()
             m = rung >= rend
+            if not np.any(m):
+                continue
+            a_new, p_new = Tree(pos, mass, params).forces()
+            nev += 1
             acc[:, m] = a_new[:, m]
             if pot is None:
                 pot = np.zeros(pos.shape[1])
@@ -516,7 +521,7 @@ def kdk_block(pos, vel, mass, params: dict, dt: float, max_rung: int, eta: float
             vel[:, m] = vel[:, m] + acc[:, m] * (0.5 * np.ldexp(dt, -rung[m]))
             if not fixed:
                 rung[m] = np.maximum(rung_of(acc[:, m], dt, max_rung, eta, eps), rend)
-    return pos, vel, acc, pot, rung
+    return pos, vel, acc, pot, rung, nev
 
 
 def kdk_trajectory(pos, vel, mass, params: dict, dt: float, nsteps: int):

@@ -168,10 +168,13 @@ __global__ void __launch_bounds__(256) k_far_apply(const double* __restrict__ sp
                                                    const double4* __restrict__ near, size_t n,
                                                    const uint32_t* __restrict__ idx, double L,
                                                    double G, const double* __restrict__ lam,
-                                                   int periodic, T* __restrict__ acc,
+                                                   int periodic, const uint8_t* __restrict__ rung,
+                                                   int rmin, T* __restrict__ acc,
                                                    T* __restrict__ pot) {
   const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
+  // block timesteps: only the particles whose step ends now get new values
+  if (rung && (int)rung[idx[s]] < rmin) return;
   double4 v = near[s];
   double phi = v.w, gx = v.x, gy = v.y, gz = v.z;
   if (periodic) {
@@ -205,8 +208,8 @@ template <int PF>
 static hipError_t far_run(const double* spos, const double* smass, const uint64_t* skey,
                           const double4* near, size_t n, const uint32_t* idx, double box,
                           double G, const double* tpsi, double* part, int nblk_max, double* mom,
-                          double* lam, int periodic, bool fp32, void* acc, void* pot,
-                          hipStream_t s) {
+                          double* lam, int periodic, const uint8_t* rung, int rmin, bool fp32,
+                          void* acc, void* pot, hipStream_t s) {
   if (periodic) {
     int nblk = (int)((n / 8 + 2047) / 2048);
     if (nblk > nblk_max) nblk = nblk_max;
@@ -219,10 +222,10 @@ static hipError_t far_run(const double* spos, const double* smass, const uint64_
   unsigned g = (unsigned)((n + 255) / 256);
   if (fp32)
     k_far_apply<PF, float><<<g, 256, 0, s>>>(spos, skey, near, n, idx, box, G, lam, periodic,
-                                              (float*)acc, (float*)pot);
+                                              rung, rmin, (float*)acc, (float*)pot);
   else
     k_far_apply<PF, double><<<g, 256, 0, s>>>(spos, skey, near, n, idx, box, G, lam, periodic,
-                                               (double*)acc, (double*)pot);
+                                               rung, rmin, (double*)acc, (double*)pot);
   return hipGetLastError();
 }
 
@@ -259,13 +262,13 @@ hipError_t far_prepare_launch(int far_order, const double* spos, const double* s
 hipError_t far_launch(int far_order, const double* spos, const double* smass,
                       const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx,
                       double box, double G, const double* tpsi, double* part, int nblk_max,
-                      double* mom, double* lam, int periodic, bool fp32, void* acc, void* pot,
-                      hipStream_t s) {
+                      double* mom, double* lam, int periodic, const uint8_t* rung, int rmin,
+                      bool fp32, void* acc, void* pot, hipStream_t s) {
   if (n == 0) return hipSuccess;
 #define HOT_FAR(PF)                                                                            \
   case PF:                                                                                     \
     return far_run<PF>(spos, smass, skey, near, n, idx, box, G, tpsi, part, nblk_max, mom, lam, \
-                       periodic, fp32, acc, pot, s);
+                       periodic, rung, rmin, fp32, acc, pot, s);
   switch (far_order) {
     HOT_FAR(0) HOT_FAR(1) HOT_FAR(2) HOT_FAR(3) HOT_FAR(4) HOT_FAR(5) HOT_FAR(6)
     HOT_FAR(7) HOT_FAR(8) HOT_FAR(9) HOT_FAR(10) HOT_FAR(11) HOT_FAR(12)

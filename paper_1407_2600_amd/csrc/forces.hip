@@ -401,6 +401,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_p2p(Cells C, Groups G, uin
   const int wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
+  if (G.active && !G.active[g]) return;  // no target due: nothing written
   p2p_group<T, T4, TAIL, K1>(g, lds, C, G, L, sf, spos, srec, n, list, out);
 }
 
@@ -416,6 +417,7 @@ __global__ void __launch_bounds__(64 * kForceWaves) k_m2p(Cells C, Groups G, uin
   const uint32_t g =
       __builtin_amdgcn_readfirstlane(TAIL ? xcd_block() : xcd_block() * kForceWaves + wid);
   if (g >= ngroups) return;
+  if (G.active && !G.active[g]) return;  // block- (tail) or wave-uniform (main)
   m2p_group<P, T, TAIL>(g, C, G, L, eps2, spos, n, list, out);
 }
 

@@ -55,9 +55,18 @@ hipError_t m2p_launch(bool fp32, int order, const Cells& C, const Groups& G, uin
                       double L, double eps, const double* spos, size_t n, const uint4* list,
                       double4* out, hipStream_t s, const SideStream& side);
 hipError_t far_launch(int far_order, const double* spos, const double* smass,
-                      const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx, double box, double G, const double* tpsi,
-                      double* part, int nblk_max, double* mroot, double* lam, int periodic,
+                      const uint64_t* skey, const double4* near, size_t n, const uint32_t* idx,
+                      double box, double G, const double* tpsi, double* part, int nblk_max,
+                      double* mroot, double* lam, int periodic, const uint8_t* rung, int rmin,
                       bool fp32, void* acc, void* pot, hipStream_t s);
+hipError_t kick_rung_launch(bool fp32, void* vel, const void* acc, const uint8_t* rung, size_t n,
+                            int rmin, double dt, hipStream_t s);
+hipError_t rung_assign_launch(bool fp32, const void* acc, uint8_t* rung, size_t n, int rmin,
+                              double dt, int max_rung, double eta, double eps, hipStream_t s);
+hipError_t group_active_launch(const Cells& C, const Groups& G, uint32_t ngroups,
+                               const uint32_t* idx, const uint8_t* rung, int rmin, uint8_t* act,
+                               hipStream_t s);
+hipError_t rung_max_launch(const uint8_t* rung, size_t n, uint32_t* out, hipStream_t s);
 hipError_t far_prepare_launch(int far_order, const double* spos, const double* smass,
                               const uint64_t* skey, size_t n, double box, const double* tpsi,
                               double* part, int nblk_max, double* mom, double* lam,
@@ -129,7 +138,8 @@ constexpr int kHostPairs = 56;
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
        CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
-       CTR_MAXW = 16, CTR_READ = 20, CTR_N = 64 };
+       CTR_MAXW = 16, CTR_READ = 20, CTR_RMAX = 60 /* block timesteps: largest rung */,
+       CTR_N = 64 };
 // largest list region requested for one evaluation (4-byte words); larger
 // list sets are processed in chunks of consecutive groups
 constexpr size_t kListMaxWords = size_t(1) << 30;
@@ -215,6 +225,7 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes, unsigned need) {
   P.o_g_cm = take(4 * Gc);
   P.o_g_op = take(4 * Gc);
   P.o_g_om = take(4 * Gc);
+  P.o_g_act = take(Gc);
   const int NQ = nt(c->p.far_order);
   P.o_far_part = take(8 * 8 * (size_t)NQ * kFarBlocks);
   P.o_far_mom = take(8 * 8 * (size_t)NQ);
@@ -297,6 +308,7 @@ Groups groups_of(void* ws, const Plan& P) {
   G.cnt_m2p = at<uint32_t>(ws, P.o_g_cm);
   G.off_p2p = at<uint32_t>(ws, P.o_g_op);
   G.off_m2p = at<uint32_t>(ws, P.o_g_om);
+  G.active = nullptr;
   return G;
 }
 
@@ -334,9 +346,13 @@ struct VjpArgs {
 // layout must be the same for every evaluation within one call)
 // after_forces: an adjoint may use the tree and lists the workspace holds
 // from the context's last evaluation (hot_vjp_after_forces)
+// rung, rmin: block timesteps, forces only for the particles with
+// rung[i] >= rmin (their groups get lists; the others' acc and pot are left
+// as they are); nullptr: every particle
 static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const void* mass, void* acc,
                               void* pot, void* ws, size_t ws_bytes, hipStream_t s, unsigned need,
-                              const VjpArgs* vjp = nullptr, bool after_forces = false) {
+                              const VjpArgs* vjp = nullptr, bool after_forces = false,
+                              const uint8_t* rung = nullptr, int rmin = 0) {
   const hot_params& p = c->p;
   const bool fp32 = p.precision == HOT_FP32;
   Plan P = make_plan(c, n, ws_bytes, need);
@@ -459,6 +475,11 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     return HOT_EDEVICE;
   }
   HOT_CHECK(tree_group_bbox(C, G, ngroups, (uint32_t)P.cap_groups, spos, n, s), "bbox");
+  if (rung) {
+    uint8_t* act = at<uint8_t>(ws, P.o_g_act);
+    HOT_CHECK(group_active_launch(C, G, ngroups, idx0, rung, rmin, act, s), "due groups");
+    G.active = act;
+  }
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
 
   // ---- walk: count pass over all groups (again with the larger stack if
@@ -553,6 +574,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     Gk.cnt_m2p += k.g0;
     Gk.off_p2p += k.g0;
     Gk.off_m2p += k.g0;
+    if (Gk.active) Gk.active += k.g0;
     uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
     if (!use_tree) {
       HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
@@ -597,7 +619,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   if (!vjp) {
     HOT_CHECK(far_launch(p.far_order, spos, smass, key0, near, n, idx0, p.box, p.G, c->d_tpsi,
                          at<double>(ws, P.o_far_part), kFarBlocks, at<double>(ws, P.o_far_mom),
-                         at<double>(ws, P.o_far_lam), p.periodic, fp32, acc, pot, s),
+                         at<double>(ws, P.o_far_lam), p.periodic, rung, rmin, fp32, acc, pot, s),
               "far field");
   } else {
     if (p.periodic)
@@ -638,7 +660,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   c->last_ws = ws;
   c->last_ncells = ncells;
   c->last_ngroups = ngroups;
-  if (chunks.size() == 1) {
+  if (chunks.size() == 1 && !rung) {
     hot_ctx::TreeRecord& T = c->tree;
     T.pos = pos;
     T.mass = mass;
@@ -882,6 +904,81 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
       return st;
     }
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
+    c->stats.kdk_steps_done = k + 1;
+  }
+  return HOT_OK;
+}
+
+hot_status hot_kdk_block(hot_ctx* c, size_t n, double* pos, void* vel, const void* mass,
+                         void* acc, void* pot, uint8_t* rung, double dt, int max_rung, double eta,
+                         int nsteps, unsigned flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !vel || !mass || !acc || !rung || !ws || nsteps < 0 || !std::isfinite(dt) ||
+      max_rung < 0 || max_rung > kMaxRung || !(eta > 0.0) || !std::isfinite(eta)) {
+    g_err = "bad argument (max_rung must be in 0..16, eta > 0)";
+    return HOT_EINVAL;
+  }
+  if (n >= (size_t)0xffffffffu) {
+    g_err = "n must be < 2^32";
+    return HOT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool fp32 = c->p.precision == HOT_FP32;
+  c->stats.kdk_steps_done = 0;
+  const Plan P = make_plan(c, n, ws_bytes, 0);
+  if (ws_bytes < P.min_total) {
+    g_err = "workspace smaller than hot_workspace_size_min(HOT_CALL_FORCES)";
+    return HOT_ENOMEM;
+  }
+  hot_status st;
+  if (!(flags & HOT_ACC_VALID)) {
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, 0);
+    if (st != HOT_OK) return st;
+  }
+  const double eps = c->p.eps;
+  if (!(flags & HOT_RUNG_VALID))
+    HOT_CHECK(rung_assign_launch(fp32, acc, rung, n, 0, dt, max_rung, eta, eps, s), "rungs");
+  // the largest rung in use: a substep boundary where no particle is due
+  // only drifts
+  uint32_t* ctr = at<uint32_t>(ws, P.o_ctr);
+  uint32_t* host = c->host_buf;
+  auto largest_rung = [&](int* out) -> hipError_t {
+    hipError_t e = rung_max_launch(rung, n, ctr + CTR_RMAX, s);
+    if (e == hipSuccess) e = readback(s, ctr + CTR_RMAX, host, 1);
+    *out = (int)host[0];
+    return e;
+  };
+  int rmax = 0;
+  HOT_CHECK(largest_rung(&rmax), "rungs");
+  if (rmax > max_rung) {
+    g_err = "a rung on entry exceeds max_rung";
+    return HOT_EINVAL;
+  }
+  const uint32_t S = 1u << max_rung;
+  const double sub = ldexp(dt, -max_rung);
+  for (int k = 0; k < nsteps; ++k) {
+    for (uint32_t q = 0; q < S; ++q) {
+      // the particles whose step starts at substep q: every rung at q = 0,
+      // else rung >= max_rung - (trailing zeros of q)
+      const int rstart = q == 0 ? 0 : max_rung - __builtin_ctz(q);
+      if (rstart <= rmax) HOT_CHECK(kick_rung_launch(fp32, vel, acc, rung, n, rstart, dt, s), "kick");
+      HOT_CHECK(drift_launch(fp32, pos, vel, n, sub, c->p.box, s), "drift");
+      // those whose step ends at the next boundary
+      const int rend = q + 1 == S ? 0 : max_rung - __builtin_ctz(q + 1);
+      if (rend > rmax) continue;
+      st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, 0, nullptr, false, rung, rend);
+      if (st != HOT_OK) return st;  // pos, vel, acc and rung are then undefined
+      HOT_CHECK(kick_rung_launch(fp32, vel, acc, rung, n, rend, dt, s), "kick");
+      if (!(flags & HOT_RUNG_FIXED)) {
+        HOT_CHECK(rung_assign_launch(fp32, acc, rung, n, rend, dt, max_rung, eta, eps, s),
+                  "rungs");
+        HOT_CHECK(largest_rung(&rmax), "rungs");
+      }
+    }
     c->stats.kdk_steps_done = k + 1;
   }
   return HOT_OK;

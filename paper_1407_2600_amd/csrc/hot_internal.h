@@ -16,6 +16,7 @@ constexpr int kMaxLevel = 21;        // 21 bits per axis in a 64-bit key
 // softening eps (equal central potential: g(0) = 945/(256 h) = 1/eps)
 inline double k1_radius(double eps) { return (945.0 / 256.0) * eps; }
 constexpr int kMaxOrder = 4;         // cell multipole order built into the kernels
+constexpr int kMaxRung = 16;         // block timesteps: steps down to dt / 2^16
 constexpr int kMaxFarOrder = 12;     // far-field local expansion order
 constexpr int kImgBits = 5;          // list entry = image << 27 | cell
 constexpr uint32_t kCellMask = (1u << 27) - 1;
@@ -143,6 +144,9 @@ struct Cells {
 
 struct Groups {
   int32_t* cell;
+  const uint8_t* active;  // nullptr: every group; else only groups with active[g] != 0
+                          // get lists and forces (block timesteps: the groups holding a
+                          // particle whose step ends now)
   double* lo;        // 3 x cap
   double* hi;        // 3 x cap
   uint32_t* cnt_p2p;
@@ -168,7 +172,7 @@ struct Plan {
   size_t o_c_key, o_c_level, o_c_first, o_c_count, o_c_child, o_c_nchild, o_c_parent;
   size_t o_c_mmx, o_c_walk, o_c_bnd, o_c_bk, o_c_mom, o_c_coef;
   size_t hcap, o_h_key, o_h_val;  // key -> cell hash (slots, key and value arrays)
-  size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om;
+  size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om, o_g_act;
   size_t o_far_part, o_far_mom, o_far_lam;
   size_t o_arec, o_adj, o_c_emom, o_c_ecoef, o_far_mbar;
   size_t o_kv_g, o_kv_x, o_kv_m;  // reverse leapfrog sweep: gacc, xbar and mbar of one step

@@ -1,6 +1,8 @@
 // Fixed-step kick-drift-kick leapfrog (the paper's Sec. 2.1 integrator is an
 // adaptive symplectic one; the fixed-step leapfrog is its single-rung case),
 // and the interaction counters reported with each force evaluation.
+#include <algorithm>
+
 #include "hot_internal.h"
 
 namespace hot {
@@ -23,6 +25,106 @@ __global__ void __launch_bounds__(256) k_drift(double* __restrict__ pos, const T
   if (x >= L) x -= L;
   if (x < 0.0) x = 0.0;
   pos[i] = x;
+}
+
+// ---------------------------------------------------------- block timesteps
+// Particle i steps dt/2^rung[i] (rungs 0..max_rung), substeps of dt/2^max_rung.
+// A particle is due (its step starts or ends at the current substep
+// boundary) when rung[i] >= rmin.
+
+// half kick of the due particles over their own step: v += a dt_i / 2
+template <typename T>
+__global__ void __launch_bounds__(256) k_kick_rung(T* __restrict__ vel, const T* __restrict__ acc,
+                                                   const uint8_t* __restrict__ rung, size_t n,
+                                                   int rmin, double dt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = rung[i];
+  if (r < rmin) return;
+  const T h = (T)(0.5 * ldexp(dt, -r));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vel[a * n + i] = fma(acc[a * n + i], h, vel[a * n + i]);
+}
+
+// rung of the due particles from their accelerations: the largest step
+// dt/2^r (r <= max_rung) not above eta sqrt(eps / |a|), but no coarser than
+// the rungs whose steps can start at this boundary (r >= rmin)
+template <typename T>
+__global__ void __launch_bounds__(256) k_rung_assign(const T* __restrict__ acc,
+                                                     uint8_t* __restrict__ rung, size_t n,
+                                                     int rmin, double dt, int max_rung,
+                                                     double eta, double eps) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if ((int)rung[i] < rmin) return;
+  const double ax = (double)acc[i], ay = (double)acc[n + i], az = (double)acc[2 * n + i];
+  double a2 = ax * ax;
+  a2 = a2 + ay * ay;
+  a2 = a2 + az * az;
+  const double amag = sqrt(a2);
+  const double want = eta * sqrt(eps / amag);
+  int r = 0;
+  while (r < max_rung && ldexp(dt, -r) > want) ++r;
+  rung[i] = (uint8_t)(r > rmin ? r : rmin);
+}
+
+// largest rung (atomic max into *out, which the caller clears)
+__global__ void __launch_bounds__(256) k_rung_max(const uint8_t* __restrict__ rung, size_t n,
+                                                  uint32_t* __restrict__ out) {
+  uint32_t m = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const uint32_t r = rung[i];
+    m = r > m ? r : m;
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint32_t o = __shfl_down(m, d, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+hipError_t kick_rung_launch(bool fp32, void* vel, const void* acc, const uint8_t* rung, size_t n,
+                            int rmin, double dt, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (fp32)
+    k_kick_rung<float><<<g, 256, 0, s>>>((float*)vel, (const float*)acc, rung, n, rmin, dt);
+  else
+    k_kick_rung<double><<<g, 256, 0, s>>>((double*)vel, (const double*)acc, rung, n, rmin, dt);
+  return hipGetLastError();
+}
+
+hipError_t rung_assign_launch(bool fp32, const void* acc, uint8_t* rung, size_t n, int rmin,
+                              double dt, int max_rung, double eta, double eps, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (fp32)
+    k_rung_assign<float><<<g, 256, 0, s>>>((const float*)acc, rung, n, rmin, dt, max_rung, eta,
+                                           eps);
+  else
+    k_rung_assign<double><<<g, 256, 0, s>>>((const double*)acc, rung, n, rmin, dt, max_rung, eta,
+                                            eps);
+  return hipGetLastError();
+}
+
+// groups holding at least one due particle (sorted order; idx = original index)
+__global__ void __launch_bounds__(256) k_group_active(Cells C, Groups G, uint32_t ngroups,
+                                                      const uint32_t* __restrict__ idx,
+                                                      const uint8_t* __restrict__ rung, int rmin,
+                                                      uint8_t* __restrict__ act) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  const int A = G.cell[g];
+  const uint32_t f = C.first[A], e = f + C.count[A];
+  uint8_t a = 0;
+  for (uint32_t s = f; s < e && !a; ++s) a = (int)rung[idx[s]] >= rmin;
+  act[g] = a;
+}
+
+hipError_t group_active_launch(const Cells& C, const Groups& G, uint32_t ngroups,
+                               const uint32_t* idx, const uint8_t* rung, int rmin, uint8_t* act,
+                               hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  k_group_active<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, idx, rung, rmin, act);
+  return hipGetLastError();
 }
 
 hipError_t kick_launch(bool fp32, void* vel, const void* acc, size_t n, double h, hipStream_t s) {
@@ -121,7 +223,7 @@ __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t
                                                      unsigned long long* __restrict__ out) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long pp = 0, mp = 0;
-  if (g < ngroups) {
+  if (g < ngroups && !(G.active && !G.active[g])) {
     const int A = G.cell[g];
     const unsigned long long na = C.count[A];
     unsigned long long src = na - 1;
@@ -145,6 +247,13 @@ hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const 
                        unsigned long long* out, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   k_count_pairs<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, list, out);
+  return hipGetLastError();
+}
+
+hipError_t rung_max_launch(const uint8_t* rung, size_t n, uint32_t* out, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  k_zero<<<1, 256, 0, s>>>((unsigned char*)out, 4);
+  k_rung_max<<<g, 256, 0, s>>>(rung, n, out);
   return hipGetLastError();
 }
 

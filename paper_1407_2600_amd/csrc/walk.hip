@@ -34,6 +34,13 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kWalkWaves + wid);
   if (g >= ngroups) return;  // whole wavefront leaves; no block barriers below
+  if (G.active && !G.active[g]) {  // no target of this group is due: no lists
+    if (!EMIT && lane == 0) {
+      G.cnt_p2p[g] = 0;
+      G.cnt_m2p[g] = 0;
+    }
+    return;
+  }
   uint32_t* st = stack_all[wid];
   const int A = G.cell[g];
   const uint64_t keyA = C.key[A];

@@ -17,13 +17,15 @@ HOT_OK, HOT_EINVAL, HOT_ENOMEM, HOT_EOVERFLOW, HOT_EDEVICE, HOT_EUNSUPPORTED = r
 HOT_FP64, HOT_FP32 = 0, 1
 HOT_ACC_VALID = 1
 HOT_KDK_NO_SNAPSHOT = 2
+HOT_RUNG_VALID = 4
+HOT_RUNG_FIXED = 8
 HOT_CALL_FORCES, HOT_CALL_KDK, HOT_CALL_VJP, HOT_CALL_KDK_VJP = 1, 2, 4, 8
 STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW",
                 4: "HOT_EDEVICE", 5: "HOT_EUNSUPPORTED"}
 
 # symbols declared in include/hot.h
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
-            "hot_forces", "hot_forces_noalloc", "hot_kdk",
+            "hot_forces", "hot_forces_noalloc", "hot_kdk", "hot_kdk_block",
             "hot_vjp", "hot_vjp_after_forces", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
             "hot_debug_list_range", "hot_cell_lookup", "hot_last_error", "hot_version",
             "hot_far_table"]
@@ -90,6 +92,9 @@ def lib():
         L.hot_kdk.restype = C.c_int
         L.hot_kdk.argtypes = [vp, sz, vp, vp, vp, vp, vp, C.c_double, C.c_int, C.c_uint, vp, sz,
                               vp]
+        L.hot_kdk_block.restype = C.c_int
+        L.hot_kdk_block.argtypes = [vp, sz, vp, vp, vp, vp, vp, vp, C.c_double, C.c_int,
+                                    C.c_double, C.c_int, C.c_uint, vp, sz, vp]
         L.hot_vjp.restype = C.c_int
         L.hot_vjp.argtypes = [vp, sz, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.hot_vjp_after_forces.restype = C.c_int
@@ -291,6 +296,41 @@ class Gravity:
             valid = valid or done > 0
             left -= done
         check(st)
+
+    def kdk_block(self, pos, vel, mass, acc, rung, dt: float, max_rung: int, eta: float,
+                  nsteps: int, acc_valid: bool, rung_valid: bool, fixed_rungs: bool = False,
+                  pot=None):
+        """In-place block-timestep steps (hot_kdk_block) on pos (FP64), vel,
+        acc (precision) and rung (uint8).  The workspace is first sized by a
+        force evaluation when it has not been yet (no snapshots are kept)."""
+        t = self.torch
+        pos_c, mass = self._check_inputs(pos, mass)
+        if not (pos_c.data_ptr() == pos.data_ptr()):
+            raise ValueError("pos must be contiguous (it is updated in place)")
+        n = pos.shape[1]
+        for name, a in (("vel", vel), ("acc", acc)):
+            if a.dtype != self.dtype or a.shape != pos.shape or not a.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous (3, N) {self.dtype} tensor")
+        if rung.dtype != t.uint8 or rung.shape != (n,) or not rung.is_contiguous():
+            raise ValueError("rung must be a contiguous (N,) uint8 tensor")
+        if self.ws is None:
+            a0, p0 = self.forces(pos, mass)
+            if not acc_valid:
+                acc.copy_(a0)
+                if pot is not None:
+                    pot.copy_(p0)
+                acc_valid = True
+        self.evals += 1
+        ws = self._workspace(n, HOT_CALL_FORCES)
+        flags = ((HOT_ACC_VALID if acc_valid else 0) | (HOT_RUNG_VALID if rung_valid else 0) |
+                 (HOT_RUNG_FIXED if fixed_rungs else 0))
+        check(self.L.hot_kdk_block(self.h, n, C.c_void_p(pos.data_ptr()),
+                                   C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
+                                   C.c_void_p(acc.data_ptr()),
+                                   C.c_void_p(pot.data_ptr() if pot is not None else 0),
+                                   C.c_void_p(rung.data_ptr()), float(dt), int(max_rung),
+                                   float(eta), int(nsteps), flags, C.c_void_p(ws.data_ptr()),
+                                   ws.numel(), self._stream()))
 
     def kdk_vjp(self, pos_ckpt, mass, dt: float, xbar, vbar):
         """Reverse sweep over len(pos_ckpt) - 1 leapfrog steps (hot_kdk_vjp).
