@@ -244,6 +244,19 @@ class StepStats:
         return st
 
 
+def lane_use(st):
+    """Lane use of the multipole kernel: interactions over the lane-steps
+    its main pass (64 lanes per pass of more than 32 targets) and tail pass
+    (8, 16 or 32 lanes for a last pass of at most 32 targets) spend, per list
+    entry, as counted by the library."""
+    main, tail, tp = st["m2p_lanes_main"], st["m2p_lanes_tail"], st["m2p_pairs_tail"]
+    mp = st["m2p_pairs"]
+    if main + tail <= 0:
+        return None
+    return {"all": mp / (main + tail), "main": (mp - tp) / main if main else None,
+            "tail": tp / tail if tail else None, "tail_pair_share": tp / mp if mp else None}
+
+
 def search(torch, Gravity, pos, mass, prm, tg, aref, dev, workload, **ctx):
     """The fastest setting of the searched grids whose FP32 rms force error
     on the selection targets tg is at most ERR_TARGET."""
@@ -368,6 +381,7 @@ def paper_scale(args):
         "per_force_eval": {"fp32_ms": st0["ms_total"], "fp32_pps": n / (1e-3 * st0["ms_total"])},
         "stage_ms": {k: st[k] for k in StepStats.KEYS},
         "pairs_per_step": {"p2p": st["p2p_pairs"], "m2p": st["m2p_pairs"]},
+        "m2p_lane_use": lane_use(st),
         "stage_bandwidth": stage_bandwidth(n, st["ncells"], st),
         "interactions_per_s": (st["p2p_pairs"] + st["m2p_pairs"]) / el,
         "list_chunks": st["list_chunks"], "workspace_bytes": int(g.ws.numel()),
@@ -514,6 +528,7 @@ def extras_128(args):
                                               "selection targets"},
         "adjoint": r32["adjoint"], "adjoint_over_forward": r32["adjoint"]["ratio"],
         "stage_ms": {k: r32["stats"][k] for k in StepStats.KEYS},
+        "m2p_lane_use": lane_use(r32["stats"]),
         "roofline": roof, "roofline_other": roof_other,
     }
 
@@ -546,6 +561,7 @@ def workload_main(args):
         "stage_ms": {k: st[k] for k in StepStats.KEYS},
         "stage_bandwidth": stage_bandwidth(n, st["ncells"], st),
         "pairs_per_step": {"p2p": st["p2p_pairs"], "m2p": st["m2p_pairs"]},
+        "m2p_lane_use": lane_use(st),
         "workspace_bytes": {"fp32": r32["workspace_bytes"], "fp64": r64["workspace_bytes"]},
         "roofline": roof, "roofline_other": roof_other,
         "operating_point_search": found,

@@ -151,6 +151,13 @@ typedef struct {
   int64_t kdk_steps_done; /* steps hot_kdk completed in its last call */
   int64_t list_chunks;    /* group ranges the interaction lists were processed
                              in (1 unless they exceeded the list region) */
+  int64_t m2p_lanes_main; /* lane-steps of the multipole kernel's main pass
+                             (64 per pass of more than 32 targets per list
+                             entry); m2p_pairs / (this + m2p_lanes_tail) is
+                             its lane use */
+  int64_t m2p_lanes_tail; /* lane-steps of its tail pass (the last pass of at
+                             most 32 targets: 8, 16 or 32 lanes per entry) */
+  int64_t m2p_pairs_tail; /* particle-cell interactions of the tail pass */
 } hot_stats;
 
 /* Host copies of the internal structures of the last hot_forces call, for

@@ -47,7 +47,7 @@ hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uin
 hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
                       hipStream_t s);
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* p2p_list,
-                       unsigned long long* out, hipStream_t s);
+                       unsigned long long* out, unsigned long long* slots, hipStream_t s);
 hipError_t p2p_launch(bool fp32, int kernel, const Cells& C, const Groups& G, uint32_t ngroups,
                       double L, double eps, const double* spos, const void* srec, size_t n,
                       const uint32_t* list, double4* out, hipStream_t s, const SideStream& side);
@@ -132,13 +132,17 @@ constexpr size_t kAlign = 256;
 
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// words of the context's pinned host buffer that receive the pair counters
-// (two u64) at the end of every evaluation
+// words of the context's pinned host buffer (kHostWords uint32) that receive
+// the pair counters (two u64) and the multipole lane-step counters (three
+// u64) at the end of every evaluation
 constexpr int kHostPairs = 56;
+constexpr int kHostSlots = 64;
+constexpr int kHostWords = 128;
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
        CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
-       CTR_MAXW = 16, CTR_READ = 20, CTR_RMAX = 60 /* block timesteps: largest rung */,
+       CTR_MAXW = 16, CTR_READ = 20, CTR_SLOTS = 24 /* three u64 at 24..29 */,
+       CTR_RMAX = 60 /* block timesteps: largest rung */,
        CTR_N = 64 };
 // largest list region requested for one evaluation (4-byte words); larger
 // list sets are processed in chunks of consecutive groups
@@ -583,7 +587,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                             p2p_list, m2p_list, ctr + CTR_STATUS, s),
                 "walk emit");
       HOT_CHECK(count_pairs(C, Gk, ng, p2p_list,
-                            reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS), s),
+                            reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS),
+                            reinterpret_cast<unsigned long long*>(ctr + CTR_SLOTS), s),
                 "pair count");
     }
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
@@ -639,6 +644,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   HOT_CHECK(hipMemcpyAsync(c->host_buf + kHostPairs, ctr + CTR_PAIRS, 16, hipMemcpyDeviceToHost,
                            s),
             "pair counters");
+  HOT_CHECK(hipMemcpyAsync(c->host_buf + kHostSlots, ctr + CTR_SLOTS, 24, hipMemcpyDeviceToHost,
+                           s),
+            "lane-step counters");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
   c->last_chunks = (int)chunks.size();
   c->last_cev = cev ? (int)chunks.size() : 0;
@@ -738,7 +746,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   e = hipMalloc(&c->d_tpsi, sizeof(double) * tab.size());
   if (e == hipSuccess)
     e = hipMemcpy(c->d_tpsi, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_buf, 4 * 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_buf, 4 * kHostWords, hipHostMallocDefault);
   if (e != hipSuccess) {
     hot_destroy(c);
     return device_error(e, "context allocation");
@@ -1143,6 +1151,11 @@ hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
       m->stats.m2p_pairs = (int64_t)pr[1];
       m->stats.flops_p2p = (double)pr[0] * kP2PFlops;
       m->stats.flops_m2p = (double)pr[1] * m2p_flops(m->p.order);
+      unsigned long long sl[3];
+      std::memcpy(sl, m->host_buf + kHostSlots, sizeof(sl));
+      m->stats.m2p_lanes_main = (int64_t)sl[0];
+      m->stats.m2p_lanes_tail = (int64_t)sl[1];
+      m->stats.m2p_pairs_tail = (int64_t)sl[2];
     }
   }
   *out = m->stats;

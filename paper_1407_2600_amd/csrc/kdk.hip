@@ -220,9 +220,10 @@ hipError_t kdk_adj_accum_launch(bool fp32, double* xbar, const double* tx, void*
 // n_A x (list length), summed over groups
 __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t ngroups,
                                                      const uint32_t* __restrict__ list,
-                                                     unsigned long long* __restrict__ out) {
+                                                     unsigned long long* __restrict__ out,
+                                                     unsigned long long* __restrict__ slots) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long pp = 0, mp = 0;
+  unsigned long long pp = 0, mp = 0, ms = 0, ts = 0, tp = 0;
   if (g < ngroups && !(G.active && !G.active[g])) {
     const int A = G.cell[g];
     const unsigned long long na = C.count[A];
@@ -230,23 +231,40 @@ __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t
     const uint32_t off = G.off_p2p[g], cnt = G.cnt_p2p[g];
     for (uint32_t q = 0; q < cnt; ++q) src += C.count[list[off + q] & kCellMask];
     pp = na * src;
-    mp = na * (unsigned long long)G.cnt_m2p[g];
+    const unsigned long long cm = G.cnt_m2p[g];
+    mp = na * cm;
+    // lane-steps of the multipole kernel: the main pass takes every pass of
+    // more than 32 targets on 64 lanes; the tail pass a last pass of at most
+    // 32 targets on sub-groups of 32, 16 or 8 lanes
+    const unsigned long long rem = na % 64;
+    const bool tail = rem != 0 && rem <= 32;
+    ms = 64ull * (na / 64 + (rem > 32 ? 1 : 0)) * cm;
+    if (tail) {
+      ts = (rem <= 8 ? 8ull : rem <= 16 ? 16ull : 32ull) * cm;
+      tp = rem * cm;
+    }
   }
   // wave reduction, then one atomic per wave
   for (int d = 32; d > 0; d >>= 1) {
     pp += __shfl_down(pp, d, 64);
     mp += __shfl_down(mp, d, 64);
+    ms += __shfl_down(ms, d, 64);
+    ts += __shfl_down(ts, d, 64);
+    tp += __shfl_down(tp, d, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     atomicAdd(&out[0], pp);
     atomicAdd(&out[1], mp);
+    atomicAdd(&slots[0], ms);
+    atomicAdd(&slots[1], ts);
+    atomicAdd(&slots[2], tp);
   }
 }
 
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* list,
-                       unsigned long long* out, hipStream_t s) {
+                       unsigned long long* out, unsigned long long* slots, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  k_count_pairs<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, list, out);
+  k_count_pairs<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, list, out, slots);
   return hipGetLastError();
 }
 

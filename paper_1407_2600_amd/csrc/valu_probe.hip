@@ -23,7 +23,9 @@ __global__ void __launch_bounds__(kThreads) k_chains(T* out, T a, T b) {
   for (int i = 0; i < kIters; ++i) {
 #pragma unroll
     for (int c = 0; c < kChains; ++c) {
-      if constexpr (KIND == 0 || KIND == 5) {
+      if constexpr (KIND == 0) {
+        x[c] = __builtin_fmaf(x[c], a, b);
+      } else if constexpr (KIND == 5) {
         x[c] = __builtin_fma(x[c], a, b);
       } else if constexpr (KIND == 1) {
         x[c] = x[c] * a;

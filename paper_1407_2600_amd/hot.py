@@ -51,7 +51,9 @@ class hot_stats(C.Structure):
                 ("flops_m2p", C.c_double), ("ms_total", C.c_double), ("ms_sort", C.c_double),
                 ("ms_build", C.c_double), ("ms_walk", C.c_double), ("ms_p2p", C.c_double),
                 ("ms_m2p", C.c_double), ("ms_far", C.c_double), ("ws_bytes_needed", C.c_size_t),
-                ("kdk_steps_done", C.c_int64), ("list_chunks", C.c_int64)]
+                ("kdk_steps_done", C.c_int64), ("list_chunks", C.c_int64),
+                ("m2p_lanes_main", C.c_int64), ("m2p_lanes_tail", C.c_int64),
+                ("m2p_pairs_tail", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
