@@ -109,6 +109,7 @@ def lib():
         L.or_ewald_xi.restype = C.c_double
         L.or_ewald_xi.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
         L.or_multipole_eval.argtypes = [i64, dp, dp, C.c_int, C.c_double, dp, dp, dp]
+        L.or_local_eval.argtypes = [i64, dp, dp, C.c_int, C.c_int, C.c_double, dp, dp, dp, dp]
         L.or_nterms.restype = C.c_int
         L.or_nterms.argtypes = [C.c_int]
         L.or_mi_get.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -125,7 +126,8 @@ class _Params(C.Structure):
     _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
                 ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
-                ("err_tol", C.c_double), ("kernel", C.c_int)]
+                ("err_tol", C.c_double), ("kernel", C.c_int), ("local_order", C.c_int),
+                ("local_tol", C.c_double)]
 
 # softening kernels: Plummer, or Dehnen's compensating K1 (kernel.c)
 KERNELS = {"plummer": 0, "k1": 1, 0: 0, 1: 1}
@@ -140,7 +142,8 @@ def _params(p: dict) -> _Params:
                    float(p.get("theta", 0.5)), int(p.get("order", 2)),
                    int(p.get("periodic", 1)), int(p.get("leaf_max", 16)),
                    int(p.get("group_max", 64)), int(p.get("far_order", 8)),
-                   float(p.get("err_tol", 0.0)), kernel_id(p))
+                   float(p.get("err_tol", 0.0)), kernel_id(p), int(p.get("local_order", 0)),
+                   float(p.get("local_tol", 0.0)))
 
 
 def pair_kernel(kernel, r2: float, eps: float):
@@ -227,6 +230,21 @@ def multipole_eval(pos, mass, order: int, eps: float, x):
     phi = np.zeros(1)
     g = np.zeros(3)
     L.or_multipole_eval(pos.shape[1], _p(pos), _p(mass), order, eps, _p(x), _p(phi), _p(g))
+    return phi[0], g
+
+
+def local_eval(pos, mass, order: int, q: int, eps: float, c, x):
+    """Phi and grad Phi at x of one cell's order-p expansion (about its COM)
+    re-expanded to order q about c: the tree's group-level local route."""
+    L = lib()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    phi = np.zeros(1)
+    g = np.zeros(3)
+    L.or_local_eval(pos.shape[1], _p(pos), _p(mass), order, q, eps, _p(c), _p(x), _p(phi),
+                    _p(g))
     return phi[0], g
 
 
@@ -347,7 +365,8 @@ class Tree:
         return cell, lo, hi
 
     def lists(self, kind: int):
-        """(offsets[ng+1], image[E], cell[E]) for kind 0 (direct) or 1 (multipole)."""
+        """(offsets[ng+1], image[E], cell[E]) for kind 0 (direct), 1 (multipole)
+        or 2 (cells taken through the group's local expansion)."""
         tot = self.lib.or_tree_list_total(self.h, kind)
         ng = self.lib.or_tree_ngroups(self.h)
         off = np.zeros(ng + 1, np.int64)
@@ -398,6 +417,8 @@ class Tree:
         are filled (NaN elsewhere).  Plummer softening only."""
         if kernel_id(self.params) != 0:
             raise NotImplementedError("the adjoint is built for Plummer softening only")
+        if int(self.params.get("local_order", 0)) > 0 and float(self.params.get("local_tol", 0)) > 0:
+            raise NotImplementedError("the adjoint is built without group local expansions")
         ga = np.ascontiguousarray(gacc, dtype=np.float64)
         gp = None if gpot is None else np.ascontiguousarray(gpot, dtype=np.float64)
         xb = np.full((3, self.n), np.nan)

@@ -33,6 +33,11 @@ typedef struct {
                      error allowed per accepted cell); 0: opening angle only */
   int kernel;     /* softening: 0 Plummer (eps), 1 Dehnen K1 of radius
                      (945/256) eps (Plummer-equivalent eps; kernel.c) */
+  int local_order;  /* > 0: accepted cells far enough from a whole sink group
+                       enter through a local expansion of this order about
+                       the group's centre (tree.c); 0: none */
+  double local_tol; /* absolute acceleration error allowed per cell for the
+                       local expansion's truncation (> 0 to use it) */
 } or_params;
 
 /* ---- softening kernels (kernel.c) ---- */

@@ -45,6 +45,27 @@
  * through the triangle inequality (binomially expanded powers), daughters in
  * octant order, and the radius is found by a fixed bisection in IEEE
  * operations only, so that any implementation reproduces it bit for bit.
+ *
+ * Group-level local expansions (local_order q > 0, local_tol > 0): the paper
+ * bundles m source cells with the n sinks of a sink cell (Sec. 2.1, dual-tree
+ * traversal).  A cell that passes the acceptance test and lies far from the
+ * whole group is not evaluated at every sink; its order-p expansion is
+ * instead re-expanded once about the group's centre c (the centre of its
+ * tight box) to order q,
+ *     L_n = sum_k (-1)^|k| C(n+k, k) M_k T_(n+k)(c - z),   |n| <= q,
+ * with T_m(R) = d^m g(R)/m! the Taylor coefficients of the softened Green's
+ * function and z the cell's image-shifted centre of mass, and every sink
+ * takes Phi += sum_n L_n (x - c)^n (and its gradient).  A sink within a of c
+ * (a = half the diagonal of the tight box) sees every particle of the cell
+ * at distance >= u = |c - z| - b, and for one point mass the acceleration
+ * error of the order-q truncation is at most
+ *     G m t^q ((q+2) - (q+1) t) / (u^2 (1 - t)^2),   t = a/u < 1
+ * (the Legendre expansion of 1/|x - s| about c, with |P_n| <= 1 and the
+ * gradient of each solid harmonic of degree n bounded by n |y|^(n-1)); the
+ * cell takes the local route when this bound with its mass is at most
+ * local_tol.  The test is evaluated in this order of IEEE operations:
+ *     t = a/u;  t^q by repeated multiplication;
+ *     G m t^q ((q+2) - (q+1) t)  <=  local_tol (u u) (1-t) (1-t).
  */
 #include <math.h>
 #include <stdint.h>
@@ -97,6 +118,7 @@ typedef struct {
   double (*ghi)[3];
   list_t* p2p;
   list_t* m2p;
+  list_t* m2l; /* cells taken through the group's local expansion */
   int* gwalked;
   int walked;
   int nmom;          /* or_nterms(order) */
@@ -581,8 +603,9 @@ void or_tree_free(void* h) {
   if (T->p2p) {
     for (int64_t g = 0; g < T->ngroups; ++g) {
       free(T->p2p[g].img); free(T->p2p[g].cell); free(T->m2p[g].img); free(T->m2p[g].cell);
+      free(T->m2l[g].img); free(T->m2l[g].cell);
     }
-    free(T->p2p); free(T->m2p); free(T->gwalked);
+    free(T->p2p); free(T->m2p); free(T->m2l); free(T->gwalked);
   }
   free(T->Tpsi); free(T->Mroot); free(T->Lam);
   free(T);
@@ -623,13 +646,62 @@ static int mac_accept(const tree_t* T, int64_t g, const cell_t* B, const int n[3
   return rc2 < d2;
 }
 
+/* centre c (middle of the tight box) and radius a (half its diagonal) of a
+ * sink group, the expansion point of its local expansion */
+static void group_centre(const tree_t* T, int64_t g, double c[3], double* a) {
+  double e[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = 0.5 * (T->glo[g][k] + T->ghi[g][k]);
+    e[k] = T->ghi[g][k] - c[k];
+  }
+  double a2 = e[0] * e[0];
+  a2 = a2 + e[1] * e[1];
+  a2 = a2 + e[2] * e[2];
+  *a = sqrt(a2);
+}
+
+/* an accepted cell takes the group's local expansion when the truncation
+ * bound of the header holds */
+static int local_accept(const tree_t* T, int64_t g, const cell_t* B, const int n[3]) {
+  const int q = T->p.local_order;
+  if (q <= 0 || !(T->p.local_tol > 0.0)) return 0;
+  double c[3], a;
+  group_centre(T, g, c, &a);
+  double L = T->p.box;
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = c[k] - (B->com[k] + (double)n[k] * L);
+  double r2 = d[0] * d[0];
+  r2 = r2 + d[1] * d[1];
+  r2 = r2 + d[2] * d[2];
+  double u = sqrt(r2) - B->bmax;
+  if (!(u > a)) return 0;
+  double t = a / u;
+  double tq = t;
+  for (int i = 1; i < q; ++i) tq = tq * t;
+  double num = T->p.G * B->m;
+  num = num * tq;
+  num = num * ((double)(q + 2) - (double)(q + 1) * t);
+  double w = 1.0 - t;
+  double den = u * u;
+  den = den * w;
+  den = den * w;
+  den = T->p.local_tol * den;
+  return num <= den;
+}
+
 static void walk_rec(tree_t* T, int64_t g, int img, const int n[3], int64_t bi) {
   const cell_t* A = &T->cells[T->groups[g]];
   const cell_t* B = &T->cells[bi];
   int zero = (n[0] == 0 && n[1] == 0 && n[2] == 0);
   if (zero && bi == T->groups[g]) return; /* own block: handled directly */
   if (!(zero && is_ancestor_or_self(B, A))) {
-    if (mac_accept(T, g, B, n)) { list_push(&T->m2p[g], img, bi); return; }
+    if (mac_accept(T, g, B, n)) {
+      if (local_accept(T, g, B, n))
+        list_push(&T->m2l[g], img, bi);
+      else
+        list_push(&T->m2p[g], img, bi);
+      return;
+    }
     if (B->is_leaf) { list_push(&T->p2p[g], img, bi); return; }
   }
   for (int o = 0; o < 8; ++o)
@@ -640,6 +712,7 @@ static void ensure_lists(tree_t* T) {
   if (T->p2p) return;
   T->p2p = calloc((size_t)T->ngroups, sizeof(list_t));
   T->m2p = calloc((size_t)T->ngroups, sizeof(list_t));
+  T->m2l = calloc((size_t)T->ngroups, sizeof(list_t));
   T->gwalked = calloc((size_t)T->ngroups, sizeof(int));
 }
 
@@ -668,7 +741,7 @@ int64_t or_tree_group_list(void* h, int64_t g, int kind, int32_t* img, int64_t* 
   tree_t* T = h;
   ensure_lists(T);
   walk_group(T, g);
-  const list_t* l = kind ? &T->m2p[g] : &T->p2p[g];
+  const list_t* l = kind == 2 ? &T->m2l[g] : kind ? &T->m2p[g] : &T->p2p[g];
   for (int64_t e = 0; e < l->n; ++e) {
     if (img) img[e] = l->img[e];
     if (cell) cell[e] = l->cell[e];
@@ -715,9 +788,76 @@ static void m2p_add(const tree_t* T, const cell_t* B, const double R[3], double*
   }
 }
 
+/* adds the local expansion about c of one cell's order-p expansion (raw
+ * moments M about its centre of mass z, R0 = c - z) to L_n, |n| <= q */
+static void local_add(int p, int q, double eps2, const double* M, const double R0[3],
+                      double* Lg) {
+  const int nq = or_nterms(q), nm = or_nterms(p);
+  double Tk[4096];
+  or_green_taylor(p + q, R0, eps2, Tk);
+  for (int ni = 0; ni < nq; ++ni) {
+    int na, nb, nc;
+    or_mi_get(ni, &na, &nb, &nc);
+    double acc = 0.0;
+    for (int k = 0; k < nm; ++k) {
+      int ka, kb, kc;
+      or_mi_get(k, &ka, &kb, &kc);
+      double sg = ((ka + kb + kc) % 2) ? -1.0 : 1.0;
+      acc += sg * binom_mi(na, nb, nc, ka, kb, kc) * M[k] * Tk[or_mi(na + ka, nb + kb, nc + kc)];
+    }
+    Lg[ni] += acc;
+  }
+}
+
+/* Phi += sum_n L_n y^n and grad Phi += its gradient in y, |n| <= q */
+static void local_poly(int q, const double* Lg, const double y[3], double* phi, double gr[3]) {
+  double pw[3][OR_DMAX + 1];
+  for (int k = 0; k < 3; ++k) {
+    pw[k][0] = 1.0;
+    for (int e = 1; e <= q; ++e) pw[k][e] = pw[k][e - 1] * y[k];
+  }
+  for (int ni = 0; ni < or_nterms(q); ++ni) {
+    int na, nb, nc;
+    or_mi_get(ni, &na, &nb, &nc);
+    double Ln = Lg[ni];
+    *phi += Ln * pw[0][na] * pw[1][nb] * pw[2][nc];
+    if (na) gr[0] += Ln * na * pw[0][na - 1] * pw[1][nb] * pw[2][nc];
+    if (nb) gr[1] += Ln * nb * pw[0][na] * pw[1][nb - 1] * pw[2][nc];
+    if (nc) gr[2] += Ln * nc * pw[0][na] * pw[1][nb] * pw[2][nc - 1];
+  }
+}
+
+/* local expansion of group g about its centre from the cells of its local
+ * list, in list order */
+static void group_local(const tree_t* T, int64_t g, double* Lg) {
+  const int q = T->p.local_order;
+  for (int i = 0; i < or_nterms(q); ++i) Lg[i] = 0.0;
+  const list_t* ll = &T->m2l[g];
+  double c[3], a;
+  group_centre(T, g, c, &a);
+  double L = T->p.box;
+  for (int64_t e = 0; e < ll->n; ++e) {
+    int img = ll->img[e];
+    double sh[3] = {(img / 9 - 1) * L, ((img / 3) % 3 - 1) * L, (img % 3 - 1) * L};
+    const cell_t* B = &T->cells[ll->cell[e]];
+    double R[3] = {c[0] - (B->com[0] + sh[0]), c[1] - (B->com[1] + sh[1]),
+                   c[2] - (B->com[2] + sh[2])};
+    local_add(T->p.order, q, m2p_eps2(T), B->M, R, Lg);
+  }
+}
+
+static void local_eval(const tree_t* T, int64_t g, const double* Lg, const double x[3],
+                       double* phi, double gr[3]) {
+  double c[3], a;
+  group_centre(T, g, c, &a);
+  double y[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+  local_poly(T->p.local_order, Lg, y, phi, gr);
+}
+
 /* accumulate Phi and grad Phi (grad w.r.t. the target position) at sorted
- * particle s of group g */
-static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, double g_out[3]) {
+ * particle s of group g; Lg is the group's local expansion (NULL: none) */
+static void target_eval(const tree_t* T, int64_t g, int64_t s, const double* Lg,
+                        double* phi_out, double g_out[3]) {
   const cell_t* A = &T->cells[T->groups[g]];
   double L = T->p.box, eps = T->p.eps;
   int kern = T->p.kernel;
@@ -743,6 +883,10 @@ static void target_eval(const tree_t* T, int64_t g, int64_t s, double* phi_out, 
     const cell_t* B = &T->cells[lm->cell[e]];
     double R[3] = {tx - (B->com[0] + sh[0]), ty - (B->com[1] + sh[1]), tz - (B->com[2] + sh[2])};
     m2p_add(T, B, R, &phi, gr);
+  }
+  if (Lg) {
+    double x[3] = {tx, ty, tz};
+    local_eval(T, g, Lg, x, &phi, gr);
   }
   if (T->far_ok) {
     double pf, gf[3];
@@ -771,9 +915,12 @@ void or_tree_forces(void* h, int64_t ngsel, const int64_t* gsel, double* acc, do
     int64_t g = ngsel < 0 ? gi : gsel[gi];
     walk_group(T, g);
     const cell_t* A = &T->cells[T->groups[g]];
+    double Lg[4096];
+    const int use_local = T->m2l[g].n > 0;
+    if (use_local) group_local(T, g, Lg);
     for (int64_t s = A->first; s < A->first + A->count; ++s) {
       double phi, gr[3];
-      target_eval(T, g, s, &phi, gr);
+      target_eval(T, g, s, use_local ? Lg : NULL, &phi, gr);
       int64_t i = T->perm[s];
       for (int a = 0; a < 3; ++a) acc[a * n + i] = G * gr[a];
       if (pot) pot[i] = -G * phi;
@@ -881,12 +1028,13 @@ void or_tree_groups(void* h, int64_t* cell, double* lo, double* hi) {
   }
 }
 
-/* total list lengths (kind 0: direct, 1: multipole) */
+/* total list lengths (kind 0: direct, 1: multipole, 2: local expansion) */
 int64_t or_tree_list_total(void* h, int kind) {
   tree_t* T = h;
   or_tree_walk(T);
   int64_t t = 0;
-  for (int64_t g = 0; g < T->ngroups; ++g) t += (kind ? T->m2p[g].n : T->p2p[g].n);
+  for (int64_t g = 0; g < T->ngroups; ++g)
+    t += (kind == 2 ? T->m2l[g].n : kind ? T->m2p[g].n : T->p2p[g].n);
   return t;
 }
 
@@ -897,7 +1045,7 @@ void or_tree_lists(void* h, int kind, int64_t* off, int32_t* img, int64_t* cell)
   or_tree_walk(T);
   int64_t t = 0;
   for (int64_t g = 0; g < T->ngroups; ++g) {
-    const list_t* l = kind ? &T->m2p[g] : &T->p2p[g];
+    const list_t* l = kind == 2 ? &T->m2l[g] : kind ? &T->m2p[g] : &T->p2p[g];
     off[g] = t;
     for (int64_t e = 0; e < l->n; ++e) {
       img[t] = l->img[e];
@@ -969,6 +1117,40 @@ void or_multipole_eval(int64_t n, const double* pos, const double* mass, int ord
   }
   *phi = P;
   for (int a = 0; a < 3; ++a) g[a] = G3[a];
+}
+
+/* The order-p expansion of one cell built from the given particles (about
+ * their centre of mass), re-expanded to order q about c and evaluated at x:
+ * Phi and grad Phi of the local expansion (the group-level route of the
+ * tree, for pinning it against the multipole and direct sums). */
+void or_local_eval(int64_t n, const double* pos, const double* mass, int order, int q,
+                   double eps, const double c[3], const double x[3], double* phi, double g[3]) {
+  or_mi_init();
+  double m = 0, mx[3] = {0, 0, 0};
+  for (int64_t j = 0; j < n; ++j) {
+    m += mass[j];
+    for (int a = 0; a < 3; ++a) mx[a] += mass[j] * pos[a * n + j];
+  }
+  double com[3] = {mx[0] / m, mx[1] / m, mx[2] / m};
+  int nm = or_nterms(order);
+  double M[4096];
+  memset(M, 0, sizeof(double) * (size_t)nm);
+  for (int64_t j = 0; j < n; ++j) {
+    for (int k = 0; k < nm; ++k) {
+      int ka, kb, kc;
+      or_mi_get(k, &ka, &kb, &kc);
+      M[k] += mass[j] * pow(pos[j] - com[0], ka) * pow(pos[n + j] - com[1], kb) *
+              pow(pos[2 * n + j] - com[2], kc);
+    }
+  }
+  double R0[3] = {c[0] - com[0], c[1] - com[1], c[2] - com[2]};
+  double Lg[4096];
+  memset(Lg, 0, sizeof(double) * (size_t)or_nterms(q));
+  local_add(order, q, eps * eps, M, R0, Lg);
+  double y[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+  *phi = 0.0;
+  g[0] = g[1] = g[2] = 0.0;
+  local_poly(q, Lg, y, phi, g);
 }
 
 /* plain open-boundary direct sum (no images): the textbook softened sum */
