@@ -102,8 +102,10 @@ typedef struct {
                       error tolerance, Sec. 2.1): a cell is accepted only
                       beyond the distance at which the Salmon & Warren bound
                       on its expansion's acceleration error, computed from
-                      sum m |x - com|^2 and the cell's extent, falls to
-                      err_tol (acceleration units); with theta > 0 as well,
+                      the cell's B_(p+1) = sum m |x - com|^(p+1) (exact at
+                      leaves, bounded from the daughters above them) and its
+                      extent, falls to err_tol (acceleration units); with
+                      theta > 0 as well,
                       the larger of the two opening radii applies.
                       0 = opening angle only.  Finite, >= 0.  A
                       fixed fraction (about 0.1) of the rms acceleration
@@ -120,6 +122,23 @@ typedef struct {
                       farther than h from every target of the group; eps
                       must be > 0.  The adjoints (hot_vjp, hot_kdk_vjp) are
                       built for Plummer softening only. */
+  int local_order; /* 0, 2 or 4.  > 0 (with local_tol > 0): group-level
+                      local expansions (the dual-tree blocking of source
+                      cells with the sinks of a sink group, Sec. 2.1).  An
+                      accepted cell whose order-p expansion, re-expanded to
+                      this order about the group's centre c (the middle of
+                      its tight box), keeps the truncation's acceleration
+                      error bound
+                        G m t^q ((q+2) - (q+1) t) / (u^2 (1-t)^2) <= local_tol,
+                      u = |c - z| - b, t = a/u < 1 (m, z, b: the cell's
+                      mass, image-shifted centre of mass and extent bound;
+                      a: half the diagonal of the group's tight box), is
+                      evaluated once per group instead of once per sink;
+                      each sink then evaluates the local polynomial.  0 =
+                      every accepted cell is evaluated at every sink.  The
+                      adjoints do not support it (HOT_EUNSUPPORTED). */
+  double local_tol; /* acceleration units, finite, >= 0; 0 = no local
+                      expansions */
 } hot_params;
 
 #define HOT_KERNEL_PLUMMER 0
@@ -158,6 +177,13 @@ typedef struct {
   int64_t m2p_lanes_tail; /* lane-steps of its tail pass (the last pass of at
                              most 32 targets: 8, 16 or 32 lanes per entry) */
   int64_t m2p_pairs_tail; /* particle-cell interactions of the tail pass */
+  int64_t m2l_entries;    /* local-list entries (cell x image) */
+  int64_t m2l_pairs;      /* particle-cell interactions they stand for (the
+                             entries times the sinks of their groups) */
+  double flops_m2l;       /* algorithmic flops of the local expansions
+                             (re-expansions and their evaluation at sinks) */
+  double ms_m2l;          /* local-expansion kernel (summed over the list
+                             chunks like ms_m2p) */
 } hot_stats;
 
 /* Host copies of the internal structures of the last hot_forces call, for
@@ -180,6 +206,8 @@ typedef struct {
   uint32_t* p2p_entry;    /* p2p_entries */
   int64_t* m2p_offset;    /* ngroups + 1 */
   uint32_t* m2p_entry;    /* m2p_entries */
+  int64_t* m2l_offset;    /* ngroups + 1: local lists (local_order > 0) */
+  uint32_t* m2l_entry;    /* hot_stats.m2l_entries */
 } hot_debug;
 
 typedef struct hot_ctx hot_ctx;
@@ -316,8 +344,8 @@ hot_status hot_kdk_block(hot_ctx* ctx, size_t n, double* pos, void* vel, const v
  * for the tree approximation of the forces at the same parameters (the
  * exact derivative of the direct sum when theta == 0).  gacc, gpot and mbar
  * use the precision type; xbar is FP64.  Same errors as hot_forces;
- * HOT_EUNSUPPORTED if the build lacks the adjoint for the order, or with the
- * K1 softening kernel. */
+ * HOT_EUNSUPPORTED if the build lacks the adjoint for the order, with the
+ * K1 softening kernel, or with group-level local expansions. */
 hot_status hot_vjp(hot_ctx* ctx, size_t n, const double* pos, const void* mass, const void* gacc,
                    const void* gpot, double* xbar, void* mbar, void* workspace, size_t ws_bytes,
                    void* stream);
@@ -397,7 +425,8 @@ hot_status hot_cell_lookup(hot_ctx* ctx, void* workspace, size_t nq, const uint6
 
 /* Copy count interaction-list entries of the last hot_forces call, starting
  * at entry first of the whole list of the given kind (0 = direct, 1 =
- * multipole; the per-group ranges are the offsets hot_debug_export gives),
+ * multipole, 2 = local; the per-group ranges are the offsets
+ * hot_debug_export gives),
  * to the host buffer out (count uint32 values, encoded as in hot_debug).
  * For checking selected sink groups' lists of a large evaluation without
  * copying all of them.  Synchronises the stream of that call.  HOT_EINVAL

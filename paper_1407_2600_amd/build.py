@@ -20,8 +20,8 @@ LIB = os.path.join(HERE, "libhot.so")
 # source in common with libhot)
 REF_LIB = os.path.join(HERE, "libhotref.so")
 REF_SOURCES = ["ewald_ref.hip", "valu_probe.hip"]
-SOURCES = ["scan.hip", "sort.hip", "tree.hip", "walk.hip", "forces.hip", "far.hip", "kdk.hip",
-           "adjoint.hip", "far_adjoint.hip", "hot_abi.hip", "ewald_table.cpp"]
+SOURCES = ["scan.hip", "sort.hip", "tree.hip", "walk.hip", "forces.hip", "local.hip", "far.hip",
+           "kdk.hip", "adjoint.hip", "far_adjoint.hip", "hot_abi.hip", "ewald_table.cpp"]
 ARCH = os.environ.get("HOT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",

@@ -42,12 +42,21 @@ hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, ui
 hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
                      size_t n, double L, void* srec, bool fp32, hipStream_t s);
 hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
-                       uint32_t gcap, double L, int periodic, uint32_t* p2p_list,
-                       uint4* m2p_list, uint32_t* status, hipStream_t s);
-hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
+                       uint32_t gcap, double L, int periodic, const LocalPrm& lp,
+                       uint32_t* p2p_list, uint4* m2p_list, uint4* m2l_list, uint32_t* status,
+                       hipStream_t s);
+hipError_t local_moments_launch(bool fp32, int order, const double* mom, uint32_t ncells,
+                                void* mt, hipStream_t s);
+hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Groups& G,
+                        uint32_t ngroups, uint32_t gcap, double L, double eps, const double* spos,
+                        size_t n, const uint4* list, const void* mt, double4* out,
+                        hipStream_t s);
+hipError_t sum_counts(const Groups& G, uint32_t ngroups, bool local, unsigned long long* sums,
+                      uint32_t* maxw,
                       hipStream_t s);
-hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* p2p_list,
-                       unsigned long long* out, unsigned long long* slots, hipStream_t s);
+hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, bool local,
+                       const uint32_t* p2p_list, unsigned long long* out,
+                       unsigned long long* slots, hipStream_t s);
 hipError_t p2p_launch(bool fp32, int kernel, const Cells& C, const Groups& G, uint32_t ngroups,
                       double L, double eps, const double* spos, const void* srec, size_t n,
                       const uint32_t* list, double4* out, hipStream_t s, const SideStream& side);
@@ -133,15 +142,15 @@ constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // words of the context's pinned host buffer (kHostWords uint32) that receive
-// the pair counters (two u64) and the multipole lane-step counters (three
-// u64) at the end of every evaluation
+// the pair counters (two u64) and the multipole lane-step and local-route
+// counters (six u64) at the end of every evaluation
 constexpr int kHostPairs = 56;
 constexpr int kHostSlots = 64;
 constexpr int kHostWords = 128;
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
-       CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
-       CTR_MAXW = 16, CTR_READ = 20, CTR_SLOTS = 24 /* three u64 at 24..29 */,
+       CTR_TL = 6, CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* three u64 at 12..17 */,
+       CTR_MAXW = 18, CTR_READ = 20, CTR_SLOTS = 24 /* six u64 at 24..35 */,
        CTR_RMAX = 60 /* block timesteps: largest rung */,
        CTR_N = 64 };
 // largest list region requested for one evaluation (4-byte words); larger
@@ -151,6 +160,9 @@ constexpr size_t kListMaxWords = size_t(1) << 30;
 constexpr size_t kListMinBytes = size_t(1) << 20;
 // workspace regions a call needs beyond the forward ones
 constexpr unsigned kNeedAdjoint = 1, kNeedSnapshot = 2, kNeedReverse = 4;
+
+// the group-level local route is in use
+bool local_on(const hot_params& p) { return p.local_order > 0 && p.local_tol > 0.0; }
 
 bool valid_params(const hot_params* p, std::string* why) {
   if (!(p->box > 0.0) || !std::isfinite(p->box)) return *why = "box must be finite and > 0", false;
@@ -171,6 +183,10 @@ bool valid_params(const hot_params* p, std::string* why) {
     return *why = "kernel must be HOT_KERNEL_PLUMMER or HOT_KERNEL_K1", false;
   if (p->kernel == HOT_KERNEL_K1 && !(p->eps > 0.0))
     return *why = "the K1 kernel needs eps > 0", false;
+  if (p->local_order != 0 && p->local_order != 2 && p->local_order != 4)
+    return *why = "local_order must be 0, 2 or 4", false;
+  if (!(p->local_tol >= 0.0 && std::isfinite(p->local_tol)))
+    return *why = "local_tol must be finite and >= 0", false;
   return true;
 }
 
@@ -229,7 +245,11 @@ Plan make_plan(const hot_ctx* c, size_t n, size_t ws_bytes, unsigned need) {
   P.o_g_cm = take(4 * Gc);
   P.o_g_op = take(4 * Gc);
   P.o_g_om = take(4 * Gc);
+  P.o_g_cl = take(4 * Gc);
+  P.o_g_ol = take(4 * Gc);
   P.o_g_act = take(Gc);
+  // local route: the cells' moments scaled for it
+  P.o_c_mloc = local_on(c->p) ? take(tsz * (size_t)NM * C) : 0;
   const int NQ = nt(c->p.far_order);
   P.o_far_part = take(8 * 8 * (size_t)NQ * kFarBlocks);
   P.o_far_mom = take(8 * 8 * (size_t)NQ);
@@ -312,6 +332,8 @@ Groups groups_of(void* ws, const Plan& P) {
   G.cnt_m2p = at<uint32_t>(ws, P.o_g_cm);
   G.off_p2p = at<uint32_t>(ws, P.o_g_op);
   G.off_m2p = at<uint32_t>(ws, P.o_g_om);
+  G.cnt_m2l = at<uint32_t>(ws, P.o_g_cl);
+  G.off_m2l = at<uint32_t>(ws, P.o_g_ol);
   G.active = nullptr;
   return G;
 }
@@ -395,11 +417,13 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   int nlev = 1;
   uint32_t ncells = 0, ngroups = 0;
   bool big = false;
-  size_t tp = 0, tm = 0;
+  size_t tp = 0, tm = 0, tl = 0;
   struct Chunk {
     uint32_t g0, g1;
-    size_t tp, tm;
+    size_t tp, tm, tl;
   };
+  const bool local = local_on(p);
+  const LocalPrm lp{local ? p.local_order : 0, local ? p.local_tol : 0.0, p.G};
   std::vector<Chunk> chunks;
 
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[0], s), "event");
@@ -411,7 +435,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     ngroups = R.ngroups;
     tp = R.tp;
     tm = R.tm;
-    chunks.push_back({0, ngroups, tp, tm});
+    chunks.push_back({0, ngroups, tp, tm, 0});
     if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[1], s), "event");
     if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
   } else {
@@ -465,6 +489,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     HOT_CHECK(tree_moments_level(C, spos, smass, n, lvl[l], lvl[l + 1] - lvl[l], p.box, p.theta,
                                  p.G, p.err_tol, k1h, p.order, fp32, s),
               "moments");
+  if (local)
+    HOT_CHECK(local_moments_launch(fp32, p.order, C.mom, ncells, at<void>(ws, P.o_c_mloc), s),
+              "local-route moments");
   uint32_t* gflag = tmp;
   uint32_t* gid = reinterpret_cast<uint32_t*>(key1);
   int32_t* gcell_at = reinterpret_cast<int32_t*>(idx1);
@@ -490,9 +517,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   // some group's pending cells overflowed the default one)
   for (;;) {
     HOT_CHECK(walk_launch(false, big, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic,
-                          nullptr, nullptr, ctr + CTR_STATUS, s),
+                          lp, nullptr, nullptr, nullptr, ctr + CTR_STATUS, s),
               "walk count");
-    HOT_CHECK(sum_counts(G, ngroups, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
+    HOT_CHECK(sum_counts(G, ngroups, local, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
                          ctr + CTR_MAXW, s),
               "list totals");
     HOT_CHECK(readback(s, ctr, host, CTR_READ), "readback");
@@ -506,13 +533,15 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     HOT_CHECK(zero_launch(ctr + CTR_STATUS, 4, s), "clear status");
     HOT_CHECK(zero_launch(ctr + CTR_SUMS, 4 * (CTR_READ - CTR_SUMS), s), "clear totals");
   }
-  unsigned long long sums[2];
+  unsigned long long sums[3];
   std::memcpy(sums, host + CTR_SUMS, sizeof(sums));
   tp = sums[0];
   tm = sums[1];
+  tl = sums[2];
   const size_t maxw = host[CTR_MAXW];
-  // list words: direct entries 1, multipole records 4, plus 16-byte alignment
-  const size_t words = tp + 4 * tm + 4;
+  // list words: direct entries 1, multipole and local records 4, plus 16-byte
+  // alignment
+  const size_t words = tp + 4 * tm + 4 * tl + 4;
   c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)words / (double)n);
   if (maxw + 4 > P.cap_list) {
     c->stats.ws_bytes_needed = make_plan(c, n, 0, need).total;
@@ -523,23 +552,28 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   // a chunk's list offsets are 32-bit words (direct) and records (multipole)
   const size_t cap = std::min(P.cap_list, (size_t)UINT32_MAX - 64);
   if (words <= cap) {
-    chunks.push_back({0, ngroups, tp, tm});
+    chunks.push_back({0, ngroups, tp, tm, tl});
   } else {
-    std::vector<uint32_t> cp(ngroups), cm(ngroups);
+    std::vector<uint32_t> cp(ngroups), cm(ngroups), cl(ngroups, 0);
     HOT_CHECK(hipMemcpyAsync(cp.data(), G.cnt_p2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
               "readback");
     HOT_CHECK(hipMemcpyAsync(cm.data(), G.cnt_m2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
               "readback");
+    if (local)
+      HOT_CHECK(hipMemcpyAsync(cl.data(), G.cnt_m2l, 4 * (size_t)ngroups, hipMemcpyDeviceToHost,
+                               s),
+                "readback");
     HOT_CHECK(hipStreamSynchronize(s), "readback");
-    Chunk ch{0, 0, 0, 0};
+    Chunk ch{0, 0, 0, 0, 0};
     for (uint32_t g = 0; g < ngroups; ++g) {
-      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g]) + 4 > cap) {
+      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g] + ch.tl + cl[g]) + 4 > cap) {
         chunks.push_back(ch);
-        ch = Chunk{g, g, 0, 0};
+        ch = Chunk{g, g, 0, 0, 0};
       }
       ch.g1 = g + 1;
       ch.tp += cp[g];
       ch.tm += cm[g];
+      ch.tl += cl[g];
     }
     chunks.push_back(ch);
   }
@@ -568,7 +602,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   uint32_t* p2p_list = at<uint32_t>(ws, P.o_list);
   size_t ck = 0;
   for (const Chunk& k : chunks) {
-    if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck], s), "event");
+    if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck], s), "event");
     const uint32_t ng = k.g1 - k.g0;
     Groups Gk = G;  // the chunk's groups (the box arrays keep their stride)
     Gk.cell += k.g0;
@@ -578,27 +612,41 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     Gk.cnt_m2p += k.g0;
     Gk.off_p2p += k.g0;
     Gk.off_m2p += k.g0;
+    Gk.cnt_m2l += k.g0;
+    Gk.off_m2l += k.g0;
     if (Gk.active) Gk.active += k.g0;
     uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
+    uint4* m2l_list = m2p_list + k.tm;
     if (!use_tree) {
       HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
       HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
-      HOT_CHECK(walk_launch(true, big, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic,
-                            p2p_list, m2p_list, ctr + CTR_STATUS, s),
+      if (local)
+        HOT_CHECK(scan_u32(Gk.cnt_m2l, Gk.off_m2l, ctr + CTR_TL, ng, scan_tmp, s), "scan");
+      HOT_CHECK(walk_launch(true, big, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic, lp,
+                            p2p_list, m2p_list, m2l_list, ctr + CTR_STATUS, s),
                 "walk emit");
-      HOT_CHECK(count_pairs(C, Gk, ng, p2p_list,
+      HOT_CHECK(count_pairs(C, Gk, ng, local, p2p_list,
                             reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS),
                             reinterpret_cast<unsigned long long*>(ctr + CTR_SLOTS), s),
                 "pair count");
     }
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
-    if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 1], s), "event");
+    if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 1], s), "event");
     if (!vjp) {
       HOT_CHECK(p2p_launch(fp32, p.kernel, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list,
                            near, s, c->side),
                 "direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
-      if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 2], s), "event");
+      if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 2], s), "event");
+      // group-level local expansions, between the direct and multipole
+      // kernels (no other kernel writes the accumulators meanwhile)
+      if (local && k.tl > 0)
+        HOT_CHECK(local_launch(fp32, p.order, p.local_order, C, Gk, ng, (uint32_t)P.cap_groups,
+                               p.box, p.kernel == HOT_KERNEL_K1 ? 0.0 : p.eps, spos, n, m2l_list,
+                               at<void>(ws, P.o_c_mloc), near, s),
+                  "local expansions");
+      if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[7], s), "event");
+      if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 3], s), "event");
       // multipoles expand the softened kernel for Plummer, the Newtonian one
       // for K1 (accepted cells lie beyond its radius)
       HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box,
@@ -610,15 +658,18 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                                s, c->side),
                 "adjoint direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
-      if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck + 2], s), "event");
+      if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[7], s), "event");
+      if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 2], s), "event");
+      if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 3], s), "event");
       HOT_CHECK(m2p_adj_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, srec, arec, ecoef, n,
                                m2p_list, adj, s, c->side),
                 "adjoint multipole kernel");
     }
     ++ck;
-    if (cev) HOT_CHECK(hipEventRecord(c->cev[3 * ck], s), "event");
+    if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck], s), "event");
   }
   if (!single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
+  if (!single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[7], s), "event");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[5], s), "event");
 
   if (!vjp) {
@@ -644,7 +695,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   HOT_CHECK(hipMemcpyAsync(c->host_buf + kHostPairs, ctr + CTR_PAIRS, 16, hipMemcpyDeviceToHost,
                            s),
             "pair counters");
-  HOT_CHECK(hipMemcpyAsync(c->host_buf + kHostSlots, ctr + CTR_SLOTS, 24, hipMemcpyDeviceToHost,
+  HOT_CHECK(hipMemcpyAsync(c->host_buf + kHostSlots, ctr + CTR_SLOTS, 48, hipMemcpyDeviceToHost,
                            s),
             "lane-step counters");
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[6], s), "event");
@@ -659,6 +710,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   st.nlevels = nlev;
   st.p2p_entries = (int64_t)tp;
   st.m2p_entries = (int64_t)tm;
+  st.m2l_entries = (int64_t)tl;
   st.list_chunks = (int64_t)chunks.size();
   st.ws_bytes_needed = P.total;
   c->have_last = 1;
@@ -755,7 +807,7 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   for (int i = 0; i < 8; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = 0;
   c->cev_ok = 1;
-  for (int i = 0; i < 3 * kChunkEvents + 1; ++i)
+  for (int i = 0; i < 4 * kChunkEvents + 1; ++i)
     if (hipEventCreate(&c->cev[i]) != hipSuccess) c->cev_ok = 0;
   (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&c->side.st, hipStreamNonBlocking) != hipSuccess ||
@@ -776,7 +828,7 @@ void hot_destroy(hot_ctx* c) {
   if (c->host_buf) (void)hipHostFree(c->host_buf);
   for (int i = 0; i < 8; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-  for (int i = 0; i < 3 * kChunkEvents + 1; ++i)
+  for (int i = 0; i < 4 * kChunkEvents + 1; ++i)
     if (c->cev[i]) (void)hipEventDestroy(c->cev[i]);
   if (c->side.st) (void)hipStreamDestroy(c->side.st);
   if (c->side.fork) (void)hipEventDestroy(c->side.fork);
@@ -1003,6 +1055,10 @@ hot_status hot_vjp(hot_ctx* c, size_t n, const double* pos, const void* mass, co
     g_err = "the adjoint is built for Plummer softening only";
     return HOT_EUNSUPPORTED;
   }
+  if (local_on(c->p)) {
+    g_err = "the adjoint is built without group-level local expansions";
+    return HOT_EUNSUPPORTED;
+  }
   if (n == 0) return HOT_OK;
   if (!pos || !mass || !gacc || !xbar || !mbar || !ws) {
     g_err = "NULL pointer argument";
@@ -1028,6 +1084,10 @@ hot_status hot_vjp_after_forces(hot_ctx* c, size_t n, const double* pos, const v
     g_err = "the adjoint is built for Plummer softening only";
     return HOT_EUNSUPPORTED;
   }
+  if (local_on(c->p)) {
+    g_err = "the adjoint is built without group-level local expansions";
+    return HOT_EUNSUPPORTED;
+  }
   if (n == 0) return HOT_OK;
   if (!pos || !mass || !gacc || !xbar || !mbar || !ws) {
     g_err = "NULL pointer argument";
@@ -1051,6 +1111,10 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
   }
   if (c->p.kernel != HOT_KERNEL_PLUMMER) {
     g_err = "the adjoint is built for Plummer softening only";
+    return HOT_EUNSUPPORTED;
+  }
+  if (local_on(c->p)) {
+    g_err = "the adjoint is built without group-level local expansions";
     return HOT_EUNSUPPORTED;
   }
   if (n == 0) return HOT_OK;
@@ -1115,27 +1179,36 @@ hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
     const hipError_t w = m->events_ok ? hipEventSynchronize(m->ev[6])
                                       : hipStreamSynchronize(m->last_stream);
     if (w == hipSuccess && m->events_ok) {
-      float t[7] = {0};
-      for (int i = 1; i <= 6; ++i) (void)hipEventElapsedTime(&t[i], m->ev[i - 1], m->ev[i]);
+      // stages: ev0 sort ev1 build ev2 walk ev3 direct ev4 local ev7
+      // multipole ev5 far ev6
+      float t[7] = {0}, tl = 0;
+      for (int i = 1; i <= 4; ++i) (void)hipEventElapsedTime(&t[i], m->ev[i - 1], m->ev[i]);
+      (void)hipEventElapsedTime(&tl, m->ev[4], m->ev[7]);
+      (void)hipEventElapsedTime(&t[5], m->ev[7], m->ev[5]);
+      (void)hipEventElapsedTime(&t[6], m->ev[5], m->ev[6]);
       float tot = 0;
       (void)hipEventElapsedTime(&tot, m->ev[0], m->ev[6]);
       if (m->last_cev > 0) {
-        // chunked lists: the emit passes count as walk, the direct and
-        // multipole kernels are summed over the chunks
-        float w = 0, d = 0, q = 0;
+        // chunked lists: the emit passes count as walk, the direct, local
+        // and multipole kernels are summed over the chunks
+        float w = 0, d = 0, l = 0, q = 0;
         for (int k = 0; k < m->last_cev; ++k) {
-          float a = 0, b = 0, e = 0;
-          (void)hipEventElapsedTime(&a, m->cev[3 * k], m->cev[3 * k + 1]);
-          (void)hipEventElapsedTime(&b, m->cev[3 * k + 1], m->cev[3 * k + 2]);
-          (void)hipEventElapsedTime(&e, m->cev[3 * k + 2], m->cev[3 * k + 3]);
+          float a = 0, b = 0, e = 0, f = 0;
+          (void)hipEventElapsedTime(&a, m->cev[4 * k], m->cev[4 * k + 1]);
+          (void)hipEventElapsedTime(&b, m->cev[4 * k + 1], m->cev[4 * k + 2]);
+          (void)hipEventElapsedTime(&e, m->cev[4 * k + 2], m->cev[4 * k + 3]);
+          (void)hipEventElapsedTime(&f, m->cev[4 * k + 3], m->cev[4 * k + 4]);
           w += a;
           d += b;
-          q += e;
+          l += e;
+          q += f;
         }
         t[3] += w;
         t[4] = d;
+        tl = l;
         t[5] = q;
       }
+      m->stats.ms_m2l = tl;
       m->stats.ms_sort = t[1];
       m->stats.ms_build = t[2];
       m->stats.ms_walk = t[3];
@@ -1151,11 +1224,14 @@ hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
       m->stats.m2p_pairs = (int64_t)pr[1];
       m->stats.flops_p2p = (double)pr[0] * kP2PFlops;
       m->stats.flops_m2p = (double)pr[1] * m2p_flops(m->p.order);
-      unsigned long long sl[3];
+      unsigned long long sl[6];
       std::memcpy(sl, m->host_buf + kHostSlots, sizeof(sl));
       m->stats.m2p_lanes_main = (int64_t)sl[0];
       m->stats.m2p_lanes_tail = (int64_t)sl[1];
       m->stats.m2p_pairs_tail = (int64_t)sl[2];
+      m->stats.m2l_pairs = (int64_t)sl[4];
+      m->stats.flops_m2l = (double)sl[3] * m2l_flops(m->p.order, m->p.local_order) +
+                           (double)sl[5] * l2p_flops(m->p.local_order);
     }
   }
   *out = m->stats;
@@ -1181,7 +1257,8 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
     g_err = "no previous hot_forces call or NULL argument";
     return HOT_EINVAL;
   }
-  if (c->last_chunks != 1 && (o->p2p_offset || o->p2p_entry || o->m2p_offset || o->m2p_entry)) {
+  if (c->last_chunks != 1 && (o->p2p_offset || o->p2p_entry || o->m2p_offset || o->m2p_entry ||
+                              o->m2l_offset || o->m2l_entry)) {
     g_err = "the last evaluation processed its lists in chunks; they are not all in memory";
     return HOT_EINVAL;
   }
@@ -1211,25 +1288,31 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
   }
   HOT_CHECK(cp(o->group_cell, P.o_g_cell, 4 * ng), "export");
   std::vector<uint32_t> cnt(ng), off(ng);
-  const size_t tp = c->stats.p2p_entries, tm = c->stats.m2p_entries;
-  for (int kind = 0; kind < 2; ++kind) {
-    int64_t* ooff = kind ? o->m2p_offset : o->p2p_offset;
-    uint32_t* oent = kind ? o->m2p_entry : o->p2p_entry;
-    if (ooff && ng) {
-      HOT_CHECK(cp(off.data(), kind ? P.o_g_om : P.o_g_op, 4 * ng), "export");
+  const size_t tp = c->stats.p2p_entries, tm = c->stats.m2p_entries,
+               tl = c->stats.m2l_entries;
+  const bool local = local_on(c->p);
+  for (int kind = 0; kind < 3; ++kind) {
+    int64_t* ooff = kind == 2 ? o->m2l_offset : kind ? o->m2p_offset : o->p2p_offset;
+    uint32_t* oent = kind == 2 ? o->m2l_entry : kind ? o->m2p_entry : o->p2p_entry;
+    const size_t tot = kind == 2 ? tl : kind ? tm : tp;
+    if (ooff && ng && (kind < 2 || local)) {
+      HOT_CHECK(cp(off.data(), kind == 2 ? P.o_g_ol : kind ? P.o_g_om : P.o_g_op, 4 * ng),
+                "export");
       for (size_t g = 0; g < ng; ++g) ooff[g] = off[g];
-      ooff[ng] = (int64_t)(kind ? tm : tp);
+      ooff[ng] = (int64_t)tot;
     } else if (ooff) {
-      ooff[0] = 0;
+      for (size_t g = 0; g <= ng; ++g) ooff[g] = 0;
     }
-    if (!oent) continue;
+    if (!oent || tot == 0) continue;
     if (kind == 0) {
       HOT_CHECK(cp(oent, P.o_list, 4 * tp), "export");
     } else {
-      // multipole records: the entry is the last word of each 16 bytes
-      std::vector<uint32_t> rec(4 * tm);
-      HOT_CHECK(cp(rec.data(), P.o_list + 4 * ((tp + 3) & ~size_t(3)), 16 * tm), "export");
-      for (size_t i = 0; i < tm; ++i) oent[i] = rec[4 * i + 3];
+      // multipole and local records: the entry is the last word of each 16
+      // bytes; the local records follow the multipole ones
+      std::vector<uint32_t> rec(4 * tot);
+      const size_t base = P.o_list + 4 * ((tp + 3) & ~size_t(3)) + (kind == 2 ? 16 * tm : 0);
+      HOT_CHECK(cp(rec.data(), base, 16 * tot), "export");
+      for (size_t i = 0; i < tot; ++i) oent[i] = rec[4 * i + 3];
     }
   }
   return HOT_OK;
@@ -1259,7 +1342,7 @@ hot_status hot_cell_lookup(hot_ctx* c, void* ws, size_t nq, const uint64_t* keys
 
 hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, int64_t count,
                                 uint32_t* out) {
-  if (!c || !c->have_last || !ws || (count > 0 && !out) || (kind != 0 && kind != 1) ||
+  if (!c || !c->have_last || !ws || (count > 0 && !out) || kind < 0 || kind > 2 ||
       first < 0 || count < 0) {
     g_err = "no previous hot_forces call or bad argument";
     return HOT_EINVAL;
@@ -1268,7 +1351,9 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
     g_err = "the last evaluation processed its lists in chunks; they are not all in memory";
     return HOT_EINVAL;
   }
-  const int64_t total = kind ? c->stats.m2p_entries : c->stats.p2p_entries;
+  const int64_t total = kind == 2 ? c->stats.m2l_entries
+                      : kind     ? c->stats.m2p_entries
+                                 : c->stats.p2p_entries;
   if (first + count > total) {
     g_err = "entry range beyond the list";
     return HOT_EINVAL;
@@ -1281,9 +1366,12 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
                         hipMemcpyDeviceToHost),
               "export");
   } else {
-    // the entry is the last word of each 16-byte multipole record
+    // the entry is the last word of each 16-byte multipole or local record
+    // (the local records follow the multipole ones)
     const size_t tp = (size_t)c->stats.p2p_entries;
-    const uint32_t* rec = at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3)) + 4 * first + 3;
+    const size_t skip = kind == 2 ? 4 * (size_t)c->stats.m2p_entries : 0;
+    const uint32_t* rec =
+        at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3)) + skip + 4 * first + 3;
     HOT_CHECK(hipMemcpy2D(out, 4, rec, 16, 4, (size_t)count, hipMemcpyDeviceToHost), "export");
   }
   return HOT_OK;

@@ -110,6 +110,29 @@ __host__ __device__ constexpr int m2p_flops(int P) {
 }
 constexpr int kP2PFlops = 20;
 
+// Algorithmic flops of the group-level local route (fma = 2): per local-list
+// entry, the derivatives D_m, |m| <= P+Q, by their recurrence (setup: s, its
+// reciprocal square root and square, the scaled R_i and the per-degree
+// factors; per component one multiply-add per nonzero m_i and per m_i >= 2
+// and the combination) and the contraction n! L_n += Mt_k D_(n+k) over
+// |n| <= Q and the stored |k| <= P (no dipole); per sink, the value and
+// gradient of the order-Q polynomial (4 fma per term) after the offset.
+__host__ __device__ constexpr int m2l_flops(int P, int Q) {
+  const int N = P + Q;
+  int f = 5 + 1 + 1 + 3 * N + 2 * N;
+  for (int d = 1; d <= N; ++d)
+    for (int a = d; a >= 0; --a)
+      for (int b = d - a; b >= 0; --b) {
+        const int c = d - a - b;
+        const int nz = (a > 0) + (b > 0) + (c > 0), n2 = (a > 1) + (b > 1) + (c > 1);
+        f += 2 * nz - 1;
+        f += n2 > 0 ? 2 * n2 - 1 + 3 : 1;
+      }
+  const int nk = nt(P) - (P >= 1 ? 3 : 0);
+  return f + 2 * nt(Q) * nk;
+}
+__host__ __device__ constexpr int l2p_flops(int Q) { return 3 + 8 * nt(Q); }
+
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its
 // own L2.  Kernels that give each wave one sink group renumber their blocks
 // so that every XCD receives one contiguous range of block indices:
@@ -153,6 +176,18 @@ struct Groups {
   uint32_t* cnt_m2p;
   uint32_t* off_p2p;
   uint32_t* off_m2p;
+  uint32_t* cnt_m2l;  // cells taken through the group's local expansion
+  uint32_t* off_m2l;
+};
+
+// Group-level local expansions: an accepted cell goes to the group's local
+// list when the truncation bound of the order-q local expansion about the
+// group's centre, G m t^q ((q+2) - (q+1) t) / (u^2 (1-t)^2) with
+// u = |c - z| - b and t = a/u, is at most tol (q = 0: never).
+struct LocalPrm {
+  int q;
+  double tol;
+  double G;
 };
 
 // list chunks whose stages are timed one by one (beyond, only the chunk
@@ -170,9 +205,9 @@ struct Plan {
   size_t o_key[2], o_idx[2], o_spos, o_smass, o_srec, o_acc, o_tmp;
   size_t o_scan, o_hist, o_ctr;
   size_t o_c_key, o_c_level, o_c_first, o_c_count, o_c_child, o_c_nchild, o_c_parent;
-  size_t o_c_mmx, o_c_walk, o_c_bnd, o_c_bk, o_c_mom, o_c_coef;
+  size_t o_c_mmx, o_c_walk, o_c_bnd, o_c_bk, o_c_mom, o_c_coef, o_c_mloc;
   size_t hcap, o_h_key, o_h_val;  // key -> cell hash (slots, key and value arrays)
-  size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om, o_g_act;
+  size_t o_g_cell, o_g_lo, o_g_hi, o_g_cp, o_g_cm, o_g_op, o_g_om, o_g_cl, o_g_ol, o_g_act;
   size_t o_far_part, o_far_mom, o_far_lam;
   size_t o_arec, o_adj, o_c_emom, o_c_ecoef, o_far_mbar;
   size_t o_kv_g, o_kv_x, o_kv_m;  // reverse leapfrog sweep: gacc, xbar and mbar of one step
@@ -250,9 +285,10 @@ struct hot_ctx {
   hipEvent_t ev[8];
   int events_ok;
   // per-chunk timing events when the lists are processed in chunks: chunk k
-  // records cev[3k] before its walk emit pass, cev[3k+1] before its direct
-  // kernel, cev[3k+2] before its multipole kernel and cev[3k+3] after it
-  hipEvent_t cev[3 * hot::kChunkEvents + 1];
+  // records cev[4k] before its walk emit pass, cev[4k+1] before its direct
+  // kernel, cev[4k+2] before its local expansions, cev[4k+3] before its
+  // multipole kernel and cev[4k+4] after it
+  hipEvent_t cev[4 * hot::kChunkEvents + 1];
   int cev_ok;
   hot::SideStream side;
 };

@@ -219,11 +219,12 @@ hipError_t kdk_adj_accum_launch(bool fp32, double* xbar, const double* tx, void*
 // direct pairs = n_A (n_A - 1 + sum of listed leaf counts); multipole pairs =
 // n_A x (list length), summed over groups
 __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t ngroups,
+                                                     int local,
                                                      const uint32_t* __restrict__ list,
                                                      unsigned long long* __restrict__ out,
                                                      unsigned long long* __restrict__ slots) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long pp = 0, mp = 0, ms = 0, ts = 0, tp = 0;
+  unsigned long long pp = 0, mp = 0, ms = 0, ts = 0, tp = 0, le = 0, lp = 0, lt = 0;
   if (g < ngroups && !(G.active && !G.active[g])) {
     const int A = G.cell[g];
     const unsigned long long na = C.count[A];
@@ -243,6 +244,13 @@ __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t
       ts = (rem <= 8 ? 8ull : rem <= 16 ? 16ull : 32ull) * cm;
       tp = rem * cm;
     }
+    // the local route: entries, the sink-cell interactions they stand for,
+    // and the sinks that evaluate a local expansion
+    if (local) {
+      le = G.cnt_m2l[g];
+      lp = na * le;
+      lt = le > 0 ? na : 0;
+    }
   }
   // wave reduction, then one atomic per wave
   for (int d = 32; d > 0; d >>= 1) {
@@ -251,6 +259,9 @@ __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t
     ms += __shfl_down(ms, d, 64);
     ts += __shfl_down(ts, d, 64);
     tp += __shfl_down(tp, d, 64);
+    le += __shfl_down(le, d, 64);
+    lp += __shfl_down(lp, d, 64);
+    lt += __shfl_down(lt, d, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     atomicAdd(&out[0], pp);
@@ -258,13 +269,18 @@ __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t
     atomicAdd(&slots[0], ms);
     atomicAdd(&slots[1], ts);
     atomicAdd(&slots[2], tp);
+    atomicAdd(&slots[3], le);
+    atomicAdd(&slots[4], lp);
+    atomicAdd(&slots[5], lt);
   }
 }
 
-hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, const uint32_t* list,
-                       unsigned long long* out, unsigned long long* slots, hipStream_t s) {
+hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, bool local,
+                       const uint32_t* list, unsigned long long* out, unsigned long long* slots,
+                       hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  k_count_pairs<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, list, out, slots);
+  k_count_pairs<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, local ? 1 : 0, list, out,
+                                                      slots);
   return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@
 //   - image 0 and the cell is the group itself: skip (the group's own
 //     particles are handled directly by the force kernel);
 //   - image 0 and the cell contains the group: open;
-//   - acceptance test passes: multipole list;
+//   - acceptance test passes: the group's local list if the local-expansion
+//     bound holds there (LocalPrm), else the multipole list;
 //   - a leaf: direct list;
 //   - otherwise: open (push the daughters).
 // Ballots and a wave prefix sum place the emitted entries and the pushed
@@ -27,8 +28,10 @@ constexpr int kWalkWaves = 4;
 template <bool EMIT, int STACK>
 __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uint32_t ngroups,
                                                           uint32_t gcap, double L, int periodic,
+                                                          LocalPrm lp,
                                                           uint32_t* __restrict__ p2p_list,
                                                           uint4* __restrict__ m2p_list,
+                                                          uint4* __restrict__ m2l_list,
                                                           uint32_t* __restrict__ status) {
   __shared__ uint32_t stack_all[kWalkWaves][STACK];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -38,6 +41,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     if (!EMIT && lane == 0) {
       G.cnt_p2p[g] = 0;
       G.cnt_m2p[g] = 0;
+      if (lp.q > 0) G.cnt_m2l[g] = 0;
     }
     return;
   }
@@ -50,6 +54,18 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   double cA[3];
   center_of(keyA, levA, L, cA);
+  // the group's local-expansion centre (middle of its tight box) and radius
+  // (half the box diagonal)
+  const bool local = lp.q > 0 && lp.tol > 0.0;
+  const double gc0 = 0.5 * (lo0 + hi0), gc1 = 0.5 * (lo1 + hi1), gc2 = 0.5 * (lo2 + hi2);
+  double ga;
+  {
+    const double e0 = hi0 - gc0, e1 = hi1 - gc1, e2 = hi2 - gc2;
+    double a2 = e0 * e0;
+    a2 = a2 + e1 * e1;
+    a2 = a2 + e2 * e2;
+    ga = sqrt(a2);
+  }
 
   uint32_t top;
   if (periodic) {
@@ -59,11 +75,12 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     if (lane == 0) st[0] = (13u << 27);
     top = 1;
   }
-  uint32_t np = 0, nm = 0;
-  uint32_t op = 0, om = 0;
+  uint32_t np = 0, nm = 0, nl = 0;
+  uint32_t op = 0, om = 0, ol = 0;
   if (EMIT) {
     op = G.off_p2p[g];
     om = G.off_m2p[g];
+    if (local) ol = G.off_m2l[g];
   }
   wave_sync();
   while (top > 0) {
@@ -80,7 +97,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     wave_sync();
     const int img = (int)(e >> 27);
     const int B = (int)(e & kCellMask);
-    // 0 none, 1 open, 2 multipole, 3 direct
+    // 0 none, 1 open, 2 multipole, 3 direct, 4 local
     int action = 0;
     int nch = 0, ch0 = 0;
     double cc0 = 0.0, cc1 = 0.0, cc2 = 0.0;  // image-shifted centre of mass
@@ -113,9 +130,33 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
           dd = dd + d1 * d1;
           dd = dd + d2 * d2;
           const double rc2 = w.w * w.w;
-          if (rc2 < dd)
+          if (rc2 < dd) {
             action = 2;
-          else if (nch == 0)
+            if (local) {
+              // truncation bound of the group's local expansion (IEEE
+              // operations in a fixed order)
+              const double m = C.mmx[B].x, b = C.bnd[B].y;
+              const double r0 = gc0 - c0, r1 = gc1 - c1, r2 = gc2 - c2;
+              double rr = r0 * r0;
+              rr = rr + r1 * r1;
+              rr = rr + r2 * r2;
+              const double u = sqrt(rr) - b;
+              if (u > ga) {
+                const double t = ga / u;
+                double tq = t;
+                for (int i = 1; i < lp.q; ++i) tq = tq * t;
+                double num = lp.G * m;
+                num = num * tq;
+                num = num * ((double)(lp.q + 2) - (double)(lp.q + 1) * t);
+                const double w1 = 1.0 - t;
+                double den = u * u;
+                den = den * w1;
+                den = den * w1;
+                den = lp.tol * den;
+                if (num <= den) action = 4;
+              }
+            }
+          } else if (nch == 0)
             action = 3;
           else
             action = 1;
@@ -124,7 +165,14 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     }
     const uint64_t bm = __ballot(action == 2);
     const uint64_t bp = __ballot(action == 3);
+    const uint64_t bl = __ballot(action == 4);
     if (EMIT) {
+      // local records: the offset of the group's centre from the cell's
+      // image-shifted centre of mass, c - z
+      if (action == 4)
+        m2l_list[ol + nl + (uint32_t)__popcll(bl & below)] =
+            make_uint4(__float_as_uint((float)(gc0 - cc0)), __float_as_uint((float)(gc1 - cc1)),
+                       __float_as_uint((float)(gc2 - cc2)), e);
       if (action == 2)
         m2p_list[om + nm + (uint32_t)__popcll(bm & below)] =
             make_uint4(__float_as_uint((float)(cc0 - cA[0])), __float_as_uint((float)(cc1 - cA[1])),
@@ -133,6 +181,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     }
     nm += (uint32_t)__popcll(bm);
     np += (uint32_t)__popcll(bp);
+    nl += (uint32_t)__popcll(bl);
     // push the daughters of opened cells
     uint32_t cnt = (action == 1) ? (uint32_t)nch : 0u;
     uint32_t inc = cnt;
@@ -150,60 +199,66 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   if (!EMIT && lane == 0) {
     G.cnt_p2p[g] = np;
     G.cnt_m2p[g] = nm;
+    if (local) G.cnt_m2l[g] = nl;
   }
 }
 
 // 64-bit totals of the per-group list counts, and the largest group's list
-// size in 4-byte words (a direct entry is one word, a multipole record four)
-__global__ void __launch_bounds__(256) k_sum_counts(Groups G, uint32_t ngroups,
+// size in 4-byte words (a direct entry is one word, a multipole or local
+// record four)
+__global__ void __launch_bounds__(256) k_sum_counts(Groups G, uint32_t ngroups, int local,
                                                     unsigned long long* __restrict__ sums,
                                                     uint32_t* __restrict__ maxw) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long p = 0, m = 0;
+  unsigned long long p = 0, m = 0, l = 0;
   uint32_t w = 0;
   if (g < ngroups) {
     p = G.cnt_p2p[g];
     m = G.cnt_m2p[g];
-    w = (uint32_t)(p + 4 * m);
+    if (local) l = G.cnt_m2l[g];
+    w = (uint32_t)(p + 4 * m + 4 * l);
   }
   for (int d = 32; d > 0; d >>= 1) {
     p += __shfl_down(p, d, 64);
     m += __shfl_down(m, d, 64);
+    l += __shfl_down(l, d, 64);
     const uint32_t o = __shfl_down(w, d, 64);
     w = o > w ? o : w;
   }
   if ((threadIdx.x & 63) == 0) {
     atomicAdd(&sums[0], p);
     atomicAdd(&sums[1], m);
+    atomicAdd(&sums[2], l);
     atomicMax(maxw, w);
   }
 }
 
-hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
-                      hipStream_t s) {
+hipError_t sum_counts(const Groups& G, uint32_t ngroups, bool local, unsigned long long* sums,
+                      uint32_t* maxw, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  k_sum_counts<<<(ngroups + 255) / 256, 256, 0, s>>>(G, ngroups, sums, maxw);
+  k_sum_counts<<<(ngroups + 255) / 256, 256, 0, s>>>(G, ngroups, local ? 1 : 0, sums, maxw);
   return hipGetLastError();
 }
 
 hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
-                       uint32_t gcap, double L, int periodic, uint32_t* p2p_list, uint4* m2p_list,
-                       uint32_t* status, hipStream_t s) {
+                       uint32_t gcap, double L, int periodic, const LocalPrm& lp,
+                       uint32_t* p2p_list, uint4* m2p_list, uint4* m2l_list, uint32_t* status,
+                       hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   const unsigned blocks = (ngroups + kWalkWaves - 1) / kWalkWaves;
   const unsigned th = 64 * kWalkWaves;
   if (emit && big)
-    k_walk<true, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
-                                                      m2p_list, status);
+    k_walk<true, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
+                                                      p2p_list, m2p_list, m2l_list, status);
   else if (emit)
-    k_walk<true, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
-                                                   m2p_list, status);
+    k_walk<true, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
+                                                   p2p_list, m2p_list, m2l_list, status);
   else if (big)
-    k_walk<false, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
-                                                       m2p_list, status);
+    k_walk<false, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
+                                                       p2p_list, m2p_list, m2l_list, status);
   else
-    k_walk<false, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, p2p_list,
-                                                    m2p_list, status);
+    k_walk<false, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
+                                                    p2p_list, m2p_list, m2l_list, status);
   return hipGetLastError();
 }
 

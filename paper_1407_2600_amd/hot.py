@@ -41,7 +41,8 @@ class hot_params(C.Structure):
     _fields_ = [("box", C.c_double), ("G", C.c_double), ("eps", C.c_double),
                 ("theta", C.c_double), ("order", C.c_int), ("periodic", C.c_int),
                 ("leaf_max", C.c_int), ("group_max", C.c_int), ("far_order", C.c_int),
-                ("precision", C.c_int), ("err_tol", C.c_double), ("kernel", C.c_int)]
+                ("precision", C.c_int), ("err_tol", C.c_double), ("kernel", C.c_int),
+                ("local_order", C.c_int), ("local_tol", C.c_double)]
 
 
 class hot_stats(C.Structure):
@@ -53,7 +54,8 @@ class hot_stats(C.Structure):
                 ("ms_m2p", C.c_double), ("ms_far", C.c_double), ("ws_bytes_needed", C.c_size_t),
                 ("kdk_steps_done", C.c_int64), ("list_chunks", C.c_int64),
                 ("m2p_lanes_main", C.c_int64), ("m2p_lanes_tail", C.c_int64),
-                ("m2p_pairs_tail", C.c_int64)]
+                ("m2p_pairs_tail", C.c_int64), ("m2l_entries", C.c_int64),
+                ("m2l_pairs", C.c_int64), ("flops_m2l", C.c_double), ("ms_m2l", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +67,8 @@ class hot_debug(C.Structure):
                 ("cell_count", C.c_void_p), ("cell_com", C.c_void_p), ("cell_mass", C.c_void_p),
                 ("group_cell", C.c_void_p), ("p2p_offset", C.c_void_p),
                 ("p2p_entry", C.c_void_p), ("m2p_offset", C.c_void_p),
-                ("m2p_entry", C.c_void_p)]
+                ("m2p_entry", C.c_void_p), ("m2l_offset", C.c_void_p),
+                ("m2l_entry", C.c_void_p)]
 
 
 _lib = None
@@ -132,13 +135,13 @@ KERNELS = {"plummer": HOT_KERNEL_PLUMMER, "k1": HOT_KERNEL_K1, 0: 0, 1: 1}
 
 def make_params(box=1.0, G=1.0, eps=0.0, theta=0.5, order=4, periodic=1, leaf_max=16,
                 group_max=64, far_order=8, precision="fp64", err_tol=0.0, kernel="plummer",
-                **_ignored) -> hot_params:
+                local_order=0, local_tol=0.0, **_ignored) -> hot_params:
     prec = precision
     if isinstance(prec, str):
         prec = {"fp64": HOT_FP64, "fp32": HOT_FP32}[prec]
     return hot_params(float(box), float(G), float(eps), float(theta), int(order), int(periodic),
                       int(leaf_max), int(group_max), int(far_order), int(prec), float(err_tol),
-                      KERNELS[kernel])
+                      KERNELS[kernel], int(local_order), float(local_tol))
 
 
 def far_table(far_order: int, box: float = 1.0, offset: int = 13):
@@ -404,8 +407,9 @@ class Gravity:
         return out
 
     def debug_list_range(self, kind: int, first: int, count: int):
-        """count entries of the last forces() call's direct (kind 0) or
-        multipole (kind 1) list, from entry first (host uint32 array)."""
+        """count entries of the last forces() call's direct (kind 0),
+        multipole (kind 1) or local (kind 2) list, from entry first (host
+        uint32 array)."""
         import numpy as np
         out = np.zeros(int(count), np.uint32)
         check(self.L.hot_debug_list_range(self.h, C.c_void_p(self.ws.data_ptr()), int(kind),
@@ -421,19 +425,22 @@ class Gravity:
         sizes = [C.c_int64() for _ in range(5)]
         check(self.L.hot_debug_sizes(self.h, *[C.byref(x) for x in sizes]))
         n, nc, ng, tp, tm = [x.value for x in sizes]
-        single = self.stats()["list_chunks"] == 1
+        st = self.stats()
+        single = st["list_chunks"] == 1
+        tl = st["m2l_entries"]
         if not lists:
-            tp = tm = 0
+            tp = tm = tl = 0
         out = dict(sorted_keys=np.zeros(n, np.uint64), perm=np.zeros(n, np.uint32),
                    cell_key=np.zeros(nc, np.uint64), cell_level=np.zeros(nc, np.int32),
                    cell_first=np.zeros(nc, np.int32), cell_count=np.zeros(nc, np.int32),
                    cell_com=np.zeros((3, nc)), cell_mass=np.zeros(nc),
                    group_cell=np.zeros(ng, np.int32), p2p_offset=np.zeros(ng + 1, np.int64),
                    p2p_entry=np.zeros(tp, np.uint32), m2p_offset=np.zeros(ng + 1, np.int64),
-                   m2p_entry=np.zeros(tm, np.uint32))
-        skip = () if lists else ("p2p_entry", "m2p_entry")
+                   m2p_entry=np.zeros(tm, np.uint32), m2l_offset=np.zeros(ng + 1, np.int64),
+                   m2l_entry=np.zeros(tl, np.uint32))
+        skip = () if lists else ("p2p_entry", "m2p_entry", "m2l_entry")
         if not single:
-            skip = skip + ("p2p_offset", "m2p_offset")
+            skip = skip + ("p2p_offset", "m2p_offset", "m2l_offset")
         dbg = hot_debug(*[C.c_void_p(None if f in skip else out[f].ctypes.data)
                           for f, _ in hot_debug._fields_])
         check(self.L.hot_debug_export(self.h, C.c_void_p(self.ws.data_ptr()), C.byref(dbg)))

@@ -54,8 +54,8 @@ def compare_sampled_lists(grav, dbg, T, sample_groups):
     c = T.cells()
     gcell_o, _, _ = T.groups()
     gpu_group = {int(ck[x]): i for i, x in enumerate(dbg["group_cell"])}
-    for kind in (0, 1):
-        off = dbg["m2p_offset" if kind else "p2p_offset"]
+    for kind in (0, 1, 2):
+        off = dbg[LIST_KEYS[kind][0]]
         for g in sample_groups:
             i = gpu_group[int(c["key"][gcell_o[g]])]
             e = grav.debug_list_range(kind, off[i], off[i + 1] - off[i]).astype(np.int64)
@@ -76,11 +76,17 @@ def max_err(a, ref):
     return float(np.max(d) / np.sqrt(np.mean(np.sum(ref ** 2, axis=0))))
 
 
+# export keys of the list kinds: direct, multipole, local (group-level
+# expansions)
+LIST_KEYS = {0: ("p2p_offset", "p2p_entry"), 1: ("m2p_offset", "m2p_entry"),
+             2: ("m2l_offset", "m2l_entry")}
+
+
 def group_lists_gpu(dbg, kind):
     """{group cell key: sorted list of (image, cell key)} from the GPU export."""
     ck = dbg["cell_key"]
-    off = dbg["m2p_offset" if kind else "p2p_offset"]
-    ent = dbg["m2p_entry" if kind else "p2p_entry"]
+    off = dbg[LIST_KEYS[kind][0]]
+    ent = dbg[LIST_KEYS[kind][1]]
     out = {}
     for g, c in enumerate(dbg["group_cell"]):
         e = ent[off[g]:off[g + 1]].astype(np.int64)
@@ -118,7 +124,7 @@ def compare_structure(dbg, T, sample_groups=None, lists=True):
     gk_gpu = sorted(int(dbg["cell_key"][x]) for x in dbg["group_cell"])
     gk_o = sorted(int(c["key"][x]) for x in gcell_o)
     assert gk_gpu == gk_o
-    for kind in ((0, 1) if lists else ()):
+    for kind in ((0, 1, 2) if lists else ()):
         lg = group_lists_gpu(dbg, kind)
         groups = range(len(gcell_o)) if sample_groups is None else sample_groups
         for g in groups:

@@ -60,7 +60,10 @@ def test_version_and_error_strings():
                                  dict(periodic=2), dict(precision=7), dict(group_max=0),
                                  dict(err_tol=-1e-3), dict(err_tol=float("nan")),
                                  dict(err_tol=float("inf")), dict(kernel=2),
-                                 dict(kernel="k1", eps=0.0)])
+                                 dict(kernel="k1", eps=0.0), dict(local_order=3),
+                                 dict(local_order=6), dict(local_order=-2),
+                                 dict(local_order=4, local_tol=-1e-3),
+                                 dict(local_order=4, local_tol=float("nan"))])
 def test_create_rejects_bad_parameters(bad):
     L = hot.lib()
     prm = hot.make_params(**dict(dict(eps=0.01), **{k: v for k, v in bad.items()

@@ -1,0 +1,126 @@
+"""GPU parity of the group-level local expansions (the dual-tree route of
+paper Sec. 2.1: an accepted cell far from the whole sink group is re-expanded
+once about the group's centre and each sink evaluates the local polynomial).
+The three lists (direct, multipole, local) must match the oracle's bit for
+bit, and the forces the oracle's to the usual bounds, at several orders,
+both precisions, both softening kernels, with the lists processed in chunks,
+and inside block timesteps."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from _gpu import compare_structure, max_err, oracle_mass, pot_ok, rms_err, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-5, "fp32": 2e-5}
+MAX_TOL = {"fp64": 1e-4, "fp32": 2e-4}
+
+CASES = [
+    # name, n_side, overrides (each case has a large share of local entries)
+    ("zeldovich128", 20, dict(theta=0.8, err_tol=2e-3, local_order=4, local_tol=2e-4)),
+    ("nfw256", 16, dict(leaf_max=8, group_max=32, theta=0.0, err_tol=2e-3, local_order=4,
+                        local_tol=2e-3)),
+    ("lattice16", 16, dict(order=2, err_tol=5e-3, local_order=2, local_tol=1e-3)),
+    ("zeldovich128", 16, dict(order=3, theta=0.6, local_order=4, local_tol=1e-3)),
+    ("zeldovich128", 20, dict(theta=0.8, err_tol=2e-3, local_order=2, local_tol=1e-3,
+                              kernel="k1")),
+]
+
+
+def _case(name, ns, over):
+    pos, mass, prm = workloads.make(name, n_side=ns)
+    return pos, mass, dict(prm, **over)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,ns,over", CASES)
+def test_lists_and_forces(name, ns, over, precision):
+    pos, mass, prm = _case(name, ns, over)
+    print(f"case {name} n_side={ns} {over} {precision}", flush=True)
+    mo = oracle_mass(mass, precision)
+    T = oracle.Tree(pos, mo, prm)
+    r = run_gpu(pos, mass, prm, precision)
+    st = r["stats"]
+    assert st["m2l_entries"] == len(T.lists(2)[2]) > 0.1 * st["m2p_entries"]
+    compare_structure(r["dbg"], T)
+    acc_o, pot_o = T.forces()
+    ea, em = rms_err(r["acc"], acc_o), max_err(r["acc"], acc_o)
+    ok, ep = pot_ok(r["pot"], pot_o, precision, prm, mo)
+    print(f"  local entries {st['m2l_entries']} (multipole {st['m2p_entries']}): acc err "
+          f"{ea:.3e} (max {em:.3e}) pot err {ep:.3e}", flush=True)
+    assert ea <= TOL[precision] and em <= MAX_TOL[precision] and ok
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chunked_lists_match_single_pass(precision):
+    """Lists built and consumed in chunks of sink groups (a workspace near the
+    minimum) give the same forces bit for bit."""
+    import torch
+    from paper_1407_2600_amd import Gravity
+    pos, mass, prm = _case("nfw256", 20, dict(leaf_max=8, group_max=32, theta=0.5,
+                                              err_tol=5e-3, local_order=4, local_tol=5e-3))
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    P = torch.as_tensor(pos, device="cuda")
+    M = torch.as_tensor(mass, dtype=dt, device="cuda")
+    g1 = Gravity(precision=precision, **prm)
+    g1.forces(P, M)
+    a1, p1 = g1.forces(P, M)
+    torch.cuda.synchronize()
+    s1 = g1.stats()
+    assert s1["list_chunks"] == 1 and s1["m2l_entries"] > 0
+    wmin = g1.L.hot_workspace_size_min(g1.h, pos.shape[1], 1)
+    g2 = Gravity(precision=precision, workspace_bytes=wmin, **prm)
+    a2, p2 = g2.forces(P, M)
+    torch.cuda.synchronize()
+    s2 = g2.stats()
+    print(f"chunks {s2['list_chunks']}, local entries {s2['m2l_entries']}", flush=True)
+    assert s2["list_chunks"] > 1
+    assert (s2["m2l_entries"], s2["m2l_pairs"]) == (s1["m2l_entries"], s1["m2l_pairs"])
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
+def test_block_steps_with_local_expansions():
+    """Block timesteps evaluate only the groups holding a due particle; their
+    local expansions too.  Against the oracle's integrator (FP64)."""
+    import torch
+    from paper_1407_2600_amd import Gravity
+    pos, mass, prm = workloads.make("nfw256", n_side=10)
+    prm = dict(prm, theta=0.5, leaf_max=8, group_max=32, eps=0.3 / 10, local_order=4,
+               local_tol=2e-2)
+    vel = np.random.default_rng(2).normal(scale=0.01, size=pos.shape)
+    dt, R, eta = 0.01, 3, 0.1
+    xo, vo, ao, po, ro, nev = oracle.kdk_block(pos, vel, mass, prm, dt, R, eta, 2)
+    g = Gravity(precision="fp64", **prm)
+    P = torch.as_tensor(pos, device="cuda").contiguous()
+    V = torch.as_tensor(vel, device="cuda").contiguous()
+    M = torch.as_tensor(mass, device="cuda")
+    A = torch.empty_like(V)
+    Rg = torch.zeros(pos.shape[1], dtype=torch.uint8, device="cuda")
+    g.kdk_block(P, V, M, A, Rg, acc_valid=False, dt=dt, max_rung=R, eta=eta, nsteps=2,
+                rung_valid=False)
+    torch.cuda.synchronize()
+    assert g.stats()["m2l_entries"] > 0
+    r = Rg.cpu().numpy().astype(np.int64)
+    assert len(np.unique(ro)) >= 3
+    np.testing.assert_array_equal(r, ro)
+    d = P.cpu().numpy() - xo
+    d -= np.round(d)
+    assert np.max(np.abs(d)) < 1e-11
+    assert oracle.rms_rel_error(V.cpu().numpy(), vo) < 1e-9
+    assert oracle.rms_rel_error(A.cpu().numpy(), ao) < 1e-9
+
+
+def test_adjoint_refuses_local_expansions():
+    import torch
+    from paper_1407_2600_amd import Gravity
+    from paper_1407_2600_amd.hot import HOT_EUNSUPPORTED, HotError
+    pos, mass, prm = _case("zeldovich128", 8, dict(theta=0.6, local_order=4, local_tol=1e-3))
+    g = Gravity(precision="fp64", **prm)
+    P = torch.as_tensor(pos, device="cuda")
+    M = torch.as_tensor(mass, device="cuda")
+    g.forces(P, M)
+    with pytest.raises(HotError) as e:
+        g.vjp(P, M, torch.zeros_like(P), None)
+    assert e.value.status == HOT_EUNSUPPORTED
