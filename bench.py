@@ -48,27 +48,38 @@ ERR_TARGET = 1e-3
 # --search on the selection targets; the error reported by a default run is
 # measured on held-out targets that played no part in the choice.
 OPERATING_POINT = {
-    # 0.15 of a_rms = 0.0488: selection error 9.08e-4
-    "zeldovich128": dict(theta=0.8, err_tol=7.31e-3, leaf_max=16, group_max=128),
+    # 0.12 of a_rms = 0.0488, group-level local expansions of order 4 at
+    # 0.002 of a_rms: selection error 8.98e-4 (without them the best
+    # setting was 0.15 of a_rms at 9.08e-4 and 1.6x the time)
+    "zeldovich128": dict(theta=0.8, err_tol=5.85e-3, leaf_max=16, group_max=128, local_order=4,
+                         local_tol=9.75e-5),
     # 1.6 of a_rms = 43.0: selection error 8.92e-4 (the clustered set's
     # leaf/group sizes run faster at lower error: its sparse background
     # otherwise splits into many small groups)
     "nfw256": dict(theta=0.0, err_tol=68.8, leaf_max=32, group_max=256),
-    # 0.102 of a_rms = 0.01857, between the searched 0.09 (selection error
-    # 8.06e-4) and 0.11 (9.59e-4); leaf 64 keeps the cells within the 27-bit
-    # cell index of a list entry (the paper ends its traversal below ~80
-    # particles)
-    "zeldovich1024": dict(theta=0.8, err_tol=1.9e-3, leaf_max=64, group_max=128),
+    # 0.09 of a_rms = 0.01857 with local expansions of order 4 at 0.0035 of
+    # a_rms: selection error 8.61e-4 (without them 0.102 of a_rms, between
+    # the searched 0.09 at 8.06e-4 and 0.11 at 9.59e-4, at 2.6x the time);
+    # leaf 64 keeps the cells within the 27-bit cell index of a list entry
+    # (the paper ends its traversal below ~80 particles)
+    "zeldovich1024": dict(theta=0.8, err_tol=1.67e-3, leaf_max=64, group_max=128, local_order=4,
+                          local_tol=6.5e-5),
 }
 # --search grids: tolerances as fractions of the rms acceleration, opening-
 # angle caps (0 = none), and opening angles alone
 ETA_GRID = {"zeldovich128": (0.06, 0.08, 0.1, 0.12, 0.15, 0.18, 0.22, 0.27, 0.33),
             "nfw256": (0.8, 1.2, 1.6, 2.4, 3.5, 5.0, 7.0, 10.0),
-            "zeldovich1024": (0.07, 0.09, 0.11, 0.13, 0.16)}
+            "zeldovich1024": (0.09, 0.11, 0.13)}
 THETA_CAPS = {"zeldovich128": (0.0, 0.7, 0.8, 0.9), "nfw256": (0.0, 0.8),
               "zeldovich1024": (0.8,)}
 THETAS = {"zeldovich128": (0.40, 0.44, 0.46, 0.47, 0.48, 0.50), "nfw256": (0.3, 0.5, 0.7),
           "zeldovich1024": ()}
+# group-level local expansions in the search: their order, and truncation
+# tolerances as fractions of the rms acceleration (0 = none)
+LOCAL_ORDER = 4
+LOCAL_FRACS = {"zeldovich128": (0.0, 0.001, 0.002, 0.003, 0.004),
+               "nfw256": (0.0, 0.01, 0.03, 0.1),
+               "zeldovich1024": (0.0, 0.0015, 0.0025, 0.0035)}
 # list region beside the minimum workspace at 1024^3 (the lists are processed
 # in chunks of groups that fit it)
 PAPER_SCALE_LIST_BYTES = 16 << 30
@@ -106,12 +117,18 @@ def parse():
                          "OPERATING_POINT")
     ap.add_argument("--theta", type=float, default=None, help="override the opening-angle cap")
     ap.add_argument("--err-tol", type=float, default=None, help="override the tolerance")
+    ap.add_argument("--local-order", type=int, default=None,
+                    help="override the order of the group-level local expansions (0 = none)")
+    ap.add_argument("--local-tol", type=float, default=None,
+                    help="override their truncation tolerance")
     ap.add_argument("--n-side", type=int, default=None, help="smaller grid (debug only)")
     ap.add_argument("--no-extras", action="store_true",
                     help="1024^3 run only: skip the 128^3 ratios and the trajectory adjoint")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true",
                     help="skip the differentiation-workload timing")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint timing (for profiling runs of the forward path)")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--valu-probe", action="store_true",
@@ -140,11 +157,11 @@ def copy_calibration():
 # counter runs summarised in profiles/k_m2p_zeldovich128_hbm_counters.md.
 # They hold only for the sources and the configuration they were taken with;
 # otherwise the roofline reports traffic as null.
-TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": 2.698e+09,
-           "config": {"theta": 0.8, "err_tol": 0.00731, "order": 4, "leaf_max": 16,
-                      "group_max": 128, "far_order": 8},
+TRAFFIC = {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_launch": None,
+           "config": {"theta": 0.8, "err_tol": 5.85e-3, "order": 4, "leaf_max": 16,
+                      "group_max": 128, "far_order": 8, "local_order": 4, "local_tol": 9.75e-5},
            "sources": ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"],
-           "sha256": "22cece326be8e1f0783266ce3a2b44adde97448e6693a5a43961cdc4b88fe14d"}
+           "sha256": ""}
 
 
 def measured_traffic(prm, workload):
@@ -195,30 +212,32 @@ def max_err(a, ref):
 def roofline(st, order, workload, prm):
     """The dominant force kernel (FP32): algorithmic flops of one evaluation
     over its HIP-event time (summed over the list chunks), against the FP32
-    peak; and the other force kernel's rate."""
-    dom = "m2p" if st["ms_m2p"] >= st["ms_p2p"] else "p2p"
-    other = "p2p" if dom == "m2p" else "m2p"
+    peak; and the other force kernels' rates."""
+    names = {"m2p": f"k_m2p<{order},float>", "p2p": "k_p2p<float>",
+             "m2l": f"k_m2l<{order},{prm.get('local_order', 0)},float>"}
+    dom = max(("m2p", "p2p", "m2l"), key=lambda k: st[f"ms_{k}"])
     ms, fl = st[f"ms_{dom}"], st[f"flops_{dom}"]
     achieved = fl / (ms * 1e-3) / 1e12
-    roof = {"kernel": f"k_m2p<{order},float>" if dom == "m2p" else "k_p2p<float>",
+    roof = {"kernel": names[dom],
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": (measured_traffic(prm, workload) if dom == "m2p" and order == 4 else None),
             "flops_per_eval": fl, "ms_per_eval": ms, "launches_per_eval": st["list_chunks"]}
-    ro = {"kernel": other, "ms_per_eval": st[f"ms_{other}"],
-          "achieved": (st[f"flops_{other}"] / (st[f"ms_{other}"] * 1e-3) / 1e12
-                       if st[f"ms_{other}"] > 0 else None)}
+    ro = [{"kernel": names[k], "ms_per_eval": st[f"ms_{k}"],
+           "achieved": (st[f"flops_{k}"] / (st[f"ms_{k}"] * 1e-3) / 1e12
+                        if st[f"ms_{k}"] > 0 else None)}
+          for k in ("m2p", "p2p", "m2l") if k != dom and st[f"ms_{k}"] > 0]
     return roof, ro
 
 
 class StepStats:
     """Per-step sums of the library's stage times, pair counts and flops."""
-    KEYS = ("ms_sort", "ms_build", "ms_walk", "ms_p2p", "ms_m2p", "ms_far", "ms_total")
+    KEYS = ("ms_sort", "ms_build", "ms_walk", "ms_p2p", "ms_m2l", "ms_m2p", "ms_far", "ms_total")
 
     def __init__(self):
         self.k = {k: 0.0 for k in self.KEYS}
-        self.pairs = {"p2p": 0.0, "m2p": 0.0}
-        self.flops = {"p2p": 0.0, "m2p": 0.0}
+        self.pairs = {"p2p": 0.0, "m2p": 0.0, "m2l": 0.0}
+        self.flops = {"p2p": 0.0, "m2p": 0.0, "m2l": 0.0}
         self.ncells = 0.0
         self.steps = 0
         self.last = None
@@ -226,7 +245,7 @@ class StepStats:
     def add(self, st):
         for k in self.KEYS:
             self.k[k] += st[k]
-        for q in ("p2p", "m2p"):
+        for q in ("p2p", "m2p", "m2l"):
             self.pairs[q] += st[f"{q}_pairs"]
             self.flops[q] += st[f"flops_{q}"]
         self.ncells += st["ncells"]
@@ -237,11 +256,20 @@ class StepStats:
         s = max(self.steps, 1)
         st = dict(self.last)
         st.update({k: v / s for k, v in self.k.items()})
-        for q in ("p2p", "m2p"):
+        for q in ("p2p", "m2p", "m2l"):
             st[f"{q}_pairs"] = self.pairs[q] / s
             st[f"flops_{q}"] = self.flops[q] / s
         st["ncells"] = self.ncells / s
         return st
+
+
+def pairs(st):
+    """Interactions per evaluation: particle pairs of the direct kernel, and
+    the particle-cell interactions taken by the multipole kernel and through
+    the groups' local expansions (with the local-list entries that carry the
+    latter)."""
+    return {"p2p": st["p2p_pairs"], "m2p": st["m2p_pairs"], "m2l": st["m2l_pairs"],
+            "m2l_entries": st["m2l_entries"]}
 
 
 def lane_use(st):
@@ -257,29 +285,49 @@ def lane_use(st):
             "tail": tp / tail if tail else None, "tail_pair_share": tp / mp if mp else None}
 
 
+# the parameters --search chooses
+SEARCHED = ("theta", "err_tol", "local_order", "local_tol")
+
+
+def overrides(prm, args):
+    """The operating point with the command line's overrides."""
+    for k, a in (("theta", args.theta), ("err_tol", args.err_tol),
+                 ("local_order", args.local_order), ("local_tol", args.local_tol)):
+        if a is not None:
+            prm[k] = a
+    return prm
+
+
 def search(torch, Gravity, pos, mass, prm, tg, aref, dev, workload, **ctx):
     """The fastest setting of the searched grids whose FP32 rms force error
     on the selection targets tg is at most ERR_TARGET."""
     a_rms = float(np.sqrt(np.mean(np.sum(aref ** 2, axis=0))))
     rows = []
-    cands = [dict(theta=cap, err_tol=float(f"{eta * a_rms:.3g}")) for cap in THETA_CAPS[workload]
-             for eta in ETA_GRID[workload]]
-    cands += [dict(theta=th, err_tol=0.0) for th in THETAS[workload]]
+    base = [dict(theta=cap, err_tol=float(f"{eta * a_rms:.3g}")) for cap in THETA_CAPS[workload]
+            for eta in ETA_GRID[workload]]
+    base += [dict(theta=th, err_tol=0.0) for th in THETAS[workload]]
+    cands = [dict(b, local_order=LOCAL_ORDER if lf > 0 else 0,
+                  local_tol=float(f"{lf * a_rms:.3g}") if lf > 0 else 0.0)
+             for b in base for lf in LOCAL_FRACS[workload]]
     n = pos.shape[1]
     a = torch.empty((3, n), dtype=mass.dtype, device=dev)
     pt = torch.empty(n, dtype=mass.dtype, device=dev)
     for c in cands:
         g = Gravity(device=dev, **ctx, **dict(prm, **c))
         g.forces(pos, mass, out_acc=a, out_pot=pt)
-        g.forces(pos, mass, out_acc=a, out_pot=pt)  # the second call runs with a sized workspace
+        if "list_bytes" not in ctx:  # the second call runs with a sized workspace
+            g.forces(pos, mass, out_acc=a, out_pot=pt)
         torch.cuda.synchronize()
         st = g.stats()
         e = rms_err(a[:, torch.as_tensor(tg, device=dev)].double().cpu().numpy(), aref)
         r = dict(c, err=e, ms_force=st["ms_total"], m2p_per_particle=st["m2p_pairs"] / st["n"],
-                 p2p_per_particle=st["p2p_pairs"] / st["n"], eta=c["err_tol"] / a_rms)
+                 p2p_per_particle=st["p2p_pairs"] / st["n"],
+                 m2l_per_particle=st["m2l_pairs"] / st["n"], eta=c["err_tol"] / a_rms,
+                 eta_local=c["local_tol"] / a_rms)
         rows.append(r)
         print(f"[bench] search {c} err={e:.3e} ms={st['ms_total']:.2f} "
-              f"m2p/particle={r['m2p_per_particle']:.1f} p2p/particle={r['p2p_per_particle']:.1f}",
+              f"m2p/particle={r['m2p_per_particle']:.1f} p2p/particle={r['p2p_per_particle']:.1f} "
+              f"local/particle={r['m2l_per_particle']:.1f}",
               file=sys.stderr, flush=True)
         del g
         torch.cuda.empty_cache()
@@ -311,11 +359,7 @@ def paper_scale(args):
     n = pos.shape[1]
     print(f"[bench] {n} particles generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
           flush=True)
-    op = dict(OPERATING_POINT["zeldovich1024"])
-    if args.theta is not None:
-        op["theta"] = args.theta
-    if args.err_tol is not None:
-        op["err_tol"] = args.err_tol
+    op = overrides(dict(OPERATING_POINT["zeldovich1024"]), args)
     prm = dict(box=1.0, G=1.0, eps=0.02 / ns, order=4, periodic=1, far_order=8,
                precision="fp32", **op)
     mass = torch.full((n,), 1.0 / n, dtype=torch.float32, device=dev)
@@ -334,7 +378,7 @@ def paper_scale(args):
     found = None
     if args.search:
         best, rows = search(torch, Gravity, pos, mass, prm, tg, aref, dev, "zeldovich1024", **ctx)
-        prm.update(theta=best["theta"], err_tol=best["err_tol"])
+        prm.update({k: best[k] for k in SEARCHED})
         found = {"chosen": best, "rows": rows, "targets": "selection"}
     g = Gravity(device=dev, **ctx, **prm)
     acc = torch.empty((3, n), dtype=torch.float32, device=dev)
@@ -372,7 +416,8 @@ def paper_scale(args):
                                "P(k)~k^-1.5, rms displacement 1.5 spacing",
                    "theta": prm["theta"], "err_tol": prm["err_tol"], "order": 4,
                    "leaf_max": prm["leaf_max"], "group_max": prm["group_max"], "far_order": 8,
-                   "eps": prm["eps"],
+                   "eps": prm["eps"], "local_order": prm.get("local_order", 0),
+                   "local_tol": prm.get("local_tol", 0.0),
                    "step": "one KDK step (one force evaluation), no state snapshots"},
         "rms_force_err": {"value": err, "max_over_rms": emax, "targets": len(tg),
                           "target_set": "selection" if args.search else "held-out",
@@ -380,10 +425,10 @@ def paper_scale(args):
                                        f"{a_rms:.5g}", "reference_s": t_ref},
         "per_force_eval": {"fp32_ms": st0["ms_total"], "fp32_pps": n / (1e-3 * st0["ms_total"])},
         "stage_ms": {k: st[k] for k in StepStats.KEYS},
-        "pairs_per_step": {"p2p": st["p2p_pairs"], "m2p": st["m2p_pairs"]},
+        "pairs_per_step": pairs(st),
         "m2p_lane_use": lane_use(st),
         "stage_bandwidth": stage_bandwidth(n, st["ncells"], st),
-        "interactions_per_s": (st["p2p_pairs"] + st["m2p_pairs"]) / el,
+        "interactions_per_s": (st["p2p_pairs"] + st["m2p_pairs"] + st["m2l_pairs"]) / el,
         "list_chunks": st["list_chunks"], "workspace_bytes": int(g.ws.numel()),
         "roofline": roof, "roofline_other": roof_other,
         "operating_point_search": found,
@@ -413,11 +458,7 @@ def workload_rates(args, workload, kdk_steps=True, adjoint=True):
     from paper_1407_2600_amd import Gravity
     W = WORKLOADS[workload]
     pos_np, mass_np, prm = workloads.make(workload, n_side=args.n_side)
-    prm = dict(prm, **OPERATING_POINT[workload])
-    if args.theta is not None:
-        prm["theta"] = args.theta
-    if args.err_tol is not None:
-        prm["err_tol"] = args.err_tol
+    prm = overrides(dict(prm, **OPERATING_POINT[workload]), args)
     n = pos_np.shape[1]
     dev = torch.device("cuda", 0)
     pos_dev = torch.as_tensor(pos_np, dtype=torch.float64, device=dev).contiguous()
@@ -427,7 +468,7 @@ def workload_rates(args, workload, kdk_steps=True, adjoint=True):
         m32 = torch.as_tensor(mass_np, dtype=torch.float32, device=dev)
         best, rows = search(torch, Gravity, pos_dev, m32, dict(prm, precision="fp32"),
                             refs["select"][0], refs["select"][1], dev, workload)
-        prm.update(theta=best["theta"], err_tol=best["err_tol"])
+        prm.update({k: best[k] for k in SEARCHED})
         found = {"chosen": best, "rows": rows, "targets": "selection"}
     res = {}
     for prec in ("fp32", "fp64"):
@@ -449,7 +490,13 @@ def workload_rates(args, workload, kdk_steps=True, adjoint=True):
         for name, (tg, aref) in refs.items():
             r["errors"][name] = {"rms": rms_err(a_first[:, tg], aref),
                                  "max_over_rms": max_err(a_first[:, tg], aref), "targets": len(tg)}
-        if prec == "fp32" and adjoint:
+        if prec == "fp32" and adjoint and not args.no_adjoint:
+            # the adjoint is built without the group-level local route: the
+            # ratio is taken at the same acceptance test with both routes off
+            g_fwd = g
+            if prm.get("local_order", 0) and prm.get("local_tol", 0.0):
+                g = Gravity(device=dev, precision=prec, **dict(prm, local_order=0))
+                g.forces(pos, mass, out_acc=a0, out_pot=p0)
             gen = torch.Generator(device=dev).manual_seed(7)
             gacc = torch.randn((3, n), dtype=dt_, device=dev, generator=gen)
             gpot = torch.randn(n, dtype=dt_, device=dev, generator=gen)
@@ -482,7 +529,12 @@ def workload_rates(args, workload, kdk_steps=True, adjoint=True):
                    "ms_vjp_with_tree_build": 1e3 * float(np.median(tb))}
             adj["ratio"] = adj["ms_vjp"] / adj["ms_forward"]
             adj["ratio_with_tree_build"] = adj["ms_vjp_with_tree_build"] / adj["ms_forward"]
+            adj["local_expansions"] = bool(g is g_fwd and prm.get("local_order", 0))
             r["adjoint"] = adj
+            if g is not g_fwd:
+                del g
+                g = g_fwd
+                g.forces(pos, mass, out_acc=a0, out_pot=p0)
         if kdk_steps:
             vel = torch.zeros((3, n), dtype=dt_, device=dev)
             acc = a0.clone()
@@ -516,8 +568,9 @@ def extras_128(args):
     roof, roof_other = roofline(r32["stats"], prm["order"], "zeldovich128", prm)
     return {
         "workload": WORKLOADS["zeldovich128"]["desc"].format(s=128, n=n),
-        "config": {k: prm[k] for k in ("theta", "err_tol", "order", "leaf_max", "group_max",
-                                       "far_order", "eps")},
+        "config": {k: prm.get(k, 0) for k in ("theta", "err_tol", "order", "leaf_max",
+                                              "group_max", "far_order", "eps", "local_order",
+                                              "local_tol")},
         "fp32_ms": r32["ms_force"], "fp64_ms": r64["ms_force"],
         "fp32_pps": r32["pps_force"], "fp64_pps": r64["pps_force"],
         "fp32_over_fp64": r32["pps_force"] / r64["pps_force"],
@@ -526,7 +579,8 @@ def extras_128(args):
                                                "targets",
                           "select_reference": "oracle's theta=0 near+far sum on the 10^4 "
                                               "selection targets"},
-        "adjoint": r32["adjoint"], "adjoint_over_forward": r32["adjoint"]["ratio"],
+        "adjoint": r32.get("adjoint"),
+        "adjoint_over_forward": r32["adjoint"]["ratio"] if "adjoint" in r32 else None,
         "stage_ms": {k: r32["stats"][k] for k in StepStats.KEYS},
         "m2p_lane_use": lane_use(r32["stats"]),
         "roofline": roof, "roofline_other": roof_other,
@@ -547,8 +601,9 @@ def workload_main(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": W["data"],
         "config": {"workload": W["desc"].format(s=round(n ** (1 / 3)), n=n),
-                   **{k: prm[k] for k in ("theta", "err_tol", "order", "eps", "leaf_max",
-                                          "group_max", "far_order")},
+                   **{k: prm.get(k, 0) for k in ("theta", "err_tol", "order", "eps", "leaf_max",
+                                                 "group_max", "far_order", "local_order",
+                                                 "local_tol")},
                    "step": "one KDK step (one force evaluation)"},
         "rms_force_err": {"fp32": r32["errors"], "fp64": r64["errors"]},
         "per_force_eval": {"fp32_ms": r32["ms_force"], "fp32_pps": r32["pps_force"],
@@ -556,11 +611,13 @@ def workload_main(args):
         "fp64": {"value": r64["kdk"]["pps"], "ms_per_step": r64["kdk"]["ms_per_step"],
                  "dtype": "f64"},
         "fp32_over_fp64": r32["pps_force"] / r64["pps_force"],
-        "adjoint_over_forward": r32["adjoint"]["ratio"], "adjoint": r32["adjoint"],
-        "interactions_per_s": (st["p2p_pairs"] + st["m2p_pairs"]) / (st["ms_total"] * 1e-3),
+        "adjoint_over_forward": r32["adjoint"]["ratio"] if "adjoint" in r32 else None,
+        "adjoint": r32.get("adjoint"),
+        "interactions_per_s": ((st["p2p_pairs"] + st["m2p_pairs"] + st["m2l_pairs"]) /
+                               (st["ms_total"] * 1e-3)),
         "stage_ms": {k: st[k] for k in StepStats.KEYS},
         "stage_bandwidth": stage_bandwidth(n, st["ncells"], st),
-        "pairs_per_step": {"p2p": st["p2p_pairs"], "m2p": st["m2p_pairs"]},
+        "pairs_per_step": pairs(st),
         "m2p_lane_use": lane_use(st),
         "workspace_bytes": {"fp32": r32["workspace_bytes"], "fp64": r64["workspace_bytes"]},
         "roofline": roof, "roofline_other": roof_other,
