@@ -53,19 +53,24 @@
  * instead re-expanded once about the group's centre c (the centre of its
  * tight box) to order q,
  *     L_n = sum_k (-1)^|k| C(n+k, k) M_k T_(n+k)(c - z),   |n| <= q,
- * with T_m(R) = d^m g(R)/m! the Taylor coefficients of the softened Green's
- * function and z the cell's image-shifted centre of mass, and every sink
- * takes Phi += sum_n L_n (x - c)^n (and its gradient).  A sink within a of c
- * (a = half the diagonal of the tight box) sees every particle of the cell
- * at distance >= u = |c - z| - b, and for one point mass the acceleration
- * error of the order-q truncation is at most
+ * with T_m(R) = d^m g(R)/m! the Taylor coefficients of the Newtonian Green's
+ * function g = 1/|R| and z the cell's image-shifted centre of mass, and
+ * every sink takes Phi += sum_n L_n (x - c)^n (and its gradient).  A sink
+ * within a of c (a = half the diagonal of the tight box) sees every particle
+ * of the cell at distance >= u = |c - z| - b.  For one point mass m the
+ * acceleration error of the order-q truncation is at most
  *     G m t^q ((q+2) - (q+1) t) / (u^2 (1 - t)^2),   t = a/u < 1
  * (the Legendre expansion of 1/|x - s| about c, with |P_n| <= 1 and the
- * gradient of each solid harmonic of degree n bounded by n |y|^(n-1)); the
- * cell takes the local route when this bound with its mass is at most
- * local_tol.  The test is evaluated in this order of IEEE operations:
- *     t = a/u;  t^q by repeated multiplication;
- *     G m t^q ((q+2) - (q+1) t)  <=  local_tol (u u) (1-t) (1-t).
+ * gradient of each solid harmonic of degree n bounded by (n+1) |y|^(n-1)),
+ * and leaving out the Plummer softening changes its acceleration by at most
+ * 1.5 G m eps^2 / (u - a)^4, u - a bounding the distance of any particle
+ * from any sink (no change for the K1 kernel, whose accepted cells lie
+ * beyond its radius).  The cell takes the local route when the sum of the
+ * two with its mass is at most local_tol.  Written without divisions,
+ *     A = G m a^q ((q+2) u - (q+1) a),   B = u^(q+1) (u - a)^2,
+ *     C = 1.5 G m eps^2,                 D = (u - a)^4,
+ * the test A D + C B <= local_tol B D is evaluated in this order of IEEE
+ * operations (powers by repeated multiplication, a^q per group).
  */
 #include <math.h>
 #include <stdint.h>
@@ -660,8 +665,10 @@ static void group_centre(const tree_t* T, int64_t g, double c[3], double* a) {
   *a = sqrt(a2);
 }
 
+static double m2p_eps2(const tree_t* T);
+
 /* an accepted cell takes the group's local expansion when the truncation
- * bound of the header holds */
+ * and softening bound of the header holds */
 static int local_accept(const tree_t* T, int64_t g, const cell_t* B, const int n[3]) {
   const int q = T->p.local_order;
   if (q <= 0 || !(T->p.local_tol > 0.0)) return 0;
@@ -675,18 +682,26 @@ static int local_accept(const tree_t* T, int64_t g, const cell_t* B, const int n
   r2 = r2 + d[2] * d[2];
   double u = sqrt(r2) - B->bmax;
   if (!(u > a)) return 0;
-  double t = a / u;
-  double tq = t;
-  for (int i = 1; i < q; ++i) tq = tq * t;
-  double num = T->p.G * B->m;
-  num = num * tq;
-  num = num * ((double)(q + 2) - (double)(q + 1) * t);
-  double w = 1.0 - t;
-  double den = u * u;
-  den = den * w;
-  den = den * w;
-  den = T->p.local_tol * den;
-  return num <= den;
+  double aq = a;
+  for (int i = 1; i < q; ++i) aq = aq * a;
+  const double e2 = m2p_eps2(T);
+  double gm = T->p.G * B->m;
+  double A = gm * aq;
+  A = A * ((double)(q + 2) * u - (double)(q + 1) * a);
+  double uq = u;
+  for (int i = 0; i < q; ++i) uq = uq * u; /* u^(q+1) */
+  double w = u - a;
+  double Bv = uq * w;
+  Bv = Bv * w;
+  double Cv = 1.5 * gm;
+  Cv = Cv * e2;
+  double w2 = w * w;
+  double Dv = w2 * w2;
+  double lhs = A * Dv;
+  lhs = lhs + Cv * Bv;
+  double rhs = Bv * Dv;
+  rhs = T->p.local_tol * rhs;
+  return lhs <= rhs;
 }
 
 static void walk_rec(tree_t* T, int64_t g, int img, const int n[3], int64_t bi) {
@@ -789,7 +804,8 @@ static void m2p_add(const tree_t* T, const cell_t* B, const double R[3], double*
 }
 
 /* adds the local expansion about c of one cell's order-p expansion (raw
- * moments M about its centre of mass z, R0 = c - z) to L_n, |n| <= q */
+ * moments M about its centre of mass z, R0 = c - z) to L_n, |n| <= q; the
+ * tree passes eps2 = 0 (the route expands the Newtonian kernel) */
 static void local_add(int p, int q, double eps2, const double* M, const double R0[3],
                       double* Lg) {
   const int nq = or_nterms(q), nm = or_nterms(p);
@@ -842,7 +858,7 @@ static void group_local(const tree_t* T, int64_t g, double* Lg) {
     const cell_t* B = &T->cells[ll->cell[e]];
     double R[3] = {c[0] - (B->com[0] + sh[0]), c[1] - (B->com[1] + sh[1]),
                    c[2] - (B->com[2] + sh[2])};
-    local_add(T->p.order, q, m2p_eps2(T), B->M, R, Lg);
+    local_add(T->p.order, q, 0.0, B->M, R, Lg);
   }
 }
 

@@ -2,8 +2,9 @@
 paper Sec. 2.1: source cells bundled with the sinks of a sink group; here a
 cell far from the whole group is re-expanded once about the group's centre).
 
-The route must reproduce what the cell's multipole expansion gives, up to a
-truncation that the acceptance bound controls:
+The route expands the Newtonian kernel.  It must reproduce what the cell's
+multipole expansion gives, up to a truncation and a softening difference that
+the acceptance bound controls:
 - at the expansion centre, orders 0 and 1 of the local expansion are the
   multipole field's value and gradient there (no truncation yet), and order
   2 holds its Hessian (checked against finite differences of the multipole
@@ -11,7 +12,8 @@ truncation that the acceptance bound controls:
 - the local expansion converges to the multipole field as its order grows,
   geometrically in (group radius / distance);
 - for a point mass (where the multipole field is exact) the acceleration
-  error never exceeds the truncation bound the walk uses;
+  error never exceeds the truncation bound the walk uses, and against the
+  Plummer-softened field the truncation bound plus 1.5 G m eps^2 / (u-a)^4;
 - in the tree, the local list and the multipole list together are exactly
   the multipole list without local expansions, and the forces move by no
   more than the bound summed over the group's local cells."""
@@ -30,11 +32,13 @@ def _cluster(n, scale=0.05, centre=(0.0, 0.0, 0.0), rng=RNG):
     return pos, mass
 
 
-def _bound(m, a, u, q, G=1.0):
+def _bound(m, a, u, q, G=1.0, eps=0.0):
     """Acceleration bound of the order-q truncation for mass m whose
-    particles are all at least u from the centre, sinks within a of it."""
+    particles are all at least u from the centre, sinks within a of it, plus
+    the change of leaving out Plummer softening eps."""
     t = a / u
-    return G * m * t ** q * ((q + 2) - (q + 1) * t) / (u * u * (1 - t) ** 2)
+    return (G * m * t ** q * ((q + 2) - (q + 1) * t) / (u * u * (1 - t) ** 2) +
+            1.5 * G * m * eps ** 2 / (u - a) ** 4)
 
 
 @pytest.mark.parametrize("order", [0, 2, 4])
@@ -96,11 +100,13 @@ def test_converges_to_multipole_field_with_order():
     assert errs[-1] < 1e-6 * np.linalg.norm(oracle.multipole_eval(pos, mass, 4, 0.0, c)[1])
 
 
+@pytest.mark.parametrize("eps_frac", [0.0, 0.05, 0.2])
 @pytest.mark.parametrize("q", [1, 2, 4, 6])
-def test_point_mass_error_within_bound(q):
+def test_point_mass_error_within_bound(q, eps_frac):
     """One particle: the multipole field is exact, and the acceleration error
-    of the local route is at most the truncation bound, for sinks anywhere in
-    the ball of radius a."""
+    of the (Newtonian) local route against the particle's Plummer-softened
+    field is at most the truncation bound plus the softening term, for sinks
+    anywhere in the ball of radius a."""
     rng = np.random.default_rng(100 + q)
     worst = 0.0
     for _ in range(300):
@@ -109,13 +115,14 @@ def test_point_mass_error_within_bound(q):
         c = np.zeros(3)
         u = np.linalg.norm(z)
         a = u * rng.uniform(0.05, 0.6)
+        eps = eps_frac * (u - a)
         y = rng.normal(0, 1, 3)
         y *= a * rng.uniform(0, 1) ** (1 / 3) / np.linalg.norm(y)
         _, gl = oracle.local_eval(z[:, None], np.array([m]), 0, q, 0.0, c, c + y)
         d = z - (c + y)
-        g_exact = m * d / np.linalg.norm(d) ** 3
+        g_exact = m * d / (d @ d + eps * eps) ** 1.5
         err = np.linalg.norm(gl - g_exact)
-        b = _bound(m, a, u, q)
+        b = _bound(m, a, u, q, eps=eps)
         assert err <= b * (1 + 1e-9) + 1e-15, (err, b)
         worst = max(worst, err / b)
     assert worst > 1e-3  # the bound is not vacuous
@@ -162,6 +169,7 @@ def test_tree_forces_move_within_summed_bound():
     truncation bound summed over the group's local cells (each cell's
     particles all lie at least u = |c - z| - b from the centre)."""
     pos, mass, prm = _small_tree(4, 0.005)
+    eps = prm["eps"]
     T_on = oracle.Tree(pos, mass, prm)
     T_off = oracle.Tree(pos, mass, dict(prm, local_order=0))
     a_on, _ = T_on.forces()
@@ -183,7 +191,7 @@ def test_tree_forces_move_within_summed_bound():
             sh = np.array([i // 9 - 1, (i // 3) % 3 - 1, i % 3 - 1], float)
             B = cl[e]
             u = np.linalg.norm(c - (cells["com"][:, B] + sh)) - bmax[B]
-            bsum += _bound(cells["mass"][B], a, u, 4)
+            bsum += _bound(cells["mass"][B], a, u, 4, eps=eps)
         A = gcell[g]
         idx = perm[cells["first"][A]:cells["first"][A] + cells["count"][A]]
         d = np.linalg.norm(a_on[:, idx] - a_off[:, idx], axis=0)
