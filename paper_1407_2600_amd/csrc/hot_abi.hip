@@ -48,9 +48,8 @@ hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uin
 hipError_t local_moments_launch(bool fp32, int order, const double* mom, uint32_t ncells,
                                 void* mt, hipStream_t s);
 hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Groups& G,
-                        uint32_t ngroups, uint32_t gcap, double L, double eps, const double* spos,
-                        size_t n, const uint4* list, const void* mt, double4* out,
-                        hipStream_t s);
+                        uint32_t ngroups, uint32_t gcap, double L, const double* spos, size_t n,
+                        const uint4* list, const void* mt, double4* out, hipStream_t s);
 hipError_t sum_counts(const Groups& G, uint32_t ngroups, bool local, unsigned long long* sums,
                       uint32_t* maxw,
                       hipStream_t s);
@@ -423,7 +422,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     size_t tp, tm, tl;
   };
   const bool local = local_on(p);
-  const LocalPrm lp{local ? p.local_order : 0, local ? p.local_tol : 0.0, p.G};
+  const LocalPrm lp{local ? p.local_order : 0, local ? p.local_tol : 0.0, p.G,
+                    p.kernel == HOT_KERNEL_K1 ? 0.0 : p.eps * p.eps};
   std::vector<Chunk> chunks;
 
   if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[0], s), "event");
@@ -642,8 +642,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
       // kernels (no other kernel writes the accumulators meanwhile)
       if (local && k.tl > 0)
         HOT_CHECK(local_launch(fp32, p.order, p.local_order, C, Gk, ng, (uint32_t)P.cap_groups,
-                               p.box, p.kernel == HOT_KERNEL_K1 ? 0.0 : p.eps, spos, n, m2l_list,
-                               at<void>(ws, P.o_c_mloc), near, s),
+                               p.box, spos, n, m2l_list, at<void>(ws, P.o_c_mloc), near, s),
                   "local expansions");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[7], s), "event");
       if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 3], s), "event");

@@ -110,13 +110,16 @@ __host__ __device__ constexpr int m2p_flops(int P) {
 }
 constexpr int kP2PFlops = 20;
 
-// Algorithmic flops of the group-level local route (fma = 2): per local-list
-// entry, the derivatives D_m, |m| <= P+Q, by their recurrence (setup: s, its
-// reciprocal square root and square, the scaled R_i and the per-degree
-// factors; per component one multiply-add per nonzero m_i and per m_i >= 2
-// and the combination) and the contraction n! L_n += Mt_k D_(n+k) over
-// |n| <= Q and the stored |k| <= P (no dipole); per sink, the value and
-// gradient of the order-Q polynomial (4 fma per term) after the offset.
+// Algorithmic flops of the group-level local route (fma = 2), as the
+// kernel formulates it: per local-list entry, the derivatives D_m,
+// |m| <= P+Q, of the Newtonian kernel (setup: |R|^2, its reciprocal square
+// root and square, the scaled R_i and the per-degree factors; the components
+// with at most one z index by the recurrence, one multiply-add per nonzero
+// m_i and per m_i >= 2 plus the combination; the others by the trace
+// relation, one add) and the contraction S_n += Mt_k D_(n+k) for the
+// independent n (at most one z index), |n| <= Q, and the stored |k| <= P
+// (no dipole); per sink, the value and gradient of the order-Q polynomial
+// (4 fma per term) after the offset.
 __host__ __device__ constexpr int m2l_flops(int P, int Q) {
   const int N = P + Q;
   int f = 5 + 1 + 1 + 3 * N + 2 * N;
@@ -124,12 +127,21 @@ __host__ __device__ constexpr int m2l_flops(int P, int Q) {
     for (int a = d; a >= 0; --a)
       for (int b = d - a; b >= 0; --b) {
         const int c = d - a - b;
-        const int nz = (a > 0) + (b > 0) + (c > 0), n2 = (a > 1) + (b > 1) + (c > 1);
+        if (c >= 2) {
+          f += 1;
+          continue;
+        }
+        const int nz = (a > 0) + (b > 0) + (c > 0), n2 = (a > 1) + (b > 1);
         f += 2 * nz - 1;
         f += n2 > 0 ? 2 * n2 - 1 + 3 : 1;
       }
-  const int nk = nt(P) - (P >= 1 ? 3 : 0);
-  return f + 2 * nt(Q) * nk;
+  int pairs = 0;
+  for (int dn = 0; dn <= Q; ++dn)
+    for (int dk = 0; dk <= P; ++dk) {
+      if (dk == 1) continue;
+      pairs += (2 * dn + 1) * ((dk + 1) * (dk + 2) / 2);
+    }
+  return f + 2 * pairs;
 }
 __host__ __device__ constexpr int l2p_flops(int Q) { return 3 + 8 * nt(Q); }
 
@@ -180,14 +192,16 @@ struct Groups {
   uint32_t* off_m2l;
 };
 
-// Group-level local expansions: an accepted cell goes to the group's local
-// list when the truncation bound of the order-q local expansion about the
-// group's centre, G m t^q ((q+2) - (q+1) t) / (u^2 (1-t)^2) with
-// u = |c - z| - b and t = a/u, is at most tol (q = 0: never).
+// Group-level local expansions (Newtonian kernel): an accepted cell goes to
+// the group's local list when the truncation bound of the order-q local
+// expansion about the group's centre, G m t^q ((q+2) - (q+1) t) /
+// (u^2 (1-t)^2) with u = |c - z| - b and t = a/u, plus the softening change
+// 1.5 G m eps2 / (u - a)^4, is at most tol (q = 0: never).
 struct LocalPrm {
   int q;
   double tol;
   double G;
+  double eps2;  // Plummer softening squared (0 for the K1 kernel)
 };
 
 // list chunks whose stages are timed one by one (beyond, only the chunk

@@ -3,18 +3,22 @@
 // them, the dual-tree m x n blocking).  The cells of a group's local list
 // are re-expanded once about the group's centre c (the middle of its tight
 // box) instead of being evaluated at every sink:
-//     n! L_n = sum_k Mt_k D_(n+k)(c - z),   |n| <= Q, |k| <= P,
+//     S_n = n! L_n = sum_k Mt_k D_(n+k)(c - z),   |n| <= Q, |k| <= P,
 // with Mt_k = (-1)^|k| M_k / k! (raw moments about the cell's centre of mass
-// z) and D_m = d^m g the derivatives of the softened Green's function
-// g = (|R|^2 + eps^2)^(-1/2).  The derivatives come from the recurrence
-//     s |m| D_m = -(2|m|-1) sum_i m_i R_i D_(m-e_i)
-//                 - (|m|-1) sum_i m_i (m_i - 1) D_(m-2 e_i),
-// s = |R|^2 + eps^2, obtained by writing (s + 2 R.h + |h|^2) g(R+h)^2 = 1,
-// applying h.grad and matching powers of h.  Every sink then takes
-// Phi += sum_n L_n (x - c)^n and its gradient.
+// z) and D_m = d^m g the derivatives of the Newtonian Green's function
+// g = 1/|R| (the route's acceptance bound covers leaving out softening).
+// The derivatives come from the recurrence
+//     |R|^2 |m| D_m = -(2|m|-1) sum_i m_i R_i D_(m-e_i)
+//                     - (|m|-1) sum_i m_i (m_i - 1) D_(m-2 e_i),
+// obtained by writing (|R|^2 + 2 R.h + |h|^2) g(R+h)^2 = 1, applying h.grad
+// and matching powers of h.  g is harmonic, so D_m and S_n are traceless:
+// D_(a,b,c+2) = -D_(a+2,b,c) - D_(a,b+2,c), and likewise S.  Only the
+// components with at most one z index (2d+1 of degree d) go through the
+// recurrence and the contraction; the others follow by that relation.
+// Every sink then takes Phi += sum_n L_n (x - c)^n and its gradient.
 //
 // One wavefront per group: its lanes take the group's local-list entries
-// one each (FP32 or FP64 arithmetic), the partial sums of n! L_n are added
+// one each (FP32 or FP64 arithmetic), the partial sums of S_n are added
 // across the lanes in FP64 in a fixed order, and the lanes then evaluate the
 // expansion at the group's sinks in FP64 and add it to their accumulators.
 // The kernel runs between the direct and multipole kernels, when no other
@@ -90,19 +94,19 @@ __host__ __device__ constexpr MIv mi_of(int idx) {
 }
 
 // The lanes' re-expansion of one cell: D_m for |m| <= P+Q in multi-index
-// order by the recurrence of the header, each D_m added into the partial
-// sums S_n (n = m - k) as soon as it exists, so that only the last two
-// degrees of D stay live.  Everything is unrolled at compile time.
+// order (the recurrence for at most one z index, the trace relation for the
+// rest), each D_m added into the partial sums S_n of the independent n
+// (c_n <= 1, n = m - k) as soon as it exists, so that only the last degrees
+// of D stay live.  Everything is unrolled at compile time.
 template <int P, int Q, typename T>
-__device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, T eps2, const T* __restrict__ M,
-                                          T* S) {
+__device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, const T* __restrict__ M, T* S) {
   constexpr int N = P + Q, ND = nt(N), NM = nt(P);
   T Mk[NM];
   static_for<NM>([&](auto KK) {
     constexpr int k = KK;
     if constexpr (k < 1 || k > 3) Mk[k] = M[k];  // the dipole about the centre of mass vanishes
   });
-  const T s = Rx * Rx + Ry * Ry + Rz * Rz + eps2;
+  const T s = Rx * Rx + Ry * Ry + Rz * Rz;
   const T d0 = rsqrt_t(s);
   const T is = d0 * d0;
   T mR[3][N + 1];
@@ -125,6 +129,9 @@ __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, T eps2, const T* __r
     constexpr int a = mv.a, b = mv.b, c = mv.c, d = a + b + c;
     if constexpr (m == 0) {
       D[0] = d0;
+    } else if constexpr (c >= 2) {
+      // traceless: (d/dz)^2 = -(d/dx)^2 - (d/dy)^2 on a harmonic function
+      D[m] = -D[mi_index(a + 2, b, c - 2)] - D[mi_index(a, b + 2, c - 2)];
     } else {
       T u;
       if constexpr (a > 0) u = mR[0][a] * D[mi_index(a - 1, b, c)];
@@ -140,7 +147,7 @@ __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, T eps2, const T* __r
         else
           u = mR[2][c] * D[mi_index(a, b, c - 1)];
       }
-      if constexpr (a > 1 || b > 1 || c > 1) {
+      if constexpr (a > 1 || b > 1) {
         T v;
         if constexpr (a > 1) v = (T)(a * (a - 1)) * D[mi_index(a - 2, b, c)];
         if constexpr (b > 1) {
@@ -149,23 +156,18 @@ __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, T eps2, const T* __r
           else
             v = (T)(b * (b - 1)) * D[mi_index(a, b - 2, c)];
         }
-        if constexpr (c > 1) {
-          if constexpr (a > 1 || b > 1)
-            v = fma((T)(c * (c - 1)), D[mi_index(a, b, c - 2)], v);
-          else
-            v = (T)(c * (c - 1)) * D[mi_index(a, b, c - 2)];
-        }
         D[m] = fma(ad[d], u, bd[d] * v);
       } else {
         D[m] = ad[d] * u;
       }
     }
-    // S_n += Mt_k D_m for every split m = n + k, |n| <= Q, |k| <= P
+    // S_n += Mt_k D_m for every split m = n + k with n independent
+    // (c_n <= 1), |n| <= Q, |k| <= P
     static_for<NM>([&](auto KK) {
       constexpr int k = KK;
       constexpr MIv kv = mi_of(k);
       if constexpr ((k < 1 || k > 3) && kv.a <= a && kv.b <= b && kv.c <= c &&
-                    d - (kv.a + kv.b + kv.c) <= Q) {
+                    d - (kv.a + kv.b + kv.c) <= Q && c - kv.c <= 1) {
         constexpr int nidx = mi_index(a - kv.a, b - kv.b, c - kv.c);
         S[nidx] = fma(Mk[k], D[m], S[nidx]);
       }
@@ -175,7 +177,7 @@ __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, T eps2, const T* __r
 
 template <int P, int Q, typename T>
 __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uint32_t ngroups,
-                                                          uint32_t gcap, double L, T eps2,
+                                                          uint32_t gcap, double L,
                                                           const double* __restrict__ spos,
                                                           size_t n,
                                                           const uint4* __restrict__ list,
@@ -195,7 +197,7 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
   const double gc0 = 0.5 * (lo0 + hi0), gc1 = 0.5 * (lo1 + hi1), gc2 = 0.5 * (lo2 + hi2);
 
   // ---- the lanes' partial sums of n! L_n over their entries
-  T S[NQ];
+  T S[NQ];  // only the entries with c_n <= 1 are used
   static_for<NQ>([&](auto I) { S[I] = (T)0; });
   for (uint32_t q = lane; q < cnt; q += 64) {
     const uint4 r = list[off + q];
@@ -213,16 +215,24 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
       Ry = gc1 - (w.y + (double)((img / 3) % 3 - 1) * L);
       Rz = gc2 - (w.z + (double)(img % 3 - 1) * L);
     }
-    m2l_entry<P, Q, T>(Rx, Ry, Rz, eps2, mt + (size_t)B * NM, S);
+    m2l_entry<P, Q, T>(Rx, Ry, Rz, mt + (size_t)B * NM, S);
   }
-  // ---- sum over the lanes in FP64 (butterfly: every lane ends with the sums)
-  double Lc[NQ];
+  // ---- sum over the lanes in FP64 (butterfly: every lane ends with the
+  // sums), then the dependent S_n by the trace relation, and L_n = S_n / n!
+  double Sd[NQ];
   static_for<NQ>([&](auto I) {
-    double v = (double)S[I];
+    constexpr MIv nv = mi_of(I);
+    if constexpr (nv.c <= 1) {
+      double v = (double)S[I];
 #pragma unroll
-    for (int w = 1; w < 64; w <<= 1) v += __shfl_xor(v, w, 64);
-    Lc[I] = v * ifac.f[I];
+      for (int w = 1; w < 64; w <<= 1) v += __shfl_xor(v, w, 64);
+      Sd[I] = v;
+    } else {
+      Sd[I] = -Sd[mi_index(nv.a + 2, nv.b, nv.c - 2)] - Sd[mi_index(nv.a, nv.b + 2, nv.c - 2)];
+    }
   });
+  double Lc[NQ];
+  static_for<NQ>([&](auto I) { Lc[I] = Sd[I] * ifac.f[I]; });
   // ---- evaluate at the group's sinks
   const int A = G.cell[g];
   const uint32_t first = C.first[A], count = C.count[A];
@@ -241,29 +251,29 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
 
 template <int P, int Q>
 static hipError_t local_launch_pq(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups,
-                                  uint32_t gcap, double L, double eps2, const double* spos,
-                                  size_t n, const uint4* list, const void* mt, double4* out,
+                                  uint32_t gcap, double L, const double* spos, size_t n,
+                                  const uint4* list, const void* mt, double4* out,
                                   hipStream_t s) {
   const unsigned nb = (ngroups + kLocalWaves - 1) / kLocalWaves;
   if (fp32)
-    k_m2l<P, Q, float><<<nb, 64 * kLocalWaves, 0, s>>>(C, G, ngroups, gcap, L, (float)eps2, spos,
-                                                       n, list, (const float*)mt, out);
+    k_m2l<P, Q, float><<<nb, 64 * kLocalWaves, 0, s>>>(C, G, ngroups, gcap, L, spos, n, list,
+                                                       (const float*)mt, out);
   else
-    k_m2l<P, Q, double><<<nb, 64 * kLocalWaves, 0, s>>>(C, G, ngroups, gcap, L, eps2, spos, n,
-                                                        list, (const double*)mt, out);
+    k_m2l<P, Q, double><<<nb, 64 * kLocalWaves, 0, s>>>(C, G, ngroups, gcap, L, spos, n, list,
+                                                        (const double*)mt, out);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t local_launch_p(int q, bool fp32, const Cells& C, const Groups& G,
-                                 uint32_t ngroups, uint32_t gcap, double L, double eps2,
-                                 const double* spos, size_t n, const uint4* list, const void* mt,
-                                 double4* out, hipStream_t s) {
+                                 uint32_t ngroups, uint32_t gcap, double L, const double* spos,
+                                 size_t n, const uint4* list, const void* mt, double4* out,
+                                 hipStream_t s) {
   switch (q) {
     case 2:
-      return local_launch_pq<P, 2>(fp32, C, G, ngroups, gcap, L, eps2, spos, n, list, mt, out, s);
+      return local_launch_pq<P, 2>(fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
     case 4:
-      return local_launch_pq<P, 4>(fp32, C, G, ngroups, gcap, L, eps2, spos, n, list, mt, out, s);
+      return local_launch_pq<P, 4>(fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -292,17 +302,15 @@ hipError_t local_moments_launch(bool fp32, int order, const double* mom, uint32_
 }
 
 hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Groups& G,
-                        uint32_t ngroups, uint32_t gcap, double L, double eps, const double* spos,
-                        size_t n, const uint4* list, const void* mt, double4* out,
-                        hipStream_t s) {
+                        uint32_t ngroups, uint32_t gcap, double L, const double* spos, size_t n,
+                        const uint4* list, const void* mt, double4* out, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  const double e2 = eps * eps;
   switch (order) {
-    case 0: return local_launch_p<0>(q, fp32, C, G, ngroups, gcap, L, e2, spos, n, list, mt, out, s);
-    case 1: return local_launch_p<1>(q, fp32, C, G, ngroups, gcap, L, e2, spos, n, list, mt, out, s);
-    case 2: return local_launch_p<2>(q, fp32, C, G, ngroups, gcap, L, e2, spos, n, list, mt, out, s);
-    case 3: return local_launch_p<3>(q, fp32, C, G, ngroups, gcap, L, e2, spos, n, list, mt, out, s);
-    case 4: return local_launch_p<4>(q, fp32, C, G, ngroups, gcap, L, e2, spos, n, list, mt, out, s);
+    case 0: return local_launch_p<0>(q, fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
+    case 1: return local_launch_p<1>(q, fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
+    case 2: return local_launch_p<2>(q, fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
+    case 3: return local_launch_p<3>(q, fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
+    case 4: return local_launch_p<4>(q, fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);
     default: return hipErrorInvalidValue;
   }
 }

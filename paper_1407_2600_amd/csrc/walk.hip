@@ -58,13 +58,15 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
   // (half the box diagonal)
   const bool local = lp.q > 0 && lp.tol > 0.0;
   const double gc0 = 0.5 * (lo0 + hi0), gc1 = 0.5 * (lo1 + hi1), gc2 = 0.5 * (lo2 + hi2);
-  double ga;
+  double ga, gaq;
   {
     const double e0 = hi0 - gc0, e1 = hi1 - gc1, e2 = hi2 - gc2;
     double a2 = e0 * e0;
     a2 = a2 + e1 * e1;
     a2 = a2 + e2 * e2;
     ga = sqrt(a2);
+    gaq = ga;
+    for (int i = 1; i < lp.q; ++i) gaq = gaq * ga;
   }
 
   uint32_t top;
@@ -133,7 +135,8 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
           if (rc2 < dd) {
             action = 2;
             if (local) {
-              // truncation bound of the group's local expansion (IEEE
+              // truncation and softening bound of the group's local
+              // expansion without divisions, A D + C B <= tol B D (IEEE
               // operations in a fixed order)
               const double m = C.mmx[B].x, b = C.bnd[B].y;
               const double r0 = gc0 - c0, r1 = gc1 - c1, r2 = gc2 - c2;
@@ -142,18 +145,23 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
               rr = rr + r2 * r2;
               const double u = sqrt(rr) - b;
               if (u > ga) {
-                const double t = ga / u;
-                double tq = t;
-                for (int i = 1; i < lp.q; ++i) tq = tq * t;
-                double num = lp.G * m;
-                num = num * tq;
-                num = num * ((double)(lp.q + 2) - (double)(lp.q + 1) * t);
-                const double w1 = 1.0 - t;
-                double den = u * u;
-                den = den * w1;
-                den = den * w1;
-                den = lp.tol * den;
-                if (num <= den) action = 4;
+                const double gm = lp.G * m;
+                double A = gm * gaq;
+                A = A * ((double)(lp.q + 2) * u - (double)(lp.q + 1) * ga);
+                double uq = u;
+                for (int i = 0; i < lp.q; ++i) uq = uq * u;
+                const double w = u - ga;
+                double Bv = uq * w;
+                Bv = Bv * w;
+                double Cv = 1.5 * gm;
+                Cv = Cv * lp.eps2;
+                const double w2 = w * w;
+                const double Dv = w2 * w2;
+                double lhs = A * Dv;
+                lhs = lhs + Cv * Bv;
+                double rhs = Bv * Dv;
+                rhs = lp.tol * rhs;
+                if (lhs <= rhs) action = 4;
               }
             }
           } else if (nch == 0)
