@@ -117,6 +117,8 @@ def parse():
                          "OPERATING_POINT")
     ap.add_argument("--theta", type=float, default=None, help="override the opening-angle cap")
     ap.add_argument("--err-tol", type=float, default=None, help="override the tolerance")
+    ap.add_argument("--leaf-max", type=int, default=None, help="override the leaf size")
+    ap.add_argument("--group-max", type=int, default=None, help="override the sink-group size")
     ap.add_argument("--local-order", type=int, default=None,
                     help="override the order of the group-level local expansions (0 = none)")
     ap.add_argument("--local-tol", type=float, default=None,
@@ -292,7 +294,8 @@ SEARCHED = ("theta", "err_tol", "local_order", "local_tol")
 def overrides(prm, args):
     """The operating point with the command line's overrides."""
     for k, a in (("theta", args.theta), ("err_tol", args.err_tol),
-                 ("local_order", args.local_order), ("local_tol", args.local_tol)):
+                 ("local_order", args.local_order), ("local_tol", args.local_tol),
+                 ("leaf_max", args.leaf_max), ("group_max", args.group_max)):
         if a is not None:
             prm[k] = a
     return prm

@@ -3,6 +3,7 @@
 // interactions, far field).  See include/hot.h for the contract.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -516,8 +517,13 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   // ---- walk: count pass over all groups (again with the larger stack if
   // some group's pending cells overflowed the default one)
   for (;;) {
-    HOT_CHECK(walk_launch(false, big, C, G, ngroups, (uint32_t)P.cap_groups, p.box, p.periodic,
-                          lp, nullptr, nullptr, nullptr, ctr + CTR_STATUS, s),
+    HOT_CHECK(for_group_batches(G, ngroups, c->group_batch,
+                                [&](const Groups& B, uint32_t nb) {
+                                  return walk_launch(false, big, C, B, nb,
+                                                     (uint32_t)P.cap_groups, p.box, p.periodic,
+                                                     lp, nullptr, nullptr, nullptr,
+                                                     ctr + CTR_STATUS, s);
+                                }),
               "walk count");
     HOT_CHECK(sum_counts(G, ngroups, local, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
                          ctr + CTR_MAXW, s),
@@ -622,8 +628,13 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
       HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
       if (local)
         HOT_CHECK(scan_u32(Gk.cnt_m2l, Gk.off_m2l, ctr + CTR_TL, ng, scan_tmp, s), "scan");
-      HOT_CHECK(walk_launch(true, big, C, Gk, ng, (uint32_t)P.cap_groups, p.box, p.periodic, lp,
-                            p2p_list, m2p_list, m2l_list, ctr + CTR_STATUS, s),
+      HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
+                                  [&](const Groups& B, uint32_t nb) {
+                                    return walk_launch(true, big, C, B, nb,
+                                                       (uint32_t)P.cap_groups, p.box, p.periodic,
+                                                       lp, p2p_list, m2p_list, m2l_list,
+                                                       ctr + CTR_STATUS, s);
+                                  }),
                 "walk emit");
       HOT_CHECK(count_pairs(C, Gk, ng, local, p2p_list,
                             reinterpret_cast<unsigned long long*>(ctr + CTR_PAIRS),
@@ -633,35 +644,54 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[3], s), "event");
     if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 1], s), "event");
     if (!vjp) {
-      HOT_CHECK(p2p_launch(fp32, p.kernel, C, Gk, ng, p.box, p.eps, spos, srec, n, p2p_list,
-                           near, s, c->side),
+      HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
+                                  [&](const Groups& B, uint32_t nb) {
+                                    return p2p_launch(fp32, p.kernel, C, B, nb, p.box, p.eps,
+                                                      spos, srec, n, p2p_list, near, s, c->side);
+                                  }),
                 "direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
       if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 2], s), "event");
       // group-level local expansions, between the direct and multipole
       // kernels (no other kernel writes the accumulators meanwhile)
       if (local && k.tl > 0)
-        HOT_CHECK(local_launch(fp32, p.order, p.local_order, C, Gk, ng, (uint32_t)P.cap_groups,
-                               p.box, spos, n, m2l_list, at<void>(ws, P.o_c_mloc), near, s),
+        HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
+                                    [&](const Groups& B, uint32_t nb) {
+                                      return local_launch(fp32, p.order, p.local_order, C, B, nb,
+                                                          (uint32_t)P.cap_groups, p.box, spos, n,
+                                                          m2l_list, at<void>(ws, P.o_c_mloc),
+                                                          near, s);
+                                    }),
                   "local expansions");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[7], s), "event");
       if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 3], s), "event");
       // multipoles expand the softened kernel for Plummer, the Newtonian one
       // for K1 (accepted cells lie beyond its radius)
-      HOT_CHECK(m2p_launch(fp32, p.order, C, Gk, ng, p.box,
-                           p.kernel == HOT_KERNEL_K1 ? 0.0 : p.eps, spos, n, m2p_list, near, s,
-                           c->side),
+      HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
+                                  [&](const Groups& B, uint32_t nb) {
+                                    return m2p_launch(fp32, p.order, C, B, nb, p.box,
+                                                      p.kernel == HOT_KERNEL_K1 ? 0.0 : p.eps,
+                                                      spos, n, m2p_list, near, s, c->side);
+                                  }),
                 "multipole kernel");
     } else {
-      HOT_CHECK(p2p_adj_launch(fp32, C, Gk, ng, p.box, p.eps, spos, srec, arec, n, p2p_list, adj,
-                               s, c->side),
+      HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
+                                  [&](const Groups& B, uint32_t nb) {
+                                    return p2p_adj_launch(fp32, C, B, nb, p.box, p.eps, spos,
+                                                          srec, arec, n, p2p_list, adj, s,
+                                                          c->side);
+                                  }),
                 "adjoint direct kernel");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[4], s), "event");
       if (single && c->events_ok) HOT_CHECK(hipEventRecord(c->ev[7], s), "event");
       if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 2], s), "event");
       if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 3], s), "event");
-      HOT_CHECK(m2p_adj_launch(fp32, p.order, C, Gk, ng, p.box, p.eps, spos, srec, arec, ecoef, n,
-                               m2p_list, adj, s, c->side),
+      HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
+                                  [&](const Groups& B, uint32_t nb) {
+                                    return m2p_adj_launch(fp32, p.order, C, B, nb, p.box, p.eps,
+                                                          spos, srec, arec, ecoef, n, m2p_list,
+                                                          adj, s, c->side);
+                                  }),
                 "adjoint multipole kernel");
     }
     ++ck;
@@ -783,6 +813,11 @@ hot_status hot_create(const hot_params* params, hot_ctx** out) {
   c->p = *params;
   c->S = 2097152.0 / params->box;
   c->cells_per_particle = 4.0 / params->leaf_max + 0.02;  // grows on overflow
+  c->group_batch = kGroupBatch;
+  if (const char* gb = std::getenv("HOT_GROUP_BATCH")) {
+    const long v = std::strtol(gb, nullptr, 10);
+    if (v > 0 && (unsigned long)v < kGroupBatch) c->group_batch = (uint32_t)v;
+  }
   c->list_per_particle = 96.0;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {

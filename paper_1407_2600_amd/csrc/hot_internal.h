@@ -204,6 +204,39 @@ struct LocalPrm {
   double eps2;  // Plummer softening squared (0 for the K1 kernel)
 };
 
+// A dispatch holds fewer than 2^32 work-items, so kernels that give each sink
+// group a wavefront (or a block) run on at most kGroupBatch groups per launch
+// (the group arrays taken from the batch's first group on; the box arrays
+// keep their stride).
+constexpr uint32_t kGroupBatch = 1u << 22;
+
+inline Groups groups_from(const Groups& G, uint32_t g0) {
+  Groups B = G;
+  B.cell += g0;
+  B.lo += g0;
+  B.hi += g0;
+  B.cnt_p2p += g0;
+  B.cnt_m2p += g0;
+  B.off_p2p += g0;
+  B.off_m2p += g0;
+  B.cnt_m2l += g0;
+  B.off_m2l += g0;
+  if (B.active) B.active += g0;
+  return B;
+}
+
+// f(groups of the batch, their number) for consecutive batches of at most
+// batch groups
+template <typename F>
+inline hipError_t for_group_batches(const Groups& G, uint32_t ng, uint32_t batch, F&& f) {
+  for (uint32_t g0 = 0; g0 < ng; g0 += batch) {
+    const uint32_t nb = ng - g0 < batch ? ng - g0 : batch;
+    const hipError_t e = f(groups_from(G, g0), nb);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // list chunks whose stages are timed one by one (beyond, only the chunk
 // loop as a whole is timed)
 constexpr int kChunkEvents = 64;
@@ -298,6 +331,10 @@ struct hot_ctx {
   } tree;
   hipEvent_t ev[8];
   int events_ok;
+  // sink groups per launch of the per-group kernels (kGroupBatch; smaller
+  // only when the environment variable HOT_GROUP_BATCH asks for it, which
+  // the tests use to check that batched launches give identical results)
+  uint32_t group_batch;
   // per-chunk timing events when the lists are processed in chunks: chunk k
   // records cev[4k] before its walk emit pass, cev[4k+1] before its direct
   // kernel, cev[4k+2] before its local expansions, cev[4k+3] before its
