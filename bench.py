@@ -264,6 +264,9 @@ class StepStats:
             st[f"{q}_pairs"] = self.pairs[q] / s
             st[f"flops_{q}"] = self.flops[q] / s
         st["ncells"] = self.ncells / s
+        # lane use is taken from one step (its lane counters and its own
+        # interactions): the steps' trees differ
+        st["m2p_pairs_last"] = self.last["m2p_pairs"]
         return st
 
 
@@ -282,7 +285,7 @@ def lane_use(st):
     (8, 16 or 32 lanes for a last pass of at most 32 targets) spend, per list
     entry, as counted by the library."""
     main, tail, tp = st["m2p_lanes_main"], st["m2p_lanes_tail"], st["m2p_pairs_tail"]
-    mp = st["m2p_pairs"]
+    mp = st.get("m2p_pairs_last", st["m2p_pairs"])
     if main + tail <= 0:
         return None
     return {"all": mp / (main + tail), "main": (mp - tp) / main if main else None,
