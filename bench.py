@@ -59,19 +59,20 @@ OPERATING_POINT = {
     # sparse background otherwise splits into many small groups)
     "nfw256": dict(theta=0.0, err_tol=51.6, leaf_max=32, group_max=256, local_order=4,
                    local_tol=0.43),
-    # 0.09 of a_rms = 0.01857 with local expansions of order 4 at 0.0035 of
-    # a_rms: selection error 8.61e-4 (without them 0.102 of a_rms, between
-    # the searched 0.09 at 8.06e-4 and 0.11 at 9.59e-4, at 2.6x the time);
-    # leaf 64 keeps the cells within the 27-bit cell index of a list entry
-    # (the paper ends its traversal below ~80 particles)
-    "zeldovich1024": dict(theta=0.8, err_tol=1.67e-3, leaf_max=64, group_max=128, local_order=4,
-                          local_tol=6.5e-5),
+    # 0.10 of a_rms = 0.01857 with local expansions of order 4 at 0.005 of
+    # a_rms: selection error 9.22e-4 (0.08 / 0.005: 8.43e-4 at 3% more time;
+    # without the local expansions 0.102 of a_rms, between the searched 0.09
+    # at 8.06e-4 and 0.11 at 9.59e-4, at 2.9x the time); leaf 64 keeps the
+    # cells within the 27-bit cell index of a list entry (the paper ends its
+    # traversal below ~80 particles)
+    "zeldovich1024": dict(theta=0.8, err_tol=1.86e-3, leaf_max=64, group_max=128, local_order=4,
+                          local_tol=9.29e-5),
 }
 # --search grids: tolerances as fractions of the rms acceleration, opening-
 # angle caps (0 = none), and opening angles alone
 ETA_GRID = {"zeldovich128": (0.06, 0.08, 0.1, 0.12, 0.15, 0.18, 0.22, 0.27, 0.33),
             "nfw256": (0.8, 1.2, 1.6, 2.4, 3.5, 5.0, 7.0, 10.0),
-            "zeldovich1024": (0.09, 0.11, 0.13)}
+            "zeldovich1024": (0.08, 0.10, 0.12)}
 THETA_CAPS = {"zeldovich128": (0.0, 0.7, 0.8, 0.9), "nfw256": (0.0, 0.8),
               "zeldovich1024": (0.8,)}
 THETAS = {"zeldovich128": (0.40, 0.44, 0.46, 0.47, 0.48, 0.50), "nfw256": (0.3, 0.5, 0.7),
@@ -81,7 +82,7 @@ THETAS = {"zeldovich128": (0.40, 0.44, 0.46, 0.47, 0.48, 0.50), "nfw256": (0.3, 
 LOCAL_ORDER = 4
 LOCAL_FRACS = {"zeldovich128": (0.0, 0.001, 0.002, 0.003, 0.004),
                "nfw256": (0.0, 0.01, 0.03, 0.1),
-               "zeldovich1024": (0.0, 0.0015, 0.0025, 0.0035)}
+               "zeldovich1024": (0.003, 0.004, 0.005)}
 # list region beside the minimum workspace at 1024^3 (the lists are processed
 # in chunks of groups that fit it)
 PAPER_SCALE_LIST_BYTES = 16 << 30
