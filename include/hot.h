@@ -396,7 +396,9 @@ hot_status hot_kdk_vjp(hot_ctx* ctx, size_t n, int nsteps, const double* pos_ckp
  * so the workspace of that call may already be released. */
 hot_status hot_get_stats(const hot_ctx* ctx, hot_stats* out);
 
-/* Sizes for hot_debug_export after the last hot_forces call. */
+/* Sizes for hot_debug_export after the last hot_forces call.  Synchronises
+ * that call's stream (the split of accepted cells into multipole and local
+ * entries is known once its work has finished). */
 hot_status hot_debug_sizes(const hot_ctx* ctx, int64_t* n, int64_t* ncells, int64_t* ngroups,
                            int64_t* p2p_entries, int64_t* m2p_entries);
 

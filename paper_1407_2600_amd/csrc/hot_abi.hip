@@ -44,15 +44,13 @@ hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const 
                      size_t n, double L, void* srec, bool fp32, hipStream_t s);
 hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
                        uint32_t gcap, double L, int periodic, const LocalPrm& lp,
-                       uint32_t* p2p_list, uint4* m2p_list, uint4* m2l_list, uint32_t* status,
-                       hipStream_t s);
+                       uint32_t* p2p_list, uint4* m2p_list, uint32_t* status, hipStream_t s);
 hipError_t local_moments_launch(bool fp32, int order, const double* mom, uint32_t ncells,
                                 void* mt, hipStream_t s);
 hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Groups& G,
                         uint32_t ngroups, uint32_t gcap, double L, const double* spos, size_t n,
                         const uint4* list, const void* mt, double4* out, hipStream_t s);
-hipError_t sum_counts(const Groups& G, uint32_t ngroups, bool local, unsigned long long* sums,
-                      uint32_t* maxw,
+hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
                       hipStream_t s);
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, bool local,
                        const uint32_t* p2p_list, unsigned long long* out,
@@ -149,7 +147,7 @@ constexpr int kHostSlots = 64;
 constexpr int kHostWords = 128;
 // counters in the workspace (uint32 unless noted)
 enum { CTR_BAD = 0, CTR_TOTAL = 1, CTR_NGROUPS = 2, CTR_TP = 3, CTR_TM = 4, CTR_STATUS = 5,
-       CTR_TL = 6, CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* three u64 at 12..17 */,
+       CTR_PAIRS = 8 /* two u64 at 8..11 */, CTR_SUMS = 12 /* two u64 at 12..15 */,
        CTR_MAXW = 18, CTR_READ = 20, CTR_SLOTS = 24 /* six u64 at 24..35 */,
        CTR_RMAX = 60 /* block timesteps: largest rung */,
        CTR_N = 64 };
@@ -417,10 +415,12 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   int nlev = 1;
   uint32_t ncells = 0, ngroups = 0;
   bool big = false;
-  size_t tp = 0, tm = 0, tl = 0;
+  // tm counts the accepted cells, multipole and local records together (the
+  // walk's count pass does not split them; its emit pass does)
+  size_t tp = 0, tm = 0;
   struct Chunk {
     uint32_t g0, g1;
-    size_t tp, tm, tl;
+    size_t tp, tm;
   };
   const bool local = local_on(p);
   const LocalPrm lp{local ? p.local_order : 0, local ? p.local_tol : 0.0, p.G,
@@ -436,7 +436,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     ngroups = R.ngroups;
     tp = R.tp;
     tm = R.tm;
-    chunks.push_back({0, ngroups, tp, tm, 0});
+    chunks.push_back({0, ngroups, tp, tm});
     if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[1], s), "event");
     if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
   } else {
@@ -521,11 +521,10 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                                 [&](const Groups& B, uint32_t nb) {
                                   return walk_launch(false, big, C, B, nb,
                                                      (uint32_t)P.cap_groups, p.box, p.periodic,
-                                                     lp, nullptr, nullptr, nullptr,
-                                                     ctr + CTR_STATUS, s);
+                                                     lp, nullptr, nullptr, ctr + CTR_STATUS, s);
                                 }),
               "walk count");
-    HOT_CHECK(sum_counts(G, ngroups, local, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
+    HOT_CHECK(sum_counts(G, ngroups, reinterpret_cast<unsigned long long*>(ctr + CTR_SUMS),
                          ctr + CTR_MAXW, s),
               "list totals");
     HOT_CHECK(readback(s, ctr, host, CTR_READ), "readback");
@@ -539,15 +538,14 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     HOT_CHECK(zero_launch(ctr + CTR_STATUS, 4, s), "clear status");
     HOT_CHECK(zero_launch(ctr + CTR_SUMS, 4 * (CTR_READ - CTR_SUMS), s), "clear totals");
   }
-  unsigned long long sums[3];
+  unsigned long long sums[2];
   std::memcpy(sums, host + CTR_SUMS, sizeof(sums));
   tp = sums[0];
   tm = sums[1];
-  tl = sums[2];
   const size_t maxw = host[CTR_MAXW];
   // list words: direct entries 1, multipole and local records 4, plus 16-byte
   // alignment
-  const size_t words = tp + 4 * tm + 4 * tl + 4;
+  const size_t words = tp + 4 * tm + 4;
   c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)words / (double)n);
   if (maxw + 4 > P.cap_list) {
     c->stats.ws_bytes_needed = make_plan(c, n, 0, need).total;
@@ -558,28 +556,23 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   // a chunk's list offsets are 32-bit words (direct) and records (multipole)
   const size_t cap = std::min(P.cap_list, (size_t)UINT32_MAX - 64);
   if (words <= cap) {
-    chunks.push_back({0, ngroups, tp, tm, tl});
+    chunks.push_back({0, ngroups, tp, tm});
   } else {
-    std::vector<uint32_t> cp(ngroups), cm(ngroups), cl(ngroups, 0);
+    std::vector<uint32_t> cp(ngroups), cm(ngroups);
     HOT_CHECK(hipMemcpyAsync(cp.data(), G.cnt_p2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
               "readback");
     HOT_CHECK(hipMemcpyAsync(cm.data(), G.cnt_m2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
               "readback");
-    if (local)
-      HOT_CHECK(hipMemcpyAsync(cl.data(), G.cnt_m2l, 4 * (size_t)ngroups, hipMemcpyDeviceToHost,
-                               s),
-                "readback");
     HOT_CHECK(hipStreamSynchronize(s), "readback");
-    Chunk ch{0, 0, 0, 0, 0};
+    Chunk ch{0, 0, 0, 0};
     for (uint32_t g = 0; g < ngroups; ++g) {
-      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g] + ch.tl + cl[g]) + 4 > cap) {
+      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g]) + 4 > cap) {
         chunks.push_back(ch);
-        ch = Chunk{g, g, 0, 0, 0};
+        ch = Chunk{g, g, 0, 0};
       }
       ch.g1 = g + 1;
       ch.tp += cp[g];
       ch.tm += cm[g];
-      ch.tl += cl[g];
     }
     chunks.push_back(ch);
   }
@@ -621,18 +614,17 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     Gk.cnt_m2l += k.g0;
     Gk.off_m2l += k.g0;
     if (Gk.active) Gk.active += k.g0;
+    // a group's accepted cells: its multipole records from off_m2p on, then
+    // its local records (the emit pass sets off_m2l and both counts)
     uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
-    uint4* m2l_list = m2p_list + k.tm;
     if (!use_tree) {
       HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
       HOT_CHECK(scan_u32(Gk.cnt_m2p, Gk.off_m2p, ctr + CTR_TM, ng, scan_tmp, s), "scan");
-      if (local)
-        HOT_CHECK(scan_u32(Gk.cnt_m2l, Gk.off_m2l, ctr + CTR_TL, ng, scan_tmp, s), "scan");
       HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
                                   [&](const Groups& B, uint32_t nb) {
                                     return walk_launch(true, big, C, B, nb,
                                                        (uint32_t)P.cap_groups, p.box, p.periodic,
-                                                       lp, p2p_list, m2p_list, m2l_list,
+                                                       lp, p2p_list, m2p_list,
                                                        ctr + CTR_STATUS, s);
                                   }),
                 "walk emit");
@@ -654,12 +646,12 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
       if (cev) HOT_CHECK(hipEventRecord(c->cev[4 * ck + 2], s), "event");
       // group-level local expansions, between the direct and multipole
       // kernels (no other kernel writes the accumulators meanwhile)
-      if (local && k.tl > 0)
+      if (local)
         HOT_CHECK(for_group_batches(Gk, ng, c->group_batch,
                                     [&](const Groups& B, uint32_t nb) {
                                       return local_launch(fp32, p.order, p.local_order, C, B, nb,
                                                           (uint32_t)P.cap_groups, p.box, spos, n,
-                                                          m2l_list, at<void>(ws, P.o_c_mloc),
+                                                          m2p_list, at<void>(ws, P.o_c_mloc),
                                                           near, s);
                                     }),
                   "local expansions");
@@ -738,8 +730,11 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   st.ngroups = ngroups;
   st.nlevels = nlev;
   st.p2p_entries = (int64_t)tp;
+  // split into multipole and local entries once the lane-step counters are
+  // on the host (settle_entries)
   st.m2p_entries = (int64_t)tm;
-  st.m2l_entries = (int64_t)tl;
+  st.m2l_entries = 0;
+  c->last_accepted = tm;
   st.list_chunks = (int64_t)chunks.size();
   st.ws_bytes_needed = P.total;
   c->have_last = 1;
@@ -1202,6 +1197,39 @@ hot_status hot_kdk_vjp(hot_ctx* c, size_t n, int nsteps, const double* pos_ckpt,
   return HOT_OK;
 }
 
+// the walk's count pass counts accepted cells without deciding between the
+// multipole and the local route; the pair-count kernel after the emit pass
+// counts the local entries.  Once its counters are on the host (the last
+// call's work has finished), split the total.
+static void settle_entries(hot_ctx* m) {
+  unsigned long long sl[6];
+  std::memcpy(sl, m->host_buf + kHostSlots, sizeof(sl));
+  const size_t tl = local_on(m->p) ? (size_t)sl[3] : 0;
+  m->stats.m2l_entries = (int64_t)tl;
+  m->stats.m2p_entries = (int64_t)(m->last_accepted - tl);
+}
+
+// per-group offsets of one list kind in the list region (entries for the
+// direct list, 16-byte records for the others) and the packed CSR offsets of
+// the same entries; the multipole and local records of a group share its
+// accepted-cell region
+static hipError_t list_layout(hot_ctx* c, void* ws, int kind, std::vector<uint32_t>& raw,
+                              std::vector<int64_t>& packed) {
+  const Plan& P = c->last_plan;
+  const size_t ng = c->last_ngroups;
+  std::vector<uint32_t> cnt(ng);
+  raw.assign(ng, 0);
+  packed.assign(ng + 1, 0);
+  if (ng == 0) return hipSuccess;
+  const size_t o_cnt = kind == 2 ? P.o_g_cl : kind ? P.o_g_cm : P.o_g_cp;
+  const size_t o_off = kind == 2 ? P.o_g_ol : kind ? P.o_g_om : P.o_g_op;
+  hipError_t e = hipMemcpy(cnt.data(), at<char>(ws, o_cnt), 4 * ng, hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(raw.data(), at<char>(ws, o_off), 4 * ng, hipMemcpyDeviceToHost);
+  for (size_t g = 0; g < ng; ++g) packed[g + 1] = packed[g] + cnt[g];
+  return e;
+}
+
 hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
   if (!c || !out) {
     g_err = "NULL argument";
@@ -1264,6 +1292,7 @@ hot_status hot_get_stats(const hot_ctx* c, hot_stats* out) {
       m->stats.m2p_lanes_tail = (int64_t)sl[1];
       m->stats.m2p_pairs_tail = (int64_t)sl[2];
       m->stats.m2l_pairs = (int64_t)sl[4];
+      settle_entries(m);
       m->stats.flops_m2l = (double)sl[3] * m2l_flops(m->p.order, m->p.local_order) +
                            (double)sl[5] * l2p_flops(m->p.local_order);
     }
@@ -1278,6 +1307,9 @@ hot_status hot_debug_sizes(const hot_ctx* c, int64_t* n, int64_t* ncells, int64_
     g_err = "no previous hot_forces call";
     return HOT_EINVAL;
   }
+  hot_ctx* m = const_cast<hot_ctx*>(c);
+  HOT_CHECK(hipStreamSynchronize(m->last_stream), "sync");
+  settle_entries(m);
   if (n) *n = (int64_t)c->last_n;
   if (ncells) *ncells = c->last_ncells;
   if (ngroups) *ngroups = c->last_ngroups;
@@ -1321,33 +1353,35 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
     }
   }
   HOT_CHECK(cp(o->group_cell, P.o_g_cell, 4 * ng), "export");
-  std::vector<uint32_t> cnt(ng), off(ng);
-  const size_t tp = c->stats.p2p_entries, tm = c->stats.m2p_entries,
-               tl = c->stats.m2l_entries;
+  settle_entries(c);
+  const size_t tp = c->stats.p2p_entries;
   const bool local = local_on(c->p);
+  std::vector<uint32_t> raw;
+  std::vector<int64_t> packed;
   for (int kind = 0; kind < 3; ++kind) {
     int64_t* ooff = kind == 2 ? o->m2l_offset : kind ? o->m2p_offset : o->p2p_offset;
     uint32_t* oent = kind == 2 ? o->m2l_entry : kind ? o->m2p_entry : o->p2p_entry;
-    const size_t tot = kind == 2 ? tl : kind ? tm : tp;
-    if (ooff && ng && (kind < 2 || local)) {
-      HOT_CHECK(cp(off.data(), kind == 2 ? P.o_g_ol : kind ? P.o_g_om : P.o_g_op, 4 * ng),
-                "export");
-      for (size_t g = 0; g < ng; ++g) ooff[g] = off[g];
-      ooff[ng] = (int64_t)tot;
-    } else if (ooff) {
-      for (size_t g = 0; g <= ng; ++g) ooff[g] = 0;
+    if (!ooff && !oent) continue;
+    if (kind == 2 && !local) {
+      if (ooff)
+        for (size_t g = 0; g <= ng; ++g) ooff[g] = 0;
+      continue;
     }
-    if (!oent || tot == 0) continue;
+    HOT_CHECK(list_layout(c, ws, kind, raw, packed), "export");
+    if (ooff) std::copy(packed.begin(), packed.end(), ooff);
+    if (!oent || packed[ng] == 0) continue;
     if (kind == 0) {
       HOT_CHECK(cp(oent, P.o_list, 4 * tp), "export");
-    } else {
-      // multipole and local records: the entry is the last word of each 16
-      // bytes; the local records follow the multipole ones
-      std::vector<uint32_t> rec(4 * tot);
-      const size_t base = P.o_list + 4 * ((tp + 3) & ~size_t(3)) + (kind == 2 ? 16 * tm : 0);
-      HOT_CHECK(cp(rec.data(), base, 16 * tot), "export");
-      for (size_t i = 0; i < tot; ++i) oent[i] = rec[4 * i + 3];
+      continue;
     }
+    // multipole and local records: the entry is the last word of each 16
+    // bytes; each group's records are packed in group order
+    const size_t acc = c->last_accepted;
+    std::vector<uint32_t> rec(4 * acc);
+    HOT_CHECK(cp(rec.data(), P.o_list + 4 * ((tp + 3) & ~size_t(3)), 16 * acc), "export");
+    for (size_t g = 0; g < ng; ++g)
+      for (int64_t i = 0; i < packed[g + 1] - packed[g]; ++i)
+        oent[packed[g] + i] = rec[4 * ((size_t)raw[g] + (size_t)i) + 3];
   }
   return HOT_OK;
 }
@@ -1385,6 +1419,9 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
     g_err = "the last evaluation processed its lists in chunks; they are not all in memory";
     return HOT_EINVAL;
   }
+  const Plan& P = c->last_plan;
+  HOT_CHECK(hipStreamSynchronize(c->last_stream), "sync");
+  settle_entries(c);
   const int64_t total = kind == 2 ? c->stats.m2l_entries
                       : kind     ? c->stats.m2p_entries
                                  : c->stats.p2p_entries;
@@ -1393,20 +1430,27 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
     return HOT_EINVAL;
   }
   if (count == 0) return HOT_OK;
-  const Plan& P = c->last_plan;
-  HOT_CHECK(hipStreamSynchronize(c->last_stream), "sync");
   if (kind == 0) {
     HOT_CHECK(hipMemcpy(out, at<uint32_t>(ws, P.o_list) + first, 4 * (size_t)count,
                         hipMemcpyDeviceToHost),
               "export");
-  } else {
-    // the entry is the last word of each 16-byte multipole or local record
-    // (the local records follow the multipole ones)
-    const size_t tp = (size_t)c->stats.p2p_entries;
-    const size_t skip = kind == 2 ? 4 * (size_t)c->stats.m2p_entries : 0;
-    const uint32_t* rec =
-        at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3)) + skip + 4 * first + 3;
-    HOT_CHECK(hipMemcpy2D(out, 4, rec, 16, 4, (size_t)count, hipMemcpyDeviceToHost), "export");
+    return HOT_OK;
+  }
+  // the entry is the last word of each 16-byte multipole or local record;
+  // copy group by group from the packed index range
+  std::vector<uint32_t> raw;
+  std::vector<int64_t> packed;
+  HOT_CHECK(list_layout(c, ws, kind, raw, packed), "export");
+  const size_t tp = (size_t)c->stats.p2p_entries;
+  const uint32_t* rec = at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3)) + 3;
+  size_t g = (size_t)(std::upper_bound(packed.begin(), packed.end(), first) - packed.begin()) - 1;
+  for (int64_t i = first; i < first + count; ++g) {
+    const int64_t take = std::min(packed[g + 1], first + count) - i;
+    if (take <= 0) continue;
+    HOT_CHECK(hipMemcpy2D(out + (i - first), 4, rec + 4 * ((size_t)raw[g] + (size_t)(i - packed[g])),
+                          16, 4, (size_t)take, hipMemcpyDeviceToHost),
+              "export");
+    i += take;
   }
   return HOT_OK;
 }

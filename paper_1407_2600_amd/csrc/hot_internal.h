@@ -313,6 +313,7 @@ struct hot_ctx {
   void* last_ws;
   uint32_t last_ncells;
   uint32_t last_ngroups;
+  size_t last_accepted;  // accepted cells of the last evaluation (multipole + local)
   uint32_t* host_buf;  // pinned host memory for counter read-backs
   int last_chunks;     // list chunks of the last evaluation
   int last_cev;        // chunks timed one by one in the last evaluation (0: none)

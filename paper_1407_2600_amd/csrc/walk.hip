@@ -9,7 +9,10 @@
 //     particles are handled directly by the force kernel);
 //   - image 0 and the cell contains the group: open;
 //   - acceptance test passes: the group's local list if the local-expansion
-//     bound holds there (LocalPrm), else the multipole list;
+//     bound holds there (LocalPrm), else the multipole list (the count pass
+//     counts both together; the emit pass decides, writing the multipole
+//     records from the front of the group's region and the local records
+//     from its back, and then the two counts and the local offset);
 //   - a leaf: direct list;
 //   - otherwise: open (push the daughters).
 // Ballots and a wave prefix sum place the emitted entries and the pushed
@@ -31,7 +34,6 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
                                                           LocalPrm lp,
                                                           uint32_t* __restrict__ p2p_list,
                                                           uint4* __restrict__ m2p_list,
-                                                          uint4* __restrict__ m2l_list,
                                                           uint32_t* __restrict__ status) {
   __shared__ uint32_t stack_all[kWalkWaves][STACK];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     if (!EMIT && lane == 0) {
       G.cnt_p2p[g] = 0;
       G.cnt_m2p[g] = 0;
-      if (lp.q > 0) G.cnt_m2l[g] = 0;
+      G.cnt_m2l[g] = 0;
     }
     return;
   }
@@ -78,11 +80,11 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     top = 1;
   }
   uint32_t np = 0, nm = 0, nl = 0;
-  uint32_t op = 0, om = 0, ol = 0;
+  uint32_t op = 0, om = 0, oe = 0;
   if (EMIT) {
     op = G.off_p2p[g];
     om = G.off_m2p[g];
-    if (local) ol = G.off_m2l[g];
+    oe = om + G.cnt_m2p[g];  // end of the group's accepted region (count pass)
   }
   wave_sync();
   while (top > 0) {
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
           const double rc2 = w.w * w.w;
           if (rc2 < dd) {
             action = 2;
-            if (local) {
+            if (EMIT && local) {
               // truncation and softening bound of the group's local
               // expansion without divisions, A D + C B <= tol B D (IEEE
               // operations in a fixed order)
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
       // local records: the offset of the group's centre from the cell's
       // image-shifted centre of mass, c - z
       if (action == 4)
-        m2l_list[ol + nl + (uint32_t)__popcll(bl & below)] =
+        m2p_list[oe - 1 - nl - (uint32_t)__popcll(bl & below)] =
             make_uint4(__float_as_uint((float)(gc0 - cc0)), __float_as_uint((float)(gc1 - cc1)),
                        __float_as_uint((float)(gc2 - cc2)), e);
       if (action == 2)
@@ -204,69 +206,73 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     top += tot;
     wave_sync();
   }
-  if (!EMIT && lane == 0) {
-    G.cnt_p2p[g] = np;
-    G.cnt_m2p[g] = nm;
-    if (local) G.cnt_m2l[g] = nl;
+  if (lane == 0) {
+    if (!EMIT) {
+      G.cnt_p2p[g] = np;
+      G.cnt_m2p[g] = nm;  // multipole and local together
+      G.cnt_m2l[g] = 0;
+    } else {
+      G.cnt_m2p[g] = nm;
+      G.cnt_m2l[g] = nl;
+      G.off_m2l[g] = om + nm;  // the local records, in reverse emission order
+    }
   }
 }
 
 // 64-bit totals of the per-group list counts, and the largest group's list
 // size in 4-byte words (a direct entry is one word, a multipole or local
 // record four)
-__global__ void __launch_bounds__(256) k_sum_counts(Groups G, uint32_t ngroups, int local,
+__global__ void __launch_bounds__(256) k_sum_counts(Groups G, uint32_t ngroups,
                                                     unsigned long long* __restrict__ sums,
                                                     uint32_t* __restrict__ maxw) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long p = 0, m = 0, l = 0;
+  unsigned long long p = 0, m = 0;
   uint32_t w = 0;
   if (g < ngroups) {
     p = G.cnt_p2p[g];
     m = G.cnt_m2p[g];
-    if (local) l = G.cnt_m2l[g];
-    w = (uint32_t)(p + 4 * m + 4 * l);
+    w = (uint32_t)(p + 4 * m);
   }
   for (int d = 32; d > 0; d >>= 1) {
     p += __shfl_down(p, d, 64);
     m += __shfl_down(m, d, 64);
-    l += __shfl_down(l, d, 64);
     const uint32_t o = __shfl_down(w, d, 64);
     w = o > w ? o : w;
   }
   if ((threadIdx.x & 63) == 0) {
     atomicAdd(&sums[0], p);
     atomicAdd(&sums[1], m);
-    atomicAdd(&sums[2], l);
     atomicMax(maxw, w);
   }
 }
 
-hipError_t sum_counts(const Groups& G, uint32_t ngroups, bool local, unsigned long long* sums,
-                      uint32_t* maxw, hipStream_t s) {
+// after the count pass: the direct entries, the accepted cells (multipole and
+// local together) and the largest group's list words
+hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
+                      hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  k_sum_counts<<<(ngroups + 255) / 256, 256, 0, s>>>(G, ngroups, local ? 1 : 0, sums, maxw);
+  k_sum_counts<<<(ngroups + 255) / 256, 256, 0, s>>>(G, ngroups, sums, maxw);
   return hipGetLastError();
 }
 
 hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
                        uint32_t gcap, double L, int periodic, const LocalPrm& lp,
-                       uint32_t* p2p_list, uint4* m2p_list, uint4* m2l_list, uint32_t* status,
-                       hipStream_t s) {
+                       uint32_t* p2p_list, uint4* m2p_list, uint32_t* status, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   const unsigned blocks = (ngroups + kWalkWaves - 1) / kWalkWaves;
   const unsigned th = 64 * kWalkWaves;
   if (emit && big)
     k_walk<true, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
-                                                      p2p_list, m2p_list, m2l_list, status);
+                                                      p2p_list, m2p_list, status);
   else if (emit)
-    k_walk<true, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
-                                                   p2p_list, m2p_list, m2l_list, status);
+    k_walk<true, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp, p2p_list,
+                                                   m2p_list, status);
   else if (big)
     k_walk<false, kWalkStackBig><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
-                                                       p2p_list, m2p_list, m2l_list, status);
+                                                       p2p_list, m2p_list, status);
   else
-    k_walk<false, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp,
-                                                    p2p_list, m2p_list, m2l_list, status);
+    k_walk<false, kWalkStack><<<blocks, th, 0, s>>>(C, G, ngroups, gcap, L, periodic, lp, p2p_list,
+                                                    m2p_list, status);
   return hipGetLastError();
 }
 
