@@ -49,7 +49,7 @@ hipError_t local_moments_launch(bool fp32, int order, const double* mom, uint32_
                                 void* mt, hipStream_t s);
 hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Groups& G,
                         uint32_t ngroups, uint32_t gcap, double L, const double* spos, size_t n,
-                        const uint4* list, const void* mt, double4* out, hipStream_t s);
+                        const uint32_t* list, const void* mt, double4* out, hipStream_t s);
 hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
                       hipStream_t s);
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, bool local,
@@ -614,8 +614,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     Gk.cnt_m2l += k.g0;
     Gk.off_m2l += k.g0;
     if (Gk.active) Gk.active += k.g0;
-    // a group's accepted cells: its multipole records from off_m2p on, then
-    // its local records (the emit pass sets off_m2l and both counts)
+    // a group's accepted cells: its multipole records from off_m2p on, its
+    // local entries (32-bit words) at the end of the same region (the emit
+    // pass sets off_m2l, a word index, and both counts)
     uint4* m2p_list = reinterpret_cast<uint4*>(p2p_list + ((k.tp + 3) & ~size_t(3)));
     if (!use_tree) {
       HOT_CHECK(scan_u32(Gk.cnt_p2p, Gk.off_p2p, ctr + CTR_TP, ng, scan_tmp, s), "scan");
@@ -651,7 +652,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
                                     [&](const Groups& B, uint32_t nb) {
                                       return local_launch(fp32, p.order, p.local_order, C, B, nb,
                                                           (uint32_t)P.cap_groups, p.box, spos, n,
-                                                          m2p_list, at<void>(ws, P.o_c_mloc),
+                                                          reinterpret_cast<const uint32_t*>(
+                                                              m2p_list),
+                                                          at<void>(ws, P.o_c_mloc),
                                                           near, s);
                                     }),
                   "local expansions");
@@ -1209,10 +1212,10 @@ static void settle_entries(hot_ctx* m) {
   m->stats.m2p_entries = (int64_t)(m->last_accepted - tl);
 }
 
-// per-group offsets of one list kind in the list region (entries for the
-// direct list, 16-byte records for the others) and the packed CSR offsets of
-// the same entries; the multipole and local records of a group share its
-// accepted-cell region
+// per-group offsets of one list kind in the list region (32-bit words for the
+// direct and local lists from their bases, 16-byte records for the multipole
+// list) and the packed CSR offsets of the same entries; the multipole records
+// and local entries of a group share its accepted-cell region
 static hipError_t list_layout(hot_ctx* c, void* ws, int kind, std::vector<uint32_t>& raw,
                               std::vector<int64_t>& packed) {
   const Plan& P = c->last_plan;
@@ -1374,14 +1377,15 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
       HOT_CHECK(cp(oent, P.o_list, 4 * tp), "export");
       continue;
     }
-    // multipole and local records: the entry is the last word of each 16
-    // bytes; each group's records are packed in group order
+    // the accepted-cell region: a multipole entry is the last word of its
+    // 16-byte record, a local entry a word of its own; packed in group order
     const size_t acc = c->last_accepted;
     std::vector<uint32_t> rec(4 * acc);
     HOT_CHECK(cp(rec.data(), P.o_list + 4 * ((tp + 3) & ~size_t(3)), 16 * acc), "export");
     for (size_t g = 0; g < ng; ++g)
       for (int64_t i = 0; i < packed[g + 1] - packed[g]; ++i)
-        oent[packed[g] + i] = rec[4 * ((size_t)raw[g] + (size_t)i) + 3];
+        oent[packed[g] + i] =
+            kind == 2 ? rec[(size_t)raw[g] + (size_t)i] : rec[4 * ((size_t)raw[g] + (size_t)i) + 3];
   }
   return HOT_OK;
 }
@@ -1436,19 +1440,21 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
               "export");
     return HOT_OK;
   }
-  // the entry is the last word of each 16-byte multipole or local record;
-  // copy group by group from the packed index range
+  // a multipole entry is the last word of its 16-byte record, a local entry a
+  // word of its own; copy group by group from the packed index range
   std::vector<uint32_t> raw;
   std::vector<int64_t> packed;
   HOT_CHECK(list_layout(c, ws, kind, raw, packed), "export");
   const size_t tp = (size_t)c->stats.p2p_entries;
-  const uint32_t* rec = at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3)) + 3;
+  const uint32_t* reg = at<uint32_t>(ws, P.o_list) + ((tp + 3) & ~size_t(3));
+  const size_t stride = kind == 2 ? 1 : 4, last = kind == 2 ? 0 : 3;
   size_t g = (size_t)(std::upper_bound(packed.begin(), packed.end(), first) - packed.begin()) - 1;
   for (int64_t i = first; i < first + count; ++g) {
     const int64_t take = std::min(packed[g + 1], first + count) - i;
     if (take <= 0) continue;
-    HOT_CHECK(hipMemcpy2D(out + (i - first), 4, rec + 4 * ((size_t)raw[g] + (size_t)(i - packed[g])),
-                          16, 4, (size_t)take, hipMemcpyDeviceToHost),
+    HOT_CHECK(hipMemcpy2D(out + (i - first), 4,
+                          reg + stride * ((size_t)raw[g] + (size_t)(i - packed[g])) + last,
+                          4 * stride, 4, (size_t)take, hipMemcpyDeviceToHost),
               "export");
     i += take;
   }

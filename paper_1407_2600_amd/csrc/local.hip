@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
                                                           uint32_t gcap, double L,
                                                           const double* __restrict__ spos,
                                                           size_t n,
-                                                          const uint4* __restrict__ list,
+                                                          const uint32_t* __restrict__ list,
                                                           const T* __restrict__ mt,
                                                           double4* __restrict__ out) {
   constexpr int NM = nt(P), NQ = nt(Q);
@@ -200,21 +200,14 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
   T S[NQ];  // only the entries with c_n <= 1 are used
   static_for<NQ>([&](auto I) { S[I] = (T)0; });
   for (uint32_t q = lane; q < cnt; q += 64) {
-    const uint4 r = list[off + q];
-    const uint32_t e = r.w;
-    const int B = (int)(e & kCellMask);
-    T Rx, Ry, Rz;
-    if constexpr (std::is_same<T, float>::value) {
-      Rx = __uint_as_float(r.x);
-      Ry = __uint_as_float(r.y);
-      Rz = __uint_as_float(r.z);
-    } else {
-      const int img = (int)(e >> 27);
-      const double4 w = C.walk[B];
-      Rx = gc0 - (w.x + (double)(img / 9 - 1) * L);
-      Ry = gc1 - (w.y + (double)((img / 3) % 3 - 1) * L);
-      Rz = gc2 - (w.z + (double)(img % 3 - 1) * L);
-    }
+    // c - z from the cell's image-shifted centre of mass, in FP64 and then
+    // rounded to the arithmetic type
+    const uint32_t e = list[off + q];
+    const int B = (int)(e & kCellMask), img = (int)(e >> 27);
+    const double4 w = C.walk[B];
+    const T Rx = (T)(gc0 - (w.x + (double)(img / 9 - 1) * L));
+    const T Ry = (T)(gc1 - (w.y + (double)((img / 3) % 3 - 1) * L));
+    const T Rz = (T)(gc2 - (w.z + (double)(img % 3 - 1) * L));
     m2l_entry<P, Q, T>(Rx, Ry, Rz, mt + (size_t)B * NM, S);
   }
   // ---- sum over the lanes in FP64 (butterfly: every lane ends with the
@@ -252,7 +245,7 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
 template <int P, int Q>
 static hipError_t local_launch_pq(bool fp32, const Cells& C, const Groups& G, uint32_t ngroups,
                                   uint32_t gcap, double L, const double* spos, size_t n,
-                                  const uint4* list, const void* mt, double4* out,
+                                  const uint32_t* list, const void* mt, double4* out,
                                   hipStream_t s) {
   const unsigned nb = (ngroups + kLocalWaves - 1) / kLocalWaves;
   if (fp32)
@@ -267,7 +260,7 @@ static hipError_t local_launch_pq(bool fp32, const Cells& C, const Groups& G, ui
 template <int P>
 static hipError_t local_launch_p(int q, bool fp32, const Cells& C, const Groups& G,
                                  uint32_t ngroups, uint32_t gcap, double L, const double* spos,
-                                 size_t n, const uint4* list, const void* mt, double4* out,
+                                 size_t n, const uint32_t* list, const void* mt, double4* out,
                                  hipStream_t s) {
   switch (q) {
     case 2:
@@ -303,7 +296,7 @@ hipError_t local_moments_launch(bool fp32, int order, const double* mom, uint32_
 
 hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Groups& G,
                         uint32_t ngroups, uint32_t gcap, double L, const double* spos, size_t n,
-                        const uint4* list, const void* mt, double4* out, hipStream_t s) {
+                        const uint32_t* list, const void* mt, double4* out, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
   switch (order) {
     case 0: return local_launch_p<0>(q, fp32, C, G, ngroups, gcap, L, spos, n, list, mt, out, s);

@@ -445,47 +445,65 @@ __global__ void __launch_bounds__(256) k_group_compact(const uint32_t* __restric
   if (gflag[s]) gcell[gid[s]] = gcell_at[s];
 }
 
+// one wavefront per sink group (grid-stride over the groups): the lanes read
+// the group's particles together, then a butterfly min/max (exact, so the
+// box does not depend on the order)
 __global__ void __launch_bounds__(256) k_group_bbox(Cells C, Groups G, uint32_t ngroups,
                                                     uint32_t gcap, const double* __restrict__ spos,
                                                     size_t n) {
-  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ngroups) return;
-  const int c = G.cell[g];
-  const uint32_t f = C.first[c], e = f + C.count[c];
-  double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
-  double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-  for (uint32_t s = f; s < e; ++s)
+  const int lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * 4;
+  for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < ngroups; g += waves) {
+    const int c = G.cell[g];
+    const uint32_t f = C.first[c], cnt = C.count[c];
+    double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+    double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+    for (uint32_t t = lane; t < cnt; t += 64)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      double v = spos[(size_t)a * n + s];
-      lo[a] = v < lo[a] ? v : lo[a];
-      hi[a] = v > hi[a] ? v : hi[a];
+      for (int a = 0; a < 3; ++a) {
+        const double v = spos[(size_t)a * n + f + t];
+        lo[a] = v < lo[a] ? v : lo[a];
+        hi[a] = v > hi[a] ? v : hi[a];
+      }
+#pragma unroll
+    for (int w = 1; w < 64; w <<= 1)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double l = __shfl_xor(lo[a], w, 64), h = __shfl_xor(hi[a], w, 64);
+        lo[a] = l < lo[a] ? l : lo[a];
+        hi[a] = h > hi[a] ? h : hi[a];
+      }
+    if (lane < 3) {
+      G.lo[(size_t)lane * gcap + g] = lane == 0 ? lo[0] : lane == 1 ? lo[1] : lo[2];
+      G.hi[(size_t)lane * gcap + g] = lane == 0 ? hi[0] : lane == 1 ? hi[1] : hi[2];
     }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    G.lo[(size_t)a * gcap + g] = lo[a];
-    G.hi[(size_t)a * gcap + g] = hi[a];
   }
 }
 
-// source records: FP32/FP64 offsets from the leaf centre and the mass
+// source records: FP32/FP64 offsets from the leaf centre and the mass; one
+// wavefront per cell (grid-stride over the cells), its lanes over the leaf's
+// particles
 template <typename T4, typename T>
 __global__ void __launch_bounds__(256) k_srec(Cells C, uint32_t ncells,
                                               const double* __restrict__ spos,
                                               const double* __restrict__ smass, size_t n, double L,
                                               T4* __restrict__ srec) {
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells || C.nchild[c] != 0) return;
-  double ctr[3], side;
-  cell_center(C.key[c], C.level[c], L, ctr, &side);
-  const uint32_t f = C.first[c], e = f + C.count[c];
-  for (uint32_t s = f; s < e; ++s) {
-    T4 r;
-    r.x = (T)(spos[s] - ctr[0]);
-    r.y = (T)(spos[n + s] - ctr[1]);
-    r.z = (T)(spos[2 * n + s] - ctr[2]);
-    r.w = (T)smass[s];
-    srec[s] = r;
+  const int lane = threadIdx.x & 63;
+  const uint32_t waves = gridDim.x * 4;
+  for (uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < ncells; c += waves) {
+    if (C.nchild[c] != 0) continue;
+    double ctr[3], side;
+    cell_center(C.key[c], C.level[c], L, ctr, &side);
+    const uint32_t f = C.first[c], cnt = C.count[c];
+    for (uint32_t t = lane; t < cnt; t += 64) {
+      const uint32_t s = f + t;
+      T4 r;
+      r.x = (T)(spos[s] - ctr[0]);
+      r.y = (T)(spos[n + s] - ctr[1]);
+      r.z = (T)(spos[2 * n + s] - ctr[2]);
+      r.w = (T)smass[s];
+      srec[s] = r;
+    }
   }
 }
 
@@ -576,13 +594,15 @@ hipError_t tree_groups(const Cells& C, uint32_t ncells, int gmax, size_t n, uint
 hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
                            const double* spos, size_t n, hipStream_t s) {
   if (ngroups == 0) return hipSuccess;
-  k_group_bbox<<<(ngroups + 255) / 256, 256, 0, s>>>(C, G, ngroups, gcap, spos, n);
+  const unsigned g = std::min<uint32_t>((ngroups + 3) / 4, 1u << 16);  // four waves a block
+  k_group_bbox<<<g, 256, 0, s>>>(C, G, ngroups, gcap, spos, n);
   return hipGetLastError();
 }
 
 hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
                      size_t n, double L, void* srec, bool fp32, hipStream_t s) {
-  unsigned g = (ncells + 255) / 256;
+  if (ncells == 0) return hipSuccess;
+  const unsigned g = std::min<uint32_t>((ncells + 3) / 4, 1u << 16);  // four waves a block
   if (fp32)
     k_srec<float4, float><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, (float4*)srec);
   else

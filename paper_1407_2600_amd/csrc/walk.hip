@@ -10,9 +10,10 @@
 //   - image 0 and the cell contains the group: open;
 //   - acceptance test passes: the group's local list if the local-expansion
 //     bound holds there (LocalPrm), else the multipole list (the count pass
-//     counts both together; the emit pass decides, writing the multipole
-//     records from the front of the group's region and the local records
-//     from its back, and then the two counts and the local offset);
+//     counts both together; the emit pass decides, writing the 16-byte
+//     multipole records from the front of the group's region and the local
+//     entries, one 32-bit word each, from its back, and then the two counts
+//     and the local entries' word offset);
 //   - a leaf: direct list;
 //   - otherwise: open (push the daughters).
 // Ballots and a wave prefix sum place the emitted entries and the pushed
@@ -177,12 +178,10 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     const uint64_t bp = __ballot(action == 3);
     const uint64_t bl = __ballot(action == 4);
     if (EMIT) {
-      // local records: the offset of the group's centre from the cell's
-      // image-shifted centre of mass, c - z
+      // local entries: the bare (image << 27 | cell) word, packed downwards
+      // from the end of the group's accepted region
       if (action == 4)
-        m2p_list[oe - 1 - nl - (uint32_t)__popcll(bl & below)] =
-            make_uint4(__float_as_uint((float)(gc0 - cc0)), __float_as_uint((float)(gc1 - cc1)),
-                       __float_as_uint((float)(gc2 - cc2)), e);
+        reinterpret_cast<uint32_t*>(m2p_list)[4 * oe - 1 - nl - (uint32_t)__popcll(bl & below)] = e;
       if (action == 2)
         m2p_list[om + nm + (uint32_t)__popcll(bm & below)] =
             make_uint4(__float_as_uint((float)(cc0 - cA[0])), __float_as_uint((float)(cc1 - cA[1])),
@@ -214,7 +213,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     } else {
       G.cnt_m2p[g] = nm;
       G.cnt_m2l[g] = nl;
-      G.off_m2l[g] = om + nm;  // the local records, in reverse emission order
+      G.off_m2l[g] = 4 * oe - nl;  // 32-bit word index of the local entries
     }
   }
 }
