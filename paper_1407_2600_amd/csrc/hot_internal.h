@@ -112,14 +112,15 @@ constexpr int kP2PFlops = 20;
 
 // Algorithmic flops of the group-level local route (fma = 2), as the
 // kernel formulates it: per local-list entry, the derivatives D_m,
-// |m| <= P+Q, of the Newtonian kernel (setup: |R|^2, its reciprocal square
-// root and square, the scaled R_i and the per-degree factors; the components
-// with at most one z index by the recurrence, one multiply-add per nonzero
-// m_i and per m_i >= 2 plus the combination; the others by the trace
-// relation, one add) and the contraction S_n += Mt_k D_(n+k) for the
-// independent n (at most one z index), |n| <= Q, and the stored |k| <= P
-// (no dipole); per sink, the value and gradient of the order-Q polynomial
-// (4 fma per term) after the offset.
+// |m| <= P+Q, of the Newtonian kernel with at most two z indices (setup:
+// |R|^2, its reciprocal square root and square, the scaled R_i and the
+// per-degree factors; at most one z index by the recurrence, one
+// multiply-add per nonzero m_i and per m_i >= 2 plus the combination; two z
+// indices by the trace relation, one add) and the contraction
+// S_n += Mt'_k D_(n+k) for the independent n (at most one z index),
+// |n| <= Q, and the folded moments k (at most one z index, |k| <= P, no
+// dipole); per sink, the value and gradient of the order-Q polynomial
+// (4 fma per term) after the offset.  The folding itself is per cell.
 __host__ __device__ constexpr int m2l_flops(int P, int Q) {
   const int N = P + Q;
   int f = 5 + 1 + 1 + 3 * N + 2 * N;
@@ -127,7 +128,8 @@ __host__ __device__ constexpr int m2l_flops(int P, int Q) {
     for (int a = d; a >= 0; --a)
       for (int b = d - a; b >= 0; --b) {
         const int c = d - a - b;
-        if (c >= 2) {
+        if (c >= 3) continue;
+        if (c == 2) {
           f += 1;
           continue;
         }
@@ -139,7 +141,7 @@ __host__ __device__ constexpr int m2l_flops(int P, int Q) {
   for (int dn = 0; dn <= Q; ++dn)
     for (int dk = 0; dk <= P; ++dk) {
       if (dk == 1) continue;
-      pairs += (2 * dn + 1) * ((dk + 1) * (dk + 2) / 2);
+      pairs += (2 * dn + 1) * (2 * dk + 1);
     }
   return f + 2 * pairs;
 }

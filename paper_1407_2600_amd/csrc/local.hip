@@ -12,9 +12,13 @@
 //                     - (|m|-1) sum_i m_i (m_i - 1) D_(m-2 e_i),
 // obtained by writing (|R|^2 + 2 R.h + |h|^2) g(R+h)^2 = 1, applying h.grad
 // and matching powers of h.  g is harmonic, so D_m and S_n are traceless:
-// D_(a,b,c+2) = -D_(a+2,b,c) - D_(a,b+2,c), and likewise S.  Only the
-// components with at most one z index (2d+1 of degree d) go through the
-// recurrence and the contraction; the others follow by that relation.
+// D_(a,b,c+2) = -D_(a+2,b,c) - D_(a,b+2,c), and likewise S.  The same
+// relation folds every moment with two or more z indices into moments of
+// the same degree with fewer (Mt_(a,b,c) D_(n+(a,b,c)) = -Mt_(a,b,c)
+// D_(n+(a+2,b,c-2)) - Mt_(a,b,c) D_(n+(a,b+2,c-2))), once per cell: the
+// contraction then runs over the 2d+1 folded moments of degree d with at
+// most one z index, for the 2d+1 such S_n, and needs D_m with at most two
+// z indices only.  The dependent S_n follow by the trace relation.
 // Every sink then takes Phi += sum_n L_n (x - c)^n and its gradient.
 //
 // One wavefront per group: its lanes take the group's local-list entries
@@ -67,18 +71,6 @@ struct InvFactorial {
   }
 };
 
-// Mt_k of every cell (cell-major, nt(P) values of type T per cell)
-template <int P, typename T>
-__global__ void __launch_bounds__(256) k_local_moments(const double* __restrict__ mom,
-                                                       uint32_t ncells, T* __restrict__ mt) {
-  constexpr LocalMomFac<P> fac{};
-  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= ncells) return;
-#pragma unroll
-  for (int k = 0; k < nt(P); ++k)
-    mt[(size_t)c * nt(P) + k] = (T)(fac.f[k] * mom[(size_t)c * nt(P) + k]);
-}
-
 // components of multi-index number idx (multi-index order)
 struct MIv {
   int a, b, c;
@@ -93,19 +85,64 @@ __host__ __device__ constexpr MIv mi_of(int idx) {
       }
 }
 
-// The lanes' re-expansion of one cell: D_m for |m| <= P+Q in multi-index
-// order (the recurrence for at most one z index, the trace relation for the
-// rest), each D_m added into the partial sums S_n of the independent n
-// (c_n <= 1, n = m - k) as soon as it exists, so that only the last degrees
-// of D stay live.  Everything is unrolled at compile time.
+// the folded moments kept per cell: at most one z index, no dipole (it
+// vanishes about the centre of mass); fold_slot(k) is the place of moment k
+// among them (multi-index order), -1 if it is not kept
+__host__ __device__ constexpr bool fold_kept(int k) {
+  const MIv v = mi_of(k);
+  return v.c <= 1 && v.a + v.b + v.c != 1;
+}
+__host__ __device__ constexpr int fold_slot(int k) {
+  if (!fold_kept(k)) return -1;
+  int s = 0;
+  for (int i = 0; i < k; ++i) s += fold_kept(i) ? 1 : 0;
+  return s;
+}
+__host__ __device__ constexpr int fold_count(int P) {
+  int s = 0;
+  for (int i = 0; i < nt(P); ++i) s += fold_kept(i) ? 1 : 0;
+  return s;
+}
+
+// the folded Mt of every cell (cell-major, fold_count(P) values of type T
+// per cell), folded in FP64: in reverse multi-index order every component
+// has received all that folds into it before it is itself folded away
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_local_moments(const double* __restrict__ mom,
+                                                       uint32_t ncells, T* __restrict__ mt) {
+  constexpr LocalMomFac<P> fac{};
+  constexpr int NM = nt(P), NF = fold_count(P);
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncells) return;
+  double v[NM];
+  static_for<NM>([&](auto K) { v[K] = fac.f[K] * mom[(size_t)c * NM + K]; });
+  static_for<NM>([&](auto KK) {
+    constexpr int k = NM - 1 - KK;
+    constexpr MIv kv = mi_of(k);
+    if constexpr (kv.c >= 2) {
+      v[mi_index(kv.a + 2, kv.b, kv.c - 2)] -= v[k];
+      v[mi_index(kv.a, kv.b + 2, kv.c - 2)] -= v[k];
+    }
+  });
+  static_for<NM>([&](auto K) {
+    if constexpr (fold_kept(K)) {
+      constexpr int slot = fold_slot(K);
+      mt[(size_t)c * NF + slot] = (T)v[K];
+    }
+  });
+}
+
+// The lanes' re-expansion of one cell: D_m for |m| <= P+Q with at most two
+// z indices, in multi-index order (the recurrence for at most one, the trace
+// relation for two), each D_m added into the partial sums S_n of the
+// independent n (c_n <= 1, n = m - k, k a folded moment) as soon as it
+// exists, so that only the last degrees of D stay live.  Everything is
+// unrolled at compile time.
 template <int P, int Q, typename T>
 __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, const T* __restrict__ M, T* S) {
-  constexpr int N = P + Q, ND = nt(N), NM = nt(P);
-  T Mk[NM];
-  static_for<NM>([&](auto KK) {
-    constexpr int k = KK;
-    if constexpr (k < 1 || k > 3) Mk[k] = M[k];  // the dipole about the centre of mass vanishes
-  });
+  constexpr int N = P + Q, ND = nt(N), NM = nt(P), NF = fold_count(P);
+  T Mk[NF];
+  static_for<NF>([&](auto I) { Mk[I] = M[I]; });
   const T s = Rx * Rx + Ry * Ry + Rz * Rz;
   const T d0 = rsqrt_t(s);
   const T is = d0 * d0;
@@ -127,9 +164,11 @@ __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, const T* __restrict_
     constexpr int m = MM;
     constexpr MIv mv = mi_of(m);
     constexpr int a = mv.a, b = mv.b, c = mv.c, d = a + b + c;
-    if constexpr (m == 0) {
+    if constexpr (c >= 3) {
+      // not needed: m = n + k with c_n, c_k <= 1
+    } else if constexpr (m == 0) {
       D[0] = d0;
-    } else if constexpr (c >= 2) {
+    } else if constexpr (c == 2) {
       // traceless: (d/dz)^2 = -(d/dx)^2 - (d/dy)^2 on a harmonic function
       D[m] = -D[mi_index(a + 2, b, c - 2)] - D[mi_index(a, b + 2, c - 2)];
     } else {
@@ -162,14 +201,15 @@ __device__ __forceinline__ void m2l_entry(T Rx, T Ry, T Rz, const T* __restrict_
       }
     }
     // S_n += Mt_k D_m for every split m = n + k with n independent
-    // (c_n <= 1), |n| <= Q, |k| <= P
+    // (c_n <= 1), |n| <= Q, and k a folded moment
     static_for<NM>([&](auto KK) {
       constexpr int k = KK;
       constexpr MIv kv = mi_of(k);
-      if constexpr ((k < 1 || k > 3) && kv.a <= a && kv.b <= b && kv.c <= c &&
+      if constexpr (c <= 2 && fold_kept(k) && kv.a <= a && kv.b <= b && kv.c <= c &&
                     d - (kv.a + kv.b + kv.c) <= Q && c - kv.c <= 1) {
         constexpr int nidx = mi_index(a - kv.a, b - kv.b, c - kv.c);
-        S[nidx] = fma(Mk[k], D[m], S[nidx]);
+        constexpr int slot = fold_slot(k);
+        S[nidx] = fma(Mk[slot], D[m], S[nidx]);
       }
     });
   });
@@ -183,7 +223,7 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
                                                           const uint32_t* __restrict__ list,
                                                           const T* __restrict__ mt,
                                                           double4* __restrict__ out) {
-  constexpr int NM = nt(P), NQ = nt(Q);
+  constexpr int NF = fold_count(P), NQ = nt(Q);
   constexpr InvFactorial<Q> ifac{};
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint32_t g = __builtin_amdgcn_readfirstlane(xcd_block() * kLocalWaves + wid);
@@ -208,7 +248,7 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
     const T Rx = (T)(gc0 - (w.x + (double)(img / 9 - 1) * L));
     const T Ry = (T)(gc1 - (w.y + (double)((img / 3) % 3 - 1) * L));
     const T Rz = (T)(gc2 - (w.z + (double)(img % 3 - 1) * L));
-    m2l_entry<P, Q, T>(Rx, Ry, Rz, mt + (size_t)B * NM, S);
+    m2l_entry<P, Q, T>(Rx, Ry, Rz, mt + (size_t)B * NF, S);
   }
   // ---- sum over the lanes in FP64 (butterfly: every lane ends with the
   // sums), then the dependent S_n by the trace relation, and L_n = S_n / n!
