@@ -8,6 +8,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -36,10 +38,10 @@ def test_workload_defaults():
         assert os.path.exists(os.path.join(ROOT, "tests", "golden", w["ref"]))
         if w["heldout"]:
             assert os.path.exists(os.path.join(ROOT, "tests", "golden", w["heldout"]))
-    # the 128^3 operating point is the configuration the counters were taken at
-    cfg = b.TRAFFIC["config"]
-    op = b.OPERATING_POINT[b.TRAFFIC["workload"]]
-    assert all(op[k] == cfg[k] for k in op)
+    # each counter record was taken at its workload's operating point
+    for t in b.TRAFFIC:
+        op = b.OPERATING_POINT[t["workload"]]
+        assert all(op[k] == t["config"][k] for k in op)
 
 
 def test_heldout_targets_are_disjoint_from_selection():
@@ -53,26 +55,28 @@ def test_heldout_targets_are_disjoint_from_selection():
     assert len(np.intersect1d(sel, held)) == 0
 
 
-def test_traffic_reported_only_for_its_configuration():
+@pytest.mark.parametrize("rec", [0, -1])
+def test_traffic_reported_only_for_its_configuration(rec):
     import hashlib
     b = _bench()
-    prm = dict(b.TRAFFIC["config"], box=1.0, G=1.0, periodic=1)
-    wl = b.TRAFFIC["workload"]
+    t = b.TRAFFIC[rec]
+    prm = dict(t["config"], box=1.0, G=1.0, periodic=1)
+    wl = t["workload"]
     h = hashlib.sha256()
-    for f in b.TRAFFIC["sources"]:
+    for f in b.TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_1407_2600_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != b.TRAFFIC["sha256"]:
-        # sources changed since the counter runs: nothing is reported
-        assert b.measured_traffic(prm, wl) is None
-        b.TRAFFIC["sha256"] = h.hexdigest()
-    assert b.measured_traffic(prm, wl) == b.TRAFFIC["bytes_per_launch"]
-    assert b.measured_traffic(dict(prm, group_max=prm["group_max"] * 2), wl) is None
-    assert b.measured_traffic(dict(prm, err_tol=prm["err_tol"] * 1.5), wl) is None
-    assert b.measured_traffic(prm, "nfw256") is None
-    saved = b.TRAFFIC["sha256"]
+    saved = t["sha256"]
     try:
-        b.TRAFFIC["sha256"] = "0" * 64  # sources changed since the counter runs
+        if h.hexdigest() != saved:
+            # sources changed since the counter runs: nothing is reported
+            assert b.measured_traffic(prm, wl) is None
+            t["sha256"] = h.hexdigest()
+        assert b.measured_traffic(prm, wl) == t["bytes_per_eval"]
+        assert b.measured_traffic(dict(prm, group_max=prm["group_max"] * 2), wl) is None
+        assert b.measured_traffic(dict(prm, err_tol=prm["err_tol"] * 1.5), wl) is None
+        assert b.measured_traffic(prm, "nfw256") is None
+        t["sha256"] = "0" * 64  # sources changed since the counter runs
         assert b.measured_traffic(prm, wl) is None
     finally:
-        b.TRAFFIC["sha256"] = saved
+        t["sha256"] = saved
