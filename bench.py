@@ -195,11 +195,11 @@ def measured_traffic(prm, workload):
 
 
 # Algorithmic HBM bytes of the bandwidth-bound stages (FP32 mode): the keys,
-# sort and gather stage per particle (keys 36 B, 8 radix passes of 24 B,
+# sort and gather stage per particle (keys 36 B, 7 radix passes of 24 B,
 # gather 56 B), and the build stage per particle and per cell (tree levels
 # 12 B + 48 B/cell, moments and coefficient blocks 28 B + 600 B/cell, groups
 # and source records 60 B).
-SORT_BYTES_PER_PARTICLE = 36 + 8 * 24 + 56
+SORT_BYTES_PER_PARTICLE = 36 + 7 * 24 + 56
 BUILD_BYTES_PER_PARTICLE = 12 + 28 + 60
 BUILD_BYTES_PER_CELL = 48 + 600
 

@@ -15,8 +15,8 @@ namespace hot {
 // stage launchers (other translation units)
 hipError_t launch_keys(const double* pos, size_t n, double L, double S, uint64_t* key,
                        uint32_t* idx, uint32_t* bad, hipStream_t s);
-hipError_t radix_sort(uint64_t* key0, uint32_t* idx0, uint64_t* key1, uint32_t* idx1, size_t n,
-                      uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
+hipError_t radix_sort(uint64_t* key_in, uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out,
+                      size_t n, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s);
 hipError_t launch_gather(const double* pos, const void* mass, bool fp32, size_t n, double L,
                          const uint32_t* idx, double* spos, double* smass, uint32_t* bad,
                          hipStream_t s);
@@ -441,8 +441,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     if (c->events_ok) HOT_CHECK(hipEventRecord(c->ev[2], s), "event");
   } else {
   HOT_CHECK(zero_launch(ctr, 4 * CTR_N, s), "clear counters");
-  HOT_CHECK(launch_keys(pos, n, p.box, c->S, key0, idx0, ctr + CTR_BAD, s), "keys");
-  HOT_CHECK(radix_sort(key0, idx0, key1, idx1, n, at<uint32_t>(ws, P.o_hist), scan_tmp, s),
+  // keys into the second buffer pair; the sort leaves them in the first
+  HOT_CHECK(launch_keys(pos, n, p.box, c->S, key1, idx1, ctr + CTR_BAD, s), "keys");
+  HOT_CHECK(radix_sort(key1, idx1, key0, idx0, n, at<uint32_t>(ws, P.o_hist), scan_tmp, s),
             "sort");
   HOT_CHECK(launch_gather(pos, mass, fp32, n, p.box, idx0, spos, smass, ctr + CTR_BAD, s),
             "gather");

@@ -22,7 +22,7 @@ constexpr int kImgBits = 5;          // list entry = image << 27 | cell
 constexpr uint32_t kCellMask = (1u << 27) - 1;
 constexpr int kWalkStack = 2048;     // LDS walk stack entries per wave
 constexpr int kWalkStackBig = 4096;  // fallback for groups with very many pending cells
-constexpr int kSortBits = 8;
+constexpr int kSortBits = 9;
 constexpr int kSortBins = 1 << kSortBits;
 constexpr int kSortTile = 4096;      // keys per sort block
 constexpr int kScanBlocks = 1024;    // blocks of the device-wide scan

@@ -7,12 +7,14 @@
 // cell's key at level l is key >> 3(21 - l), its parent key >> 3 and its
 // daughters key << 3 | octant.
 //
-// Sort: least-significant-digit radix sort of (key, index) with 8-bit digits.
+// Sort: least-significant-digit radix sort of (key, index) with 9-bit digits
+// over bits 0..62 (7 passes; the placeholder bit is the same in every key).
 // Each pass builds per-tile digit histograms in LDS, scans them digit-major
 // across tiles, and scatters with a stable in-tile rank computed from wave
-// ballots, so equal keys keep their original order; each tile is put in
-// digit order in LDS first and written out run by run.
-#include "hot_internal.h"
+// ballots and per-wavefront digit counts, so equal keys keep their original
+// order; each tile is put in digit order in LDS first and written out run by
+// run.
+#include "device_math.h"
 
 namespace hot {
 
@@ -61,11 +63,17 @@ __global__ void __launch_bounds__(256) k_keys(const double* __restrict__ pos, si
 namespace {
 constexpr int kT = 256;
 constexpr int kRounds = kSortTile / kT;
+constexpr int kDPT = kSortBins / kT;  // digits per thread, consecutive
+// bit 63 (the placeholder) is the same in every key: the passes cover bits
+// 0..62
+constexpr int kPasses = (63 + kSortBits - 1) / kSortBits;
+static_assert(kSortBins % kT == 0, "each thread owns whole digits");
+static_assert(kPasses % 2 == 1, "the last pass writes the second buffer pair");
 
 __global__ void __launch_bounds__(kT) k_hist(const uint64_t* __restrict__ key, size_t n, int shift,
                                              uint32_t* __restrict__ hist, int nblk) {
   __shared__ uint32_t h[kSortBins];
-  h[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < kSortBins; d += kT) h[d] = 0;
   __syncthreads();
   size_t beg = (size_t)blockIdx.x * kSortTile;
   for (int r = 0; r < kRounds; ++r) {
@@ -73,82 +81,131 @@ __global__ void __launch_bounds__(kT) k_hist(const uint64_t* __restrict__ key, s
     if (i < n) atomicAdd(&h[(key[i] >> shift) & (kSortBins - 1)], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < kSortBins; d += kT) hist[(size_t)d * nblk + blockIdx.x] = h[d];
 }
 
-// Scatter of one tile: stable tile-local ranks (wave ballots, per-wave digit
-// counts) place the tile's keys in LDS in digit order; the tile is then
-// written out in that order, so consecutive threads write consecutive
-// addresses of each digit's run in the output.
+// Scatter of one tile.  Each wavefront takes a contiguous quarter of the
+// tile (16 rounds of 64 keys) and counts its keys per digit in a row of its
+// own (wave ballots find the lanes with the same digit; one leader per digit
+// adds), with no block barrier between rounds.  The digit offsets within the
+// tile (from the scanned histogram) and the rows give each wavefront's
+// starting offset per digit; the wavefronts then place their keys in LDS in
+// digit order (stable: earlier rounds, then lower lanes, then lower
+// wavefronts first), and the tile is written out run by run, so consecutive
+// threads write consecutive addresses of each digit's run in the output.
 __global__ void __launch_bounds__(kT) k_scatter(const uint64_t* __restrict__ kin,
                                                 const uint32_t* __restrict__ vin, size_t n,
                                                 int shift, const uint32_t* __restrict__ off,
                                                 int nblk, uint64_t* __restrict__ kout,
                                                 uint32_t* __restrict__ vout) {
+  constexpr int kWaves = kT / 64, kPerWave = kSortTile / kWaves, kWR = kPerWave / 64;
   __shared__ uint32_t base[kSortBins];  // output offset of this tile's digit d
-  __shared__ uint32_t loff[kSortBins];  // tile-local offset of digit d, advanced per round
   __shared__ uint32_t lbeg[kSortBins];  // tile-local offset of digit d
-  __shared__ uint32_t wcnt[kT / 64][kSortBins];
+  __shared__ uint32_t wrow[kWaves][kSortBins];  // per wavefront: its count, then its offset
+  __shared__ uint32_t psum[kT];
   __shared__ uint64_t sk[kSortTile];
   __shared__ uint32_t sv[kSortTile];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const size_t beg = (size_t)blockIdx.x * kSortTile;
   const uint32_t tn = (uint32_t)(n - beg < (size_t)kSortTile ? n - beg : (size_t)kSortTile);
-  // this tile's count of digit t: the next entry of the digit-major scanned
-  // histogram (the same digit's next tile, or the next digit's first tile)
-  const size_t e = (size_t)t * nblk + blockIdx.x;
-  const uint32_t o0 = off[e];
-  const uint32_t o1 = (e + 1 < (size_t)kSortBins * nblk) ? off[e + 1] : (uint32_t)n;
-  base[t] = o0;
-  // exclusive scan of the counts over the 256 digits (one per thread)
-  uint32_t c = o1 - o0;
-  wcnt[0][t] = c;
-  __syncthreads();
-  for (int d = 1; d < kSortBins; d <<= 1) {
-    const uint32_t u = t >= d ? wcnt[0][t - d] : 0u;
-    __syncthreads();
-    c += u;
-    wcnt[0][t] = c;
-    __syncthreads();
+  // this tile's count of each of the thread's digits: the next entry of the
+  // digit-major scanned histogram (the same digit's next tile, or the next
+  // digit's first tile)
+  uint32_t cnt[kDPT];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int j = 0; j < kDPT; ++j) {
+    const int d = t * kDPT + j;
+    const size_t e = (size_t)d * nblk + blockIdx.x;
+    const uint32_t o0 = off[e];
+    const uint32_t o1 = (e + 1 < (size_t)kSortBins * nblk) ? off[e + 1] : (uint32_t)n;
+    base[d] = o0;
+    cnt[j] = o1 - o0;
+    tsum += cnt[j];
+    for (int w = 0; w < kWaves; ++w) wrow[w][d] = 0;
   }
-  loff[t] = c - (o1 - o0);
-  lbeg[t] = c - (o1 - o0);
-  for (int w = 0; w < kT / 64; ++w) wcnt[w][t] = 0;
+  // the wavefront's keys and values
+  const uint32_t w0 = (uint32_t)wid * kPerWave;
+  uint64_t kr[kWR];
+  uint32_t vr[kWR];
+#pragma unroll
+  for (int r = 0; r < kWR; ++r) {
+    const uint32_t li = w0 + (uint32_t)(r * 64 + lane);
+    kr[r] = li < tn ? kin[beg + li] : 0ull;
+    vr[r] = li < tn ? vin[beg + li] : 0u;
+  }
   __syncthreads();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t li = (uint32_t)(r * kT + t);
-    const bool valid = li < tn;
-    const uint64_t k = valid ? kin[beg + li] : 0ull;
-    const uint32_t v = valid ? vin[beg + li] : 0u;
-    const uint32_t d = valid ? (uint32_t)((k >> shift) & (kSortBins - 1)) : 0u;
-    // lanes of this wave with the same digit
+  // lanes of this wavefront whose keys have the same digit d
+  auto match = [](uint32_t d, bool valid) {
     uint64_t same = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kSortBits; ++b) {
       const uint64_t bb = __ballot((d >> b) & 1u);
       same &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(same & below);
-    const bool leader = valid && ((same & below) == 0ull);
-    if (leader) wcnt[wid][d] = (uint32_t)__popcll(same);
+    return same;
+  };
+  auto digit = [&](uint64_t k, bool valid) {
+    return valid ? (uint32_t)((k >> shift) & (kSortBins - 1)) : 0u;
+  };
+  // ---- count per digit in the wavefront's own row; keep per round the
+  // digit, the rank among the round's lanes with that digit, their number
+  // and whether the lane holds a key: d | rank << 9 | count << 15 | 1 << 22
+  static_assert(kSortBits <= 9, "digit field");
+  uint32_t info[kWR];
+#pragma unroll
+  for (int r = 0; r < kWR; ++r) {
+    const bool valid = w0 + (uint32_t)(r * 64 + lane) < tn;
+    const uint32_t d = digit(kr[r], valid);
+    const uint64_t same = match(d, valid);
+    const uint32_t rank = (uint32_t)__popcll(same & below), num = (uint32_t)__popcll(same);
+    if (valid && rank == 0) wrow[wid][d] += num;
+    info[r] = d | rank << 9 | num << 15 | (valid ? 1u << 22 : 0u);
+    wave_sync();
+  }
+  // ---- tile offsets per digit (scan of the threads' counts, digits in
+  // thread order), then each wavefront's offset per digit
+  uint32_t c = tsum;
+  psum[t] = c;
+  __syncthreads();
+  for (int d = 1; d < kT; d <<= 1) {
+    const uint32_t u = t >= d ? psum[t - d] : 0u;
     __syncthreads();
-    if (valid) {
-      uint32_t pre = loff[d];
-      for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
-      sk[pre + rank] = k;
-      sv[pre + rank] = v;
-    }
-    __syncthreads();
-    // advance the per-digit tile offsets and clear the wave counts
-    uint32_t add = 0;
-    for (int w = 0; w < kT / 64; ++w) {
-      add += wcnt[w][t];
-      wcnt[w][t] = 0;
-    }
-    loff[t] += add;
+    c += u;
+    psum[t] = c;
     __syncthreads();
   }
+  uint32_t run = c - tsum;
+#pragma unroll
+  for (int j = 0; j < kDPT; ++j) {
+    const int d = t * kDPT + j;
+    lbeg[d] = run;
+    uint32_t o = run;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t k = wrow[w][d];
+      wrow[w][d] = o;
+      o += k;
+    }
+    run += cnt[j];
+  }
+  __syncthreads();
+  // ---- place the keys in digit order
+#pragma unroll
+  for (int r = 0; r < kWR; ++r) {
+    const bool valid = (info[r] >> 22) & 1u;
+    const uint32_t d = info[r] & (kSortBins - 1), rank = (info[r] >> 9) & 63u,
+                   num = (info[r] >> 15) & 127u;
+    const uint32_t o = valid ? wrow[wid][d] : 0u;
+    wave_sync();
+    if (valid) {
+      sk[o + rank] = kr[r];
+      sv[o + rank] = vr[r];
+      if (rank == 0) wrow[wid][d] = o + num;
+    }
+    wave_sync();
+  }
+  __syncthreads();
   for (uint32_t j = (uint32_t)t; j < tn; j += kT) {
     const uint64_t k = sk[j];
     const uint32_t d = (uint32_t)((k >> shift) & (kSortBins - 1));
@@ -159,17 +216,18 @@ __global__ void __launch_bounds__(kT) k_scatter(const uint64_t* __restrict__ kin
 }
 }  // namespace
 
-// Sort (key, idx) ascending by key, stable.  Buffers a and b alternate; the
-// result ends in buffer 0 after an even number of passes (8).
-hipError_t radix_sort(uint64_t* key0, uint32_t* idx0, uint64_t* key1, uint32_t* idx1, size_t n,
-                      uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
+// Sort (key, idx) ascending by key, stable, from the first buffer pair into
+// the second; the passes alternate between the pairs (an odd number of them,
+// so the last writes the second pair) and the first pair is overwritten.
+hipError_t radix_sort(uint64_t* key_in, uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out,
+                      size_t n, uint32_t* hist, uint32_t* scan_tmp, hipStream_t s) {
   if (n == 0) return hipSuccess;
   int nblk = (int)((n + kSortTile - 1) / kSortTile);
-  uint64_t* kin = key0;
-  uint32_t* vin = idx0;
-  uint64_t* kout = key1;
-  uint32_t* vout = idx1;
-  for (int pass = 0; pass < 8; ++pass) {
+  uint64_t* kin = key_in;
+  uint32_t* vin = idx_in;
+  uint64_t* kout = key_out;
+  uint32_t* vout = idx_out;
+  for (int pass = 0; pass < kPasses; ++pass) {
     int shift = pass * kSortBits;
     k_hist<<<nblk, kT, 0, s>>>(kin, n, shift, hist, nblk);
     hipError_t e = scan_u32(hist, hist, nullptr, (size_t)kSortBins * nblk, scan_tmp, s);

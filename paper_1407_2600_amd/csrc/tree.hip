@@ -304,6 +304,11 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
   // (daughters in octant order, j ascending)
   double b2 = 0.0, bmax = 0.0;
   double bk[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // raw moments about the centre of mass (at a leaf summed in the same pass
+  // over its particles as the B_k)
+  double M[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) M[k] = 0.0;
   if (nc == 0) {
     double r2max = 0.0;
     for (uint32_t s = f; s < e; ++s) {
@@ -323,6 +328,16 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
       bk[3] = bk[3] + ms * r3;
       bk[4] = bk[4] + ms * r4;
       bk[5] = bk[5] + ms * r5;
+      const double d[3] = {ex, ey, ez};
+      double pw[3][P + 1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        pw[a][0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
+      }
+#pragma unroll
+      for (int k = 0; k < NM; ++k) M[k] += ms * pw[0][mi.a[k]] * pw[1][mi.b[k]] * pw[2][mi.c[k]];
     }
     bmax = sqrt(r2max);
   } else {
@@ -381,25 +396,8 @@ __global__ void __launch_bounds__(128) k_moments(Cells C, const double* __restri
   C.mmx[c] = make_double4(m, sx, sy, sz);
   C.walk[c] = make_double4(com[0], com[1], com[2], rcrit);
 
-  // raw moments about the centre of mass
-  double M[NM];
-#pragma unroll
-  for (int k = 0; k < NM; ++k) M[k] = 0.0;
-  if (nc == 0) {
-    for (uint32_t s = f; s < e; ++s) {
-      double ms = smass[s];
-      double d[3] = {spos[s] - com[0], spos[n + s] - com[1], spos[2 * n + s] - com[2]};
-      double pw[3][P + 1];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        pw[a][0] = 1.0;
-#pragma unroll
-        for (int q = 1; q <= P; ++q) pw[a][q] = pw[a][q - 1] * d[a];
-      }
-#pragma unroll
-      for (int k = 0; k < NM; ++k) M[k] += ms * pw[0][mi.a[k]] * pw[1][mi.b[k]] * pw[2][mi.c[k]];
-    }
-  } else {
+  // raw moments above the leaves: the daughters' shifted to this centre
+  if (nc != 0) {
     for (int kc = 0; kc < nc; ++kc) {
       const int ch = c0 + kc;
       const double4 w = C.walk[ch];
