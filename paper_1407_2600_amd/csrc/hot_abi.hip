@@ -415,8 +415,9 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   int nlev = 1;
   uint32_t ncells = 0, ngroups = 0;
   bool big = false;
-  // tm counts the accepted cells, multipole and local records together (the
-  // walk's count pass does not split them; its emit pass does)
+  // tm counts the accepted cells, multipole and local entries together (the
+  // walk's count pass does not split them; its emit pass does), with room for
+  // a 16-byte record each
   size_t tp = 0, tm = 0;
   struct Chunk {
     uint32_t g0, g1;
@@ -544,8 +545,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   tp = sums[0];
   tm = sums[1];
   const size_t maxw = host[CTR_MAXW];
-  // list words: direct entries 1, multipole and local records 4, plus 16-byte
-  // alignment
+  // list words: direct entries 1, accepted cells 4 (room for a multipole
+  // record; a local entry takes 1 of them), plus 16-byte alignment
   const size_t words = tp + 4 * tm + 4;
   c->list_per_particle = std::max(c->list_per_particle, 1.25 * (double)words / (double)n);
   if (maxw + 4 > P.cap_list) {
