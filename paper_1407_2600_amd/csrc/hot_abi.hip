@@ -52,6 +52,8 @@ hipError_t local_launch(bool fp32, int order, int q, const Cells& C, const Group
                         const uint32_t* list, const void* mt, double4* out, hipStream_t s);
 hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sums, uint32_t* maxw,
                       hipStream_t s);
+hipError_t block_counts(const Groups& G, uint32_t ngroups, unsigned long long* bp,
+                        unsigned long long* bm, hipStream_t s);
 hipError_t count_pairs(const Cells& C, const Groups& G, uint32_t ngroups, bool local,
                        const uint32_t* p2p_list, unsigned long long* out,
                        unsigned long long* slots, hipStream_t s);
@@ -560,21 +562,45 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   if (words <= cap) {
     chunks.push_back({0, ngroups, tp, tm});
   } else {
-    std::vector<uint32_t> cp(ngroups), cm(ngroups);
-    HOT_CHECK(hipMemcpyAsync(cp.data(), G.cnt_p2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
-              "readback");
-    HOT_CHECK(hipMemcpyAsync(cm.data(), G.cnt_m2p, 4 * (size_t)ngroups, hipMemcpyDeviceToHost, s),
-              "readback");
+    // greedy over groups in order (a new chunk when the next group would
+    // overflow), taken a block of kCountBlock groups at a time where the whole
+    // block fits: only the blocks where a chunk ends are read group by group.
+    // The block sums go to the second key buffer (free after the groups).
+    const uint32_t nb = (ngroups + kCountBlock - 1) / kCountBlock;
+    unsigned long long* bp = reinterpret_cast<unsigned long long*>(key1);
+    unsigned long long* bm = bp + nb;
+    HOT_CHECK(block_counts(G, ngroups, bp, bm, s), "list totals");
+    std::vector<unsigned long long> hp(nb), hm(nb);
+    HOT_CHECK(hipMemcpyAsync(hp.data(), bp, 8 * (size_t)nb, hipMemcpyDeviceToHost, s), "readback");
+    HOT_CHECK(hipMemcpyAsync(hm.data(), bm, 8 * (size_t)nb, hipMemcpyDeviceToHost, s), "readback");
     HOT_CHECK(hipStreamSynchronize(s), "readback");
+    std::vector<uint32_t> cp(kCountBlock), cm(kCountBlock);
     Chunk ch{0, 0, 0, 0};
-    for (uint32_t g = 0; g < ngroups; ++g) {
-      if (ch.g1 > ch.g0 && ch.tp + cp[g] + 4 * (ch.tm + cm[g]) + 4 > cap) {
-        chunks.push_back(ch);
-        ch = Chunk{g, g, 0, 0};
+    for (uint32_t b = 0; b < nb; ++b) {
+      const uint32_t g0 = b * kCountBlock, g1 = std::min(ngroups, g0 + kCountBlock);
+      if (ch.tp + hp[b] + 4 * (ch.tm + hm[b]) + 4 <= cap) {
+        ch.g1 = g1;
+        ch.tp += hp[b];
+        ch.tm += hm[b];
+        continue;
       }
-      ch.g1 = g + 1;
-      ch.tp += cp[g];
-      ch.tm += cm[g];
+      HOT_CHECK(hipMemcpyAsync(cp.data(), G.cnt_p2p + g0, 4 * (size_t)(g1 - g0),
+                               hipMemcpyDeviceToHost, s),
+                "readback");
+      HOT_CHECK(hipMemcpyAsync(cm.data(), G.cnt_m2p + g0, 4 * (size_t)(g1 - g0),
+                               hipMemcpyDeviceToHost, s),
+                "readback");
+      HOT_CHECK(hipStreamSynchronize(s), "readback");
+      for (uint32_t g = g0; g < g1; ++g) {
+        const size_t gp = cp[g - g0], gm = cm[g - g0];
+        if (ch.g1 > ch.g0 && ch.tp + gp + 4 * (ch.tm + gm) + 4 > cap) {
+          chunks.push_back(ch);
+          ch = Chunk{g, g, 0, 0};
+        }
+        ch.g1 = g + 1;
+        ch.tp += gp;
+        ch.tm += gm;
+      }
     }
     chunks.push_back(ch);
   }

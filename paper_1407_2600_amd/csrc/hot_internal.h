@@ -211,6 +211,8 @@ struct LocalPrm {
 // (the group arrays taken from the batch's first group on; the box arrays
 // keep their stride).
 constexpr uint32_t kGroupBatch = 1u << 22;
+// groups per block of the list-chunk planning sums (a multiple of 256)
+constexpr uint32_t kCountBlock = 1024;
 
 inline Groups groups_from(const Groups& G, uint32_t g0) {
   Groups B = G;

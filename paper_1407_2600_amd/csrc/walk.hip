@@ -254,6 +254,43 @@ hipError_t sum_counts(const Groups& G, uint32_t ngroups, unsigned long long* sum
   return hipGetLastError();
 }
 
+// per block of kCountBlock consecutive groups: the sums of their direct
+// entries and accepted cells (64-bit), for planning list chunks
+__global__ void __launch_bounds__(256) k_block_counts(Groups G, uint32_t ngroups,
+                                                      unsigned long long* __restrict__ bp,
+                                                      unsigned long long* __restrict__ bm) {
+  __shared__ unsigned long long sp[4], sm[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned long long p = 0, m = 0;
+  for (uint32_t i = 0; i < kCountBlock; i += 256) {
+    const uint32_t g = blockIdx.x * kCountBlock + i + threadIdx.x;
+    if (g < ngroups) {
+      p += G.cnt_p2p[g];
+      m += G.cnt_m2p[g];
+    }
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    p += __shfl_down(p, d, 64);
+    m += __shfl_down(m, d, 64);
+  }
+  if (lane == 0) {
+    sp[wid] = p;
+    sm[wid] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bp[blockIdx.x] = sp[0] + sp[1] + sp[2] + sp[3];
+    bm[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+  }
+}
+
+hipError_t block_counts(const Groups& G, uint32_t ngroups, unsigned long long* bp,
+                        unsigned long long* bm, hipStream_t s) {
+  if (ngroups == 0) return hipSuccess;
+  k_block_counts<<<(ngroups + kCountBlock - 1) / kCountBlock, 256, 0, s>>>(G, ngroups, bp, bm);
+  return hipGetLastError();
+}
+
 hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
                        uint32_t gcap, double L, int periodic, const LocalPrm& lp,
                        uint32_t* p2p_list, uint4* m2p_list, uint32_t* status, hipStream_t s) {
