@@ -686,6 +686,10 @@ def main():
                                         for p in ("fp32", "fp64")}
             print(f"[bench] trajectory adjoint {ex['trajectory_adjoint']}", file=sys.stderr,
                   flush=True)
+            # the differentiation workload's backward/forward beside the
+            # single-evaluation ratio (it is above 3 in FP64)
+            out["trajectory_backward_over_forward"] = {
+                p: ex["trajectory_adjoint"][p]["backward_over_forward"] for p in ("fp32", "fp64")}
         out["at_128cubed"] = ex
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))
