@@ -225,12 +225,25 @@ __global__ void __launch_bounds__(256) k_count_pairs(Cells C, Groups G, uint32_t
                                                      unsigned long long* __restrict__ slots) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long pp = 0, mp = 0, ms = 0, ts = 0, tp = 0, le = 0, lp = 0, lt = 0;
+  // the listed leaves' particles of each of the wavefront's 64 groups, one
+  // group at a time across the lanes (coalesced list reads); lane j keeps
+  // group j's sum
+  const int lane = threadIdx.x & 63;
+  unsigned long long listed = 0;
+  for (int j = 0; j < 64; ++j) {
+    const uint32_t gj = g - (uint32_t)lane + (uint32_t)j;  // wave-uniform
+    if (gj >= ngroups) break;
+    if (G.active && !G.active[gj]) continue;
+    const uint32_t off = G.off_p2p[gj], cnt = G.cnt_p2p[gj];
+    unsigned long long v = 0;
+    for (uint32_t q = (uint32_t)lane; q < cnt; q += 64) v += C.count[list[off + q] & kCellMask];
+    for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+    if (lane == j) listed = v;
+  }
   if (g < ngroups && !(G.active && !G.active[g])) {
     const int A = G.cell[g];
     const unsigned long long na = C.count[A];
-    unsigned long long src = na - 1;
-    const uint32_t off = G.off_p2p[g], cnt = G.cnt_p2p[g];
-    for (uint32_t q = 0; q < cnt; ++q) src += C.count[list[off + q] & kCellMask];
+    const unsigned long long src = na - 1 + listed;
     pp = na * src;
     const unsigned long long cm = G.cnt_m2p[g];
     mp = na * cm;
