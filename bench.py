@@ -89,8 +89,9 @@ LOCAL_FRACS = {"zeldovich128": (0.0, 0.002, 0.003, 0.004, 0.005, 0.006),
                "nfw256": (0.0, 0.01, 0.03, 0.1, 0.2),
                "zeldovich1024": (0.004, 0.005, 0.0065, 0.008)}
 # list region beside the minimum workspace at 1024^3 (the lists are processed
-# in chunks of groups that fit it)
-PAPER_SCALE_LIST_BYTES = 16 << 30
+# in chunks of groups that fit it; 236 GB of workspace with the caller's 47 GB
+# of arrays leave ~20 GB of the GPU's 288 GiB free)
+PAPER_SCALE_LIST_BYTES = 32 << 30
 # targets at 1024^3: 2000 distinct particles drawn with this seed, the first
 # 1000 for --search (selection), the last 1000 for the reported error
 C5_TARGET_SEED = 5

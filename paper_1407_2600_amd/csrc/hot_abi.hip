@@ -556,10 +556,14 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     g_err = "interaction-list capacity below one group's lists; call hot_workspace_size again";
     return HOT_EOVERFLOW;
   }
-  // chunks of consecutive groups whose lists fit the list region together
-  // a chunk's list offsets are 32-bit words (direct) and records (multipole)
-  const size_t cap = std::min(P.cap_list, (size_t)UINT32_MAX - 64);
-  if (words <= cap) {
+  // chunks of consecutive groups whose lists fit the list region together;
+  // a chunk's offsets are 32-bit: words for its direct entries, 16-byte
+  // records for its accepted cells
+  const size_t cap = P.cap_list, off_max = (size_t)UINT32_MAX - 64;
+  auto fits = [&](size_t wp, size_t wm) {
+    return wp + 4 * wm + 4 <= cap && wp <= off_max && wm <= off_max;
+  };
+  if (fits(tp, tm)) {
     chunks.push_back({0, ngroups, tp, tm});
   } else {
     // greedy over groups in order (a new chunk when the next group would
@@ -578,7 +582,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
     Chunk ch{0, 0, 0, 0};
     for (uint32_t b = 0; b < nb; ++b) {
       const uint32_t g0 = b * kCountBlock, g1 = std::min(ngroups, g0 + kCountBlock);
-      if (ch.tp + hp[b] + 4 * (ch.tm + hm[b]) + 4 <= cap) {
+      if (fits(ch.tp + hp[b], ch.tm + hm[b])) {
         ch.g1 = g1;
         ch.tp += hp[b];
         ch.tm += hm[b];
@@ -593,7 +597,7 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
       HOT_CHECK(hipStreamSynchronize(s), "readback");
       for (uint32_t g = g0; g < g1; ++g) {
         const size_t gp = cp[g - g0], gm = cm[g - g0];
-        if (ch.g1 > ch.g0 && ch.tp + gp + 4 * (ch.tm + gm) + 4 > cap) {
+        if (ch.g1 > ch.g0 && !fits(ch.tp + gp, ch.tm + gm)) {
           chunks.push_back(ch);
           ch = Chunk{g, g, 0, 0};
         }
@@ -1244,7 +1248,7 @@ static void settle_entries(hot_ctx* m) {
 // direct and local lists from their bases, 16-byte records for the multipole
 // list) and the packed CSR offsets of the same entries; the multipole records
 // and local entries of a group share its accepted-cell region
-static hipError_t list_layout(hot_ctx* c, void* ws, int kind, std::vector<uint32_t>& raw,
+static hipError_t list_layout(hot_ctx* c, void* ws, int kind, std::vector<size_t>& raw,
                               std::vector<int64_t>& packed) {
   const Plan& P = c->last_plan;
   const size_t ng = c->last_ngroups;
@@ -1254,10 +1258,15 @@ static hipError_t list_layout(hot_ctx* c, void* ws, int kind, std::vector<uint32
   if (ng == 0) return hipSuccess;
   const size_t o_cnt = kind == 2 ? P.o_g_cl : kind ? P.o_g_cm : P.o_g_cp;
   const size_t o_off = kind == 2 ? P.o_g_ol : kind ? P.o_g_om : P.o_g_op;
+  std::vector<uint32_t> off(ng);
   hipError_t e = hipMemcpy(cnt.data(), at<char>(ws, o_cnt), 4 * ng, hipMemcpyDeviceToHost);
   if (e == hipSuccess)
-    e = hipMemcpy(raw.data(), at<char>(ws, o_off), 4 * ng, hipMemcpyDeviceToHost);
-  for (size_t g = 0; g < ng; ++g) packed[g + 1] = packed[g] + cnt[g];
+    e = hipMemcpy(off.data(), at<char>(ws, o_off), 4 * ng, hipMemcpyDeviceToHost);
+  for (size_t g = 0; g < ng; ++g) {
+    packed[g + 1] = packed[g] + cnt[g];
+    // local entries: the words before the end of the group's region
+    raw[g] = kind == 2 ? (cnt[g] ? 4 * (size_t)off[g] - cnt[g] : 0) : off[g];
+  }
   return e;
 }
 
@@ -1387,7 +1396,7 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
   settle_entries(c);
   const size_t tp = c->stats.p2p_entries;
   const bool local = local_on(c->p);
-  std::vector<uint32_t> raw;
+  std::vector<size_t> raw;
   std::vector<int64_t> packed;
   for (int kind = 0; kind < 3; ++kind) {
     int64_t* ooff = kind == 2 ? o->m2l_offset : kind ? o->m2p_offset : o->p2p_offset;
@@ -1413,7 +1422,7 @@ hot_status hot_debug_export(hot_ctx* c, void* ws, hot_debug* o) {
     for (size_t g = 0; g < ng; ++g)
       for (int64_t i = 0; i < packed[g + 1] - packed[g]; ++i)
         oent[packed[g] + i] =
-            kind == 2 ? rec[(size_t)raw[g] + (size_t)i] : rec[4 * ((size_t)raw[g] + (size_t)i) + 3];
+            kind == 2 ? rec[raw[g] + (size_t)i] : rec[4 * (raw[g] + (size_t)i) + 3];
   }
   return HOT_OK;
 }
@@ -1470,7 +1479,7 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
   }
   // a multipole entry is the last word of its 16-byte record, a local entry a
   // word of its own; copy group by group from the packed index range
-  std::vector<uint32_t> raw;
+  std::vector<size_t> raw;
   std::vector<int64_t> packed;
   HOT_CHECK(list_layout(c, ws, kind, raw, packed), "export");
   const size_t tp = (size_t)c->stats.p2p_entries;
@@ -1481,7 +1490,7 @@ hot_status hot_debug_list_range(hot_ctx* c, void* ws, int kind, int64_t first, i
     const int64_t take = std::min(packed[g + 1], first + count) - i;
     if (take <= 0) continue;
     HOT_CHECK(hipMemcpy2D(out + (i - first), 4,
-                          reg + stride * ((size_t)raw[g] + (size_t)(i - packed[g])) + last,
+                          reg + stride * (raw[g] + (size_t)(i - packed[g])) + last,
                           4 * stride, 4, (size_t)take, hipMemcpyDeviceToHost),
               "export");
     i += take;

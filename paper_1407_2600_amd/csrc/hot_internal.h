@@ -191,7 +191,8 @@ struct Groups {
   uint32_t* off_p2p;
   uint32_t* off_m2p;
   uint32_t* cnt_m2l;  // cells taken through the group's local expansion
-  uint32_t* off_m2l;
+  uint32_t* off_m2l;  // end of the group's accepted-cell region (16-byte records):
+                      // its local entries are the cnt_m2l words before it
 };
 
 // Group-level local expansions (Newtonian kernel): an accepted cell goes to

@@ -231,7 +231,8 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
   if (G.active && !G.active[g]) return;
   const uint32_t cnt = G.cnt_m2l[g];
   if (cnt == 0) return;
-  const uint32_t off = G.off_m2l[g];
+  // the group's local entries end where its accepted-cell region ends
+  const uint32_t* __restrict__ ent = list + ((size_t)4 * G.off_m2l[g] - cnt);
   const double lo0 = G.lo[g], lo1 = G.lo[gcap + g], lo2 = G.lo[2 * (size_t)gcap + g];
   const double hi0 = G.hi[g], hi1 = G.hi[gcap + g], hi2 = G.hi[2 * (size_t)gcap + g];
   const double gc0 = 0.5 * (lo0 + hi0), gc1 = 0.5 * (lo1 + hi1), gc2 = 0.5 * (lo2 + hi2);
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(64 * kLocalWaves) k_m2l(Cells C, Groups G, uin
   for (uint32_t q = lane; q < cnt; q += 64) {
     // c - z from the cell's image-shifted centre of mass, in FP64 and then
     // rounded to the arithmetic type
-    const uint32_t e = list[off + q];
+    const uint32_t e = ent[q];
     const int B = (int)(e & kCellMask), img = (int)(e >> 27);
     const double4 w = C.walk[B];
     const T Rx = (T)(gc0 - (w.x + (double)(img / 9 - 1) * L));

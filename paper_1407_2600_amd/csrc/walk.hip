@@ -13,7 +13,7 @@
 //     counts both together; the emit pass decides, writing the 16-byte
 //     multipole records from the front of the group's region and the local
 //     entries, one 32-bit word each, from its back, and then the two counts
-//     and the local entries' word offset);
+//     and the end of the region);
 //   - a leaf: direct list;
 //   - otherwise: open (push the daughters).
 // Ballots and a wave prefix sum place the emitted entries and the pushed
@@ -181,7 +181,8 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
       // local entries: the bare (image << 27 | cell) word, packed downwards
       // from the end of the group's accepted region
       if (action == 4)
-        reinterpret_cast<uint32_t*>(m2p_list)[4 * oe - 1 - nl - (uint32_t)__popcll(bl & below)] = e;
+        reinterpret_cast<uint32_t*>(m2p_list)[(size_t)4 * oe - 1 - nl -
+                                              (uint32_t)__popcll(bl & below)] = e;
       if (action == 2)
         m2p_list[om + nm + (uint32_t)__popcll(bm & below)] =
             make_uint4(__float_as_uint((float)(cc0 - cA[0])), __float_as_uint((float)(cc1 - cA[1])),
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(64 * kWalkWaves) k_walk(Cells C, Groups G, uin
     } else {
       G.cnt_m2p[g] = nm;
       G.cnt_m2l[g] = nl;
-      G.off_m2l[g] = 4 * oe - nl;  // 32-bit word index of the local entries
+      G.off_m2l[g] = oe;  // the local entries: words [4 oe - nl, 4 oe)
     }
   }
 }

@@ -26,7 +26,7 @@ N_SIDE = 1024
 # the benchmark's launch configuration at this size
 LAUNCH = dict(box=1.0, G=1.0, eps=0.02 / N_SIDE, order=4, periodic=1, far_order=8,
               **operating_point("zeldovich1024"))
-LIST_BYTES = 16 << 30
+LIST_BYTES = 32 << 30
 # bound on the largest per-target acceleration error over the rms reference
 # acceleration, FP32 mode against the FP64 oracle
 MAX_FP32 = 2e-4
