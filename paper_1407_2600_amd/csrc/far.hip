@@ -162,6 +162,10 @@ __global__ void __launch_bounds__(64) k_far_lambda(const double* __restrict__ tp
   if (lane == 0) lam[(size_t)t * NQ + q] = acc;
 }
 
+// One particle per thread.  The block's particles (consecutive in key order)
+// almost always lie in one octant: its local coefficients are staged in LDS
+// once per block and read from there (broadcast reads), the few particles of
+// another octant read theirs from global memory.
 template <int PF, typename T>
 __global__ void __launch_bounds__(256) k_far_apply(const double* __restrict__ spos,
                                                    const uint64_t* __restrict__ skey,
@@ -171,24 +175,28 @@ __global__ void __launch_bounds__(256) k_far_apply(const double* __restrict__ sp
                                                    int periodic, const uint8_t* __restrict__ rung,
                                                    int rmin, T* __restrict__ acc,
                                                    T* __restrict__ pot) {
-  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int NQ = nt(PF);
+  __shared__ double cs[NQ];
+  const size_t b0 = (size_t)blockIdx.x * blockDim.x;
+  const size_t s = b0 + threadIdx.x;
+  const int ob = periodic ? (int)((skey[b0] >> 60) & 7ull) : 0;
+  if (periodic) {
+    for (int i = threadIdx.x; i < NQ; i += blockDim.x) cs[i] = lam[(size_t)ob * NQ + i];
+    __syncthreads();
+  }
   if (s >= n) return;
   // block timesteps: only the particles whose step ends now get new values
   if (rung && (int)rung[idx[s]] < rmin) return;
   double4 v = near[s];
   double phi = v.w, gx = v.x, gy = v.y, gz = v.z;
   if (periodic) {
-    constexpr int NQ = nt(PF);
     const int o = (int)((skey[s] >> 60) & 7ull);
     double c[3];
     octant_center(o, L, c);
     const double h[3] = {spos[s] - c[0], spos[n + s] - c[1], spos[2 * n + s] - c[2]};
     double r[4];
-    // where the whole wavefront lies in one octant (all but at most 7
-    // wavefronts) the coefficients are wave-uniform: scalar loads
-    const int o0 = __builtin_amdgcn_readfirstlane(o);
-    if (__all(o == o0))
-      local_horner<PF, double>(lam + (size_t)o0 * NQ, h[0], h[1], h[2], r);
+    if (o == ob)
+      local_horner<PF, double>(cs, h[0], h[1], h[2], r);
     else
       local_horner<PF, double>(lam + (size_t)o * NQ, h[0], h[1], h[2], r);
     const double P = r[3], Gx = r[0], Gy = r[1], Gz = r[2];
