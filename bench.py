@@ -171,14 +171,14 @@ def copy_calibration():
 # reports traffic as null.
 TRAFFIC_SOURCES = ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"]
 TRAFFIC = [
-    {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_eval": 1.511e9,
+    {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_eval": 1.513e9,
      "config": {"theta": 0.8, "err_tol": 4.88e-3, "order": 4, "leaf_max": 16, "group_max": 128,
                 "far_order": 8, "local_order": 4, "local_tol": 1.46e-4},
-     "sha256": "f380f5a565a4da73a77bb7d1c13b510900de160733beee973498ddb7be3e84c7"},
-    {"workload": "zeldovich1024", "kernel": "k_m2p<4,float>", "bytes_per_eval": 3.911e11,
+     "sha256": "9827a598a718ac63917c5044a0122966ad804bff23ed0338f40d1d7121081183"},
+    {"workload": "zeldovich1024", "kernel": "k_m2p<4,float>", "bytes_per_eval": 3.908e11,
      "config": {"theta": 0.8, "err_tol": 1.67e-3, "order": 4, "leaf_max": 64, "group_max": 128,
                 "far_order": 8, "local_order": 4, "local_tol": 1.49e-4},
-     "sha256": "f380f5a565a4da73a77bb7d1c13b510900de160733beee973498ddb7be3e84c7"},
+     "sha256": "9827a598a718ac63917c5044a0122966ad804bff23ed0338f40d1d7121081183"},
 ]
 
 

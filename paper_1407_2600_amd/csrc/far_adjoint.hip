@@ -167,13 +167,26 @@ __global__ void __launch_bounds__(256) k_far_adj_apply(
     const double4* __restrict__ near, size_t n, const uint32_t* __restrict__ idx, double L,
     double G, const double* __restrict__ lam, const double* __restrict__ mbar, int periodic,
     double* __restrict__ xbar, T* __restrict__ mbar_out) {
-  const size_t s = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the block's octant's coefficients in LDS (the block's particles are
+  // consecutive in key order, almost always in one octant); particles of
+  // another octant read theirs from global memory
+  constexpr int NQ = nt(PF);
+  __shared__ double cl[NQ], cm[NQ];
+  const size_t b0 = (size_t)blockIdx.x * blockDim.x;
+  const size_t s = b0 + threadIdx.x;
+  const int ob = periodic ? (int)((skey[b0] >> 60) & 7ull) : 0;
+  if (periodic) {
+    for (int i = threadIdx.x; i < NQ; i += blockDim.x) {
+      cl[i] = lam[(size_t)ob * NQ + i];
+      cm[i] = mbar[(size_t)ob * NQ + i];
+    }
+    __syncthreads();
+  }
   if (s >= n) return;
   const double4 v = near[s];
   double xb[3] = {G * v.x, G * v.y, G * v.z};
   double mb = G * v.w;
   if (periodic) {
-    constexpr int NQ = nt(PF);
     const int o = (int)((skey[s] >> 60) & 7ull);
     double c[3];
     octant_center(o, L, c);
@@ -181,17 +194,13 @@ __global__ void __launch_bounds__(256) k_far_adj_apply(
     const T4 r = arec[s];
     const double ga[3] = {(double)r.x, (double)r.y, (double)r.z};
     const double gp = (double)r.w;
-    // target side: gradient and its derivative along gacc; source side.
-    // Where the whole wavefront lies in one octant (all but at most 7
-    // wavefronts), the coefficient pointers are wave-uniform and the
-    // coefficients come through the scalar cache.
+    // target side: gradient and its derivative along gacc; source side
     Dual<double> f[4];
     double sm[4];
-    const int o0 = __builtin_amdgcn_readfirstlane(o);
-    if (__all(o == o0)) {
-      local_horner<PF, Dual<double>>(lam + (size_t)o0 * NQ, Dual<double>(h[0], ga[0]),
-                                   Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
-      local_horner<PF, double>(mbar + (size_t)o0 * NQ, h[0], h[1], h[2], sm);
+    if (o == ob) {
+      local_horner<PF, Dual<double>>(cl, Dual<double>(h[0], ga[0]), Dual<double>(h[1], ga[1]),
+                                   Dual<double>(h[2], ga[2]), f);
+      local_horner<PF, double>(cm, h[0], h[1], h[2], sm);
     } else {
       local_horner<PF, Dual<double>>(lam + (size_t)o * NQ, Dual<double>(h[0], ga[0]),
                                    Dual<double>(h[1], ga[1]), Dual<double>(h[2], ga[2]), f);
