@@ -302,6 +302,43 @@ hot_status hot_kdk(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* m
                    void* pot, double dt, int nsteps, unsigned flags, void* workspace,
                    size_t ws_bytes, void* stream);
 
+/* The kick-drift-kick steps of hot_kdk in comoving coordinates of an
+ * expanding background (paper Sec. 2.1: the symplectic integrator; Sec. 3:
+ * comoving cosmological volumes in a flat background with omega_m 0.295 and
+ * omega_lambda 0.705).  pos are comoving
+ * positions in the periodic box, vel the canonical momenta per unit mass
+ * p = a^2 dx/dt, and the force evaluation is the peculiar one the tree
+ * computes from comoving positions and masses (its periodic sum subtracts
+ * the mean density).  The equations of motion dx/dt = p / a^2 and
+ * dp/dt = acc / a give, over a step from a_k to a_k+1 = a_k + da in the
+ * scale factor, with a_h = a_k + da/2:
+ *   p += acc K(a_k, a_h); x = wrap(x + p D(a_k, a_k+1)); acc = forces(x);
+ *   p += acc K(a_h, a_k+1),
+ * K(a1, a2) = int da / (a^2 H(a)) and D(a1, a2) = int da / (a^3 H(a))
+ * (hot_comoving_factors), H(a) = h0 sqrt(omega_m a^-3 + omega_k a^-2 +
+ * omega_l), omega_k = 1 - omega_m - omega_l.  Time is in units of the
+ * context's G: h0 is the Hubble constant in those units (with G = 1 and the
+ * mean comoving density rho, 4 pi rho / 3 = omega_m h0^2 / 2 holds for a
+ * consistent background; the library does not impose it).
+ *   a0 > 0   the scale factor at the start; da the step in it (any sign;
+ *            every a_k must stay > 0 and H^2 > 0 on the path)
+ *   omega_m, omega_l, h0 > 0  the background
+ * Other arguments, flags, errors and the failure behaviour as hot_kdk
+ * (kdk_steps_done counts the completed steps). */
+hot_status hot_kdk_comoving(hot_ctx* ctx, size_t n, double* pos, void* vel, const void* mass,
+                            void* acc, void* pot, double a0, double da, int nsteps,
+                            double omega_m, double omega_l, double h0, unsigned flags,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/* The kick and drift factors of hot_kdk_comoving over [a1, a2] (a1, a2 > 0):
+ * out[0] = K = int_a1^a2 da / (a^2 H(a)), out[1] = D = int_a1^a2 da /
+ * (a^3 H(a)), by Gauss-Legendre quadrature in ln a (16 nodes per panel,
+ * panels at most 0.05 wide in ln a).  Host-only; touches no GPU.  HOT_EINVAL
+ * on non-positive or non-finite a1, a2, h0, a non-finite omega, or
+ * H^2 <= 0 somewhere in [a1, a2]. */
+hot_status hot_comoving_factors(double a1, double a2, double omega_m, double omega_l, double h0,
+                                double* out);
+
 /* Block (multiple) timesteps: nsteps steps of length dt of the paper's
  * adaptive symplectic integrator (Sec. 2.1), read as hierarchical
  * kick-drift-kick on power-of-two rungs.  Particle i advances in steps of

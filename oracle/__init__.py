@@ -476,6 +476,53 @@ def kdk(pos, vel, mass, params: dict, dt: float, nsteps: int, acc=None):
     return pos, vel, acc, pot
 
 
+def hubble(a, omega_m: float, omega_l: float, h0: float):
+    """H(a) = h0 sqrt(omega_m a^-3 + omega_k a^-2 + omega_l), omega_k =
+    1 - omega_m - omega_l: the expansion rate of the background of the
+    paper's comoving volumes (Sec. 3: omega_m 0.295, omega_lambda 0.705)."""
+    return h0 * np.sqrt(omega_m / a ** 3 + (1.0 - omega_m - omega_l) / a ** 2 + omega_l)
+
+
+def comoving_factors(a1: float, a2: float, omega_m: float, omega_l: float, h0: float):
+    """(K, D) over [a1, a2]: K = int da / (a^2 H(a)) = int dt / a (the kick of
+    the canonical momentum p = a^2 dx/dt under dp/dt = -grad(phi) / a) and
+    D = int da / (a^3 H(a)) = int dt / a^2 (the drift, dx/dt = p / a^2),
+    by adaptive quadrature in a."""
+    from scipy.integrate import quad
+    k = quad(lambda a: 1.0 / (a * a * hubble(a, omega_m, omega_l, h0)), a1, a2,
+             epsabs=0.0, epsrel=2e-14, limit=200)[0]
+    d = quad(lambda a: 1.0 / (a ** 3 * hubble(a, omega_m, omega_l, h0)), a1, a2,
+             epsabs=0.0, epsrel=2e-14, limit=200)[0]
+    return k, d
+
+
+def kdk_comoving(pos, vel, mass, params: dict, a0: float, da: float, nsteps: int,
+                 omega_m: float, omega_l: float, h0: float, acc=None):
+    """Kick-drift-kick leapfrog in comoving coordinates (paper Sec. 2.1's
+    symplectic integrator for the comoving volumes of Sec. 3): pos comoving,
+    vel the canonical momenta p = a^2 dx/dt, steps of da in the scale factor;
+    per step, with a_h the middle of [a_k, a_k+1],
+    p += acc K(a_k, a_h); x = wrap(x + p D(a_k, a_k+1)); acc = forces(x);
+    p += acc K(a_h, a_k+1).  Returns (pos, vel, acc, pot)."""
+    box = float(params.get("box", 1.0))
+    periodic = int(params.get("periodic", 1))
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    pot = None
+    if acc is None:
+        acc, pot = Tree(pos, mass, params).forces()
+    for k in range(nsteps):
+        ak, a1 = a0 + k * da, a0 + (k + 1) * da
+        ah = ak + 0.5 * da
+        vel = vel + comoving_factors(ak, ah, omega_m, omega_l, h0)[0] * acc
+        pos = pos + comoving_factors(ak, a1, omega_m, omega_l, h0)[1] * vel
+        if periodic:
+            pos = wrap_box(pos, box)
+        acc, pot = Tree(pos, mass, params).forces()
+        vel = vel + comoving_factors(ah, a1, omega_m, omega_l, h0)[0] * acc
+    return pos, vel, acc, pot
+
+
 def rung_of(acc, dt: float, max_rung: int, eta: float, eps: float):
     """Block-timestep rung of each particle from its acceleration: the
     largest step dt/2^r, r <= max_rung, not above eta sqrt(eps/|a|) (the

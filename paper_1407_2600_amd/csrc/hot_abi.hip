@@ -805,6 +805,71 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
 
 using namespace hot;
 
+// ---- comoving kick and drift factors: K = int da / (a^2 H), D = int da /
+// (a^3 H) over [a1, a2], integrated in u = ln a (da = a du, a smooth
+// integrand), composite Gauss-Legendre with 16 nodes per panel and panels at
+// most 0.05 wide in u
+namespace {
+struct GaussLegendre16 {
+  double x[16], w[16];
+  GaussLegendre16() {
+    // roots of P_16 by Newton's method from the usual cosine guesses
+    const int m = 16;
+    for (int i = 0; i < m; ++i) {
+      double z = std::cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 0.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = 0.0;
+        for (int j = 1; j <= m; ++j) {
+          const double p2 = p1;
+          p1 = p0;
+          p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+        }
+        dp = m * (z * p0 - p1) / (z * z - 1.0);
+        const double z1 = z;
+        z = z1 - p0 / dp;
+        if (std::fabs(z - z1) < 1e-16) break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+};
+const GaussLegendre16& gauss16() {
+  static const GaussLegendre16 g;
+  return g;
+}
+// H(a)^2 / h0^2
+double hubble2(double a, double om, double ol) {
+  return om / (a * a * a) + (1.0 - om - ol) / (a * a) + ol;
+}
+}  // namespace
+
+static bool comoving_factors(double a1, double a2, double om, double ol, double h0, double* K,
+                             double* D) {
+  if (!(a1 > 0.0) || !(a2 > 0.0) || !std::isfinite(a1) || !std::isfinite(a2) ||
+      !(h0 > 0.0) || !std::isfinite(h0) || !std::isfinite(om) || !std::isfinite(ol))
+    return false;
+  const double u1 = std::log(a1), u2 = std::log(a2);
+  const int panels = std::max(1, (int)std::ceil(std::fabs(u2 - u1) / 0.05));
+  const double hw = 0.5 * (u2 - u1) / panels;
+  const GaussLegendre16& g = gauss16();
+  double k = 0.0, d = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double mid = u1 + (2 * p + 1) * hw;
+    for (int i = 0; i < 16; ++i) {
+      const double a = std::exp(mid + hw * g.x[i]);
+      const double h2 = hubble2(a, om, ol);
+      if (!(h2 > 0.0)) return false;
+      const double e = g.w[i] / std::sqrt(h2);  // da / H = a du / H
+      k += e / a;                               // a du / (a^2 H)
+      d += e / (a * a);                         // a du / (a^3 H)
+    }
+  }
+  *K = k * hw / h0;
+  *D = d * hw / h0;
+  return true;
+}
+
 extern "C" {
 
 const char* hot_version(void) { return "libhot 0.1 (gfx950)"; }
@@ -1028,6 +1093,81 @@ hot_status hot_kdk(hot_ctx* c, size_t n, double* pos, void* vel, const void* mas
       return st;
     }
     HOT_CHECK(kick_launch(fp32, vel, acc, n, 0.5 * dt, s), "kick");
+    c->stats.kdk_steps_done = k + 1;
+  }
+  return HOT_OK;
+}
+
+hot_status hot_comoving_factors(double a1, double a2, double omega_m, double omega_l, double h0,
+                                double* out) {
+  if (!out || !comoving_factors(a1, a2, omega_m, omega_l, h0, &out[0], &out[1])) {
+    g_err = "bad argument (a1, a2, h0 > 0 and finite, H^2 > 0 on [a1, a2], out not NULL)";
+    return HOT_EINVAL;
+  }
+  return HOT_OK;
+}
+
+hot_status hot_kdk_comoving(hot_ctx* c, size_t n, double* pos, void* vel, const void* mass,
+                            void* acc, void* pot, double a0, double da, int nsteps,
+                            double omega_m, double omega_l, double h0, unsigned flags, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (!c) {
+    g_err = "ctx is NULL";
+    return HOT_EINVAL;
+  }
+  if (n == 0) return HOT_OK;
+  if (!pos || !vel || !mass || !acc || !ws || nsteps < 0 || !std::isfinite(da)) {
+    g_err = "bad argument";
+    return HOT_EINVAL;
+  }
+  // every step's factors first, so that a bad background fails before any
+  // particle moves
+  std::vector<double> f(3 * (size_t)nsteps);
+  for (int k = 0; k < nsteps; ++k) {
+    const double ak = a0 + k * da, ah = ak + 0.5 * da, a1 = a0 + (k + 1) * da;
+    double d_unused;
+    if (!comoving_factors(ak, ah, omega_m, omega_l, h0, &f[3 * k], &d_unused) ||
+        !comoving_factors(ak, a1, omega_m, omega_l, h0, &d_unused, &f[3 * k + 1]) ||
+        !comoving_factors(ah, a1, omega_m, omega_l, h0, &f[3 * k + 2], &d_unused)) {
+      g_err = "bad background (a0 > 0, every a_k > 0, h0 > 0, H^2 > 0 on the path)";
+      return HOT_EINVAL;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool fp32 = c->p.precision == HOT_FP32;
+  const size_t tsz = fp32 ? 4 : 8;
+  c->stats.kdk_steps_done = 0;
+  const bool snap = !(flags & HOT_KDK_NO_SNAPSHOT);
+  const unsigned need = snap ? kNeedSnapshot : 0;
+  const Plan P = make_plan(c, n, ws_bytes, need);
+  if (ws_bytes < P.min_total) {
+    g_err = "workspace smaller than hot_workspace_size_min(HOT_CALL_KDK)";
+    return HOT_ENOMEM;
+  }
+  hot_status st;
+  if (!(flags & HOT_ACC_VALID)) {
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, need);
+    if (st != HOT_OK) return st;
+  }
+  double* sx = snap ? at<double>(ws, P.o_kv_sx) : nullptr;
+  void* sv = snap ? at<void>(ws, P.o_kv_sv) : nullptr;
+  for (int k = 0; k < nsteps; ++k) {
+    if (snap) {
+      HOT_CHECK(hipMemcpyAsync(sx, pos, 24 * n, hipMemcpyDeviceToDevice, s), "snapshot");
+      HOT_CHECK(hipMemcpyAsync(sv, vel, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
+    }
+    HOT_CHECK(kick_launch(fp32, vel, acc, n, f[3 * k], s), "kick");
+    HOT_CHECK(drift_launch(fp32, pos, vel, n, f[3 * k + 1], c->p.box, s), "drift");
+    st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, need);
+    if (st != HOT_OK) {
+      if (snap) {
+        HOT_CHECK(hipMemcpyAsync(pos, sx, 24 * n, hipMemcpyDeviceToDevice, s), "restore");
+        HOT_CHECK(hipMemcpyAsync(vel, sv, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "restore");
+        HOT_CHECK(hipStreamSynchronize(s), "restore");
+      }
+      return st;
+    }
+    HOT_CHECK(kick_launch(fp32, vel, acc, n, f[3 * k + 2], s), "kick");
     c->stats.kdk_steps_done = k + 1;
   }
   return HOT_OK;

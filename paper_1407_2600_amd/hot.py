@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "HOT_OK", 1: "HOT_EINVAL", 2: "HOT_ENOMEM", 3: "HOT_EOVERFLOW
 
 # symbols declared in include/hot.h
 EXPORTED = ["hot_create", "hot_destroy", "hot_workspace_size", "hot_workspace_size_min",
-            "hot_forces", "hot_forces_noalloc", "hot_kdk", "hot_kdk_block",
+            "hot_forces", "hot_forces_noalloc", "hot_kdk", "hot_kdk_comoving",
+            "hot_comoving_factors", "hot_kdk_block",
             "hot_vjp", "hot_vjp_after_forces", "hot_kdk_vjp", "hot_get_stats", "hot_debug_sizes", "hot_debug_export",
             "hot_debug_list_range", "hot_cell_lookup", "hot_last_error", "hot_version",
             "hot_far_table"]
@@ -118,6 +119,12 @@ def lib():
         L.hot_debug_list_range.argtypes = [vp, vp, C.c_int, C.c_int64, C.c_int64, vp]
         L.hot_last_error.restype = C.c_char_p
         L.hot_version.restype = C.c_char_p
+        L.hot_kdk_comoving.restype = C.c_int
+        L.hot_kdk_comoving.argtypes = [vp, sz, vp, vp, vp, vp, vp, C.c_double, C.c_double,
+                                       C.c_int, C.c_double, C.c_double, C.c_double, C.c_uint,
+                                       vp, sz, vp]
+        L.hot_comoving_factors.restype = C.c_int
+        L.hot_comoving_factors.argtypes = [C.c_double] * 5 + [C.POINTER(C.c_double)]
         L.hot_far_table.restype = C.c_int
         L.hot_far_table.argtypes = [C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double), sz]
         _lib = L
@@ -142,6 +149,15 @@ def make_params(box=1.0, G=1.0, eps=0.0, theta=0.5, order=4, periodic=1, leaf_ma
     return hot_params(float(box), float(G), float(eps), float(theta), int(order), int(periodic),
                       int(leaf_max), int(group_max), int(far_order), int(prec), float(err_tol),
                       KERNELS[kernel], int(local_order), float(local_tol))
+
+
+def comoving_factors(a1: float, a2: float, omega_m: float, omega_l: float, h0: float):
+    """(K, D): the kick and drift factors of hot_kdk_comoving over [a1, a2]
+    (host-only)."""
+    out = (C.c_double * 2)()
+    check(lib().hot_comoving_factors(float(a1), float(a2), float(omega_m), float(omega_l),
+                                     float(h0), out))
+    return out[0], out[1]
 
 
 def far_table(far_order: int, box: float = 1.0, offset: int = 13):
@@ -300,6 +316,43 @@ class Gravity:
             done = self.stats()["kdk_steps_done"]
             valid = valid or done > 0
             left -= done
+        check(st)
+
+    def kdk_comoving(self, pos, vel, mass, acc, a0: float, da: float, nsteps: int,
+                     omega_m: float, omega_l: float, h0: float, acc_valid: bool, pot=None,
+                     snapshot: bool = True):
+        """In-place leapfrog steps in comoving coordinates (pos comoving, vel
+        the canonical momenta p = a^2 dx/dt), nsteps steps of da in the scale
+        factor from a0 (hot_kdk_comoving).  Resumes after HOT_EOVERFLOW like
+        kdk()."""
+        pos_c, mass = self._check_inputs(pos, mass)
+        if not (pos_c.data_ptr() == pos.data_ptr()):
+            raise ValueError("pos must be contiguous (it is updated in place)")
+        for name, a in (("vel", vel), ("acc", acc)):
+            if a.dtype != self.dtype or a.shape != pos.shape or not a.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous (3, N) {self.dtype} tensor")
+        n = pos.shape[1]
+        s = self._stream()
+        self.evals += 1
+        left, valid, a = int(nsteps), bool(acc_valid), float(a0)
+        for _ in range(6):
+            ws = self._workspace(n, HOT_CALL_KDK if snapshot else HOT_CALL_FORCES)
+            st = self.L.hot_kdk_comoving(self.h, n, C.c_void_p(pos.data_ptr()),
+                                         C.c_void_p(vel.data_ptr()), C.c_void_p(mass.data_ptr()),
+                                         C.c_void_p(acc.data_ptr()),
+                                         C.c_void_p(pot.data_ptr() if pot is not None else 0),
+                                         a, float(da), left, float(omega_m), float(omega_l),
+                                         float(h0),
+                                         (HOT_ACC_VALID if valid else 0) |
+                                         (0 if snapshot else HOT_KDK_NO_SNAPSHOT),
+                                         C.c_void_p(ws.data_ptr()), ws.numel(), s)
+            if st != HOT_EOVERFLOW or not snapshot:
+                check(st)
+                return
+            done = self.stats()["kdk_steps_done"]
+            valid = valid or done > 0
+            left -= done
+            a += done * float(da)
         check(st)
 
     def kdk_block(self, pos, vel, mass, acc, rung, dt: float, max_rung: int, eta: float,
