@@ -1120,19 +1120,23 @@ hot_status hot_kdk_comoving(hot_ctx* c, size_t n, double* pos, void* vel, const 
     g_err = "bad argument";
     return HOT_EINVAL;
   }
-  // every step's factors first, so that a bad background fails before any
-  // particle moves
-  std::vector<double> f(3 * (size_t)nsteps);
-  for (int k = 0; k < nsteps; ++k) {
-    const double ak = a0 + k * da, ah = ak + 0.5 * da, a1 = a0 + (k + 1) * da;
-    double d_unused;
-    if (!comoving_factors(ak, ah, omega_m, omega_l, h0, &f[3 * k], &d_unused) ||
-        !comoving_factors(ak, a1, omega_m, omega_l, h0, &d_unused, &f[3 * k + 1]) ||
-        !comoving_factors(ah, a1, omega_m, omega_l, h0, &f[3 * k + 2], &d_unused)) {
+  // the whole path first (a_k is monotone in k, so its ends bound it), so
+  // that a bad background fails before any particle moves
+  {
+    double k_unused, d_unused;
+    if (!comoving_factors(a0, a0 + nsteps * da, omega_m, omega_l, h0, &k_unused, &d_unused)) {
       g_err = "bad background (a0 > 0, every a_k > 0, h0 > 0, H^2 > 0 on the path)";
       return HOT_EINVAL;
     }
   }
+  // one step's factors: opening kick, drift, closing kick
+  auto factors = [&](int k, double* f) {
+    const double ak = a0 + k * da, ah = ak + 0.5 * da, a1 = a0 + (k + 1) * da;
+    double u;
+    return comoving_factors(ak, ah, omega_m, omega_l, h0, &f[0], &u) &&
+           comoving_factors(ak, a1, omega_m, omega_l, h0, &u, &f[1]) &&
+           comoving_factors(ah, a1, omega_m, omega_l, h0, &f[2], &u);
+  };
   hipStream_t s = (hipStream_t)stream;
   const bool fp32 = c->p.precision == HOT_FP32;
   const size_t tsz = fp32 ? 4 : 8;
@@ -1152,12 +1156,17 @@ hot_status hot_kdk_comoving(hot_ctx* c, size_t n, double* pos, void* vel, const 
   double* sx = snap ? at<double>(ws, P.o_kv_sx) : nullptr;
   void* sv = snap ? at<void>(ws, P.o_kv_sv) : nullptr;
   for (int k = 0; k < nsteps; ++k) {
+    double f[3];
+    if (!factors(k, f)) {
+      g_err = "bad background on a step (H^2 <= 0 at a quadrature node)";
+      return HOT_EINVAL;
+    }
     if (snap) {
       HOT_CHECK(hipMemcpyAsync(sx, pos, 24 * n, hipMemcpyDeviceToDevice, s), "snapshot");
       HOT_CHECK(hipMemcpyAsync(sv, vel, 3 * tsz * n, hipMemcpyDeviceToDevice, s), "snapshot");
     }
-    HOT_CHECK(kick_launch(fp32, vel, acc, n, f[3 * k], s), "kick");
-    HOT_CHECK(drift_launch(fp32, pos, vel, n, f[3 * k + 1], c->p.box, s), "drift");
+    HOT_CHECK(kick_launch(fp32, vel, acc, n, f[0], s), "kick");
+    HOT_CHECK(drift_launch(fp32, pos, vel, n, f[1], c->p.box, s), "drift");
     st = forces_impl(c, n, pos, mass, acc, pot, ws, ws_bytes, s, need);
     if (st != HOT_OK) {
       if (snap) {
@@ -1167,7 +1176,7 @@ hot_status hot_kdk_comoving(hot_ctx* c, size_t n, double* pos, void* vel, const 
       }
       return st;
     }
-    HOT_CHECK(kick_launch(fp32, vel, acc, n, f[3 * k + 2], s), "kick");
+    HOT_CHECK(kick_launch(fp32, vel, acc, n, f[2], s), "kick");
     c->stats.kdk_steps_done = k + 1;
   }
   return HOT_OK;
