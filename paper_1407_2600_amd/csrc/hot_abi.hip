@@ -41,7 +41,7 @@ hipError_t tree_groups(const Cells& C, uint32_t ncells, int gmax, size_t n, uint
 hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, uint32_t gcap,
                            const double* spos, size_t n, hipStream_t s);
 hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
-                     size_t n, double L, void* srec, bool fp32, hipStream_t s);
+                     size_t n, double L, int leaf_max, void* srec, bool fp32, hipStream_t s);
 hipError_t walk_launch(bool emit, bool big, const Cells& C, const Groups& G, uint32_t ngroups,
                        uint32_t gcap, double L, int periodic, const LocalPrm& lp,
                        uint32_t* p2p_list, uint4* m2p_list, uint32_t* status, hipStream_t s);
@@ -503,7 +503,8 @@ static hot_status forces_impl(hot_ctx* c, size_t n, const double* pos, const voi
   HOT_CHECK(tree_groups(C, ncells, p.group_max, n, gflag, gid, gcell_at, G, ctr + CTR_NGROUPS,
                         scan_tmp, s),
             "groups");
-  HOT_CHECK(tree_srec(C, ncells, spos, smass, n, p.box, srec, fp32, s), "source records");
+  HOT_CHECK(tree_srec(C, ncells, spos, smass, n, p.box, p.leaf_max, srec, fp32, s),
+            "source records");
   HOT_CHECK(readback(s, ctr, host, 8), "readback");
   ngroups = host[CTR_NGROUPS];
   if (ngroups > P.cap_groups) {

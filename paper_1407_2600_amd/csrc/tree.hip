@@ -479,21 +479,25 @@ __global__ void __launch_bounds__(256) k_group_bbox(Cells C, Groups G, uint32_t 
 }
 
 // source records: FP32/FP64 offsets from the leaf centre and the mass; one
-// wavefront per cell (grid-stride over the cells), its lanes over the leaf's
-// particles
+// sub-group of 2^wshift lanes per cell (the leaf size rounded up to a power
+// of two, at most a wavefront; grid-stride over the cells), its lanes over
+// the leaf's particles
 template <typename T4, typename T>
 __global__ void __launch_bounds__(256) k_srec(Cells C, uint32_t ncells,
                                               const double* __restrict__ spos,
                                               const double* __restrict__ smass, size_t n, double L,
-                                              T4* __restrict__ srec) {
+                                              int wshift, T4* __restrict__ srec) {
   const int lane = threadIdx.x & 63;
-  const uint32_t waves = gridDim.x * 4;
-  for (uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < ncells; c += waves) {
+  const uint32_t w = 1u << wshift, per_wave = 64u >> wshift;
+  const uint32_t sub = (uint32_t)lane >> wshift, sl = (uint32_t)lane & (w - 1);
+  const uint32_t step = gridDim.x * 4 * per_wave;
+  for (uint32_t c = (blockIdx.x * 4 + (threadIdx.x >> 6)) * per_wave + sub; c < ncells;
+       c += step) {
     if (C.nchild[c] != 0) continue;
     double ctr[3], side;
     cell_center(C.key[c], C.level[c], L, ctr, &side);
     const uint32_t f = C.first[c], cnt = C.count[c];
-    for (uint32_t t = lane; t < cnt; t += 64) {
+    for (uint32_t t = sl; t < cnt; t += w) {
       const uint32_t s = f + t;
       T4 r;
       r.x = (T)(spos[s] - ctr[0]);
@@ -598,13 +602,17 @@ hipError_t tree_group_bbox(const Cells& C, const Groups& G, uint32_t ngroups, ui
 }
 
 hipError_t tree_srec(const Cells& C, uint32_t ncells, const double* spos, const double* smass,
-                     size_t n, double L, void* srec, bool fp32, hipStream_t s) {
+                     size_t n, double L, int leaf_max, void* srec, bool fp32, hipStream_t s) {
   if (ncells == 0) return hipSuccess;
-  const unsigned g = std::min<uint32_t>((ncells + 3) / 4, 1u << 16);  // four waves a block
+  int wshift = 0;
+  while (wshift < 6 && (1 << wshift) < leaf_max) ++wshift;
+  const uint32_t per_block = 4u * (64u >> wshift);  // four waves a block
+  const unsigned g = std::min<uint32_t>((ncells + per_block - 1) / per_block, 1u << 16);
   if (fp32)
-    k_srec<float4, float><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, (float4*)srec);
+    k_srec<float4, float><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, wshift, (float4*)srec);
   else
-    k_srec<double4, double><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, (double4*)srec);
+    k_srec<double4, double><<<g, 256, 0, s>>>(C, ncells, spos, smass, n, L, wshift,
+                                               (double4*)srec);
   return hipGetLastError();
 }
 
