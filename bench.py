@@ -171,14 +171,14 @@ def copy_calibration():
 # reports traffic as null.
 TRAFFIC_SOURCES = ["forces.hip", "device_math.h", "hot_internal.h", "walk.hip", "tree.hip"]
 TRAFFIC = [
-    {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_eval": 1.513e9,
+    {"workload": "zeldovich128", "kernel": "k_m2p<4,float>", "bytes_per_eval": 1.517e9,
      "config": {"theta": 0.8, "err_tol": 4.88e-3, "order": 4, "leaf_max": 16, "group_max": 128,
                 "far_order": 8, "local_order": 4, "local_tol": 1.46e-4},
-     "sha256": "9827a598a718ac63917c5044a0122966ad804bff23ed0338f40d1d7121081183"},
-    {"workload": "zeldovich1024", "kernel": "k_m2p<4,float>", "bytes_per_eval": 3.908e11,
+     "sha256": "b0569cd9b0c1a9885db49f54dcbc92e361477d32c8da0257d8e3a6a86b36d401"},
+    {"workload": "zeldovich1024", "kernel": "k_m2p<4,float>", "bytes_per_eval": 3.910e11,
      "config": {"theta": 0.8, "err_tol": 1.67e-3, "order": 4, "leaf_max": 64, "group_max": 128,
                 "far_order": 8, "local_order": 4, "local_tol": 1.49e-4},
-     "sha256": "9827a598a718ac63917c5044a0122966ad804bff23ed0338f40d1d7121081183"},
+     "sha256": "b0569cd9b0c1a9885db49f54dcbc92e361477d32c8da0257d8e3a6a86b36d401"},
 ]
 
 
